@@ -1,0 +1,155 @@
+"""Benchmark of the ACS construction hot path on one MI355X.
+
+Workload (one "step" = one iteration of Alg. 1 = construction of m tours,
+iteration best, global update): n = 2392 cities uniform in [0, 10000)^2
+(seed 2392), m = n ants, candidate lists of 32, beta = 2, q0 = 0.9,
+phi = rho = 0.1, dense FP32 pheromone.  The headline value is construction
+steps per second (m * (n - 1) ant moves per iteration) in the asynchronous
+atomic mode; the synchronous (bit-exact) mode is timed beside it.
+
+Prints one JSON line.  Only one GPU is supported; --gpus N > 1 exits.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+N, CL = 2392, 32
+
+
+def algorithmic_bytes(st_delta: dict, n: int, m: int, cl: int, iters: int) -> float:
+    """Bytes the method must move per the per-step model of the design notes:
+    per construction step cl * (4 candidate index + 4 tau + 4 eta) + 2 (d of
+    the chosen edge) + 4 (tour entry) + 16 (two 4-byte read-modify-writes of
+    the local update); per fallback step additionally 6 bytes (4 tau + 2 d)
+    for every unvisited city scanned; per ant the closing edge (2 + 16)."""
+    steps = st_delta["steps"]
+    b = steps * (cl * 12 + 2 + 4 + 16)
+    b += st_delta["fallback_unvisited"] * 6
+    b += iters * m * (2 + 16)
+    return float(b)
+
+
+def run_mode(acs, xy, mode, steps, warmup, seed=0):
+    import torch
+    col = acs.Colony(xy, m=0, cl=CL, mode=mode, seed=seed)
+    col.iterate(max(warmup, 1))
+    st0 = col.stats()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    col.iterate(steps)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    st1 = col.stats()
+    delta = {k: st1[k] - st0[k] for k in ("steps", "fallback", "fallback_unvisited", "greedy", "roulette")}
+    res = dict(
+        seconds=t1 - t0,
+        steps=delta["steps"],
+        construct_ms=st1["construct_ms"],
+        launches=st1["construct_launches"],
+        iterate_ms=st1["iterate_ms"],
+        best=st1["best_length"],
+        nn_length=st1["nn_length"],
+        delta=delta,
+        n=col.n, m=col.m, cl=col.cl,
+    )
+    col.close()
+    return res
+
+
+def cpu_baseline(xy, budget_s: float = 12.0):
+    import oracle
+    threads = min(os.cpu_count() or 1, 16)
+    oracle.set_threads(threads)
+    orc = oracle.Oracle(xy, cl=CL, seed=0)
+    t0 = time.perf_counter()
+    iters = 0
+    while True:
+        orc.iterate(1)
+        iters += 1
+        if time.perf_counter() - t0 > budget_s or iters >= 8:
+            break
+    dt = time.perf_counter() - t0
+    steps = orc.counts()["steps"]
+    oracle.set_threads(1)
+    return dict(value=steps / dt, unit="steps/s", cores=threads, kind="oracle",
+                sample=f"{iters} synchronous iterations of the n={N}, m={N} workload "
+                       f"({steps} steps, {dt:.1f} s, {threads} OpenMP threads)")
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=50)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--sync-steps", type=int, default=5)
+    ap.add_argument("--no-cpu", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py: only one GPU is supported (asked for {args.gpus}); "
+              "the colony runs on a single MI355X.", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_1605_02669_amd import acs, inputs
+
+    if not torch.cuda.is_available():
+        print("bench.py: no GPU visible", file=sys.stderr)
+        sys.exit(1)
+    acs.load()
+    xy = inputs.uniform(N)
+
+    asy = run_mode(acs, xy, acs.ACS_ASYNC_ATOMIC, args.steps, args.warmup)
+    print(f"# async: {asy['seconds']*1e3/args.steps:.3f} ms/iteration", file=sys.stderr, flush=True)
+    syn = run_mode(acs, xy, acs.ACS_SYNC, args.sync_steps, 1)
+    print(f"# sync: {syn['seconds']*1e3/args.sync_steps:.3f} ms/iteration", file=sys.stderr, flush=True)
+
+    value = asy["steps"] / asy["seconds"]
+    ms_per_step = asy["seconds"] * 1e3 / args.steps
+    avg_launch_s = asy["construct_ms"] / asy["launches"] / 1e3
+    bytes_per_launch = algorithmic_bytes(asy["delta"], asy["n"], asy["m"], asy["cl"], args.steps) / args.steps
+    achieved = bytes_per_launch / avg_launch_s / 1e9
+    out = {
+        "metric": "ant construction steps/s at n=2392, m=n",
+        "value": value,
+        "unit": "steps/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_per_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": "ACS construction, n=2392 uniform [0,1e4)^2 (seed 2392), m=n, "
+                               "cl=32, beta=2, q0=0.9, phi=rho=0.1, dense FP32 pheromone, "
+                               "asynchronous atomic local updates",
+                   "n": asy["n"], "m": asy["m"], "cl": asy["cl"], "mode": "async_atomic"},
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "kernel": "k_construct_dense (async)",
+                     "bytes_per_launch": bytes_per_launch,
+                     "avg_launch_ms": avg_launch_s * 1e3},
+        "sync_mode": {"value": syn["steps"] / syn["seconds"], "unit": "steps/s",
+                      "ms_per_step": syn["seconds"] * 1e3 / args.sync_steps,
+                      "avg_construct_ms": syn["construct_ms"] / syn["launches"]},
+        "fallback_share": asy["delta"]["fallback"] / max(asy["delta"]["steps"], 1),
+        "best_length_async": asy["best"],
+        "nn_length": asy["nn_length"],
+    }
+    if not args.no_cpu:
+        cb = cpu_baseline(xy)
+        out["cpu_baseline"] = cb
+    print(json.dumps(out))
+
+
+if __name__ == "__main__":
+    main()

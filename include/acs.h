@@ -1,0 +1,163 @@
+/*
+ * libacs -- Ant Colony System hot path for AMD Instinct MI355X (gfx950).
+ *
+ * Method: R. Skinderowicz, "The GPU-based Parallel Ant Colony System",
+ * J. Parallel Distrib. Comput. 2016 (arXiv:1605.02669), Sec. 3.
+ *
+ * One handle holds one colony on one symmetric Euclidean TSP instance
+ * (the complete graph of Sec. 3).  Each call of acs_iterate runs whole
+ * iterations of Alg. 1: every ant picks a start city, extends its tour with
+ * the pseudo-random-proportional rule (Eq. 1, Eq. 2) over its candidate set
+ * of nearest neighbours and falls back to the greedy choice over all
+ * unvisited cities when that set is empty (Alg. 2); every crossing is
+ * followed by the local update (Eq. 3); the iteration ends with the global
+ * update (Eq. 4) on the best-so-far tour.  The pheromone lives either in a
+ * dense n x n matrix or in the selective pheromone memory of Sec. 3.2
+ * (Alg. 3), which keeps at most s trails per city and reads every other
+ * trail as tau0.
+ *
+ * Conventions for every entry point:
+ *   - Return 0 (ACS_OK) on success, a negative ACS_E_* code otherwise; the
+ *     message of the last failure on the calling thread is acs_last_error().
+ *   - Host pointers are plain host memory owned by the caller; inputs are
+ *     copied, outputs are written to caller-owned buffers of the stated size.
+ *     Device pointers appear only as the optional stream and workspace.
+ *   - A handle is not thread-safe; distinct handles are independent.
+ *   - Nothing here falls back to the CPU: the iteration runs in the
+ *     library's HIP kernels, and a missing or unusable GPU is an error.
+ */
+#ifndef ACS_H
+#define ACS_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define ACS_OK 0
+#define ACS_E_INVALID (-1)     /* argument out of range */
+#define ACS_E_NOMEM (-2)       /* device or host allocation failed */
+#define ACS_E_DEVICE (-3)      /* a HIP call or kernel failed */
+#define ACS_E_BUFSIZE (-4)     /* caller buffer or workspace too small */
+#define ACS_E_STATE (-5)       /* NULL or destroyed handle */
+#define ACS_E_UNSUPPORTED (-6) /* valid request this handle cannot serve */
+
+typedef struct acs_t acs_t; /* opaque handle, owned by the library */
+
+enum acs_memory { ACS_DENSE = 0, ACS_SPM = 1 };
+
+/* ACS_SYNC: within a step every ant selects from the pheromone as it was at
+ * the start of the step; then every crossing of that step is applied (an
+ * edge crossed k times gets the map k times).  Tours and pheromone are a
+ * deterministic function of (instance, parameters, seed).
+ * ACS_ASYNC_ATOMIC: every ant runs its whole tour without waiting for the
+ * others and applies the local update of Eq. 3 right after each move with an
+ * atomic compare-and-swap; reads see whatever the other ants have written
+ * so far (the unsynchronised single-kernel construction of Sec. 3.1.2). */
+enum acs_mode { ACS_SYNC = 0, ACS_ASYNC_ATOMIC = 1 };
+
+typedef struct acs_params {
+  uint32_t struct_size;  /* = sizeof(acs_params) */
+  uint32_t m;            /* ants; 0 -> n */
+  uint32_t cl;           /* candidate-list length; clamped to n-1; <= 64 */
+  uint32_t memory;       /* enum acs_memory */
+  uint32_t spm_s;        /* SPM trails per city (Sec. 3.2), >= 1 */
+  uint32_t mode;         /* enum acs_mode */
+  uint32_t local_update_period; /* must be 1 */
+  uint32_t instance;     /* fourth word of every random-number counter */
+  double beta;           /* exponent of eta = 1/d in Eq. 1-2, >= 0 */
+  double q0;             /* exploitation probability of Eq. 1, in [0, 1] */
+  double phi;            /* local evaporation of Eq. 3, in (0, 1) */
+  double rho;            /* global evaporation of Eq. 4, in (0, 1) */
+  double tau0;           /* > 0: initial pheromone; <= 0: 1/(n * L_nn) */
+  uint64_t seed;         /* key of the Philox4x32-10 draws */
+  void *stream;          /* hipStream_t to run on; NULL: the library's own */
+  void *workspace;       /* optional device buffer (e.g. a torch tensor) */
+  size_t workspace_bytes;
+} acs_params;
+
+typedef struct acs_stats {
+  uint32_t struct_size;      /* = sizeof(acs_stats_t) */
+  uint32_t iteration;        /* iterations completed */
+  int64_t best_length;       /* best-so-far L_gb, -1 before the first */
+  int64_t iter_best_length;  /* best of the last iteration */
+  int32_t iter_best_ant;
+  int32_t n, m, cl;
+  int64_t nn_length;         /* L_nn of the nearest-neighbour tour from 0 */
+  float tau0;
+  float pad0;
+  int64_t steps;             /* construction steps since create */
+  int64_t greedy;            /* ... decided by the argmax of Eq. 1 */
+  int64_t roulette;          /* ... decided by Eq. 2 */
+  int64_t fallback;          /* ... with an empty candidate set */
+  int64_t spm_hits;          /* SPM updates that found the trail */
+  int64_t spm_misses;        /* SPM updates that inserted it */
+  int64_t fallback_unvisited;/* sum over fallback steps of the unvisited
+                                cities the greedy scan had to consider */
+  double construct_ms;       /* device time of the construction kernels of
+                                the last acs_iterate call (HIP events) */
+  int32_t construct_launches;/* construction launches of that call */
+  int32_t pad1;
+  double iterate_ms;         /* device time of the whole last acs_iterate */
+} acs_stats_t;
+
+/* Fills *p with the defaults: m = n, cl = 32, dense, s = 8, sync,
+ * beta = 2, q0 = 0.9, phi = rho = 0.1, tau0 = 1/(n L_nn), seed 0. */
+int acs_default_params(acs_params *p);
+
+/* Device bytes the library needs for an instance of n cities with these
+ * parameters; a workspace of at least this size makes acs_create allocate
+ * nothing on the device. */
+int acs_workspace_bytes(int32_t n, const acs_params *p, size_t *out);
+
+/* Builds the instance on the device: exact integer EUC_2D costs (the
+ * d_ij of Sec. 3), the cl nearest neighbours of each city sorted by
+ * (d, index) (the candidate set of Sec. 3), eta^beta, the nearest-neighbour
+ * tour from city 0 and tau0, and the initial pheromone (dense: tau0
+ * everywhere; SPM: empty records).
+ * coords_xy: n (x, y) pairs of finite doubles, copied.  n >= 3.
+ * Errors: ACS_E_INVALID (bad n, coordinates or parameters), ACS_E_NOMEM,
+ * ACS_E_DEVICE, ACS_E_UNSUPPORTED (cl > 64, n > 65535, distances > 65535,
+ * or m beyond what one synchronous launch can hold). */
+int acs_create(const double *coords_xy, int32_t n, const acs_params *p,
+               struct acs_t **out);
+
+/* Runs k >= 0 iterations of Alg. 1 on the handle's stream and returns once
+ * they have finished.  The iteration counter persists across calls, so
+ * acs_iterate(h, 2) equals acs_iterate(h, 1) twice. */
+int acs_iterate(struct acs_t *h, int32_t k);
+
+/* Best-so-far tour (n cities, starting at its ant's start city) and its
+ * length.  Before the first iteration: ACS_E_STATE. */
+int acs_best_tour(struct acs_t *h, int32_t *tour_out, int64_t *len_out);
+
+/* Logical pheromone tau(i, j) as the ants read it, row-major n x n floats
+ * (count must be >= n*n).  Dense handles only (SPM: ACS_E_UNSUPPORTED). */
+int acs_pheromone_snapshot(struct acs_t *h, float *out, size_t count);
+
+/* SPM records of Alg. 3: nodes[n*s] (-1 = empty slot), vals[n*s],
+ * tail[n] (index of the most recently added slot).  SPM handles only. */
+int acs_spm_snapshot(struct acs_t *h, int32_t *nodes, float *vals,
+                     int32_t *tail);
+
+/* Tours (m x n) and lengths (m) of the last iteration. */
+int acs_tours(struct acs_t *h, int32_t *out, size_t count);
+int acs_lengths(struct acs_t *h, int64_t *out, size_t count);
+
+/* Candidate lists (n x cl, the nearest neighbours of Sec. 3) as built. */
+int acs_candidates(struct acs_t *h, int32_t *out, size_t count);
+
+int acs_stats(struct acs_t *h, acs_stats_t *out);
+
+/* Releases every resource of the handle; NULL is a no-op. */
+void acs_destroy(struct acs_t *h);
+
+/* Message of the last failing call on this thread ("" if none). */
+const char *acs_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* ACS_H */

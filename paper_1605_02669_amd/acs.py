@@ -1,0 +1,236 @@
+"""Python binding of libacs (ctypes).  Argument marshalling only.
+
+Every step of the method runs in the library's HIP kernels.  PyTorch is used
+for the plumbing the C-ABI accepts: a device workspace tensor and the current
+HIP stream.  If libacs.so has not been built the import fails loudly; there
+is no CPU path.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libacs.so")
+
+ACS_OK = 0
+ACS_E_INVALID = -1
+ACS_E_NOMEM = -2
+ACS_E_DEVICE = -3
+ACS_E_BUFSIZE = -4
+ACS_E_STATE = -5
+ACS_E_UNSUPPORTED = -6
+
+ACS_DENSE, ACS_SPM = 0, 1
+ACS_SYNC, ACS_ASYNC_ATOMIC = 0, 1
+
+
+class acs_params(C.Structure):
+    _fields_ = [
+        ("struct_size", C.c_uint32), ("m", C.c_uint32), ("cl", C.c_uint32),
+        ("memory", C.c_uint32), ("spm_s", C.c_uint32), ("mode", C.c_uint32),
+        ("local_update_period", C.c_uint32), ("instance", C.c_uint32),
+        ("beta", C.c_double), ("q0", C.c_double), ("phi", C.c_double),
+        ("rho", C.c_double), ("tau0", C.c_double), ("seed", C.c_uint64),
+        ("stream", C.c_void_p), ("workspace", C.c_void_p), ("workspace_bytes", C.c_size_t),
+    ]
+
+
+class acs_stats_t(C.Structure):
+    _fields_ = [
+        ("struct_size", C.c_uint32), ("iteration", C.c_uint32),
+        ("best_length", C.c_int64), ("iter_best_length", C.c_int64),
+        ("iter_best_ant", C.c_int32), ("n", C.c_int32), ("m", C.c_int32), ("cl", C.c_int32),
+        ("nn_length", C.c_int64), ("tau0", C.c_float), ("pad0", C.c_float),
+        ("steps", C.c_int64), ("greedy", C.c_int64), ("roulette", C.c_int64),
+        ("fallback", C.c_int64), ("spm_hits", C.c_int64), ("spm_misses", C.c_int64),
+        ("fallback_unvisited", C.c_int64),
+        ("construct_ms", C.c_double), ("construct_launches", C.c_int32), ("pad1", C.c_int32),
+        ("iterate_ms", C.c_double),
+    ]
+
+
+class AcsError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"libacs error {code}: {msg}")
+        self.code = code
+
+
+_lib = None
+
+
+def load() -> C.CDLL:
+    """Loads libacs.so; raises if it has not been built."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(f"{LIB_PATH} is missing: build it with __graft_entry__.build()")
+    lib = C.CDLL(LIB_PATH)
+    P, i32, i64, sz = C.c_void_p, C.c_int32, C.c_int64, C.c_size_t
+    lib.acs_default_params.argtypes = [C.POINTER(acs_params)]
+    lib.acs_workspace_bytes.argtypes = [i32, C.POINTER(acs_params), C.POINTER(sz)]
+    lib.acs_create.argtypes = [P, i32, C.POINTER(acs_params), C.POINTER(P)]
+    lib.acs_iterate.argtypes = [P, i32]
+    lib.acs_best_tour.argtypes = [P, P, C.POINTER(i64)]
+    lib.acs_pheromone_snapshot.argtypes = [P, P, sz]
+    lib.acs_spm_snapshot.argtypes = [P, P, P, P]
+    lib.acs_tours.argtypes = [P, P, sz]
+    lib.acs_lengths.argtypes = [P, P, sz]
+    lib.acs_candidates.argtypes = [P, P, sz]
+    lib.acs_stats.argtypes = [P, C.POINTER(acs_stats_t)]
+    lib.acs_destroy.argtypes = [P]
+    lib.acs_destroy.restype = None
+    lib.acs_last_error.restype = C.c_char_p
+    _lib = lib
+    return lib
+
+
+def _check(rc: int) -> None:
+    if rc != ACS_OK:
+        raise AcsError(rc, load().acs_last_error().decode())
+
+
+def _ptr(a: np.ndarray):
+    return a.ctypes.data_as(C.c_void_p)
+
+
+def acs_default_params() -> acs_params:
+    p = acs_params()
+    _check(load().acs_default_params(C.byref(p)))
+    return p
+
+
+def acs_workspace_bytes(n: int, p: acs_params) -> int:
+    out = C.c_size_t()
+    _check(load().acs_workspace_bytes(n, C.byref(p), C.byref(out)))
+    return out.value
+
+
+def acs_create(xy: np.ndarray, p: acs_params) -> C.c_void_p:
+    xy = np.ascontiguousarray(xy, dtype=np.float64).reshape(-1, 2)
+    h = C.c_void_p()
+    _check(load().acs_create(_ptr(xy), xy.shape[0], C.byref(p), C.byref(h)))
+    return h
+
+
+def acs_iterate(h, k: int) -> None:
+    _check(load().acs_iterate(h, k))
+
+
+def acs_best_tour(h, n: int):
+    t = np.empty(n, dtype=np.int32)
+    L = C.c_int64()
+    _check(load().acs_best_tour(h, _ptr(t), C.byref(L)))
+    return t, L.value
+
+
+def acs_pheromone_snapshot(h, n: int) -> np.ndarray:
+    out = np.empty((n, n), dtype=np.float32)
+    _check(load().acs_pheromone_snapshot(h, _ptr(out), out.size))
+    return out
+
+
+def acs_spm_snapshot(h, n: int, s: int):
+    nodes = np.empty((n, s), dtype=np.int32)
+    vals = np.empty((n, s), dtype=np.float32)
+    tail = np.empty(n, dtype=np.int32)
+    _check(load().acs_spm_snapshot(h, _ptr(nodes), _ptr(vals), _ptr(tail)))
+    return nodes, vals, tail
+
+
+def acs_tours(h, m: int, n: int) -> np.ndarray:
+    out = np.empty((m, n), dtype=np.int32)
+    _check(load().acs_tours(h, _ptr(out), out.size))
+    return out
+
+
+def acs_lengths(h, m: int) -> np.ndarray:
+    out = np.empty(m, dtype=np.int64)
+    _check(load().acs_lengths(h, _ptr(out), out.size))
+    return out
+
+
+def acs_candidates(h, n: int, cl: int) -> np.ndarray:
+    out = np.empty((n, cl), dtype=np.int32)
+    _check(load().acs_candidates(h, _ptr(out), out.size))
+    return out
+
+
+def acs_stats(h) -> dict:
+    s = acs_stats_t()
+    s.struct_size = C.sizeof(acs_stats_t)
+    _check(load().acs_stats(h, C.byref(s)))
+    return {name: getattr(s, name) for name, _ in acs_stats_t._fields_
+            if not name.startswith("pad") and name != "struct_size"}
+
+
+def acs_destroy(h) -> None:
+    load().acs_destroy(h)
+
+
+class Colony:
+    """One colony on one instance, owning its handle.
+
+    With ``torch_memory`` the device workspace is a torch tensor and the
+    library runs on torch's current stream; otherwise the library allocates
+    and uses a stream of its own.
+    """
+
+    def __init__(self, xy, m=0, cl=32, beta=2.0, q0=0.9, phi=0.1, rho=0.1, tau0=0.0,
+                 memory=ACS_DENSE, spm_s=8, mode=ACS_SYNC, seed=0, instance=0,
+                 torch_memory=True):
+        self.xy = np.ascontiguousarray(xy, dtype=np.float64).reshape(-1, 2)
+        n = self.xy.shape[0]
+        p = acs_default_params()
+        p.m, p.cl, p.beta, p.q0, p.phi, p.rho, p.tau0 = m, cl, beta, q0, phi, rho, tau0
+        p.memory, p.spm_s, p.mode, p.seed, p.instance = memory, spm_s, mode, seed, instance
+        self._ws = None
+        if torch_memory:
+            import torch
+            nbytes = acs_workspace_bytes(n, p)
+            self._ws = torch.empty(nbytes, dtype=torch.uint8, device="cuda")
+            p.workspace, p.workspace_bytes = self._ws.data_ptr(), nbytes
+            p.stream = torch.cuda.current_stream().cuda_stream
+        self.params = p
+        self.h = acs_create(self.xy, p)
+        st = acs_stats(self.h)
+        self.n, self.m, self.cl = st["n"], st["m"], st["cl"]
+        self.memory, self.spm_s = memory, spm_s
+
+    def close(self):
+        if getattr(self, "h", None):
+            acs_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def iterate(self, k=1):
+        acs_iterate(self.h, k)
+
+    def best(self):
+        return acs_best_tour(self.h, self.n)
+
+    def tau(self):
+        return acs_pheromone_snapshot(self.h, self.n)
+
+    def spm(self):
+        return acs_spm_snapshot(self.h, self.n, self.spm_s)
+
+    def tours(self):
+        return acs_tours(self.h, self.m, self.n)
+
+    def lengths(self):
+        return acs_lengths(self.h, self.m)
+
+    def cand(self):
+        return acs_candidates(self.h, self.n, self.cl)
+
+    def stats(self):
+        return acs_stats(self.h)

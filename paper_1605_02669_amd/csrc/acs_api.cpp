@@ -1,0 +1,493 @@
+// C-ABI of libacs: argument checks, device memory layout, instance
+// preparation, the iteration loop and read-back.  The arithmetic of the
+// method runs in the HIP kernels of acs_kernels.hip; this file only
+// validates, allocates, launches and copies.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <mutex>
+#include <string>
+#include <unordered_set>
+#include <vector>
+
+#include "../../include/acs.h"
+#include "acs_internal.hpp"
+
+namespace {
+
+thread_local std::string g_err;
+
+int fail(int code, const char *fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof buf, fmt, ap);
+  va_end(ap);
+  g_err = buf;
+  return code;
+}
+
+#define HIP_TRY(expr)                                                              \
+  do {                                                                             \
+    hipError_t e_ = (expr);                                                        \
+    if (e_ != hipSuccess)                                                          \
+      return fail(e_ == hipErrorOutOfMemory ? ACS_E_NOMEM : ACS_E_DEVICE, "%s: %s", \
+                  #expr, hipGetErrorString(e_));                                   \
+  } while (0)
+
+std::mutex g_live_mu;
+std::unordered_set<const void *> g_live;
+
+size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
+
+// Device buffers of one handle, as offsets into one allocation.
+struct Layout {
+  size_t xy, dist, crec, cand, eta, tau, tau_nn, spm_node, spm_val, spm_tail, tours, lens,
+      best, gstate, counters, sync, dmax, lnn, total;
+};
+
+constexpr int kEtaEntries = 65536;  // eta^beta for every 16-bit distance
+
+Layout make_layout(int n, int m, int cl, int ldn, int memory, int s) {
+  Layout L{};
+  size_t off = 0;
+  auto take = [&](size_t bytes) {
+    const size_t at = off;
+    off = align_up(off + bytes, 256);
+    return at;
+  };
+  L.xy = take(sizeof(double) * 2 * (size_t)n);
+  L.dist = take(sizeof(uint16_t) * (size_t)n * ldn);
+  L.crec = take(sizeof(uint4) * (size_t)n * cl);
+  L.cand = take(sizeof(int32_t) * (size_t)n * cl);
+  L.eta = take(sizeof(float) * kEtaEntries);
+  if (memory == ACS_DENSE) {
+    L.tau = take(sizeof(float) * (size_t)n * ldn);
+    L.tau_nn = take(sizeof(float) * (size_t)n * cl);
+  } else {
+    L.spm_node = take(sizeof(int32_t) * (size_t)n * s);
+    L.spm_val = take(sizeof(float) * (size_t)n * s);
+    L.spm_tail = take(sizeof(int32_t) * (size_t)n);
+  }
+  L.tours = take(sizeof(int32_t) * (size_t)m * n);
+  L.lens = take(sizeof(int64_t) * (size_t)m);
+  L.best = take(sizeof(int32_t) * (size_t)n);
+  L.gstate = take(sizeof(int64_t) * 4);
+  L.counters = take(sizeof(unsigned long long) * 8);
+  L.sync = take(sizeof(uint32_t) * 4);
+  L.dmax = take(sizeof(uint32_t));
+  L.lnn = take(sizeof(int64_t));
+  L.total = off;
+  return L;
+}
+
+int check_params(int32_t n, const acs_params *p) {
+  if (!p) return fail(ACS_E_INVALID, "params is NULL");
+  if (p->struct_size != sizeof(acs_params))
+    return fail(ACS_E_INVALID, "params.struct_size %u != %zu", p->struct_size, sizeof(acs_params));
+  if (n < 3) return fail(ACS_E_INVALID, "n = %d < 3", n);
+  if (p->cl < 1) return fail(ACS_E_INVALID, "cl must be >= 1");
+  if (!(p->q0 >= 0.0 && p->q0 <= 1.0)) return fail(ACS_E_INVALID, "q0 not in [0, 1]");
+  if (!(p->phi > 0.0 && p->phi < 1.0)) return fail(ACS_E_INVALID, "phi not in (0, 1)");
+  if (!(p->rho > 0.0 && p->rho < 1.0)) return fail(ACS_E_INVALID, "rho not in (0, 1)");
+  if (!(p->beta >= 0.0) || !std::isfinite(p->beta)) return fail(ACS_E_INVALID, "beta invalid");
+  if (!std::isfinite(p->tau0)) return fail(ACS_E_INVALID, "tau0 not finite");
+  if (p->memory != ACS_DENSE && p->memory != ACS_SPM) return fail(ACS_E_INVALID, "bad memory");
+  if (p->memory == ACS_SPM && p->spm_s < 1) return fail(ACS_E_INVALID, "spm_s must be >= 1");
+  if (p->mode != ACS_SYNC && p->mode != ACS_ASYNC_ATOMIC) return fail(ACS_E_INVALID, "bad mode");
+  if (p->local_update_period != 1)
+    return fail(ACS_E_UNSUPPORTED, "local_update_period must be 1");
+  if (n > 65535) return fail(ACS_E_UNSUPPORTED, "n = %d > 65535", n);
+  const uint32_t cl = std::min<uint32_t>(p->cl, (uint32_t)n - 1);
+  if (cl > 64) return fail(ACS_E_UNSUPPORTED, "cl = %u > 64", cl);
+  if (p->memory == ACS_SPM) return fail(ACS_E_UNSUPPORTED, "selective memory not built yet");
+  return ACS_OK;
+}
+
+// eta^beta for integer distance d (eta = 1/d; a zero distance reads as 1/2).
+float eta_beta(double beta, uint32_t d) {
+  if (d == 0) return (float)std::pow(2.0, beta);
+  return (float)(1.0 / std::pow((double)d, beta));
+}
+
+}  // namespace
+
+struct acs_t {
+  acs_params p{};
+  int n = 0, m = 0, cl = 0, ldn = 0;
+  hipStream_t stream = nullptr;
+  bool own_stream = false;
+  char *ws = nullptr;
+  bool own_ws = false;
+  Layout L{};
+  acs::Dev dev{};
+  acs::Iter base{};
+  int64_t lnn = 0;
+  float tau0 = 0.f;
+  uint32_t iter = 0;
+  double construct_ms = 0.0, iterate_ms = 0.0;
+  int construct_launches = 0;
+  std::vector<hipEvent_t> ev;
+  hipEvent_t ev_begin = nullptr, ev_end = nullptr;
+};
+
+namespace {
+
+bool live(const acs_t *h) {
+  std::lock_guard<std::mutex> g(g_live_mu);
+  return h && g_live.count(h);
+}
+
+void release(acs_t *h) {
+  if (!h) return;
+  if (h->stream) (void)hipStreamSynchronize(h->stream);
+  for (auto e : h->ev) (void)hipEventDestroy(e);
+  if (h->ev_begin) (void)hipEventDestroy(h->ev_begin);
+  if (h->ev_end) (void)hipEventDestroy(h->ev_end);
+  if (h->own_ws && h->ws) (void)hipFree(h->ws);
+  if (h->own_stream && h->stream) (void)hipStreamDestroy(h->stream);
+  delete h;
+}
+
+int sync_and_check(acs_t *h) {
+  HIP_TRY(hipStreamSynchronize(h->stream));
+  uint32_t flags[2] = {0, 0};
+  HIP_TRY(hipMemcpy(flags, h->ws + h->L.sync, sizeof flags, hipMemcpyDeviceToHost));
+  if (flags[1]) return fail(ACS_E_DEVICE, "grid barrier wait exhausted (flag %u)", flags[1]);
+  return ACS_OK;
+}
+
+int build(acs_t *h, const double *xy) {
+  const int n = h->n;
+  HIP_TRY(hipMemcpyAsync(h->ws + h->L.xy, xy, sizeof(double) * 2 * n, hipMemcpyHostToDevice,
+                         h->stream));
+  HIP_TRY(hipMemsetAsync(h->ws + h->L.dmax, 0, sizeof(uint32_t), h->stream));
+  HIP_TRY(acs::launch_dist(h->dev, reinterpret_cast<uint32_t *>(h->ws + h->L.dmax), h->stream));
+  uint32_t dmax = 0;
+  HIP_TRY(hipMemcpyAsync(&dmax, h->ws + h->L.dmax, sizeof dmax, hipMemcpyDeviceToHost, h->stream));
+  HIP_TRY(hipStreamSynchronize(h->stream));
+  if (dmax > 65535u)
+    return fail(ACS_E_UNSUPPORTED, "largest distance %u exceeds 65535", dmax);
+
+  int32_t *cand = reinterpret_cast<int32_t *>(h->ws + h->L.cand);
+  HIP_TRY(acs::launch_cand(h->dev, cand, h->stream));
+  int64_t *lnn_d = reinterpret_cast<int64_t *>(h->ws + h->L.lnn);
+  HIP_TRY(acs::launch_nn_tour(h->dev, lnn_d, h->stream));
+  HIP_TRY(hipMemcpyAsync(&h->lnn, lnn_d, sizeof(int64_t), hipMemcpyDeviceToHost, h->stream));
+  HIP_TRY(hipStreamSynchronize(h->stream));
+  if (h->lnn <= 0) return fail(ACS_E_INVALID, "nearest-neighbour tour has length %lld",
+                               (long long)h->lnn);
+
+  // Host constants of the method (scalars and the per-distance eta table).
+  const acs_params &p = h->p;
+  h->tau0 = p.tau0 > 0.0 ? (float)p.tau0 : (float)(1.0 / ((double)n * (double)h->lnn));
+  std::vector<float> eta(kEtaEntries, 0.f);
+  for (uint32_t d = 0; d <= dmax; ++d) eta[d] = eta_beta(p.beta, d);
+  HIP_TRY(hipMemcpyAsync(h->ws + h->L.eta, eta.data(), sizeof(float) * kEtaEntries,
+                         hipMemcpyHostToDevice, h->stream));
+  HIP_TRY(acs::launch_crec(h->dev, cand, h->stream));
+  HIP_TRY(acs::launch_init_pheromone(h->dev, h->tau0, h->stream));
+  HIP_TRY(hipStreamSynchronize(h->stream));
+
+  acs::Iter &b = h->base;
+  b.it = 0;
+  b.instance = p.instance;
+  b.key0 = (uint32_t)p.seed;
+  b.key1 = (uint32_t)(p.seed >> 32);
+  b.q0_24 = (uint32_t)std::ceil(p.q0 * 16777216.0);
+  b.a_loc = (float)(1.0 - p.phi);
+  b.b_loc = (float)(p.phi * (double)h->tau0);
+  b.a_glob = (float)(1.0 - p.rho);
+  b.tau0 = h->tau0;
+  b.rho = p.rho;
+  return ACS_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int acs_default_params(acs_params *p) {
+  if (!p) return fail(ACS_E_INVALID, "params is NULL");
+  std::memset(p, 0, sizeof *p);
+  p->struct_size = sizeof(acs_params);
+  p->m = 0;
+  p->cl = 32;
+  p->memory = ACS_DENSE;
+  p->spm_s = 8;
+  p->mode = ACS_SYNC;
+  p->local_update_period = 1;
+  p->beta = 2.0;
+  p->q0 = 0.9;
+  p->phi = 0.1;
+  p->rho = 0.1;
+  p->tau0 = 0.0;
+  p->seed = 0;
+  return ACS_OK;
+}
+
+int acs_workspace_bytes(int32_t n, const acs_params *p, size_t *out) {
+  int rc = check_params(n, p);
+  if (rc) return rc;
+  if (!out) return fail(ACS_E_INVALID, "out is NULL");
+  const int m = p->m ? (int)p->m : n;
+  const int cl = (int)std::min<uint32_t>(p->cl, (uint32_t)n - 1);
+  const int ldn = (int)align_up((size_t)n, 64);
+  *out = make_layout(n, m, cl, ldn, (int)p->memory, (int)p->spm_s).total;
+  return ACS_OK;
+}
+
+int acs_create(const double *coords_xy, int32_t n, const acs_params *p, acs_t **out) {
+  if (!out) return fail(ACS_E_INVALID, "out is NULL");
+  *out = nullptr;
+  int rc = check_params(n, p);
+  if (rc) return rc;
+  if (!coords_xy) return fail(ACS_E_INVALID, "coords is NULL");
+  for (int i = 0; i < 2 * n; ++i)
+    if (!std::isfinite(coords_xy[i])) return fail(ACS_E_INVALID, "coordinate %d not finite", i);
+  const int m = p->m ? (int)p->m : n;
+  if (m < 1) return fail(ACS_E_INVALID, "m < 1");
+
+  int ndev = 0;
+  if (hipGetDeviceCount(&ndev) != hipSuccess || ndev < 1)
+    return fail(ACS_E_DEVICE, "no HIP device available");
+
+  acs_t *h = new (std::nothrow) acs_t;
+  if (!h) return fail(ACS_E_NOMEM, "host allocation failed");
+  h->p = *p;
+  h->n = n;
+  h->m = m;
+  h->cl = (int)std::min<uint32_t>(p->cl, (uint32_t)n - 1);
+  h->ldn = (int)align_up((size_t)n, 64);
+  h->L = make_layout(n, m, h->cl, h->ldn, (int)p->memory, (int)p->spm_s);
+
+  auto bail = [&](int code) {
+    std::string keep = g_err;
+    release(h);
+    g_err = keep;
+    return code;
+  };
+  if (p->stream) {
+    h->stream = reinterpret_cast<hipStream_t>(p->stream);
+  } else {
+    if (hipStreamCreateWithFlags(&h->stream, hipStreamNonBlocking) != hipSuccess)
+      return bail(fail(ACS_E_DEVICE, "stream creation failed"));
+    h->own_stream = true;
+  }
+  if (p->workspace) {
+    if (p->workspace_bytes < h->L.total)
+      return bail(fail(ACS_E_BUFSIZE, "workspace of %zu bytes < %zu needed", p->workspace_bytes,
+                       h->L.total));
+    h->ws = reinterpret_cast<char *>(p->workspace);
+  } else {
+    hipError_t e = hipMalloc(&h->ws, h->L.total);
+    if (e != hipSuccess) {
+      h->ws = nullptr;
+      return bail(fail(ACS_E_NOMEM, "hipMalloc(%zu): %s", h->L.total, hipGetErrorString(e)));
+    }
+    h->own_ws = true;
+  }
+  if (hipEventCreate(&h->ev_begin) != hipSuccess || hipEventCreate(&h->ev_end) != hipSuccess)
+    return bail(fail(ACS_E_DEVICE, "event creation failed"));
+
+  acs::Dev &d = h->dev;
+  char *w = h->ws;
+  d.n = n;
+  d.m = m;
+  d.cl = h->cl;
+  d.ldn = h->ldn;
+  d.spm_s = (int)p->spm_s;
+  d.xy = reinterpret_cast<const double *>(w + h->L.xy);
+  d.dist = reinterpret_cast<const uint16_t *>(w + h->L.dist);
+  d.crec = reinterpret_cast<const uint4 *>(w + h->L.crec);
+  d.eta_tab = reinterpret_cast<const float *>(w + h->L.eta);
+  if (p->memory == ACS_DENSE) {
+    d.tau = reinterpret_cast<float *>(w + h->L.tau);
+    d.tau_nn = reinterpret_cast<float *>(w + h->L.tau_nn);
+  } else {
+    d.spm_node = reinterpret_cast<int32_t *>(w + h->L.spm_node);
+    d.spm_val = reinterpret_cast<float *>(w + h->L.spm_val);
+    d.spm_tail = reinterpret_cast<int32_t *>(w + h->L.spm_tail);
+  }
+  d.tours = reinterpret_cast<int32_t *>(w + h->L.tours);
+  d.lens = reinterpret_cast<int64_t *>(w + h->L.lens);
+  d.best = reinterpret_cast<int32_t *>(w + h->L.best);
+  d.gstate = reinterpret_cast<int64_t *>(w + h->L.gstate);
+  d.counters = reinterpret_cast<unsigned long long *>(w + h->L.counters);
+  d.sync = reinterpret_cast<uint32_t *>(w + h->L.sync);
+
+  if (p->mode == ACS_SYNC) {
+    const int cap = acs::max_sync_ants(d, (int)p->memory);
+    if (m > cap)
+      return bail(fail(ACS_E_UNSUPPORTED, "m = %d ants exceed the %d one synchronous launch holds",
+                       m, cap));
+  }
+  rc = build(h, coords_xy);
+  if (rc) return bail(rc);
+  {
+    std::lock_guard<std::mutex> g(g_live_mu);
+    g_live.insert(h);
+  }
+  *out = h;
+  return ACS_OK;
+}
+
+int acs_iterate(acs_t *h, int32_t k) {
+  if (!live(h)) return fail(ACS_E_STATE, "invalid handle");
+  if (k < 0) return fail(ACS_E_INVALID, "k < 0");
+  if (k == 0) return ACS_OK;
+  while ((int)h->ev.size() < 2 * k) {
+    hipEvent_t e;
+    HIP_TRY(hipEventCreate(&e));
+    h->ev.push_back(e);
+  }
+  HIP_TRY(hipEventRecord(h->ev_begin, h->stream));
+  for (int i = 0; i < k; ++i) {
+    acs::Iter it = h->base;
+    it.it = h->iter + (uint32_t)i;
+    HIP_TRY(hipEventRecord(h->ev[2 * i], h->stream));
+    HIP_TRY(acs::launch_construct(h->dev, it, (int)h->p.mode, (int)h->p.memory, h->stream));
+    HIP_TRY(hipEventRecord(h->ev[2 * i + 1], h->stream));
+    HIP_TRY(acs::launch_best_global(h->dev, it, (int)h->p.memory, h->stream));
+  }
+  HIP_TRY(hipEventRecord(h->ev_end, h->stream));
+  int rc = sync_and_check(h);
+  h->iter += (uint32_t)k;
+  if (rc) return rc;
+  double cms = 0.0;
+  for (int i = 0; i < k; ++i) {
+    float ms = 0.f;
+    HIP_TRY(hipEventElapsedTime(&ms, h->ev[2 * i], h->ev[2 * i + 1]));
+    cms += ms;
+  }
+  float total = 0.f;
+  HIP_TRY(hipEventElapsedTime(&total, h->ev_begin, h->ev_end));
+  h->construct_ms = cms;
+  h->construct_launches = k;
+  h->iterate_ms = total;
+  return ACS_OK;
+}
+
+int acs_best_tour(acs_t *h, int32_t *tour_out, int64_t *len_out) {
+  if (!live(h)) return fail(ACS_E_STATE, "invalid handle");
+  int64_t g[3];
+  HIP_TRY(hipStreamSynchronize(h->stream));
+  HIP_TRY(hipMemcpy(g, h->ws + h->L.gstate, sizeof g, hipMemcpyDeviceToHost));
+  if (g[0] < 0) return fail(ACS_E_STATE, "no iteration has run yet");
+  if (len_out) *len_out = g[0];
+  if (tour_out)
+    HIP_TRY(hipMemcpy(tour_out, h->ws + h->L.best, sizeof(int32_t) * h->n, hipMemcpyDeviceToHost));
+  return ACS_OK;
+}
+
+int acs_pheromone_snapshot(acs_t *h, float *out, size_t count) {
+  if (!live(h)) return fail(ACS_E_STATE, "invalid handle");
+  if (h->p.memory != ACS_DENSE) return fail(ACS_E_UNSUPPORTED, "not a dense handle");
+  const size_t n = (size_t)h->n, ldn = (size_t)h->ldn, cl = (size_t)h->cl;
+  if (!out || count < n * n) return fail(ACS_E_BUFSIZE, "need %zu floats", n * n);
+  HIP_TRY(hipStreamSynchronize(h->stream));
+  HIP_TRY(hipMemcpy2D(out, n * sizeof(float), h->ws + h->L.tau, ldn * sizeof(float),
+                      n * sizeof(float), n, hipMemcpyDeviceToHost));
+  std::vector<float> tnn(n * cl);
+  std::vector<int32_t> cand(n * cl);
+  HIP_TRY(hipMemcpy(tnn.data(), h->ws + h->L.tau_nn, tnn.size() * sizeof(float),
+                    hipMemcpyDeviceToHost));
+  HIP_TRY(hipMemcpy(cand.data(), h->ws + h->L.cand, cand.size() * sizeof(int32_t),
+                    hipMemcpyDeviceToHost));
+  // candidate entries live in the candidate-major array
+  for (size_t i = 0; i < n; ++i)
+    for (size_t k = 0; k < cl; ++k) out[i * n + (size_t)cand[i * cl + k]] = tnn[i * cl + k];
+  return ACS_OK;
+}
+
+int acs_spm_snapshot(acs_t *h, int32_t *nodes, float *vals, int32_t *tail) {
+  if (!live(h)) return fail(ACS_E_STATE, "invalid handle");
+  if (h->p.memory != ACS_SPM) return fail(ACS_E_UNSUPPORTED, "not an SPM handle");
+  if (!nodes || !vals || !tail) return fail(ACS_E_INVALID, "NULL output");
+  const size_t ns = (size_t)h->n * h->p.spm_s;
+  HIP_TRY(hipStreamSynchronize(h->stream));
+  HIP_TRY(hipMemcpy(nodes, h->ws + h->L.spm_node, ns * sizeof(int32_t), hipMemcpyDeviceToHost));
+  HIP_TRY(hipMemcpy(vals, h->ws + h->L.spm_val, ns * sizeof(float), hipMemcpyDeviceToHost));
+  HIP_TRY(hipMemcpy(tail, h->ws + h->L.spm_tail, (size_t)h->n * sizeof(int32_t),
+                    hipMemcpyDeviceToHost));
+  return ACS_OK;
+}
+
+int acs_tours(acs_t *h, int32_t *out, size_t count) {
+  if (!live(h)) return fail(ACS_E_STATE, "invalid handle");
+  const size_t need = (size_t)h->m * h->n;
+  if (!out || count < need) return fail(ACS_E_BUFSIZE, "need %zu ints", need);
+  HIP_TRY(hipStreamSynchronize(h->stream));
+  HIP_TRY(hipMemcpy(out, h->ws + h->L.tours, need * sizeof(int32_t), hipMemcpyDeviceToHost));
+  return ACS_OK;
+}
+
+int acs_lengths(acs_t *h, int64_t *out, size_t count) {
+  if (!live(h)) return fail(ACS_E_STATE, "invalid handle");
+  if (!out || count < (size_t)h->m) return fail(ACS_E_BUFSIZE, "need %d values", h->m);
+  HIP_TRY(hipStreamSynchronize(h->stream));
+  HIP_TRY(hipMemcpy(out, h->ws + h->L.lens, (size_t)h->m * sizeof(int64_t),
+                    hipMemcpyDeviceToHost));
+  return ACS_OK;
+}
+
+int acs_candidates(acs_t *h, int32_t *out, size_t count) {
+  if (!live(h)) return fail(ACS_E_STATE, "invalid handle");
+  const size_t need = (size_t)h->n * h->cl;
+  if (!out || count < need) return fail(ACS_E_BUFSIZE, "need %zu ints", need);
+  HIP_TRY(hipStreamSynchronize(h->stream));
+  HIP_TRY(hipMemcpy(out, h->ws + h->L.cand, need * sizeof(int32_t), hipMemcpyDeviceToHost));
+  return ACS_OK;
+}
+
+int acs_stats(acs_t *h, acs_stats_t *out) {
+  if (!live(h)) return fail(ACS_E_STATE, "invalid handle");
+  if (!out) return fail(ACS_E_INVALID, "out is NULL");
+  if (out->struct_size != sizeof(acs_stats_t))
+    return fail(ACS_E_INVALID, "stats.struct_size %u != %zu", out->struct_size,
+                sizeof(acs_stats_t));
+  HIP_TRY(hipStreamSynchronize(h->stream));
+  int64_t g[3];
+  unsigned long long c[6];
+  HIP_TRY(hipMemcpy(g, h->ws + h->L.gstate, sizeof g, hipMemcpyDeviceToHost));
+  HIP_TRY(hipMemcpy(c, h->ws + h->L.counters, sizeof c, hipMemcpyDeviceToHost));
+  std::memset(out, 0, sizeof *out);
+  out->struct_size = sizeof(acs_stats_t);
+  out->iteration = h->iter;
+  out->best_length = g[0];
+  out->iter_best_length = g[1];
+  out->iter_best_ant = (int32_t)g[2];
+  out->n = h->n;
+  out->m = h->m;
+  out->cl = h->cl;
+  out->nn_length = h->lnn;
+  out->tau0 = h->tau0;
+  out->greedy = (int64_t)c[0];
+  out->roulette = (int64_t)c[1];
+  out->fallback = (int64_t)c[2];
+  out->spm_hits = (int64_t)c[3];
+  out->spm_misses = (int64_t)c[4];
+  out->fallback_unvisited = (int64_t)c[5];
+  out->steps = out->greedy + out->roulette + out->fallback;
+  out->construct_ms = h->construct_ms;
+  out->construct_launches = h->construct_launches;
+  out->iterate_ms = h->iterate_ms;
+  return ACS_OK;
+}
+
+void acs_destroy(acs_t *h) {
+  {
+    std::lock_guard<std::mutex> g(g_live_mu);
+    if (!h || !g_live.count(h)) return;
+    g_live.erase(h);
+  }
+  release(h);
+}
+
+const char *acs_last_error(void) { return g_err.c_str(); }
+
+}  // extern "C"

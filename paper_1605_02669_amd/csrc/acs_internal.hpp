@@ -1,0 +1,65 @@
+// Internal interface between the C-ABI host code (acs_api.cpp) and the HIP
+// kernels (acs_kernels.hip).  Not installed; not part of the public ABI.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace acs {
+
+// Static record of candidate k of city i (the cl nearest neighbours of
+// Sec. 3, sorted by (d, j)), one 16-byte load per lane:
+//   x = neighbour j, y = d(i, j), z = bits of eta^beta(d), w = position of i in
+//   the candidate list of j, or 0xffffffff if i is not a candidate of j.
+struct CandRec {
+  uint32_t j, d, eta, inv;
+};
+
+// Device view of one colony.  Row-major matrices use the padded stride ldn.
+struct Dev {
+  int32_t n, m, cl, ldn;
+  int32_t spm_s;
+  const double *xy;        // n x 2
+  const uint16_t *dist;    // n x ldn exact integer distances
+  const uint4 *crec;       // n x cl CandRec
+  const float *eta_tab;    // eta^beta indexed by distance (dmax + 1)
+  float *tau;              // dense: n x ldn, home of non-candidate entries
+  float *tau_nn;           // dense: n x cl, home of candidate entries
+  int32_t *spm_node;       // SPM: n x s (-1 empty)
+  float *spm_val;          // SPM: n x s
+  int32_t *spm_tail;       // SPM: n
+  int32_t *tours;          // m x n
+  int64_t *lens;           // m
+  int32_t *best;           // n, best-so-far tour
+  int64_t *gstate;         // [0] L_gb (-1 none), [1] L_ib, [2] ib ant
+  unsigned long long *counters;  // greedy, roulette, fallback, hits, misses,
+                                 // unvisited cities at fallback steps
+  uint32_t *sync;          // [0] grid barrier counter, [1] error flag
+};
+
+// Per-iteration scalars.
+struct Iter {
+  uint32_t it, instance, key0, key1;
+  uint32_t q0_24;
+  float a_loc, b_loc, a_glob;
+  float tau0;
+  double rho;
+};
+
+// ---- instance preparation ----
+hipError_t launch_dist(const Dev &d, uint32_t *dmax, hipStream_t s);
+hipError_t launch_cand(const Dev &d, int32_t *cand_tmp, hipStream_t s);
+hipError_t launch_nn_tour(const Dev &d, int64_t *lnn_out, hipStream_t s);
+hipError_t launch_crec(const Dev &d, const int32_t *cand_tmp, hipStream_t s);
+hipError_t launch_init_pheromone(const Dev &d, float tau0, hipStream_t s);
+
+// ---- one iteration ----
+// Construction of all m tours.  mode 0 = synchronous steps (cooperative
+// persistent launch), 1 = asynchronous with atomic local updates.
+hipError_t launch_construct(const Dev &d, const Iter &it, int mode,
+                            int memory, hipStream_t s);
+// Largest m a synchronous launch can keep resident for this instance.
+int max_sync_ants(const Dev &d, int memory);
+hipError_t launch_best_global(const Dev &d, const Iter &it, int memory,
+                              hipStream_t s);
+
+}  // namespace acs
