@@ -96,6 +96,8 @@ typedef struct acs_stats {
   int64_t spm_misses;        /* SPM updates that inserted it */
   int64_t fallback_unvisited;/* sum over fallback steps of the unvisited
                                 cities the greedy scan had to consider */
+  int64_t cas_retries;       /* local-update compare-and-swaps that found
+                                the entry changed and were repeated */
   double construct_ms;       /* device time of the construction kernels of
                                 the last acs_iterate call (HIP events) */
   int32_t construct_launches;/* construction launches of that call */

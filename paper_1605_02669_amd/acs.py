@@ -46,7 +46,7 @@ class acs_stats_t(C.Structure):
         ("nn_length", C.c_int64), ("tau0", C.c_float), ("pad0", C.c_float),
         ("steps", C.c_int64), ("greedy", C.c_int64), ("roulette", C.c_int64),
         ("fallback", C.c_int64), ("spm_hits", C.c_int64), ("spm_misses", C.c_int64),
-        ("fallback_unvisited", C.c_int64),
+        ("fallback_unvisited", C.c_int64), ("cas_retries", C.c_int64),
         ("construct_ms", C.c_double), ("construct_launches", C.c_int32), ("pad1", C.c_int32),
         ("iterate_ms", C.c_double),
     ]

@@ -46,7 +46,7 @@ size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
 
 // Device buffers of one handle, as offsets into one allocation.
 struct Layout {
-  size_t xy, dist, crec, cand, eta, tau, tau_nn, spm_node, spm_val, spm_tail, tours, lens,
+  size_t xy, dist, crec, cand, eta, tau, spm_node, spm_val, spm_tail, tours, lens,
       best, gstate, counters, sync, dmax, lnn, total;
 };
 
@@ -67,7 +67,6 @@ Layout make_layout(int n, int m, int cl, int ldn, int memory, int s) {
   L.eta = take(sizeof(float) * kEtaEntries);
   if (memory == ACS_DENSE) {
     L.tau = take(sizeof(float) * (size_t)n * ldn);
-    L.tau_nn = take(sizeof(float) * (size_t)n * cl);
   } else {
     L.spm_node = take(sizeof(int32_t) * (size_t)n * s);
     L.spm_val = take(sizeof(float) * (size_t)n * s);
@@ -189,7 +188,7 @@ int build(acs_t *h, const double *xy) {
   for (uint32_t d = 0; d <= dmax; ++d) eta[d] = eta_beta(p.beta, d);
   HIP_TRY(hipMemcpyAsync(h->ws + h->L.eta, eta.data(), sizeof(float) * kEtaEntries,
                          hipMemcpyHostToDevice, h->stream));
-  HIP_TRY(acs::launch_crec(h->dev, cand, h->stream));
+  HIP_TRY(acs::launch_crec(h->dev, cand, h->tau0, h->stream));
   HIP_TRY(acs::launch_init_pheromone(h->dev, h->tau0, h->stream));
   HIP_TRY(hipStreamSynchronize(h->stream));
 
@@ -307,7 +306,6 @@ int acs_create(const double *coords_xy, int32_t n, const acs_params *p, acs_t **
   d.eta_tab = reinterpret_cast<const float *>(w + h->L.eta);
   if (p->memory == ACS_DENSE) {
     d.tau = reinterpret_cast<float *>(w + h->L.tau);
-    d.tau_nn = reinterpret_cast<float *>(w + h->L.tau_nn);
   } else {
     d.spm_node = reinterpret_cast<int32_t *>(w + h->L.spm_node);
     d.spm_val = reinterpret_cast<float *>(w + h->L.spm_val);
@@ -392,15 +390,15 @@ int acs_pheromone_snapshot(acs_t *h, float *out, size_t count) {
   HIP_TRY(hipStreamSynchronize(h->stream));
   HIP_TRY(hipMemcpy2D(out, n * sizeof(float), h->ws + h->L.tau, ldn * sizeof(float),
                       n * sizeof(float), n, hipMemcpyDeviceToHost));
-  std::vector<float> tnn(n * cl);
-  std::vector<int32_t> cand(n * cl);
-  HIP_TRY(hipMemcpy(tnn.data(), h->ws + h->L.tau_nn, tnn.size() * sizeof(float),
+  std::vector<uint32_t> rec(n * cl * 4);
+  HIP_TRY(hipMemcpy(rec.data(), h->ws + h->L.crec, rec.size() * sizeof(uint32_t),
                     hipMemcpyDeviceToHost));
-  HIP_TRY(hipMemcpy(cand.data(), h->ws + h->L.cand, cand.size() * sizeof(int32_t),
-                    hipMemcpyDeviceToHost));
-  // candidate entries live in the candidate-major array
-  for (size_t i = 0; i < n; ++i)
-    for (size_t k = 0; k < cl; ++k) out[i * n + (size_t)cand[i * cl + k]] = tnn[i * cl + k];
+  // candidate entries live in the last word of the candidate records
+  for (size_t e = 0; e < n * cl; ++e) {
+    float v;
+    std::memcpy(&v, &rec[4 * e + 3], sizeof v);
+    out[(e / cl) * n + rec[4 * e]] = v;
+  }
   return ACS_OK;
 }
 
@@ -452,7 +450,7 @@ int acs_stats(acs_t *h, acs_stats_t *out) {
                 sizeof(acs_stats_t));
   HIP_TRY(hipStreamSynchronize(h->stream));
   int64_t g[3];
-  unsigned long long c[6];
+  unsigned long long c[7];
   HIP_TRY(hipMemcpy(g, h->ws + h->L.gstate, sizeof g, hipMemcpyDeviceToHost));
   HIP_TRY(hipMemcpy(c, h->ws + h->L.counters, sizeof c, hipMemcpyDeviceToHost));
   std::memset(out, 0, sizeof *out);
@@ -472,6 +470,7 @@ int acs_stats(acs_t *h, acs_stats_t *out) {
   out->spm_hits = (int64_t)c[3];
   out->spm_misses = (int64_t)c[4];
   out->fallback_unvisited = (int64_t)c[5];
+  out->cas_retries = (int64_t)c[6];
   out->steps = out->greedy + out->roulette + out->fallback;
   out->construct_ms = h->construct_ms;
   out->construct_launches = h->construct_launches;

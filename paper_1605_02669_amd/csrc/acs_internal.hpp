@@ -6,13 +6,10 @@
 
 namespace acs {
 
-// Static record of candidate k of city i (the cl nearest neighbours of
-// Sec. 3, sorted by (d, j)), one 16-byte load per lane:
-//   x = neighbour j, y = d(i, j), z = bits of eta^beta(d), w = position of i in
-//   the candidate list of j, or 0xffffffff if i is not a candidate of j.
-struct CandRec {
-  uint32_t j, d, eta, inv;
-};
+// Record of candidate k of city i (the cl nearest neighbours of Sec. 3,
+// sorted by (d, j)), one 16-byte load per lane:
+//   x = neighbour j, y = d(i, j), z = bits of eta^beta(d),
+//   w = bits of the pheromone tau(i, j) (the home of that directed entry).
 
 // Device view of one colony.  Row-major matrices use the padded stride ldn.
 struct Dev {
@@ -20,10 +17,9 @@ struct Dev {
   int32_t spm_s;
   const double *xy;        // n x 2
   const uint16_t *dist;    // n x ldn exact integer distances
-  const uint4 *crec;       // n x cl CandRec
+  const uint4 *crec;       // n x cl candidate records (see above)
   const float *eta_tab;    // eta^beta indexed by distance (dmax + 1)
   float *tau;              // dense: n x ldn, home of non-candidate entries
-  float *tau_nn;           // dense: n x cl, home of candidate entries
   int32_t *spm_node;       // SPM: n x s (-1 empty)
   float *spm_val;          // SPM: n x s
   int32_t *spm_tail;       // SPM: n
@@ -32,7 +28,8 @@ struct Dev {
   int32_t *best;           // n, best-so-far tour
   int64_t *gstate;         // [0] L_gb (-1 none), [1] L_ib, [2] ib ant
   unsigned long long *counters;  // greedy, roulette, fallback, hits, misses,
-                                 // unvisited cities at fallback steps
+                                 // unvisited cities at fallback steps,
+                                 // compare-and-swap retries
   uint32_t *sync;          // [0] grid barrier counter, [1] error flag
 };
 
@@ -49,7 +46,7 @@ struct Iter {
 hipError_t launch_dist(const Dev &d, uint32_t *dmax, hipStream_t s);
 hipError_t launch_cand(const Dev &d, int32_t *cand_tmp, hipStream_t s);
 hipError_t launch_nn_tour(const Dev &d, int64_t *lnn_out, hipStream_t s);
-hipError_t launch_crec(const Dev &d, const int32_t *cand_tmp, hipStream_t s);
+hipError_t launch_crec(const Dev &d, const int32_t *cand_tmp, float tau0, hipStream_t s);
 hipError_t launch_init_pheromone(const Dev &d, float tau0, hipStream_t s);
 
 // ---- one iteration ----

@@ -1,19 +1,22 @@
 // HIP kernels for the Ant Colony System hot path on gfx950 (MI355X).
 //
 // Method: Skinderowicz, "The GPU-based Parallel Ant Colony System" (JPDC
-// 2016), Sec. 3.  Layout and mapping are designed for CDNA4: one group of
-// LANES lanes (16, 32 or 64 of a 64-wide wavefront) per ant, the candidate
-// set evaluated one candidate per lane, the visited set as a bitmap in LDS,
-// the argmax and the roulette prefix sums as group-level reductions in a
-// fixed order, and the local update as a compare-and-swap loop applying the
-// exact map of Eq. 3.
+// 2016), Sec. 3.  The paper maps one ant to one 32-thread block and its 32
+// candidates to the threads; here one ant owns one 64-wide wavefront, the
+// candidates sit one per lane, and every decision of the ant (which branch of
+// Eq. 1, which candidate, the fallback) is wave-uniform, so it runs on the
+// scalar unit: reductions use DPP and permlane swaps (no LDS round trips),
+// the winning lane's values are read with readlane, the Philox draws are
+// scalar.  The visited set is a bitmap in LDS.
 //
-// Pheromone homes (dense memory): the value of the directed entry (i, j)
-// lives in tau_nn[i][k] when j is the k-th candidate of i, otherwise in
-// tau[i][j].  Reads of the candidate set are then one coalesced row of
-// tau_nn; the fallback scan only ever reads non-candidate entries of tau
-// (it runs only when every candidate is visited), so each entry has exactly
-// one home and every update goes to it.
+// Data layout (dense memory).  The static record of candidate k of city i
+// and the pheromone of that directed entry share one 16-byte slot,
+//   crec[i][k] = {j, d(i, j), eta^beta(d) bits, tau(i, j) bits},
+// so one step reads one coalesced 16-byte load per lane.  The pheromone of a
+// non-candidate entry (i, j) lives in tau[i][j] (n x ldn).  Every directed
+// entry therefore has exactly one home; the fallback scan only reads
+// non-candidate entries, because it runs only when every candidate is
+// visited.
 //
 // Compiled with -ffp-contract=off: every float expression is the written
 // sequence of IEEE operations; fmaf is used only for the pheromone maps.
@@ -80,64 +83,98 @@ __device__ __forceinline__ T wave_max(T v) {
   return v;
 }
 
-template <int LANES>
-__device__ __forceinline__ float group_max(float v) {
-#pragma unroll
-  for (int off = LANES / 2; off; off >>= 1) v = fmaxf(v, __shfl_xor(v, off, LANES));
-  return v;
+// Wave-wide unsigned max / min, all lanes active: quad and row permutations
+// by DPP, then the row-pair and half-wave swaps of gfx950.  Returns the
+// result as a wave-uniform value.
+__device__ __forceinline__ uint32_t wave_umax_u(uint32_t v) {
+  v = max(v, (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0xB1, 0xF, 0xF, false));
+  v = max(v, (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x4E, 0xF, 0xF, false));
+  v = max(v, (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x141, 0xF, 0xF, false));
+  v = max(v, (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x140, 0xF, 0xF, false));
+  const auto a = __builtin_amdgcn_permlane16_swap(v, v, false, false);
+  v = max(v, max((uint32_t)a[0], (uint32_t)a[1]));
+  const auto b = __builtin_amdgcn_permlane32_swap(v, v, false, false);
+  v = max(v, max((uint32_t)b[0], (uint32_t)b[1]));
+  return (uint32_t)__builtin_amdgcn_readfirstlane((int)v);
 }
 
-template <int LANES>
-__device__ __forceinline__ int group_min_i(int v) {
-#pragma unroll
-  for (int off = LANES / 2; off; off >>= 1) v = min(v, __shfl_xor(v, off, LANES));
-  return v;
+__device__ __forceinline__ uint32_t wave_umin_u(uint32_t v) {
+  v = min(v, (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0xB1, 0xF, 0xF, false));
+  v = min(v, (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x4E, 0xF, 0xF, false));
+  v = min(v, (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x141, 0xF, 0xF, false));
+  v = min(v, (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x140, 0xF, 0xF, false));
+  const auto a = __builtin_amdgcn_permlane16_swap(v, v, false, false);
+  v = min(v, min((uint32_t)a[0], (uint32_t)a[1]));
+  const auto b = __builtin_amdgcn_permlane32_swap(v, v, false, false);
+  v = min(v, min((uint32_t)b[0], (uint32_t)b[1]));
+  return (uint32_t)__builtin_amdgcn_readfirstlane((int)v);
 }
 
-// Local or global map x -> fma(a, x, b) applied atomically to one entry.
-__device__ __forceinline__ void cas_map(float *p, float a, float b) {
+__device__ __forceinline__ uint32_t rdlane(uint32_t v, int k) {
+  return (uint32_t)__builtin_amdgcn_readlane((int)v, k);
+}
+
+__device__ __forceinline__ int uni(int v) { return __builtin_amdgcn_readfirstlane(v); }
+
+// Pheromone slot of candidate k in city u's record.
+__device__ __forceinline__ float *cand_tau(const Dev &D, int u, int k) {
+  return reinterpret_cast<float *>(const_cast<uint4 *>(D.crec) + (size_t)u * D.cl + k) + 3;
+}
+
+// Home of the directed entry (u, v): candidate slot k of u, or tau[u][v].
+__device__ __forceinline__ float *home(const Dev &D, int u, int v, int k) {
+  return k >= 0 ? cand_tau(D, u, k) : D.tau + (size_t)u * D.ldn + v;
+}
+
+// Agent-coherent read of one pheromone value (sees every CAS performed so
+// far on the device, whichever XCD performed it).
+__device__ __forceinline__ float tau_load(const float *p) {
+  return __uint_as_float(__hip_atomic_load(reinterpret_cast<const unsigned int *>(p),
+                                           __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
+}
+
+// Local or global map x -> fma(a, x, b), applied atomically.  `seen` is the
+// value the caller believes the entry holds; a failed compare-and-swap (the
+// entry changed meanwhile) retries with the value it returned.  Returns the
+// number of retries.
+__device__ __forceinline__ uint32_t cas_apply(float *p, unsigned int seen, float a, float b) {
   unsigned int *q = reinterpret_cast<unsigned int *>(p);
-  unsigned int old = __hip_atomic_load(q, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  unsigned int old = seen;
+  uint32_t retries = 0;
   while (true) {
     const unsigned int nw = __float_as_uint(fmaf(a, __uint_as_float(old), b));
     const unsigned int prev = atomicCAS(q, old, nw);
     if (prev == old) break;
     old = prev;
+    ++retries;
   }
+  return retries;
 }
 
-// Home of the directed pheromone entry (u, v) when the candidate position of
-// v in u's list is already known (k >= 0) or not in it (k < 0).
-__device__ __forceinline__ float *home(const Dev &D, int u, int v, int k) {
-  return k >= 0 ? D.tau_nn + (size_t)u * D.cl + k : D.tau + (size_t)u * D.ldn + v;
+// Position of v in the candidate list of u (wave-uniform), or -1.
+__device__ __forceinline__ int cand_pos(const Dev &D, int u, int v, int lane) {
+  const int kl = lane < D.cl ? lane : D.cl - 1;
+  const uint32_t j = D.crec[(size_t)u * D.cl + kl].x;
+  const uint64_t b = __ballot(lane < D.cl && j == (uint32_t)v);
+  return b ? (int)__ffsll((unsigned long long)b) - 1 : -1;
 }
 
-// Position of v in the candidate list of u, or -1: one probe per lane.
-template <int LANES>
-__device__ __forceinline__ int cand_pos(const Dev &D, int u, int v, int g, uint64_t gmask,
-                                        int gbase) {
-  bool hit = false;
-  for (int k0 = 0; k0 < D.cl; k0 += LANES) {
-    const int k = k0 + g;
-    hit = k < D.cl && D.crec[(size_t)u * D.cl + k].x == (uint32_t)v;
-    const uint64_t b = __ballot(hit) & gmask;
-    if (b) return k0 + (__ffsll((unsigned long long)b) - 1 - gbase);
-  }
-  return -1;
-}
-
-// Grid-wide barrier for a cooperative launch: every wave publishes its
-// writes at agent scope, one arrival per block on a monotonically growing
-// counter, and every wave acquires after the wait.  The wait is bounded: on
-// exhaustion an error flag is raised and the kernel runs on, so it always
-// terminates.
+// Grid-wide barrier for a cooperative launch.  Every wave waits for its own
+// memory operations first (the local updates are compare-and-swaps whose
+// results have been consumed, so they are performed at the device's
+// coherence point); one thread per block then arrives on a monotonically
+// growing counter and waits for all blocks.  Readers after the barrier use
+// agent-coherent loads for everything the updates touch, so no cache
+// write-back or invalidation is needed.  The wait is bounded: on exhaustion
+// an error flag is raised, later barriers no longer wait, and the kernel
+// runs to its end.
 __device__ __forceinline__ void grid_barrier(uint32_t *sync, uint32_t target) {
-  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+  __builtin_amdgcn_s_waitcnt(0);
   __syncthreads();
   if (threadIdx.x == 0) {
-    __hip_atomic_fetch_add(sync, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+    __hip_atomic_fetch_add(sync, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     uint32_t spins = 0;
-    while (__hip_atomic_load(sync, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) < target) {
+    while (__hip_atomic_load(sync, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < target) {
       // once any block has given up, no later barrier waits either
       if (__hip_atomic_load(sync + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) break;
       __builtin_amdgcn_s_sleep(1);
@@ -148,7 +185,7 @@ __device__ __forceinline__ void grid_barrier(uint32_t *sync, uint32_t target) {
     }
   }
   __syncthreads();
-  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+  __atomic_signal_fence(__ATOMIC_SEQ_CST);
 }
 
 // ---------------------------------------------------------------------------
@@ -221,23 +258,21 @@ __global__ __launch_bounds__(1024) void k_nn_tour(Dev D, int64_t *lnn) {
   if (tid == 0) *lnn = L + D.dist[(size_t)cur * D.ldn];
 }
 
-__global__ __launch_bounds__(256) void k_crec(Dev D, const int32_t *cand) {
+// Candidate records with the initial pheromone tau0 in the last word.
+__global__ __launch_bounds__(256) void k_crec(Dev D, const int32_t *cand, float tau0) {
   const int e = blockIdx.x * 256 + threadIdx.x;
   if (e >= D.n * D.cl) return;
   const int i = e / D.cl;
   const uint32_t c = (uint32_t)cand[e];
   const uint32_t d = D.dist[(size_t)i * D.ldn + c];
-  uint32_t inv = kNone;
-  for (int q = 0; q < D.cl; ++q)
-    if (cand[(size_t)c * D.cl + q] == i) { inv = (uint32_t)q; break; }
-  const_cast<uint4 *>(D.crec)[e] = make_uint4(c, d, __float_as_uint(D.eta_tab[d]), inv);
+  const_cast<uint4 *>(D.crec)[e] =
+      make_uint4(c, d, __float_as_uint(D.eta_tab[d]), __float_as_uint(tau0));
 }
 
 __global__ __launch_bounds__(256) void k_init(Dev D, float tau0) {
   const size_t e = (size_t)blockIdx.x * 256 + threadIdx.x;
   const size_t nd = (size_t)D.n * D.ldn;
   if (D.tau && e < nd) D.tau[e] = tau0;
-  if (D.tau_nn && e < (size_t)D.n * D.cl) D.tau_nn[e] = tau0;
   if (D.spm_node && e < (size_t)D.n * D.spm_s) {
     D.spm_node[e] = -1;
     D.spm_val[e] = tau0;
@@ -254,145 +289,295 @@ __global__ __launch_bounds__(256) void k_init(Dev D, float tau0) {
 }
 
 // ---------------------------------------------------------------------------
-// Construction, dense pheromone memory (Alg. 1 steps, Alg. 2 per ant).
-// One group of LANES lanes per ant; lane g < cl evaluates candidate g.
-// SYNC = true: persistent cooperative kernel, every step is
-//   SELECT (reads only) | grid barrier | UPDATE (Eq. 3 by CAS) | grid barrier.
-// SYNC = false: no barriers, the update follows each ant's own move.
+// One step of Alg. 2 for the ant of this wave (dense memory).  `rec` is lane
+// k's record of the current city (lanes >= cl hold a copy of the last one).
+// Wave-uniform result.
 // ---------------------------------------------------------------------------
-template <int LANES, bool SYNC>
-__global__ __launch_bounds__(256) void k_construct_dense(Dev D, Iter A) {
-  extern __shared__ uint32_t smem[];
-  const int apb = blockDim.x / LANES;
-  const int lane = threadIdx.x & 63;
-  const int g = threadIdx.x & (LANES - 1);
-  const int grp = threadIdx.x / LANES;
-  const int gbase = lane & ~(LANES - 1);
-  const uint64_t gmask =
-      LANES == 64 ? ~0ull : (((1ull << (LANES & 63)) - 1ull) << gbase);
-  const int ant = blockIdx.x * apb + grp;
-  const bool active = ant < D.m;
-  const int n = D.n, cl = D.cl, ldn = D.ldn;
-  const int W = (n + 31) >> 5;
-  uint32_t *vis = smem + grp * W;
+struct Pick {
+  int next;    // chosen city
+  int k;       // its candidate position, -1 for the fallback
+  uint32_t d;  // d(cur, next)
+  float tval;  // pheromone of the entry (cur, next) as read
+  int kind;    // 0 greedy (Eq. 1), 1 roulette (Eq. 2), 2 fallback
+};
 
-  for (int w = g; w < W; w += LANES) vis[w] = 0u;
+template <bool COHERENT>
+__device__ __forceinline__ Pick select_dense(const Dev &D, const Iter &A, const uint32_t *vis,
+                                             int cur, int lane, uint4 rec, uint4 rnd) {
+  const int n = D.n, cl = D.cl;
+  const bool unv = lane < cl && !((vis[rec.x >> 5] >> (rec.x & 31)) & 1u);
+  // tau * eta^beta >= 0, so its bit pattern orders like the value
+  const float w = unv ? __uint_as_float(rec.w) * __uint_as_float(rec.z) : 0.f;
+  const uint64_t umask = __ballot(unv);
+  Pick p;
+  if (umask) {
+    int k;
+    if ((rnd.x >> 8) < A.q0_24) {
+      // Eq. 1, exploitation: maximum of tau * eta^beta, lowest position
+      const uint32_t mx = wave_umax_u(__float_as_uint(w));
+      const uint64_t sel = __ballot(unv && __float_as_uint(w) == mx);
+      k = (int)__ffsll((unsigned long long)sel) - 1;
+      p.kind = 0;
+    } else {
+      // Eq. 2 by roulette: inclusive Hillis-Steele scan over the positions
+      // (offsets 1, 2, 4, ... < cl), r = u * total, first member of the
+      // candidate set whose prefix sum exceeds r
+      float P = w;
+      for (int off = 1; off < cl; off <<= 1) {
+        const float o = __shfl_up(P, off, 64);
+        if (lane >= off) P = P + o;
+      }
+      const float total = __uint_as_float(rdlane(__float_as_uint(P), cl - 1));
+      const float r = ((float)(rnd.y >> 8) * 0x1p-24f) * total;
+      const uint64_t sel = __ballot(unv && P > r);
+      k = sel ? (int)__ffsll((unsigned long long)sel) - 1 : 63 - (int)__clzll((long long)umask);
+      p.kind = 1;
+    }
+    k = uni(k);
+    p.k = k;
+    p.next = (int)rdlane(rec.x, k);
+    p.d = rdlane(rec.y, k);
+    p.tval = __uint_as_float(rdlane(rec.w, k));
+    return p;
+  }
+  // Alg. 2, empty candidate set: greedy over every unvisited city, ties ->
+  // lowest index.  Each lane scans four consecutive cities per round.
+  const float *trow = D.tau + (size_t)cur * D.ldn;
+  const uint16_t *drow = D.dist + (size_t)cur * D.ldn;
+  float bv = 0.f, bt = 0.f;
+  uint32_t bj = kNone, bd = 0;
+  for (int j0 = 4 * lane; j0 < n; j0 += 256) {
+    uint32_t bits = (vis[j0 >> 5] >> (j0 & 31)) & 0xfu;
+    if (j0 + 4 > n) bits |= (0xfu << (n - j0)) & 0xfu;
+    if (bits != 0xfu) {
+      float tq[4];
+      if (COHERENT) {
+#pragma unroll
+        for (int q = 0; q < 4; ++q) tq[q] = tau_load(trow + j0 + q);
+      } else {
+        const float4 tv = *reinterpret_cast<const float4 *>(trow + j0);
+        tq[0] = tv.x; tq[1] = tv.y; tq[2] = tv.z; tq[3] = tv.w;
+      }
+      const ushort4 dv = *reinterpret_cast<const ushort4 *>(drow + j0);
+      const uint32_t dq[4] = {dv.x, dv.y, dv.z, dv.w};
+#pragma unroll
+      for (int q = 0; q < 4; ++q)
+        if (!((bits >> q) & 1u)) {
+          const float v = tq[q] * D.eta_tab[dq[q]];
+          if (bj == kNone || v > bv) { bv = v; bj = (uint32_t)(j0 + q); bt = tq[q]; bd = dq[q]; }
+        }
+    }
+  }
+  const uint32_t mx = wave_umax_u(bj == kNone ? 0u : __float_as_uint(bv));
+  const uint32_t jn = wave_umin_u((bj != kNone && __float_as_uint(bv) == mx) ? bj : kNone);
+  const uint64_t own = __ballot(bj == jn);
+  const int owner = uni((int)__ffsll((unsigned long long)own) - 1);
+  p.k = -1;
+  p.next = (int)jn;
+  p.d = rdlane(bd, owner);
+  p.tval = __uint_as_float(rdlane(__float_as_uint(bt), owner));
+  p.kind = 2;
+  return p;
+}
+
+__device__ __forceinline__ void add_counters(const Dev &D, uint32_t greedy, uint32_t roul,
+                                             uint32_t fb, uint64_t fbu, uint32_t retries) {
+  atomicAdd(&D.counters[0], (unsigned long long)greedy);
+  atomicAdd(&D.counters[1], (unsigned long long)roul);
+  atomicAdd(&D.counters[2], (unsigned long long)fb);
+  atomicAdd(&D.counters[5], (unsigned long long)fbu);
+  atomicAdd(&D.counters[6], (unsigned long long)retries);
+}
+
+// Tour entries are collected 64 at a time in one register (lane t % 64 holds
+// entry t) and written with one coalesced store per 64 steps.
+__device__ __forceinline__ void tour_put(const Dev &D, int ant, int t, int lane, int city,
+                                         int &buf) {
+  buf = lane == (t & 63) ? city : buf;
+  if ((t & 63) == 63 || t == D.n - 1) {
+    const int base = t & ~63;
+    if (lane <= (t & 63)) D.tours[(size_t)ant * D.n + base + lane] = buf;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Synchronous construction, dense memory: persistent cooperative kernel, one
+// ant per wave.  Step t is
+//   SELECT (reads only, from the pheromone at the start of the step)
+//   | barrier | UPDATE (Eq. 3 on both entries of each crossing, by CAS)
+//   | barrier.
+// The map is the same for every crossing, so the order of the updates of one
+// step does not change the result: an entry crossed k times gets f^k.
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(1024) void k_construct_sync_dense(Dev D, Iter A) {
+  extern __shared__ uint32_t smem[];
+  const int lane = threadIdx.x & 63;
+  const int wv = threadIdx.x >> 6;
+  const int ant = uni(blockIdx.x * (blockDim.x >> 6) + wv);
+  const bool active = ant < D.m;
+  const int n = D.n, cl = D.cl;
+  const int W = (n + 31) >> 5;
+  const int kl = lane < cl ? lane : cl - 1;
+  uint32_t *vis = smem + wv * W;
+
+  for (int w = lane; w < W; w += 64) vis[w] = 0u;
   const uint4 r0 = philox10(make_uint4(0u, (uint32_t)ant, A.it, A.instance), A.key0, A.key1);
   const int start = (int)__umulhi(r0.z, (uint32_t)n);
-  if (g == 0) vis[start >> 5] |= 1u << (start & 31);
-  if (g == 0 && active) D.tours[(size_t)ant * n] = start;
+  if (lane == 0) vis[start >> 5] |= 1u << (start & 31);
+  int tb = start;
 
   int cur = start;
   int64_t len = 0;
-  uint32_t c_greedy = 0, c_roul = 0, c_fb = 0;
-  uint64_t c_fbu = 0;  // unvisited cities scanned by fallbacks
-  uint32_t bar = 0;  // barriers passed (sync)
-
+  uint32_t c_greedy = 0, c_roul = 0, c_fb = 0, c_retry = 0;
+  uint64_t c_fbu = 0;
+  uint32_t bar = 0;
   for (int t = 1; t < n; ++t) {
-    int next = 0, kstar = -1;
-    uint32_t dnext = 0, inv = kNone;
+    Pick p{};
     if (active) {
-      uint4 rec = make_uint4(0, 0, 0, kNone);
-      float tn = 0.f;
-      if (g < cl) {
-        rec = D.crec[(size_t)cur * cl + g];
-        tn = D.tau_nn[(size_t)cur * cl + g];
-      }
+      uint4 rec = D.crec[(size_t)cur * cl + kl];
+      rec.w = __float_as_uint(tau_load(cand_tau(D, cur, kl)));
       const uint4 rnd = philox10(make_uint4((uint32_t)t, (uint32_t)ant, A.it, A.instance), A.key0, A.key1);
-      bool unv = false;
-      float w = 0.f;
-      if (g < cl) {
-        unv = !((vis[rec.x >> 5] >> (rec.x & 31)) & 1u);
-        w = unv ? tn * __uint_as_float(rec.z) : 0.f;
-      }
-      const uint64_t umask = __ballot(unv) & gmask;
-      if (umask) {
-        if ((rnd.x >> 8) < A.q0_24) {
-          // Eq. 1, exploitation: argmax of tau * eta^beta, lowest position
-          const float mv = group_max<LANES>(unv ? w : -1.f);
-          const uint64_t sel = __ballot(unv && w == mv) & gmask;
-          kstar = __ffsll((unsigned long long)sel) - 1 - gbase;
-          ++c_greedy;
-        } else {
-          // Eq. 2 by roulette: Hillis-Steele inclusive scan over positions
-          float P = w;
-          for (int off = 1; off < cl; off <<= 1) {
-            const float o = __shfl_up(P, off, LANES);
-            if (g >= off) P = P + o;
-          }
-          const float total = __shfl(P, cl - 1, LANES);
-          const float u = (float)(rnd.y >> 8) * 0x1p-24f;
-          const float r = u * total;
-          const uint64_t sel = __ballot(unv && P > r) & gmask;
-          kstar = sel ? __ffsll((unsigned long long)sel) - 1 - gbase
-                      : 63 - __clzll((long long)umask) - gbase;
-          ++c_roul;
-        }
-        next = (int)__shfl(rec.x, kstar, LANES);
-        dnext = __shfl(rec.y, kstar, LANES);
-        inv = __shfl(rec.w, kstar, LANES);
-      } else {
-        // Alg. 2, empty candidate set: greedy over every unvisited city,
-        // ties -> lowest index.  Four consecutive cities per lane.
-        const float *trow = D.tau + (size_t)cur * ldn;
-        const uint16_t *drow = D.dist + (size_t)cur * ldn;
-        float bv = -1.f;
-        int bj = INT_MAX;
-        for (int j0 = 4 * g; j0 < n; j0 += 4 * LANES) {
-          uint32_t bits = (vis[j0 >> 5] >> (j0 & 31)) & 0xfu;
-          if (j0 + 4 > n) bits |= (0xfu << (n - j0)) & 0xfu;
-          if (bits != 0xfu) {
-            const float4 tv = *reinterpret_cast<const float4 *>(trow + j0);
-            const ushort4 dv = *reinterpret_cast<const ushort4 *>(drow + j0);
-            const float tq[4] = {tv.x, tv.y, tv.z, tv.w};
-            const uint32_t dq[4] = {dv.x, dv.y, dv.z, dv.w};
-#pragma unroll
-            for (int q = 0; q < 4; ++q)
-              if (!((bits >> q) & 1u)) {
-                const float v = tq[q] * D.eta_tab[dq[q]];
-                if (v > bv) { bv = v; bj = j0 + q; }
-              }
-          }
-        }
-        const float mv = group_max<LANES>(bv);
-        next = group_min_i<LANES>(bv == mv ? bj : INT_MAX);
-        dnext = drow[next];
-        ++c_fb;
-        c_fbu += (uint64_t)(n - t);
-      }
-      if (g == 0) {
-        vis[next >> 5] |= 1u << (next & 31);
-        D.tours[(size_t)ant * n + t] = next;
-      }
-      len += dnext;
+      p = select_dense<true>(D, A, vis, cur, lane, rec, rnd);
+      c_greedy += p.kind == 0;
+      c_roul += p.kind == 1;
+      if (p.kind == 2) { ++c_fb; c_fbu += (uint64_t)(n - t); }
+      if (lane == 0) vis[p.next >> 5] |= 1u << (p.next & 31);
+      tour_put(D, ant, t, lane, p.next, tb);
+      len += p.d;
     }
-    if (SYNC) grid_barrier(D.sync, (++bar) * gridDim.x);
+    grid_barrier(D.sync, (++bar) * gridDim.x);
     if (active) {
-      // Eq. 3 on both directed entries of the crossed edge.
-      int k2;
-      if (kstar >= 0) k2 = inv == kNone ? -1 : (int)inv;
-      else k2 = cand_pos<LANES>(D, next, cur, g, gmask, gbase);
-      // lanes 0 and 1 update the two directed entries concurrently
-      float *h = g == 0 ? home(D, cur, next, kstar) : home(D, next, cur, k2);
-      if (g < 2) cas_map(h, A.a_loc, A.b_loc);
-      cur = next;
+      const int k2 = cand_pos(D, p.next, cur, lane);
+      float *h = lane == 0 ? home(D, cur, p.next, p.k) : home(D, p.next, cur, k2);
+      if (lane < 2) c_retry += cas_apply(h, __float_as_uint(p.tval), A.a_loc, A.b_loc);
+      cur = p.next;
     }
-    if (SYNC && t + 1 < n) grid_barrier(D.sync, (++bar) * gridDim.x);
+    if (t + 1 < n) grid_barrier(D.sync, (++bar) * gridDim.x);
   }
   if (active) {
-    // closing edge: length and local update (the last step's crossings)
-    len += D.dist[(size_t)cur * ldn + start];
-    const int k1 = cand_pos<LANES>(D, cur, start, g, gmask, gbase);
-    const int k2 = cand_pos<LANES>(D, start, cur, g, gmask, gbase);
-    float *h = g == 0 ? home(D, cur, start, k1) : home(D, start, cur, k2);
-    if (g < 2) cas_map(h, A.a_loc, A.b_loc);
-    if (g == 0) {
-      D.lens[ant] = len;
-      atomicAdd(&D.counters[0], (unsigned long long)c_greedy);
-      atomicAdd(&D.counters[1], (unsigned long long)c_roul);
-      atomicAdd(&D.counters[2], (unsigned long long)c_fb);
-      atomicAdd(&D.counters[5], (unsigned long long)c_fbu);
+    // closing edge: its length and, as the last step's crossings, its update
+    len += D.dist[(size_t)cur * D.ldn + start];
+    const int k1 = cand_pos(D, cur, start, lane);
+    const int k2 = cand_pos(D, start, cur, lane);
+    float *h = lane == 0 ? home(D, cur, start, k1) : home(D, start, cur, k2);
+    if (lane < 2) {
+      const float seen = tau_load(h);
+      c_retry += cas_apply(h, __float_as_uint(seen), A.a_loc, A.b_loc);
     }
+    c_retry = (uint32_t)uni((int)(rdlane(c_retry, 0) + rdlane(c_retry, 1)));
+    if (lane == 0) {
+      D.lens[ant] = len;
+      add_counters(D, c_greedy, c_roul, c_fb, c_fbu, c_retry);
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Asynchronous construction, dense memory: one launch per iteration, one ant
+// per wave, no waiting for the other ants.  After each move the local update
+// of Eq. 3 is a compare-and-swap of the exact map on both directed entries of
+// the crossed edge.
+//
+// The steps of one ant form a dependent chain, so the latency of a step sets
+// the iteration time.  Per step the wave issues the load of the next city's
+// record right after choosing it; the forward entry's CAS uses the value the
+// selection read as its expected value (no extra load before it); the
+// reverse entry is resolved one step later from the next city's record,
+// which holds its current value when the previous city is a candidate of the
+// next one; CAS results are checked one step after issue, and a failed CAS
+// (the entry changed meanwhile) is retried with the value it returned.
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void k_construct_async_dense(Dev D, Iter A) {
+  extern __shared__ uint32_t smem[];
+  const int lane = threadIdx.x & 63;
+  const int wv = threadIdx.x >> 6;
+  const int ant = uni(blockIdx.x * (blockDim.x >> 6) + wv);
+  if (ant >= D.m) return;  // the whole wave leaves; no block-level sync below
+  const int n = D.n, cl = D.cl, ldn = D.ldn;
+  const int W = (n + 31) >> 5;
+  const int kl = lane < cl ? lane : cl - 1;
+  uint32_t *vis = smem + wv * W;
+  const float al = A.a_loc, bl = A.b_loc;
+
+  for (int w = lane; w < W; w += 64) vis[w] = 0u;
+  const uint4 r0 = philox10(make_uint4(0u, (uint32_t)ant, A.it, A.instance), A.key0, A.key1);
+  const int start = (int)__umulhi(r0.z, (uint32_t)n);
+  if (lane == 0) vis[start >> 5] |= 1u << (start & 31);
+  int tb = start;
+  uint4 rec = D.crec[(size_t)start * cl + kl];
+
+  int cur = start, prev = -1;
+  float prev_tval = 0.f;
+  int64_t len = 0;
+  uint32_t c_greedy = 0, c_roul = 0, c_fb = 0, c_retry = 0;
+  uint64_t c_fbu = 0;
+  // compare-and-swap in flight: lane 0 forward entry, lane 1 reverse entry
+  float *pptr = nullptr;
+  unsigned int pexp = 0, pret = 0;
+  bool pend = false;
+
+  for (int t = 1; t < n; ++t) {
+    const uint4 rnd = philox10(make_uint4((uint32_t)t, (uint32_t)ant, A.it, A.instance), A.key0, A.key1);
+    // reverse entry (cur, prev) of the previous move, from cur's record
+    float *rptr = nullptr;
+    float rexp = prev_tval;
+    if (t > 1) {
+      const uint64_t b = __ballot(lane < cl && rec.x == (uint32_t)prev);
+      if (b) {
+        const int k = uni((int)__ffsll((unsigned long long)b) - 1);
+        rptr = cand_tau(D, cur, k);
+        rexp = __uint_as_float(rdlane(rec.w, k));
+      } else {
+        rptr = D.tau + (size_t)cur * ldn + prev;
+      }
+    }
+    const Pick p = select_dense<false>(D, A, vis, cur, lane, rec, rnd);
+    c_greedy += p.kind == 0;
+    c_roul += p.kind == 1;
+    if (p.kind == 2) { ++c_fb; c_fbu += (uint64_t)(n - t); }
+    if (lane == 0) vis[p.next >> 5] |= 1u << (p.next & 31);
+    tour_put(D, ant, t, lane, p.next, tb);
+    len += p.d;
+
+    rec = D.crec[(size_t)p.next * cl + kl];
+    if (pend && pret != pexp) c_retry += 1 + cas_apply(pptr, pret, al, bl);
+    pend = false;
+    if (lane == 0) {
+      pptr = home(D, cur, p.next, p.k);
+      pexp = __float_as_uint(p.tval);
+      pend = true;
+    } else if (lane == 1 && t > 1) {
+      pptr = rptr;
+      pexp = __float_as_uint(rexp);
+      pend = true;
+    }
+    if (pend)
+      pret = atomicCAS(reinterpret_cast<unsigned int *>(pptr), pexp,
+                       __float_as_uint(fmaf(al, __uint_as_float(pexp), bl)));
+    prev = cur;
+    prev_tval = p.tval;
+    cur = p.next;
+  }
+  if (pend && pret != pexp) c_retry += 1 + cas_apply(pptr, pret, al, bl);
+  // reverse entry of the last move, both entries of the closing edge
+  {
+    const uint64_t b = __ballot(lane < cl && rec.x == (uint32_t)prev);
+    const int kr = b ? uni((int)__ffsll((unsigned long long)b) - 1) : -1;
+    const float er = kr >= 0 ? __uint_as_float(rdlane(rec.w, kr)) : prev_tval;
+    const int k1 = cand_pos(D, cur, start, lane);
+    const int k2 = cand_pos(D, start, cur, lane);
+    float *h = lane == 0 ? home(D, cur, prev, kr)
+                         : (lane == 1 ? home(D, cur, start, k1) : home(D, start, cur, k2));
+    if (lane < 3) {
+      const float seen = lane == 0 ? er : tau_load(h);
+      c_retry += cas_apply(h, __float_as_uint(seen), al, bl);
+    }
+  }
+  len += D.dist[(size_t)cur * ldn + start];
+  c_retry = (uint32_t)uni((int)(rdlane(c_retry, 0) + rdlane(c_retry, 1) + rdlane(c_retry, 2)));
+  if (lane == 0) {
+    D.lens[ant] = len;
+    add_counters(D, c_greedy, c_roul, c_fb, c_fbu, c_retry);
   }
 }
 
@@ -458,38 +643,12 @@ __global__ __launch_bounds__(1024) void k_best_global_dense(Dev D, Iter A) {
   }
 }
 
-template <int LANES, bool SYNC>
-hipError_t launch_dense(const Dev &D, const Iter &A, hipStream_t s) {
-  const int block = SYNC ? 256 : 64;
-  const int apb = block / LANES;
-  const int grid = (D.m + apb - 1) / apb;
-  const size_t lds = (size_t)apb * ((D.n + 31) / 32) * sizeof(uint32_t);
-  if (SYNC) {
-    Dev d = D;
-    Iter a = A;
-    void *args[] = {&d, &a};
-    return hipLaunchCooperativeKernel(reinterpret_cast<void *>(&k_construct_dense<LANES, true>),
-                                      dim3(grid), dim3(block), args, lds, s);
-  }
-  hipLaunchKernelGGL((k_construct_dense<LANES, false>), dim3(grid), dim3(block), lds, s, D, A);
-  return hipGetLastError();
+size_t lds_bytes(const Dev &D, int block) {
+  return (size_t)(block / 64) * ((D.n + 31) / 32) * sizeof(uint32_t);
 }
 
-template <int LANES>
-int max_sync_dense(const Dev &D) {
-  const int block = 256;
-  const size_t lds = (size_t)(block / LANES) * ((D.n + 31) / 32) * sizeof(uint32_t);
-  int per_cu = 0;
-  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(
-          &per_cu, reinterpret_cast<const void *>(&k_construct_dense<LANES, true>), block, lds) !=
-      hipSuccess)
-    return 0;
-  int dev = 0, cus = 0;
-  if (hipGetDevice(&dev) != hipSuccess) return 0;
-  if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
-    return 0;
-  return per_cu * cus * (block / LANES);
-}
+constexpr int kSyncBlock = 1024;
+constexpr int kAsyncBlock = 256;
 
 }  // namespace
 
@@ -512,15 +671,14 @@ hipError_t launch_nn_tour(const Dev &d, int64_t *lnn_out, hipStream_t s) {
   return hipGetLastError();
 }
 
-hipError_t launch_crec(const Dev &d, const int32_t *cand_tmp, hipStream_t s) {
+hipError_t launch_crec(const Dev &d, const int32_t *cand_tmp, float tau0, hipStream_t s) {
   const int total = d.n * d.cl;
-  hipLaunchKernelGGL(k_crec, dim3((total + 255) / 256), dim3(256), 0, s, d, cand_tmp);
+  hipLaunchKernelGGL(k_crec, dim3((total + 255) / 256), dim3(256), 0, s, d, cand_tmp, tau0);
   return hipGetLastError();
 }
 
 hipError_t launch_init_pheromone(const Dev &d, float tau0, hipStream_t s) {
   size_t total = (size_t)d.n * d.ldn;
-  if (total < (size_t)d.n * d.cl) total = (size_t)d.n * d.cl;
   if (total < (size_t)d.n * d.spm_s) total = (size_t)d.n * d.spm_s;
   if (total < 8) total = 8;
   hipLaunchKernelGGL(k_init, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, s, d, tau0);
@@ -529,17 +687,34 @@ hipError_t launch_init_pheromone(const Dev &d, float tau0, hipStream_t s) {
 
 hipError_t launch_construct(const Dev &d, const Iter &it, int mode, int memory, hipStream_t s) {
   if (memory != 0) return hipErrorInvalidValue;
-  const bool sync = mode == 0;
-  if (d.cl <= 16) return sync ? launch_dense<16, true>(d, it, s) : launch_dense<16, false>(d, it, s);
-  if (d.cl <= 32) return sync ? launch_dense<32, true>(d, it, s) : launch_dense<32, false>(d, it, s);
-  return sync ? launch_dense<64, true>(d, it, s) : launch_dense<64, false>(d, it, s);
+  if (mode == 0) {
+    const int apb = kSyncBlock / 64;
+    const int grid = (d.m + apb - 1) / apb;
+    Dev dd = d;
+    Iter a = it;
+    void *args[] = {&dd, &a};
+    return hipLaunchCooperativeKernel(reinterpret_cast<void *>(&k_construct_sync_dense),
+                                      dim3(grid), dim3(kSyncBlock), args, lds_bytes(d, kSyncBlock), s);
+  }
+  const int apb = kAsyncBlock / 64;
+  const int grid = (d.m + apb - 1) / apb;
+  hipLaunchKernelGGL(k_construct_async_dense, dim3(grid), dim3(kAsyncBlock),
+                     lds_bytes(d, kAsyncBlock), s, d, it);
+  return hipGetLastError();
 }
 
 int max_sync_ants(const Dev &d, int memory) {
   if (memory != 0) return 0;
-  if (d.cl <= 16) return max_sync_dense<16>(d);
-  if (d.cl <= 32) return max_sync_dense<32>(d);
-  return max_sync_dense<64>(d);
+  int per_cu = 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(
+          &per_cu, reinterpret_cast<const void *>(&k_construct_sync_dense), kSyncBlock,
+          lds_bytes(d, kSyncBlock)) != hipSuccess)
+    return 0;
+  int dev = 0, cus = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return 0;
+  if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
+    return 0;
+  return per_cu * cus * (kSyncBlock / 64);
 }
 
 hipError_t launch_best_global(const Dev &d, const Iter &it, int memory, hipStream_t s) {
