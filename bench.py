@@ -48,7 +48,8 @@ def run_mode(acs, xy, mode, steps, warmup, seed=0):
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     st1 = col.stats()
-    delta = {k: st1[k] - st0[k] for k in ("steps", "fallback", "fallback_unvisited", "greedy", "roulette")}
+    delta = {k: st1[k] - st0[k] for k in ("steps", "fallback", "fallback_unvisited", "greedy",
+                                          "roulette", "cas_retries")}
     res = dict(
         seconds=t1 - t0,
         steps=delta["steps"],
@@ -91,6 +92,9 @@ def main():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--sync-steps", type=int, default=5)
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--copy-calibration-mb", type=int, default=0,
+                    help="after timing, run one plain device copy of this many MiB "
+                         "(reference kernel for hardware byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: only one GPU is supported (asked for {args.gpus}); "
@@ -142,9 +146,17 @@ def main():
                       "ms_per_step": syn["seconds"] * 1e3 / args.sync_steps,
                       "avg_construct_ms": syn["construct_ms"] / syn["launches"]},
         "fallback_share": asy["delta"]["fallback"] / max(asy["delta"]["steps"], 1),
+        "cas_retry_share": asy["delta"]["cas_retries"] / max(2 * asy["delta"]["steps"], 1),
         "best_length_async": asy["best"],
         "nn_length": asy["nn_length"],
     }
+    if args.copy_calibration_mb:
+        nbytes = args.copy_calibration_mb << 20
+        src = torch.ones(nbytes // 4, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        out["copy_calibration_bytes"] = nbytes
     if not args.no_cpu:
         cb = cpu_baseline(xy)
         out["cpu_baseline"] = cb

@@ -301,18 +301,46 @@ struct Pick {
   int kind;    // 0 greedy (Eq. 1), 1 roulette (Eq. 2), 2 fallback
 };
 
+// Candidate-set membership and weight of this lane's candidate.
+struct Cand {
+  bool unv;  // member of the candidate set (an unvisited neighbour)
+  float w;   // tau * eta^beta, 0 for non-members
+};
+
+__device__ __forceinline__ Cand weigh(const Dev &D, const uint32_t *vis, int lane, uint4 rec) {
+  // every lane holds a valid city (lanes >= cl repeat the last candidate), so
+  // the bitmap read needs no branch
+  const uint32_t word = vis[rec.x >> 5];
+  Cand c;
+  c.unv = (lane < D.cl) & !((word >> (rec.x & 31)) & 1u);
+  // tau * eta^beta >= 0, so its bit pattern orders like the value
+  c.w = c.unv ? __uint_as_float(rec.w) * __uint_as_float(rec.z) : 0.f;
+  return c;
+}
+
+// Philox words of 64 consecutive steps, one step per lane: lane l holds the
+// draw of step base + l.  Each step then reads its words with readlane.
+__device__ __forceinline__ uint4 philox_batch(const Iter &A, int ant, int base, int lane) {
+  return philox10(make_uint4((uint32_t)(base + lane), (uint32_t)ant, A.it, A.instance), A.key0,
+                  A.key1);
+}
+
+// q24 and u24 of step t from the batch that holds it.
+__device__ __forceinline__ uint2 draw_of(uint4 batch, int t) {
+  return make_uint2(rdlane(batch.x, t & 63) >> 8, rdlane(batch.y, t & 63) >> 8);
+}
+
 template <bool COHERENT>
 __device__ __forceinline__ Pick select_dense(const Dev &D, const Iter &A, const uint32_t *vis,
-                                             int cur, int lane, uint4 rec, uint4 rnd) {
+                                             int cur, int lane, uint4 rec, Cand c, uint2 q) {
   const int n = D.n, cl = D.cl;
-  const bool unv = lane < cl && !((vis[rec.x >> 5] >> (rec.x & 31)) & 1u);
-  // tau * eta^beta >= 0, so its bit pattern orders like the value
-  const float w = unv ? __uint_as_float(rec.w) * __uint_as_float(rec.z) : 0.f;
+  const bool unv = c.unv;
+  const float w = c.w;
   const uint64_t umask = __ballot(unv);
   Pick p;
   if (umask) {
     int k;
-    if ((rnd.x >> 8) < A.q0_24) {
+    if (q.x < A.q0_24) {
       // Eq. 1, exploitation: maximum of tau * eta^beta, lowest position
       const uint32_t mx = wave_umax_u(__float_as_uint(w));
       const uint64_t sel = __ballot(unv && __float_as_uint(w) == mx);
@@ -328,7 +356,7 @@ __device__ __forceinline__ Pick select_dense(const Dev &D, const Iter &A, const 
         if (lane >= off) P = P + o;
       }
       const float total = __uint_as_float(rdlane(__float_as_uint(P), cl - 1));
-      const float r = ((float)(rnd.y >> 8) * 0x1p-24f) * total;
+      const float r = ((float)q.y * 0x1p-24f) * total;
       const uint64_t sel = __ballot(unv && P > r);
       k = sel ? (int)__ffsll((unsigned long long)sel) - 1 : 63 - (int)__clzll((long long)umask);
       p.kind = 1;
@@ -421,8 +449,8 @@ __global__ __launch_bounds__(1024) void k_construct_sync_dense(Dev D, Iter A) {
   uint32_t *vis = smem + wv * W;
 
   for (int w = lane; w < W; w += 64) vis[w] = 0u;
-  const uint4 r0 = philox10(make_uint4(0u, (uint32_t)ant, A.it, A.instance), A.key0, A.key1);
-  const int start = (int)__umulhi(r0.z, (uint32_t)n);
+  uint4 draws = philox_batch(A, ant, 0, lane);
+  const int start = (int)__umulhi(rdlane(draws.z, 0), (uint32_t)n);
   if (lane == 0) vis[start >> 5] |= 1u << (start & 31);
   int tb = start;
 
@@ -433,11 +461,12 @@ __global__ __launch_bounds__(1024) void k_construct_sync_dense(Dev D, Iter A) {
   uint32_t bar = 0;
   for (int t = 1; t < n; ++t) {
     Pick p{};
+    if ((t & 63) == 0) draws = philox_batch(A, ant, t, lane);
     if (active) {
       uint4 rec = D.crec[(size_t)cur * cl + kl];
       rec.w = __float_as_uint(tau_load(cand_tau(D, cur, kl)));
-      const uint4 rnd = philox10(make_uint4((uint32_t)t, (uint32_t)ant, A.it, A.instance), A.key0, A.key1);
-      p = select_dense<true>(D, A, vis, cur, lane, rec, rnd);
+      const Cand c = weigh(D, vis, lane, rec);
+      p = select_dense<true>(D, A, vis, cur, lane, rec, c, draw_of(draws, t));
       c_greedy += p.kind == 0;
       c_roul += p.kind == 1;
       if (p.kind == 2) { ++c_fb; c_fbu += (uint64_t)(n - t); }
@@ -474,18 +503,23 @@ __global__ __launch_bounds__(1024) void k_construct_sync_dense(Dev D, Iter A) {
 
 // ---------------------------------------------------------------------------
 // Asynchronous construction, dense memory: one launch per iteration, one ant
-// per wave, no waiting for the other ants.  After each move the local update
-// of Eq. 3 is a compare-and-swap of the exact map on both directed entries of
-// the crossed edge.
+// per wave, no waiting for the other ants.  Each crossing gets the local
+// update of Eq. 3 as a compare-and-swap of the exact map on both directed
+// entries of the crossed edge.
 //
 // The steps of one ant form a dependent chain, so the latency of a step sets
-// the iteration time.  Per step the wave issues the load of the next city's
-// record right after choosing it; the forward entry's CAS uses the value the
-// selection read as its expected value (no extra load before it); the
-// reverse entry is resolved one step later from the next city's record,
-// which holds its current value when the previous city is a candidate of the
-// next one; CAS results are checked one step after issue, and a failed CAS
-// (the entry changed meanwhile) is retried with the value it returned.
+// the iteration time, and the wave waits for its memory operations in issue
+// order.  The step is therefore arranged so that nothing slow is issued
+// right before the wait for the next record:
+//   1. wait for the record of the current city cur (issued at the end of the
+//      previous step); check the compare-and-swaps issued one step earlier
+//      and repeat any that found the entry changed;
+//   2. issue the two compare-and-swaps of the previous move (prev, cur): the
+//      forward entry with the pheromone the selection read as its expected
+//      value, the reverse entry with the value cur's record holds (or the
+//      forward value when prev is not a candidate of cur);
+//   3. select the next city (Alg. 2) while those are in flight;
+//   4. issue the load of the next city's record.
 // ---------------------------------------------------------------------------
 __global__ __launch_bounds__(256) void k_construct_async_dense(Dev D, Iter A) {
   extern __shared__ uint32_t smem[];
@@ -500,81 +534,76 @@ __global__ __launch_bounds__(256) void k_construct_async_dense(Dev D, Iter A) {
   const float al = A.a_loc, bl = A.b_loc;
 
   for (int w = lane; w < W; w += 64) vis[w] = 0u;
-  const uint4 r0 = philox10(make_uint4(0u, (uint32_t)ant, A.it, A.instance), A.key0, A.key1);
-  const int start = (int)__umulhi(r0.z, (uint32_t)n);
+  uint4 draws = philox_batch(A, ant, 0, lane);
+  const int start = (int)__umulhi(rdlane(draws.z, 0), (uint32_t)n);
   if (lane == 0) vis[start >> 5] |= 1u << (start & 31);
   int tb = start;
   uint4 rec = D.crec[(size_t)start * cl + kl];
 
   int cur = start, prev = -1;
-  float prev_tval = 0.f;
+  float *fwd = nullptr;  // home of the forward entry of the previous move
+  float fval = 0.f;      // its value as read by the selection
   int64_t len = 0;
   uint32_t c_greedy = 0, c_roul = 0, c_fb = 0, c_retry = 0;
   uint64_t c_fbu = 0;
-  // compare-and-swap in flight: lane 0 forward entry, lane 1 reverse entry
+  // compare-and-swap in flight on lanes 0 (forward) and 1 (reverse)
   float *pptr = nullptr;
   unsigned int pexp = 0, pret = 0;
   bool pend = false;
 
-  for (int t = 1; t < n; ++t) {
-    const uint4 rnd = philox10(make_uint4((uint32_t)t, (uint32_t)ant, A.it, A.instance), A.key0, A.key1);
-    // reverse entry (cur, prev) of the previous move, from cur's record
-    float *rptr = nullptr;
-    float rexp = prev_tval;
+  for (int t = 1; t <= n; ++t) {
+    // 1. the record of cur is needed now; so are last step's CAS results
+    if (pend && pret != pexp) c_retry += 1 + cas_apply(pptr, pret, al, bl);
+    pend = false;
+    const Cand c = weigh(D, vis, lane, rec);
+    // the weights are complete here, before the updates below are issued, so
+    // no later wait for this record also waits for those updates
+    __asm__ volatile("" ::"v"(c.w), "v"((int)c.unv));
+    // 2. updates of the previous move (prev, cur)
     if (t > 1) {
       const uint64_t b = __ballot(lane < cl && rec.x == (uint32_t)prev);
-      if (b) {
-        const int k = uni((int)__ffsll((unsigned long long)b) - 1);
-        rptr = cand_tau(D, cur, k);
-        rexp = __uint_as_float(rdlane(rec.w, k));
-      } else {
-        rptr = D.tau + (size_t)cur * ldn + prev;
+      const int kr = b ? uni((int)__ffsll((unsigned long long)b) - 1) : -1;
+      const float rval = kr >= 0 ? __uint_as_float(rdlane(rec.w, kr)) : fval;
+      if (lane == 0) {
+        pptr = fwd;
+        pexp = __float_as_uint(fval);
+        pend = true;
+      } else if (lane == 1) {
+        pptr = home(D, cur, prev, kr);
+        pexp = __float_as_uint(rval);
+        pend = true;
       }
+      if (pend)
+        pret = atomicCAS(reinterpret_cast<unsigned int *>(pptr), pexp,
+                         __float_as_uint(fmaf(al, __uint_as_float(pexp), bl)));
     }
-    const Pick p = select_dense<false>(D, A, vis, cur, lane, rec, rnd);
+    if (t == n) break;
+    // 3. selection
+    if ((t & 63) == 0) draws = philox_batch(A, ant, t, lane);
+    const Pick p = select_dense<false>(D, A, vis, cur, lane, rec, c, draw_of(draws, t));
     c_greedy += p.kind == 0;
     c_roul += p.kind == 1;
     if (p.kind == 2) { ++c_fb; c_fbu += (uint64_t)(n - t); }
     if (lane == 0) vis[p.next >> 5] |= 1u << (p.next & 31);
     tour_put(D, ant, t, lane, p.next, tb);
     len += p.d;
-
+    // 4. record of the next city
     rec = D.crec[(size_t)p.next * cl + kl];
-    if (pend && pret != pexp) c_retry += 1 + cas_apply(pptr, pret, al, bl);
-    pend = false;
-    if (lane == 0) {
-      pptr = home(D, cur, p.next, p.k);
-      pexp = __float_as_uint(p.tval);
-      pend = true;
-    } else if (lane == 1 && t > 1) {
-      pptr = rptr;
-      pexp = __float_as_uint(rexp);
-      pend = true;
-    }
-    if (pend)
-      pret = atomicCAS(reinterpret_cast<unsigned int *>(pptr), pexp,
-                       __float_as_uint(fmaf(al, __uint_as_float(pexp), bl)));
+    fwd = home(D, cur, p.next, p.k);
+    fval = p.tval;
     prev = cur;
-    prev_tval = p.tval;
     cur = p.next;
   }
   if (pend && pret != pexp) c_retry += 1 + cas_apply(pptr, pret, al, bl);
-  // reverse entry of the last move, both entries of the closing edge
+  // closing edge: both entries, read fresh (once per ant)
   {
-    const uint64_t b = __ballot(lane < cl && rec.x == (uint32_t)prev);
-    const int kr = b ? uni((int)__ffsll((unsigned long long)b) - 1) : -1;
-    const float er = kr >= 0 ? __uint_as_float(rdlane(rec.w, kr)) : prev_tval;
     const int k1 = cand_pos(D, cur, start, lane);
     const int k2 = cand_pos(D, start, cur, lane);
-    float *h = lane == 0 ? home(D, cur, prev, kr)
-                         : (lane == 1 ? home(D, cur, start, k1) : home(D, start, cur, k2));
-    if (lane < 3) {
-      const float seen = lane == 0 ? er : tau_load(h);
-      c_retry += cas_apply(h, __float_as_uint(seen), al, bl);
-    }
+    float *h = lane == 0 ? home(D, cur, start, k1) : home(D, start, cur, k2);
+    if (lane < 2) c_retry += cas_apply(h, __float_as_uint(tau_load(h)), al, bl);
   }
   len += D.dist[(size_t)cur * ldn + start];
-  c_retry = (uint32_t)uni((int)(rdlane(c_retry, 0) + rdlane(c_retry, 1) + rdlane(c_retry, 2)));
+  c_retry = (uint32_t)uni((int)(rdlane(c_retry, 0) + rdlane(c_retry, 1)));
   if (lane == 0) {
     D.lens[ant] = len;
     add_counters(D, c_greedy, c_roul, c_fb, c_fbu, c_retry);
