@@ -37,9 +37,11 @@ def algorithmic_bytes(st_delta: dict, n: int, m: int, cl: int, iters: int) -> fl
     return float(b)
 
 
-def run_mode(acs, xy, mode, steps, warmup, seed=0):
+def run_mode(acs, xy, mode, steps, warmup, seed=0, **kw):
     import torch
-    col = acs.Colony(xy, m=0, cl=CL, mode=mode, seed=seed)
+    kw.setdefault("m", 0)
+    kw.setdefault("cl", CL)
+    col = acs.Colony(xy, mode=mode, seed=seed, **kw)
     col.iterate(max(warmup, 1))
     st0 = col.stats()
     torch.cuda.synchronize()
@@ -49,7 +51,7 @@ def run_mode(acs, xy, mode, steps, warmup, seed=0):
     t1 = time.perf_counter()
     st1 = col.stats()
     delta = {k: st1[k] - st0[k] for k in ("steps", "fallback", "fallback_unvisited", "greedy",
-                                          "roulette", "cas_retries")}
+                                          "roulette", "cas_retries", "spm_hits", "spm_misses")}
     res = dict(
         seconds=t1 - t0,
         steps=delta["steps"],
@@ -85,6 +87,31 @@ def cpu_baseline(xy, budget_s: float = 12.0):
                        f"({steps} steps, {dt:.1f} s, {threads} OpenMP threads)")
 
 
+EXTRA = {
+    # n=198 uniform, m=n, cl=32, dense (the paper's d198 size)
+    "c1": dict(kind="uniform", n=198, kw=dict(), modes=(("sync", 20), ("async", 50))),
+    # n=1000 clustered (20 Gaussian clusters), m=n, cl=32, dense
+    "c2c": dict(kind="clustered", n=1000, kw=dict(), modes=(("sync", 3), ("async", 20))),
+    # n=20000 uniform, m=1024, cl=16, selective memory with s=8
+    "c3": dict(kind="uniform", n=20000, kw=dict(m=1024, cl=16, memory=1, spm_s=8),
+               modes=(("sync", 1), ("async", 5))),
+}
+
+
+def run_extra(acs, inputs, name):
+    spec = EXTRA[name]
+    xy = inputs.uniform(spec["n"]) if spec["kind"] == "uniform" else inputs.clustered(spec["n"])
+    res = {"n": spec["n"], **{k: v for k, v in spec["kw"].items()}}
+    for mode_name, iters in spec["modes"]:
+        mode = acs.ACS_SYNC if mode_name == "sync" else acs.ACS_ASYNC_ATOMIC
+        r = run_mode(acs, xy, mode, iters, 1, **spec["kw"])
+        res[mode_name] = {"steps_per_s": r["steps"] / r["seconds"],
+                          "ms_per_iteration": r["seconds"] * 1e3 / iters,
+                          "construct_ms": r["construct_ms"] / r["launches"],
+                          "iterations": iters, "best": r["best"]}
+    return res
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -92,6 +119,9 @@ def main():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--sync-steps", type=int, default=5)
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--extra", default="c1,c2c,c3",
+                    help="other workloads timed beside the headline (comma list of c1, c2c, c3; "
+                         "empty for none)")
     ap.add_argument("--copy-calibration-mb", type=int, default=0,
                     help="after timing, run one plain device copy of this many MiB "
                          "(reference kernel for hardware byte counters)")
@@ -112,8 +142,11 @@ def main():
 
     asy = run_mode(acs, xy, acs.ACS_ASYNC_ATOMIC, args.steps, args.warmup)
     print(f"# async: {asy['seconds']*1e3/args.steps:.3f} ms/iteration", file=sys.stderr, flush=True)
-    syn = run_mode(acs, xy, acs.ACS_SYNC, args.sync_steps, 1)
-    print(f"# sync: {syn['seconds']*1e3/args.sync_steps:.3f} ms/iteration", file=sys.stderr, flush=True)
+    syn = None
+    if args.sync_steps > 0:
+        syn = run_mode(acs, xy, acs.ACS_SYNC, args.sync_steps, 1)
+        print(f"# sync: {syn['seconds']*1e3/args.sync_steps:.3f} ms/iteration", file=sys.stderr,
+              flush=True)
 
     value = asy["steps"] / asy["seconds"]
     ms_per_step = asy["seconds"] * 1e3 / args.steps
@@ -142,14 +175,21 @@ def main():
                      "kernel": "k_construct_dense (async)",
                      "bytes_per_launch": bytes_per_launch,
                      "avg_launch_ms": avg_launch_s * 1e3},
-        "sync_mode": {"value": syn["steps"] / syn["seconds"], "unit": "steps/s",
-                      "ms_per_step": syn["seconds"] * 1e3 / args.sync_steps,
-                      "avg_construct_ms": syn["construct_ms"] / syn["launches"]},
+        "sync_mode": None if syn is None else {
+            "value": syn["steps"] / syn["seconds"], "unit": "steps/s",
+            "ms_per_step": syn["seconds"] * 1e3 / args.sync_steps,
+            "avg_construct_ms": syn["construct_ms"] / syn["launches"]},
         "fallback_share": asy["delta"]["fallback"] / max(asy["delta"]["steps"], 1),
         "cas_retry_share": asy["delta"]["cas_retries"] / max(2 * asy["delta"]["steps"], 1),
         "best_length_async": asy["best"],
         "nn_length": asy["nn_length"],
     }
+    extra = {}
+    for name in [x for x in args.extra.split(",") if x]:
+        extra[name] = run_extra(acs, inputs, name)
+        print(f"# {name}: {extra[name]}", file=sys.stderr, flush=True)
+    if extra:
+        out["other_workloads"] = extra
     if args.copy_calibration_mb:
         nbytes = args.copy_calibration_mb << 20
         src = torch.ones(nbytes // 4, dtype=torch.float32, device="cuda")

@@ -159,6 +159,49 @@ void acs_destroy(struct acs_t *h);
 /* Message of the last failing call on this thread ("" if none). */
 const char *acs_last_error(void);
 
+/* ------------------------------------------------------------------------
+ * Batches: many independent instances solved together, each by its own
+ * colony (the independent-colony setting the paper names as future work,
+ * Sec. 5), one launch per iteration over every ant of every instance.
+ * The iteration (construction, iteration best, global update of Alg. 1)
+ * is captured once as a HIP graph and replayed.  Batches run in the
+ * asynchronous atomic mode on the dense memory (other combinations:
+ * ACS_E_UNSUPPORTED).  Instance i uses the random-number counter word
+ * params->instance + i and otherwise the same parameters, so it reproduces
+ * a single-instance handle created with that instance value.
+ * ------------------------------------------------------------------------ */
+typedef struct acs_batch_t acs_batch_t;
+
+/* Device bytes for a batch of `count` instances of sizes n[0..count). */
+int acs_batch_workspace_bytes(const int32_t *n, int32_t count, const acs_params *p,
+                              size_t *out);
+
+/* coords[i]: n[i] (x, y) pairs of instance i, copied.  params as for
+ * acs_create (mode must be ACS_ASYNC_ATOMIC, memory ACS_DENSE); a given
+ * workspace must hold acs_batch_workspace_bytes. */
+int acs_batch_create(const double *const *coords, const int32_t *n, int32_t count,
+                     const acs_params *p, acs_batch_t **out);
+
+/* k iterations of every instance; returns once they have finished. */
+int acs_batch_iterate(acs_batch_t *b, int32_t k);
+
+/* Number of instances, construction steps of one iteration (sum of
+ * m_i (n_i - 1)), whether the iteration runs as a graph (1) or as direct
+ * launches (0), and the device time of the last acs_batch_iterate. */
+int acs_batch_info(acs_batch_t *b, int32_t *count, int64_t *steps_per_iteration,
+                   int32_t *graph, double *last_iterate_ms);
+
+/* Handle of instance i, for the read-back calls above (acs_best_tour,
+ * acs_tours, acs_lengths, acs_pheromone_snapshot, acs_stats, ...).  It is
+ * owned by the batch: do not destroy it or iterate it on its own. */
+int acs_batch_instance(acs_batch_t *b, int32_t i, struct acs_t **out);
+
+/* Best-so-far tour of instance i (as acs_best_tour). */
+int acs_batch_best_tour(acs_batch_t *b, int32_t i, int32_t *tour_out, int64_t *len_out);
+
+/* Releases the batch and every instance handle in it; NULL is a no-op. */
+void acs_batch_destroy(acs_batch_t *b);
+
 #ifdef __cplusplus
 }
 #endif

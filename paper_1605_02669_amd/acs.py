@@ -83,6 +83,15 @@ def load() -> C.CDLL:
     lib.acs_stats.argtypes = [P, C.POINTER(acs_stats_t)]
     lib.acs_destroy.argtypes = [P]
     lib.acs_destroy.restype = None
+    lib.acs_batch_workspace_bytes.argtypes = [P, i32, C.POINTER(acs_params), C.POINTER(sz)]
+    lib.acs_batch_create.argtypes = [P, P, i32, C.POINTER(acs_params), C.POINTER(P)]
+    lib.acs_batch_iterate.argtypes = [P, i32]
+    lib.acs_batch_info.argtypes = [P, C.POINTER(i32), C.POINTER(i64), C.POINTER(i32),
+                                   C.POINTER(C.c_double)]
+    lib.acs_batch_instance.argtypes = [P, i32, C.POINTER(P)]
+    lib.acs_batch_best_tour.argtypes = [P, i32, P, C.POINTER(i64)]
+    lib.acs_batch_destroy.argtypes = [P]
+    lib.acs_batch_destroy.restype = None
     lib.acs_last_error.restype = C.c_char_p
     _lib = lib
     return lib
@@ -234,3 +243,78 @@ class Colony:
 
     def stats(self):
         return acs_stats(self.h)
+
+
+def acs_batch_workspace_bytes(sizes, p: acs_params) -> int:
+    n = np.ascontiguousarray(sizes, dtype=np.int32)
+    out = C.c_size_t()
+    _check(load().acs_batch_workspace_bytes(_ptr(n), len(n), C.byref(p), C.byref(out)))
+    return out.value
+
+
+class Batch:
+    """Many instances, one colony each, iterated together (asynchronous mode)."""
+
+    def __init__(self, instances, m=0, cl=32, beta=2.0, q0=0.9, phi=0.1, rho=0.1, tau0=0.0,
+                 seed=0, instance=0, torch_memory=True):
+        self.xys = [np.ascontiguousarray(x, dtype=np.float64).reshape(-1, 2) for x in instances]
+        sizes = np.array([x.shape[0] for x in self.xys], dtype=np.int32)
+        p = acs_default_params()
+        p.m, p.cl, p.beta, p.q0, p.phi, p.rho, p.tau0 = m, cl, beta, q0, phi, rho, tau0
+        p.mode, p.memory, p.seed, p.instance = ACS_ASYNC_ATOMIC, ACS_DENSE, seed, instance
+        self._ws = None
+        if torch_memory:
+            import torch
+            nbytes = acs_batch_workspace_bytes(sizes, p)
+            self._ws = torch.empty(nbytes, dtype=torch.uint8, device="cuda")
+            p.workspace, p.workspace_bytes = self._ws.data_ptr(), nbytes
+            p.stream = torch.cuda.current_stream().cuda_stream
+        ptrs = (C.c_void_p * len(self.xys))(*[x.ctypes.data for x in self.xys])
+        h = C.c_void_p()
+        _check(load().acs_batch_create(ptrs, _ptr(sizes), len(sizes), C.byref(p), C.byref(h)))
+        self.h = h
+        self.sizes = sizes
+        self.params = p
+
+    def close(self):
+        if getattr(self, "h", None):
+            load().acs_batch_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def iterate(self, k=1):
+        _check(load().acs_batch_iterate(self.h, k))
+
+    def info(self) -> dict:
+        c, steps, g, ms = C.c_int32(), C.c_int64(), C.c_int32(), C.c_double()
+        _check(load().acs_batch_info(self.h, C.byref(c), C.byref(steps), C.byref(g), C.byref(ms)))
+        return dict(count=c.value, steps_per_iteration=steps.value, graph=bool(g.value),
+                    last_iterate_ms=ms.value)
+
+    def handle(self, i: int):
+        h = C.c_void_p()
+        _check(load().acs_batch_instance(self.h, i, C.byref(h)))
+        return h
+
+    def best(self, i: int):
+        return acs_best_tour(self.handle(i), int(self.sizes[i]))
+
+    def tours(self, i: int):
+        n = int(self.sizes[i])
+        m = self.params.m or n
+        return acs_tours(self.handle(i), m, n)
+
+    def lengths(self, i: int):
+        n = int(self.sizes[i])
+        return acs_lengths(self.handle(i), self.params.m or n)
+
+    def tau(self, i: int):
+        return acs_pheromone_snapshot(self.handle(i), int(self.sizes[i]))
+
+    def stats(self, i: int):
+        return acs_stats(self.handle(i))

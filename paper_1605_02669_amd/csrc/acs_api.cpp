@@ -46,7 +46,7 @@ size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
 
 // Device buffers of one handle, as offsets into one allocation.
 struct Layout {
-  size_t xy, dist, crec, cand, eta, tau, spm_node, spm_val, spm_tail, tours, lens,
+  size_t xy, dist, crec, cand, eta, tau, etad, spm, spm_tail, upd_rec, upd_nb, upd_lead, tours, lens,
       best, gstate, counters, sync, dmax, lnn, total;
 };
 
@@ -67,10 +67,13 @@ Layout make_layout(int n, int m, int cl, int ldn, int memory, int s) {
   L.eta = take(sizeof(float) * kEtaEntries);
   if (memory == ACS_DENSE) {
     L.tau = take(sizeof(float) * (size_t)n * ldn);
+    L.etad = take(sizeof(float) * (size_t)n * ldn);
   } else {
-    L.spm_node = take(sizeof(int32_t) * (size_t)n * s);
-    L.spm_val = take(sizeof(float) * (size_t)n * s);
-    L.spm_tail = take(sizeof(int32_t) * (size_t)n);
+    L.spm = take(sizeof(uint32_t) * 2 * (size_t)n * s);
+    L.spm_tail = take(sizeof(uint32_t) * (size_t)n);
+    L.upd_rec = take(sizeof(int32_t) * 2 * (size_t)m);
+    L.upd_nb = take(sizeof(int32_t) * 2 * (size_t)m);
+    L.upd_lead = take(sizeof(int32_t) * (size_t)n);
   }
   L.tours = take(sizeof(int32_t) * (size_t)m * n);
   L.lens = take(sizeof(int64_t) * (size_t)m);
@@ -103,7 +106,8 @@ int check_params(int32_t n, const acs_params *p) {
   if (n > 65535) return fail(ACS_E_UNSUPPORTED, "n = %d > 65535", n);
   const uint32_t cl = std::min<uint32_t>(p->cl, (uint32_t)n - 1);
   if (cl > 64) return fail(ACS_E_UNSUPPORTED, "cl = %u > 64", cl);
-  if (p->memory == ACS_SPM) return fail(ACS_E_UNSUPPORTED, "selective memory not built yet");
+  if (p->memory == ACS_SPM && p->spm_s > (uint32_t)acs::kMaxSpmS)
+    return fail(ACS_E_UNSUPPORTED, "spm_s = %u > %d", p->spm_s, acs::kMaxSpmS);
   return ACS_OK;
 }
 
@@ -186,6 +190,14 @@ int build(acs_t *h, const double *xy) {
   h->tau0 = p.tau0 > 0.0 ? (float)p.tau0 : (float)(1.0 / ((double)n * (double)h->lnn));
   std::vector<float> eta(kEtaEntries, 0.f);
   for (uint32_t d = 0; d <= dmax; ++d) eta[d] = eta_beta(p.beta, d);
+  if (p.memory == ACS_SPM) {
+    // the selective memory's fallback relies on tau0 * eta^beta(d) strictly
+    // decreasing in d (every trail outside a record holds tau0)
+    for (uint32_t d = 0; d < dmax; ++d)
+      if (!(h->tau0 * eta[d] > h->tau0 * eta[d + 1]))
+        return fail(ACS_E_UNSUPPORTED,
+                    "tau0 * eta^beta is not strictly decreasing at d = %u (selective memory)", d);
+  }
   HIP_TRY(hipMemcpyAsync(h->ws + h->L.eta, eta.data(), sizeof(float) * kEtaEntries,
                          hipMemcpyHostToDevice, h->stream));
   HIP_TRY(acs::launch_crec(h->dev, cand, h->tau0, h->stream));
@@ -306,10 +318,13 @@ int acs_create(const double *coords_xy, int32_t n, const acs_params *p, acs_t **
   d.eta_tab = reinterpret_cast<const float *>(w + h->L.eta);
   if (p->memory == ACS_DENSE) {
     d.tau = reinterpret_cast<float *>(w + h->L.tau);
+    d.etad = reinterpret_cast<const float *>(w + h->L.etad);
   } else {
-    d.spm_node = reinterpret_cast<int32_t *>(w + h->L.spm_node);
-    d.spm_val = reinterpret_cast<float *>(w + h->L.spm_val);
-    d.spm_tail = reinterpret_cast<int32_t *>(w + h->L.spm_tail);
+    d.spm = reinterpret_cast<uint2 *>(w + h->L.spm);
+    d.spm_tail = reinterpret_cast<uint32_t *>(w + h->L.spm_tail);
+    d.upd_rec = reinterpret_cast<int32_t *>(w + h->L.upd_rec);
+    d.upd_nb = reinterpret_cast<int32_t *>(w + h->L.upd_nb);
+    d.upd_lead = reinterpret_cast<int32_t *>(w + h->L.upd_lead);
   }
   d.tours = reinterpret_cast<int32_t *>(w + h->L.tours);
   d.lens = reinterpret_cast<int64_t *>(w + h->L.lens);
@@ -406,12 +421,19 @@ int acs_spm_snapshot(acs_t *h, int32_t *nodes, float *vals, int32_t *tail) {
   if (!live(h)) return fail(ACS_E_STATE, "invalid handle");
   if (h->p.memory != ACS_SPM) return fail(ACS_E_UNSUPPORTED, "not an SPM handle");
   if (!nodes || !vals || !tail) return fail(ACS_E_INVALID, "NULL output");
-  const size_t ns = (size_t)h->n * h->p.spm_s;
+  const size_t s = h->p.spm_s, ns = (size_t)h->n * s;
   HIP_TRY(hipStreamSynchronize(h->stream));
-  HIP_TRY(hipMemcpy(nodes, h->ws + h->L.spm_node, ns * sizeof(int32_t), hipMemcpyDeviceToHost));
-  HIP_TRY(hipMemcpy(vals, h->ws + h->L.spm_val, ns * sizeof(float), hipMemcpyDeviceToHost));
-  HIP_TRY(hipMemcpy(tail, h->ws + h->L.spm_tail, (size_t)h->n * sizeof(int32_t),
+  std::vector<uint32_t> pairs(2 * ns), cnt((size_t)h->n);
+  HIP_TRY(hipMemcpy(pairs.data(), h->ws + h->L.spm, pairs.size() * sizeof(uint32_t),
                     hipMemcpyDeviceToHost));
+  HIP_TRY(hipMemcpy(cnt.data(), h->ws + h->L.spm_tail, cnt.size() * sizeof(uint32_t),
+                    hipMemcpyDeviceToHost));
+  for (size_t e = 0; e < ns; ++e) {
+    nodes[e] = (int32_t)pairs[2 * e];
+    std::memcpy(&vals[e], &pairs[2 * e + 1], sizeof(float));
+  }
+  // the record keeps an insert counter; the most recently added slot is it mod s
+  for (size_t i = 0; i < (size_t)h->n; ++i) tail[i] = (int32_t)(cnt[i] % s);
   return ACS_OK;
 }
 
@@ -488,5 +510,276 @@ void acs_destroy(acs_t *h) {
 }
 
 const char *acs_last_error(void) { return g_err.c_str(); }
+
+}  // extern "C"
+
+// ---------------------------------------------------------------------------
+// Batches: many independent instances, one launch per iteration.
+// ---------------------------------------------------------------------------
+struct acs_batch_t {
+  int count = 0;
+  std::vector<acs_t *> inst;
+  hipStream_t stream = nullptr;
+  bool own_stream = false;
+  char *ws = nullptr;
+  bool own_ws = false;
+  acs::Dev *d_devs = nullptr;
+  acs::Iter *d_iters = nullptr;
+  int2 *d_items = nullptr;
+  int nitems = 0, nmax = 0;
+  int64_t steps_per_iteration = 0;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  double iterate_ms = 0.0;
+};
+
+namespace {
+
+std::unordered_set<const void *> g_live_batches;
+
+bool live_batch(const acs_batch_t *b) {
+  std::lock_guard<std::mutex> g(g_live_mu);
+  return b && g_live_batches.count(b);
+}
+
+void release_batch(acs_batch_t *b) {
+  if (!b) return;
+  if (b->stream) (void)hipStreamSynchronize(b->stream);
+  for (acs_t *h : b->inst) acs_destroy(h);
+  if (b->exec) (void)hipGraphExecDestroy(b->exec);
+  if (b->graph) (void)hipGraphDestroy(b->graph);
+  if (b->e0) (void)hipEventDestroy(b->e0);
+  if (b->e1) (void)hipEventDestroy(b->e1);
+  if (b->own_ws && b->ws) (void)hipFree(b->ws);
+  if (b->own_stream && b->stream) (void)hipStreamDestroy(b->stream);
+  delete b;
+}
+
+struct BatchLayout {
+  std::vector<size_t> off;
+  size_t devs, iters, items, total;
+};
+
+int batch_layout(const int32_t *n, int32_t count, const acs_params *p, BatchLayout *L,
+                 int *nitems) {
+  size_t off = 0;
+  *nitems = 0;
+  L->off.resize((size_t)count);
+  for (int i = 0; i < count; ++i) {
+    size_t bytes = 0;
+    const int rc = acs_workspace_bytes(n[i], p, &bytes);
+    if (rc) return rc;
+    L->off[(size_t)i] = off;
+    off = align_up(off + bytes, 256);
+    *nitems += p->m ? (int)p->m : n[i];
+  }
+  L->devs = off;
+  off = align_up(off + sizeof(acs::Dev) * (size_t)count, 256);
+  L->iters = off;
+  off = align_up(off + sizeof(acs::Iter) * (size_t)count, 256);
+  L->items = off;
+  off = align_up(off + sizeof(int2) * (size_t)*nitems, 256);
+  L->total = off;
+  return ACS_OK;
+}
+
+int check_batch_args(const int32_t *n, int32_t count, const acs_params *p) {
+  if (count < 1) return fail(ACS_E_INVALID, "count < 1");
+  if (!n || !p) return fail(ACS_E_INVALID, "NULL argument");
+  if (p->mode != ACS_ASYNC_ATOMIC)
+    return fail(ACS_E_UNSUPPORTED, "batches run in the asynchronous atomic mode");
+  if (p->memory != ACS_DENSE) return fail(ACS_E_UNSUPPORTED, "batches use the dense memory");
+  for (int i = 0; i < count; ++i) {
+    const int rc = check_params(n[i], p);
+    if (rc) return rc;
+  }
+  return ACS_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int acs_batch_workspace_bytes(const int32_t *n, int32_t count, const acs_params *p, size_t *out) {
+  int rc = check_batch_args(n, count, p);
+  if (rc) return rc;
+  if (!out) return fail(ACS_E_INVALID, "out is NULL");
+  BatchLayout L;
+  int nitems = 0;
+  rc = batch_layout(n, count, p, &L, &nitems);
+  if (rc) return rc;
+  *out = L.total;
+  return ACS_OK;
+}
+
+int acs_batch_create(const double *const *coords, const int32_t *n, int32_t count,
+                     const acs_params *p, acs_batch_t **out) {
+  if (!out) return fail(ACS_E_INVALID, "out is NULL");
+  *out = nullptr;
+  int rc = check_batch_args(n, count, p);
+  if (rc) return rc;
+  if (!coords) return fail(ACS_E_INVALID, "coords is NULL");
+  for (int i = 0; i < count; ++i)
+    if (!coords[i]) return fail(ACS_E_INVALID, "coords[%d] is NULL", i);
+  BatchLayout L;
+  int nitems = 0;
+  rc = batch_layout(n, count, p, &L, &nitems);
+  if (rc) return rc;
+
+  acs_batch_t *b = new (std::nothrow) acs_batch_t;
+  if (!b) return fail(ACS_E_NOMEM, "host allocation failed");
+  b->count = count;
+  auto bail = [&](int code) {
+    std::string keep = g_err;
+    release_batch(b);
+    g_err = keep;
+    return code;
+  };
+  if (p->stream) {
+    b->stream = reinterpret_cast<hipStream_t>(p->stream);
+  } else {
+    if (hipStreamCreateWithFlags(&b->stream, hipStreamNonBlocking) != hipSuccess)
+      return bail(fail(ACS_E_DEVICE, "stream creation failed"));
+    b->own_stream = true;
+  }
+  if (p->workspace) {
+    if (p->workspace_bytes < L.total)
+      return bail(fail(ACS_E_BUFSIZE, "workspace of %zu bytes < %zu needed", p->workspace_bytes,
+                       L.total));
+    b->ws = reinterpret_cast<char *>(p->workspace);
+  } else {
+    hipError_t e = hipMalloc(&b->ws, L.total);
+    if (e != hipSuccess) {
+      b->ws = nullptr;
+      return bail(fail(ACS_E_NOMEM, "hipMalloc(%zu): %s", L.total, hipGetErrorString(e)));
+    }
+    b->own_ws = true;
+  }
+  if (hipEventCreate(&b->e0) != hipSuccess || hipEventCreate(&b->e1) != hipSuccess)
+    return bail(fail(ACS_E_DEVICE, "event creation failed"));
+
+  std::vector<acs::Dev> devs((size_t)count);
+  std::vector<acs::Iter> iters((size_t)count);
+  for (int i = 0; i < count; ++i) {
+    acs_params pi = *p;
+    pi.instance = p->instance + (uint32_t)i;
+    pi.stream = b->stream;
+    pi.workspace = b->ws + L.off[(size_t)i];
+    size_t bytes = 0;
+    acs_workspace_bytes(n[i], &pi, &bytes);
+    pi.workspace_bytes = bytes;
+    acs_t *h = nullptr;
+    rc = acs_create(coords[i], n[i], &pi, &h);
+    if (rc) return bail(rc);
+    b->inst.push_back(h);
+    devs[(size_t)i] = h->dev;
+    iters[(size_t)i] = h->base;
+    b->nmax = std::max(b->nmax, n[i]);
+    b->steps_per_iteration += (int64_t)h->m * (h->n - 1);
+  }
+  // work list: instances by decreasing n, so the longest chains start first
+  std::vector<int> order((size_t)count);
+  for (int i = 0; i < count; ++i) order[(size_t)i] = i;
+  std::stable_sort(order.begin(), order.end(), [&](int a, int c) { return n[a] > n[c]; });
+  std::vector<int2> items;
+  items.reserve((size_t)nitems);
+  for (int i : order)
+    for (int a = 0; a < b->inst[(size_t)i]->m; ++a) items.push_back(make_int2(i, a));
+  b->nitems = (int)items.size();
+  b->d_devs = reinterpret_cast<acs::Dev *>(b->ws + L.devs);
+  b->d_iters = reinterpret_cast<acs::Iter *>(b->ws + L.iters);
+  b->d_items = reinterpret_cast<int2 *>(b->ws + L.items);
+  if (hipMemcpyAsync(b->d_devs, devs.data(), sizeof(acs::Dev) * devs.size(),
+                     hipMemcpyHostToDevice, b->stream) != hipSuccess ||
+      hipMemcpyAsync(b->d_iters, iters.data(), sizeof(acs::Iter) * iters.size(),
+                     hipMemcpyHostToDevice, b->stream) != hipSuccess ||
+      hipMemcpyAsync(b->d_items, items.data(), sizeof(int2) * items.size(),
+                     hipMemcpyHostToDevice, b->stream) != hipSuccess ||
+      hipStreamSynchronize(b->stream) != hipSuccess)
+    return bail(fail(ACS_E_DEVICE, "copy of batch descriptors failed"));
+
+  // one iteration captured once as a graph (no memset nodes: plain kernels)
+  if (hipStreamBeginCapture(b->stream, hipStreamCaptureModeThreadLocal) == hipSuccess) {
+    const hipError_t le = acs::launch_batch_iteration(b->d_devs, b->d_iters, b->d_items, b->nitems,
+                                                      b->count, b->nmax, b->stream);
+    hipGraph_t g = nullptr;
+    const hipError_t ce = hipStreamEndCapture(b->stream, &g);
+    if (le == hipSuccess && ce == hipSuccess && g) {
+      b->graph = g;
+      if (hipGraphInstantiate(&b->exec, g, nullptr, nullptr, 0) != hipSuccess) b->exec = nullptr;
+    } else if (g) {
+      (void)hipGraphDestroy(g);
+    }
+  }
+  (void)hipGetLastError();
+  {
+    std::lock_guard<std::mutex> g(g_live_mu);
+    g_live_batches.insert(b);
+  }
+  *out = b;
+  return ACS_OK;
+}
+
+int acs_batch_iterate(acs_batch_t *b, int32_t k) {
+  if (!live_batch(b)) return fail(ACS_E_STATE, "invalid batch handle");
+  if (k < 0) return fail(ACS_E_INVALID, "k < 0");
+  if (k == 0) return ACS_OK;
+  HIP_TRY(hipEventRecord(b->e0, b->stream));
+  for (int i = 0; i < k; ++i) {
+    if (b->exec) {
+      HIP_TRY(hipGraphLaunch(b->exec, b->stream));
+    } else {
+      HIP_TRY(acs::launch_batch_iteration(b->d_devs, b->d_iters, b->d_items, b->nitems, b->count,
+                                          b->nmax, b->stream));
+    }
+  }
+  HIP_TRY(hipEventRecord(b->e1, b->stream));
+  HIP_TRY(hipStreamSynchronize(b->stream));
+  float ms = 0.f;
+  HIP_TRY(hipEventElapsedTime(&ms, b->e0, b->e1));
+  b->iterate_ms = ms;
+  for (acs_t *h : b->inst) {
+    h->iter += (uint32_t)k;
+    h->iterate_ms = ms;
+    h->construct_ms = 0.0;
+    h->construct_launches = 0;
+  }
+  return ACS_OK;
+}
+
+int acs_batch_info(acs_batch_t *b, int32_t *count, int64_t *steps_per_iteration,
+                   int32_t *graph, double *last_iterate_ms) {
+  if (!live_batch(b)) return fail(ACS_E_STATE, "invalid batch handle");
+  if (count) *count = b->count;
+  if (steps_per_iteration) *steps_per_iteration = b->steps_per_iteration;
+  if (graph) *graph = b->exec ? 1 : 0;
+  if (last_iterate_ms) *last_iterate_ms = b->iterate_ms;
+  return ACS_OK;
+}
+
+int acs_batch_instance(acs_batch_t *b, int32_t i, acs_t **out) {
+  if (!live_batch(b)) return fail(ACS_E_STATE, "invalid batch handle");
+  if (i < 0 || i >= b->count || !out) return fail(ACS_E_INVALID, "instance %d out of range", i);
+  *out = b->inst[(size_t)i];
+  return ACS_OK;
+}
+
+int acs_batch_best_tour(acs_batch_t *b, int32_t i, int32_t *tour_out, int64_t *len_out) {
+  acs_t *h = nullptr;
+  const int rc = acs_batch_instance(b, i, &h);
+  if (rc) return rc;
+  return acs_best_tour(h, tour_out, len_out);
+}
+
+void acs_batch_destroy(acs_batch_t *b) {
+  {
+    std::lock_guard<std::mutex> g(g_live_mu);
+    if (!b || !g_live_batches.count(b)) return;
+    g_live_batches.erase(b);
+  }
+  release_batch(b);
+}
+
 
 }  // extern "C"

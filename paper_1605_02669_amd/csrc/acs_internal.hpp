@@ -20,9 +20,15 @@ struct Dev {
   const uint4 *crec;       // n x cl candidate records (see above)
   const float *eta_tab;    // eta^beta indexed by distance (dmax + 1)
   float *tau;              // dense: n x ldn, home of non-candidate entries
-  int32_t *spm_node;       // SPM: n x s (-1 empty)
-  float *spm_val;          // SPM: n x s
-  int32_t *spm_tail;       // SPM: n
+  const float *etad;       // dense: n x ldn, eta^beta(d(i, j))
+  // selective pheromone memory (Sec. 3.2): the record of city i is s pairs
+  // {neighbour (-1 = empty slot), pheromone bits}; spm_tail[i] counts the
+  // inserts (the most recently added slot is spm_tail[i] mod s)
+  uint2 *spm;              // SPM: n x s
+  uint32_t *spm_tail;      // SPM: n
+  int32_t *upd_rec;        // SPM synchronous updates of one step: record
+  int32_t *upd_nb;         //   ... and neighbour of update e = 2 * ant + w
+  int32_t *upd_lead;       //   per record: smallest e updating it (INT_MAX none)
   int32_t *tours;          // m x n
   int64_t *lens;           // m
   int32_t *best;           // n, best-so-far tour
@@ -58,5 +64,13 @@ hipError_t launch_construct(const Dev &d, const Iter &it, int mode,
 int max_sync_ants(const Dev &d, int memory);
 hipError_t launch_best_global(const Dev &d, const Iter &it, int memory,
                               hipStream_t s);
+// One iteration of many dense instances (asynchronous mode): construction of
+// every (instance, ant) work item, then per-instance best and global update.
+// Descriptors, iteration state and the work list are device arrays, so the
+// three launches can be captured once in a graph and replayed.
+hipError_t launch_batch_iteration(const Dev *devs, Iter *iters, const int2 *items, int nitems,
+                                  int count, int nmax, hipStream_t s);
+// Largest spm_s the GPU kernels support.
+constexpr int kMaxSpmS = 16;
 
 }  // namespace acs

@@ -269,15 +269,23 @@ __global__ __launch_bounds__(256) void k_crec(Dev D, const int32_t *cand, float 
       make_uint4(c, d, __float_as_uint(D.eta_tab[d]), __float_as_uint(tau0));
 }
 
+// eta^beta of every entry (dense memory): one load per city in the fallback
+// scan instead of a distance load followed by a table lookup.
+__global__ __launch_bounds__(256) void k_etad(Dev D) {
+  const size_t e = (size_t)blockIdx.x * 256 + threadIdx.x;
+  if (e >= (size_t)D.n * D.ldn) return;
+  const_cast<float *>(D.etad)[e] = D.eta_tab[D.dist[e]];
+}
+
 __global__ __launch_bounds__(256) void k_init(Dev D, float tau0) {
   const size_t e = (size_t)blockIdx.x * 256 + threadIdx.x;
   const size_t nd = (size_t)D.n * D.ldn;
   if (D.tau && e < nd) D.tau[e] = tau0;
-  if (D.spm_node && e < (size_t)D.n * D.spm_s) {
-    D.spm_node[e] = -1;
-    D.spm_val[e] = tau0;
+  if (D.spm && e < (size_t)D.n * D.spm_s) D.spm[e] = make_uint2(kNone, __float_as_uint(tau0));
+  if (D.spm_tail && e < (size_t)D.n) {
+    D.spm_tail[e] = (uint32_t)(D.spm_s - 1);
+    D.upd_lead[e] = INT_MAX;
   }
-  if (D.spm_tail && e < (size_t)D.n) D.spm_tail[e] = D.spm_s - 1;
   if (e == 0) {
     D.gstate[0] = -1;
     D.gstate[1] = -1;
@@ -330,38 +338,46 @@ __device__ __forceinline__ uint2 draw_of(uint4 batch, int t) {
   return make_uint2(rdlane(batch.x, t & 63) >> 8, rdlane(batch.y, t & 63) >> 8);
 }
 
-template <bool COHERENT>
-__device__ __forceinline__ Pick select_dense(const Dev &D, const Iter &A, const uint32_t *vis,
-                                             int cur, int lane, uint4 rec, Cand c, uint2 q) {
-  const int n = D.n, cl = D.cl;
+// Eq. 1 over the candidate set: the wave-uniform candidate position chosen,
+// or -1 when the candidate set is empty (Alg. 2 then falls back).
+__device__ __forceinline__ int pick_candidate(const Iter &A, int lane, int cl, Cand c, uint2 q,
+                                              int &kind) {
   const bool unv = c.unv;
   const float w = c.w;
   const uint64_t umask = __ballot(unv);
-  Pick p;
-  if (umask) {
-    int k;
-    if (q.x < A.q0_24) {
-      // Eq. 1, exploitation: maximum of tau * eta^beta, lowest position
-      const uint32_t mx = wave_umax_u(__float_as_uint(w));
-      const uint64_t sel = __ballot(unv && __float_as_uint(w) == mx);
-      k = (int)__ffsll((unsigned long long)sel) - 1;
-      p.kind = 0;
-    } else {
-      // Eq. 2 by roulette: inclusive Hillis-Steele scan over the positions
-      // (offsets 1, 2, 4, ... < cl), r = u * total, first member of the
-      // candidate set whose prefix sum exceeds r
-      float P = w;
-      for (int off = 1; off < cl; off <<= 1) {
-        const float o = __shfl_up(P, off, 64);
-        if (lane >= off) P = P + o;
-      }
-      const float total = __uint_as_float(rdlane(__float_as_uint(P), cl - 1));
-      const float r = ((float)q.y * 0x1p-24f) * total;
-      const uint64_t sel = __ballot(unv && P > r);
-      k = sel ? (int)__ffsll((unsigned long long)sel) - 1 : 63 - (int)__clzll((long long)umask);
-      p.kind = 1;
+  if (!umask) return -1;
+  int k;
+  if (q.x < A.q0_24) {
+    // exploitation: maximum of tau * eta^beta, lowest position
+    const uint32_t mx = wave_umax_u(__float_as_uint(w));
+    const uint64_t sel = __ballot(unv && __float_as_uint(w) == mx);
+    k = (int)__ffsll((unsigned long long)sel) - 1;
+    kind = 0;
+  } else {
+    // Eq. 2 by roulette: inclusive Hillis-Steele scan over the positions
+    // (offsets 1, 2, 4, ... < cl), r = u * total, first member of the
+    // candidate set whose prefix sum exceeds r
+    float P = w;
+    for (int off = 1; off < cl; off <<= 1) {
+      const float o = __shfl_up(P, off, 64);
+      if (lane >= off) P = P + o;
     }
-    k = uni(k);
+    const float total = __uint_as_float(rdlane(__float_as_uint(P), cl - 1));
+    const float r = ((float)q.y * 0x1p-24f) * total;
+    const uint64_t sel = __ballot(unv && P > r);
+    k = sel ? (int)__ffsll((unsigned long long)sel) - 1 : 63 - (int)__clzll((long long)umask);
+    kind = 1;
+  }
+  return uni(k);
+}
+
+template <bool COHERENT>
+__device__ __forceinline__ Pick select_dense(const Dev &D, const Iter &A, const uint32_t *vis,
+                                             int cur, int lane, uint4 rec, Cand c, uint2 q) {
+  const int n = D.n;
+  Pick p;
+  const int k = pick_candidate(A, lane, D.cl, c, q, p.kind);
+  if (k >= 0) {
     p.k = k;
     p.next = (int)rdlane(rec.x, k);
     p.d = rdlane(rec.y, k);
@@ -369,31 +385,36 @@ __device__ __forceinline__ Pick select_dense(const Dev &D, const Iter &A, const 
     return p;
   }
   // Alg. 2, empty candidate set: greedy over every unvisited city, ties ->
-  // lowest index.  Each lane scans four consecutive cities per round.
+  // lowest index.  Each lane scans four consecutive cities per round; the
+  // loads of a round do not depend on the visited set (rows are padded to
+  // ldn), so unrolled rounds keep several loads in flight.
   const float *trow = D.tau + (size_t)cur * D.ldn;
+  const float *erow = D.etad + (size_t)cur * D.ldn;
   const uint16_t *drow = D.dist + (size_t)cur * D.ldn;
   float bv = 0.f, bt = 0.f;
   uint32_t bj = kNone, bd = 0;
+#pragma unroll 4
   for (int j0 = 4 * lane; j0 < n; j0 += 256) {
+    float tq[4];
+    if (COHERENT) {
+#pragma unroll
+      for (int q = 0; q < 4; ++q) tq[q] = tau_load(trow + j0 + q);
+    } else {
+      const float4 tv = *reinterpret_cast<const float4 *>(trow + j0);
+      tq[0] = tv.x; tq[1] = tv.y; tq[2] = tv.z; tq[3] = tv.w;
+    }
+    const float4 ev = *reinterpret_cast<const float4 *>(erow + j0);
+    const ushort4 dv = *reinterpret_cast<const ushort4 *>(drow + j0);
+    const float eq[4] = {ev.x, ev.y, ev.z, ev.w};
+    const uint32_t dq[4] = {dv.x, dv.y, dv.z, dv.w};
     uint32_t bits = (vis[j0 >> 5] >> (j0 & 31)) & 0xfu;
     if (j0 + 4 > n) bits |= (0xfu << (n - j0)) & 0xfu;
-    if (bits != 0xfu) {
-      float tq[4];
-      if (COHERENT) {
 #pragma unroll
-        for (int q = 0; q < 4; ++q) tq[q] = tau_load(trow + j0 + q);
-      } else {
-        const float4 tv = *reinterpret_cast<const float4 *>(trow + j0);
-        tq[0] = tv.x; tq[1] = tv.y; tq[2] = tv.z; tq[3] = tv.w;
+    for (int q = 0; q < 4; ++q) {
+      const float v = tq[q] * eq[q];
+      if (!((bits >> q) & 1u) && (bj == kNone || v > bv)) {
+        bv = v; bj = (uint32_t)(j0 + q); bt = tq[q]; bd = dq[q];
       }
-      const ushort4 dv = *reinterpret_cast<const ushort4 *>(drow + j0);
-      const uint32_t dq[4] = {dv.x, dv.y, dv.z, dv.w};
-#pragma unroll
-      for (int q = 0; q < 4; ++q)
-        if (!((bits >> q) & 1u)) {
-          const float v = tq[q] * D.eta_tab[dq[q]];
-          if (bj == kNone || v > bv) { bv = v; bj = (uint32_t)(j0 + q); bt = tq[q]; bd = dq[q]; }
-        }
     }
   }
   const uint32_t mx = wave_umax_u(bj == kNone ? 0u : __float_as_uint(bv));
@@ -521,16 +542,11 @@ __global__ __launch_bounds__(1024) void k_construct_sync_dense(Dev D, Iter A) {
 //   3. select the next city (Alg. 2) while those are in flight;
 //   4. issue the load of the next city's record.
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(256) void k_construct_async_dense(Dev D, Iter A) {
-  extern __shared__ uint32_t smem[];
-  const int lane = threadIdx.x & 63;
-  const int wv = threadIdx.x >> 6;
-  const int ant = uni(blockIdx.x * (blockDim.x >> 6) + wv);
-  if (ant >= D.m) return;  // the whole wave leaves; no block-level sync below
+__device__ __forceinline__ void ant_async_dense(const Dev &D, const Iter &A, int ant,
+                                                uint32_t *vis, int lane) {
   const int n = D.n, cl = D.cl, ldn = D.ldn;
   const int W = (n + 31) >> 5;
   const int kl = lane < cl ? lane : cl - 1;
-  uint32_t *vis = smem + wv * W;
   const float al = A.a_loc, bl = A.b_loc;
 
   for (int w = lane; w < W; w += 64) vis[w] = 0u;
@@ -610,6 +626,461 @@ __global__ __launch_bounds__(256) void k_construct_async_dense(Dev D, Iter A) {
   }
 }
 
+__global__ __launch_bounds__(256) void k_construct_async_dense(Dev D, Iter A) {
+  extern __shared__ uint32_t smem[];
+  const int lane = threadIdx.x & 63;
+  const int wv = threadIdx.x >> 6;
+  const int ant = uni(blockIdx.x * (blockDim.x >> 6) + wv);
+  if (ant >= D.m) return;  // the whole wave leaves; no block-level sync below
+  ant_async_dense(D, A, ant, smem + wv * ((D.n + 31) >> 5), lane);
+}
+
+// Many instances in one launch: wave w builds the tour of ant items[w].y of
+// instance items[w].x, whose descriptor and iteration state live in device
+// memory (so the launch can be replayed from a graph).  The work list is
+// ordered by decreasing n, so the longest chains start first.
+__global__ __launch_bounds__(256) void k_construct_async_batch(const Dev *devs, const Iter *iters,
+                                                               const int2 *items, int nitems,
+                                                               int wmax) {
+  extern __shared__ uint32_t smem[];
+  const int lane = threadIdx.x & 63;
+  const int wv = threadIdx.x >> 6;
+  const int w = uni(blockIdx.x * (blockDim.x >> 6) + wv);
+  if (w >= nitems) return;
+  const int2 item = items[w];
+  const int inst = uni(item.x);
+  const Dev D = devs[inst];
+  const Iter A = iters[inst];
+  ant_async_dense(D, A, uni(item.y), smem + wv * wmax, lane);
+}
+
+// ---------------------------------------------------------------------------
+// Selective pheromone memory (Sec. 3.2, Alg. 3).  The record of city c is s
+// pairs {neighbour, pheromone}; a wave holds it with slot i on lane i.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ uint2 pair_load_coherent(const uint2 *p) {
+  const unsigned long long v = __hip_atomic_load(reinterpret_cast<const unsigned long long *>(p),
+                                                 __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  return make_uint2((uint32_t)v, (uint32_t)(v >> 32));
+}
+
+__device__ __forceinline__ void pair_store_coherent(uint2 *p, uint2 v) {
+  __hip_atomic_store(reinterpret_cast<unsigned long long *>(p),
+                     ((unsigned long long)v.y << 32) | v.x, __ATOMIC_RELAXED,
+                     __HIP_MEMORY_SCOPE_AGENT);
+}
+
+__device__ __forceinline__ unsigned long long pack(uint2 v) {
+  return ((unsigned long long)v.y << 32) | v.x;
+}
+
+template <bool COHERENT>
+__device__ __forceinline__ uint2 spm_record(const Dev &D, int c, int lane) {
+  const int i = lane < D.spm_s ? lane : D.spm_s - 1;
+  const uint2 *p = D.spm + (size_t)c * D.spm_s + i;
+  return COHERENT ? pair_load_coherent(p) : *p;
+}
+
+// Pheromone of (c, j) for this lane's j: the value of the first slot of c's
+// record holding j, else tau0 (every trail not stored is at the minimum).
+__device__ __forceinline__ float spm_tau(uint2 pr, int s, uint32_t j, float tau0) {
+  float t = tau0;
+  for (int i = s - 1; i >= 0; --i) {
+    const uint32_t node = rdlane(pr.x, i);
+    const uint32_t val = rdlane(pr.y, i);
+    t = j == node ? __uint_as_float(val) : t;
+  }
+  return t;
+}
+
+__device__ __forceinline__ Cand weigh_spm(const Dev &D, const uint32_t *vis, int lane, uint4 rec,
+                                          uint2 pr, float tau0) {
+  const uint32_t word = vis[rec.x >> 5];
+  Cand c;
+  c.unv = (lane < D.cl) & !((word >> (rec.x & 31)) & 1u);
+  const float t = spm_tau(pr, D.spm_s, rec.x, tau0);
+  c.w = c.unv ? t * __uint_as_float(rec.z) : 0.f;
+  return c;
+}
+
+// Alg. 2's fallback with the selective memory.  Every trail outside cur's
+// record holds tau0 and tau0 * eta^beta strictly decreases with d (checked
+// when the handle is created), so among the unvisited cities outside the
+// record the nearest one by (d, j) has the largest value and the lowest
+// index among equals.  The result is the best of that city and the
+// unvisited cities of the record, ties -> lowest index: exactly the greedy
+// argmax over all unvisited cities.
+__device__ __forceinline__ Pick fallback_spm(const Dev &D, uint32_t *vis, int cur, int lane,
+                                             uint2 pr, float tau0) {
+  const int n = D.n, s = D.spm_s;
+  const uint16_t *drow = D.dist + (size_t)cur * D.ldn;
+  const bool in_rec = lane < s && pr.x != kNone;
+  const uint32_t rj = in_rec ? pr.x : 0u;
+  const bool rec_unv = in_rec && !((vis[rj >> 5] >> (rj & 31)) & 1u);
+  // hide the record's unvisited cities from the scan of the others
+  if (rec_unv) atomicOr(&vis[rj >> 5], 1u << (rj & 31));
+  uint32_t key = kNone;
+#pragma unroll 4
+  for (int j0 = 4 * lane; j0 < n; j0 += 256) {
+    const ushort4 dv = *reinterpret_cast<const ushort4 *>(drow + j0);
+    const uint32_t dq[4] = {dv.x, dv.y, dv.z, dv.w};
+    uint32_t bits = (vis[j0 >> 5] >> (j0 & 31)) & 0xfu;
+    if (j0 + 4 > n) bits |= (0xfu << (n - j0)) & 0xfu;
+#pragma unroll
+    for (int q = 0; q < 4; ++q)
+      if (!((bits >> q) & 1u)) key = min(key, (dq[q] << 16) | (uint32_t)(j0 + q));
+  }
+  key = wave_umin_u(key);
+  if (rec_unv) atomicAnd(&vis[rj >> 5], ~(1u << (rj & 31)));
+  // record candidates on lanes < s, the off-record candidate on its own
+  uint32_t rd = 0;
+  float rv = 0.f;
+  if (rec_unv) {
+    rd = drow[rj];
+    rv = __uint_as_float(pr.y) * D.eta_tab[rd];
+  }
+  const bool off = key != kNone;
+  const float ov = off ? tau0 * D.eta_tab[key >> 16] : 0.f;
+  const uint64_t any_rec = __ballot(rec_unv);
+  uint32_t mx = any_rec ? wave_umax_u(rec_unv ? __float_as_uint(rv) : 0u) : 0u;
+  if (off && (!any_rec || __float_as_uint(ov) > mx)) mx = __float_as_uint(ov);
+  const bool rec_win = rec_unv && __float_as_uint(rv) == mx;
+  uint32_t jn = wave_umin_u(rec_win ? rj : kNone);
+  const bool off_win = off && __float_as_uint(ov) == mx && (key & 0xffffu) < jn;
+  Pick p;
+  p.k = -1;
+  p.kind = 2;
+  if (off_win) {
+    jn = key & 0xffffu;
+    p.d = key >> 16;
+    p.tval = tau0;
+  } else {
+    const int owner = uni((int)__ffsll((unsigned long long)__ballot(rec_win && rj == jn)) - 1);
+    p.d = rdlane(rd, owner);
+    p.tval = __uint_as_float(rdlane(pr.y, owner));
+  }
+  p.next = (int)jn;
+  return p;
+}
+
+// Alg. 3 on a record held by the wave (slot i on lane i, insert counter
+// `tail`): the trail for neighbour nb gets the map x -> fma(a, x, b); a
+// missing trail gets the map applied to tau0 in the slot after the most
+// recently added one, which overwrites the least recently added trail.
+__device__ __forceinline__ void spm_update_wave(uint2 &pr, uint32_t &tail, int s, int lane,
+                                                int nb, float a, float b, float tau0,
+                                                uint32_t &hits, uint32_t &misses) {
+  const uint64_t hit = __ballot(lane < s && pr.x == (uint32_t)nb);
+  if (hit) {
+    const int i = (int)__ffsll((unsigned long long)hit) - 1;
+    if (lane == i) pr.y = __float_as_uint(fmaf(a, __uint_as_float(pr.y), b));
+    ++hits;
+  } else {
+    tail += 1;
+    const int slot = (int)(tail % (uint32_t)s);
+    if (lane == slot) pr = make_uint2((uint32_t)nb, __float_as_uint(fmaf(a, tau0, b)));
+    ++misses;
+  }
+}
+
+// Synchronous step updates of record r: every registered update of this step
+// whose record is r, in increasing update index e = 2 * ant + w (ant
+// ascending, the ant's own record before the next city's).
+__device__ __forceinline__ void spm_apply_step(const Dev &D, int r, int ne, float a, float b,
+                                               float tau0, int lane, uint32_t &hits,
+                                               uint32_t &misses) {
+  const int s = D.spm_s;
+  uint2 pr = spm_record<true>(D, r, lane);
+  uint32_t tail = __hip_atomic_load(D.spm_tail + r, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  for (int e0 = 0; e0 < ne; e0 += 64) {
+    const int e = e0 + lane;
+    int rr = -1, nbv = 0;
+    if (e < ne) {
+      rr = __hip_atomic_load(D.upd_rec + e, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      nbv = __hip_atomic_load(D.upd_nb + e, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+    uint64_t mask = __ballot(rr == r);
+    while (mask) {
+      const int l = (int)__ffsll((unsigned long long)mask) - 1;
+      mask &= mask - 1;
+      spm_update_wave(pr, tail, s, lane, (int)rdlane((uint32_t)nbv, l), a, b, tau0, hits, misses);
+    }
+  }
+  if (lane < s) pair_store_coherent(D.spm + (size_t)r * s + lane, pr);
+  if (lane == 0) {
+    __hip_atomic_store(D.spm_tail + r, tail, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    __hip_atomic_store(D.upd_lead + r, INT_MAX, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  }
+}
+
+// Registers update e (record r, neighbour nb) for this step.
+__device__ __forceinline__ void spm_register(const Dev &D, int e, int r, int nb) {
+  __hip_atomic_store(D.upd_rec + e, r, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  __hip_atomic_store(D.upd_nb + e, nb, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  __hip_atomic_fetch_min(D.upd_lead + r, e, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// The UPDATE phase of one synchronous step with the selective memory: the
+// wave of ant `ant` applies the lists of the records it leads (the smallest
+// update index of a record leads it).
+__device__ __forceinline__ void spm_sync_updates(const Dev &D, int ant, int r0, int r1, float a,
+                                                 float b, float tau0, int lane, uint32_t &hits,
+                                                 uint32_t &misses) {
+  const int ne = 2 * D.m;
+  const int e0 = 2 * ant;
+  if (__hip_atomic_load(D.upd_lead + r0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == e0)
+    spm_apply_step(D, r0, ne, a, b, tau0, lane, hits, misses);
+  if (__hip_atomic_load(D.upd_lead + r1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == e0 + 1)
+    spm_apply_step(D, r1, ne, a, b, tau0, lane, hits, misses);
+}
+
+__device__ __forceinline__ void add_spm_counters(const Dev &D, uint32_t hits, uint32_t misses) {
+  atomicAdd(&D.counters[3], (unsigned long long)hits);
+  atomicAdd(&D.counters[4], (unsigned long long)misses);
+}
+
+// ---------------------------------------------------------------------------
+// Synchronous construction with the selective memory.  Per step:
+//   SELECT (coherent reads) and registration of the step's 2m updates
+//   | barrier | each record's updates applied in (ant, record i then j)
+//   order by the wave that leads it | barrier.
+// The closing edges are one more such round.
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(1024) void k_construct_sync_spm(Dev D, Iter A) {
+  extern __shared__ uint32_t smem[];
+  const int lane = threadIdx.x & 63;
+  const int wv = threadIdx.x >> 6;
+  const int ant = uni(blockIdx.x * (blockDim.x >> 6) + wv);
+  const bool active = ant < D.m;
+  const int n = D.n, cl = D.cl;
+  const int W = (n + 31) >> 5;
+  const int kl = lane < cl ? lane : cl - 1;
+  uint32_t *vis = smem + wv * W;
+  const float tau0 = A.tau0;
+
+  for (int w = lane; w < W; w += 64) vis[w] = 0u;
+  uint4 draws = philox_batch(A, ant, 0, lane);
+  const int start = (int)__umulhi(rdlane(draws.z, 0), (uint32_t)n);
+  if (lane == 0) vis[start >> 5] |= 1u << (start & 31);
+  int tb = start;
+
+  int cur = start;
+  int64_t len = 0;
+  uint32_t c_greedy = 0, c_roul = 0, c_fb = 0, hits = 0, misses = 0;
+  uint64_t c_fbu = 0;
+  uint32_t bar = 0;
+  for (int t = 1; t <= n; ++t) {
+    int next = start;
+    if ((t & 63) == 0) draws = philox_batch(A, ant, t, lane);
+    if (active && t < n) {
+      const uint4 rec = D.crec[(size_t)cur * cl + kl];
+      const uint2 pr = spm_record<true>(D, cur, lane);
+      const Cand c = weigh_spm(D, vis, lane, rec, pr, tau0);
+      Pick p;
+      const int k = pick_candidate(A, lane, cl, c, draw_of(draws, t), p.kind);
+      if (k >= 0) {
+        p.next = (int)rdlane(rec.x, k);
+        p.d = rdlane(rec.y, k);
+      } else {
+        p = fallback_spm(D, vis, cur, lane, pr, tau0);
+      }
+      c_greedy += p.kind == 0;
+      c_roul += p.kind == 1;
+      if (p.kind == 2) { ++c_fb; c_fbu += (uint64_t)(n - t); }
+      if (lane == 0) vis[p.next >> 5] |= 1u << (p.next & 31);
+      tour_put(D, ant, t, lane, p.next, tb);
+      len += p.d;
+      next = p.next;
+    }
+    if (active) {
+      // t < n: the step's crossing; t == n: the closing edge
+      if (t == n) len += D.dist[(size_t)cur * D.ldn + start];
+      if (lane == 0) spm_register(D, 2 * ant, cur, next);
+      if (lane == 1) spm_register(D, 2 * ant + 1, next, cur);
+    }
+    grid_barrier(D.sync, (++bar) * gridDim.x);
+    if (active) spm_sync_updates(D, ant, cur, next, A.a_loc, A.b_loc, tau0, lane, hits, misses);
+    if (t < n) grid_barrier(D.sync, (++bar) * gridDim.x);
+    cur = next;
+  }
+  if (active && lane == 0) {
+    D.lens[ant] = len;
+    add_counters(D, c_greedy, c_roul, c_fb, c_fbu, 0);
+    add_spm_counters(D, hits, misses);
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Asynchronous construction with the selective memory: no barriers; each
+// crossing's two record updates are lock-free.  A trail already in the
+// record gets the map by a 64-bit compare-and-swap of its {neighbour, value}
+// pair (a pair that changed meanwhile is re-examined); a missing trail takes
+// the next slot of the record by an atomic increment of its insert counter
+// and is written there as one 64-bit store.  Two ants inserting the same
+// trail at the same moment can both succeed (a duplicate; reads take the
+// first slot).  The updates of a move are issued at the start of the next
+// step and checked one step later, like the dense kernel's.
+// ---------------------------------------------------------------------------
+struct SpmOp {
+  uint2 *pair;         // hit: the pair's slot
+  uint32_t *tail;      // miss: the record's insert counter
+  unsigned long long expect, desired;
+  uint32_t ret_lo, ret_hi;
+  int nb, rec;
+  bool hit, live;
+};
+
+__device__ __forceinline__ void spm_async_issue(const Dev &D, SpmOp &op, uint2 pr, int r, int nb,
+                                                int lane, int owner, float a, float b,
+                                                float tau0, uint32_t &hits, uint32_t &misses) {
+  const int s = D.spm_s;
+  const uint64_t hm = __ballot(lane < s && pr.x == (uint32_t)nb);
+  if (lane != owner) return;
+  op.live = true;
+  op.nb = nb;
+  op.rec = r;
+  if (hm) {
+    const int i = (int)__ffsll((unsigned long long)hm) - 1;
+    const uint32_t v = rdlane(pr.y, i);
+    op.hit = true;
+    op.pair = D.spm + (size_t)r * s + i;
+    op.expect = ((unsigned long long)v << 32) | (uint32_t)nb;
+    op.desired = ((unsigned long long)__float_as_uint(fmaf(a, __uint_as_float(v), b)) << 32) |
+                 (uint32_t)nb;
+    const unsigned long long got = atomicCAS(reinterpret_cast<unsigned long long *>(op.pair),
+                                             op.expect, op.desired);
+    op.ret_lo = (uint32_t)got;
+    op.ret_hi = (uint32_t)(got >> 32);
+    ++hits;
+  } else {
+    op.hit = false;
+    op.tail = D.spm_tail + r;
+    op.ret_lo = atomicAdd(op.tail, 1u);
+    ++misses;
+  }
+}
+
+// Finishes an issued update: a miss writes its pair into the slot it took;
+// a hit whose pair changed is redone against the record's current state.
+__device__ __forceinline__ uint32_t spm_async_finish(const Dev &D, SpmOp &op, float a, float b,
+                                                     float tau0) {
+  if (!op.live) return 0;
+  op.live = false;
+  const int s = D.spm_s;
+  if (!op.hit) {
+    const uint32_t slot = (op.ret_lo + 1u) % (uint32_t)s;
+    pair_store_coherent(D.spm + (size_t)op.rec * s + slot,
+                        make_uint2((uint32_t)op.nb, __float_as_uint(fmaf(a, tau0, b))));
+    return 0;
+  }
+  if ((((unsigned long long)op.ret_hi << 32) | op.ret_lo) == op.expect) return 0;
+  // the pair changed: look for the trail again and apply the map
+  uint32_t retries = 1;
+  while (true) {
+    int found = -1;
+    uint2 cur_pair = make_uint2(0, 0);
+    for (int i = 0; i < s; ++i) {
+      const uint2 q = pair_load_coherent(D.spm + (size_t)op.rec * s + i);
+      if (found < 0 && q.x == (uint32_t)op.nb) { found = i; cur_pair = q; }
+    }
+    if (found < 0) {
+      const uint32_t t = atomicAdd(D.spm_tail + op.rec, 1u);
+      pair_store_coherent(D.spm + (size_t)op.rec * s + (t + 1u) % (uint32_t)s,
+                          make_uint2((uint32_t)op.nb, __float_as_uint(fmaf(a, tau0, b))));
+      return retries;
+    }
+    const unsigned long long ex = pack(cur_pair);
+    const unsigned long long de =
+        ((unsigned long long)__float_as_uint(fmaf(a, __uint_as_float(cur_pair.y), b)) << 32) |
+        (uint32_t)op.nb;
+    if (atomicCAS(reinterpret_cast<unsigned long long *>(D.spm + (size_t)op.rec * s + found), ex,
+                  de) == ex)
+      return retries;
+    ++retries;
+  }
+}
+
+__global__ __launch_bounds__(256) void k_construct_async_spm(Dev D, Iter A) {
+  extern __shared__ uint32_t smem[];
+  const int lane = threadIdx.x & 63;
+  const int wv = threadIdx.x >> 6;
+  const int ant = uni(blockIdx.x * (blockDim.x >> 6) + wv);
+  if (ant >= D.m) return;
+  const int n = D.n, cl = D.cl;
+  const int W = (n + 31) >> 5;
+  const int kl = lane < cl ? lane : cl - 1;
+  uint32_t *vis = smem + wv * W;
+  const float al = A.a_loc, bl = A.b_loc, tau0 = A.tau0;
+
+  for (int w = lane; w < W; w += 64) vis[w] = 0u;
+  uint4 draws = philox_batch(A, ant, 0, lane);
+  const int start = (int)__umulhi(rdlane(draws.z, 0), (uint32_t)n);
+  if (lane == 0) vis[start >> 5] |= 1u << (start & 31);
+  int tb = start;
+  uint4 rec = D.crec[(size_t)start * cl + kl];
+  uint2 pr = spm_record<false>(D, start, lane);
+  uint2 pr_prev = pr;
+
+  int cur = start, prev = -1;
+  int64_t len = 0;
+  uint32_t c_greedy = 0, c_roul = 0, c_fb = 0, c_retry = 0, hits = 0, misses = 0;
+  uint64_t c_fbu = 0;
+  SpmOp op{};
+  op.live = false;
+
+  for (int t = 1; t <= n; ++t) {
+    c_retry += spm_async_finish(D, op, al, bl, tau0);
+    const Cand c = weigh_spm(D, vis, lane, rec, pr, tau0);
+    __asm__ volatile("" ::"v"(c.w), "v"((int)c.unv));
+    if (t > 1) {
+      // forward entry of the previous move in prev's record (lane 0),
+      // reverse entry in cur's record (lane 1)
+      spm_async_issue(D, op, pr_prev, prev, cur, lane, 0, al, bl, tau0, hits, misses);
+      spm_async_issue(D, op, pr, cur, prev, lane, 1, al, bl, tau0, hits, misses);
+    }
+    if (t == n) break;
+    if ((t & 63) == 0) draws = philox_batch(A, ant, t, lane);
+    Pick p;
+    const int k = pick_candidate(A, lane, cl, c, draw_of(draws, t), p.kind);
+    if (k >= 0) {
+      p.next = (int)rdlane(rec.x, k);
+      p.d = rdlane(rec.y, k);
+    } else {
+      p = fallback_spm(D, vis, cur, lane, pr, tau0);
+    }
+    c_greedy += p.kind == 0;
+    c_roul += p.kind == 1;
+    if (p.kind == 2) { ++c_fb; c_fbu += (uint64_t)(n - t); }
+    if (lane == 0) vis[p.next >> 5] |= 1u << (p.next & 31);
+    tour_put(D, ant, t, lane, p.next, tb);
+    len += p.d;
+    rec = D.crec[(size_t)p.next * cl + kl];
+    pr_prev = pr;
+    pr = spm_record<false>(D, p.next, lane);
+    prev = cur;
+    cur = p.next;
+  }
+  c_retry += spm_async_finish(D, op, al, bl, tau0);
+  // closing edge, read fresh: record cur (neighbour start), record start
+  {
+    const uint2 q0 = spm_record<true>(D, cur, lane);
+    spm_async_issue(D, op, q0, cur, start, lane, 0, al, bl, tau0, hits, misses);
+    c_retry += spm_async_finish(D, op, al, bl, tau0);
+    const uint2 q1 = spm_record<true>(D, start, lane);
+    spm_async_issue(D, op, q1, start, cur, lane, 0, al, bl, tau0, hits, misses);
+    c_retry += spm_async_finish(D, op, al, bl, tau0);
+  }
+  len += D.dist[(size_t)cur * D.ldn + start];
+  c_retry = (uint32_t)uni((int)(rdlane(c_retry, 0) + rdlane(c_retry, 1)));
+  hits = (uint32_t)uni((int)(rdlane(hits, 0) + rdlane(hits, 1)));
+  misses = (uint32_t)uni((int)(rdlane(misses, 0) + rdlane(misses, 1)));
+  if (lane == 0) {
+    D.lens[ant] = len;
+    add_counters(D, c_greedy, c_roul, c_fb, c_fbu, c_retry);
+    add_spm_counters(D, hits, misses);
+  }
+}
+
 // ---------------------------------------------------------------------------
 // Iteration best, best-so-far and the global update (Alg. 1, Eq. 4), one
 // block.  Every directed entry of the best tour is touched exactly once, so
@@ -636,17 +1107,15 @@ __device__ __forceinline__ void argmin_len(const Dev &D, int64_t &bl, int &ba) {
     if (sl[w] < bl || (sl[w] == bl && sa[w] < ba)) { bl = sl[w]; ba = sa[w]; }
 }
 
-__global__ __launch_bounds__(1024) void k_best_global_dense(Dev D, Iter A) {
+__global__ __launch_bounds__(1024) void k_best(Dev D) {
   __shared__ int s_better;
-  __shared__ int64_t s_lgb;
   int64_t bl;
   int ba;
   argmin_len(D, bl, ba);
   if (threadIdx.x == 0) {
     const int64_t lgb = D.gstate[0];
     s_better = (lgb < 0 || bl < lgb) ? 1 : 0;
-    s_lgb = s_better ? bl : lgb;
-    D.gstate[0] = s_lgb;
+    D.gstate[0] = s_better ? bl : lgb;
     D.gstate[1] = bl;
     D.gstate[2] = ba;
     D.sync[0] = 0;  // barrier counter for the next construction
@@ -655,21 +1124,95 @@ __global__ __launch_bounds__(1024) void k_best_global_dense(Dev D, Iter A) {
   const int n = D.n;
   if (s_better)
     for (int p = threadIdx.x; p < n; p += blockDim.x) D.best[p] = D.tours[(size_t)ba * n + p];
-  __syncthreads();
+}
+
+// Eq. 4 on the best-so-far tour, dense memory: one thread per tour edge; the
+// 2n directed entries are distinct, so plain read-modify-writes suffice.
+__global__ __launch_bounds__(256) void k_global_dense(Dev D, Iter A) {
+  const int p = blockIdx.x * blockDim.x + threadIdx.x;
+  const int n = D.n;
+  if (p >= n) return;
   const float ag = A.a_glob;
-  const float bg = (float)(A.rho / (double)s_lgb);
-  for (int p = threadIdx.x; p < n; p += blockDim.x) {
-    const int u = D.best[p], v = D.best[p + 1 < n ? p + 1 : 0];
-    int ku = -1, kv = -1;
-    for (int k = 0; k < D.cl; ++k) {
-      if (D.crec[(size_t)u * D.cl + k].x == (uint32_t)v) ku = k;
-      if (D.crec[(size_t)v * D.cl + k].x == (uint32_t)u) kv = k;
-    }
-    float *h1 = home(D, u, v, ku);
-    float *h2 = home(D, v, u, kv);
-    *h1 = fmaf(ag, *h1, bg);
-    *h2 = fmaf(ag, *h2, bg);
+  const float bg = (float)(A.rho / (double)D.gstate[0]);
+  const int u = D.best[p], v = D.best[p + 1 < n ? p + 1 : 0];
+  int ku = -1, kv = -1;
+  for (int k = 0; k < D.cl; ++k) {
+    if (D.crec[(size_t)u * D.cl + k].x == (uint32_t)v) ku = k;
+    if (D.crec[(size_t)v * D.cl + k].x == (uint32_t)u) kv = k;
   }
+  float *h1 = home(D, u, v, ku);
+  float *h2 = home(D, v, u, kv);
+  *h1 = fmaf(ag, *h1, bg);
+  *h2 = fmaf(ag, *h2, bg);
+}
+
+// Eq. 4 with the selective memory, in the order of the tour: edge p updates
+// record u_p then record v_p.  City best[p] is touched by edges p-1 and p
+// (edges 0 and n-1 for p = 0), so one wave per tour position applies its
+// record's two updates in that order and no record is shared.
+__global__ __launch_bounds__(256) void k_global_spm(Dev D, Iter A) {
+  const int lane = threadIdx.x & 63;
+  const int p = uni(blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6));
+  const int n = D.n, s = D.spm_s;
+  if (p >= n) return;
+  const float ag = A.a_glob;
+  const float bg = (float)(A.rho / (double)D.gstate[0]);
+  const int r = D.best[p];
+  const int nb1 = p >= 1 ? D.best[p - 1] : D.best[1];
+  const int nb2 = p >= 1 ? D.best[p + 1 < n ? p + 1 : 0] : D.best[n - 1];
+  uint2 pr = spm_record<false>(D, r, lane);
+  uint32_t tail = D.spm_tail[r];
+  uint32_t hits = 0, misses = 0;
+  spm_update_wave(pr, tail, s, lane, nb1, ag, bg, A.tau0, hits, misses);
+  spm_update_wave(pr, tail, s, lane, nb2, ag, bg, A.tau0, hits, misses);
+  if (lane < s) D.spm[(size_t)r * s + lane] = pr;
+  if (lane == 0) {
+    D.spm_tail[r] = tail;
+    add_spm_counters(D, hits, misses);
+  }
+}
+
+// Batched iteration end: block b handles instance b (iteration best and
+// best-so-far), then advances that instance's iteration counter.
+__global__ __launch_bounds__(1024) void k_best_batch(const Dev *devs, Iter *iters) {
+  __shared__ int s_better;
+  const Dev D = devs[blockIdx.x];
+  int64_t bl;
+  int ba;
+  argmin_len(D, bl, ba);
+  if (threadIdx.x == 0) {
+    const int64_t lgb = D.gstate[0];
+    s_better = (lgb < 0 || bl < lgb) ? 1 : 0;
+    D.gstate[0] = s_better ? bl : lgb;
+    D.gstate[1] = bl;
+    D.gstate[2] = ba;
+    iters[blockIdx.x].it += 1;
+  }
+  __syncthreads();
+  const int n = D.n;
+  if (s_better)
+    for (int p = threadIdx.x; p < n; p += blockDim.x) D.best[p] = D.tours[(size_t)ba * n + p];
+}
+
+// Batched global update (dense): grid (edges / 256, instances).
+__global__ __launch_bounds__(256) void k_global_batch(const Dev *devs, const Iter *iters) {
+  const Dev D = devs[blockIdx.y];
+  const Iter A = iters[blockIdx.y];
+  const int p = blockIdx.x * blockDim.x + threadIdx.x;
+  const int n = D.n;
+  if (p >= n) return;
+  const float ag = A.a_glob;
+  const float bg = (float)(A.rho / (double)D.gstate[0]);
+  const int u = D.best[p], v = D.best[p + 1 < n ? p + 1 : 0];
+  int ku = -1, kv = -1;
+  for (int k = 0; k < D.cl; ++k) {
+    if (D.crec[(size_t)u * D.cl + k].x == (uint32_t)v) ku = k;
+    if (D.crec[(size_t)v * D.cl + k].x == (uint32_t)u) kv = k;
+  }
+  float *h1 = home(D, u, v, ku);
+  float *h2 = home(D, v, u, kv);
+  *h1 = fmaf(ag, *h1, bg);
+  *h2 = fmaf(ag, *h2, bg);
 }
 
 size_t lds_bytes(const Dev &D, int block) {
@@ -707,6 +1250,12 @@ hipError_t launch_crec(const Dev &d, const int32_t *cand_tmp, float tau0, hipStr
 }
 
 hipError_t launch_init_pheromone(const Dev &d, float tau0, hipStream_t s) {
+  if (d.etad) {
+    const size_t total = (size_t)d.n * d.ldn;
+    hipLaunchKernelGGL(k_etad, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, s, d);
+    const hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+  }
   size_t total = (size_t)d.n * d.ldn;
   if (total < (size_t)d.n * d.spm_s) total = (size_t)d.n * d.spm_s;
   if (total < 8) total = 8;
@@ -715,29 +1264,34 @@ hipError_t launch_init_pheromone(const Dev &d, float tau0, hipStream_t s) {
 }
 
 hipError_t launch_construct(const Dev &d, const Iter &it, int mode, int memory, hipStream_t s) {
-  if (memory != 0) return hipErrorInvalidValue;
   if (mode == 0) {
     const int apb = kSyncBlock / 64;
     const int grid = (d.m + apb - 1) / apb;
     Dev dd = d;
     Iter a = it;
     void *args[] = {&dd, &a};
-    return hipLaunchCooperativeKernel(reinterpret_cast<void *>(&k_construct_sync_dense),
-                                      dim3(grid), dim3(kSyncBlock), args, lds_bytes(d, kSyncBlock), s);
+    const void *fn = memory == 0 ? reinterpret_cast<const void *>(&k_construct_sync_dense)
+                                 : reinterpret_cast<const void *>(&k_construct_sync_spm);
+    return hipLaunchCooperativeKernel(fn, dim3(grid), dim3(kSyncBlock), args,
+                                      lds_bytes(d, kSyncBlock), s);
   }
   const int apb = kAsyncBlock / 64;
   const int grid = (d.m + apb - 1) / apb;
-  hipLaunchKernelGGL(k_construct_async_dense, dim3(grid), dim3(kAsyncBlock),
-                     lds_bytes(d, kAsyncBlock), s, d, it);
+  if (memory == 0)
+    hipLaunchKernelGGL(k_construct_async_dense, dim3(grid), dim3(kAsyncBlock),
+                       lds_bytes(d, kAsyncBlock), s, d, it);
+  else
+    hipLaunchKernelGGL(k_construct_async_spm, dim3(grid), dim3(kAsyncBlock),
+                       lds_bytes(d, kAsyncBlock), s, d, it);
   return hipGetLastError();
 }
 
 int max_sync_ants(const Dev &d, int memory) {
-  if (memory != 0) return 0;
   int per_cu = 0;
-  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(
-          &per_cu, reinterpret_cast<const void *>(&k_construct_sync_dense), kSyncBlock,
-          lds_bytes(d, kSyncBlock)) != hipSuccess)
+  const void *fn = memory == 0 ? reinterpret_cast<const void *>(&k_construct_sync_dense)
+                               : reinterpret_cast<const void *>(&k_construct_sync_spm);
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, kSyncBlock,
+                                                   lds_bytes(d, kSyncBlock)) != hipSuccess)
     return 0;
   int dev = 0, cus = 0;
   if (hipGetDevice(&dev) != hipSuccess) return 0;
@@ -747,8 +1301,30 @@ int max_sync_ants(const Dev &d, int memory) {
 }
 
 hipError_t launch_best_global(const Dev &d, const Iter &it, int memory, hipStream_t s) {
-  if (memory != 0) return hipErrorInvalidValue;
-  hipLaunchKernelGGL(k_best_global_dense, dim3(1), dim3(1024), 0, s, d, it);
+  hipLaunchKernelGGL(k_best, dim3(1), dim3(1024), 0, s, d);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  if (memory == 0)
+    hipLaunchKernelGGL(k_global_dense, dim3((d.n + 255) / 256), dim3(256), 0, s, d, it);
+  else
+    hipLaunchKernelGGL(k_global_spm, dim3((d.n + 3) / 4), dim3(256), 0, s, d, it);
+  return hipGetLastError();
+}
+
+hipError_t launch_batch_iteration(const Dev *devs, Iter *iters, const int2 *items, int nitems,
+                                  int count, int nmax, hipStream_t s) {
+  const int apb = kAsyncBlock / 64;
+  const int wmax = (nmax + 31) / 32;
+  const size_t lds = (size_t)apb * wmax * sizeof(uint32_t);
+  hipLaunchKernelGGL(k_construct_async_batch, dim3((nitems + apb - 1) / apb), dim3(kAsyncBlock),
+                     lds, s, devs, iters, items, nitems, wmax);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_best_batch, dim3(count), dim3(1024), 0, s, devs, iters);
+  e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_global_batch, dim3((nmax + 255) / 256, count), dim3(256), 0, s, devs,
+                     iters);
   return hipGetLastError();
 }
 

@@ -212,3 +212,146 @@ def test_async_quality_distribution(acs):
     assert abs(asy.mean() - sync.mean()) / sync.mean() < 0.03
     p = mannwhitneyu(sync, asy).pvalue
     _say(f"sync mean {sync.mean():.1f}, async mean {asy.mean():.1f}, rank-sum p={p:.3f}")
+
+
+# ---------------------------------------------------------------------------
+# Selective pheromone memory (Sec. 3.2, Alg. 3): records, tails and tours
+# bit-exact in synchronous mode.
+# ---------------------------------------------------------------------------
+SPM_CASES = [
+    ("n300_m60_s8", 300, dict(m=60, cl=16, spm_s=8), 6),
+    ("n201_m201_s4", 201, dict(cl=32, spm_s=4), 4),
+    ("n150_m33_s1", 150, dict(m=33, cl=10, spm_s=1), 4),
+    ("n97_m200_s16_q0", 97, dict(m=200, cl=20, spm_s=16, q0=0.0), 4),
+]
+
+
+@pytest.mark.parametrize("name,n,kw,iters", SPM_CASES, ids=[c[0] for c in SPM_CASES])
+def test_spm_sync_parity(acs, name, n, kw, iters):
+    _say(f"SPM sync {name}")
+    xy = inputs.uniform(n, 500 + n)
+    col, orc = _pair(acs, xy, memory=1, seed=11, **kw)
+    for it in range(iters):
+        col.iterate(1)
+        orc.iterate(1)
+        _compare(col, orc, it)
+        st, oc = col.stats(), orc.counts()
+        assert st["spm_hits"] == oc["spm_hits"] and st["spm_misses"] == oc["spm_misses"]
+    col.close()
+
+
+def test_spm_without_eviction_equals_dense_on_gpu(acs):
+    n = 16
+    xy = inputs.uniform(n, 77)
+    spm = acs.Colony(xy, cl=8, memory=1, spm_s=n - 1, seed=2)
+    den = acs.Colony(xy, cl=8, memory=0, seed=2)
+    for it in range(8):
+        spm.iterate(1)
+        den.iterate(1)
+        assert np.array_equal(spm.tours(), den.tours())
+        # the logical pheromone of the records equals the dense matrix
+        nodes, vals, _ = spm.spm()
+        tau = np.full((n, n), np.float32(spm.stats()["tau0"]))
+        for i in range(n):
+            for slot in range(n - 1):
+                if nodes[i, slot] >= 0:
+                    tau[i, nodes[i, slot]] = vals[i, slot]
+        dt = den.tau()
+        off = ~np.eye(n, dtype=bool)
+        assert np.array_equal(tau[off], dt[off])
+    spm.close(); den.close()
+
+
+def test_spm_full_size_first_iteration(acs):
+    """n=20000 uniform, m=1024, cl=16, s=8: the first iteration bit-exact."""
+    oracle.set_threads(16)
+    xy = inputs.uniform(20000)
+    _say("SPM n=20000 create")
+    col = acs.Colony(xy, m=1024, cl=16, memory=1, spm_s=8, seed=3)
+    orc = oracle.Oracle(xy, m=1024, cl=16, memory=1, spm_s=8, seed=3)
+    _say("SPM n=20000 iteration 0")
+    col.iterate(1)
+    orc.iterate(1)
+    _compare(col, orc, 0)
+    col.close()
+    oracle.set_threads(1)
+
+
+@pytest.mark.parametrize("n,m", [(300, 300), (20000, 1024)])
+def test_spm_async_tours_valid(acs, n, m):
+    xy = inputs.uniform(n)
+    col = acs.Colony(xy, m=m, cl=16, memory=1, spm_s=8, mode=acs.ACS_ASYNC_ATOMIC, seed=1)
+    for it in range(2):
+        _say(f"SPM async n={n} iteration {it}")
+        col.iterate(1)
+        tours, lens = col.tours(), col.lengths()
+        assert np.all(np.sort(tours, axis=1) == np.arange(n)[None, :])
+        d = None
+        if n <= 1000:
+            d = defs.dist_matrix(xy)
+            rec = d[tours, np.roll(tours, -1, axis=1)].sum(axis=1)
+            assert np.array_equal(rec, lens)
+        nodes, vals, tail = col.spm()
+        assert np.all((nodes >= -1) & (nodes < n))
+        assert np.all(np.isfinite(vals)) and np.all(vals > 0)
+        assert np.all((tail >= 0) & (tail < 8))
+        st = col.stats()
+        assert st["steps"] == (it + 1) * m * (n - 1)
+        assert st["spm_hits"] + st["spm_misses"] == (it + 1) * (2 * m * n + 2 * n)
+    col.close()
+
+
+def test_spm_async_single_ant_equals_oracle(acs):
+    xy = inputs.uniform(250, 6)
+    col = acs.Colony(xy, m=1, cl=12, memory=1, spm_s=6, mode=acs.ACS_ASYNC_ATOMIC, seed=8)
+    orc = oracle.Oracle(xy, m=1, cl=12, memory=1, spm_s=6, seed=8)
+    for it in range(6):
+        col.iterate(1)
+        orc.iterate(1)
+        _compare(col, orc, it)
+    col.close()
+
+
+# ---------------------------------------------------------------------------
+# Batches: many instances in one graph-replayed launch per iteration.
+# ---------------------------------------------------------------------------
+def test_batch_single_ant_equals_oracle(acs):
+    """With one ant per instance the asynchronous schedule equals the
+    synchronous one, so every instance of the batch must match the oracle
+    run with its own counter word (instance = i) bit for bit."""
+    insts = inputs.batch(6, seed=31, nmin=40, nmax=300)
+    b = acs.Batch(insts, m=1, cl=16, seed=5)
+    orcs = [oracle.Oracle(x, m=1, cl=16, seed=5, instance=i) for i, x in enumerate(insts)]
+    assert b.info()["count"] == 6
+    for it in range(4):
+        b.iterate(1)
+        for i, o in enumerate(orcs):
+            o.iterate(1)
+            assert np.array_equal(b.tours(i), o.tours()), (i, it)
+            assert np.array_equal(b.lengths(i), o.lengths()), (i, it)
+            assert b.best(i)[1] == o.best()[1], (i, it)
+            assert np.array_equal(b.tau(i), o.tau()), (i, it)
+    b.close()
+
+
+def test_batch_tours_valid(acs):
+    insts = inputs.batch(24, seed=7, nmin=60, nmax=400)
+    b = acs.Batch(insts, seed=2)
+    info = b.info()
+    _say(f"batch info {info}")
+    b.iterate(3)
+    total = 0
+    for i, xy in enumerate(insts):
+        n = len(xy)
+        tours, lens = b.tours(i), b.lengths(i)
+        assert tours.shape == (n, n)
+        assert np.all(np.sort(tours, axis=1) == np.arange(n)[None, :])
+        d = defs.dist_matrix(xy)
+        assert np.array_equal(d[tours, np.roll(tours, -1, axis=1)].sum(axis=1), lens)
+        best, L = b.best(i)
+        assert defs.tour_length(d, best) == L
+        st = b.stats(i)
+        assert st["steps"] == 3 * n * (n - 1) and st["iteration"] == 3
+        total += n * (n - 1)
+    assert info["steps_per_iteration"] == total
+    b.close()
