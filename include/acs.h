@@ -202,6 +202,50 @@ int acs_batch_best_tour(acs_batch_t *b, int32_t i, int32_t *tour_out, int64_t *l
 /* Releases the batch and every instance handle in it; NULL is a no-op. */
 void acs_batch_destroy(acs_batch_t *b);
 
+/* ------------------------------------------------------------------------
+ * Learned edge prior (an addition to the paper's method).  A 4-64-64-1 MLP
+ * (ReLU hidden layers, bf16 operands, fp32 accumulation on the matrix
+ * cores) scores the edge from city i to its r-th nearest neighbour j
+ * (r < 16) from the features (dx / s_i, dy / s_i, d_ij / s_i, r / 15),
+ * s_i = d(i, 16th nearest neighbour).  max(sigmoid(z), 1e-6) then replaces
+ * eta^beta of that candidate in Eq. 1 and Eq. 2 (Sec. 3); the fallback over
+ * all unvisited cities keeps eta^beta.  Parameters are one device array of
+ * ACS_PRIOR_PARAMS floats: W1[4][64] | b1[64] | W2[64][64] | b2[64] |
+ * W3[64] | b3.  Functions taking `stream` run asynchronously on it (NULL:
+ * the default stream); their pointer arguments are device pointers.
+ * ------------------------------------------------------------------------ */
+#define ACS_PRIOR_PARAMS 4545
+
+/* Features of the 16 candidate edges of every city of h into X_dev
+ * (n * 16 rows of 4 floats, row i * 16 + r).  Needs cl = 16. */
+int acs_prior_features(struct acs_t *h, float *X_dev);
+
+/* Logits of `rows` feature rows. */
+int acs_prior_forward(const float *P_dev, const float *X_dev, int32_t rows, float *Z_dev,
+                      void *stream);
+
+/* Adds to G_dev the gradient of the mean binary cross-entropy (with logits)
+ * of the rows against labels Y_dev in [0, 1], and the summed loss to
+ * *loss_dev (both caller-initialised). */
+int acs_prior_grad(const float *P_dev, const float *X_dev, const float *Y_dev, int32_t rows,
+                   float *G_dev, float *loss_dev, void *stream);
+
+/* One Adam step (Kingma and Ba, 2015; bias-corrected, `step` >= 1) on the
+ * parameters; zeroes G_dev afterwards.  M_dev, V_dev: moment estimates. */
+int acs_prior_adam(float *P_dev, float *G_dev, float *M_dev, float *V_dev, int32_t step,
+                   float lr, float beta1, float beta2, float eps, void *stream);
+
+/* Scores of every candidate edge of h from the network, written in place
+ * of eta^beta (needs cl = 16).  Later iterations of h use them. */
+int acs_prior_apply(struct acs_t *h, const float *P_dev);
+
+/* Replaces the candidate weights (eta^beta) of h by host scores[n * cl],
+ * each a positive finite float. */
+int acs_set_candidate_scores(struct acs_t *h, const float *scores);
+
+/* The candidate weights h currently uses (eta^beta or scores), n * cl. */
+int acs_candidate_weights(struct acs_t *h, float *out, size_t count);
+
 #ifdef __cplusplus
 }
 #endif

@@ -92,6 +92,13 @@ def load() -> C.CDLL:
     lib.acs_batch_best_tour.argtypes = [P, i32, P, C.POINTER(i64)]
     lib.acs_batch_destroy.argtypes = [P]
     lib.acs_batch_destroy.restype = None
+    lib.acs_prior_features.argtypes = [P, P]
+    lib.acs_prior_forward.argtypes = [P, P, i32, P, P]
+    lib.acs_prior_grad.argtypes = [P, P, P, i32, P, P, P]
+    lib.acs_prior_adam.argtypes = [P, P, P, P, i32, C.c_float, C.c_float, C.c_float, C.c_float, P]
+    lib.acs_prior_apply.argtypes = [P, P]
+    lib.acs_set_candidate_scores.argtypes = [P, P]
+    lib.acs_candidate_weights.argtypes = [P, P, sz]
     lib.acs_last_error.restype = C.c_char_p
     _lib = lib
     return lib
@@ -244,6 +251,26 @@ class Colony:
     def stats(self):
         return acs_stats(self.h)
 
+    def candidate_weights(self):
+        out = np.empty((self.n, self.cl), dtype=np.float32)
+        _check(load().acs_candidate_weights(self.h, _ptr(out), out.size))
+        return out
+
+    def set_candidate_scores(self, scores):
+        sc = np.ascontiguousarray(scores, dtype=np.float32).reshape(self.n, self.cl)
+        _check(load().acs_set_candidate_scores(self.h, _ptr(sc)))
+
+    def prior_features(self):
+        """Edge features (n*16, 4) as a torch tensor on the GPU."""
+        import torch
+        X = torch.empty((self.n * 16, 4), dtype=torch.float32, device="cuda")
+        _check(load().acs_prior_features(self.h, C.c_void_p(X.data_ptr())))
+        return X
+
+    def apply_prior(self, params):
+        """Replace the candidate weights by the network's scores (params: cuda tensor)."""
+        _check(load().acs_prior_apply(self.h, C.c_void_p(params.data_ptr())))
+
 
 def acs_batch_workspace_bytes(sizes, p: acs_params) -> int:
     n = np.ascontiguousarray(sizes, dtype=np.int32)
@@ -318,3 +345,47 @@ class Batch:
 
     def stats(self, i: int):
         return acs_stats(self.handle(i))
+
+
+PRIOR_PARAMS = 4545
+
+
+def _stream_ptr():
+    import torch
+    return C.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def prior_forward(P, X):
+    """Logits of the rows of X (cuda float32 tensors)."""
+    import torch
+    Z = torch.empty(X.shape[0], dtype=torch.float32, device=X.device)
+    _check(load().acs_prior_forward(C.c_void_p(P.data_ptr()), C.c_void_p(X.data_ptr()),
+                                    X.shape[0], C.c_void_p(Z.data_ptr()), _stream_ptr()))
+    return Z
+
+
+def prior_grad(P, X, Y, G, L):
+    """Accumulates the mean-BCE gradient into G and the summed loss into L."""
+    _check(load().acs_prior_grad(C.c_void_p(P.data_ptr()), C.c_void_p(X.data_ptr()),
+                                 C.c_void_p(Y.data_ptr()), X.shape[0], C.c_void_p(G.data_ptr()),
+                                 C.c_void_p(L.data_ptr()), _stream_ptr()))
+
+
+def prior_adam(P, G, M, V, step, lr=1e-3, beta1=0.9, beta2=0.999, eps=1e-8):
+    _check(load().acs_prior_adam(C.c_void_p(P.data_ptr()), C.c_void_p(G.data_ptr()),
+                                 C.c_void_p(M.data_ptr()), C.c_void_p(V.data_ptr()), step, lr,
+                                 beta1, beta2, eps, _stream_ptr()))
+
+
+def pack_prior(p: dict) -> np.ndarray:
+    """Parameter dict (W1, b1, W2, b2, W3, b3) -> flat float32 vector."""
+    v = np.concatenate([p["W1"].reshape(-1), p["b1"].reshape(-1), p["W2"].reshape(-1),
+                        p["b2"].reshape(-1), p["W3"].reshape(-1), p["b3"].reshape(-1)])
+    assert v.size == PRIOR_PARAMS
+    return v.astype(np.float32)
+
+
+def unpack_prior(v) -> dict:
+    v = np.asarray(v, dtype=np.float32)
+    return {"W1": v[0:256].reshape(4, 64), "b1": v[256:320], "W2": v[320:4416].reshape(64, 64),
+            "b2": v[4416:4480], "W3": v[4480:4544].reshape(64, 1), "b3": v[4544:4545]}

@@ -772,6 +772,82 @@ int acs_batch_best_tour(acs_batch_t *b, int32_t i, int32_t *tour_out, int64_t *l
   return acs_best_tour(h, tour_out, len_out);
 }
 
+// ---------------------------------------------------------------------------
+// Learned edge prior.
+// ---------------------------------------------------------------------------
+int acs_prior_features(acs_t *h, float *X_dev) {
+  if (!live(h)) return fail(ACS_E_STATE, "invalid handle");
+  if (!X_dev) return fail(ACS_E_INVALID, "X is NULL");
+  if (h->cl != 16) return fail(ACS_E_UNSUPPORTED, "the prior uses cl = 16 (handle has %d)", h->cl);
+  HIP_TRY(acs::launch_prior_features(h->dev, X_dev, h->stream));
+  HIP_TRY(hipStreamSynchronize(h->stream));
+  return ACS_OK;
+}
+
+int acs_prior_forward(const float *P_dev, const float *X_dev, int32_t rows, float *Z_dev,
+                      void *stream) {
+  if (!P_dev || !X_dev || !Z_dev || rows < 0) return fail(ACS_E_INVALID, "bad argument");
+  if (rows == 0) return ACS_OK;
+  HIP_TRY(acs::launch_prior_forward(P_dev, X_dev, rows, Z_dev,
+                                    reinterpret_cast<hipStream_t>(stream)));
+  return ACS_OK;
+}
+
+int acs_prior_grad(const float *P_dev, const float *X_dev, const float *Y_dev, int32_t rows,
+                   float *G_dev, float *loss_dev, void *stream) {
+  if (!P_dev || !X_dev || !Y_dev || !G_dev || !loss_dev || rows < 1)
+    return fail(ACS_E_INVALID, "bad argument");
+  HIP_TRY(acs::launch_prior_grad(P_dev, X_dev, Y_dev, rows, G_dev, loss_dev,
+                                 reinterpret_cast<hipStream_t>(stream)));
+  return ACS_OK;
+}
+
+int acs_prior_adam(float *P_dev, float *G_dev, float *M_dev, float *V_dev, int32_t step, float lr,
+                   float beta1, float beta2, float eps, void *stream) {
+  if (!P_dev || !G_dev || !M_dev || !V_dev || step < 1) return fail(ACS_E_INVALID, "bad argument");
+  HIP_TRY(acs::launch_prior_adam(P_dev, G_dev, M_dev, V_dev, step, lr, beta1, beta2, eps,
+                                 reinterpret_cast<hipStream_t>(stream)));
+  return ACS_OK;
+}
+
+int acs_prior_apply(acs_t *h, const float *P_dev) {
+  if (!live(h)) return fail(ACS_E_STATE, "invalid handle");
+  if (!P_dev) return fail(ACS_E_INVALID, "P is NULL");
+  if (h->cl != 16) return fail(ACS_E_UNSUPPORTED, "the prior uses cl = 16 (handle has %d)", h->cl);
+  HIP_TRY(acs::launch_prior_apply(h->dev, P_dev, h->stream));
+  HIP_TRY(hipStreamSynchronize(h->stream));
+  return ACS_OK;
+}
+
+int acs_set_candidate_scores(acs_t *h, const float *scores) {
+  if (!live(h)) return fail(ACS_E_STATE, "invalid handle");
+  if (!scores) return fail(ACS_E_INVALID, "scores is NULL");
+  const size_t cnt = (size_t)h->n * h->cl;
+  for (size_t e = 0; e < cnt; ++e)
+    if (!(scores[e] > 0.f) || !std::isfinite(scores[e]))
+      return fail(ACS_E_INVALID, "score %zu is not a positive finite number", e);
+  std::vector<uint32_t> rec(cnt * 4);
+  HIP_TRY(hipStreamSynchronize(h->stream));
+  HIP_TRY(hipMemcpy(rec.data(), h->ws + h->L.crec, rec.size() * sizeof(uint32_t),
+                    hipMemcpyDeviceToHost));
+  for (size_t e = 0; e < cnt; ++e) std::memcpy(&rec[4 * e + 2], &scores[e], sizeof(float));
+  HIP_TRY(hipMemcpy(h->ws + h->L.crec, rec.data(), rec.size() * sizeof(uint32_t),
+                    hipMemcpyHostToDevice));
+  return ACS_OK;
+}
+
+int acs_candidate_weights(acs_t *h, float *out, size_t count) {
+  if (!live(h)) return fail(ACS_E_STATE, "invalid handle");
+  const size_t cnt = (size_t)h->n * h->cl;
+  if (!out || count < cnt) return fail(ACS_E_BUFSIZE, "need %zu floats", cnt);
+  std::vector<uint32_t> rec(cnt * 4);
+  HIP_TRY(hipStreamSynchronize(h->stream));
+  HIP_TRY(hipMemcpy(rec.data(), h->ws + h->L.crec, rec.size() * sizeof(uint32_t),
+                    hipMemcpyDeviceToHost));
+  for (size_t e = 0; e < cnt; ++e) std::memcpy(&out[e], &rec[4 * e + 2], sizeof(float));
+  return ACS_OK;
+}
+
 void acs_batch_destroy(acs_batch_t *b) {
   {
     std::lock_guard<std::mutex> g(g_live_mu);

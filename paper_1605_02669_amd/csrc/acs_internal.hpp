@@ -70,6 +70,16 @@ hipError_t launch_best_global(const Dev &d, const Iter &it, int memory,
 // three launches can be captured once in a graph and replayed.
 hipError_t launch_batch_iteration(const Dev *devs, Iter *iters, const int2 *items, int nitems,
                                   int count, int nmax, hipStream_t s);
+// Learned edge prior (acs_prior.hip): parameter count and kernels.
+constexpr int kPriorParams = 4545;
+hipError_t launch_prior_forward(const float *P, const float *X, int rows, float *Z,
+                                hipStream_t s);
+hipError_t launch_prior_grad(const float *P, const float *X, const float *Y, int rows, float *G,
+                             float *L, hipStream_t s);
+hipError_t launch_prior_adam(float *P, float *G, float *M, float *V, int t, float lr, float b1,
+                             float b2, float eps, hipStream_t s);
+hipError_t launch_prior_features(const Dev &d, float *X, hipStream_t s);
+hipError_t launch_prior_apply(const Dev &d, const float *P, hipStream_t s);
 // Largest spm_s the GPU kernels support.
 constexpr int kMaxSpmS = 16;
 

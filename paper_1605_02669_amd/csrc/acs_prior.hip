@@ -1,0 +1,339 @@
+// Learned edge prior on gfx950: a 4 -> 64 -> 64 -> 1 MLP (ReLU hidden
+// layers) whose sigmoid output scores candidate edges; the scores replace
+// eta^beta of the candidates in the transition rule (Eq. 1, Eq. 2 of the
+// paper's Sec. 3).  This is an addition of this project, not the paper's.
+//
+// The matrix products run on the BF16 matrix cores (v_mfma_f32_16x16x32_bf16,
+// fp32 accumulation).  Lane layout of that instruction (checked on the GPU):
+//   A (16 x 32): lane l holds A[l % 16][8 (l / 16) + 0..7]
+//   B (32 x 16): lane l holds B[8 (l / 16) + 0..7][l % 16]
+//   D (16 x 16): lane l holds D[4 (l / 16) + 0..3][l % 16]
+// Weights are kept in fp32 (master copy, optimizer state) and rounded to
+// bf16 when staged into LDS; activations are rounded to bf16 between layers.
+//
+// Parameter vector (floats): W1[4][64] | b1[64] | W2[64][64] | b2[64] |
+// W3[64] | b3[1] (row-major, x @ W + b).
+#include <hip/hip_runtime.h>
+
+#include "acs_internal.hpp"
+
+namespace acs {
+namespace {
+
+typedef __attribute__((__vector_size__(8 * sizeof(__bf16)))) __bf16 bf16x8;
+typedef __attribute__((__vector_size__(4 * sizeof(float)))) float f32x4;
+
+constexpr int H = 64;
+constexpr int OW1 = 0, OB1 = 256, OW2 = 320, OB2 = 4416, OW3 = 4480, OB3 = 4544;
+
+// Weights staged in LDS, transposed so that a B operand is one 16-byte read:
+//   w1t[n][k]  (64 x 32, k >= 4 zero)        B[k][n] = W1[k][n]
+//   w2t[n][k]  (64 x 64)                      B[k][n] = W2[k][n]
+//   w2r[n][k]  (64 x 64) = W2 row-major       B[k][n] = W2[n][k]   (W2^T)
+//   w3t[n][k]  (16 x 64, n >= 1 zero)         B[k][n] = W3[k]
+struct alignas(16) Stage {
+  __bf16 w1t[H * 32];
+  __bf16 w2t[H * H];
+  __bf16 w2r[H * H];
+  __bf16 w3t[16 * H];
+  float b1[H], b2[H], w3[H], b3;
+};
+
+__device__ __forceinline__ void stage_weights(Stage &S, const float *P) {
+  for (int e = threadIdx.x; e < H * 32; e += blockDim.x) {
+    const int n = e / 32, k = e % 32;
+    S.w1t[e] = (__bf16)(k < 4 ? P[OW1 + k * H + n] : 0.f);
+  }
+  for (int e = threadIdx.x; e < H * H; e += blockDim.x) {
+    const int n = e / H, k = e % H;
+    S.w2t[e] = (__bf16)P[OW2 + k * H + n];
+    S.w2r[e] = (__bf16)P[OW2 + e];
+  }
+  for (int e = threadIdx.x; e < 16 * H; e += blockDim.x) {
+    const int n = e / H, k = e % H;
+    S.w3t[e] = (__bf16)(n == 0 ? P[OW3 + k] : 0.f);
+  }
+  for (int e = threadIdx.x; e < H; e += blockDim.x) {
+    S.b1[e] = P[OB1 + e];
+    S.b2[e] = P[OB2 + e];
+    S.w3[e] = P[OW3 + e];
+  }
+  if (threadIdx.x == 0) S.b3 = P[OB3];
+  __syncthreads();
+}
+
+__device__ __forceinline__ bf16x8 ld8(const __bf16 *p) {
+  return *reinterpret_cast<const bf16x8 *>(p);
+}
+
+__device__ __forceinline__ f32x4 mfma(bf16x8 a, bf16x8 b, f32x4 c) {
+  return __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, c, 0, 0, 0);
+}
+
+// Forward pass of 16 rows held by one wave.  x: this lane's row features
+// (valid in lane group 0).  Writes relu activations (bf16, row-major
+// [16][64]) to h1 and h2 and returns the logit of rows 4g + v in z[v] for
+// lanes with l % 16 == 0.
+__device__ __forceinline__ f32x4 forward16(const Stage &S, float4 x, int lane, __bf16 *h1,
+                                           __bf16 *h2) {
+  const int g = lane >> 4, c16 = lane & 15;
+  bf16x8 a1;
+  for (int q = 0; q < 8; ++q) a1[q] = (__bf16)0.f;
+  if (g == 0) {
+    a1[0] = (__bf16)x.x;
+    a1[1] = (__bf16)x.y;
+    a1[2] = (__bf16)x.z;
+    a1[3] = (__bf16)x.w;
+  }
+  const f32x4 zero = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+  for (int t = 0; t < 4; ++t) {
+    const f32x4 d = mfma(a1, ld8(S.w1t + (16 * t + c16) * 32 + 8 * g), zero);
+#pragma unroll
+    for (int v = 0; v < 4; ++v)
+      h1[(4 * g + v) * H + 16 * t + c16] = (__bf16)fmaxf(d[v] + S.b1[16 * t + c16], 0.f);
+  }
+  const bf16x8 a2a = ld8(h1 + c16 * H + 8 * g), a2b = ld8(h1 + c16 * H + 32 + 8 * g);
+#pragma unroll
+  for (int t = 0; t < 4; ++t) {
+    f32x4 d = mfma(a2a, ld8(S.w2t + (16 * t + c16) * H + 8 * g), zero);
+    d = mfma(a2b, ld8(S.w2t + (16 * t + c16) * H + 32 + 8 * g), d);
+#pragma unroll
+    for (int v = 0; v < 4; ++v)
+      h2[(4 * g + v) * H + 16 * t + c16] = (__bf16)fmaxf(d[v] + S.b2[16 * t + c16], 0.f);
+  }
+  const bf16x8 a3a = ld8(h2 + c16 * H + 8 * g), a3b = ld8(h2 + c16 * H + 32 + 8 * g);
+  f32x4 d = mfma(a3a, ld8(S.w3t + c16 * H + 8 * g), zero);
+  d = mfma(a3b, ld8(S.w3t + c16 * H + 32 + 8 * g), d);
+  for (int v = 0; v < 4; ++v) d[v] += S.b3;
+  return d;
+}
+
+__device__ __forceinline__ float4 load_x(const float *X, int row, int rows) {
+  return row < rows ? *reinterpret_cast<const float4 *>(X + (size_t)row * 4)
+                    : make_float4(0.f, 0.f, 0.f, 0.f);
+}
+
+// Logits of `rows` feature rows: one wave per block, 16 rows per tile.
+__global__ __launch_bounds__(64) void k_prior_forward(const float *P, const float *X, int rows,
+                                                      float *Z) {
+  __shared__ Stage S;
+  __shared__ alignas(16) __bf16 h1[16 * H];
+  __shared__ alignas(16) __bf16 h2[16 * H];
+  stage_weights(S, P);
+  const int lane = threadIdx.x;
+  for (int r0 = blockIdx.x * 16; r0 < rows; r0 += gridDim.x * 16) {
+    const f32x4 z = forward16(S, load_x(X, r0 + (lane & 15), rows), lane, h1, h2);
+    if ((lane & 15) == 0)
+      for (int v = 0; v < 4; ++v) {
+        const int r = r0 + 4 * (lane >> 4) + v;
+        if (r < rows) Z[r] = z[v];
+      }
+  }
+}
+
+// Gradient of the mean binary cross-entropy (with logits) over all `rows`
+// rows, accumulated into G; loss sum into *L.  One wave per block, 32 rows
+// per tile (two 16-row forward passes).  dW2 = H1^T dH2 and dH1 = dH2 W2^T
+// run on the matrix cores; the 4-wide first layer, the 64 -> 1 last layer
+// and the biases on the vector units.
+__global__ __launch_bounds__(64) void k_prior_grad(const float *P, const float *X,
+                                                   const float *Y, int rows, float *G,
+                                                   float *L) {
+  __shared__ Stage S;
+  __shared__ alignas(16) __bf16 h1[32 * H];    // row-major activations
+  __shared__ alignas(16) __bf16 h2[32 * H];
+  __shared__ alignas(16) __bf16 h1t[H * 32];   // H1^T [feature][row]
+  __shared__ alignas(16) __bf16 dh2[32 * H];
+  __shared__ alignas(16) __bf16 dh2t[H * 32];
+  __shared__ float zs[32], dzs[32], xs[32 * 4];
+  stage_weights(S, P);
+  const int lane = threadIdx.x, g = lane >> 4, c16 = lane & 15;
+  const float inv_rows = 1.f / (float)rows;
+  f32x4 gw2[4][4];
+  for (int a = 0; a < 4; ++a)
+    for (int b = 0; b < 4; ++b) gw2[a][b] = (f32x4){0.f, 0.f, 0.f, 0.f};
+  float gw1[4][4] = {};  // [nt][input] partials for feature 16 nt + c16
+  float gb1[4] = {};
+  float gw3 = 0.f, gb2 = 0.f, gb3 = 0.f, loss = 0.f;  // lane = feature
+
+  for (int r0 = blockIdx.x * 32; r0 < rows; r0 += gridDim.x * 32) {
+    // forward of two 16-row halves
+    for (int hf = 0; hf < 2; ++hf) {
+      const int row = r0 + 16 * hf + c16;
+      const float4 x = load_x(X, row, rows);
+      if (g == 0) {
+        xs[(16 * hf + c16) * 4 + 0] = x.x;
+        xs[(16 * hf + c16) * 4 + 1] = x.y;
+        xs[(16 * hf + c16) * 4 + 2] = x.z;
+        xs[(16 * hf + c16) * 4 + 3] = x.w;
+      }
+      const f32x4 z = forward16(S, x, lane, h1 + 16 * hf * H, h2 + 16 * hf * H);
+      if (c16 == 0)
+        for (int v = 0; v < 4; ++v) zs[16 * hf + 4 * g + v] = z[v];
+    }
+    // dz = (sigmoid(z) - y) / rows, loss = softplus(z) - y z (rows past the end: 0)
+    if (lane < 32) {
+      const int row = r0 + lane;
+      float dz = 0.f;
+      if (row < rows) {
+        const float z = zs[lane], y = Y[row];
+        dz = (1.f / (1.f + __expf(-z)) - y) * inv_rows;
+        loss += fmaxf(z, 0.f) + log1pf(__expf(-fabsf(z))) - y * z;
+      }
+      dzs[lane] = dz;
+    }
+    // last layer and dH2 (lane = feature f)
+    {
+      const int f = lane;
+      for (int r = 0; r < 32; ++r) {
+        const float hv = (float)h2[r * H + f];
+        const float dz = dzs[r];
+        gw3 += hv * dz;
+        const float dh = hv > 0.f ? dz * S.w3[f] : 0.f;
+        gb2 += dh;
+        dh2[r * H + f] = (__bf16)dh;
+        dh2t[f * 32 + r] = (__bf16)dh;
+        h1t[f * 32 + r] = h1[r * H + f];
+      }
+      if (lane < 32) gb3 += dzs[lane];
+    }
+    // dW2 += H1^T dH2: M = 64 features (4 tiles), N = 64 (4 tiles), K = 32 rows
+    for (int mt = 0; mt < 4; ++mt) {
+      const bf16x8 a = ld8(h1t + (16 * mt + c16) * 32 + 8 * g);
+      for (int nt = 0; nt < 4; ++nt)
+        gw2[mt][nt] = mfma(a, ld8(dh2t + (16 * nt + c16) * 32 + 8 * g), gw2[mt][nt]);
+    }
+    // dH1 = dH2 W2^T, masked by H1 > 0: M = 32 rows (2 tiles), N = 64, K = 64
+    for (int mh = 0; mh < 2; ++mh) {
+      const bf16x8 aa = ld8(dh2 + (16 * mh + c16) * H + 8 * g);
+      const bf16x8 ab = ld8(dh2 + (16 * mh + c16) * H + 32 + 8 * g);
+      for (int nt = 0; nt < 4; ++nt) {
+        const f32x4 zero = {0.f, 0.f, 0.f, 0.f};
+        f32x4 d = mfma(aa, ld8(S.w2r + (16 * nt + c16) * H + 8 * g), zero);
+        d = mfma(ab, ld8(S.w2r + (16 * nt + c16) * H + 32 + 8 * g), d);
+        for (int v = 0; v < 4; ++v) {
+          const int r = 16 * mh + 4 * g + v;
+          const int f = 16 * nt + c16;
+          const float dh1 = (float)h1[r * H + f] > 0.f ? d[v] : 0.f;
+          gb1[nt] += dh1;
+          for (int c = 0; c < 4; ++c) gw1[nt][c] += xs[r * 4 + c] * dh1;
+        }
+      }
+    }
+  }
+  // write out: dW2 in the D layout, the rest per lane
+  for (int mt = 0; mt < 4; ++mt)
+    for (int nt = 0; nt < 4; ++nt)
+      for (int v = 0; v < 4; ++v)
+        atomicAdd(&G[OW2 + (16 * mt + 4 * g + v) * H + 16 * nt + c16], gw2[mt][nt][v]);
+  for (int nt = 0; nt < 4; ++nt) {
+    atomicAdd(&G[OB1 + 16 * nt + c16], gb1[nt]);
+    for (int c = 0; c < 4; ++c) atomicAdd(&G[OW1 + c * H + 16 * nt + c16], gw1[nt][c]);
+  }
+  atomicAdd(&G[OW3 + lane], gw3);
+  atomicAdd(&G[OB2 + lane], gb2);
+  if (lane < 32) {
+    atomicAdd(&G[OB3], gb3);
+    atomicAdd(L, loss);
+  }
+}
+
+// Adam (Kingma and Ba, 2015) on the fp32 parameters; clears the gradient.
+__global__ __launch_bounds__(256) void k_prior_adam(float *P, float *G, float *M, float *V,
+                                                    int t, float lr, float b1, float b2,
+                                                    float eps) {
+  const int e = blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= kPriorParams) return;
+  const float g = G[e];
+  const float m = b1 * M[e] + (1.f - b1) * g;
+  const float v = b2 * V[e] + (1.f - b2) * g * g;
+  M[e] = m;
+  V[e] = v;
+  const float mh = m / (1.f - powf(b1, (float)t));
+  const float vh = v / (1.f - powf(b2, (float)t));
+  P[e] -= lr * mh / (sqrtf(vh) + eps);
+  G[e] = 0.f;
+}
+
+// Features of the first 16 candidates of every city (row i * 16 + r):
+// (dx / s_i, dy / s_i, d_ij / s_i, r / 15), s_i = d(i, 16th neighbour).
+__device__ __forceinline__ float4 edge_features(const Dev &D, int i, int r) {
+  const uint4 rec = D.crec[(size_t)i * D.cl + r];
+  const uint32_t s16 = D.crec[(size_t)i * D.cl + 15].y;
+  const double s = s16 ? (double)s16 : 1.0;
+  const int j = (int)rec.x;
+  return make_float4((float)((D.xy[2 * j] - D.xy[2 * i]) / s),
+                     (float)((D.xy[2 * j + 1] - D.xy[2 * i + 1]) / s), (float)(rec.y / s),
+                     (float)(r / 15.0));
+}
+
+__global__ __launch_bounds__(256) void k_prior_features(Dev D, float *X) {
+  const int e = blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= D.n * 16) return;
+  *reinterpret_cast<float4 *>(X + (size_t)e * 4) = edge_features(D, e / 16, e % 16);
+}
+
+// Scores of every candidate edge of the instance straight into the
+// eta^beta word of the candidate records: max(sigmoid(z), 1e-6).
+__global__ __launch_bounds__(64) void k_prior_apply(Dev D, const float *P) {
+  __shared__ Stage S;
+  __shared__ alignas(16) __bf16 h1[16 * H];
+  __shared__ alignas(16) __bf16 h2[16 * H];
+  stage_weights(S, P);
+  const int lane = threadIdx.x;
+  const int rows = D.n * 16;
+  for (int r0 = blockIdx.x * 16; r0 < rows; r0 += gridDim.x * 16) {
+    const int row = r0 + (lane & 15);
+    const float4 x = row < rows ? edge_features(D, row / 16, row % 16)
+                                : make_float4(0.f, 0.f, 0.f, 0.f);
+    const f32x4 z = forward16(S, x, lane, h1, h2);
+    if ((lane & 15) == 0)
+      for (int v = 0; v < 4; ++v) {
+        const int r = r0 + 4 * (lane >> 4) + v;
+        if (r < rows) {
+          const float sc = fmaxf(1.f / (1.f + __expf(-z[v])), 1e-6f);
+          const_cast<uint4 *>(D.crec)[(size_t)(r / 16) * D.cl + r % 16].z = __float_as_uint(sc);
+        }
+      }
+  }
+}
+
+}  // namespace
+
+hipError_t launch_prior_forward(const float *P, const float *X, int rows, float *Z,
+                                hipStream_t s) {
+  const int blocks = (rows + 15) / 16 < 4096 ? (rows + 15) / 16 : 4096;
+  hipLaunchKernelGGL(k_prior_forward, dim3(blocks > 0 ? blocks : 1), dim3(64), 0, s, P, X, rows,
+                     Z);
+  return hipGetLastError();
+}
+
+hipError_t launch_prior_grad(const float *P, const float *X, const float *Y, int rows, float *G,
+                             float *L, hipStream_t s) {
+  const int blocks = (rows + 31) / 32 < 2048 ? (rows + 31) / 32 : 2048;
+  hipLaunchKernelGGL(k_prior_grad, dim3(blocks > 0 ? blocks : 1), dim3(64), 0, s, P, X, Y, rows,
+                     G, L);
+  return hipGetLastError();
+}
+
+hipError_t launch_prior_adam(float *P, float *G, float *M, float *V, int t, float lr, float b1,
+                             float b2, float eps, hipStream_t s) {
+  hipLaunchKernelGGL(k_prior_adam, dim3((kPriorParams + 255) / 256), dim3(256), 0, s, P, G, M, V,
+                     t, lr, b1, b2, eps);
+  return hipGetLastError();
+}
+
+hipError_t launch_prior_features(const Dev &d, float *X, hipStream_t s) {
+  hipLaunchKernelGGL(k_prior_features, dim3((d.n * 16 + 255) / 256), dim3(256), 0, s, d, X);
+  return hipGetLastError();
+}
+
+hipError_t launch_prior_apply(const Dev &d, const float *P, hipStream_t s) {
+  const int rows = d.n * 16;
+  const int blocks = (rows + 15) / 16 < 2048 ? (rows + 15) / 16 : 2048;
+  hipLaunchKernelGGL(k_prior_apply, dim3(blocks), dim3(64), 0, s, d, P);
+  return hipGetLastError();
+}
+
+}  // namespace acs
