@@ -65,7 +65,10 @@ typedef struct acs_params {
   uint32_t memory;       /* enum acs_memory */
   uint32_t spm_s;        /* SPM trails per city (Sec. 3.2), >= 1 */
   uint32_t mode;         /* enum acs_mode */
-  uint32_t local_update_period; /* must be 1 */
+  uint32_t local_update_period; /* k >= 1: the local update of Eq. 3 follows only
+                                   the edges selected at steps k, 2k, ... (and
+                                   the closing edge); Sec. 4, limiting the
+                                   number of local pheromone updates */
   uint32_t instance;     /* fourth word of every random-number counter */
   double beta;           /* exponent of eta = 1/d in Eq. 1-2, >= 0 */
   double q0;             /* exploitation probability of Eq. 1, in [0, 1] */

@@ -34,6 +34,8 @@ def load() -> C.CDLL:
     lib.orc_create.argtypes = [P, i32, i32, i32, dbl, dbl, dbl, dbl, dbl, i32, i32, i32, u64, u32]
     lib.orc_destroy.argtypes = [P]
     lib.orc_set_threads.argtypes = [i32]
+    lib.orc_set_local_period.argtypes = [P, i32]
+    lib.orc_set_local_period.restype = C.c_int
     for name in ("orc_iterate",):
         getattr(lib, name).argtypes = [P, i32]
     for name in ("orc_construct", "orc_select_best", "orc_global_update"):
@@ -104,7 +106,8 @@ class Oracle:
     """One ACS colony on one instance, computed on the CPU."""
 
     def __init__(self, xy, m=None, cl=32, beta=2.0, q0=0.9, phi=0.1, rho=0.1,
-                 tau0=0.0, memory=DENSE, spm_s=8, mode=SYNC, seed=0, instance=0):
+                 tau0=0.0, memory=DENSE, spm_s=8, mode=SYNC, seed=0, instance=0,
+                 local_update_period=1):
         self.lib = load()
         self.xy = np.ascontiguousarray(xy, dtype=np.float64).reshape(-1, 2)
         n = self.xy.shape[0]
@@ -114,6 +117,9 @@ class Oracle:
                                      tau0, memory, spm_s, mode, seed, instance)
         if not self.h:
             raise ValueError("oracle: invalid arguments")
+        if self.lib.orc_set_local_period(self.h, int(local_update_period)) != 0:
+            self.close()
+            raise ValueError("oracle: local_update_period must be >= 1")
         self.n, self.m = n, m
         self.cl = self.lib.orc_cl(self.h)
         self.memory, self.spm_s = memory, spm_s

@@ -33,6 +33,7 @@ struct orc {
   uint64_t seed;
   uint32_t instance;
   uint32_t iter;
+  int32_t lperiod; /* local update after every lperiod-th selected edge */
 
   double *xy;
   int32_t *dist;  /* n*n exact integer distances */
@@ -258,6 +259,7 @@ orc *orc_create(const double *xy, int32_t n, int32_t m, int32_t cl,
   o->seed = seed;
   o->instance = instance;
   o->lgb = -1;
+  o->lperiod = 1;
   o->ib = -1;
   o->lib = -1;
 
@@ -443,8 +445,9 @@ void orc_construct(orc *o) {
         move_ant(o, a, t, o->choice[a]);
         count_kind(o, o->kind[a]);
       }
-      for (int32_t a = 0; a < m; ++a)
-        local_update(o, o->tour[(size_t)a * n + t - 1], o->tour[(size_t)a * n + t]);
+      if (t % o->lperiod == 0)
+        for (int32_t a = 0; a < m; ++a)
+          local_update(o, o->tour[(size_t)a * n + t - 1], o->tour[(size_t)a * n + t]);
     } else {
       for (int32_t a = 0; a < m; ++a) {
         int32_t cur = o->tour[(size_t)a * n + t - 1];
@@ -452,11 +455,12 @@ void orc_construct(orc *o) {
         int32_t next = select_next(o, a, t, cur, &k);
         move_ant(o, a, t, next);
         count_kind(o, k);
-        local_update(o, cur, next);
+        if (t % o->lperiod == 0) local_update(o, cur, next);
       }
     }
   }
-  /* closing edges: length and local update (the last step of the schedule) */
+  /* closing edges: length and local update (the last step of the schedule;
+   * updated whatever the period) */
   for (int32_t a = 0; a < m; ++a) {
     int32_t last = o->tour[(size_t)a * n + n - 1], first = o->tour[(size_t)a * n];
     o->len[a] += D(o, last, first);
@@ -495,6 +499,15 @@ void orc_global_update(orc *o) {
       spm_update(o, v, u, a, b);
     }
   }
+}
+
+/* Sec. 4, limiting the number of local updates: the update follows only
+ * every k-th edge an ant selects, i.e. the edges of steps t = k, 2k, ...
+ * (1-based); the closing edge keeps its update. */
+int orc_set_local_period(orc *o, int32_t k) {
+  if (k < 1) return -1;
+  o->lperiod = k;
+  return 0;
 }
 
 void orc_iterate(orc *o, int32_t k) {

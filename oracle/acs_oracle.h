@@ -39,6 +39,9 @@ orc *orc_create(const double *xy, int32_t n, int32_t m, int32_t cl,
                 uint32_t instance);
 void orc_destroy(orc *o);
 void orc_set_threads(int32_t threads);
+/* Local update only after every k-th selected edge (k >= 1; default 1);
+ * returns 0, or -1 for k < 1. */
+int orc_set_local_period(orc *o, int32_t k);
 
 /* One full iteration of Alg. 1 = construct + select_best + global_update. */
 void orc_iterate(orc *o, int32_t k);

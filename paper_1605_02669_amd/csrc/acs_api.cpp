@@ -101,8 +101,7 @@ int check_params(int32_t n, const acs_params *p) {
   if (p->memory != ACS_DENSE && p->memory != ACS_SPM) return fail(ACS_E_INVALID, "bad memory");
   if (p->memory == ACS_SPM && p->spm_s < 1) return fail(ACS_E_INVALID, "spm_s must be >= 1");
   if (p->mode != ACS_SYNC && p->mode != ACS_ASYNC_ATOMIC) return fail(ACS_E_INVALID, "bad mode");
-  if (p->local_update_period != 1)
-    return fail(ACS_E_UNSUPPORTED, "local_update_period must be 1");
+  if (p->local_update_period < 1) return fail(ACS_E_INVALID, "local_update_period must be >= 1");
   if (n > 65535) return fail(ACS_E_UNSUPPORTED, "n = %d > 65535", n);
   const uint32_t cl = std::min<uint32_t>(p->cl, (uint32_t)n - 1);
   if (cl > 64) return fail(ACS_E_UNSUPPORTED, "cl = %u > 64", cl);
@@ -214,6 +213,7 @@ int build(acs_t *h, const double *xy) {
   b.b_loc = (float)(p.phi * (double)h->tau0);
   b.a_glob = (float)(1.0 - p.rho);
   b.tau0 = h->tau0;
+  b.lperiod = p.local_update_period;
   b.rho = p.rho;
   return ACS_OK;
 }

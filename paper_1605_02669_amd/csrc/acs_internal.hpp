@@ -45,6 +45,7 @@ struct Iter {
   uint32_t q0_24;
   float a_loc, b_loc, a_glob;
   float tau0;
+  uint32_t lperiod;  // local update after every lperiod-th selected edge
   double rho;
 };
 

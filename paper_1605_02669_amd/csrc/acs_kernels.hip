@@ -457,6 +457,9 @@ __device__ __forceinline__ void tour_put(const Dev &D, int ant, int t, int lane,
 //   | barrier.
 // The map is the same for every crossing, so the order of the updates of one
 // step does not change the result: an entry crossed k times gets f^k.
+// With a local-update period above 1, a step without updates leaves the
+// pheromone as it is, so it needs neither barrier; the closing edges wait for
+// the last step's selections before they write.
 // ---------------------------------------------------------------------------
 __global__ __launch_bounds__(1024) void k_construct_sync_dense(Dev D, Iter A) {
   extern __shared__ uint32_t smem[];
@@ -495,15 +498,18 @@ __global__ __launch_bounds__(1024) void k_construct_sync_dense(Dev D, Iter A) {
       tour_put(D, ant, t, lane, p.next, tb);
       len += p.d;
     }
-    grid_barrier(D.sync, (++bar) * gridDim.x);
-    if (active) {
-      const int k2 = cand_pos(D, p.next, cur, lane);
-      float *h = lane == 0 ? home(D, cur, p.next, p.k) : home(D, p.next, cur, k2);
-      if (lane < 2) c_retry += cas_apply(h, __float_as_uint(p.tval), A.a_loc, A.b_loc);
-      cur = p.next;
+    if (t % A.lperiod == 0) {
+      grid_barrier(D.sync, (++bar) * gridDim.x);
+      if (active) {
+        const int k2 = cand_pos(D, p.next, cur, lane);
+        float *h = lane == 0 ? home(D, cur, p.next, p.k) : home(D, p.next, cur, k2);
+        if (lane < 2) c_retry += cas_apply(h, __float_as_uint(p.tval), A.a_loc, A.b_loc);
+      }
+      if (t + 1 < n) grid_barrier(D.sync, (++bar) * gridDim.x);
     }
-    if (t + 1 < n) grid_barrier(D.sync, (++bar) * gridDim.x);
+    if (active) cur = p.next;
   }
+  if ((n - 1) % A.lperiod != 0) grid_barrier(D.sync, (++bar) * gridDim.x);
   if (active) {
     // closing edge: its length and, as the last step's crossings, its update
     len += D.dist[(size_t)cur * D.ldn + start];
@@ -575,8 +581,8 @@ __device__ __forceinline__ void ant_async_dense(const Dev &D, const Iter &A, int
     // the weights are complete here, before the updates below are issued, so
     // no later wait for this record also waits for those updates
     __asm__ volatile("" ::"v"(c.w), "v"((int)c.unv));
-    // 2. updates of the previous move (prev, cur)
-    if (t > 1) {
+    // 2. updates of the previous move (prev, cur), selected at step t - 1
+    if (t > 1 && (t - 1) % A.lperiod == 0) {
       const uint64_t b = __ballot(lane < cl && rec.x == (uint32_t)prev);
       const int kr = b ? uni((int)__ffsll((unsigned long long)b) - 1) : -1;
       const float rval = kr >= 0 ? __uint_as_float(rdlane(rec.w, kr)) : fval;
@@ -892,15 +898,17 @@ __global__ __launch_bounds__(1024) void k_construct_sync_spm(Dev D, Iter A) {
       len += p.d;
       next = p.next;
     }
-    if (active) {
-      // t < n: the step's crossing; t == n: the closing edge
-      if (t == n) len += D.dist[(size_t)cur * D.ldn + start];
-      if (lane == 0) spm_register(D, 2 * ant, cur, next);
-      if (lane == 1) spm_register(D, 2 * ant + 1, next, cur);
+    if (active && t == n) len += D.dist[(size_t)cur * D.ldn + start];
+    // t < n: the step's crossing (every lperiod-th step); t == n: the closing edge
+    if (t == n || t % A.lperiod == 0) {
+      if (active) {
+        if (lane == 0) spm_register(D, 2 * ant, cur, next);
+        if (lane == 1) spm_register(D, 2 * ant + 1, next, cur);
+      }
+      grid_barrier(D.sync, (++bar) * gridDim.x);
+      if (active) spm_sync_updates(D, ant, cur, next, A.a_loc, A.b_loc, tau0, lane, hits, misses);
+      if (t < n) grid_barrier(D.sync, (++bar) * gridDim.x);
     }
-    grid_barrier(D.sync, (++bar) * gridDim.x);
-    if (active) spm_sync_updates(D, ant, cur, next, A.a_loc, A.b_loc, tau0, lane, hits, misses);
-    if (t < n) grid_barrier(D.sync, (++bar) * gridDim.x);
     cur = next;
   }
   if (active && lane == 0) {
@@ -1032,7 +1040,7 @@ __global__ __launch_bounds__(256) void k_construct_async_spm(Dev D, Iter A) {
     c_retry += spm_async_finish(D, op, al, bl, tau0);
     const Cand c = weigh_spm(D, vis, lane, rec, pr, tau0);
     __asm__ volatile("" ::"v"(c.w), "v"((int)c.unv));
-    if (t > 1) {
+    if (t > 1 && (t - 1) % A.lperiod == 0) {
       // forward entry of the previous move in prev's record (lane 0),
       // reverse entry in cur's record (lane 1)
       spm_async_issue(D, op, pr_prev, prev, cur, lane, 0, al, bl, tau0, hits, misses);

@@ -93,7 +93,7 @@ def test_default_params():
     ({"struct_size": 8}, 10, acs.ACS_E_INVALID, "struct_size"),
     ({"cl": 0}, 10, acs.ACS_E_INVALID, "cl"),
     ({"cl": 100}, 200, acs.ACS_E_UNSUPPORTED, "cl = 100"),
-    ({"local_update_period": 4}, 10, acs.ACS_E_UNSUPPORTED, "period"),
+    ({"local_update_period": 0}, 10, acs.ACS_E_INVALID, "period"),
 ])
 def test_invalid_parameters_rejected_before_any_device_work(kw, n, code, needle):
     rc, msg, h = _create_rc(inputs.uniform(max(n, 3))[:n], **kw)

@@ -355,3 +355,70 @@ def test_batch_tours_valid(acs):
         total += n * (n - 1)
     assert info["steps_per_iteration"] == total
     b.close()
+
+
+# ---------------------------------------------------------------------------
+# Local-update period k (Sec. 4): only the edges of steps k, 2k, ... and the
+# closing edge get Eq. 3.  Synchronous mode stays bit-exact; one ant makes
+# the asynchronous and batched kernels equal the oracle too.
+# ---------------------------------------------------------------------------
+PERIOD_CASES = [
+    ("dense_k2_n198", 198, dict(local_update_period=2), 6),
+    ("dense_k5_ragged", 141, dict(m=77, cl=16, local_update_period=5), 6),
+    ("dense_k16_n1000_clustered", 1000, dict(m=256, local_update_period=16), 2),
+    ("dense_k_n_minus_1", 97, dict(local_update_period=96), 4),
+    ("dense_k_above_n", 64, dict(local_update_period=1000), 4),
+    ("spm_k4", 300, dict(cl=16, memory=1, spm_s=8, local_update_period=4), 4),
+    ("spm_k7_ragged", 173, dict(m=61, cl=12, memory=1, spm_s=4, local_update_period=7), 4),
+]
+
+
+@pytest.mark.parametrize("name,n,kw,iters", PERIOD_CASES, ids=[c[0] for c in PERIOD_CASES])
+def test_local_update_period_sync_parity(acs, name, n, kw, iters):
+    _say(f"period case {name}")
+    xy = inputs.clustered(n, n + 3) if "clustered" in name else inputs.uniform(n, n + 3)
+    col, orc = _pair(acs, xy, seed=4, **kw)
+    for it in range(iters):
+        col.iterate(1)
+        orc.iterate(1)
+        _compare(col, orc, it)
+    col.close()
+
+
+@pytest.mark.parametrize("memory", [0, 1])
+def test_local_update_period_async_single_ant(acs, memory):
+    xy = inputs.uniform(260, 19)
+    kw = dict(m=1, cl=16, memory=memory, spm_s=6, seed=3, local_update_period=3)
+    col = acs.Colony(xy, mode=acs.ACS_ASYNC_ATOMIC, **kw)
+    orc = oracle.Oracle(xy, **kw)
+    for it in range(5):
+        col.iterate(1)
+        orc.iterate(1)
+        _compare(col, orc, it)
+    col.close()
+
+
+def test_local_update_period_batch_single_ant(acs):
+    insts = inputs.batch(5, seed=41, nmin=50, nmax=250)
+    b = acs.Batch(insts, m=1, cl=16, seed=6, local_update_period=4)
+    orcs = [oracle.Oracle(x, m=1, cl=16, seed=6, instance=i, local_update_period=4)
+            for i, x in enumerate(insts)]
+    for it in range(3):
+        b.iterate(1)
+        for i, o in enumerate(orcs):
+            o.iterate(1)
+            assert np.array_equal(b.tours(i), o.tours()), (i, it)
+            assert np.array_equal(b.tau(i), o.tau()), (i, it)
+    b.close()
+
+
+def test_local_update_period_async_valid(acs):
+    n = 1000
+    xy = inputs.uniform(n, 5)
+    col = acs.Colony(xy, mode=acs.ACS_ASYNC_ATOMIC, seed=1, local_update_period=8)
+    d = defs.dist_matrix(xy)
+    col.iterate(3)
+    tours, lens = col.tours(), col.lengths()
+    assert np.all(np.sort(tours, axis=1) == np.arange(n)[None, :])
+    assert np.array_equal(d[tours, np.roll(tours, -1, axis=1)].sum(axis=1), lens)
+    col.close()

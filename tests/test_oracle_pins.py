@@ -303,6 +303,61 @@ def test_sync_and_sequential_differ_with_many_ants():
     assert not np.array_equal(s.tau(), q.tau())
 
 
+# --------------------------------------------------------------------------
+# Local-update period k (Sec. 4, limiting the number of local updates): the
+# map follows only the edges an ant selects at steps k, 2k, ... plus the
+# closing edge.  Pinned by recounting, from the tours alone, how often each
+# entry must have been mapped: f composes, so every entry must end at
+# f^c(before) with c its count, whatever the order of the updates.
+# --------------------------------------------------------------------------
+@pytest.mark.parametrize("k", [1, 2, 5, 16])
+@pytest.mark.parametrize("mode", [oracle.SYNC, oracle.SEQUENTIAL])
+def test_local_update_period_counts_crossings(k, mode):
+    n, m = 60, 24
+    xy = inputs.uniform(n, 12)
+    o = oracle.Oracle(xy, m=m, cl=8, mode=mode, seed=3, local_update_period=k)
+    o.iterate(6)  # moves the entries of the best tours off the fixed point tau0
+    before = o.tau()
+    o.construct()
+    tours = o.tours()
+    cnt = np.zeros((n, n), dtype=np.int64)
+    for a in range(m):
+        edges = [(tours[a, t - 1], tours[a, t]) for t in range(1, n) if t % k == 0]
+        edges.append((tours[a, n - 1], tours[a, 0]))
+        for u, v in edges:
+            cnt[u, v] += 1
+            cnt[v, u] += 1
+    expect = before.copy()
+    for i, j in zip(*np.nonzero(cnt)):
+        expect[i, j] = o.local_map_k(float(before[i, j]), int(cnt[i, j]))
+    assert np.array_equal(o.tau(), expect)
+    tau0 = np.float32(o.constants()["tau0"])
+    assert np.count_nonzero((cnt > 0) & (before != tau0)) >= 10  # the check has teeth
+
+
+def test_local_update_period_changes_the_run():
+    xy = inputs.uniform(120, 13)
+    a = oracle.Oracle(xy, seed=2)
+    b = oracle.Oracle(xy, seed=2, local_update_period=4)
+    a.iterate(3); b.iterate(3)
+    assert not np.array_equal(a.tours(), b.tours())
+    with pytest.raises(ValueError):
+        oracle.Oracle(xy, local_update_period=0)
+
+
+@pytest.mark.parametrize("k", [3, 8])
+def test_spm_without_eviction_equals_dense_with_period(k):
+    n = 50
+    xy = inputs.clustered(n, 14)
+    den = oracle.Oracle(xy, m=20, cl=10, seed=5, local_update_period=k)
+    spm = oracle.Oracle(xy, m=20, cl=10, seed=5, local_update_period=k,
+                        memory=oracle.SPM, spm_s=n - 1)
+    for _ in range(4):
+        den.iterate(1); spm.iterate(1)
+        assert np.array_equal(den.tours(), spm.tours())
+    assert np.array_equal(den.tau(), spm.tau())
+
+
 @pytest.mark.parametrize("kind", ["uniform", "clustered"])
 def test_spm_without_eviction_equals_dense(kind):
     n = 70
