@@ -55,8 +55,11 @@ enum acs_memory { ACS_DENSE = 0, ACS_SPM = 1 };
  * ACS_ASYNC_ATOMIC: every ant runs its whole tour without waiting for the
  * others and applies the local update of Eq. 3 right after each move with an
  * atomic compare-and-swap; reads see whatever the other ants have written
- * so far (the unsynchronised single-kernel construction of Sec. 3.1.2). */
-enum acs_mode { ACS_SYNC = 0, ACS_ASYNC_ATOMIC = 1 };
+ * so far (the unsynchronised single-kernel construction of Sec. 3.1.2).
+ * ACS_ASYNC_RACY: as ACS_ASYNC_ATOMIC, but each update writes the map of the
+ * value the ant read with a plain store, so updates that race are lost: the
+ * paper's ACS-GPU-Alt (Sec. 3.1.2, the variant without atomic operations). */
+enum acs_mode { ACS_SYNC = 0, ACS_ASYNC_ATOMIC = 1, ACS_ASYNC_RACY = 2 };
 
 typedef struct acs_params {
   uint32_t struct_size;  /* = sizeof(acs_params) */
@@ -180,7 +183,7 @@ int acs_batch_workspace_bytes(const int32_t *n, int32_t count, const acs_params 
                               size_t *out);
 
 /* coords[i]: n[i] (x, y) pairs of instance i, copied.  params as for
- * acs_create (mode must be ACS_ASYNC_ATOMIC, memory ACS_DENSE); a given
+ * acs_create (mode ACS_ASYNC_ATOMIC or ACS_ASYNC_RACY, memory ACS_DENSE); a given
  * workspace must hold acs_batch_workspace_bytes. */
 int acs_batch_create(const double *const *coords, const int32_t *n, int32_t count,
                      const acs_params *p, acs_batch_t **out);

@@ -24,7 +24,7 @@ ACS_E_STATE = -5
 ACS_E_UNSUPPORTED = -6
 
 ACS_DENSE, ACS_SPM = 0, 1
-ACS_SYNC, ACS_ASYNC_ATOMIC = 0, 1
+ACS_SYNC, ACS_ASYNC_ATOMIC, ACS_ASYNC_RACY = 0, 1, 2
 
 
 class acs_params(C.Structure):
@@ -284,12 +284,13 @@ class Batch:
     """Many instances, one colony each, iterated together (asynchronous mode)."""
 
     def __init__(self, instances, m=0, cl=32, beta=2.0, q0=0.9, phi=0.1, rho=0.1, tau0=0.0,
-                 seed=0, instance=0, local_update_period=1, torch_memory=True):
+                 seed=0, instance=0, local_update_period=1, mode=ACS_ASYNC_ATOMIC,
+                 torch_memory=True):
         self.xys = [np.ascontiguousarray(x, dtype=np.float64).reshape(-1, 2) for x in instances]
         sizes = np.array([x.shape[0] for x in self.xys], dtype=np.int32)
         p = acs_default_params()
         p.m, p.cl, p.beta, p.q0, p.phi, p.rho, p.tau0 = m, cl, beta, q0, phi, rho, tau0
-        p.mode, p.memory, p.seed, p.instance = ACS_ASYNC_ATOMIC, ACS_DENSE, seed, instance
+        p.mode, p.memory, p.seed, p.instance = mode, ACS_DENSE, seed, instance
         p.local_update_period = local_update_period
         self._ws = None
         if torch_memory:

@@ -100,7 +100,8 @@ int check_params(int32_t n, const acs_params *p) {
   if (!std::isfinite(p->tau0)) return fail(ACS_E_INVALID, "tau0 not finite");
   if (p->memory != ACS_DENSE && p->memory != ACS_SPM) return fail(ACS_E_INVALID, "bad memory");
   if (p->memory == ACS_SPM && p->spm_s < 1) return fail(ACS_E_INVALID, "spm_s must be >= 1");
-  if (p->mode != ACS_SYNC && p->mode != ACS_ASYNC_ATOMIC) return fail(ACS_E_INVALID, "bad mode");
+  if (p->mode != ACS_SYNC && p->mode != ACS_ASYNC_ATOMIC && p->mode != ACS_ASYNC_RACY)
+    return fail(ACS_E_INVALID, "bad mode");
   if (p->local_update_period < 1) return fail(ACS_E_INVALID, "local_update_period must be >= 1");
   if (n > 65535) return fail(ACS_E_UNSUPPORTED, "n = %d > 65535", n);
   const uint32_t cl = std::min<uint32_t>(p->cl, (uint32_t)n - 1);
@@ -526,7 +527,7 @@ struct acs_batch_t {
   acs::Dev *d_devs = nullptr;
   acs::Iter *d_iters = nullptr;
   int2 *d_items = nullptr;
-  int nitems = 0, nmax = 0;
+  int nitems = 0, nmax = 0, mode = ACS_ASYNC_ATOMIC;
   int64_t steps_per_iteration = 0;
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
@@ -587,8 +588,8 @@ int batch_layout(const int32_t *n, int32_t count, const acs_params *p, BatchLayo
 int check_batch_args(const int32_t *n, int32_t count, const acs_params *p) {
   if (count < 1) return fail(ACS_E_INVALID, "count < 1");
   if (!n || !p) return fail(ACS_E_INVALID, "NULL argument");
-  if (p->mode != ACS_ASYNC_ATOMIC)
-    return fail(ACS_E_UNSUPPORTED, "batches run in the asynchronous atomic mode");
+  if (p->mode != ACS_ASYNC_ATOMIC && p->mode != ACS_ASYNC_RACY)
+    return fail(ACS_E_UNSUPPORTED, "batches run in an asynchronous mode");
   if (p->memory != ACS_DENSE) return fail(ACS_E_UNSUPPORTED, "batches use the dense memory");
   for (int i = 0; i < count; ++i) {
     const int rc = check_params(n[i], p);
@@ -630,6 +631,7 @@ int acs_batch_create(const double *const *coords, const int32_t *n, int32_t coun
   acs_batch_t *b = new (std::nothrow) acs_batch_t;
   if (!b) return fail(ACS_E_NOMEM, "host allocation failed");
   b->count = count;
+  b->mode = (int)p->mode;
   auto bail = [&](int code) {
     std::string keep = g_err;
     release_batch(b);
@@ -702,7 +704,7 @@ int acs_batch_create(const double *const *coords, const int32_t *n, int32_t coun
   // one iteration captured once as a graph (no memset nodes: plain kernels)
   if (hipStreamBeginCapture(b->stream, hipStreamCaptureModeThreadLocal) == hipSuccess) {
     const hipError_t le = acs::launch_batch_iteration(b->d_devs, b->d_iters, b->d_items, b->nitems,
-                                                      b->count, b->nmax, b->stream);
+                                                      b->count, b->nmax, b->mode, b->stream);
     hipGraph_t g = nullptr;
     const hipError_t ce = hipStreamEndCapture(b->stream, &g);
     if (le == hipSuccess && ce == hipSuccess && g) {
@@ -731,7 +733,7 @@ int acs_batch_iterate(acs_batch_t *b, int32_t k) {
       HIP_TRY(hipGraphLaunch(b->exec, b->stream));
     } else {
       HIP_TRY(acs::launch_batch_iteration(b->d_devs, b->d_iters, b->d_items, b->nitems, b->count,
-                                          b->nmax, b->stream));
+                                          b->nmax, b->mode, b->stream));
     }
   }
   HIP_TRY(hipEventRecord(b->e1, b->stream));

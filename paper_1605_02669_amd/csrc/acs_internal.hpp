@@ -68,9 +68,10 @@ hipError_t launch_best_global(const Dev &d, const Iter &it, int memory,
 // One iteration of many dense instances (asynchronous mode): construction of
 // every (instance, ant) work item, then per-instance best and global update.
 // Descriptors, iteration state and the work list are device arrays, so the
-// three launches can be captured once in a graph and replayed.
+// three launches can be captured once in a graph and replayed.  mode 1:
+// updates by compare-and-swap; mode 2: plain stores (lost updates).
 hipError_t launch_batch_iteration(const Dev *devs, Iter *iters, const int2 *items, int nitems,
-                                  int count, int nmax, hipStream_t s);
+                                  int count, int nmax, int mode, hipStream_t s);
 // Learned edge prior (acs_prior.hip): parameter count and kernels.
 constexpr int kPriorParams = 4545;
 hipError_t launch_prior_forward(const float *P, const float *X, int rows, float *Z,

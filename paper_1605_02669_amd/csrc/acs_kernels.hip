@@ -547,7 +547,11 @@ __global__ __launch_bounds__(1024) void k_construct_sync_dense(Dev D, Iter A) {
 //      forward value when prev is not a candidate of cur);
 //   3. select the next city (Alg. 2) while those are in flight;
 //   4. issue the load of the next city's record.
+// ATOMIC = false is the paper's unsynchronised variant (ACS-GPU-Alt,
+// Sec. 3.1.2): each entry gets the map of the value the ant read, by a plain
+// (not read-modify-write) store, and updates that race with it are lost.
 // ---------------------------------------------------------------------------
+template <bool ATOMIC>
 __device__ __forceinline__ void ant_async_dense(const Dev &D, const Iter &A, int ant,
                                                 uint32_t *vis, int lane) {
   const int n = D.n, cl = D.cl, ldn = D.ldn;
@@ -586,18 +590,24 @@ __device__ __forceinline__ void ant_async_dense(const Dev &D, const Iter &A, int
       const uint64_t b = __ballot(lane < cl && rec.x == (uint32_t)prev);
       const int kr = b ? uni((int)__ffsll((unsigned long long)b) - 1) : -1;
       const float rval = kr >= 0 ? __uint_as_float(rdlane(rec.w, kr)) : fval;
-      if (lane == 0) {
-        pptr = fwd;
-        pexp = __float_as_uint(fval);
-        pend = true;
-      } else if (lane == 1) {
-        pptr = home(D, cur, prev, kr);
-        pexp = __float_as_uint(rval);
-        pend = true;
+      if (ATOMIC) {
+        if (lane == 0) {
+          pptr = fwd;
+          pexp = __float_as_uint(fval);
+          pend = true;
+        } else if (lane == 1) {
+          pptr = home(D, cur, prev, kr);
+          pexp = __float_as_uint(rval);
+          pend = true;
+        }
+        if (pend)
+          pret = atomicCAS(reinterpret_cast<unsigned int *>(pptr), pexp,
+                           __float_as_uint(fmaf(al, __uint_as_float(pexp), bl)));
+      } else if (lane < 2) {
+        float *h = lane == 0 ? fwd : home(D, cur, prev, kr);
+        __hip_atomic_store(h, fmaf(al, lane == 0 ? fval : rval, bl), __ATOMIC_RELAXED,
+                           __HIP_MEMORY_SCOPE_AGENT);
       }
-      if (pend)
-        pret = atomicCAS(reinterpret_cast<unsigned int *>(pptr), pexp,
-                         __float_as_uint(fmaf(al, __uint_as_float(pexp), bl)));
     }
     if (t == n) break;
     // 3. selection
@@ -622,7 +632,13 @@ __device__ __forceinline__ void ant_async_dense(const Dev &D, const Iter &A, int
     const int k1 = cand_pos(D, cur, start, lane);
     const int k2 = cand_pos(D, start, cur, lane);
     float *h = lane == 0 ? home(D, cur, start, k1) : home(D, start, cur, k2);
-    if (lane < 2) c_retry += cas_apply(h, __float_as_uint(tau_load(h)), al, bl);
+    if (lane < 2) {
+      if (ATOMIC)
+        c_retry += cas_apply(h, __float_as_uint(tau_load(h)), al, bl);
+      else
+        __hip_atomic_store(h, fmaf(al, tau_load(h), bl), __ATOMIC_RELAXED,
+                           __HIP_MEMORY_SCOPE_AGENT);
+    }
   }
   len += D.dist[(size_t)cur * ldn + start];
   c_retry = (uint32_t)uni((int)(rdlane(c_retry, 0) + rdlane(c_retry, 1)));
@@ -632,19 +648,21 @@ __device__ __forceinline__ void ant_async_dense(const Dev &D, const Iter &A, int
   }
 }
 
+template <bool ATOMIC>
 __global__ __launch_bounds__(256) void k_construct_async_dense(Dev D, Iter A) {
   extern __shared__ uint32_t smem[];
   const int lane = threadIdx.x & 63;
   const int wv = threadIdx.x >> 6;
   const int ant = uni(blockIdx.x * (blockDim.x >> 6) + wv);
   if (ant >= D.m) return;  // the whole wave leaves; no block-level sync below
-  ant_async_dense(D, A, ant, smem + wv * ((D.n + 31) >> 5), lane);
+  ant_async_dense<ATOMIC>(D, A, ant, smem + wv * ((D.n + 31) >> 5), lane);
 }
 
 // Many instances in one launch: wave w builds the tour of ant items[w].y of
 // instance items[w].x, whose descriptor and iteration state live in device
 // memory (so the launch can be replayed from a graph).  The work list is
 // ordered by decreasing n, so the longest chains start first.
+template <bool ATOMIC>
 __global__ __launch_bounds__(256) void k_construct_async_batch(const Dev *devs, const Iter *iters,
                                                                const int2 *items, int nitems,
                                                                int wmax) {
@@ -657,7 +675,7 @@ __global__ __launch_bounds__(256) void k_construct_async_batch(const Dev *devs, 
   const int inst = uni(item.x);
   const Dev D = devs[inst];
   const Iter A = iters[inst];
-  ant_async_dense(D, A, uni(item.y), smem + wv * wmax, lane);
+  ant_async_dense<ATOMIC>(D, A, uni(item.y), smem + wv * wmax, lane);
 }
 
 // ---------------------------------------------------------------------------
@@ -1008,13 +1026,46 @@ __device__ __forceinline__ uint32_t spm_async_finish(const Dev &D, SpmOp &op, fl
   }
 }
 
+// The unsynchronised variant of Alg. 3 (ACS-GPU-Alt): the owner lane writes
+// the changed pair of the record the wave read (pr, insert counter tl) and,
+// for a new trail, the advanced insert counter, with plain (not
+// read-modify-write) device-coherent stores; updates that race with it are
+// lost.
+__device__ __forceinline__ void spm_racy_issue(const Dev &D, uint2 pr, uint32_t tl, int r, int nb,
+                                               int lane, int owner, float a, float b, float tau0,
+                                               uint32_t &hits, uint32_t &misses) {
+  const int s = D.spm_s;
+  const uint64_t hm = __ballot(lane < s && pr.x == (uint32_t)nb);
+  if (lane != owner) return;
+  if (hm) {
+    const int i = (int)__ffsll((unsigned long long)hm) - 1;
+    const uint32_t v = rdlane(pr.y, i);
+    pair_store_coherent(D.spm + (size_t)r * s + i,
+                        make_uint2((uint32_t)nb, __float_as_uint(fmaf(a, __uint_as_float(v), b))));
+    ++hits;
+  } else {
+    const uint32_t slot = (tl + 1u) % (uint32_t)s;
+    pair_store_coherent(D.spm + (size_t)r * s + slot,
+                        make_uint2((uint32_t)nb, __float_as_uint(fmaf(a, tau0, b))));
+    __hip_atomic_store(D.spm_tail + r, tl + 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    ++misses;
+  }
+}
+
+// The wave keeps the record of its current city in registers (pr, tl).  Its
+// own update of that record (the reverse entry of the move that reached the
+// city) is applied to the copy before the copy is read, so an ant always
+// sees its own updates, as in Alg. 1; with one ant the result is exactly the
+// sequential one.  The memory operations of the update are issued after the
+// weights are formed (see the dense kernel for why).
+template <bool ATOMIC>
 __global__ __launch_bounds__(256) void k_construct_async_spm(Dev D, Iter A) {
   extern __shared__ uint32_t smem[];
   const int lane = threadIdx.x & 63;
   const int wv = threadIdx.x >> 6;
   const int ant = uni(blockIdx.x * (blockDim.x >> 6) + wv);
   if (ant >= D.m) return;
-  const int n = D.n, cl = D.cl;
+  const int n = D.n, cl = D.cl, s = D.spm_s;
   const int W = (n + 31) >> 5;
   const int kl = lane < cl ? lane : cl - 1;
   uint32_t *vis = smem + wv * W;
@@ -1027,7 +1078,9 @@ __global__ __launch_bounds__(256) void k_construct_async_spm(Dev D, Iter A) {
   int tb = start;
   uint4 rec = D.crec[(size_t)start * cl + kl];
   uint2 pr = spm_record<false>(D, start, lane);
+  uint32_t tl = D.spm_tail[start];
   uint2 pr_prev = pr;
+  uint32_t tl_prev = tl;
 
   int cur = start, prev = -1;
   int64_t len = 0;
@@ -1037,14 +1090,27 @@ __global__ __launch_bounds__(256) void k_construct_async_spm(Dev D, Iter A) {
   op.live = false;
 
   for (int t = 1; t <= n; ++t) {
-    c_retry += spm_async_finish(D, op, al, bl, tau0);
+    if (ATOMIC) c_retry += spm_async_finish(D, op, al, bl, tau0);
+    const bool upd = t > 1 && (t - 1) % A.lperiod == 0;
+    // record of cur as it was read, then with this ant's reverse update
+    const uint2 pr_read = pr;
+    const uint32_t tl_read = tl;
+    if (upd) {
+      uint32_t h0 = 0, m0 = 0;
+      spm_update_wave(pr, tl, s, lane, prev, al, bl, tau0, h0, m0);
+    }
     const Cand c = weigh_spm(D, vis, lane, rec, pr, tau0);
     __asm__ volatile("" ::"v"(c.w), "v"((int)c.unv));
-    if (t > 1 && (t - 1) % A.lperiod == 0) {
+    if (upd) {
       // forward entry of the previous move in prev's record (lane 0),
       // reverse entry in cur's record (lane 1)
-      spm_async_issue(D, op, pr_prev, prev, cur, lane, 0, al, bl, tau0, hits, misses);
-      spm_async_issue(D, op, pr, cur, prev, lane, 1, al, bl, tau0, hits, misses);
+      if (ATOMIC) {
+        spm_async_issue(D, op, pr_prev, prev, cur, lane, 0, al, bl, tau0, hits, misses);
+        spm_async_issue(D, op, pr_read, cur, prev, lane, 1, al, bl, tau0, hits, misses);
+      } else {
+        spm_racy_issue(D, pr_prev, tl_prev, prev, cur, lane, 0, al, bl, tau0, hits, misses);
+        spm_racy_issue(D, pr_read, tl_read, cur, prev, lane, 1, al, bl, tau0, hits, misses);
+      }
     }
     if (t == n) break;
     if ((t & 63) == 0) draws = philox_batch(A, ant, t, lane);
@@ -1064,19 +1130,33 @@ __global__ __launch_bounds__(256) void k_construct_async_spm(Dev D, Iter A) {
     len += p.d;
     rec = D.crec[(size_t)p.next * cl + kl];
     pr_prev = pr;
+    tl_prev = tl;
     pr = spm_record<false>(D, p.next, lane);
+    tl = D.spm_tail[p.next];
     prev = cur;
     cur = p.next;
   }
-  c_retry += spm_async_finish(D, op, al, bl, tau0);
+  if (ATOMIC) c_retry += spm_async_finish(D, op, al, bl, tau0);
   // closing edge, read fresh: record cur (neighbour start), record start
   {
     const uint2 q0 = spm_record<true>(D, cur, lane);
-    spm_async_issue(D, op, q0, cur, start, lane, 0, al, bl, tau0, hits, misses);
-    c_retry += spm_async_finish(D, op, al, bl, tau0);
+    if (ATOMIC) {
+      spm_async_issue(D, op, q0, cur, start, lane, 0, al, bl, tau0, hits, misses);
+      c_retry += spm_async_finish(D, op, al, bl, tau0);
+    } else {
+      const uint32_t t0 = __hip_atomic_load(D.spm_tail + cur, __ATOMIC_RELAXED,
+                                            __HIP_MEMORY_SCOPE_AGENT);
+      spm_racy_issue(D, q0, t0, cur, start, lane, 0, al, bl, tau0, hits, misses);
+    }
     const uint2 q1 = spm_record<true>(D, start, lane);
-    spm_async_issue(D, op, q1, start, cur, lane, 0, al, bl, tau0, hits, misses);
-    c_retry += spm_async_finish(D, op, al, bl, tau0);
+    if (ATOMIC) {
+      spm_async_issue(D, op, q1, start, cur, lane, 0, al, bl, tau0, hits, misses);
+      c_retry += spm_async_finish(D, op, al, bl, tau0);
+    } else {
+      const uint32_t t1 = __hip_atomic_load(D.spm_tail + start, __ATOMIC_RELAXED,
+                                            __HIP_MEMORY_SCOPE_AGENT);
+      spm_racy_issue(D, q1, t1, start, cur, lane, 0, al, bl, tau0, hits, misses);
+    }
   }
   len += D.dist[(size_t)cur * D.ldn + start];
   c_retry = (uint32_t)uni((int)(rdlane(c_retry, 0) + rdlane(c_retry, 1)));
@@ -1285,12 +1365,23 @@ hipError_t launch_construct(const Dev &d, const Iter &it, int mode, int memory, 
   }
   const int apb = kAsyncBlock / 64;
   const int grid = (d.m + apb - 1) / apb;
-  if (memory == 0)
-    hipLaunchKernelGGL(k_construct_async_dense, dim3(grid), dim3(kAsyncBlock),
-                       lds_bytes(d, kAsyncBlock), s, d, it);
-  else
-    hipLaunchKernelGGL(k_construct_async_spm, dim3(grid), dim3(kAsyncBlock),
-                       lds_bytes(d, kAsyncBlock), s, d, it);
+  const size_t lds = lds_bytes(d, kAsyncBlock);
+  const bool atomic = mode == 1;
+  if (memory == 0) {
+    if (atomic)
+      hipLaunchKernelGGL(k_construct_async_dense<true>, dim3(grid), dim3(kAsyncBlock), lds, s, d,
+                         it);
+    else
+      hipLaunchKernelGGL(k_construct_async_dense<false>, dim3(grid), dim3(kAsyncBlock), lds, s,
+                         d, it);
+  } else {
+    if (atomic)
+      hipLaunchKernelGGL(k_construct_async_spm<true>, dim3(grid), dim3(kAsyncBlock), lds, s, d,
+                         it);
+    else
+      hipLaunchKernelGGL(k_construct_async_spm<false>, dim3(grid), dim3(kAsyncBlock), lds, s, d,
+                         it);
+  }
   return hipGetLastError();
 }
 
@@ -1320,12 +1411,17 @@ hipError_t launch_best_global(const Dev &d, const Iter &it, int memory, hipStrea
 }
 
 hipError_t launch_batch_iteration(const Dev *devs, Iter *iters, const int2 *items, int nitems,
-                                  int count, int nmax, hipStream_t s) {
+                                  int count, int nmax, int mode, hipStream_t s) {
   const int apb = kAsyncBlock / 64;
   const int wmax = (nmax + 31) / 32;
   const size_t lds = (size_t)apb * wmax * sizeof(uint32_t);
-  hipLaunchKernelGGL(k_construct_async_batch, dim3((nitems + apb - 1) / apb), dim3(kAsyncBlock),
-                     lds, s, devs, iters, items, nitems, wmax);
+  const dim3 grid((nitems + apb - 1) / apb);
+  if (mode == 1)
+    hipLaunchKernelGGL(k_construct_async_batch<true>, grid, dim3(kAsyncBlock), lds, s, devs,
+                       iters, items, nitems, wmax);
+  else
+    hipLaunchKernelGGL(k_construct_async_batch<false>, grid, dim3(kAsyncBlock), lds, s, devs,
+                       iters, items, nitems, wmax);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(k_best_batch, dim3(count), dim3(1024), 0, s, devs, iters);

@@ -26,6 +26,27 @@ def exact_dist(xi: float, yi: float, xj: float, yj: float) -> int:
     return (k + 1) // 2
 
 
+def edge_dists(xy: np.ndarray, u: np.ndarray, v: np.ndarray) -> np.ndarray:
+    """exact_dist of the pairs (u[k], v[k]), vectorised: the integer d >= 0 with
+    (d - 1/2)^2 <= s < (d + 1/2)^2 (d = 0 for s < 1/4), found from a rounded square root and
+    corrected by those two exact comparisons (every square of d +- 1/2 below
+    2^26 is exact in double)."""
+    dx = xy[u, 0] - xy[v, 0]
+    dy = xy[u, 1] - xy[v, 1]
+    s = dx * dx + dy * dy
+    d = np.floor(np.sqrt(s) + 0.5)
+    for _ in range(2):
+        d = np.where((d >= 1) & ((d - 0.5) * (d - 0.5) > s), d - 1, d)
+        d = np.where((d + 0.5) * (d + 0.5) <= s, d + 1, d)
+    return d.astype(np.int64)
+
+
+def tour_lengths(xy: np.ndarray, tours: np.ndarray) -> np.ndarray:
+    """Length of every row of `tours` (closing edge included)."""
+    t = np.asarray(tours, dtype=np.int64)
+    return edge_dists(xy, t, np.roll(t, -1, axis=1)).sum(axis=1)
+
+
 def dist_matrix(xy: np.ndarray) -> np.ndarray:
     n = len(xy)
     d = np.zeros((n, n), dtype=np.int64)

@@ -416,9 +416,60 @@ def test_local_update_period_async_valid(acs):
     n = 1000
     xy = inputs.uniform(n, 5)
     col = acs.Colony(xy, mode=acs.ACS_ASYNC_ATOMIC, seed=1, local_update_period=8)
-    d = defs.dist_matrix(xy)
     col.iterate(3)
     tours, lens = col.tours(), col.lengths()
     assert np.all(np.sort(tours, axis=1) == np.arange(n)[None, :])
-    assert np.array_equal(d[tours, np.roll(tours, -1, axis=1)].sum(axis=1), lens)
+    assert np.array_equal(defs.tour_lengths(xy, tours), lens)
     col.close()
+
+
+# ---------------------------------------------------------------------------
+# Unsynchronised mode without atomics (the paper's ACS-GPU-Alt): updates that
+# race are lost, so only one ant has an exact reference; many ants are
+# checked for valid tours, consistent lengths and pheromone bounds.
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("memory", [0, 1])
+def test_racy_single_ant_equals_oracle(acs, memory):
+    xy = inputs.uniform(240, 23)
+    kw = dict(m=1, cl=16, memory=memory, spm_s=5, seed=9)
+    col = acs.Colony(xy, mode=acs.ACS_ASYNC_RACY, **kw)
+    orc = oracle.Oracle(xy, **kw)
+    for it in range(6):
+        col.iterate(1)
+        orc.iterate(1)
+        _compare(col, orc, it)
+    col.close()
+
+
+@pytest.mark.parametrize("n,m,memory", [(1000, 1000, 0), (2392, 2392, 0), (20000, 1024, 1)])
+def test_racy_tours_valid(acs, n, m, memory):
+    _say(f"racy n={n} m={m} memory={memory}")
+    xy = inputs.uniform(n)
+    cl = 16 if memory else 32
+    col = acs.Colony(xy, m=m, cl=cl, memory=memory, spm_s=8, mode=acs.ACS_ASYNC_RACY, seed=3)
+    col.iterate(2 if n < 20000 else 1)
+    tours, lens = col.tours(), col.lengths()
+    assert np.all(np.sort(tours, axis=1) == np.arange(n)[None, :])
+    assert np.array_equal(defs.tour_lengths(xy, tours), lens)
+    c = col.stats()
+    if memory == 0:
+        tau = col.tau()
+        assert np.all(np.isfinite(tau)) and tau.min() >= np.float32(c["tau0"]) * np.float32(0.999)
+    else:
+        nodes, vals, _ = col.spm()
+        assert np.all((nodes == -1) | ((nodes >= 0) & (nodes < n)))
+        assert np.all(np.isfinite(vals)) and vals.min() >= np.float32(c["tau0"]) * np.float32(0.999)
+    col.close()
+
+
+def test_racy_batch_single_ant_equals_oracle(acs):
+    insts = inputs.batch(4, seed=51, nmin=50, nmax=200)
+    b = acs.Batch(insts, m=1, cl=16, seed=2, mode=acs.ACS_ASYNC_RACY)
+    orcs = [oracle.Oracle(x, m=1, cl=16, seed=2, instance=i) for i, x in enumerate(insts)]
+    for it in range(3):
+        b.iterate(1)
+        for i, o in enumerate(orcs):
+            o.iterate(1)
+            assert np.array_equal(b.tours(i), o.tours()), (i, it)
+            assert np.array_equal(b.tau(i), o.tau()), (i, it)
+    b.close()

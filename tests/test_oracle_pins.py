@@ -433,3 +433,18 @@ def test_invalid_arguments_rejected():
     bad = xy.copy(); bad[3, 0] = np.nan
     with pytest.raises(ValueError):
         oracle.Oracle(bad)
+
+
+def test_vectorised_edge_distances_match_exact_definition():
+    """The vectorised helper the GPU tests use for large tours agrees with
+    the rational-arithmetic definition, including near-half cases."""
+    g = np.random.default_rng(17)
+    xy = np.concatenate([inputs.uniform(400, 3), inputs.clustered(300, 3),
+                         np.array([[0.0, 0.0], [0.5, 0.0], [1.5, 0.0], [3.0, 4.0], [0.0, 2.5]])])
+    u = g.integers(0, len(xy), size=4000)
+    v = g.integers(0, len(xy), size=4000)
+    u = np.concatenate([u, [700, 700, 700, 700]])
+    v = np.concatenate([v, [701, 702, 703, 704]])
+    got = defs.edge_dists(xy, u, v)
+    want = [defs.exact_dist(*xy[a], *xy[b]) for a, b in zip(u, v)]
+    assert np.array_equal(got, want)
