@@ -5,23 +5,32 @@ iteration best, global update): n = 2392 cities uniform in [0, 10000)^2
 (seed 2392), m = n ants, candidate lists of 32, beta = 2, q0 = 0.9,
 phi = rho = 0.1, dense FP32 pheromone.  The headline value is construction
 steps per second (m * (n - 1) ant moves per iteration) in the asynchronous
-atomic mode; the synchronous (bit-exact) mode is timed beside it.
+atomic mode; the synchronous (bit-exact) mode is timed beside it, and the
+other workloads (n=198, n=1000 clustered, n=20000 with the selective memory,
+a batch of 256 instances, the non-atomic variant, local-update period 16)
+follow as context.
 
 Prints one JSON line.  Only one GPU is supported; --gpus N > 1 exits.
 """
 from __future__ import annotations
 
 import argparse
+import hashlib
 import json
 import os
+import re
 import sys
 import time
 
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
+METRIC = "ant construction steps/s at n=2392,m=n; tour gap vs plain ACS at equal time"
 HBM_PEAK_GBS = 8000.0
 N, CL = 2392, 32
+KERNEL = "k_construct_async_dense<true>"
+KERNEL_SOURCE = os.path.join(ROOT, "paper_1605_02669_amd", "csrc", "acs_kernels.hip")
+TRAFFIC_PROFILE = os.path.join(ROOT, "profiles", "k_construct_async_dense_n2392.md")
 
 
 def algorithmic_bytes(st_delta: dict, n: int, m: int, cl: int, iters: int) -> float:
@@ -37,6 +46,22 @@ def algorithmic_bytes(st_delta: dict, n: int, m: int, cl: int, iters: int) -> fl
     return float(b)
 
 
+def measured_traffic():
+    """HBM bytes per launch of the headline kernel from the committed
+    rocprofv3 counter summary, or None when the kernel source has changed
+    since the counters were taken (the summary records the source's hash)."""
+    try:
+        text = open(TRAFFIC_PROFILE).read()
+        src = hashlib.sha256(open(KERNEL_SOURCE, "rb").read()).hexdigest()
+    except OSError:
+        return None
+    h = re.search(r"kernel_source_sha256:\s*([0-9a-f]{64})", text)
+    t = re.search(r"traffic_bytes_per_launch:\s*([0-9.eE+]+)", text)
+    if not h or not t or h.group(1) != src:
+        return None
+    return float(t.group(1))
+
+
 def run_mode(acs, xy, mode, steps, warmup, seed=0, **kw):
     import torch
     kw.setdefault("m", 0)
@@ -46,7 +71,7 @@ def run_mode(acs, xy, mode, steps, warmup, seed=0, **kw):
     st0 = col.stats()
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    col.iterate(steps)
+    col.iterate(steps)  # one call: the library records events around every construction
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     st1 = col.stats()
@@ -55,7 +80,7 @@ def run_mode(acs, xy, mode, steps, warmup, seed=0, **kw):
     res = dict(
         seconds=t1 - t0,
         steps=delta["steps"],
-        construct_ms=st1["construct_ms"],
+        construct_ms=st1["construct_ms"],  # summed over the launches of the timed call
         launches=st1["construct_launches"],
         iterate_ms=st1["iterate_ms"],
         best=st1["best_length"],
@@ -68,6 +93,8 @@ def run_mode(acs, xy, mode, steps, warmup, seed=0, **kw):
 
 
 def cpu_baseline(xy, budget_s: float = 12.0):
+    """The oracle on the host cores: all cores (OpenMP over the ants of a
+    step), then one thread (the paper's sequential convention)."""
     import oracle
     threads = min(os.cpu_count() or 1, 16)
     oracle.set_threads(threads)
@@ -82,9 +109,18 @@ def cpu_baseline(xy, budget_s: float = 12.0):
     dt = time.perf_counter() - t0
     steps = orc.counts()["steps"]
     oracle.set_threads(1)
+    orc.close()
+    one = oracle.Oracle(xy, cl=CL, seed=0)
+    t0 = time.perf_counter()
+    one.iterate(1)
+    dt1 = time.perf_counter() - t0
+    steps1 = one.counts()["steps"]
+    one.close()
     return dict(value=steps / dt, unit="steps/s", cores=threads, kind="oracle",
+                single_thread_value=steps1 / dt1,
                 sample=f"{iters} synchronous iterations of the n={N}, m={N} workload "
-                       f"({steps} steps, {dt:.1f} s, {threads} OpenMP threads)")
+                       f"({steps} steps, {dt:.1f} s, {threads} OpenMP threads); "
+                       f"single thread: 1 iteration ({dt1:.1f} s)")
 
 
 EXTRA = {
@@ -94,7 +130,12 @@ EXTRA = {
     "c2c": dict(kind="clustered", n=1000, kw=dict(), modes=(("sync", 3), ("async", 20))),
     # n=20000 uniform, m=1024, cl=16, selective memory with s=8
     "c3": dict(kind="uniform", n=20000, kw=dict(m=1024, cl=16, memory=1, spm_s=8),
-               modes=(("sync", 1), ("async", 5))),
+               modes=(("sync", 1), ("async", 5), ("racy", 5))),
+    # the headline instance without atomics (the paper's Alt) and with the
+    # local update after every 16th edge only
+    "alt": dict(kind="uniform", n=N, kw=dict(), modes=(("racy", 20),)),
+    "k16": dict(kind="uniform", n=N, kw=dict(local_update_period=16),
+                modes=(("async", 20), ("racy", 20), ("sync", 2))),
 }
 
 
@@ -102,14 +143,39 @@ def run_extra(acs, inputs, name):
     spec = EXTRA[name]
     xy = inputs.uniform(spec["n"]) if spec["kind"] == "uniform" else inputs.clustered(spec["n"])
     res = {"n": spec["n"], **{k: v for k, v in spec["kw"].items()}}
+    modes = {"sync": acs.ACS_SYNC, "async": acs.ACS_ASYNC_ATOMIC, "racy": acs.ACS_ASYNC_RACY}
     for mode_name, iters in spec["modes"]:
-        mode = acs.ACS_SYNC if mode_name == "sync" else acs.ACS_ASYNC_ATOMIC
-        r = run_mode(acs, xy, mode, iters, 1, **spec["kw"])
+        r = run_mode(acs, xy, modes[mode_name], iters, 1, **spec["kw"])
         res[mode_name] = {"steps_per_s": r["steps"] / r["seconds"],
                           "ms_per_iteration": r["seconds"] * 1e3 / iters,
                           "construct_ms": r["construct_ms"] / r["launches"],
                           "iterations": iters, "best": r["best"]}
     return res
+
+
+def run_batch(acs, inputs, iters=5, count=256):
+    """256 instances, n log-uniform in [100, 2000], half uniform and half
+    clustered, m = n each, dense, asynchronous; one graph launch per
+    iteration."""
+    import torch
+    insts = inputs.batch(count)
+    t0 = time.perf_counter()
+    b = acs.Batch(insts, cl=CL, seed=0)
+    create_s = time.perf_counter() - t0
+    b.iterate(1)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    b.iterate(iters)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    info = b.info()
+    b.close()
+    return {"instances": count, "n_min": int(min(len(x) for x in insts)),
+            "n_max": int(max(len(x) for x in insts)),
+            "steps_per_iteration": info["steps_per_iteration"], "graph": info["graph"],
+            "steps_per_s": info["steps_per_iteration"] * iters / dt,
+            "ms_per_iteration": dt * 1e3 / iters, "iterations": iters,
+            "create_s": create_s}
 
 
 def main():
@@ -119,9 +185,9 @@ def main():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--sync-steps", type=int, default=5)
     ap.add_argument("--no-cpu", action="store_true")
-    ap.add_argument("--extra", default="c1,c2c,c3",
-                    help="other workloads timed beside the headline (comma list of c1, c2c, c3; "
-                         "empty for none)")
+    ap.add_argument("--extra", default="c1,c2c,c3,c4,alt,k16",
+                    help="other workloads timed beside the headline (comma list of "
+                         "c1, c2c, c3, c4, alt, k16; empty for none)")
     ap.add_argument("--copy-calibration-mb", type=int, default=0,
                     help="after timing, run one plain device copy of this many MiB "
                          "(reference kernel for hardware byte counters)")
@@ -151,10 +217,11 @@ def main():
     value = asy["steps"] / asy["seconds"]
     ms_per_step = asy["seconds"] * 1e3 / args.steps
     avg_launch_s = asy["construct_ms"] / asy["launches"] / 1e3
-    bytes_per_launch = algorithmic_bytes(asy["delta"], asy["n"], asy["m"], asy["cl"], args.steps) / args.steps
+    bytes_per_launch = algorithmic_bytes(asy["delta"], asy["n"], asy["m"], asy["cl"],
+                                         args.steps) / args.steps
     achieved = bytes_per_launch / avg_launch_s / 1e9
     out = {
-        "metric": "ant construction steps/s at n=2392, m=n",
+        "metric": METRIC,
         "value": value,
         "unit": "steps/s",
         "n_gpus": 1,
@@ -171,8 +238,8 @@ def main():
                                "asynchronous atomic local updates",
                    "n": asy["n"], "m": asy["m"], "cl": asy["cl"], "mode": "async_atomic"},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
-                     "kernel": "k_construct_dense (async)",
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic(),
+                     "kernel": KERNEL,
                      "bytes_per_launch": bytes_per_launch,
                      "avg_launch_ms": avg_launch_s * 1e3},
         "sync_mode": None if syn is None else {
@@ -186,7 +253,10 @@ def main():
     }
     extra = {}
     for name in [x for x in args.extra.split(",") if x]:
-        extra[name] = run_extra(acs, inputs, name)
+        if name == "c4":
+            extra[name] = run_batch(acs, inputs)
+        else:
+            extra[name] = run_extra(acs, inputs, name)
         print(f"# {name}: {extra[name]}", file=sys.stderr, flush=True)
     if extra:
         out["other_workloads"] = extra
@@ -198,8 +268,7 @@ def main():
         torch.cuda.synchronize()
         out["copy_calibration_bytes"] = nbytes
     if not args.no_cpu:
-        cb = cpu_baseline(xy)
-        out["cpu_baseline"] = cb
+        out["cpu_baseline"] = cpu_baseline(xy)
     print(json.dumps(out))
 
 
