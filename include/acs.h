@@ -82,6 +82,12 @@ typedef struct acs_params {
   void *stream;          /* hipStream_t to run on; NULL: the library's own */
   void *workspace;       /* optional device buffer (e.g. a torch tensor) */
   size_t workspace_bytes;
+  uint32_t lanes_per_ant; /* asynchronous dense kernels: lanes of a wavefront
+                             that carry one ant, 64, 32 or 16 (at least cl);
+                             0: 64 for one instance, chosen by timing for a
+                             batch.  Never changes a decision, only how many
+                             ants share a wavefront. */
+  uint32_t reserved;     /* 0 */
 } acs_params;
 
 typedef struct acs_stats {
@@ -188,8 +194,20 @@ int acs_batch_workspace_bytes(const int32_t *n, int32_t count, const acs_params 
 int acs_batch_create(const double *const *coords, const int32_t *n, int32_t count,
                      const acs_params *p, acs_batch_t **out);
 
-/* k iterations of every instance; returns once they have finished. */
+/* k iterations of every instance; returns once they have finished.  With
+ * lanes_per_ant = 0 the first iterations also choose the launch shape: one
+ * untimed iteration, then one timed iteration with each candidate number of
+ * lanes per ant (64, and 32 and 16 where every candidate list fits); later
+ * iterations use the fastest.  Tuning iterations are ordinary iterations
+ * (the shape never changes a decision). */
 int acs_batch_iterate(acs_batch_t *b, int32_t k);
+
+/* Launch-shape tuning: the chosen lanes per ant (0 while still tuning), the
+ * number of candidates, and per candidate its lanes per ant and the device
+ * time of its timed iteration in ms (-1 if not yet timed).  The arrays hold
+ * `cap` entries; at most 3 are written. */
+int acs_batch_tuning(acs_batch_t *b, int32_t *chosen_lanes, int32_t *count, int32_t *lanes,
+                     double *ms, int32_t cap);
 
 /* Number of instances, construction steps of one iteration (sum of
  * m_i (n_i - 1)), whether the iteration runs as a graph (1) or as direct

@@ -35,6 +35,7 @@ class acs_params(C.Structure):
         ("beta", C.c_double), ("q0", C.c_double), ("phi", C.c_double),
         ("rho", C.c_double), ("tau0", C.c_double), ("seed", C.c_uint64),
         ("stream", C.c_void_p), ("workspace", C.c_void_p), ("workspace_bytes", C.c_size_t),
+        ("lanes_per_ant", C.c_uint32), ("reserved", C.c_uint32),
     ]
 
 
@@ -88,6 +89,7 @@ def load() -> C.CDLL:
     lib.acs_batch_iterate.argtypes = [P, i32]
     lib.acs_batch_info.argtypes = [P, C.POINTER(i32), C.POINTER(i64), C.POINTER(i32),
                                    C.POINTER(C.c_double)]
+    lib.acs_batch_tuning.argtypes = [P, C.POINTER(i32), C.POINTER(i32), P, P, i32]
     lib.acs_batch_instance.argtypes = [P, i32, C.POINTER(P)]
     lib.acs_batch_best_tour.argtypes = [P, i32, P, C.POINTER(i64)]
     lib.acs_batch_destroy.argtypes = [P]
@@ -197,13 +199,14 @@ class Colony:
 
     def __init__(self, xy, m=0, cl=32, beta=2.0, q0=0.9, phi=0.1, rho=0.1, tau0=0.0,
                  memory=ACS_DENSE, spm_s=8, mode=ACS_SYNC, seed=0, instance=0,
-                 local_update_period=1, torch_memory=True):
+                 local_update_period=1, lanes_per_ant=0, torch_memory=True):
         self.xy = np.ascontiguousarray(xy, dtype=np.float64).reshape(-1, 2)
         n = self.xy.shape[0]
         p = acs_default_params()
         p.m, p.cl, p.beta, p.q0, p.phi, p.rho, p.tau0 = m, cl, beta, q0, phi, rho, tau0
         p.memory, p.spm_s, p.mode, p.seed, p.instance = memory, spm_s, mode, seed, instance
         p.local_update_period = local_update_period
+        p.lanes_per_ant = lanes_per_ant
         self._ws = None
         if torch_memory:
             import torch
@@ -285,13 +288,14 @@ class Batch:
 
     def __init__(self, instances, m=0, cl=32, beta=2.0, q0=0.9, phi=0.1, rho=0.1, tau0=0.0,
                  seed=0, instance=0, local_update_period=1, mode=ACS_ASYNC_ATOMIC,
-                 torch_memory=True):
+                 lanes_per_ant=0, torch_memory=True):
         self.xys = [np.ascontiguousarray(x, dtype=np.float64).reshape(-1, 2) for x in instances]
         sizes = np.array([x.shape[0] for x in self.xys], dtype=np.int32)
         p = acs_default_params()
         p.m, p.cl, p.beta, p.q0, p.phi, p.rho, p.tau0 = m, cl, beta, q0, phi, rho, tau0
         p.mode, p.memory, p.seed, p.instance = mode, ACS_DENSE, seed, instance
         p.local_update_period = local_update_period
+        p.lanes_per_ant = lanes_per_ant
         self._ws = None
         if torch_memory:
             import torch
@@ -325,6 +329,14 @@ class Batch:
         _check(load().acs_batch_info(self.h, C.byref(c), C.byref(steps), C.byref(g), C.byref(ms)))
         return dict(count=c.value, steps_per_iteration=steps.value, graph=bool(g.value),
                     last_iterate_ms=ms.value)
+
+    def tuning(self) -> dict:
+        ch, cnt = C.c_int32(), C.c_int32()
+        lanes = (C.c_int32 * 3)()
+        ms = (C.c_double * 3)()
+        _check(load().acs_batch_tuning(self.h, C.byref(ch), C.byref(cnt), lanes, ms, 3))
+        return dict(chosen_lanes=ch.value,
+                    candidates={int(lanes[j]): float(ms[j]) for j in range(cnt.value)})
 
     def handle(self, i: int):
         h = C.c_void_p()

@@ -108,6 +108,14 @@ int check_params(int32_t n, const acs_params *p) {
   if (cl > 64) return fail(ACS_E_UNSUPPORTED, "cl = %u > 64", cl);
   if (p->memory == ACS_SPM && p->spm_s > (uint32_t)acs::kMaxSpmS)
     return fail(ACS_E_UNSUPPORTED, "spm_s = %u > %d", p->spm_s, acs::kMaxSpmS);
+  const uint32_t lpa = p->lanes_per_ant;
+  if (lpa != 0 && lpa != 64 && lpa != 32 && lpa != 16)
+    return fail(ACS_E_INVALID, "lanes_per_ant = %u not in {0, 16, 32, 64}", lpa);
+  if (lpa != 0 && lpa < cl)
+    return fail(ACS_E_UNSUPPORTED, "lanes_per_ant = %u < cl = %u", lpa, cl);
+  if (lpa != 0 && lpa != 64 && (p->mode == ACS_SYNC || p->memory != ACS_DENSE))
+    return fail(ACS_E_UNSUPPORTED, "lanes_per_ant < 64 needs an asynchronous mode and dense memory");
+  if (p->reserved != 0) return fail(ACS_E_INVALID, "reserved must be 0");
   return ACS_OK;
 }
 
@@ -364,7 +372,8 @@ int acs_iterate(acs_t *h, int32_t k) {
     acs::Iter it = h->base;
     it.it = h->iter + (uint32_t)i;
     HIP_TRY(hipEventRecord(h->ev[2 * i], h->stream));
-    HIP_TRY(acs::launch_construct(h->dev, it, (int)h->p.mode, (int)h->p.memory, h->stream));
+    HIP_TRY(acs::launch_construct(h->dev, it, (int)h->p.mode, (int)h->p.memory,
+                                  h->p.lanes_per_ant ? (int)h->p.lanes_per_ant : 64, h->stream));
     HIP_TRY(hipEventRecord(h->ev[2 * i + 1], h->stream));
     HIP_TRY(acs::launch_best_global(h->dev, it, (int)h->p.memory, h->stream));
   }
@@ -526,11 +535,22 @@ struct acs_batch_t {
   bool own_ws = false;
   acs::Dev *d_devs = nullptr;
   acs::Iter *d_iters = nullptr;
-  int2 *d_items = nullptr;
-  int nitems = 0, nmax = 0, mode = ACS_ASYNC_ATOMIC;
+  int nmax = 0, mode = ACS_ASYNC_ATOMIC;
   int64_t steps_per_iteration = 0;
-  hipGraph_t graph = nullptr;
-  hipGraphExec_t exec = nullptr;
+  // One launch configuration per candidate lanes-per-ant value: its work
+  // list and its captured iteration.  The first iterations time each of
+  // them once (after one untimed warm-up iteration); the fastest is kept.
+  struct Variant {
+    int lanes = 64;
+    int2 *d_items = nullptr;
+    int nitems = 0;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    double ms = -1.0;
+  };
+  std::vector<Variant> var;
+  int chosen = -1;     // index into var once tuned
+  int tuning_step = 0; // iterations spent on tuning so far
   hipEvent_t e0 = nullptr, e1 = nullptr;
   double iterate_ms = 0.0;
 };
@@ -548,8 +568,10 @@ void release_batch(acs_batch_t *b) {
   if (!b) return;
   if (b->stream) (void)hipStreamSynchronize(b->stream);
   for (acs_t *h : b->inst) acs_destroy(h);
-  if (b->exec) (void)hipGraphExecDestroy(b->exec);
-  if (b->graph) (void)hipGraphDestroy(b->graph);
+  for (auto &v : b->var) {
+    if (v.exec) (void)hipGraphExecDestroy(v.exec);
+    if (v.graph) (void)hipGraphDestroy(v.graph);
+  }
   if (b->e0) (void)hipEventDestroy(b->e0);
   if (b->e1) (void)hipEventDestroy(b->e1);
   if (b->own_ws && b->ws) (void)hipFree(b->ws);
@@ -573,7 +595,8 @@ int batch_layout(const int32_t *n, int32_t count, const acs_params *p, BatchLayo
     if (rc) return rc;
     L->off[(size_t)i] = off;
     off = align_up(off + bytes, 256);
-    *nitems += p->m ? (int)p->m : n[i];
+    const int m = p->m ? (int)p->m : n[i];
+    *nitems += m + (m + 1) / 2 + (m + 3) / 4;  // work lists for 64, 32 and 16 lanes per ant
   }
   L->devs = off;
   off = align_up(off + sizeof(acs::Dev) * (size_t)count, 256);
@@ -680,41 +703,66 @@ int acs_batch_create(const double *const *coords, const int32_t *n, int32_t coun
     b->nmax = std::max(b->nmax, n[i]);
     b->steps_per_iteration += (int64_t)h->m * (h->n - 1);
   }
-  // work list: instances by decreasing n, so the longest chains start first
+  // candidate lanes per ant: the requested one, else every width that holds
+  // the largest candidate list (64 always; 32 and 16 when cl fits)
+  int clmax = 0;
+  for (acs_t *h : b->inst) clmax = std::max(clmax, h->cl);
+  std::vector<int> widths;
+  if (p->lanes_per_ant) {
+    widths.push_back((int)p->lanes_per_ant);
+  } else {
+    for (int w : {64, 32, 16})
+      if (w >= clmax) widths.push_back(w);
+  }
+  // work lists: instances by decreasing n, so the longest chains start
+  // first; a wave's ants always belong to one instance
   std::vector<int> order((size_t)count);
   for (int i = 0; i < count; ++i) order[(size_t)i] = i;
   std::stable_sort(order.begin(), order.end(), [&](int a, int c) { return n[a] > n[c]; });
-  std::vector<int2> items;
-  items.reserve((size_t)nitems);
-  for (int i : order)
-    for (int a = 0; a < b->inst[(size_t)i]->m; ++a) items.push_back(make_int2(i, a));
-  b->nitems = (int)items.size();
   b->d_devs = reinterpret_cast<acs::Dev *>(b->ws + L.devs);
   b->d_iters = reinterpret_cast<acs::Iter *>(b->ws + L.iters);
-  b->d_items = reinterpret_cast<int2 *>(b->ws + L.items);
+  int2 *d_items = reinterpret_cast<int2 *>(b->ws + L.items);
+  std::vector<int2> items;
+  items.reserve((size_t)nitems);
+  for (int w : widths) {
+    acs_batch_t::Variant v;
+    v.lanes = w;
+    v.d_items = d_items + items.size();
+    const int g = 64 / w;
+    for (int i : order)
+      for (int a = 0; a < b->inst[(size_t)i]->m; a += g) items.push_back(make_int2(i, a));
+    v.nitems = (int)(items.size() - (size_t)(v.d_items - d_items));
+    b->var.push_back(v);
+  }
+  if (items.size() > (size_t)nitems)
+    return bail(fail(ACS_E_STATE, "batch work lists exceed their reserved space"));
   if (hipMemcpyAsync(b->d_devs, devs.data(), sizeof(acs::Dev) * devs.size(),
                      hipMemcpyHostToDevice, b->stream) != hipSuccess ||
       hipMemcpyAsync(b->d_iters, iters.data(), sizeof(acs::Iter) * iters.size(),
                      hipMemcpyHostToDevice, b->stream) != hipSuccess ||
-      hipMemcpyAsync(b->d_items, items.data(), sizeof(int2) * items.size(),
+      hipMemcpyAsync(d_items, items.data(), sizeof(int2) * items.size(),
                      hipMemcpyHostToDevice, b->stream) != hipSuccess ||
       hipStreamSynchronize(b->stream) != hipSuccess)
     return bail(fail(ACS_E_DEVICE, "copy of batch descriptors failed"));
 
-  // one iteration captured once as a graph (no memset nodes: plain kernels)
-  if (hipStreamBeginCapture(b->stream, hipStreamCaptureModeThreadLocal) == hipSuccess) {
-    const hipError_t le = acs::launch_batch_iteration(b->d_devs, b->d_iters, b->d_items, b->nitems,
-                                                      b->count, b->nmax, b->mode, b->stream);
+  // each variant's iteration captured once as a graph (plain kernels only,
+  // no memset nodes); a variant whose capture fails is launched directly
+  for (auto &v : b->var) {
+    if (hipStreamBeginCapture(b->stream, hipStreamCaptureModeThreadLocal) != hipSuccess) continue;
+    const hipError_t le = acs::launch_batch_iteration(b->d_devs, b->d_iters, v.d_items, v.nitems,
+                                                      b->count, b->nmax, b->mode, v.lanes,
+                                                      b->stream);
     hipGraph_t g = nullptr;
     const hipError_t ce = hipStreamEndCapture(b->stream, &g);
     if (le == hipSuccess && ce == hipSuccess && g) {
-      b->graph = g;
-      if (hipGraphInstantiate(&b->exec, g, nullptr, nullptr, 0) != hipSuccess) b->exec = nullptr;
+      v.graph = g;
+      if (hipGraphInstantiate(&v.exec, g, nullptr, nullptr, 0) != hipSuccess) v.exec = nullptr;
     } else if (g) {
       (void)hipGraphDestroy(g);
     }
   }
   (void)hipGetLastError();
+  if (b->var.size() == 1) b->chosen = 0;
   {
     std::lock_guard<std::mutex> g(g_live_mu);
     g_live_batches.insert(b);
@@ -727,19 +775,44 @@ int acs_batch_iterate(acs_batch_t *b, int32_t k) {
   if (!live_batch(b)) return fail(ACS_E_STATE, "invalid batch handle");
   if (k < 0) return fail(ACS_E_INVALID, "k < 0");
   if (k == 0) return ACS_OK;
-  HIP_TRY(hipEventRecord(b->e0, b->stream));
-  for (int i = 0; i < k; ++i) {
-    if (b->exec) {
-      HIP_TRY(hipGraphLaunch(b->exec, b->stream));
-    } else {
-      HIP_TRY(acs::launch_batch_iteration(b->d_devs, b->d_iters, b->d_items, b->nitems, b->count,
-                                          b->nmax, b->mode, b->stream));
+  auto launch = [&](const acs_batch_t::Variant &v) -> hipError_t {
+    if (v.exec) return hipGraphLaunch(v.exec, b->stream);
+    return acs::launch_batch_iteration(b->d_devs, b->d_iters, v.d_items, v.nitems, b->count,
+                                       b->nmax, b->mode, v.lanes, b->stream);
+  };
+  double total_ms = 0.0;
+  int i = 0;
+  // tuning: one untimed warm-up iteration, then one timed iteration per
+  // variant (each a full iteration of every instance), then the fastest
+  while (b->chosen < 0 && i < k) {
+    const int v = b->tuning_step - 1;
+    HIP_TRY(hipEventRecord(b->e0, b->stream));
+    HIP_TRY(launch(b->var[(size_t)(v < 0 ? 0 : v)]));
+    HIP_TRY(hipEventRecord(b->e1, b->stream));
+    HIP_TRY(hipStreamSynchronize(b->stream));
+    float ms = 0.f;
+    HIP_TRY(hipEventElapsedTime(&ms, b->e0, b->e1));
+    total_ms += ms;
+    if (v >= 0) b->var[(size_t)v].ms = ms;
+    ++b->tuning_step;
+    ++i;
+    if (b->tuning_step > (int)b->var.size()) {
+      int best = 0;
+      for (int j = 1; j < (int)b->var.size(); ++j)
+        if (b->var[(size_t)j].ms < b->var[(size_t)best].ms) best = j;
+      b->chosen = best;
     }
   }
-  HIP_TRY(hipEventRecord(b->e1, b->stream));
-  HIP_TRY(hipStreamSynchronize(b->stream));
-  float ms = 0.f;
-  HIP_TRY(hipEventElapsedTime(&ms, b->e0, b->e1));
+  if (i < k) {
+    HIP_TRY(hipEventRecord(b->e0, b->stream));
+    for (; i < k; ++i) HIP_TRY(launch(b->var[(size_t)b->chosen]));
+    HIP_TRY(hipEventRecord(b->e1, b->stream));
+    HIP_TRY(hipStreamSynchronize(b->stream));
+    float ms = 0.f;
+    HIP_TRY(hipEventElapsedTime(&ms, b->e0, b->e1));
+    total_ms += ms;
+  }
+  const double ms = total_ms;
   b->iterate_ms = ms;
   for (acs_t *h : b->inst) {
     h->iter += (uint32_t)k;
@@ -755,8 +828,20 @@ int acs_batch_info(acs_batch_t *b, int32_t *count, int64_t *steps_per_iteration,
   if (!live_batch(b)) return fail(ACS_E_STATE, "invalid batch handle");
   if (count) *count = b->count;
   if (steps_per_iteration) *steps_per_iteration = b->steps_per_iteration;
-  if (graph) *graph = b->exec ? 1 : 0;
+  if (graph) *graph = b->var[(size_t)(b->chosen < 0 ? 0 : b->chosen)].exec ? 1 : 0;
   if (last_iterate_ms) *last_iterate_ms = b->iterate_ms;
+  return ACS_OK;
+}
+
+int acs_batch_tuning(acs_batch_t *b, int32_t *chosen_lanes, int32_t *count, int32_t *lanes,
+                     double *ms, int32_t cap) {
+  if (!live_batch(b)) return fail(ACS_E_STATE, "invalid batch handle");
+  if (chosen_lanes) *chosen_lanes = b->chosen < 0 ? 0 : b->var[(size_t)b->chosen].lanes;
+  if (count) *count = (int32_t)b->var.size();
+  for (int j = 0; j < (int)b->var.size() && j < cap; ++j) {
+    if (lanes) lanes[j] = b->var[(size_t)j].lanes;
+    if (ms) ms[j] = b->var[(size_t)j].ms;
+  }
   return ACS_OK;
 }
 

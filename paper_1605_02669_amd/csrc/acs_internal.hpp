@@ -58,9 +58,11 @@ hipError_t launch_init_pheromone(const Dev &d, float tau0, hipStream_t s);
 
 // ---- one iteration ----
 // Construction of all m tours.  mode 0 = synchronous steps (cooperative
-// persistent launch), 1 = asynchronous with atomic local updates.
-hipError_t launch_construct(const Dev &d, const Iter &it, int mode,
-                            int memory, hipStream_t s);
+// persistent launch), 1 = asynchronous with atomic local updates, 2 =
+// asynchronous with plain stores.  lanes: lanes per ant of the asynchronous
+// dense kernels (64, 32 or 16; at least cl).
+hipError_t launch_construct(const Dev &d, const Iter &it, int mode, int memory, int lanes,
+                            hipStream_t s);
 // Largest m a synchronous launch can keep resident for this instance.
 int max_sync_ants(const Dev &d, int memory);
 hipError_t launch_best_global(const Dev &d, const Iter &it, int memory,
@@ -69,9 +71,11 @@ hipError_t launch_best_global(const Dev &d, const Iter &it, int memory,
 // every (instance, ant) work item, then per-instance best and global update.
 // Descriptors, iteration state and the work list are device arrays, so the
 // three launches can be captured once in a graph and replayed.  mode 1:
-// updates by compare-and-swap; mode 2: plain stores (lost updates).
+// updates by compare-and-swap; mode 2: plain stores (lost updates).  lanes =
+// 64: items are (instance, ant), one per wave; lanes = 32 or 16: items are
+// (instance, first ant) of the 64 / lanes ants of one wave.
 hipError_t launch_batch_iteration(const Dev *devs, Iter *iters, const int2 *items, int nitems,
-                                  int count, int nmax, int mode, hipStream_t s);
+                                  int count, int nmax, int mode, int lanes, hipStream_t s);
 // Learned edge prior (acs_prior.hip): parameter count and kernels.
 constexpr int kPriorParams = 4545;
 hipError_t launch_prior_forward(const float *P, const float *X, int rows, float *Z,

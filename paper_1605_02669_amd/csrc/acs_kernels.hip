@@ -679,6 +679,242 @@ __global__ __launch_bounds__(256) void k_construct_async_batch(const Dev *devs, 
 }
 
 // ---------------------------------------------------------------------------
+// Asynchronous construction with several ants per wave: a group of L lanes
+// (L = 32 or 16, L >= cl) carries one ant, so a wave advances 64 / L ants in
+// lockstep.  The rule is the same as above, computed group by group: the
+// argmax and the roulette scan over candidate positions in the same order
+// (so the choice of L never changes a decision), reductions confined to the
+// group's rows (DPP within a row of 16, the row-pair swap for L = 32),
+// group-local lane reads by ds_bpermute.  All ants of a wave belong to one
+// instance and step together (same n); a group whose ant index is past m
+// leaves at the start.
+// ---------------------------------------------------------------------------
+template <int L>
+__device__ __forceinline__ uint32_t grp_umax(uint32_t v) {
+  v = max(v, (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0xB1, 0xF, 0xF, false));
+  v = max(v, (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x4E, 0xF, 0xF, false));
+  v = max(v, (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x141, 0xF, 0xF, false));
+  v = max(v, (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x140, 0xF, 0xF, false));
+  if (L == 32) {
+    const auto a = __builtin_amdgcn_permlane16_swap(v, v, false, false);
+    v = max(v, max((uint32_t)a[0], (uint32_t)a[1]));
+  }
+  return v;
+}
+
+template <int L>
+__device__ __forceinline__ uint32_t grp_umin(uint32_t v) {
+  v = min(v, (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0xB1, 0xF, 0xF, false));
+  v = min(v, (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x4E, 0xF, 0xF, false));
+  v = min(v, (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x141, 0xF, 0xF, false));
+  v = min(v, (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x140, 0xF, 0xF, false));
+  if (L == 32) {
+    const auto a = __builtin_amdgcn_permlane16_swap(v, v, false, false);
+    v = min(v, min((uint32_t)a[0], (uint32_t)a[1]));
+  }
+  return v;
+}
+
+// This group's bits of a wave ballot.
+template <int L>
+__device__ __forceinline__ uint32_t grp_bits(uint64_t ballot, int base) {
+  const uint32_t b = (uint32_t)(ballot >> base);
+  return L == 32 ? b : (b & 0xffffu);
+}
+
+// Value of v on lane k of this group.
+__device__ __forceinline__ uint32_t grp_read(uint32_t v, int base, int k) {
+  return (uint32_t)__shfl((int)v, base + k, 64);
+}
+
+template <int L, bool ATOMIC>
+__device__ __forceinline__ void ants_async_dense(const Dev &D, const Iter &A, int first,
+                                                 uint32_t *vis_wave, int lane) {
+  const int gi = lane / L, gl = lane % L, base = gi * L;
+  const int ant = first + gi;
+  if (ant >= D.m) return;  // the whole group leaves
+  const int n = D.n, cl = D.cl, ldn = D.ldn;
+  const int W = (n + 31) >> 5;
+  const int kl = gl < cl ? gl : cl - 1;
+  const float al = A.a_loc, bl = A.b_loc;
+  uint32_t *vis = vis_wave + gi * W;
+
+  for (int w = gl; w < W; w += L) vis[w] = 0u;
+  uint4 draws = philox10(make_uint4((uint32_t)gl, (uint32_t)ant, A.it, A.instance), A.key0, A.key1);
+  const int start = (int)__umulhi(grp_read(draws.z, base, 0), (uint32_t)n);
+  if (gl == 0) vis[start >> 5] |= 1u << (start & 31);
+  int tb = start;
+  uint4 rec = D.crec[(size_t)start * cl + kl];
+
+  int cur = start, prev = -1;
+  float *fwd = nullptr;
+  float fval = 0.f;
+  int64_t len = 0;
+  uint32_t c_greedy = 0, c_roul = 0, c_fb = 0, c_retry = 0;
+  uint64_t c_fbu = 0;
+  float *pptr = nullptr;
+  unsigned int pexp = 0, pret = 0;
+  bool pend = false;
+
+  for (int t = 1; t <= n; ++t) {
+    if (ATOMIC && pend && pret != pexp) c_retry += 1 + cas_apply(pptr, pret, al, bl);
+    pend = false;
+    const uint32_t word = vis[rec.x >> 5];
+    const bool unv = (gl < cl) & !((word >> (rec.x & 31)) & 1u);
+    const float w = unv ? __uint_as_float(rec.w) * __uint_as_float(rec.z) : 0.f;
+    __asm__ volatile("" ::"v"(w), "v"((int)unv));
+    if (t > 1 && (t - 1) % A.lperiod == 0) {
+      const uint32_t b = grp_bits<L>(__ballot(gl < cl && rec.x == (uint32_t)prev), base);
+      const int kr = b ? __builtin_ctz(b) : -1;
+      const float rval = kr >= 0 ? __uint_as_float(grp_read(rec.w, base, kr)) : fval;
+      if (gl < 2) {
+        float *h = gl == 0 ? fwd : home(D, cur, prev, kr);
+        const float seen = gl == 0 ? fval : rval;
+        if (ATOMIC) {
+          pptr = h;
+          pexp = __float_as_uint(seen);
+          pend = true;
+          pret = atomicCAS(reinterpret_cast<unsigned int *>(h), pexp,
+                           __float_as_uint(fmaf(al, seen, bl)));
+        } else {
+          __hip_atomic_store(h, fmaf(al, seen, bl), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        }
+      }
+    }
+    if (t == n) break;
+    if ((t & (L - 1)) == 0)
+      draws = philox10(make_uint4((uint32_t)(t + gl), (uint32_t)ant, A.it, A.instance), A.key0,
+                       A.key1);
+    const uint32_t q24 = grp_read(draws.x, base, t & (L - 1)) >> 8;
+    const uint32_t u24 = grp_read(draws.y, base, t & (L - 1)) >> 8;
+    const uint32_t umask = grp_bits<L>(__ballot(unv), base);
+    int next, kind, k = -1;
+    uint32_t d;
+    float tval;
+    if (umask) {
+      if (q24 < A.q0_24) {
+        const uint32_t mx = grp_umax<L>(__float_as_uint(w));
+        k = __builtin_ctz(grp_bits<L>(__ballot(unv && __float_as_uint(w) == mx), base));
+        kind = 0;
+      } else {
+        float P = w;
+        for (int off = 1; off < cl; off <<= 1) {
+          const float o = __shfl_up(P, off, L);
+          if (gl >= off) P = P + o;
+        }
+        const float total = __uint_as_float(grp_read(__float_as_uint(P), base, cl - 1));
+        const float r = ((float)u24 * 0x1p-24f) * total;
+        const uint32_t sel = grp_bits<L>(__ballot(unv && P > r), base);
+        k = sel ? __builtin_ctz(sel) : 31 - __builtin_clz(umask);
+        kind = 1;
+      }
+      next = (int)grp_read(rec.x, base, k);
+      d = grp_read(rec.y, base, k);
+      tval = __uint_as_float(grp_read(rec.w, base, k));
+    } else {
+      // Alg. 2's fallback over every unvisited city, ties -> lowest index
+      const float *trow = D.tau + (size_t)cur * ldn;
+      const float *erow = D.etad + (size_t)cur * ldn;
+      const uint16_t *drow = D.dist + (size_t)cur * ldn;
+      float bv = 0.f, bt = 0.f;
+      uint32_t bj = kNone, bd = 0;
+#pragma unroll 2
+      for (int j0 = 4 * gl; j0 < n; j0 += 4 * L) {
+        const float4 tv = *reinterpret_cast<const float4 *>(trow + j0);
+        const float4 ev = *reinterpret_cast<const float4 *>(erow + j0);
+        const ushort4 dv = *reinterpret_cast<const ushort4 *>(drow + j0);
+        const float tq[4] = {tv.x, tv.y, tv.z, tv.w};
+        const float eq[4] = {ev.x, ev.y, ev.z, ev.w};
+        const uint32_t dq[4] = {dv.x, dv.y, dv.z, dv.w};
+        uint32_t bits = (vis[j0 >> 5] >> (j0 & 31)) & 0xfu;
+        if (j0 + 4 > n) bits |= (0xfu << (n - j0)) & 0xfu;
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          const float v = tq[q] * eq[q];
+          if (!((bits >> q) & 1u) && (bj == kNone || v > bv)) {
+            bv = v; bj = (uint32_t)(j0 + q); bt = tq[q]; bd = dq[q];
+          }
+        }
+      }
+      const uint32_t mx = grp_umax<L>(bj == kNone ? 0u : __float_as_uint(bv));
+      const uint32_t jn = grp_umin<L>((bj != kNone && __float_as_uint(bv) == mx) ? bj : kNone);
+      const int owner = __builtin_ctz(grp_bits<L>(__ballot(bj == jn), base));
+      next = (int)jn;
+      d = grp_read(bd, base, owner);
+      tval = __uint_as_float(grp_read(__float_as_uint(bt), base, owner));
+      kind = 2;
+    }
+    c_greedy += kind == 0;
+    c_roul += kind == 1;
+    if (kind == 2) { ++c_fb; c_fbu += (uint64_t)(n - t); }
+    if (gl == 0) vis[next >> 5] |= 1u << (next & 31);
+    tb = gl == (t & (L - 1)) ? next : tb;
+    if ((t & (L - 1)) == L - 1 || t == n - 1) {
+      const int tbase = t & ~(L - 1);
+      if (gl <= (t & (L - 1))) D.tours[(size_t)ant * n + tbase + gl] = tb;
+    }
+    len += d;
+    rec = D.crec[(size_t)next * cl + kl];
+    fwd = home(D, cur, next, k);
+    fval = tval;
+    prev = cur;
+    cur = next;
+  }
+  if (ATOMIC && pend && pret != pexp) c_retry += 1 + cas_apply(pptr, pret, al, bl);
+  {
+    const uint32_t b1 = grp_bits<L>(__ballot(gl < cl && D.crec[(size_t)cur * cl + kl].x ==
+                                                         (uint32_t)start), base);
+    const uint32_t b2 = grp_bits<L>(__ballot(gl < cl && D.crec[(size_t)start * cl + kl].x ==
+                                                         (uint32_t)cur), base);
+    const int k1 = b1 ? __builtin_ctz(b1) : -1, k2 = b2 ? __builtin_ctz(b2) : -1;
+    float *h = gl == 0 ? home(D, cur, start, k1) : home(D, start, cur, k2);
+    if (gl < 2) {
+      if (ATOMIC)
+        c_retry += cas_apply(h, __float_as_uint(tau_load(h)), al, bl);
+      else
+        __hip_atomic_store(h, fmaf(al, tau_load(h), bl), __ATOMIC_RELAXED,
+                           __HIP_MEMORY_SCOPE_AGENT);
+    }
+  }
+  len += D.dist[(size_t)cur * ldn + start];
+  c_retry += grp_read(c_retry, base, 1);
+  if (gl == 0) {
+    D.lens[ant] = len;
+    add_counters(D, c_greedy, c_roul, c_fb, c_fbu, c_retry);
+  }
+}
+
+// Batch of instances, L lanes per ant: wave w runs ants witems[w].y ..
+// witems[w].y + 64 / L - 1 of instance witems[w].x.
+template <int L, bool ATOMIC>
+__global__ __launch_bounds__(256) void k_construct_async_batch_g(const Dev *devs,
+                                                                 const Iter *iters,
+                                                                 const int2 *witems, int nw,
+                                                                 int wmax) {
+  extern __shared__ uint32_t smem[];
+  const int lane = threadIdx.x & 63;
+  const int wv = threadIdx.x >> 6;
+  const int w = uni(blockIdx.x * (blockDim.x >> 6) + wv);
+  if (w >= nw) return;
+  const int2 item = witems[w];
+  const int inst = uni(item.x);
+  const Dev D = devs[inst];
+  const Iter A = iters[inst];
+  ants_async_dense<L, ATOMIC>(D, A, uni(item.y), smem + wv * (64 / L) * wmax, lane);
+}
+
+// One instance, L lanes per ant.
+template <int L, bool ATOMIC>
+__global__ __launch_bounds__(256) void k_construct_async_dense_g(Dev D, Iter A) {
+  extern __shared__ uint32_t smem[];
+  const int lane = threadIdx.x & 63;
+  const int wv = threadIdx.x >> 6;
+  const int first = uni((blockIdx.x * (blockDim.x >> 6) + wv) * (64 / L));
+  if (first >= D.m) return;
+  ants_async_dense<L, ATOMIC>(D, A, first, smem + wv * (64 / L) * ((D.n + 31) >> 5), lane);
+}
+
+// ---------------------------------------------------------------------------
 // Selective pheromone memory (Sec. 3.2, Alg. 3).  The record of city c is s
 // pairs {neighbour, pheromone}; a wave holds it with slot i on lane i.
 // ---------------------------------------------------------------------------
@@ -1351,7 +1587,8 @@ hipError_t launch_init_pheromone(const Dev &d, float tau0, hipStream_t s) {
   return hipGetLastError();
 }
 
-hipError_t launch_construct(const Dev &d, const Iter &it, int mode, int memory, hipStream_t s) {
+hipError_t launch_construct(const Dev &d, const Iter &it, int mode, int memory, int lanes,
+                            hipStream_t s) {
   if (mode == 0) {
     const int apb = kSyncBlock / 64;
     const int grid = (d.m + apb - 1) / apb;
@@ -1367,7 +1604,19 @@ hipError_t launch_construct(const Dev &d, const Iter &it, int mode, int memory, 
   const int grid = (d.m + apb - 1) / apb;
   const size_t lds = lds_bytes(d, kAsyncBlock);
   const bool atomic = mode == 1;
-  if (memory == 0) {
+  if (memory == 0 && lanes < 64) {
+    const int g = 64 / lanes;
+    const dim3 gg((d.m + apb * g - 1) / (apb * g));
+    const size_t lg = lds * g;
+    if (lanes == 32 && atomic)
+      hipLaunchKernelGGL((k_construct_async_dense_g<32, true>), gg, dim3(kAsyncBlock), lg, s, d, it);
+    else if (lanes == 32)
+      hipLaunchKernelGGL((k_construct_async_dense_g<32, false>), gg, dim3(kAsyncBlock), lg, s, d, it);
+    else if (atomic)
+      hipLaunchKernelGGL((k_construct_async_dense_g<16, true>), gg, dim3(kAsyncBlock), lg, s, d, it);
+    else
+      hipLaunchKernelGGL((k_construct_async_dense_g<16, false>), gg, dim3(kAsyncBlock), lg, s, d, it);
+  } else if (memory == 0) {
     if (atomic)
       hipLaunchKernelGGL(k_construct_async_dense<true>, dim3(grid), dim3(kAsyncBlock), lds, s, d,
                          it);
@@ -1411,17 +1660,30 @@ hipError_t launch_best_global(const Dev &d, const Iter &it, int memory, hipStrea
 }
 
 hipError_t launch_batch_iteration(const Dev *devs, Iter *iters, const int2 *items, int nitems,
-                                  int count, int nmax, int mode, hipStream_t s) {
+                                  int count, int nmax, int mode, int lanes, hipStream_t s) {
   const int apb = kAsyncBlock / 64;
   const int wmax = (nmax + 31) / 32;
-  const size_t lds = (size_t)apb * wmax * sizeof(uint32_t);
-  const dim3 grid((nitems + apb - 1) / apb);
-  if (mode == 1)
-    hipLaunchKernelGGL(k_construct_async_batch<true>, grid, dim3(kAsyncBlock), lds, s, devs,
-                       iters, items, nitems, wmax);
+  const size_t lds = (size_t)apb * (64 / lanes) * wmax * sizeof(uint32_t);
+  const dim3 grid((nitems + apb - 1) / apb), blk(kAsyncBlock);
+  const bool atomic = mode == 1;
+  if (lanes == 64 && atomic)
+    hipLaunchKernelGGL(k_construct_async_batch<true>, grid, blk, lds, s, devs, iters, items,
+                       nitems, wmax);
+  else if (lanes == 64)
+    hipLaunchKernelGGL(k_construct_async_batch<false>, grid, blk, lds, s, devs, iters, items,
+                       nitems, wmax);
+  else if (lanes == 32 && atomic)
+    hipLaunchKernelGGL((k_construct_async_batch_g<32, true>), grid, blk, lds, s, devs, iters,
+                       items, nitems, wmax);
+  else if (lanes == 32)
+    hipLaunchKernelGGL((k_construct_async_batch_g<32, false>), grid, blk, lds, s, devs, iters,
+                       items, nitems, wmax);
+  else if (atomic)
+    hipLaunchKernelGGL((k_construct_async_batch_g<16, true>), grid, blk, lds, s, devs, iters,
+                       items, nitems, wmax);
   else
-    hipLaunchKernelGGL(k_construct_async_batch<false>, grid, dim3(kAsyncBlock), lds, s, devs,
-                       iters, items, nitems, wmax);
+    hipLaunchKernelGGL((k_construct_async_batch_g<16, false>), grid, blk, lds, s, devs, iters,
+                       items, nitems, wmax);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(k_best_batch, dim3(count), dim3(1024), 0, s, devs, iters);

@@ -473,3 +473,99 @@ def test_racy_batch_single_ant_equals_oracle(acs):
             assert np.array_equal(b.tours(i), o.tours()), (i, it)
             assert np.array_equal(b.tau(i), o.tau()), (i, it)
     b.close()
+
+
+# ---------------------------------------------------------------------------
+# First iteration of the asynchronous kernels.  Every entry starts at tau0 and
+# the local map fixes tau0 (f(tau0) = tau0 in FP32, checked on the oracle),
+# so no read can see another ant's update: with any number of ants, any
+# number of ants per wavefront and either update kind, the first iteration's
+# tours must equal the synchronous oracle's bit for bit.
+# ---------------------------------------------------------------------------
+ASYNC_FIRST = [
+    ("atomic_l64", dict(), 64, "ASYNC_ATOMIC"),
+    ("atomic_l32", dict(), 32, "ASYNC_ATOMIC"),
+    ("racy_l32", dict(), 32, "ASYNC_RACY"),
+    ("atomic_l16_cl16", dict(cl=16), 16, "ASYNC_ATOMIC"),
+    ("racy_l16_ragged", dict(cl=12, m=203), 16, "ASYNC_RACY"),
+    ("racy_l64", dict(m=333), 64, "ASYNC_RACY"),
+    ("spm_atomic", dict(cl=16, memory=1, spm_s=8), 0, "ASYNC_ATOMIC"),
+    ("spm_racy", dict(cl=16, memory=1, spm_s=4, m=250), 0, "ASYNC_RACY"),
+]
+
+
+@pytest.mark.parametrize("name,kw,lanes,mode", ASYNC_FIRST, ids=[c[0] for c in ASYNC_FIRST])
+def test_async_first_iteration_equals_oracle(acs, name, kw, lanes, mode):
+    n = 733
+    xy = inputs.clustered(n, 77) if "ragged" in name else inputs.uniform(n, 77)
+    orc = oracle.Oracle(xy, seed=12, **kw)
+    c = orc.constants()
+    assert orc.local_map_k(c["tau0"], 1) == c["tau0"]
+    col = acs.Colony(xy, mode=getattr(acs, "ACS_" + mode), seed=12, lanes_per_ant=lanes, **kw)
+    col.iterate(1)
+    orc.iterate(1)
+    assert np.array_equal(col.tours(), orc.tours())
+    assert np.array_equal(col.lengths(), orc.lengths())
+    assert col.best()[1] == orc.best()[1]
+    st, oc = col.stats(), orc.counts()
+    for k in ("greedy", "roulette", "fallback"):
+        assert st[k] == oc[k], k
+    col.close()
+
+
+@pytest.mark.parametrize("lanes", [32, 16])
+def test_grouped_single_ant_equals_oracle(acs, lanes):
+    xy = inputs.uniform(310, 31)
+    col = acs.Colony(xy, m=1, cl=16, mode=acs.ACS_ASYNC_ATOMIC, seed=5, lanes_per_ant=lanes)
+    orc = oracle.Oracle(xy, m=1, cl=16, seed=5)
+    for it in range(6):
+        col.iterate(1)
+        orc.iterate(1)
+        _compare(col, orc, it)
+    col.close()
+
+
+@pytest.mark.parametrize("lanes,mode", [(32, "ASYNC_ATOMIC"), (16, "ASYNC_RACY")])
+def test_grouped_tours_valid(acs, lanes, mode):
+    n = 1500
+    xy = inputs.uniform(n, 8)
+    col = acs.Colony(xy, cl=16, mode=getattr(acs, "ACS_" + mode), seed=2, lanes_per_ant=lanes)
+    col.iterate(3)
+    tours, lens = col.tours(), col.lengths()
+    assert np.all(np.sort(tours, axis=1) == np.arange(n)[None, :])
+    assert np.array_equal(defs.tour_lengths(xy, tours), lens)
+    assert col.stats()["steps"] == 3 * n * (n - 1)
+    col.close()
+
+
+def test_batch_tuner_picks_a_shape_and_keeps_iterating(acs):
+    insts = inputs.batch(40, seed=61, nmin=100, nmax=700)
+    b = acs.Batch(insts, cl=16, seed=3)
+    assert b.tuning()["chosen_lanes"] == 0
+    b.iterate(2)  # warm-up + first candidate
+    b.iterate(3)  # the other candidates, then the chosen shape
+    tu = b.tuning()
+    _say(f"batch tuning {tu}")
+    assert set(tu["candidates"]) == {64, 32, 16}
+    assert all(v > 0 for v in tu["candidates"].values())
+    assert tu["chosen_lanes"] == min(tu["candidates"], key=tu["candidates"].get)
+    for i, xy in enumerate(insts):
+        tours, lens = b.tours(i), b.lengths(i)
+        assert np.all(np.sort(tours, axis=1) == np.arange(len(xy))[None, :])
+        assert np.array_equal(defs.tour_lengths(xy, tours), lens)
+        assert b.stats(i)["iteration"] == 5
+    b.close()
+
+
+@pytest.mark.parametrize("lanes", [32, 16])
+def test_batch_grouped_single_ant_equals_oracle(acs, lanes):
+    insts = inputs.batch(5, seed=71, nmin=40, nmax=260)
+    b = acs.Batch(insts, m=1, cl=16, seed=4, lanes_per_ant=lanes)
+    orcs = [oracle.Oracle(x, m=1, cl=16, seed=4, instance=i) for i, x in enumerate(insts)]
+    for it in range(3):
+        b.iterate(1)
+        for i, o in enumerate(orcs):
+            o.iterate(1)
+            assert np.array_equal(b.tours(i), o.tours()), (i, it)
+            assert np.array_equal(b.tau(i), o.tau()), (i, it)
+    b.close()
