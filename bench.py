@@ -162,20 +162,76 @@ def run_batch(acs, inputs, iters=5, count=256):
     t0 = time.perf_counter()
     b = acs.Batch(insts, cl=CL, seed=0)
     create_s = time.perf_counter() - t0
-    b.iterate(1)
+    b.iterate(4)  # warm-up and the launch-shape tuning
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     b.iterate(iters)
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
     info = b.info()
+    tuning = b.tuning()
     b.close()
-    return {"instances": count, "n_min": int(min(len(x) for x in insts)),
+    return {"instances": count, "lanes_per_ant": tuning["chosen_lanes"],
+            "tuning_ms": tuning["candidates"], "n_min": int(min(len(x) for x in insts)),
             "n_max": int(max(len(x) for x in insts)),
             "steps_per_iteration": info["steps_per_iteration"], "graph": info["graph"],
             "steps_per_s": info["steps_per_iteration"] * iters / dt,
             "ms_per_iteration": dt * 1e3 / iters, "iterations": iters,
             "create_s": create_s}
+
+
+MFMA_BF16_PEAK_TFLOPS = 2500.0
+# algorithmic flops per feature row of the 4-64-64-1 network: forward
+# 2 (4*64 + 64*64 + 64); backward adds the weight and input gradients of the
+# two upper layers and the first layer's weight gradient, 2 (64 + 64 + 2*4096
+# + 256), plus the recomputed forward
+PRIOR_FWD_FLOPS = 2 * (4 * 64 + 64 * 64 + 64)
+PRIOR_BWD_FLOPS = PRIOR_FWD_FLOPS + 2 * (64 + 64 + 2 * 64 * 64 + 4 * 64)
+
+
+def run_prior(acs, inputs, rows=1 << 22, reps=5, eval_seeds=5, eval_budget_s=1.0):
+    """The learned prior's kernels at training scale (BF16 matrix cores), and
+    the equal-wall-clock comparison with plain ACS when trained parameters
+    are present."""
+    import numpy as np
+    import torch
+    from paper_1605_02669_amd import prior
+    g = torch.Generator(device="cuda")
+    g.manual_seed(0)
+    X = torch.randn((rows, 4), generator=g, device="cuda")
+    Y = torch.rand((rows,), generator=g, device="cuda")
+    P = torch.tensor(prior.init_params(0), device="cuda")
+    G = torch.zeros_like(P)
+    L = torch.zeros(1, device="cuda")
+    acs.prior_forward(P, X)
+    acs.prior_grad(P, X, Y, G, L)
+    e = [torch.cuda.Event(enable_timing=True) for _ in range(4)]
+    e[0].record()
+    for _ in range(reps):
+        acs.prior_forward(P, X)
+    e[1].record()
+    for _ in range(reps):
+        acs.prior_grad(P, X, Y, G, L)
+    e[2].record()
+    torch.cuda.synchronize()
+    fwd_s = e[0].elapsed_time(e[1]) / 1e3 / reps
+    bwd_s = e[1].elapsed_time(e[2]) / 1e3 / reps
+    fwd_tf = rows * PRIOR_FWD_FLOPS / fwd_s / 1e12
+    bwd_tf = rows * PRIOR_BWD_FLOPS / bwd_s / 1e12
+    out = {"rows": rows,
+           "forward": {"ms": fwd_s * 1e3, "tflops": fwd_tf,
+                       "mfma_frac": fwd_tf / MFMA_BF16_PEAK_TFLOPS},
+           "gradient": {"ms": bwd_s * 1e3, "tflops": bwd_tf,
+                        "mfma_frac": bwd_tf / MFMA_BF16_PEAK_TFLOPS},
+           "peak_tflops": MFMA_BF16_PEAK_TFLOPS, "flops_per_row": [PRIOR_FWD_FLOPS, PRIOR_BWD_FLOPS]}
+    if os.path.exists(prior.DEFAULT_PARAMS):
+        params = torch.tensor(np.load(prior.DEFAULT_PARAMS), device="cuda")
+        out["equal_time"] = prior.evaluate(params, seeds=eval_seeds, budget_s=eval_budget_s,
+                                           log=lambda s: print("# " + s, file=sys.stderr,
+                                                               flush=True))
+    else:
+        out["equal_time"] = None
+    return out
 
 
 def main():
@@ -185,9 +241,9 @@ def main():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--sync-steps", type=int, default=5)
     ap.add_argument("--no-cpu", action="store_true")
-    ap.add_argument("--extra", default="c1,c2c,c3,c4,alt,k16",
+    ap.add_argument("--extra", default="c1,c2c,c3,c4,c5,alt,k16",
                     help="other workloads timed beside the headline (comma list of "
-                         "c1, c2c, c3, c4, alt, k16; empty for none)")
+                         "c1, c2c, c3, c4, c5, alt, k16; empty for none)")
     ap.add_argument("--copy-calibration-mb", type=int, default=0,
                     help="after timing, run one plain device copy of this many MiB "
                          "(reference kernel for hardware byte counters)")
@@ -255,6 +311,8 @@ def main():
     for name in [x for x in args.extra.split(",") if x]:
         if name == "c4":
             extra[name] = run_batch(acs, inputs)
+        elif name == "c5":
+            extra[name] = run_prior(acs, inputs)
         else:
             extra[name] = run_extra(acs, inputs, name)
         print(f"# {name}: {extra[name]}", file=sys.stderr, flush=True)
