@@ -62,6 +62,14 @@ __device__ __forceinline__ void stage_weights(Stage &S, const float *P) {
   __syncthreads();
 }
 
+// The lanes of a wave exchange activations through LDS.  LDS operations of
+// one wave complete in issue order; this keeps the compiler from moving LDS
+// accesses across the exchange points.
+__device__ __forceinline__ void wave_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+}
+
 __device__ __forceinline__ bf16x8 ld8(const __bf16 *p) {
   return *reinterpret_cast<const bf16x8 *>(p);
 }
@@ -93,6 +101,7 @@ __device__ __forceinline__ f32x4 forward16(const Stage &S, float4 x, int lane, _
     for (int v = 0; v < 4; ++v)
       h1[(4 * g + v) * H + 16 * t + c16] = (__bf16)fmaxf(d[v] + S.b1[16 * t + c16], 0.f);
   }
+  wave_sync();
   const bf16x8 a2a = ld8(h1 + c16 * H + 8 * g), a2b = ld8(h1 + c16 * H + 32 + 8 * g);
 #pragma unroll
   for (int t = 0; t < 4; ++t) {
@@ -102,6 +111,7 @@ __device__ __forceinline__ f32x4 forward16(const Stage &S, float4 x, int lane, _
     for (int v = 0; v < 4; ++v)
       h2[(4 * g + v) * H + 16 * t + c16] = (__bf16)fmaxf(d[v] + S.b2[16 * t + c16], 0.f);
   }
+  wave_sync();
   const bf16x8 a3a = ld8(h2 + c16 * H + 8 * g), a3b = ld8(h2 + c16 * H + 32 + 8 * g);
   f32x4 d = mfma(a3a, ld8(S.w3t + c16 * H + 8 * g), zero);
   d = mfma(a3b, ld8(S.w3t + c16 * H + 32 + 8 * g), d);
@@ -123,6 +133,7 @@ __global__ __launch_bounds__(64) void k_prior_forward(const float *P, const floa
   stage_weights(S, P);
   const int lane = threadIdx.x;
   for (int r0 = blockIdx.x * 16; r0 < rows; r0 += gridDim.x * 16) {
+    wave_sync();
     const f32x4 z = forward16(S, load_x(X, r0 + (lane & 15), rows), lane, h1, h2);
     if ((lane & 15) == 0)
       for (int v = 0; v < 4; ++v) {
@@ -158,20 +169,23 @@ __global__ __launch_bounds__(64) void k_prior_grad(const float *P, const float *
   float gw3 = 0.f, gb2 = 0.f, gb3 = 0.f, loss = 0.f;  // lane = feature
 
   for (int r0 = blockIdx.x * 32; r0 < rows; r0 += gridDim.x * 32) {
-    // forward of two 16-row halves
+    wave_sync();
+    // forward of two 16-row halves; the first layer's inputs are kept as the
+    // bf16 values the matrix cores multiplied (for its weight gradient)
     for (int hf = 0; hf < 2; ++hf) {
       const int row = r0 + 16 * hf + c16;
       const float4 x = load_x(X, row, rows);
       if (g == 0) {
-        xs[(16 * hf + c16) * 4 + 0] = x.x;
-        xs[(16 * hf + c16) * 4 + 1] = x.y;
-        xs[(16 * hf + c16) * 4 + 2] = x.z;
-        xs[(16 * hf + c16) * 4 + 3] = x.w;
+        xs[(16 * hf + c16) * 4 + 0] = (float)(__bf16)x.x;
+        xs[(16 * hf + c16) * 4 + 1] = (float)(__bf16)x.y;
+        xs[(16 * hf + c16) * 4 + 2] = (float)(__bf16)x.z;
+        xs[(16 * hf + c16) * 4 + 3] = (float)(__bf16)x.w;
       }
       const f32x4 z = forward16(S, x, lane, h1 + 16 * hf * H, h2 + 16 * hf * H);
       if (c16 == 0)
         for (int v = 0; v < 4; ++v) zs[16 * hf + 4 * g + v] = z[v];
     }
+    wave_sync();
     // dz = (sigmoid(z) - y) / rows, loss = softplus(z) - y z (rows past the end: 0)
     if (lane < 32) {
       const int row = r0 + lane;
@@ -183,14 +197,16 @@ __global__ __launch_bounds__(64) void k_prior_grad(const float *P, const float *
       }
       dzs[lane] = dz;
     }
-    // last layer and dH2 (lane = feature f)
+    wave_sync();
+    // last layer and dH2 (lane = feature f); W3 as the forward pass used it (bf16)
     {
       const int f = lane;
+      const float w3f = (float)S.w3t[f];
       for (int r = 0; r < 32; ++r) {
         const float hv = (float)h2[r * H + f];
         const float dz = dzs[r];
         gw3 += hv * dz;
-        const float dh = hv > 0.f ? dz * S.w3[f] : 0.f;
+        const float dh = hv > 0.f ? dz * w3f : 0.f;
         gb2 += dh;
         dh2[r * H + f] = (__bf16)dh;
         dh2t[f * 32 + r] = (__bf16)dh;
@@ -198,6 +214,7 @@ __global__ __launch_bounds__(64) void k_prior_grad(const float *P, const float *
       }
       if (lane < 32) gb3 += dzs[lane];
     }
+    wave_sync();
     // dW2 += H1^T dH2: M = 64 features (4 tiles), N = 64 (4 tiles), K = 32 rows
     for (int mt = 0; mt < 4; ++mt) {
       const bf16x8 a = ld8(h1t + (16 * mt + c16) * 32 + 8 * g);
@@ -284,6 +301,7 @@ __global__ __launch_bounds__(64) void k_prior_apply(Dev D, const float *P) {
   const int lane = threadIdx.x;
   const int rows = D.n * 16;
   for (int r0 = blockIdx.x * 16; r0 < rows; r0 += gridDim.x * 16) {
+    wave_sync();
     const int row = r0 + (lane & 15);
     const float4 x = row < rows ? edge_features(D, row / 16, row % 16)
                                 : make_float4(0.f, 0.f, 0.f, 0.f);
