@@ -35,7 +35,7 @@ class acs_params(C.Structure):
         ("beta", C.c_double), ("q0", C.c_double), ("phi", C.c_double),
         ("rho", C.c_double), ("tau0", C.c_double), ("seed", C.c_uint64),
         ("stream", C.c_void_p), ("workspace", C.c_void_p), ("workspace_bytes", C.c_size_t),
-        ("lanes_per_ant", C.c_uint32), ("reserved", C.c_uint32),
+        ("lanes_per_ant", C.c_uint32), ("update_path", C.c_uint32),
     ]
 
 
@@ -199,7 +199,7 @@ class Colony:
 
     def __init__(self, xy, m=0, cl=32, beta=2.0, q0=0.9, phi=0.1, rho=0.1, tau0=0.0,
                  memory=ACS_DENSE, spm_s=8, mode=ACS_SYNC, seed=0, instance=0,
-                 local_update_period=1, lanes_per_ant=0, torch_memory=True):
+                 local_update_period=1, lanes_per_ant=0, update_path=0, torch_memory=True):
         self.xy = np.ascontiguousarray(xy, dtype=np.float64).reshape(-1, 2)
         n = self.xy.shape[0]
         p = acs_default_params()
@@ -207,6 +207,7 @@ class Colony:
         p.memory, p.spm_s, p.mode, p.seed, p.instance = memory, spm_s, mode, seed, instance
         p.local_update_period = local_update_period
         p.lanes_per_ant = lanes_per_ant
+        p.update_path = update_path
         self._ws = None
         if torch_memory:
             import torch

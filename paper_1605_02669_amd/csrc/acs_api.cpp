@@ -115,7 +115,8 @@ int check_params(int32_t n, const acs_params *p) {
     return fail(ACS_E_UNSUPPORTED, "lanes_per_ant = %u < cl = %u", lpa, cl);
   if (lpa != 0 && lpa != 64 && (p->mode == ACS_SYNC || p->memory != ACS_DENSE))
     return fail(ACS_E_UNSUPPORTED, "lanes_per_ant < 64 needs an asynchronous mode and dense memory");
-  if (p->reserved != 0) return fail(ACS_E_INVALID, "reserved must be 0");
+  if (p->update_path > 2) return fail(ACS_E_INVALID, "update_path = %u not in {0, 1, 2}",
+                                      p->update_path);
   return ACS_OK;
 }
 
@@ -168,7 +169,9 @@ int sync_and_check(acs_t *h) {
   HIP_TRY(hipStreamSynchronize(h->stream));
   uint32_t flags[2] = {0, 0};
   HIP_TRY(hipMemcpy(flags, h->ws + h->L.sync, sizeof flags, hipMemcpyDeviceToHost));
-  if (flags[1]) return fail(ACS_E_DEVICE, "grid barrier wait exhausted (flag %u)", flags[1]);
+  if (flags[1])
+    return fail(ACS_E_DEVICE, "a bounded device wait was exhausted (flag %u: 1 grid barrier, "
+                              "2 update ring)", flags[1]);
   return ACS_OK;
 }
 
@@ -373,7 +376,8 @@ int acs_iterate(acs_t *h, int32_t k) {
     it.it = h->iter + (uint32_t)i;
     HIP_TRY(hipEventRecord(h->ev[2 * i], h->stream));
     HIP_TRY(acs::launch_construct(h->dev, it, (int)h->p.mode, (int)h->p.memory,
-                                  h->p.lanes_per_ant ? (int)h->p.lanes_per_ant : 64, h->stream));
+                                  h->p.lanes_per_ant ? (int)h->p.lanes_per_ant : 64,
+                                  h->p.update_path == 2 ? 1 : 0, h->stream));
     HIP_TRY(hipEventRecord(h->ev[2 * i + 1], h->stream));
     HIP_TRY(acs::launch_best_global(h->dev, it, (int)h->p.memory, h->stream));
   }

@@ -60,9 +60,10 @@ hipError_t launch_init_pheromone(const Dev &d, float tau0, hipStream_t s);
 // Construction of all m tours.  mode 0 = synchronous steps (cooperative
 // persistent launch), 1 = asynchronous with atomic local updates, 2 =
 // asynchronous with plain stores.  lanes: lanes per ant of the asynchronous
-// dense kernels (64, 32 or 16; at least cl).
+// dense kernels (64, 32 or 16; at least cl).  queued: the one-ant-per-wave
+// dense kernel hands its local updates to an updater wave per block.
 hipError_t launch_construct(const Dev &d, const Iter &it, int mode, int memory, int lanes,
-                            hipStream_t s);
+                            int queued, hipStream_t s);
 // Largest m a synchronous launch can keep resident for this instance.
 int max_sync_ants(const Dev &d, int memory);
 hipError_t launch_best_global(const Dev &d, const Iter &it, int memory,

@@ -529,6 +529,126 @@ __global__ __launch_bounds__(1024) void k_construct_sync_dense(Dev D, Iter A) {
 }
 
 // ---------------------------------------------------------------------------
+// Local updates handed to an updater wave.  gfx950 counts loads, stores and
+// atomics of a wave in one in-order counter, so a wave that waits for its
+// next record also waits for every update it issued before that load.  With
+// the ring, an ant wave only writes (home, value read) pairs into LDS and
+// never waits for an atomic; one updater wave per block applies them.
+// Each ant wave owns a ring (single producer, single consumer): it writes
+// entries, then publishes its head; the updater applies entries, then
+// publishes its tail.  LDS instructions of one wave take effect in issue
+// order, so a published head covers entries already written, and a
+// published tail frees entries already read.  Every wait is bounded: on
+// exhaustion the error flag (2) is raised and the ant applies its update
+// itself, so every wave still reaches its end.
+// ---------------------------------------------------------------------------
+constexpr int kQAnts = 4;   // ant waves per block
+constexpr int kQRing = 64;  // entries per ring (power of 2)
+constexpr uint32_t kQSpin = 1u << 22;
+
+struct UpdRing {
+  uint4 ent[kQAnts][kQRing];  // {home lo, home hi, value read, 0}
+  uint32_t head[kQAnts];      // entries written by the ant wave
+  uint32_t tail[kQAnts];      // entries applied by the updater
+  uint32_t done;              // ant waves that have written their last entry
+};
+
+__device__ __forceinline__ uint32_t lds_ld(const uint32_t *p) {
+  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+}
+__device__ __forceinline__ void lds_st(uint32_t *p, uint32_t v) {
+  __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+}
+
+// Lanes 0 and 1 each hand over one update (home p, value read x).
+// `head` and `room` (entries known free) are the wave's own counters.
+template <bool ATOMIC>
+__device__ __forceinline__ uint32_t ring_push2(const Dev &D, const Iter &A, UpdRing &q, int w,
+                                               uint32_t &head, uint32_t &room, int lane,
+                                               float *p, float x) {
+  if (room < 2) {
+    uint32_t spins = 0;
+    while (true) {
+      room = kQRing - (head - uni((int)lds_ld(&q.tail[w])));
+      if (room >= 2) break;
+      __builtin_amdgcn_s_sleep(1);
+      if (++spins > kQSpin) {
+        // the updater does not drain: raise the flag, apply directly
+        if (lane == 0)
+          __hip_atomic_store(D.sync + 1, 2u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        uint32_t r = 0;
+        if (lane < 2) {
+          if (ATOMIC)
+            r = cas_apply(p, __float_as_uint(x), A.a_loc, A.b_loc);
+          else
+            __hip_atomic_store(p, fmaf(A.a_loc, x, A.b_loc), __ATOMIC_RELAXED,
+                               __HIP_MEMORY_SCOPE_AGENT);
+        }
+        return r;
+      }
+    }
+  }
+  if (lane < 2) {
+    const uint64_t a = reinterpret_cast<uint64_t>(p);
+    q.ent[w][(head + lane) & (kQRing - 1)] =
+        make_uint4((uint32_t)a, (uint32_t)(a >> 32), __float_as_uint(x), 0u);
+  }
+  head += 2;
+  room -= 2;
+  __atomic_signal_fence(__ATOMIC_SEQ_CST);
+  if (lane == 0) lds_st(&q.head[w], head);
+  return 0;
+}
+
+// The updater wave: applies the entries of every ring of its block until
+// all ant waves are done and every ring is empty.
+template <bool ATOMIC>
+__device__ __forceinline__ void ring_updater(const Dev &D, const Iter &A, UpdRing &q, int lane) {
+  uint32_t tl[kQAnts];
+#pragma unroll
+  for (int w = 0; w < kQAnts; ++w) tl[w] = 0;
+  uint32_t retries = 0, idle = 0;
+  while (true) {
+    // read `done` before the heads: an ant wave publishes its last head
+    // before it counts itself done
+    const uint32_t done = uni((int)lds_ld(&q.done));
+    __atomic_signal_fence(__ATOMIC_SEQ_CST);
+    bool any = false;
+#pragma unroll
+    for (int w = 0; w < kQAnts; ++w) {
+      const uint32_t h = uni((int)lds_ld(&q.head[w]));
+      if (h == tl[w]) continue;
+      any = true;
+      const uint32_t cnt = min(h - tl[w], 64u);
+      if ((uint32_t)lane < cnt) {
+        const uint4 e = q.ent[w][(tl[w] + lane) & (kQRing - 1)];
+        float *p = reinterpret_cast<float *>(((uint64_t)e.y << 32) | e.x);
+        if (ATOMIC)
+          retries += cas_apply(p, e.z, A.a_loc, A.b_loc);
+        else
+          __hip_atomic_store(p, fmaf(A.a_loc, __uint_as_float(e.z), A.b_loc), __ATOMIC_RELAXED,
+                             __HIP_MEMORY_SCOPE_AGENT);
+      }
+      tl[w] += cnt;
+      __atomic_signal_fence(__ATOMIC_SEQ_CST);
+      if (lane == 0) lds_st(&q.tail[w], tl[w]);
+    }
+    if (any) {
+      idle = 0;
+    } else {
+      if (done == kQAnts) break;
+      __builtin_amdgcn_s_sleep(1);
+      if (++idle > kQSpin) {
+        if (lane == 0)
+          __hip_atomic_store(D.sync + 1, 2u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        break;
+      }
+    }
+  }
+  if (retries) atomicAdd(&D.counters[6], (unsigned long long)retries);
+}
+
+// ---------------------------------------------------------------------------
 // Asynchronous construction, dense memory: one launch per iteration, one ant
 // per wave, no waiting for the other ants.  Each crossing gets the local
 // update of Eq. 3 as a compare-and-swap of the exact map on both directed
@@ -550,10 +670,13 @@ __global__ __launch_bounds__(1024) void k_construct_sync_dense(Dev D, Iter A) {
 // ATOMIC = false is the paper's unsynchronised variant (ACS-GPU-Alt,
 // Sec. 3.1.2): each entry gets the map of the value the ant read, by a plain
 // (not read-modify-write) store, and updates that race with it are lost.
+// QUEUE = true hands steps 2's updates to the block's updater wave instead.
 // ---------------------------------------------------------------------------
-template <bool ATOMIC>
+template <bool ATOMIC, bool QUEUE = false>
 __device__ __forceinline__ void ant_async_dense(const Dev &D, const Iter &A, int ant,
-                                                uint32_t *vis, int lane) {
+                                                uint32_t *vis, int lane, UpdRing *q = nullptr,
+                                                int qw = 0) {
+  uint32_t qhead = 0, qroom = kQRing;
   const int n = D.n, cl = D.cl, ldn = D.ldn;
   const int W = (n + 31) >> 5;
   const int kl = lane < cl ? lane : cl - 1;
@@ -590,7 +713,10 @@ __device__ __forceinline__ void ant_async_dense(const Dev &D, const Iter &A, int
       const uint64_t b = __ballot(lane < cl && rec.x == (uint32_t)prev);
       const int kr = b ? uni((int)__ffsll((unsigned long long)b) - 1) : -1;
       const float rval = kr >= 0 ? __uint_as_float(rdlane(rec.w, kr)) : fval;
-      if (ATOMIC) {
+      if (QUEUE) {
+        float *h = lane == 0 ? fwd : home(D, cur, prev, kr);
+        c_retry += ring_push2<ATOMIC>(D, A, *q, qw, qhead, qroom, lane, h, lane == 0 ? fval : rval);
+      } else if (ATOMIC) {
         if (lane == 0) {
           pptr = fwd;
           pexp = __float_as_uint(fval);
@@ -632,7 +758,9 @@ __device__ __forceinline__ void ant_async_dense(const Dev &D, const Iter &A, int
     const int k1 = cand_pos(D, cur, start, lane);
     const int k2 = cand_pos(D, start, cur, lane);
     float *h = lane == 0 ? home(D, cur, start, k1) : home(D, start, cur, k2);
-    if (lane < 2) {
+    if (QUEUE) {
+      c_retry += ring_push2<ATOMIC>(D, A, *q, qw, qhead, qroom, lane, h, tau_load(h));
+    } else if (lane < 2) {
       if (ATOMIC)
         c_retry += cas_apply(h, __float_as_uint(tau_load(h)), al, bl);
       else
@@ -656,6 +784,31 @@ __global__ __launch_bounds__(256) void k_construct_async_dense(Dev D, Iter A) {
   const int ant = uni(blockIdx.x * (blockDim.x >> 6) + wv);
   if (ant >= D.m) return;  // the whole wave leaves; no block-level sync below
   ant_async_dense<ATOMIC>(D, A, ant, smem + wv * ((D.n + 31) >> 5), lane);
+}
+
+// One instance, updates through the block's ring: waves 0..kQAnts-1 are
+// ants, wave kQAnts applies their updates.
+template <bool ATOMIC>
+__global__ __launch_bounds__(64 * (kQAnts + 1)) void k_construct_async_dense_q(Dev D, Iter A) {
+  extern __shared__ uint32_t smem[];
+  __shared__ UpdRing q;
+  const int lane = threadIdx.x & 63;
+  const int wv = threadIdx.x >> 6;
+  if (threadIdx.x < kQAnts) {
+    q.head[threadIdx.x] = 0;
+    q.tail[threadIdx.x] = 0;
+  }
+  if (threadIdx.x == 0) q.done = 0;
+  __syncthreads();
+  if (wv == kQAnts) {
+    ring_updater<ATOMIC>(D, A, q, lane);
+    return;
+  }
+  const int ant = uni(blockIdx.x * kQAnts + wv);
+  if (ant < D.m)
+    ant_async_dense<ATOMIC, true>(D, A, ant, smem + wv * ((D.n + 31) >> 5), lane, &q, wv);
+  __atomic_signal_fence(__ATOMIC_SEQ_CST);
+  if (lane == 0) atomicAdd(&q.done, 1u);
 }
 
 // Many instances in one launch: wave w builds the tour of ant items[w].y of
@@ -1588,7 +1741,7 @@ hipError_t launch_init_pheromone(const Dev &d, float tau0, hipStream_t s) {
 }
 
 hipError_t launch_construct(const Dev &d, const Iter &it, int mode, int memory, int lanes,
-                            hipStream_t s) {
+                            int queued, hipStream_t s) {
   if (mode == 0) {
     const int apb = kSyncBlock / 64;
     const int grid = (d.m + apb - 1) / apb;
@@ -1604,7 +1757,14 @@ hipError_t launch_construct(const Dev &d, const Iter &it, int mode, int memory, 
   const int grid = (d.m + apb - 1) / apb;
   const size_t lds = lds_bytes(d, kAsyncBlock);
   const bool atomic = mode == 1;
-  if (memory == 0 && lanes < 64) {
+  if (memory == 0 && lanes == 64 && queued) {
+    const dim3 gq((d.m + kQAnts - 1) / kQAnts), bq(64 * (kQAnts + 1));
+    const size_t lq = (size_t)kQAnts * ((d.n + 31) / 32) * sizeof(uint32_t);
+    if (atomic)
+      hipLaunchKernelGGL(k_construct_async_dense_q<true>, gq, bq, lq, s, d, it);
+    else
+      hipLaunchKernelGGL(k_construct_async_dense_q<false>, gq, bq, lq, s, d, it);
+  } else if (memory == 0 && lanes < 64) {
     const int g = 64 / lanes;
     const dim3 gg((d.m + apb * g - 1) / (apb * g));
     const size_t lg = lds * g;

@@ -491,6 +491,8 @@ ASYNC_FIRST = [
     ("racy_l64", dict(m=333), 64, "ASYNC_RACY"),
     ("spm_atomic", dict(cl=16, memory=1, spm_s=8), 0, "ASYNC_ATOMIC"),
     ("spm_racy", dict(cl=16, memory=1, spm_s=4, m=250), 0, "ASYNC_RACY"),
+    ("queued_atomic", dict(), -2, "ASYNC_ATOMIC"),
+    ("queued_racy_ragged", dict(m=333), -2, "ASYNC_RACY"),
 ]
 
 
@@ -501,7 +503,8 @@ def test_async_first_iteration_equals_oracle(acs, name, kw, lanes, mode):
     orc = oracle.Oracle(xy, seed=12, **kw)
     c = orc.constants()
     assert orc.local_map_k(c["tau0"], 1) == c["tau0"]
-    col = acs.Colony(xy, mode=getattr(acs, "ACS_" + mode), seed=12, lanes_per_ant=lanes, **kw)
+    gpu = dict(lanes_per_ant=lanes) if lanes >= 0 else dict(update_path=-lanes)
+    col = acs.Colony(xy, mode=getattr(acs, "ACS_" + mode), seed=12, **gpu, **kw)
     col.iterate(1)
     orc.iterate(1)
     assert np.array_equal(col.tours(), orc.tours())
@@ -569,3 +572,39 @@ def test_batch_grouped_single_ant_equals_oracle(acs, lanes):
             assert np.array_equal(b.tours(i), o.tours()), (i, it)
             assert np.array_equal(b.tau(i), o.tau()), (i, it)
     b.close()
+
+
+# ---------------------------------------------------------------------------
+# Local updates through the updater wave's LDS rings (update_path = 2).
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("mode", ["ASYNC_ATOMIC", "ASYNC_RACY"])
+def test_queued_single_ant_equals_oracle(acs, mode):
+    xy = inputs.uniform(280, 33)
+    col = acs.Colony(xy, m=1, mode=getattr(acs, "ACS_" + mode), seed=6, update_path=2)
+    orc = oracle.Oracle(xy, m=1, seed=6)
+    for it in range(6):
+        col.iterate(1)
+        orc.iterate(1)
+        _compare(col, orc, it)
+    col.close()
+
+
+@pytest.mark.parametrize("n,m,period", [(2392, 2392, 1), (30, 2000, 1), (1000, 1001, 3)])
+def test_queued_tours_valid(acs, n, m, period):
+    """Full size, heavy contention on a tiny instance (many updates of the
+    same entries at once) and a ragged ant count with a local-update period."""
+    _say(f"queued n={n} m={m} period={period}")
+    xy = inputs.uniform(n, 44)
+    col = acs.Colony(xy, m=m, cl=min(32, n - 1), mode=acs.ACS_ASYNC_ATOMIC, seed=7,
+                     update_path=2, local_update_period=period)
+    c = None
+    for it in range(3):
+        col.iterate(1)
+        tours, lens = col.tours(), col.lengths()
+        assert np.all(np.sort(tours, axis=1) == np.arange(n)[None, :])
+        assert np.array_equal(defs.tour_lengths(xy, tours), lens)
+        c = col.stats()
+        assert c["steps"] == (it + 1) * m * (n - 1)
+    tau = col.tau()
+    assert np.all(np.isfinite(tau)) and tau.min() >= np.float32(c["tau0"]) * np.float32(0.999)
+    col.close()
