@@ -98,6 +98,18 @@ __device__ __forceinline__ uint32_t wave_umax_u(uint32_t v) {
   return (uint32_t)__builtin_amdgcn_readfirstlane((int)v);
 }
 
+// Maximum over lanes 0..31 (lanes 32..63 hold no candidate when cl <= 32),
+// as a wave-uniform value.
+__device__ __forceinline__ uint32_t half_umax_u(uint32_t v) {
+  v = max(v, (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0xB1, 0xF, 0xF, false));
+  v = max(v, (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x4E, 0xF, 0xF, false));
+  v = max(v, (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x141, 0xF, 0xF, false));
+  v = max(v, (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x140, 0xF, 0xF, false));
+  const auto a = __builtin_amdgcn_permlane16_swap(v, v, false, false);
+  v = max(v, max((uint32_t)a[0], (uint32_t)a[1]));
+  return (uint32_t)__builtin_amdgcn_readfirstlane((int)v);
+}
+
 __device__ __forceinline__ uint32_t wave_umin_u(uint32_t v) {
   v = min(v, (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0xB1, 0xF, 0xF, false));
   v = min(v, (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x4E, 0xF, 0xF, false));
@@ -108,6 +120,14 @@ __device__ __forceinline__ uint32_t wave_umin_u(uint32_t v) {
   const auto b = __builtin_amdgcn_permlane32_swap(v, v, false, false);
   v = min(v, min((uint32_t)b[0], (uint32_t)b[1]));
   return (uint32_t)__builtin_amdgcn_readfirstlane((int)v);
+}
+
+// Marks city c visited in an LDS bitmap without waiting for the old word
+// (LDS operations of a wave take effect in issue order, so the next read of
+// the word sees the bit).
+__device__ __forceinline__ void mark(uint32_t *vis, int c) {
+  __hip_atomic_fetch_or(vis + (c >> 5), 1u << (c & 31), __ATOMIC_RELAXED,
+                        __HIP_MEMORY_SCOPE_WORKGROUP);
 }
 
 __device__ __forceinline__ uint32_t rdlane(uint32_t v, int k) {
@@ -349,7 +369,7 @@ __device__ __forceinline__ int pick_candidate(const Iter &A, int lane, int cl, C
   int k;
   if (q.x < A.q0_24) {
     // exploitation: maximum of tau * eta^beta, lowest position
-    const uint32_t mx = wave_umax_u(__float_as_uint(w));
+    const uint32_t mx = cl <= 32 ? half_umax_u(__float_as_uint(w)) : wave_umax_u(__float_as_uint(w));
     const uint64_t sel = __ballot(unv && __float_as_uint(w) == mx);
     k = (int)__ffsll((unsigned long long)sel) - 1;
     kind = 0;
@@ -385,30 +405,40 @@ __device__ __forceinline__ Pick select_dense(const Dev &D, const Iter &A, const 
     return p;
   }
   // Alg. 2, empty candidate set: greedy over every unvisited city, ties ->
-  // lowest index.  Each lane scans four consecutive cities per round; the
-  // loads of a round do not depend on the visited set (rows are padded to
-  // ldn), so unrolled rounds keep several loads in flight.
+  // lowest index.  Each lane scans four consecutive cities per round.  The
+  // loads of round r + 1 are issued before round r is examined (every round
+  // loads, at an address clamped into the padded row, so the number of loads
+  // in flight is fixed and the wait covers round r only).
   const float *trow = D.tau + (size_t)cur * D.ldn;
   const float *erow = D.etad + (size_t)cur * D.ldn;
   const uint16_t *drow = D.dist + (size_t)cur * D.ldn;
+  const int rounds = (n + 255) >> 8;
   float bv = 0.f, bt = 0.f;
   uint32_t bj = kNone, bd = 0;
-#pragma unroll 4
-  for (int j0 = 4 * lane; j0 < n; j0 += 256) {
-    float tq[4];
-    if (COHERENT) {
-#pragma unroll
-      for (int q = 0; q < 4; ++q) tq[q] = tau_load(trow + j0 + q);
-    } else {
-      const float4 tv = *reinterpret_cast<const float4 *>(trow + j0);
-      tq[0] = tv.x; tq[1] = tv.y; tq[2] = tv.z; tq[3] = tv.w;
-    }
-    const float4 ev = *reinterpret_cast<const float4 *>(erow + j0);
-    const ushort4 dv = *reinterpret_cast<const ushort4 *>(drow + j0);
+  float4 tv, ev;
+  ushort4 dv;
+  auto fetch = [&](int r, float4 &t4, float4 &e4, ushort4 &d4) {
+    const int j = min(4 * lane + 256 * r, D.ldn - 4);
+    if (COHERENT)
+      t4 = make_float4(tau_load(trow + j), tau_load(trow + j + 1), tau_load(trow + j + 2),
+                       tau_load(trow + j + 3));
+    else
+      t4 = *reinterpret_cast<const float4 *>(trow + j);
+    e4 = *reinterpret_cast<const float4 *>(erow + j);
+    d4 = *reinterpret_cast<const ushort4 *>(drow + j);
+  };
+  fetch(0, tv, ev, dv);
+  for (int r = 0; r < rounds; ++r) {
+    float4 tn, en;
+    ushort4 dn;
+    fetch(min(r + 1, rounds - 1), tn, en, dn);
+    const int j0 = 4 * lane + 256 * r;
+    uint32_t bits = (vis[min(j0, n - 1) >> 5] >> (j0 & 31)) & 0xfu;
+    if (j0 >= n) bits = 0xfu;
+    else if (j0 + 4 > n) bits |= (0xfu << (n - j0)) & 0xfu;
+    const float tq[4] = {tv.x, tv.y, tv.z, tv.w};
     const float eq[4] = {ev.x, ev.y, ev.z, ev.w};
     const uint32_t dq[4] = {dv.x, dv.y, dv.z, dv.w};
-    uint32_t bits = (vis[j0 >> 5] >> (j0 & 31)) & 0xfu;
-    if (j0 + 4 > n) bits |= (0xfu << (n - j0)) & 0xfu;
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
       const float v = tq[q] * eq[q];
@@ -416,6 +446,9 @@ __device__ __forceinline__ Pick select_dense(const Dev &D, const Iter &A, const 
         bv = v; bj = (uint32_t)(j0 + q); bt = tq[q]; bd = dq[q];
       }
     }
+    tv = tn;
+    ev = en;
+    dv = dn;
   }
   const uint32_t mx = wave_umax_u(bj == kNone ? 0u : __float_as_uint(bv));
   const uint32_t jn = wave_umin_u((bj != kNone && __float_as_uint(bv) == mx) ? bj : kNone);
@@ -494,7 +527,7 @@ __global__ __launch_bounds__(1024) void k_construct_sync_dense(Dev D, Iter A) {
       c_greedy += p.kind == 0;
       c_roul += p.kind == 1;
       if (p.kind == 2) { ++c_fb; c_fbu += (uint64_t)(n - t); }
-      if (lane == 0) vis[p.next >> 5] |= 1u << (p.next & 31);
+      if (lane == 0) mark(vis, p.next);
       tour_put(D, ant, t, lane, p.next, tb);
       len += p.d;
     }
@@ -742,7 +775,7 @@ __device__ __forceinline__ void ant_async_dense(const Dev &D, const Iter &A, int
     c_greedy += p.kind == 0;
     c_roul += p.kind == 1;
     if (p.kind == 2) { ++c_fb; c_fbu += (uint64_t)(n - t); }
-    if (lane == 0) vis[p.next >> 5] |= 1u << (p.next & 31);
+    if (lane == 0) mark(vis, p.next);
     tour_put(D, ant, t, lane, p.next, tb);
     len += p.d;
     // 4. record of the next city
@@ -1000,7 +1033,7 @@ __device__ __forceinline__ void ants_async_dense(const Dev &D, const Iter &A, in
     c_greedy += kind == 0;
     c_roul += kind == 1;
     if (kind == 2) { ++c_fb; c_fbu += (uint64_t)(n - t); }
-    if (gl == 0) vis[next >> 5] |= 1u << (next & 31);
+    if (gl == 0) mark(vis, next);
     tb = gl == (t & (L - 1)) ? next : tb;
     if ((t & (L - 1)) == L - 1 || t == n - 1) {
       const int tbase = t & ~(L - 1);
@@ -1300,7 +1333,7 @@ __global__ __launch_bounds__(1024) void k_construct_sync_spm(Dev D, Iter A) {
       c_greedy += p.kind == 0;
       c_roul += p.kind == 1;
       if (p.kind == 2) { ++c_fb; c_fbu += (uint64_t)(n - t); }
-      if (lane == 0) vis[p.next >> 5] |= 1u << (p.next & 31);
+      if (lane == 0) mark(vis, p.next);
       tour_put(D, ant, t, lane, p.next, tb);
       len += p.d;
       next = p.next;
@@ -1514,7 +1547,7 @@ __global__ __launch_bounds__(256) void k_construct_async_spm(Dev D, Iter A) {
     c_greedy += p.kind == 0;
     c_roul += p.kind == 1;
     if (p.kind == 2) { ++c_fb; c_fbu += (uint64_t)(n - t); }
-    if (lane == 0) vis[p.next >> 5] |= 1u << (p.next & 31);
+    if (lane == 0) mark(vis, p.next);
     tour_put(D, ant, t, lane, p.next, tb);
     len += p.d;
     rec = D.crec[(size_t)p.next * cl + kl];
