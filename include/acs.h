@@ -87,11 +87,11 @@ typedef struct acs_params {
                              0: 64 for one instance, chosen by timing for a
                              batch.  Never changes a decision, only how many
                              ants share a wavefront. */
-  uint32_t update_path;  /* asynchronous dense, one ant per wavefront: 0
-                            library default, 1 the ant wave issues its
-                            local updates itself, 2 the ant waves hand them
-                            to one updater wavefront per workgroup through
-                            LDS (the ant never waits for an atomic) */
+  uint32_t update_path;  /* asynchronous dense, one ant per wavefront: 1 the
+                            ant wave issues its local updates itself; 2 (and
+                            0, the default) the ant waves hand them to one
+                            updater wavefront per workgroup through LDS, so
+                            an ant never waits for an atomic */
 } acs_params;
 
 typedef struct acs_stats {

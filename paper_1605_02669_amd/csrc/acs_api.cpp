@@ -377,7 +377,7 @@ int acs_iterate(acs_t *h, int32_t k) {
     HIP_TRY(hipEventRecord(h->ev[2 * i], h->stream));
     HIP_TRY(acs::launch_construct(h->dev, it, (int)h->p.mode, (int)h->p.memory,
                                   h->p.lanes_per_ant ? (int)h->p.lanes_per_ant : 64,
-                                  h->p.update_path == 2 ? 1 : 0, h->stream));
+                                  h->p.update_path == 1 ? 0 : 1, h->stream));
     HIP_TRY(hipEventRecord(h->ev[2 * i + 1], h->stream));
     HIP_TRY(acs::launch_best_global(h->dev, it, (int)h->p.memory, h->stream));
   }

@@ -634,43 +634,44 @@ __device__ __forceinline__ uint32_t ring_push2(const Dev &D, const Iter &A, UpdR
 }
 
 // The updater wave: applies the entries of every ring of its block until
-// all ant waves are done and every ring is empty.
+// all ant waves are done and every ring is empty.  One pass gathers up to 16
+// pending entries of each ring onto its 64 lanes and applies them together
+// (one round of atomics per pass); with little pending it sleeps, so it
+// takes few issue slots from the ant waves that share its SIMD (a ring holds
+// many steps of slack).
 template <bool ATOMIC>
 __device__ __forceinline__ void ring_updater(const Dev &D, const Iter &A, UpdRing &q, int lane) {
-  uint32_t tl[kQAnts];
-#pragma unroll
-  for (int w = 0; w < kQAnts; ++w) tl[w] = 0;
+  static_assert(kQAnts * 16 == 64, "one pass covers 16 entries of each ring");
+  const int w = lane >> 4, slot = lane & 15;
+  uint32_t tl = 0;  // this lane's ring tail (lanes of a ring agree)
   uint32_t retries = 0, idle = 0;
   while (true) {
     // read `done` before the heads: an ant wave publishes its last head
     // before it counts itself done
     const uint32_t done = uni((int)lds_ld(&q.done));
     __atomic_signal_fence(__ATOMIC_SEQ_CST);
-    bool any = false;
-#pragma unroll
-    for (int w = 0; w < kQAnts; ++w) {
-      const uint32_t h = uni((int)lds_ld(&q.head[w]));
-      if (h == tl[w]) continue;
-      any = true;
-      const uint32_t cnt = min(h - tl[w], 64u);
-      if ((uint32_t)lane < cnt) {
-        const uint4 e = q.ent[w][(tl[w] + lane) & (kQRing - 1)];
-        float *p = reinterpret_cast<float *>(((uint64_t)e.y << 32) | e.x);
-        if (ATOMIC)
-          retries += cas_apply(p, e.z, A.a_loc, A.b_loc);
-        else
-          __hip_atomic_store(p, fmaf(A.a_loc, __uint_as_float(e.z), A.b_loc), __ATOMIC_RELAXED,
-                             __HIP_MEMORY_SCOPE_AGENT);
-      }
-      tl[w] += cnt;
-      __atomic_signal_fence(__ATOMIC_SEQ_CST);
-      if (lane == 0) lds_st(&q.tail[w], tl[w]);
+    const uint32_t h = lds_ld(&q.head[w]);
+    const uint32_t cnt = min(h - tl, 16u);
+    const bool any = __ballot(cnt > 0u) != 0;
+    if ((uint32_t)slot < cnt) {
+      const uint4 e = q.ent[w][(tl + slot) & (kQRing - 1)];
+      float *p = reinterpret_cast<float *>(((uint64_t)e.y << 32) | e.x);
+      if (ATOMIC)
+        retries += cas_apply(p, e.z, A.a_loc, A.b_loc);
+      else
+        __hip_atomic_store(p, fmaf(A.a_loc, __uint_as_float(e.z), A.b_loc), __ATOMIC_RELAXED,
+                           __HIP_MEMORY_SCOPE_AGENT);
     }
+    tl += cnt;
+    __atomic_signal_fence(__ATOMIC_SEQ_CST);
+    if (slot == 0 && cnt) lds_st(&q.tail[w], tl);
     if (any) {
       idle = 0;
+      // fewer than 4 pending entries in every ring: let them accumulate
+      if (__ballot(cnt >= 4u) == 0) __builtin_amdgcn_s_sleep(8);
     } else {
       if (done == kQAnts) break;
-      __builtin_amdgcn_s_sleep(1);
+      __builtin_amdgcn_s_sleep(8);
       if (++idle > kQSpin) {
         if (lane == 0)
           __hip_atomic_store(D.sync + 1, 2u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
@@ -710,6 +711,7 @@ __device__ __forceinline__ void ant_async_dense(const Dev &D, const Iter &A, int
                                                 uint32_t *vis, int lane, UpdRing *q = nullptr,
                                                 int qw = 0) {
   uint32_t qhead = 0, qroom = kQRing;
+  uint32_t uleft = A.lperiod;  // steps until the next local update
   const int n = D.n, cl = D.cl, ldn = D.ldn;
   const int W = (n + 31) >> 5;
   const int kl = lane < cl ? lane : cl - 1;
@@ -726,14 +728,22 @@ __device__ __forceinline__ void ant_async_dense(const Dev &D, const Iter &A, int
   float *fwd = nullptr;  // home of the forward entry of the previous move
   float fval = 0.f;      // its value as read by the selection
   int64_t len = 0;
-  uint32_t c_greedy = 0, c_roul = 0, c_fb = 0, c_retry = 0;
+  // decisions by kind, 21 bits each: greedy | roulette << 21 | fallback << 42
+  uint64_t c_kind = 0;
+  uint32_t c_retry = 0;
   uint64_t c_fbu = 0;
   // compare-and-swap in flight on lanes 0 (forward) and 1 (reverse)
   float *pptr = nullptr;
   unsigned int pexp = 0, pret = 0;
   bool pend = false;
 
-  for (int t = 1; t <= n; ++t) {
+  // steps in chunks of 64: a chunk's draws come from one Philox batch and
+  // its tour entries leave in one store, so no step tests for either
+  for (int t0 = 0; t0 <= n; t0 += 64) {
+  if (t0 > 0) draws = philox_batch(A, ant, t0, lane);
+  uint32_t clen = 0;  // at most 64 distances below 2^16 each
+  const int tend = min(t0 + 64, n + 1);
+  for (int t = t0 > 0 ? t0 : 1; t < tend; ++t) {
     // 1. the record of cur is needed now; so are last step's CAS results
     if (pend && pret != pexp) c_retry += 1 + cas_apply(pptr, pret, al, bl);
     pend = false;
@@ -742,7 +752,8 @@ __device__ __forceinline__ void ant_async_dense(const Dev &D, const Iter &A, int
     // no later wait for this record also waits for those updates
     __asm__ volatile("" ::"v"(c.w), "v"((int)c.unv));
     // 2. updates of the previous move (prev, cur), selected at step t - 1
-    if (t > 1 && (t - 1) % A.lperiod == 0) {
+    if (t > 1 && --uleft == 0) {
+      uleft = A.lperiod;
       const uint64_t b = __ballot(lane < cl && rec.x == (uint32_t)prev);
       const int kr = b ? uni((int)__ffsll((unsigned long long)b) - 1) : -1;
       const float rval = kr >= 0 ? __uint_as_float(rdlane(rec.w, kr)) : fval;
@@ -770,20 +781,22 @@ __device__ __forceinline__ void ant_async_dense(const Dev &D, const Iter &A, int
     }
     if (t == n) break;
     // 3. selection
-    if ((t & 63) == 0) draws = philox_batch(A, ant, t, lane);
     const Pick p = select_dense<false>(D, A, vis, cur, lane, rec, c, draw_of(draws, t));
-    c_greedy += p.kind == 0;
-    c_roul += p.kind == 1;
-    if (p.kind == 2) { ++c_fb; c_fbu += (uint64_t)(n - t); }
+    c_kind += 1ull << (21 * p.kind);
+    if (p.kind == 2) c_fbu += (uint64_t)(n - t);
     if (lane == 0) mark(vis, p.next);
-    tour_put(D, ant, t, lane, p.next, tb);
-    len += p.d;
+    tb = lane == t - t0 ? p.next : tb;
+    clen += p.d;
     // 4. record of the next city
     rec = D.crec[(size_t)p.next * cl + kl];
     fwd = home(D, cur, p.next, p.k);
     fval = p.tval;
     prev = cur;
     cur = p.next;
+  }
+  len += clen;
+  // tour entries t0 .. min(t0 + 63, n - 1) of this chunk
+  if (t0 < n && lane <= min(63, n - 1 - t0)) D.tours[(size_t)ant * n + t0 + lane] = tb;
   }
   if (pend && pret != pexp) c_retry += 1 + cas_apply(pptr, pret, al, bl);
   // closing edge: both entries, read fresh (once per ant)
@@ -805,7 +818,9 @@ __device__ __forceinline__ void ant_async_dense(const Dev &D, const Iter &A, int
   c_retry = (uint32_t)uni((int)(rdlane(c_retry, 0) + rdlane(c_retry, 1)));
   if (lane == 0) {
     D.lens[ant] = len;
-    add_counters(D, c_greedy, c_roul, c_fb, c_fbu, c_retry);
+    const uint32_t m21 = (1u << 21) - 1;
+    add_counters(D, (uint32_t)c_kind & m21, (uint32_t)(c_kind >> 21) & m21,
+                 (uint32_t)(c_kind >> 42) & m21, c_fbu, c_retry);
   }
 }
 
