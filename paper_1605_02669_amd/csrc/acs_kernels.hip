@@ -580,7 +580,8 @@ constexpr int kQRing = 64;  // entries per ring (power of 2)
 constexpr uint32_t kQSpin = 1u << 22;
 
 struct UpdRing {
-  uint4 ent[kQAnts][kQRing];  // {home lo, home hi, value read, 0}
+  uint4 ent[kQAnts][kQRing];  // {u | v << 16, candidate position of v in u's list or -1,
+                              //  value read, 0}: the entry (u, v)
   uint32_t head[kQAnts];      // entries written by the ant wave
   uint32_t tail[kQAnts];      // entries applied by the updater
   uint32_t done;              // ant waves that have written their last entry
@@ -593,12 +594,13 @@ __device__ __forceinline__ void lds_st(uint32_t *p, uint32_t v) {
   __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
 }
 
-// Lanes 0 and 1 each hand over one update (home p, value read x).
-// `head` and `room` (entries known free) are the wave's own counters.
+// Lanes 0 and 1 each hand over one update: entry (u, v), v the k-th
+// candidate of u (k = -1 if it is none), value read x.  `head` and `room`
+// (entries known free) are the wave's own counters.
 template <bool ATOMIC>
 __device__ __forceinline__ uint32_t ring_push2(const Dev &D, const Iter &A, UpdRing &q, int w,
-                                               uint32_t &head, uint32_t &room, int lane,
-                                               float *p, float x) {
+                                               uint32_t &head, uint32_t &room, int lane, int u,
+                                               int v, int k, float x) {
   if (room < 2) {
     uint32_t spins = 0;
     while (true) {
@@ -610,6 +612,7 @@ __device__ __forceinline__ uint32_t ring_push2(const Dev &D, const Iter &A, UpdR
         if (lane == 0)
           __hip_atomic_store(D.sync + 1, 2u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         uint32_t r = 0;
+        float *p = home(D, u, v, k);
         if (lane < 2) {
           if (ATOMIC)
             r = cas_apply(p, __float_as_uint(x), A.a_loc, A.b_loc);
@@ -621,11 +624,9 @@ __device__ __forceinline__ uint32_t ring_push2(const Dev &D, const Iter &A, UpdR
       }
     }
   }
-  if (lane < 2) {
-    const uint64_t a = reinterpret_cast<uint64_t>(p);
+  if (lane < 2)
     q.ent[w][(head + lane) & (kQRing - 1)] =
-        make_uint4((uint32_t)a, (uint32_t)(a >> 32), __float_as_uint(x), 0u);
-  }
+        make_uint4((uint32_t)u | ((uint32_t)v << 16), (uint32_t)k, __float_as_uint(x), 0u);
   head += 2;
   room -= 2;
   __atomic_signal_fence(__ATOMIC_SEQ_CST);
@@ -655,7 +656,7 @@ __device__ __forceinline__ void ring_updater(const Dev &D, const Iter &A, UpdRin
     const bool any = __ballot(cnt > 0u) != 0;
     if ((uint32_t)slot < cnt) {
       const uint4 e = q.ent[w][(tl + slot) & (kQRing - 1)];
-      float *p = reinterpret_cast<float *>(((uint64_t)e.y << 32) | e.x);
+      float *p = home(D, (int)(e.x & 0xffffu), (int)(e.x >> 16), (int)e.y);
       if (ATOMIC)
         retries += cas_apply(p, e.z, A.a_loc, A.b_loc);
       else
@@ -726,6 +727,7 @@ __device__ __forceinline__ void ant_async_dense(const Dev &D, const Iter &A, int
 
   int cur = start, prev = -1;
   float *fwd = nullptr;  // home of the forward entry of the previous move
+  int fk = -1;           // its candidate position
   float fval = 0.f;      // its value as read by the selection
   int64_t len = 0;
   // decisions by kind, 21 bits each: greedy | roulette << 21 | fallback << 42
@@ -758,8 +760,9 @@ __device__ __forceinline__ void ant_async_dense(const Dev &D, const Iter &A, int
       const int kr = b ? uni((int)__ffsll((unsigned long long)b) - 1) : -1;
       const float rval = kr >= 0 ? __uint_as_float(rdlane(rec.w, kr)) : fval;
       if (QUEUE) {
-        float *h = lane == 0 ? fwd : home(D, cur, prev, kr);
-        c_retry += ring_push2<ATOMIC>(D, A, *q, qw, qhead, qroom, lane, h, lane == 0 ? fval : rval);
+        c_retry += ring_push2<ATOMIC>(D, A, *q, qw, qhead, qroom, lane, lane == 0 ? prev : cur,
+                                      lane == 0 ? cur : prev, lane == 0 ? fk : kr,
+                                      lane == 0 ? fval : rval);
       } else if (ATOMIC) {
         if (lane == 0) {
           pptr = fwd;
@@ -789,7 +792,8 @@ __device__ __forceinline__ void ant_async_dense(const Dev &D, const Iter &A, int
     clen += p.d;
     // 4. record of the next city
     rec = D.crec[(size_t)p.next * cl + kl];
-    fwd = home(D, cur, p.next, p.k);
+    if (!QUEUE) fwd = home(D, cur, p.next, p.k);
+    fk = p.k;
     fval = p.tval;
     prev = cur;
     cur = p.next;
@@ -805,7 +809,8 @@ __device__ __forceinline__ void ant_async_dense(const Dev &D, const Iter &A, int
     const int k2 = cand_pos(D, start, cur, lane);
     float *h = lane == 0 ? home(D, cur, start, k1) : home(D, start, cur, k2);
     if (QUEUE) {
-      c_retry += ring_push2<ATOMIC>(D, A, *q, qw, qhead, qroom, lane, h, tau_load(h));
+      c_retry += ring_push2<ATOMIC>(D, A, *q, qw, qhead, qroom, lane, lane == 0 ? cur : start,
+                                    lane == 0 ? start : cur, lane == 0 ? k1 : k2, tau_load(h));
     } else if (lane < 2) {
       if (ATOMIC)
         c_retry += cas_apply(h, __float_as_uint(tau_load(h)), al, bl);
