@@ -46,7 +46,7 @@ size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
 
 // Device buffers of one handle, as offsets into one allocation.
 struct Layout {
-  size_t xy, dist, crec, cand, eta, tau, etad, spm, spm_tail, upd_rec, upd_nb, upd_lead, tours, lens,
+  size_t xy, dist, crec, cand, eta, tau, etad, rpos, spm, spm_tail, upd_rec, upd_nb, upd_lead, tours, lens,
       best, gstate, counters, sync, dmax, lnn, total;
 };
 
@@ -68,6 +68,7 @@ Layout make_layout(int n, int m, int cl, int ldn, int memory, int s) {
   if (memory == ACS_DENSE) {
     L.tau = take(sizeof(float) * (size_t)n * ldn);
     L.etad = take(sizeof(float) * (size_t)n * ldn);
+    L.rpos = take(sizeof(int8_t) * (size_t)n * cl);
   } else {
     L.spm = take(sizeof(uint32_t) * 2 * (size_t)n * s);
     L.spm_tail = take(sizeof(uint32_t) * (size_t)n);
@@ -331,6 +332,7 @@ int acs_create(const double *coords_xy, int32_t n, const acs_params *p, acs_t **
   if (p->memory == ACS_DENSE) {
     d.tau = reinterpret_cast<float *>(w + h->L.tau);
     d.etad = reinterpret_cast<const float *>(w + h->L.etad);
+    d.rpos = reinterpret_cast<const int8_t *>(w + h->L.rpos);
   } else {
     d.spm = reinterpret_cast<uint2 *>(w + h->L.spm);
     d.spm_tail = reinterpret_cast<uint32_t *>(w + h->L.spm_tail);

@@ -21,6 +21,8 @@ struct Dev {
   const float *eta_tab;    // eta^beta indexed by distance (dmax + 1)
   float *tau;              // dense: n x ldn, home of non-candidate entries
   const float *etad;       // dense: n x ldn, eta^beta(d(i, j))
+  const int8_t *rpos;      // dense: n x cl, position of i in the candidate list
+                           //   of its k-th candidate, -1 if i is not in it
   // selective pheromone memory (Sec. 3.2): the record of city i is s pairs
   // {neighbour (-1 = empty slot), pheromone bits}; spm_tail[i] counts the
   // inserts (the most recently added slot is spm_tail[i] mod s)

@@ -297,6 +297,19 @@ __global__ __launch_bounds__(256) void k_etad(Dev D) {
   const_cast<float *>(D.etad)[e] = D.eta_tab[D.dist[e]];
 }
 
+// Reverse positions: for candidate k of city i (j = cand[i][k]), the position
+// of i in j's candidate list, -1 if i is not a candidate of j.
+__global__ __launch_bounds__(256) void k_rpos(Dev D) {
+  const int e = blockIdx.x * 256 + threadIdx.x;
+  if (e >= D.n * D.cl) return;
+  const int i = e / D.cl;
+  const uint32_t j = D.crec[e].x;
+  int r = -1;
+  for (int k = 0; k < D.cl && r < 0; ++k)
+    if (D.crec[(size_t)j * D.cl + k].x == (uint32_t)i) r = k;
+  const_cast<int8_t *>(D.rpos)[e] = (int8_t)r;
+}
+
 __global__ __launch_bounds__(256) void k_init(Dev D, float tau0) {
   const size_t e = (size_t)blockIdx.x * 256 + threadIdx.x;
   const size_t nd = (size_t)D.n * D.ldn;
@@ -580,8 +593,9 @@ constexpr int kQRing = 64;  // entries per ring (power of 2)
 constexpr uint32_t kQSpin = 1u << 22;
 
 struct UpdRing {
-  uint4 ent[kQAnts][kQRing];  // {u | v << 16, candidate position of v in u's list or -1,
-                              //  value read, 0}: the entry (u, v)
+  uint4 ent[kQAnts][kQRing];  // crossings u -> v: {u | v << 16, position of v in u's
+                              //  list or -1, value of (u, v) read, reverse position
+                              //  (see reverse_pos)}
   uint32_t head[kQAnts];      // entries written by the ant wave
   uint32_t tail[kQAnts];      // entries applied by the updater
   uint32_t done;              // ant waves that have written their last entry
@@ -594,41 +608,57 @@ __device__ __forceinline__ void lds_st(uint32_t *p, uint32_t v) {
   __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
 }
 
-// Lanes 0 and 1 each hand over one update: entry (u, v), v the k-th
-// candidate of u (k = -1 if it is none), value read x.  `head` and `room`
-// (entries known free) are the wave's own counters.
+// Position of u in the candidate list of v for the crossing u -> v (v the
+// k-th candidate of u, k = -1 if none): `kr` if the ant found it (-1: u is
+// not a candidate of v), or, for kr = -2, the reverse table.
+__device__ __forceinline__ int reverse_pos(const Dev &D, int u, int k, int kr) {
+  return kr != -2 ? kr : (int)D.rpos[(size_t)u * D.cl + k];
+}
+
+// Eq. 3 on both directed entries of the crossed edge {u, v}: lane 0 the
+// forward entry (u, v), lane 1 the reverse entry (v, u), each with x, the
+// pheromone of (u, v) the ant read, as the expected value (the two entries
+// of an edge always receive the same maps, so they hold the same value once
+// the updates in flight have landed; a compare-and-swap that finds another
+// value retries with it).  Returns the retries.
 template <bool ATOMIC>
-__device__ __forceinline__ uint32_t ring_push2(const Dev &D, const Iter &A, UpdRing &q, int w,
-                                               uint32_t &head, uint32_t &room, int lane, int u,
-                                               int v, int k, float x) {
-  if (room < 2) {
+__device__ __forceinline__ uint32_t apply_crossing(const Dev &D, const Iter &A, int lane, int u,
+                                                   int v, int k, int kr, float x) {
+  if (lane > 1) return 0;
+  float *p = lane == 0 ? home(D, u, v, k) : home(D, v, u, reverse_pos(D, u, k, kr));
+  if (ATOMIC) return cas_apply(p, __float_as_uint(x), A.a_loc, A.b_loc);
+  __hip_atomic_store(p, fmaf(A.a_loc, x, A.b_loc), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  return 0;
+}
+
+// Lane 0 hands over the local update of one crossing: the move u -> v, v
+// the k-th candidate of u (k = -1 if it is none), kr as for reverse_pos, x
+// the pheromone of (u, v) as the ant read it.  The updater applies the map to both directed entries
+// of the edge.  `head` and `room` (entries known free) are the wave's own.
+template <bool ATOMIC>
+__device__ __forceinline__ uint32_t ring_push(const Dev &D, const Iter &A, UpdRing &q, int w,
+                                              uint32_t &head, uint32_t &room, int lane, int u,
+                                              int v, int k, int kr, float x) {
+  if (room < 1) {
     uint32_t spins = 0;
     while (true) {
       room = kQRing - (head - uni((int)lds_ld(&q.tail[w])));
-      if (room >= 2) break;
+      if (room >= 1) break;
       __builtin_amdgcn_s_sleep(1);
       if (++spins > kQSpin) {
         // the updater does not drain: raise the flag, apply directly
         if (lane == 0)
           __hip_atomic_store(D.sync + 1, 2u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        uint32_t r = 0;
-        float *p = home(D, u, v, k);
-        if (lane < 2) {
-          if (ATOMIC)
-            r = cas_apply(p, __float_as_uint(x), A.a_loc, A.b_loc);
-          else
-            __hip_atomic_store(p, fmaf(A.a_loc, x, A.b_loc), __ATOMIC_RELAXED,
-                               __HIP_MEMORY_SCOPE_AGENT);
-        }
-        return r;
+        return apply_crossing<ATOMIC>(D, A, lane, u, v, k, kr, x);
       }
     }
   }
-  if (lane < 2)
-    q.ent[w][(head + lane) & (kQRing - 1)] =
-        make_uint4((uint32_t)u | ((uint32_t)v << 16), (uint32_t)k, __float_as_uint(x), 0u);
-  head += 2;
-  room -= 2;
+  if (lane == 0)
+    q.ent[w][head & (kQRing - 1)] =
+        make_uint4((uint32_t)u | ((uint32_t)v << 16), (uint32_t)k, __float_as_uint(x),
+                   (uint32_t)kr);
+  head += 1;
+  room -= 1;
   __atomic_signal_fence(__ATOMIC_SEQ_CST);
   if (lane == 0) lds_st(&q.head[w], head);
   return 0;
@@ -656,12 +686,17 @@ __device__ __forceinline__ void ring_updater(const Dev &D, const Iter &A, UpdRin
     const bool any = __ballot(cnt > 0u) != 0;
     if ((uint32_t)slot < cnt) {
       const uint4 e = q.ent[w][(tl + slot) & (kQRing - 1)];
-      float *p = home(D, (int)(e.x & 0xffffu), (int)(e.x >> 16), (int)e.y);
-      if (ATOMIC)
-        retries += cas_apply(p, e.z, A.a_loc, A.b_loc);
-      else
-        __hip_atomic_store(p, fmaf(A.a_loc, __uint_as_float(e.z), A.b_loc), __ATOMIC_RELAXED,
-                           __HIP_MEMORY_SCOPE_AGENT);
+      const int u = (int)(e.x & 0xffffu), v = (int)(e.x >> 16), k = (int)e.y;
+      float *pf = home(D, u, v, k);
+      float *pr = home(D, v, u, reverse_pos(D, u, k, (int)e.w));
+      if (ATOMIC) {
+        retries += cas_apply(pf, e.z, A.a_loc, A.b_loc);
+        retries += cas_apply(pr, e.z, A.a_loc, A.b_loc);
+      } else {
+        const float y = fmaf(A.a_loc, __uint_as_float(e.z), A.b_loc);
+        __hip_atomic_store(pf, y, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        __hip_atomic_store(pr, y, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      }
     }
     tl += cnt;
     __atomic_signal_fence(__ATOMIC_SEQ_CST);
@@ -754,16 +789,23 @@ __device__ __forceinline__ void ant_async_dense(const Dev &D, const Iter &A, int
     // no later wait for this record also waits for those updates
     __asm__ volatile("" ::"v"(c.w), "v"((int)c.unv));
     // 2. updates of the previous move (prev, cur), selected at step t - 1
-    if (t > 1 && --uleft == 0) {
+    if (QUEUE && t > 1 && --uleft == 0) {
+      uleft = A.lperiod;
+      // the reverse position comes from the table, except after a fallback
+      // move (cur is not a candidate of prev, so the table has no entry):
+      // then from cur's record
+      int kr = -2;
+      if (fk < 0) {
+        const uint64_t b = __ballot(lane < cl && rec.x == (uint32_t)prev);
+        kr = b ? uni((int)__ffsll((unsigned long long)b) - 1) : -1;
+      }
+      c_retry += ring_push<ATOMIC>(D, A, *q, qw, qhead, qroom, lane, prev, cur, fk, kr, fval);
+    } else if (!QUEUE && t > 1 && --uleft == 0) {
       uleft = A.lperiod;
       const uint64_t b = __ballot(lane < cl && rec.x == (uint32_t)prev);
       const int kr = b ? uni((int)__ffsll((unsigned long long)b) - 1) : -1;
       const float rval = kr >= 0 ? __uint_as_float(rdlane(rec.w, kr)) : fval;
-      if (QUEUE) {
-        c_retry += ring_push2<ATOMIC>(D, A, *q, qw, qhead, qroom, lane, lane == 0 ? prev : cur,
-                                      lane == 0 ? cur : prev, lane == 0 ? fk : kr,
-                                      lane == 0 ? fval : rval);
-      } else if (ATOMIC) {
+      if (ATOMIC) {
         if (lane == 0) {
           pptr = fwd;
           pexp = __float_as_uint(fval);
@@ -809,8 +851,8 @@ __device__ __forceinline__ void ant_async_dense(const Dev &D, const Iter &A, int
     const int k2 = cand_pos(D, start, cur, lane);
     float *h = lane == 0 ? home(D, cur, start, k1) : home(D, start, cur, k2);
     if (QUEUE) {
-      c_retry += ring_push2<ATOMIC>(D, A, *q, qw, qhead, qroom, lane, lane == 0 ? cur : start,
-                                    lane == 0 ? start : cur, lane == 0 ? k1 : k2, tau_load(h));
+      c_retry += ring_push<ATOMIC>(D, A, *q, qw, qhead, qroom, lane, cur, start, k1, k2,
+                                   __uint_as_float(rdlane(__float_as_uint(tau_load(h)), 0)));
     } else if (lane < 2) {
       if (ATOMIC)
         c_retry += cas_apply(h, __float_as_uint(tau_load(h)), al, bl);
@@ -1780,6 +1822,11 @@ hipError_t launch_crec(const Dev &d, const int32_t *cand_tmp, float tau0, hipStr
 }
 
 hipError_t launch_init_pheromone(const Dev &d, float tau0, hipStream_t s) {
+  if (d.rpos) {
+    hipLaunchKernelGGL(k_rpos, dim3((d.n * d.cl + 255) / 256), dim3(256), 0, s, d);
+    const hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+  }
   if (d.etad) {
     const size_t total = (size_t)d.n * d.ldn;
     hipLaunchKernelGGL(k_etad, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, s, d);
