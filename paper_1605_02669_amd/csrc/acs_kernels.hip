@@ -22,6 +22,7 @@
 // sequence of IEEE operations; fmaf is used only for the pheromone maps.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <climits>
 
 #include "acs_internal.hpp"
@@ -588,7 +589,7 @@ __global__ __launch_bounds__(1024) void k_construct_sync_dense(Dev D, Iter A) {
 // exhaustion the error flag (2) is raised and the ant applies its update
 // itself, so every wave still reaches its end.
 // ---------------------------------------------------------------------------
-constexpr int kQAnts = 4;   // ant waves per block
+constexpr int kQAnts = 8;   // at most this many ant waves per block
 constexpr int kQRing = 64;  // entries per ring (power of 2)
 constexpr uint32_t kQSpin = 1u << 22;
 
@@ -665,15 +666,16 @@ __device__ __forceinline__ uint32_t ring_push(const Dev &D, const Iter &A, UpdRi
 }
 
 // The updater wave: applies the entries of every ring of its block until
-// all ant waves are done and every ring is empty.  One pass gathers up to 16
-// pending entries of each ring onto its 64 lanes and applies them together
-// (one round of atomics per pass); with little pending it sleeps, so it
-// takes few issue slots from the ant waves that share its SIMD (a ring holds
-// many steps of slack).
+// all `na` ant waves are done and every ring is empty.  One pass gathers
+// up to 8 pending entries of each ring onto its 64 lanes and applies them
+// together (one round of atomics per pass); with little pending it sleeps,
+// so it takes few issue slots from the ant waves that share its SIMD (a
+// ring holds many steps of slack).
 template <bool ATOMIC>
-__device__ __forceinline__ void ring_updater(const Dev &D, const Iter &A, UpdRing &q, int lane) {
-  static_assert(kQAnts * 16 == 64, "one pass covers 16 entries of each ring");
-  const int w = lane >> 4, slot = lane & 15;
+__device__ __forceinline__ void ring_updater(const Dev &D, const Iter &A, UpdRing &q, int lane,
+                                             int na) {
+  static_assert(kQAnts * 8 == 64, "one pass covers 8 entries of each ring");
+  const int w = lane >> 3, slot = lane & 7;
   uint32_t tl = 0;  // this lane's ring tail (lanes of a ring agree)
   uint32_t retries = 0, idle = 0;
   while (true) {
@@ -681,8 +683,8 @@ __device__ __forceinline__ void ring_updater(const Dev &D, const Iter &A, UpdRin
     // before it counts itself done
     const uint32_t done = uni((int)lds_ld(&q.done));
     __atomic_signal_fence(__ATOMIC_SEQ_CST);
-    const uint32_t h = lds_ld(&q.head[w]);
-    const uint32_t cnt = min(h - tl, 16u);
+    const uint32_t h = w < na ? lds_ld(&q.head[w]) : tl;
+    const uint32_t cnt = min(h - tl, 8u);
     const bool any = __ballot(cnt > 0u) != 0;
     if ((uint32_t)slot < cnt) {
       const uint4 e = q.ent[w][(tl + slot) & (kQRing - 1)];
@@ -704,10 +706,10 @@ __device__ __forceinline__ void ring_updater(const Dev &D, const Iter &A, UpdRin
     if (any) {
       idle = 0;
       // fewer than 4 pending entries in every ring: let them accumulate
-      if (__ballot(cnt >= 4u) == 0) __builtin_amdgcn_s_sleep(8);
+      if (__ballot(cnt >= 4u) == 0) __builtin_amdgcn_s_sleep(16);
     } else {
-      if (done == kQAnts) break;
-      __builtin_amdgcn_s_sleep(8);
+      if (done == (uint32_t)na) break;
+      __builtin_amdgcn_s_sleep(16);
       if (++idle > kQSpin) {
         if (lane == 0)
           __hip_atomic_store(D.sync + 1, 2u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
@@ -881,25 +883,28 @@ __global__ __launch_bounds__(256) void k_construct_async_dense(Dev D, Iter A) {
   ant_async_dense<ATOMIC>(D, A, ant, smem + wv * ((D.n + 31) >> 5), lane);
 }
 
-// One instance, updates through the block's ring: waves 0..kQAnts-1 are
-// ants, wave kQAnts applies their updates.
+// One instance, updates through the block's rings: waves 0..na-1 are ants
+// blockIdx.x * na + wave, wave na (the last) applies their updates.  The
+// host picks na so that every compute unit holds about the same number of
+// ants (the slowest unit sets the iteration time).
 template <bool ATOMIC>
 __global__ __launch_bounds__(64 * (kQAnts + 1)) void k_construct_async_dense_q(Dev D, Iter A) {
   extern __shared__ uint32_t smem[];
   __shared__ UpdRing q;
   const int lane = threadIdx.x & 63;
   const int wv = threadIdx.x >> 6;
+  const int na = (int)(blockDim.x >> 6) - 1;
   if (threadIdx.x < kQAnts) {
     q.head[threadIdx.x] = 0;
     q.tail[threadIdx.x] = 0;
   }
   if (threadIdx.x == 0) q.done = 0;
   __syncthreads();
-  if (wv == kQAnts) {
-    ring_updater<ATOMIC>(D, A, q, lane);
+  if (wv == na) {
+    ring_updater<ATOMIC>(D, A, q, lane, na);
     return;
   }
-  const int ant = uni(blockIdx.x * kQAnts + wv);
+  const int ant = uni(blockIdx.x * na + wv);
   if (ant < D.m)
     ant_async_dense<ATOMIC, true>(D, A, ant, smem + wv * ((D.n + 31) >> 5), lane, &q, wv);
   __atomic_signal_fence(__ATOMIC_SEQ_CST);
@@ -1858,8 +1863,17 @@ hipError_t launch_construct(const Dev &d, const Iter &it, int mode, int memory, 
   const size_t lds = lds_bytes(d, kAsyncBlock);
   const bool atomic = mode == 1;
   if (memory == 0 && lanes == 64 && queued) {
-    const dim3 gq((d.m + kQAnts - 1) / kQAnts), bq(64 * (kQAnts + 1));
-    const size_t lq = (size_t)kQAnts * ((d.n + 31) / 32) * sizeof(uint32_t);
+    // ants per block: spread the m ants evenly over the compute units, two
+    // or more blocks per unit, at most kQAnts per block
+    int dev = 0, cus = 256;
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
+      return hipErrorInvalidDevice;
+    const int per_cu = (d.m + cus - 1) / cus;
+    const int bpc = std::max(2, (per_cu + kQAnts - 1) / kQAnts);
+    const int na = std::max(1, std::min(kQAnts, (d.m + cus * bpc - 1) / (cus * bpc)));
+    const dim3 gq((d.m + na - 1) / na), bq(64 * (na + 1));
+    const size_t lq = (size_t)na * ((d.n + 31) / 32) * sizeof(uint32_t);
     if (atomic)
       hipLaunchKernelGGL(k_construct_async_dense_q<true>, gq, bq, lq, s, d, it);
     else
