@@ -1003,20 +1003,30 @@ __device__ __forceinline__ void ants_async_dense(const Dev &D, const Iter &A, in
   float *fwd = nullptr;
   float fval = 0.f;
   int64_t len = 0;
-  uint32_t c_greedy = 0, c_roul = 0, c_fb = 0, c_retry = 0;
+  uint64_t c_kind = 0;  // greedy | roulette << 21 | fallback << 42
+  uint32_t c_retry = 0;
   uint64_t c_fbu = 0;
   float *pptr = nullptr;
   unsigned int pexp = 0, pret = 0;
   bool pend = false;
+  uint32_t uleft = A.lperiod;
 
-  for (int t = 1; t <= n; ++t) {
+  // chunks of L steps: one Philox batch and one tour store per chunk
+  for (int t0 = 0; t0 <= n; t0 += L) {
+  if (t0 > 0)
+    draws = philox10(make_uint4((uint32_t)(t0 + gl), (uint32_t)ant, A.it, A.instance), A.key0,
+                     A.key1);
+  uint32_t clen = 0;
+  const int tend = min(t0 + L, n + 1);
+  for (int t = t0 > 0 ? t0 : 1; t < tend; ++t) {
     if (ATOMIC && pend && pret != pexp) c_retry += 1 + cas_apply(pptr, pret, al, bl);
     pend = false;
     const uint32_t word = vis[rec.x >> 5];
     const bool unv = (gl < cl) & !((word >> (rec.x & 31)) & 1u);
     const float w = unv ? __uint_as_float(rec.w) * __uint_as_float(rec.z) : 0.f;
     __asm__ volatile("" ::"v"(w), "v"((int)unv));
-    if (t > 1 && (t - 1) % A.lperiod == 0) {
+    if (t > 1 && --uleft == 0) {
+      uleft = A.lperiod;
       const uint32_t b = grp_bits<L>(__ballot(gl < cl && rec.x == (uint32_t)prev), base);
       const int kr = b ? __builtin_ctz(b) : -1;
       const float rval = kr >= 0 ? __uint_as_float(grp_read(rec.w, base, kr)) : fval;
@@ -1035,11 +1045,8 @@ __device__ __forceinline__ void ants_async_dense(const Dev &D, const Iter &A, in
       }
     }
     if (t == n) break;
-    if ((t & (L - 1)) == 0)
-      draws = philox10(make_uint4((uint32_t)(t + gl), (uint32_t)ant, A.it, A.instance), A.key0,
-                       A.key1);
-    const uint32_t q24 = grp_read(draws.x, base, t & (L - 1)) >> 8;
-    const uint32_t u24 = grp_read(draws.y, base, t & (L - 1)) >> 8;
+    const uint32_t q24 = grp_read(draws.x, base, t - t0) >> 8;
+    const uint32_t u24 = grp_read(draws.y, base, t - t0) >> 8;
     const uint32_t umask = grp_bits<L>(__ballot(unv), base);
     int next, kind, k = -1;
     uint32_t d;
@@ -1097,21 +1104,19 @@ __device__ __forceinline__ void ants_async_dense(const Dev &D, const Iter &A, in
       tval = __uint_as_float(grp_read(__float_as_uint(bt), base, owner));
       kind = 2;
     }
-    c_greedy += kind == 0;
-    c_roul += kind == 1;
-    if (kind == 2) { ++c_fb; c_fbu += (uint64_t)(n - t); }
+    c_kind += 1ull << (21 * kind);
+    if (kind == 2) c_fbu += (uint64_t)(n - t);
     if (gl == 0) mark(vis, next);
-    tb = gl == (t & (L - 1)) ? next : tb;
-    if ((t & (L - 1)) == L - 1 || t == n - 1) {
-      const int tbase = t & ~(L - 1);
-      if (gl <= (t & (L - 1))) D.tours[(size_t)ant * n + tbase + gl] = tb;
-    }
-    len += d;
+    tb = gl == t - t0 ? next : tb;
+    clen += d;
     rec = D.crec[(size_t)next * cl + kl];
     fwd = home(D, cur, next, k);
     fval = tval;
     prev = cur;
     cur = next;
+  }
+  len += clen;
+  if (t0 < n && gl <= min(L - 1, n - 1 - t0)) D.tours[(size_t)ant * n + t0 + gl] = tb;
   }
   if (ATOMIC && pend && pret != pexp) c_retry += 1 + cas_apply(pptr, pret, al, bl);
   {
@@ -1133,7 +1138,9 @@ __device__ __forceinline__ void ants_async_dense(const Dev &D, const Iter &A, in
   c_retry += grp_read(c_retry, base, 1);
   if (gl == 0) {
     D.lens[ant] = len;
-    add_counters(D, c_greedy, c_roul, c_fb, c_fbu, c_retry);
+    const uint32_t m21 = (1u << 21) - 1;
+    add_counters(D, (uint32_t)c_kind & m21, (uint32_t)(c_kind >> 21) & m21,
+                 (uint32_t)(c_kind >> 42) & m21, c_fbu, c_retry);
   }
 }
 
@@ -1573,14 +1580,25 @@ __global__ __launch_bounds__(256) void k_construct_async_spm(Dev D, Iter A) {
 
   int cur = start, prev = -1;
   int64_t len = 0;
-  uint32_t c_greedy = 0, c_roul = 0, c_fb = 0, c_retry = 0, hits = 0, misses = 0;
+  uint64_t c_kind = 0;  // greedy | roulette << 21 | fallback << 42
+  uint32_t c_retry = 0, hits = 0, misses = 0;
   uint64_t c_fbu = 0;
   SpmOp op{};
   op.live = false;
+  uint32_t uleft = A.lperiod;
 
-  for (int t = 1; t <= n; ++t) {
+  // chunks of 64 steps: one Philox batch and one tour store per chunk
+  for (int t0 = 0; t0 <= n; t0 += 64) {
+  if (t0 > 0) draws = philox_batch(A, ant, t0, lane);
+  uint32_t clen = 0;
+  const int tend = min(t0 + 64, n + 1);
+  for (int t = t0 > 0 ? t0 : 1; t < tend; ++t) {
     if (ATOMIC) c_retry += spm_async_finish(D, op, al, bl, tau0);
-    const bool upd = t > 1 && (t - 1) % A.lperiod == 0;
+    bool upd = false;
+    if (t > 1 && --uleft == 0) {
+      uleft = A.lperiod;
+      upd = true;
+    }
     // record of cur as it was read, then with this ant's reverse update
     const uint2 pr_read = pr;
     const uint32_t tl_read = tl;
@@ -1602,7 +1620,6 @@ __global__ __launch_bounds__(256) void k_construct_async_spm(Dev D, Iter A) {
       }
     }
     if (t == n) break;
-    if ((t & 63) == 0) draws = philox_batch(A, ant, t, lane);
     Pick p;
     const int k = pick_candidate(A, lane, cl, c, draw_of(draws, t), p.kind);
     if (k >= 0) {
@@ -1611,12 +1628,11 @@ __global__ __launch_bounds__(256) void k_construct_async_spm(Dev D, Iter A) {
     } else {
       p = fallback_spm(D, vis, cur, lane, pr, tau0);
     }
-    c_greedy += p.kind == 0;
-    c_roul += p.kind == 1;
-    if (p.kind == 2) { ++c_fb; c_fbu += (uint64_t)(n - t); }
+    c_kind += 1ull << (21 * p.kind);
+    if (p.kind == 2) c_fbu += (uint64_t)(n - t);
     if (lane == 0) mark(vis, p.next);
-    tour_put(D, ant, t, lane, p.next, tb);
-    len += p.d;
+    tb = lane == t - t0 ? p.next : tb;
+    clen += p.d;
     rec = D.crec[(size_t)p.next * cl + kl];
     pr_prev = pr;
     tl_prev = tl;
@@ -1624,6 +1640,9 @@ __global__ __launch_bounds__(256) void k_construct_async_spm(Dev D, Iter A) {
     tl = D.spm_tail[p.next];
     prev = cur;
     cur = p.next;
+  }
+  len += clen;
+  if (t0 < n && lane <= min(63, n - 1 - t0)) D.tours[(size_t)ant * n + t0 + lane] = tb;
   }
   if (ATOMIC) c_retry += spm_async_finish(D, op, al, bl, tau0);
   // closing edge, read fresh: record cur (neighbour start), record start
@@ -1653,7 +1672,9 @@ __global__ __launch_bounds__(256) void k_construct_async_spm(Dev D, Iter A) {
   misses = (uint32_t)uni((int)(rdlane(misses, 0) + rdlane(misses, 1)));
   if (lane == 0) {
     D.lens[ant] = len;
-    add_counters(D, c_greedy, c_roul, c_fb, c_fbu, c_retry);
+    const uint32_t m21 = (1u << 21) - 1;
+    add_counters(D, (uint32_t)c_kind & m21, (uint32_t)(c_kind >> 21) & m21,
+                 (uint32_t)(c_kind >> 42) & m21, c_fbu, c_retry);
     add_spm_counters(D, hits, misses);
   }
 }
