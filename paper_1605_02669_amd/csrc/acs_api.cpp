@@ -46,7 +46,7 @@ size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
 
 // Device buffers of one handle, as offsets into one allocation.
 struct Layout {
-  size_t xy, dist, crec, cand, eta, tau, etad, rpos, spm, spm_tail, upd_rec, upd_nb, upd_lead, tours, lens,
+  size_t xy, dist, crec, cand, eta, tau, etad, rpos, spm, spm_tail, upd_rec, upd_nb, upd_next, upd_head, tours, lens,
       best, gstate, counters, sync, dmax, lnn, total;
 };
 
@@ -74,7 +74,8 @@ Layout make_layout(int n, int m, int cl, int ldn, int memory, int s) {
     L.spm_tail = take(sizeof(uint32_t) * (size_t)n);
     L.upd_rec = take(sizeof(int32_t) * 2 * (size_t)m);
     L.upd_nb = take(sizeof(int32_t) * 2 * (size_t)m);
-    L.upd_lead = take(sizeof(int32_t) * (size_t)n);
+    L.upd_next = take(sizeof(int32_t) * 2 * (size_t)m);
+    L.upd_head = take(sizeof(int32_t) * (size_t)n);
   }
   L.tours = take(sizeof(int32_t) * (size_t)m * n);
   L.lens = take(sizeof(int64_t) * (size_t)m);
@@ -338,7 +339,8 @@ int acs_create(const double *coords_xy, int32_t n, const acs_params *p, acs_t **
     d.spm_tail = reinterpret_cast<uint32_t *>(w + h->L.spm_tail);
     d.upd_rec = reinterpret_cast<int32_t *>(w + h->L.upd_rec);
     d.upd_nb = reinterpret_cast<int32_t *>(w + h->L.upd_nb);
-    d.upd_lead = reinterpret_cast<int32_t *>(w + h->L.upd_lead);
+    d.upd_next = reinterpret_cast<int32_t *>(w + h->L.upd_next);
+    d.upd_head = reinterpret_cast<int32_t *>(w + h->L.upd_head);
   }
   d.tours = reinterpret_cast<int32_t *>(w + h->L.tours);
   d.lens = reinterpret_cast<int64_t *>(w + h->L.lens);

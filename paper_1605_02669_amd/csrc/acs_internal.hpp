@@ -29,8 +29,9 @@ struct Dev {
   uint2 *spm;              // SPM: n x s
   uint32_t *spm_tail;      // SPM: n
   int32_t *upd_rec;        // SPM synchronous updates of one step: record
-  int32_t *upd_nb;         //   ... and neighbour of update e = 2 * ant + w
-  int32_t *upd_lead;       //   per record: smallest e updating it (INT_MAX none)
+  int32_t *upd_nb;         //   ... and neighbour of update e = 2 * ant + w,
+  int32_t *upd_next;       //   ... the next update of the same record (-1 end)
+  int32_t *upd_head;       //   per record: first update of its list (-1 none)
   int32_t *tours;          // m x n
   int64_t *lens;           // m
   int32_t *best;           // n, best-so-far tour

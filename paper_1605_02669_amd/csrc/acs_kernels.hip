@@ -318,7 +318,7 @@ __global__ __launch_bounds__(256) void k_init(Dev D, float tau0) {
   if (D.spm && e < (size_t)D.n * D.spm_s) D.spm[e] = make_uint2(kNone, __float_as_uint(tau0));
   if (D.spm_tail && e < (size_t)D.n) {
     D.spm_tail[e] = (uint32_t)(D.spm_s - 1);
-    D.upd_lead[e] = INT_MAX;
+    D.upd_head[e] = -1;
   }
   if (e == 0) {
     D.gstate[0] = -1;
@@ -1305,53 +1305,76 @@ __device__ __forceinline__ void spm_update_wave(uint2 &pr, uint32_t &tail, int s
 
 // Synchronous step updates of record r: every registered update of this step
 // whose record is r, in increasing update index e = 2 * ant + w (ant
-// ascending, the ant's own record before the next city's).
+// ascending, the ant's own record before the next city's).  The updates of
+// r form a list (in arrival order); up to 64 of them are gathered onto the
+// lanes and applied smallest e first.  A longer list (more than 64 updates
+// of one record in one step) is found by scanning every registration.
 __device__ __forceinline__ void spm_apply_step(const Dev &D, int r, int ne, float a, float b,
                                                float tau0, int lane, uint32_t &hits,
                                                uint32_t &misses) {
   const int s = D.spm_s;
   uint2 pr = spm_record<true>(D, r, lane);
   uint32_t tail = __hip_atomic_load(D.spm_tail + r, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-  for (int e0 = 0; e0 < ne; e0 += 64) {
-    const int e = e0 + lane;
-    int rr = -1, nbv = 0;
-    if (e < ne) {
-      rr = __hip_atomic_load(D.upd_rec + e, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-      nbv = __hip_atomic_load(D.upd_nb + e, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  int cnt = 0, mine = INT_MAX;
+  int e = __hip_atomic_load(D.upd_head + r, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  while (e >= 0 && cnt <= 64) {
+    if (lane == cnt) mine = e;
+    ++cnt;
+    e = __hip_atomic_load(D.upd_next + e, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  }
+  if (cnt <= 64) {
+    for (int i = 0; i < cnt; ++i) {
+      const int emin = (int)wave_umin_u((uint32_t)mine);
+      if (mine == emin) mine = INT_MAX;
+      const int nb = __hip_atomic_load(D.upd_nb + emin, __ATOMIC_RELAXED,
+                                       __HIP_MEMORY_SCOPE_AGENT);
+      spm_update_wave(pr, tail, s, lane, nb, a, b, tau0, hits, misses);
     }
-    uint64_t mask = __ballot(rr == r);
-    while (mask) {
-      const int l = (int)__ffsll((unsigned long long)mask) - 1;
-      mask &= mask - 1;
-      spm_update_wave(pr, tail, s, lane, (int)rdlane((uint32_t)nbv, l), a, b, tau0, hits, misses);
+  } else {
+    for (int e0 = 0; e0 < ne; e0 += 64) {
+      const int ee = e0 + lane;
+      int rr = -1, nbv = 0;
+      if (ee < ne) {
+        rr = __hip_atomic_load(D.upd_rec + ee, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        nbv = __hip_atomic_load(D.upd_nb + ee, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      }
+      uint64_t mask = __ballot(rr == r);
+      while (mask) {
+        const int l = (int)__ffsll((unsigned long long)mask) - 1;
+        mask &= mask - 1;
+        spm_update_wave(pr, tail, s, lane, (int)rdlane((uint32_t)nbv, l), a, b, tau0, hits,
+                        misses);
+      }
     }
   }
   if (lane < s) pair_store_coherent(D.spm + (size_t)r * s + lane, pr);
   if (lane == 0) {
     __hip_atomic_store(D.spm_tail + r, tail, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    __hip_atomic_store(D.upd_lead + r, INT_MAX, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    __hip_atomic_store(D.upd_head + r, -1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
   }
 }
 
-// Registers update e (record r, neighbour nb) for this step.
-__device__ __forceinline__ void spm_register(const Dev &D, int e, int r, int nb) {
+// Registers update e (record r, neighbour nb) for this step by pushing it
+// onto r's list.  Returns true for the update that found the list empty:
+// its wave applies the record's list after the barrier.
+__device__ __forceinline__ bool spm_register(const Dev &D, int e, int r, int nb) {
   __hip_atomic_store(D.upd_rec + e, r, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
   __hip_atomic_store(D.upd_nb + e, nb, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-  __hip_atomic_fetch_min(D.upd_lead + r, e, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  const int old = __hip_atomic_exchange(D.upd_head + r, e, __ATOMIC_RELAXED,
+                                        __HIP_MEMORY_SCOPE_AGENT);
+  __hip_atomic_store(D.upd_next + e, old, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  return old < 0;
 }
 
 // The UPDATE phase of one synchronous step with the selective memory: the
-// wave of ant `ant` applies the lists of the records it leads (the smallest
-// update index of a record leads it).
-__device__ __forceinline__ void spm_sync_updates(const Dev &D, int ant, int r0, int r1, float a,
-                                                 float b, float tau0, int lane, uint32_t &hits,
-                                                 uint32_t &misses) {
+// wave of ant `ant` applies the lists of the records it leads (lead0: its
+// own record r0, lead1: the next city's record r1).
+__device__ __forceinline__ void spm_sync_updates(const Dev &D, bool lead0, bool lead1, int r0,
+                                                 int r1, float a, float b, float tau0, int lane,
+                                                 uint32_t &hits, uint32_t &misses) {
   const int ne = 2 * D.m;
-  const int e0 = 2 * ant;
-  if (__hip_atomic_load(D.upd_lead + r0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == e0)
-    spm_apply_step(D, r0, ne, a, b, tau0, lane, hits, misses);
-  if (__hip_atomic_load(D.upd_lead + r1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == e0 + 1)
-    spm_apply_step(D, r1, ne, a, b, tau0, lane, hits, misses);
+  if (lead0) spm_apply_step(D, r0, ne, a, b, tau0, lane, hits, misses);
+  if (lead1) spm_apply_step(D, r1, ne, a, b, tau0, lane, hits, misses);
 }
 
 __device__ __forceinline__ void add_spm_counters(const Dev &D, uint32_t hits, uint32_t misses) {
@@ -1415,12 +1438,14 @@ __global__ __launch_bounds__(1024) void k_construct_sync_spm(Dev D, Iter A) {
     if (active && t == n) len += D.dist[(size_t)cur * D.ldn + start];
     // t < n: the step's crossing (every lperiod-th step); t == n: the closing edge
     if (t == n || t % A.lperiod == 0) {
-      if (active) {
-        if (lane == 0) spm_register(D, 2 * ant, cur, next);
-        if (lane == 1) spm_register(D, 2 * ant + 1, next, cur);
-      }
+      bool lead = false;
+      if (active && lane < 2)
+        lead = spm_register(D, 2 * ant + lane, lane == 0 ? cur : next, lane == 0 ? next : cur);
+      const uint64_t leads = __ballot(lead);
       grid_barrier(D.sync, (++bar) * gridDim.x);
-      if (active) spm_sync_updates(D, ant, cur, next, A.a_loc, A.b_loc, tau0, lane, hits, misses);
+      if (active)
+        spm_sync_updates(D, leads & 1u, (leads >> 1) & 1u, cur, next, A.a_loc, A.b_loc, tau0,
+                         lane, hits, misses);
       if (t < n) grid_barrier(D.sync, (++bar) * gridDim.x);
     }
     cur = next;
