@@ -46,7 +46,7 @@ size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
 
 // Device buffers of one handle, as offsets into one allocation.
 struct Layout {
-  size_t xy, dist, crec, cand, eta, tau, etad, rpos, spm, spm_tail, upd_rec, upd_nb, upd_next, upd_head, tours, lens,
+  size_t xy, dist, crec, cand, eta, tau, etad, rpos, spm, spm_tail, xnn, upd_rec, upd_nb, upd_next, upd_head, tours, lens,
       best, gstate, counters, sync, dmax, lnn, total;
 };
 
@@ -72,6 +72,7 @@ Layout make_layout(int n, int m, int cl, int ldn, int memory, int s) {
   } else {
     L.spm = take(sizeof(uint32_t) * 2 * (size_t)n * s);
     L.spm_tail = take(sizeof(uint32_t) * (size_t)n);
+    L.xnn = take(sizeof(uint16_t) * (size_t)n * std::min(acs::kXnn, n - 1));
     L.upd_rec = take(sizeof(int32_t) * 2 * (size_t)m);
     L.upd_nb = take(sizeof(int32_t) * 2 * (size_t)m);
     L.upd_next = take(sizeof(int32_t) * 2 * (size_t)m);
@@ -337,6 +338,8 @@ int acs_create(const double *coords_xy, int32_t n, const acs_params *p, acs_t **
   } else {
     d.spm = reinterpret_cast<uint2 *>(w + h->L.spm);
     d.spm_tail = reinterpret_cast<uint32_t *>(w + h->L.spm_tail);
+    d.xnn = reinterpret_cast<const uint16_t *>(w + h->L.xnn);
+    d.xl = std::min(acs::kXnn, n - 1);
     d.upd_rec = reinterpret_cast<int32_t *>(w + h->L.upd_rec);
     d.upd_nb = reinterpret_cast<int32_t *>(w + h->L.upd_nb);
     d.upd_next = reinterpret_cast<int32_t *>(w + h->L.upd_next);

@@ -27,6 +27,8 @@ struct Dev {
   // {neighbour (-1 = empty slot), pheromone bits}; spm_tail[i] counts the
   // inserts (the most recently added slot is spm_tail[i] mod s)
   uint2 *spm;              // SPM: n x s
+  const uint16_t *xnn;     // SPM: n x xl, the xl nearest cities by (d, j)
+  int32_t xl;              //   (xl = min(kXnn, n - 1))
   uint32_t *spm_tail;      // SPM: n
   int32_t *upd_rec;        // SPM synchronous updates of one step: record
   int32_t *upd_nb;         //   ... and neighbour of update e = 2 * ant + w,
@@ -92,5 +94,6 @@ hipError_t launch_prior_features(const Dev &d, float *X, hipStream_t s);
 hipError_t launch_prior_apply(const Dev &d, const float *P, hipStream_t s);
 // Largest spm_s the GPU kernels support.
 constexpr int kMaxSpmS = 16;
+constexpr int kXnn = 128;  // extended neighbour list of the selective memory's fallback
 
 }  // namespace acs

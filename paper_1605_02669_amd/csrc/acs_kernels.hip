@@ -245,6 +245,27 @@ __global__ __launch_bounds__(256) void k_cand(Dev D, int32_t *cand) {
   }
 }
 
+// The xl nearest cities of every city by (d, j) (selective memory only):
+// the fallback's nearest unvisited city is usually among them.
+__global__ __launch_bounds__(256) void k_xnn(Dev D) {
+  const int lane = threadIdx.x & 63;
+  const int i = blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (i >= D.n) return;
+  const uint16_t *row = D.dist + (size_t)i * D.ldn;
+  int64_t last = -1;
+  for (int k = 0; k < D.xl; ++k) {
+    int64_t best = INT64_MAX;
+    for (int j = lane; j < D.n; j += 64) {
+      if (j == i) continue;
+      const int64_t key = ((int64_t)row[j] << 16) | j;
+      if (key > last && key < best) best = key;
+    }
+    best = wave_min(best);
+    if (lane == 0) const_cast<uint16_t *>(D.xnn)[(size_t)i * D.xl + k] = (uint16_t)(best & 0xffff);
+    last = best;
+  }
+}
+
 // Nearest-neighbour tour from city 0 (ties: lowest index), one block; its
 // length L_nn defines tau0 = 1 / (n * L_nn).
 __global__ __launch_bounds__(1024) void k_nn_tour(Dev D, int64_t *lnn) {
@@ -1240,17 +1261,33 @@ __device__ __forceinline__ Pick fallback_spm(const Dev &D, uint32_t *vis, int cu
   // hide the record's unvisited cities from the scan of the others
   if (rec_unv) atomicOr(&vis[rj >> 5], 1u << (rj & 31));
   uint32_t key = kNone;
-#pragma unroll 4
-  for (int j0 = 4 * lane; j0 < n; j0 += 256) {
-    const ushort4 dv = *reinterpret_cast<const ushort4 *>(drow + j0);
-    const uint32_t dq[4] = {dv.x, dv.y, dv.z, dv.w};
-    uint32_t bits = (vis[j0 >> 5] >> (j0 & 31)) & 0xfu;
-    if (j0 + 4 > n) bits |= (0xfu << (n - j0)) & 0xfu;
-#pragma unroll
-    for (int q = 0; q < 4; ++q)
-      if (!((bits >> q) & 1u)) key = min(key, (dq[q] << 16) | (uint32_t)(j0 + q));
+  // the extended neighbour list is sorted by (d, j), so its first city that
+  // is neither visited nor in the record is the nearest such city overall
+  const uint16_t *xr = D.xnn + (size_t)cur * D.xl;
+  for (int b0 = 0; b0 < D.xl; b0 += 64) {
+    const int idx = b0 + lane;
+    const uint32_t j = idx < D.xl ? (uint32_t)xr[idx] : 0u;
+    const uint64_t ok = __ballot(idx < D.xl && !((vis[j >> 5] >> (j & 31)) & 1u));
+    if (ok) {
+      const uint32_t jj = rdlane(j, (int)__ffsll((unsigned long long)ok) - 1);
+      key = ((uint32_t)drow[jj] << 16) | jj;
+      break;
+    }
   }
-  key = wave_umin_u(key);
+  if (key == kNone) {
+    // every listed city is taken: scan the whole row
+#pragma unroll 4
+    for (int j0 = 4 * lane; j0 < n; j0 += 256) {
+      const ushort4 dv = *reinterpret_cast<const ushort4 *>(drow + j0);
+      const uint32_t dq[4] = {dv.x, dv.y, dv.z, dv.w};
+      uint32_t bits = (vis[j0 >> 5] >> (j0 & 31)) & 0xfu;
+      if (j0 + 4 > n) bits |= (0xfu << (n - j0)) & 0xfu;
+#pragma unroll
+      for (int q = 0; q < 4; ++q)
+        if (!((bits >> q) & 1u)) key = min(key, (dq[q] << 16) | (uint32_t)(j0 + q));
+    }
+    key = wave_umin_u(key);
+  }
   if (rec_unv) atomicAnd(&vis[rj >> 5], ~(1u << (rj & 31)));
   // record candidates on lanes < s, the off-record candidate on its own
   uint32_t rd = 0;
@@ -1873,6 +1910,11 @@ hipError_t launch_crec(const Dev &d, const int32_t *cand_tmp, float tau0, hipStr
 }
 
 hipError_t launch_init_pheromone(const Dev &d, float tau0, hipStream_t s) {
+  if (d.xnn) {
+    hipLaunchKernelGGL(k_xnn, dim3((d.n + 3) / 4), dim3(256), 0, s, d);
+    const hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+  }
   if (d.rpos) {
     hipLaunchKernelGGL(k_rpos, dim3((d.n * d.cl + 255) / 256), dim3(256), 0, s, d);
     const hipError_t e = hipGetLastError();
