@@ -440,50 +440,55 @@ __device__ __forceinline__ Pick select_dense(const Dev &D, const Iter &A, const 
     return p;
   }
   // Alg. 2, empty candidate set: greedy over every unvisited city, ties ->
-  // lowest index.  Each lane scans four consecutive cities per round.  The
+  // lowest index.  Each lane scans eight consecutive cities per round.  The
   // loads of round r + 1 are issued before round r is examined (every round
   // loads, at an address clamped into the padded row, so the number of loads
   // in flight is fixed and the wait covers round r only).
   const float *trow = D.tau + (size_t)cur * D.ldn;
   const float *erow = D.etad + (size_t)cur * D.ldn;
   const uint16_t *drow = D.dist + (size_t)cur * D.ldn;
-  const int rounds = (n + 255) >> 8;
+  const int rounds = (n + 511) >> 9;
   float bv = 0.f, bt = 0.f;
   uint32_t bj = kNone, bd = 0;
-  float4 tv, ev;
-  ushort4 dv;
-  auto fetch = [&](int r, float4 &t4, float4 &e4, ushort4 &d4) {
-    const int j = min(4 * lane + 256 * r, D.ldn - 4);
-    if (COHERENT)
-      t4 = make_float4(tau_load(trow + j), tau_load(trow + j + 1), tau_load(trow + j + 2),
-                       tau_load(trow + j + 3));
-    else
-      t4 = *reinterpret_cast<const float4 *>(trow + j);
-    e4 = *reinterpret_cast<const float4 *>(erow + j);
-    d4 = *reinterpret_cast<const ushort4 *>(drow + j);
+  struct Round {
+    float t[8], e[8];
+    uint4 d;
   };
-  fetch(0, tv, ev, dv);
-  for (int r = 0; r < rounds; ++r) {
-    float4 tn, en;
-    ushort4 dn;
-    fetch(min(r + 1, rounds - 1), tn, en, dn);
-    const int j0 = 4 * lane + 256 * r;
-    uint32_t bits = (vis[min(j0, n - 1) >> 5] >> (j0 & 31)) & 0xfu;
-    if (j0 >= n) bits = 0xfu;
-    else if (j0 + 4 > n) bits |= (0xfu << (n - j0)) & 0xfu;
-    const float tq[4] = {tv.x, tv.y, tv.z, tv.w};
-    const float eq[4] = {ev.x, ev.y, ev.z, ev.w};
-    const uint32_t dq[4] = {dv.x, dv.y, dv.z, dv.w};
+  auto fetch = [&](int r, Round &x) {
+    const int j = min(8 * lane + 512 * r, D.ldn - 8);
+    if (COHERENT) {
 #pragma unroll
-    for (int q = 0; q < 4; ++q) {
-      const float v = tq[q] * eq[q];
+      for (int q = 0; q < 8; ++q) x.t[q] = tau_load(trow + j + q);
+    } else {
+      const float4 a = *reinterpret_cast<const float4 *>(trow + j);
+      const float4 b = *reinterpret_cast<const float4 *>(trow + j + 4);
+      x.t[0] = a.x; x.t[1] = a.y; x.t[2] = a.z; x.t[3] = a.w;
+      x.t[4] = b.x; x.t[5] = b.y; x.t[6] = b.z; x.t[7] = b.w;
+    }
+    const float4 a = *reinterpret_cast<const float4 *>(erow + j);
+    const float4 b = *reinterpret_cast<const float4 *>(erow + j + 4);
+    x.e[0] = a.x; x.e[1] = a.y; x.e[2] = a.z; x.e[3] = a.w;
+    x.e[4] = b.x; x.e[5] = b.y; x.e[6] = b.z; x.e[7] = b.w;
+    x.d = *reinterpret_cast<const uint4 *>(drow + j);
+  };
+  Round cr;
+  fetch(0, cr);
+  for (int r = 0; r < rounds; ++r) {
+    Round nr;
+    fetch(min(r + 1, rounds - 1), nr);
+    const int j0 = 8 * lane + 512 * r;
+    uint32_t bits = (vis[min(j0, n - 1) >> 5] >> (j0 & 31)) & 0xffu;
+    if (j0 >= n) bits = 0xffu;
+    else if (j0 + 8 > n) bits |= (0xffu << (n - j0)) & 0xffu;
+    const uint32_t dw[4] = {cr.d.x, cr.d.y, cr.d.z, cr.d.w};
+#pragma unroll
+    for (int q = 0; q < 8; ++q) {
+      const float v = cr.t[q] * cr.e[q];
       if (!((bits >> q) & 1u) && (bj == kNone || v > bv)) {
-        bv = v; bj = (uint32_t)(j0 + q); bt = tq[q]; bd = dq[q];
+        bv = v; bj = (uint32_t)(j0 + q); bt = cr.t[q]; bd = (dw[q >> 1] >> (16 * (q & 1))) & 0xffffu;
       }
     }
-    tv = tn;
-    ev = en;
-    dv = dn;
+    cr = nr;
   }
   const uint32_t mx = wave_umax_u(bj == kNone ? 0u : __float_as_uint(bv));
   const uint32_t jn = wave_umin_u((bj != kNone && __float_as_uint(bv) == mx) ? bj : kNone);
