@@ -608,3 +608,42 @@ def test_queued_tours_valid(acs, n, m, period):
     tau = col.tau()
     assert np.all(np.isfinite(tau)) and tau.min() >= np.float32(c["tau0"]) * np.float32(0.999)
     col.close()
+
+
+# ---------------------------------------------------------------------------
+# Edge cases of the asynchronous kernels (default updater path, in-wave
+# updates, several ants per wavefront): one ant must equal the oracle, any
+# number of ants must give valid tours.
+# ---------------------------------------------------------------------------
+ASYNC_EDGE = [
+    ("n3", 3, dict()),
+    ("n4_cl1", 4, dict(cl=1)),
+    ("n5_q0_zero", 5, dict(q0=0.0)),
+    ("n9_q0_one", 9, dict(q0=1.0)),
+    ("n65_cl64", 65, dict(cl=64)),
+    ("n130_cl16_beta3", 130, dict(cl=16, beta=3.0)),
+]
+ASYNC_PATHS = [("queued", dict(update_path=2)), ("inwave", dict(update_path=1)),
+               ("lanes16", dict(lanes_per_ant=16))]
+
+
+@pytest.mark.parametrize("path,gkw", ASYNC_PATHS, ids=[p[0] for p in ASYNC_PATHS])
+@pytest.mark.parametrize("name,n,kw", ASYNC_EDGE, ids=[c[0] for c in ASYNC_EDGE])
+def test_async_edge_cases(acs, name, n, kw, path, gkw):
+    if path == "lanes16" and kw.get("cl", 32) > 16 and n - 1 > 16:
+        pytest.skip("16 lanes per ant hold at most 16 candidates")
+    xy = inputs.uniform(n, 1000 + n)
+    col = acs.Colony(xy, m=1, mode=acs.ACS_ASYNC_ATOMIC, seed=7, **kw, **gkw)
+    orc = oracle.Oracle(xy, m=1, seed=7, **kw)
+    for it in range(4):
+        col.iterate(1)
+        orc.iterate(1)
+        _compare(col, orc, it)
+    col.close()
+    m = 3 * n + 5
+    col = acs.Colony(xy, m=m, mode=acs.ACS_ASYNC_ATOMIC, seed=7, **kw, **gkw)
+    col.iterate(3)
+    tours, lens = col.tours(), col.lengths()
+    assert np.all(np.sort(tours, axis=1) == np.arange(n)[None, :])
+    assert np.array_equal(defs.tour_lengths(xy, tours), lens)
+    col.close()
