@@ -124,15 +124,19 @@ __device__ __forceinline__ float4 load_x(const float *X, int row, int rows) {
                     : make_float4(0.f, 0.f, 0.f, 0.f);
 }
 
-// Logits of `rows` feature rows: one wave per block, 16 rows per tile.
-__global__ __launch_bounds__(64) void k_prior_forward(const float *P, const float *X, int rows,
-                                                      float *Z) {
+// Logits of `rows` feature rows: four waves per block share the staged
+// weights; each wave takes 16-row tiles with its own activation buffers.
+constexpr int kFwdWaves = 4;
+
+__global__ __launch_bounds__(64 * kFwdWaves) void k_prior_forward(const float *P, const float *X,
+                                                                  int rows, float *Z) {
   __shared__ Stage S;
-  __shared__ alignas(16) __bf16 h1[16 * H];
-  __shared__ alignas(16) __bf16 h2[16 * H];
+  __shared__ alignas(16) __bf16 hb[kFwdWaves][2][16 * H];
   stage_weights(S, P);
-  const int lane = threadIdx.x;
-  for (int r0 = blockIdx.x * 16; r0 < rows; r0 += gridDim.x * 16) {
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  __bf16 *h1 = hb[wv][0], *h2 = hb[wv][1];
+  for (int r0 = (blockIdx.x * kFwdWaves + wv) * 16; r0 < rows;
+       r0 += gridDim.x * kFwdWaves * 16) {
     wave_sync();
     const f32x4 z = forward16(S, load_x(X, r0 + (lane & 15), rows), lane, h1, h2);
     if ((lane & 15) == 0)
@@ -144,22 +148,36 @@ __global__ __launch_bounds__(64) void k_prior_forward(const float *P, const floa
 }
 
 // Gradient of the mean binary cross-entropy (with logits) over all `rows`
-// rows, accumulated into G; loss sum into *L.  One wave per block, 32 rows
-// per tile (two 16-row forward passes).  dW2 = H1^T dH2 and dH1 = dH2 W2^T
+// rows, accumulated into G; loss sum into *L.  kGradWaves waves per block
+// share the staged weights; each wave takes 32-row tiles (two 16-row
+// forward passes) with its own buffers.  dW2 = H1^T dH2 and dH1 = dH2 W2^T
 // run on the matrix cores; the 4-wide first layer, the 64 -> 1 last layer
-// and the biases on the vector units.
-__global__ __launch_bounds__(64) void k_prior_grad(const float *P, const float *X,
-                                                   const float *Y, int rows, float *G,
-                                                   float *L) {
+// and the biases on the vector units.  The waves' partial sums meet in LDS,
+// and each block adds its total to G once per parameter.
+constexpr int kGradWaves = 3;
+
+struct GradWave {
+  __bf16 h1[32 * H];    // row-major activations of the first hidden layer
+  __bf16 h2[32 * H];    // second hidden layer, then (in place) dL/dH2
+  __bf16 h1t[H * 32];   // H1^T [feature][row]
+  __bf16 dh2t[H * 32];  // dH2^T [feature][row]
+  float zs[32], dzs[32], xs[32 * 4];
+};
+
+__global__ __launch_bounds__(64 * kGradWaves) void k_prior_grad(const float *P, const float *X,
+                                                                const float *Y, int rows,
+                                                                float *G, float *L) {
   __shared__ Stage S;
-  __shared__ alignas(16) __bf16 h1[32 * H];    // row-major activations
-  __shared__ alignas(16) __bf16 h2[32 * H];
-  __shared__ alignas(16) __bf16 h1t[H * 32];   // H1^T [feature][row]
-  __shared__ alignas(16) __bf16 dh2[32 * H];
-  __shared__ alignas(16) __bf16 dh2t[H * 32];
-  __shared__ float zs[32], dzs[32], xs[32 * 4];
+  __shared__ union alignas(16) {
+    GradWave w[kGradWaves];
+    float red[kPriorParams + 1];  // block totals (the last entry: loss)
+  } U;
   stage_weights(S, P);
-  const int lane = threadIdx.x, g = lane >> 4, c16 = lane & 15;
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const int g = lane >> 4, c16 = lane & 15;
+  GradWave &B = U.w[wv];
+  __bf16 *h1 = B.h1, *h2 = B.h2, *dh2 = B.h2, *h1t = B.h1t, *dh2t = B.dh2t;
+  float *zs = B.zs, *dzs = B.dzs, *xs = B.xs;
   const float inv_rows = 1.f / (float)rows;
   f32x4 gw2[4][4];
   for (int a = 0; a < 4; ++a)
@@ -167,8 +185,10 @@ __global__ __launch_bounds__(64) void k_prior_grad(const float *P, const float *
   float gw1[4][4] = {};  // [nt][input] partials for feature 16 nt + c16
   float gb1[4] = {};
   float gw3 = 0.f, gb2 = 0.f, gb3 = 0.f, loss = 0.f;  // lane = feature
+  const float w3f = (float)S.w3t[lane];  // W3 as the forward pass used it (bf16)
 
-  for (int r0 = blockIdx.x * 32; r0 < rows; r0 += gridDim.x * 32) {
+  for (int r0 = (blockIdx.x * kGradWaves + wv) * 32; r0 < rows;
+       r0 += gridDim.x * kGradWaves * 32) {
     wave_sync();
     // forward of two 16-row halves; the first layer's inputs are kept as the
     // bf16 values the matrix cores multiplied (for its weight gradient)
@@ -198,10 +218,9 @@ __global__ __launch_bounds__(64) void k_prior_grad(const float *P, const float *
       dzs[lane] = dz;
     }
     wave_sync();
-    // last layer and dH2 (lane = feature f); W3 as the forward pass used it (bf16)
+    // last layer and dH2 (lane = feature f), dH2 written over H2 in place
     {
       const int f = lane;
-      const float w3f = (float)S.w3t[f];
       for (int r = 0; r < 32; ++r) {
         const float hv = (float)h2[r * H + f];
         const float dz = dzs[r];
@@ -239,21 +258,27 @@ __global__ __launch_bounds__(64) void k_prior_grad(const float *P, const float *
       }
     }
   }
-  // write out: dW2 in the D layout, the rest per lane
+  // the waves' partial sums meet in LDS (over the now unused wave buffers)
+  __syncthreads();
+  for (int e = threadIdx.x; e <= kPriorParams; e += blockDim.x) U.red[e] = 0.f;
+  __syncthreads();
   for (int mt = 0; mt < 4; ++mt)
     for (int nt = 0; nt < 4; ++nt)
       for (int v = 0; v < 4; ++v)
-        atomicAdd(&G[OW2 + (16 * mt + 4 * g + v) * H + 16 * nt + c16], gw2[mt][nt][v]);
+        atomicAdd(&U.red[OW2 + (16 * mt + 4 * g + v) * H + 16 * nt + c16], gw2[mt][nt][v]);
   for (int nt = 0; nt < 4; ++nt) {
-    atomicAdd(&G[OB1 + 16 * nt + c16], gb1[nt]);
-    for (int c = 0; c < 4; ++c) atomicAdd(&G[OW1 + c * H + 16 * nt + c16], gw1[nt][c]);
+    atomicAdd(&U.red[OB1 + 16 * nt + c16], gb1[nt]);
+    for (int c = 0; c < 4; ++c) atomicAdd(&U.red[OW1 + c * H + 16 * nt + c16], gw1[nt][c]);
   }
-  atomicAdd(&G[OW3 + lane], gw3);
-  atomicAdd(&G[OB2 + lane], gb2);
+  atomicAdd(&U.red[OW3 + lane], gw3);
+  atomicAdd(&U.red[OB2 + lane], gb2);
   if (lane < 32) {
-    atomicAdd(&G[OB3], gb3);
-    atomicAdd(L, loss);
+    atomicAdd(&U.red[OB3], gb3);
+    atomicAdd(&U.red[kPriorParams], loss);
   }
+  __syncthreads();
+  for (int e = threadIdx.x; e < kPriorParams; e += blockDim.x) atomicAdd(&G[e], U.red[e]);
+  if (threadIdx.x == 0) atomicAdd(L, U.red[kPriorParams]);
 }
 
 // Adam (Kingma and Ba, 2015) on the fp32 parameters; clears the gradient.
@@ -293,14 +318,15 @@ __global__ __launch_bounds__(256) void k_prior_features(Dev D, float *X) {
 
 // Scores of every candidate edge of the instance straight into the
 // eta^beta word of the candidate records: max(sigmoid(z), 1e-6).
-__global__ __launch_bounds__(64) void k_prior_apply(Dev D, const float *P) {
+__global__ __launch_bounds__(64 * kFwdWaves) void k_prior_apply(Dev D, const float *P) {
   __shared__ Stage S;
-  __shared__ alignas(16) __bf16 h1[16 * H];
-  __shared__ alignas(16) __bf16 h2[16 * H];
+  __shared__ alignas(16) __bf16 hb[kFwdWaves][2][16 * H];
   stage_weights(S, P);
-  const int lane = threadIdx.x;
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  __bf16 *h1 = hb[wv][0], *h2 = hb[wv][1];
   const int rows = D.n * 16;
-  for (int r0 = blockIdx.x * 16; r0 < rows; r0 += gridDim.x * 16) {
+  for (int r0 = (blockIdx.x * kFwdWaves + wv) * 16; r0 < rows;
+       r0 += gridDim.x * kFwdWaves * 16) {
     wave_sync();
     const int row = r0 + (lane & 15);
     const float4 x = row < rows ? edge_features(D, row / 16, row % 16)
@@ -321,17 +347,20 @@ __global__ __launch_bounds__(64) void k_prior_apply(Dev D, const float *P) {
 
 hipError_t launch_prior_forward(const float *P, const float *X, int rows, float *Z,
                                 hipStream_t s) {
-  const int blocks = (rows + 15) / 16 < 4096 ? (rows + 15) / 16 : 4096;
-  hipLaunchKernelGGL(k_prior_forward, dim3(blocks > 0 ? blocks : 1), dim3(64), 0, s, P, X, rows,
-                     Z);
+  const int tiles = (rows + 15) / 16;
+  int blocks = (tiles + kFwdWaves - 1) / kFwdWaves;
+  blocks = blocks < 1024 ? (blocks > 0 ? blocks : 1) : 1024;
+  hipLaunchKernelGGL(k_prior_forward, dim3(blocks), dim3(64 * kFwdWaves), 0, s, P, X, rows, Z);
   return hipGetLastError();
 }
 
 hipError_t launch_prior_grad(const float *P, const float *X, const float *Y, int rows, float *G,
                              float *L, hipStream_t s) {
-  const int blocks = (rows + 31) / 32 < 2048 ? (rows + 31) / 32 : 2048;
-  hipLaunchKernelGGL(k_prior_grad, dim3(blocks > 0 ? blocks : 1), dim3(64), 0, s, P, X, Y, rows,
-                     G, L);
+  const int tiles = (rows + 31) / 32;
+  int blocks = (tiles + kGradWaves - 1) / kGradWaves;
+  blocks = blocks < 512 ? (blocks > 0 ? blocks : 1) : 512;
+  hipLaunchKernelGGL(k_prior_grad, dim3(blocks), dim3(64 * kGradWaves), 0, s, P, X, Y, rows, G,
+                     L);
   return hipGetLastError();
 }
 
@@ -348,9 +377,10 @@ hipError_t launch_prior_features(const Dev &d, float *X, hipStream_t s) {
 }
 
 hipError_t launch_prior_apply(const Dev &d, const float *P, hipStream_t s) {
-  const int rows = d.n * 16;
-  const int blocks = (rows + 15) / 16 < 2048 ? (rows + 15) / 16 : 2048;
-  hipLaunchKernelGGL(k_prior_apply, dim3(blocks), dim3(64), 0, s, d, P);
+  const int tiles = d.n;  // 16 rows per city
+  int blocks = (tiles + kFwdWaves - 1) / kFwdWaves;
+  blocks = blocks < 1024 ? blocks : 1024;
+  hipLaunchKernelGGL(k_prior_apply, dim3(blocks), dim3(64 * kFwdWaves), 0, s, d, P);
   return hipGetLastError();
 }
 
