@@ -162,7 +162,7 @@ def run_batch(acs, inputs, iters=5, count=256):
     t0 = time.perf_counter()
     b = acs.Batch(insts, cl=CL, seed=0)
     create_s = time.perf_counter() - t0
-    b.iterate(4)  # warm-up and the launch-shape tuning
+    b.iterate(1 + 4 + 1)  # warm-up and the launch-shape tuning (up to 4 candidates)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     b.iterate(iters)
@@ -171,7 +171,7 @@ def run_batch(acs, inputs, iters=5, count=256):
     info = b.info()
     tuning = b.tuning()
     b.close()
-    return {"instances": count, "lanes_per_ant": tuning["chosen_lanes"],
+    return {"instances": count, "launch_shape": tuning["chosen"],
             "tuning_ms": tuning["candidates"], "n_min": int(min(len(x) for x in insts)),
             "n_max": int(max(len(x) for x in insts)),
             "steps_per_iteration": info["steps_per_iteration"], "graph": info["graph"],

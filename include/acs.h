@@ -198,20 +198,23 @@ int acs_batch_workspace_bytes(const int32_t *n, int32_t count, const acs_params 
 int acs_batch_create(const double *const *coords, const int32_t *n, int32_t count,
                      const acs_params *p, acs_batch_t **out);
 
-/* k iterations of every instance; returns once they have finished.  With
- * lanes_per_ant = 0 the first iterations also choose the launch shape: one
- * untimed iteration, then one timed iteration with each candidate number of
- * lanes per ant (64, and 32 and 16 where every candidate list fits); later
- * iterations use the fastest.  Tuning iterations are ordinary iterations
- * (the shape never changes a decision). */
+/* k iterations of every instance; returns once they have finished.  The
+ * first iterations also choose the launch shape: one untimed iteration,
+ * then one timed iteration with each candidate, later iterations with the
+ * fastest.  The candidates are 64 lanes per ant with the ant issuing its
+ * local updates, 64 lanes with an updater wave per block, and 32 and 16
+ * lanes per ant where every candidate list fits; lanes_per_ant and
+ * update_path, when set, restrict them.  Tuning iterations are ordinary
+ * iterations (the shape never changes a decision). */
 int acs_batch_iterate(acs_batch_t *b, int32_t k);
 
-/* Launch-shape tuning: the chosen lanes per ant (0 while still tuning), the
- * number of candidates, and per candidate its lanes per ant and the device
- * time of its timed iteration in ms (-1 if not yet timed).  The arrays hold
- * `cap` entries; at most 3 are written. */
-int acs_batch_tuning(acs_batch_t *b, int32_t *chosen_lanes, int32_t *count, int32_t *lanes,
-                     double *ms, int32_t cap);
+/* Launch-shape tuning: the index of the chosen candidate (-1 while still
+ * tuning), the number of candidates, and per candidate its lanes per ant,
+ * whether an updater wave applies the local updates (1) or the ant itself
+ * (0), and the device time of its timed iteration in ms (-1 if not yet
+ * timed).  The arrays hold `cap` entries; at most 4 are written. */
+int acs_batch_tuning(acs_batch_t *b, int32_t *chosen, int32_t *count, int32_t *lanes,
+                     int32_t *updater, double *ms, int32_t cap);
 
 /* Number of instances, construction steps of one iteration (sum of
  * m_i (n_i - 1)), whether the iteration runs as a graph (1) or as direct

@@ -89,7 +89,7 @@ def load() -> C.CDLL:
     lib.acs_batch_iterate.argtypes = [P, i32]
     lib.acs_batch_info.argtypes = [P, C.POINTER(i32), C.POINTER(i64), C.POINTER(i32),
                                    C.POINTER(C.c_double)]
-    lib.acs_batch_tuning.argtypes = [P, C.POINTER(i32), C.POINTER(i32), P, P, i32]
+    lib.acs_batch_tuning.argtypes = [P, C.POINTER(i32), C.POINTER(i32), P, P, P, i32]
     lib.acs_batch_instance.argtypes = [P, i32, C.POINTER(P)]
     lib.acs_batch_best_tour.argtypes = [P, i32, P, C.POINTER(i64)]
     lib.acs_batch_destroy.argtypes = [P]
@@ -289,7 +289,7 @@ class Batch:
 
     def __init__(self, instances, m=0, cl=32, beta=2.0, q0=0.9, phi=0.1, rho=0.1, tau0=0.0,
                  seed=0, instance=0, local_update_period=1, mode=ACS_ASYNC_ATOMIC,
-                 lanes_per_ant=0, torch_memory=True):
+                 lanes_per_ant=0, update_path=0, torch_memory=True):
         self.xys = [np.ascontiguousarray(x, dtype=np.float64).reshape(-1, 2) for x in instances]
         sizes = np.array([x.shape[0] for x in self.xys], dtype=np.int32)
         p = acs_default_params()
@@ -297,6 +297,7 @@ class Batch:
         p.mode, p.memory, p.seed, p.instance = mode, ACS_DENSE, seed, instance
         p.local_update_period = local_update_period
         p.lanes_per_ant = lanes_per_ant
+        p.update_path = update_path
         self._ws = None
         if torch_memory:
             import torch
@@ -332,12 +333,16 @@ class Batch:
                     last_iterate_ms=ms.value)
 
     def tuning(self) -> dict:
+        """Launch-shape candidates, named by lanes per ant ("64u": 64 lanes
+        with an updater wave), with the ms of their timed iterations, and
+        the chosen one (None while tuning)."""
         ch, cnt = C.c_int32(), C.c_int32()
-        lanes = (C.c_int32 * 3)()
-        ms = (C.c_double * 3)()
-        _check(load().acs_batch_tuning(self.h, C.byref(ch), C.byref(cnt), lanes, ms, 3))
-        return dict(chosen_lanes=ch.value,
-                    candidates={int(lanes[j]): float(ms[j]) for j in range(cnt.value)})
+        lanes, upd = (C.c_int32 * 4)(), (C.c_int32 * 4)()
+        ms = (C.c_double * 4)()
+        _check(load().acs_batch_tuning(self.h, C.byref(ch), C.byref(cnt), lanes, upd, ms, 4))
+        names = [f"{lanes[j]}{'u' if upd[j] else ''}" for j in range(cnt.value)]
+        return dict(chosen=names[ch.value] if ch.value >= 0 else None,
+                    candidates={names[j]: float(ms[j]) for j in range(cnt.value)})
 
     def handle(self, i: int):
         h = C.c_void_p()

@@ -553,6 +553,7 @@ struct acs_batch_t {
   // them once (after one untimed warm-up iteration); the fastest is kept.
   struct Variant {
     int lanes = 64;
+    bool queued = false;  // 64 lanes, updates through an updater wave per block
     int2 *d_items = nullptr;
     int nitems = 0;
     hipGraph_t graph = nullptr;
@@ -607,7 +608,9 @@ int batch_layout(const int32_t *n, int32_t count, const acs_params *p, BatchLayo
     L->off[(size_t)i] = off;
     off = align_up(off + bytes, 256);
     const int m = p->m ? (int)p->m : n[i];
-    *nitems += m + (m + 1) / 2 + (m + 3) / 4;  // work lists for 64, 32 and 16 lanes per ant
+    // work lists: 64 lanes per ant, 64 with the updater, 32 and 16 lanes
+    *nitems += m + (m + acs::kBatchQAntsPerBlock - 1) / acs::kBatchQAntsPerBlock + (m + 1) / 2 +
+               (m + 3) / 4;
   }
   L->devs = off;
   off = align_up(off + sizeof(acs::Dev) * (size_t)count, 256);
@@ -718,12 +721,18 @@ int acs_batch_create(const double *const *coords, const int32_t *n, int32_t coun
   // the largest candidate list (64 always; 32 and 16 when cl fits)
   int clmax = 0;
   for (acs_t *h : b->inst) clmax = std::max(clmax, h->cl);
-  std::vector<int> widths;
-  if (p->lanes_per_ant) {
-    widths.push_back((int)p->lanes_per_ant);
-  } else {
-    for (int w : {64, 32, 16})
-      if (w >= clmax) widths.push_back(w);
+  // candidates (lanes per ant, updater wave): 64 lanes with updates issued
+  // by the ant (update_path 1) or handed to an updater wave (update_path 2),
+  // both unless one is asked for; 32 and 16 lanes issue their own
+  std::vector<std::pair<int, bool>> widths;
+  for (int w : {64, 32, 16}) {
+    if (p->lanes_per_ant ? w != (int)p->lanes_per_ant : w < clmax) continue;
+    if (w == 64) {
+      if (p->update_path != 2) widths.push_back({64, false});
+      if (p->update_path != 1) widths.push_back({64, true});
+    } else {
+      widths.push_back({w, false});
+    }
   }
   // work lists: instances by decreasing n, so the longest chains start
   // first; a wave's ants always belong to one instance
@@ -735,11 +744,12 @@ int acs_batch_create(const double *const *coords, const int32_t *n, int32_t coun
   int2 *d_items = reinterpret_cast<int2 *>(b->ws + L.items);
   std::vector<int2> items;
   items.reserve((size_t)nitems);
-  for (int w : widths) {
+  for (const auto &wq : widths) {
     acs_batch_t::Variant v;
-    v.lanes = w;
+    v.lanes = wq.first;
+    v.queued = wq.second;
     v.d_items = d_items + items.size();
-    const int g = 64 / w;
+    const int g = v.queued ? acs::kBatchQAntsPerBlock : 64 / v.lanes;
     for (int i : order)
       for (int a = 0; a < b->inst[(size_t)i]->m; a += g) items.push_back(make_int2(i, a));
     v.nitems = (int)(items.size() - (size_t)(v.d_items - d_items));
@@ -762,7 +772,7 @@ int acs_batch_create(const double *const *coords, const int32_t *n, int32_t coun
     if (hipStreamBeginCapture(b->stream, hipStreamCaptureModeThreadLocal) != hipSuccess) continue;
     const hipError_t le = acs::launch_batch_iteration(b->d_devs, b->d_iters, v.d_items, v.nitems,
                                                       b->count, b->nmax, b->mode, v.lanes,
-                                                      b->stream);
+                                                      v.queued ? 1 : 0, b->stream);
     hipGraph_t g = nullptr;
     const hipError_t ce = hipStreamEndCapture(b->stream, &g);
     if (le == hipSuccess && ce == hipSuccess && g) {
@@ -789,7 +799,7 @@ int acs_batch_iterate(acs_batch_t *b, int32_t k) {
   auto launch = [&](const acs_batch_t::Variant &v) -> hipError_t {
     if (v.exec) return hipGraphLaunch(v.exec, b->stream);
     return acs::launch_batch_iteration(b->d_devs, b->d_iters, v.d_items, v.nitems, b->count,
-                                       b->nmax, b->mode, v.lanes, b->stream);
+                                       b->nmax, b->mode, v.lanes, v.queued ? 1 : 0, b->stream);
   };
   double total_ms = 0.0;
   int i = 0;
@@ -844,13 +854,14 @@ int acs_batch_info(acs_batch_t *b, int32_t *count, int64_t *steps_per_iteration,
   return ACS_OK;
 }
 
-int acs_batch_tuning(acs_batch_t *b, int32_t *chosen_lanes, int32_t *count, int32_t *lanes,
-                     double *ms, int32_t cap) {
+int acs_batch_tuning(acs_batch_t *b, int32_t *chosen, int32_t *count, int32_t *lanes,
+                     int32_t *updater, double *ms, int32_t cap) {
   if (!live_batch(b)) return fail(ACS_E_STATE, "invalid batch handle");
-  if (chosen_lanes) *chosen_lanes = b->chosen < 0 ? 0 : b->var[(size_t)b->chosen].lanes;
+  if (chosen) *chosen = b->chosen;
   if (count) *count = (int32_t)b->var.size();
   for (int j = 0; j < (int)b->var.size() && j < cap; ++j) {
     if (lanes) lanes[j] = b->var[(size_t)j].lanes;
+    if (updater) updater[j] = b->var[(size_t)j].queued ? 1 : 0;
     if (ms) ms[j] = b->var[(size_t)j].ms;
   }
   return ACS_OK;

@@ -79,9 +79,13 @@ hipError_t launch_best_global(const Dev &d, const Iter &it, int memory,
 // three launches can be captured once in a graph and replayed.  mode 1:
 // updates by compare-and-swap; mode 2: plain stores (lost updates).  lanes =
 // 64: items are (instance, ant), one per wave; lanes = 32 or 16: items are
-// (instance, first ant) of the 64 / lanes ants of one wave.
+// (instance, first ant) of the 64 / lanes ants of one wave; lanes = 64 with
+// `queued`: items are (instance, first ant) of the kBatchQAntsPerBlock ants
+// of one block, whose updates an updater wave applies.
+constexpr int kBatchQAntsPerBlock = 4;
 hipError_t launch_batch_iteration(const Dev *devs, Iter *iters, const int2 *items, int nitems,
-                                  int count, int nmax, int mode, int lanes, hipStream_t s);
+                                  int count, int nmax, int mode, int lanes, int queued,
+                                  hipStream_t s);
 // Learned edge prior (acs_prior.hip): parameter count and kernels.
 constexpr int kPriorParams = 4545;
 hipError_t launch_prior_forward(const float *P, const float *X, int rows, float *Z,

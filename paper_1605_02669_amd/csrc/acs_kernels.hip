@@ -937,6 +937,41 @@ __global__ __launch_bounds__(64 * (kQAnts + 1)) void k_construct_async_dense_q(D
   if (lane == 0) atomicAdd(&q.done, 1u);
 }
 
+// Many instances in one launch, updates through each block's rings: block b
+// runs ants bitems[b].y .. bitems[b].y + kBatchQAnts - 1 of instance
+// bitems[b].x (one instance per block, so the updater wave works with one
+// descriptor), wave kBatchQAnts applies their updates.
+constexpr int kBatchQAnts = kBatchQAntsPerBlock;
+
+template <bool ATOMIC>
+__global__ __launch_bounds__(64 * (kBatchQAnts + 1)) void k_construct_async_batch_q(
+    const Dev *devs, const Iter *iters, const int2 *bitems, int nb, int wmax) {
+  extern __shared__ uint32_t smem[];
+  __shared__ UpdRing q;
+  const int lane = threadIdx.x & 63;
+  const int wv = threadIdx.x >> 6;
+  if (threadIdx.x < kQAnts) {
+    q.head[threadIdx.x] = 0;
+    q.tail[threadIdx.x] = 0;
+  }
+  if (threadIdx.x == 0) q.done = 0;
+  __syncthreads();
+  const int b = blockIdx.x;  // the grid has exactly nb blocks
+  const int2 item = bitems[b];
+  const int inst = uni(item.x);
+  const Dev D = devs[inst];
+  const Iter A = iters[inst];
+  if (wv == kBatchQAnts) {
+    ring_updater<ATOMIC>(D, A, q, lane, kBatchQAnts);
+    return;
+  }
+  const int ant = uni(item.y + wv);
+  if (ant < D.m)
+    ant_async_dense<ATOMIC, true>(D, A, ant, smem + wv * wmax, lane, &q, wv);
+  __atomic_signal_fence(__ATOMIC_SEQ_CST);
+  if (lane == 0) atomicAdd(&q.done, 1u);
+}
+
 // Many instances in one launch: wave w builds the tour of ant items[w].y of
 // instance items[w].x, whose descriptor and iteration state live in device
 // memory (so the launch can be replayed from a graph).  The work list is
@@ -2027,9 +2062,28 @@ hipError_t launch_best_global(const Dev &d, const Iter &it, int memory, hipStrea
 }
 
 hipError_t launch_batch_iteration(const Dev *devs, Iter *iters, const int2 *items, int nitems,
-                                  int count, int nmax, int mode, int lanes, hipStream_t s) {
+                                  int count, int nmax, int mode, int lanes, int queued,
+                                  hipStream_t s) {
   const int apb = kAsyncBlock / 64;
   const int wmax = (nmax + 31) / 32;
+  if (lanes == 64 && queued) {
+    const size_t lq = (size_t)kBatchQAnts * wmax * sizeof(uint32_t);
+    const dim3 gq(nitems), bq(64 * (kBatchQAnts + 1));
+    if (mode == 1)
+      hipLaunchKernelGGL(k_construct_async_batch_q<true>, gq, bq, lq, s, devs, iters, items,
+                         nitems, wmax);
+    else
+      hipLaunchKernelGGL(k_construct_async_batch_q<false>, gq, bq, lq, s, devs, iters, items,
+                         nitems, wmax);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_best_batch, dim3(count), dim3(1024), 0, s, devs, iters);
+    e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_global_batch, dim3((nmax + 255) / 256, count), dim3(256), 0, s, devs,
+                       iters);
+    return hipGetLastError();
+  }
   const size_t lds = (size_t)apb * (64 / lanes) * wmax * sizeof(uint32_t);
   const dim3 grid((nitems + apb - 1) / apb), blk(kAsyncBlock);
   const bool atomic = mode == 1;

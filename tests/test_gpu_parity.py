@@ -544,14 +544,14 @@ def test_grouped_tours_valid(acs, lanes, mode):
 def test_batch_tuner_picks_a_shape_and_keeps_iterating(acs):
     insts = inputs.batch(40, seed=61, nmin=100, nmax=700)
     b = acs.Batch(insts, cl=16, seed=3)
-    assert b.tuning()["chosen_lanes"] == 0
+    assert b.tuning()["chosen"] is None
     b.iterate(2)  # warm-up + first candidate
     b.iterate(3)  # the other candidates, then the chosen shape
     tu = b.tuning()
     _say(f"batch tuning {tu}")
-    assert set(tu["candidates"]) == {64, 32, 16}
+    assert set(tu["candidates"]) == {"64", "64u", "32", "16"}
     assert all(v > 0 for v in tu["candidates"].values())
-    assert tu["chosen_lanes"] == min(tu["candidates"], key=tu["candidates"].get)
+    assert tu["chosen"] == min(tu["candidates"], key=tu["candidates"].get)
     for i, xy in enumerate(insts):
         tours, lens = b.tours(i), b.lengths(i)
         assert np.all(np.sort(tours, axis=1) == np.arange(len(xy))[None, :])
@@ -647,3 +647,17 @@ def test_async_edge_cases(acs, name, n, kw, path, gkw):
     assert np.all(np.sort(tours, axis=1) == np.arange(n)[None, :])
     assert np.array_equal(defs.tour_lengths(xy, tours), lens)
     col.close()
+
+
+def test_batch_updater_wave_single_ant_equals_oracle(acs):
+    insts = inputs.batch(5, seed=81, nmin=40, nmax=300)
+    b = acs.Batch(insts, m=1, cl=16, seed=8, lanes_per_ant=64, update_path=2)
+    assert set(b.tuning()["candidates"]) == {"64u"}
+    orcs = [oracle.Oracle(x, m=1, cl=16, seed=8, instance=i) for i, x in enumerate(insts)]
+    for it in range(3):
+        b.iterate(1)
+        for i, o in enumerate(orcs):
+            o.iterate(1)
+            assert np.array_equal(b.tours(i), o.tours()), (i, it)
+            assert np.array_equal(b.tau(i), o.tau()), (i, it)
+    b.close()
