@@ -125,16 +125,16 @@ def cpu_baseline(xy, budget_s: float = 12.0):
 
 EXTRA = {
     # n=198 uniform, m=n, cl=32, dense (the paper's d198 size)
-    "c1": dict(kind="uniform", n=198, kw=dict(), modes=(("sync", 20), ("async", 50))),
+    "n198": dict(kind="uniform", n=198, kw=dict(), modes=(("sync", 20), ("async", 50))),
     # n=1000 clustered (20 Gaussian clusters), m=n, cl=32, dense
-    "c2c": dict(kind="clustered", n=1000, kw=dict(), modes=(("sync", 3), ("async", 20))),
+    "n1000_clustered": dict(kind="clustered", n=1000, kw=dict(), modes=(("sync", 3), ("async", 20))),
     # n=20000 uniform, m=1024, cl=16, selective memory with s=8
-    "c3": dict(kind="uniform", n=20000, kw=dict(m=1024, cl=16, memory=1, spm_s=8),
+    "n20000_spm": dict(kind="uniform", n=20000, kw=dict(m=1024, cl=16, memory=1, spm_s=8),
                modes=(("sync", 1), ("async", 5), ("racy", 5))),
     # the headline instance without atomics (the paper's Alt) and with the
     # local update after every 16th edge only
-    "alt": dict(kind="uniform", n=N, kw=dict(), modes=(("racy", 20),)),
-    "k16": dict(kind="uniform", n=N, kw=dict(local_update_period=16),
+    "n2392_alt": dict(kind="uniform", n=N, kw=dict(), modes=(("racy", 20),)),
+    "n2392_period16": dict(kind="uniform", n=N, kw=dict(local_update_period=16),
                 modes=(("async", 20), ("racy", 20), ("sync", 2))),
 }
 
@@ -241,9 +241,10 @@ def main():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--sync-steps", type=int, default=5)
     ap.add_argument("--no-cpu", action="store_true")
-    ap.add_argument("--extra", default="c1,c2c,c3,c4,c5,alt,k16",
+    ap.add_argument("--extra", default="n198,n1000_clustered,n20000_spm,batch256,prior,n2392_alt,n2392_period16",
                     help="other workloads timed beside the headline (comma list of "
-                         "c1, c2c, c3, c4, c5, alt, k16; empty for none)")
+                         "n198, n1000_clustered, n20000_spm, batch256, prior, n2392_alt, n2392_period16; "
+                         "empty for none)")
     ap.add_argument("--copy-calibration-mb", type=int, default=0,
                     help="after timing, run one plain device copy of this many MiB "
                          "(reference kernel for hardware byte counters)")
@@ -309,9 +310,9 @@ def main():
     }
     extra = {}
     for name in [x for x in args.extra.split(",") if x]:
-        if name == "c4":
+        if name == "batch256":
             extra[name] = run_batch(acs, inputs)
-        elif name == "c5":
+        elif name == "prior":
             extra[name] = run_prior(acs, inputs)
         else:
             extra[name] = run_extra(acs, inputs, name)

@@ -68,7 +68,8 @@ def load() -> C.CDLL:
     if _lib is not None:
         return _lib
     if not os.path.exists(LIB_PATH):
-        raise RuntimeError(f"{LIB_PATH} is missing: build it with __graft_entry__.build()")
+        raise RuntimeError(f"{LIB_PATH} is missing: build it with "
+                           "python -m paper_1605_02669_amd.build")
     lib = C.CDLL(LIB_PATH)
     P, i32, i64, sz = C.c_void_p, C.c_int32, C.c_int64, C.c_size_t
     lib.acs_default_params.argtypes = [C.POINTER(acs_params)]

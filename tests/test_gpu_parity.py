@@ -75,7 +75,7 @@ def test_instance_preparation_matches(acs):
         col.close()
 
 
-def test_config1_n198_sync_100_iterations(acs):
+def test_n198_sync_100_iterations(acs):
     """n=198 uniform, m=198, cl=32, beta=2, q0=0.9, phi=rho=0.1, dense, sync."""
     xy = inputs.uniform(198)
     col, orc = _pair(acs, xy, seed=0)
