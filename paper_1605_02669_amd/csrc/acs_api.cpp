@@ -546,7 +546,7 @@ struct acs_batch_t {
   bool own_ws = false;
   acs::Dev *d_devs = nullptr;
   acs::Iter *d_iters = nullptr;
-  int nmax = 0, mode = ACS_ASYNC_ATOMIC;
+  int nmax = 0, clmax = 0, mode = ACS_ASYNC_ATOMIC;
   int64_t steps_per_iteration = 0;
   // One launch configuration per candidate lanes-per-ant value: its work
   // list and its captured iteration.  The first iterations time each of
@@ -721,6 +721,7 @@ int acs_batch_create(const double *const *coords, const int32_t *n, int32_t coun
   // the largest candidate list (64 always; 32 and 16 when cl fits)
   int clmax = 0;
   for (acs_t *h : b->inst) clmax = std::max(clmax, h->cl);
+  b->clmax = clmax;
   // candidates (lanes per ant, updater wave): 64 lanes with updates issued
   // by the ant (update_path 1) or handed to an updater wave (update_path 2),
   // both unless one is asked for; 32 and 16 lanes issue their own
@@ -771,7 +772,7 @@ int acs_batch_create(const double *const *coords, const int32_t *n, int32_t coun
   for (auto &v : b->var) {
     if (hipStreamBeginCapture(b->stream, hipStreamCaptureModeThreadLocal) != hipSuccess) continue;
     const hipError_t le = acs::launch_batch_iteration(b->d_devs, b->d_iters, v.d_items, v.nitems,
-                                                      b->count, b->nmax, b->mode, v.lanes,
+                                                      b->count, b->nmax, b->clmax, b->mode, v.lanes,
                                                       v.queued ? 1 : 0, b->stream);
     hipGraph_t g = nullptr;
     const hipError_t ce = hipStreamEndCapture(b->stream, &g);
@@ -799,7 +800,8 @@ int acs_batch_iterate(acs_batch_t *b, int32_t k) {
   auto launch = [&](const acs_batch_t::Variant &v) -> hipError_t {
     if (v.exec) return hipGraphLaunch(v.exec, b->stream);
     return acs::launch_batch_iteration(b->d_devs, b->d_iters, v.d_items, v.nitems, b->count,
-                                       b->nmax, b->mode, v.lanes, v.queued ? 1 : 0, b->stream);
+                                       b->nmax, b->clmax, b->mode, v.lanes, v.queued ? 1 : 0,
+                                       b->stream);
   };
   double total_ms = 0.0;
   int i = 0;

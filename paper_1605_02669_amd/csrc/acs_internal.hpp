@@ -84,7 +84,7 @@ hipError_t launch_best_global(const Dev &d, const Iter &it, int memory,
 // of one block, whose updates an updater wave applies.
 constexpr int kBatchQAntsPerBlock = 4;
 hipError_t launch_batch_iteration(const Dev *devs, Iter *iters, const int2 *items, int nitems,
-                                  int count, int nmax, int mode, int lanes, int queued,
+                                  int count, int nmax, int clmax, int mode, int lanes, int queued,
                                   hipStream_t s);
 // Learned edge prior (acs_prior.hip): parameter count and kernels.
 constexpr int kPriorParams = 4545;

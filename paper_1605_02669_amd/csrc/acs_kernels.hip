@@ -111,6 +111,13 @@ __device__ __forceinline__ uint32_t half_umax_u(uint32_t v) {
   return (uint32_t)__builtin_amdgcn_readfirstlane((int)v);
 }
 
+// Wave-wide sum, every lane active (rare paths only: LDS permutes).
+__device__ __forceinline__ uint32_t wave_sum_u(uint32_t v) {
+#pragma unroll
+  for (int off = 32; off; off >>= 1) v += (uint32_t)__shfl_xor((int)v, off, 64);
+  return v;
+}
+
 __device__ __forceinline__ uint32_t wave_umin_u(uint32_t v) {
   v = min(v, (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0xB1, 0xF, 0xF, false));
   v = min(v, (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x4E, 0xF, 0xF, false));
@@ -426,24 +433,16 @@ __device__ __forceinline__ int pick_candidate(const Iter &A, int lane, int cl, C
   return uni(k);
 }
 
+// Alg. 2, empty candidate set: greedy over every unvisited city, ties ->
+// lowest index.  Each lane scans eight consecutive cities per round.  The
+// loads of round r + 1 are issued before round r is examined (every round
+// loads, at an address clamped into the padded row, so the number of loads
+// in flight is fixed and the wait covers round r only).
 template <bool COHERENT>
-__device__ __forceinline__ Pick select_dense(const Dev &D, const Iter &A, const uint32_t *vis,
-                                             int cur, int lane, uint4 rec, Cand c, uint2 q) {
+__device__ __forceinline__ Pick fallback_dense(const Dev &D, const uint32_t *vis, int cur,
+                                               int lane) {
   const int n = D.n;
   Pick p;
-  const int k = pick_candidate(A, lane, D.cl, c, q, p.kind);
-  if (k >= 0) {
-    p.k = k;
-    p.next = (int)rdlane(rec.x, k);
-    p.d = rdlane(rec.y, k);
-    p.tval = __uint_as_float(rdlane(rec.w, k));
-    return p;
-  }
-  // Alg. 2, empty candidate set: greedy over every unvisited city, ties ->
-  // lowest index.  Each lane scans eight consecutive cities per round.  The
-  // loads of round r + 1 are issued before round r is examined (every round
-  // loads, at an address clamped into the padded row, so the number of loads
-  // in flight is fixed and the wait covers round r only).
   const float *trow = D.tau + (size_t)cur * D.ldn;
   const float *erow = D.etad + (size_t)cur * D.ldn;
   const uint16_t *drow = D.dist + (size_t)cur * D.ldn;
@@ -499,6 +498,19 @@ __device__ __forceinline__ Pick select_dense(const Dev &D, const Iter &A, const 
   p.d = rdlane(bd, owner);
   p.tval = __uint_as_float(rdlane(__float_as_uint(bt), owner));
   p.kind = 2;
+  return p;
+}
+
+template <bool COHERENT>
+__device__ __forceinline__ Pick select_dense(const Dev &D, const Iter &A, const uint32_t *vis,
+                                             int cur, int lane, uint4 rec, Cand c, uint2 q) {
+  Pick p;
+  const int k = pick_candidate(A, lane, D.cl, c, q, p.kind);
+  if (k < 0) return fallback_dense<COHERENT>(D, vis, cur, lane);
+  p.k = k;
+  p.next = (int)rdlane(rec.x, k);
+  p.d = rdlane(rec.y, k);
+  p.tval = __uint_as_float(rdlane(rec.w, k));
   return p;
 }
 
@@ -602,151 +614,6 @@ __global__ __launch_bounds__(1024) void k_construct_sync_dense(Dev D, Iter A) {
 }
 
 // ---------------------------------------------------------------------------
-// Local updates handed to an updater wave.  gfx950 counts loads, stores and
-// atomics of a wave in one in-order counter, so a wave that waits for its
-// next record also waits for every update it issued before that load.  With
-// the ring, an ant wave only writes (home, value read) pairs into LDS and
-// never waits for an atomic; one updater wave per block applies them.
-// Each ant wave owns a ring (single producer, single consumer): it writes
-// entries, then publishes its head; the updater applies entries, then
-// publishes its tail.  LDS instructions of one wave take effect in issue
-// order, so a published head covers entries already written, and a
-// published tail frees entries already read.  Every wait is bounded: on
-// exhaustion the error flag (2) is raised and the ant applies its update
-// itself, so every wave still reaches its end.
-// ---------------------------------------------------------------------------
-constexpr int kQAnts = 8;   // at most this many ant waves per block
-constexpr int kQRing = 64;  // entries per ring (power of 2)
-constexpr uint32_t kQSpin = 1u << 22;
-
-struct UpdRing {
-  uint4 ent[kQAnts][kQRing];  // crossings u -> v: {u | v << 16, position of v in u's
-                              //  list or -1, value of (u, v) read, reverse position
-                              //  (see reverse_pos)}
-  uint32_t head[kQAnts];      // entries written by the ant wave
-  uint32_t tail[kQAnts];      // entries applied by the updater
-  uint32_t done;              // ant waves that have written their last entry
-};
-
-__device__ __forceinline__ uint32_t lds_ld(const uint32_t *p) {
-  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
-}
-__device__ __forceinline__ void lds_st(uint32_t *p, uint32_t v) {
-  __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
-}
-
-// Position of u in the candidate list of v for the crossing u -> v (v the
-// k-th candidate of u, k = -1 if none): `kr` if the ant found it (-1: u is
-// not a candidate of v), or, for kr = -2, the reverse table.
-__device__ __forceinline__ int reverse_pos(const Dev &D, int u, int k, int kr) {
-  return kr != -2 ? kr : (int)D.rpos[(size_t)u * D.cl + k];
-}
-
-// Eq. 3 on both directed entries of the crossed edge {u, v}: lane 0 the
-// forward entry (u, v), lane 1 the reverse entry (v, u), each with x, the
-// pheromone of (u, v) the ant read, as the expected value (the two entries
-// of an edge always receive the same maps, so they hold the same value once
-// the updates in flight have landed; a compare-and-swap that finds another
-// value retries with it).  Returns the retries.
-template <bool ATOMIC>
-__device__ __forceinline__ uint32_t apply_crossing(const Dev &D, const Iter &A, int lane, int u,
-                                                   int v, int k, int kr, float x) {
-  if (lane > 1) return 0;
-  float *p = lane == 0 ? home(D, u, v, k) : home(D, v, u, reverse_pos(D, u, k, kr));
-  if (ATOMIC) return cas_apply(p, __float_as_uint(x), A.a_loc, A.b_loc);
-  __hip_atomic_store(p, fmaf(A.a_loc, x, A.b_loc), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-  return 0;
-}
-
-// Lane 0 hands over the local update of one crossing: the move u -> v, v
-// the k-th candidate of u (k = -1 if it is none), kr as for reverse_pos, x
-// the pheromone of (u, v) as the ant read it.  The updater applies the map to both directed entries
-// of the edge.  `head` and `room` (entries known free) are the wave's own.
-template <bool ATOMIC>
-__device__ __forceinline__ uint32_t ring_push(const Dev &D, const Iter &A, UpdRing &q, int w,
-                                              uint32_t &head, uint32_t &room, int lane, int u,
-                                              int v, int k, int kr, float x) {
-  if (room < 1) {
-    uint32_t spins = 0;
-    while (true) {
-      room = kQRing - (head - uni((int)lds_ld(&q.tail[w])));
-      if (room >= 1) break;
-      __builtin_amdgcn_s_sleep(1);
-      if (++spins > kQSpin) {
-        // the updater does not drain: raise the flag, apply directly
-        if (lane == 0)
-          __hip_atomic_store(D.sync + 1, 2u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        return apply_crossing<ATOMIC>(D, A, lane, u, v, k, kr, x);
-      }
-    }
-  }
-  if (lane == 0)
-    q.ent[w][head & (kQRing - 1)] =
-        make_uint4((uint32_t)u | ((uint32_t)v << 16), (uint32_t)k, __float_as_uint(x),
-                   (uint32_t)kr);
-  head += 1;
-  room -= 1;
-  __atomic_signal_fence(__ATOMIC_SEQ_CST);
-  if (lane == 0) lds_st(&q.head[w], head);
-  return 0;
-}
-
-// The updater wave: applies the entries of every ring of its block until
-// all `na` ant waves are done and every ring is empty.  One pass gathers
-// up to 8 pending entries of each ring onto its 64 lanes and applies them
-// together (one round of atomics per pass); with little pending it sleeps,
-// so it takes few issue slots from the ant waves that share its SIMD (a
-// ring holds many steps of slack).
-template <bool ATOMIC>
-__device__ __forceinline__ void ring_updater(const Dev &D, const Iter &A, UpdRing &q, int lane,
-                                             int na) {
-  static_assert(kQAnts * 8 == 64, "one pass covers 8 entries of each ring");
-  const int w = lane >> 3, slot = lane & 7;
-  uint32_t tl = 0;  // this lane's ring tail (lanes of a ring agree)
-  uint32_t retries = 0, idle = 0;
-  while (true) {
-    // read `done` before the heads: an ant wave publishes its last head
-    // before it counts itself done
-    const uint32_t done = uni((int)lds_ld(&q.done));
-    __atomic_signal_fence(__ATOMIC_SEQ_CST);
-    const uint32_t h = w < na ? lds_ld(&q.head[w]) : tl;
-    const uint32_t cnt = min(h - tl, 8u);
-    const bool any = __ballot(cnt > 0u) != 0;
-    if ((uint32_t)slot < cnt) {
-      const uint4 e = q.ent[w][(tl + slot) & (kQRing - 1)];
-      const int u = (int)(e.x & 0xffffu), v = (int)(e.x >> 16), k = (int)e.y;
-      float *pf = home(D, u, v, k);
-      float *pr = home(D, v, u, reverse_pos(D, u, k, (int)e.w));
-      if (ATOMIC) {
-        retries += cas_apply(pf, e.z, A.a_loc, A.b_loc);
-        retries += cas_apply(pr, e.z, A.a_loc, A.b_loc);
-      } else {
-        const float y = fmaf(A.a_loc, __uint_as_float(e.z), A.b_loc);
-        __hip_atomic_store(pf, y, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        __hip_atomic_store(pr, y, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-      }
-    }
-    tl += cnt;
-    __atomic_signal_fence(__ATOMIC_SEQ_CST);
-    if (slot == 0 && cnt) lds_st(&q.tail[w], tl);
-    if (any) {
-      idle = 0;
-      // fewer than 4 pending entries in every ring: let them accumulate
-      if (__ballot(cnt >= 4u) == 0) __builtin_amdgcn_s_sleep(16);
-    } else {
-      if (done == (uint32_t)na) break;
-      __builtin_amdgcn_s_sleep(16);
-      if (++idle > kQSpin) {
-        if (lane == 0)
-          __hip_atomic_store(D.sync + 1, 2u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        break;
-      }
-    }
-  }
-  if (retries) atomicAdd(&D.counters[6], (unsigned long long)retries);
-}
-
-// ---------------------------------------------------------------------------
 // Asynchronous construction, dense memory: one launch per iteration, one ant
 // per wave, no waiting for the other ants.  Each crossing gets the local
 // update of Eq. 3 as a compare-and-swap of the exact map on both directed
@@ -768,13 +635,10 @@ __device__ __forceinline__ void ring_updater(const Dev &D, const Iter &A, UpdRin
 // ATOMIC = false is the paper's unsynchronised variant (ACS-GPU-Alt,
 // Sec. 3.1.2): each entry gets the map of the value the ant read, by a plain
 // (not read-modify-write) store, and updates that race with it are lost.
-// QUEUE = true hands steps 2's updates to the block's updater wave instead.
 // ---------------------------------------------------------------------------
-template <bool ATOMIC, bool QUEUE = false>
+template <bool ATOMIC>
 __device__ __forceinline__ void ant_async_dense(const Dev &D, const Iter &A, int ant,
-                                                uint32_t *vis, int lane, UpdRing *q = nullptr,
-                                                int qw = 0) {
-  uint32_t qhead = 0, qroom = kQRing;
+                                                uint32_t *vis, int lane) {
   uint32_t uleft = A.lperiod;  // steps until the next local update
   const int n = D.n, cl = D.cl, ldn = D.ldn;
   const int W = (n + 31) >> 5;
@@ -790,7 +654,6 @@ __device__ __forceinline__ void ant_async_dense(const Dev &D, const Iter &A, int
 
   int cur = start, prev = -1;
   float *fwd = nullptr;  // home of the forward entry of the previous move
-  int fk = -1;           // its candidate position
   float fval = 0.f;      // its value as read by the selection
   int64_t len = 0;
   // decisions by kind, 21 bits each: greedy | roulette << 21 | fallback << 42
@@ -817,18 +680,7 @@ __device__ __forceinline__ void ant_async_dense(const Dev &D, const Iter &A, int
     // no later wait for this record also waits for those updates
     __asm__ volatile("" ::"v"(c.w), "v"((int)c.unv));
     // 2. updates of the previous move (prev, cur), selected at step t - 1
-    if (QUEUE && t > 1 && --uleft == 0) {
-      uleft = A.lperiod;
-      // the reverse position comes from the table, except after a fallback
-      // move (cur is not a candidate of prev, so the table has no entry):
-      // then from cur's record
-      int kr = -2;
-      if (fk < 0) {
-        const uint64_t b = __ballot(lane < cl && rec.x == (uint32_t)prev);
-        kr = b ? uni((int)__ffsll((unsigned long long)b) - 1) : -1;
-      }
-      c_retry += ring_push<ATOMIC>(D, A, *q, qw, qhead, qroom, lane, prev, cur, fk, kr, fval);
-    } else if (!QUEUE && t > 1 && --uleft == 0) {
+    if (t > 1 && --uleft == 0) {
       uleft = A.lperiod;
       const uint64_t b = __ballot(lane < cl && rec.x == (uint32_t)prev);
       const int kr = b ? uni((int)__ffsll((unsigned long long)b) - 1) : -1;
@@ -862,8 +714,7 @@ __device__ __forceinline__ void ant_async_dense(const Dev &D, const Iter &A, int
     clen += p.d;
     // 4. record of the next city
     rec = D.crec[(size_t)p.next * cl + kl];
-    if (!QUEUE) fwd = home(D, cur, p.next, p.k);
-    fk = p.k;
+    fwd = home(D, cur, p.next, p.k);
     fval = p.tval;
     prev = cur;
     cur = p.next;
@@ -878,10 +729,7 @@ __device__ __forceinline__ void ant_async_dense(const Dev &D, const Iter &A, int
     const int k1 = cand_pos(D, cur, start, lane);
     const int k2 = cand_pos(D, start, cur, lane);
     float *h = lane == 0 ? home(D, cur, start, k1) : home(D, start, cur, k2);
-    if (QUEUE) {
-      c_retry += ring_push<ATOMIC>(D, A, *q, qw, qhead, qroom, lane, cur, start, k1, k2,
-                                   __uint_as_float(rdlane(__float_as_uint(tau_load(h)), 0)));
-    } else if (lane < 2) {
+    if (lane < 2) {
       if (ATOMIC)
         c_retry += cas_apply(h, __float_as_uint(tau_load(h)), al, bl);
       else
@@ -909,67 +757,358 @@ __global__ __launch_bounds__(256) void k_construct_async_dense(Dev D, Iter A) {
   ant_async_dense<ATOMIC>(D, A, ant, smem + wv * ((D.n + 31) >> 5), lane);
 }
 
-// One instance, updates through the block's rings: waves 0..na-1 are ants
-// blockIdx.x * na + wave, wave na (the last) applies their updates.  The
-// host picks na so that every compute unit holds about the same number of
-// ants (the slowest unit sets the iteration time).
+// ---------------------------------------------------------------------------
+// Local updates handed to an updater wave, 64 crossings at a time.  gfx950
+// counts loads, stores and atomics of a wave in one in-order counter, so a
+// wave that waits for its next record also waits for every update it issued
+// before that load.  The ant wave therefore issues no update: the crossing
+// selected at step t goes into lane t % 64 of an entry held in registers,
+// and at the end of each 64-step chunk one LDS store of all lanes hands the
+// chunk to the block's updater wave, which applies Eq. 3 to both directed
+// entries of each crossed edge.
+// Each ant wave owns kQChunks chunk slots (single producer, single consumer):
+// it writes a chunk, then publishes its head; the updater reads a chunk,
+// then publishes its tail.  LDS instructions of one wave take effect in
+// issue order, so a published head covers a chunk already written, and a
+// published tail frees a chunk already read.  Every wait is bounded: on
+// exhaustion the error flag (2) is raised and the ant applies its chunks
+// itself, so every wave still reaches its end.
+//
+// Entry of the crossing u -> v: {u | v << 16, k, x, kr}: k the position of v
+// in u's candidate list (-1 if none), x the pheromone of (u, v) as the ant
+// read it, kr the position of u in v's list: -2 = look it up in the reverse
+// table (v is the k-th candidate of u), -3 = search v's list (v is not a
+// candidate of u), else kr itself (-1: u is not a candidate of v).  Lanes
+// without a crossing hold x = kNoEntry in the first word.
+// ---------------------------------------------------------------------------
+constexpr int kQAnts = 8;    // at most this many ant waves per block
+constexpr int kQChunks = 4;  // chunk slots per ant wave
+constexpr uint32_t kQSpin = 1u << 22;
+constexpr uint32_t kQIdle = 1u << 20;
+constexpr uint32_t kNoEntry = 0xffffffffu;
+// fourth word of a buffer resource for untyped dword loads (gfx9 family)
+constexpr int kBufWord3 = 0x00020000;
+
+struct QRing {
+  uint4 *ent;      // [ant wave][kQChunks][64]
+  uint32_t *head;  // chunks written, per ant wave
+  uint32_t *tail;  // chunks read by the updater, per ant wave
+  uint32_t *done;  // ant waves that have pushed their last chunk
+};
+
+__device__ __forceinline__ uint32_t lds_ld(const uint32_t *p) {
+  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+}
+__device__ __forceinline__ void lds_st(uint32_t *p, uint32_t v) {
+  __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+}
+
+// Eq. 3 on both directed entries of the crossings held by the lanes of the
+// wave (one entry per lane, all lanes active).  Compare-and-swap mode: each
+// entry with x as the expected value (the two entries of an edge receive the
+// same maps, so they hold the same value once the updates in flight have
+// landed; a compare-and-swap that finds another value retries with it).
+// Unsynchronised mode (ACS-GPU-Alt, Sec. 3.1.2): the forward entry is read,
+// its map stored to both, and updates landing in between are lost.  Returns
+// this lane's retries.
 template <bool ATOMIC>
+__device__ __forceinline__ uint32_t apply_entries(const Dev &D, const Iter &A, uint4 e,
+                                                  int lane) {
+  const bool valid = e.x != kNoEntry;
+  const int u = (int)(e.x & 0xffffu), v = (int)(e.x >> 16), k = (int)e.y;
+  int kr = (int)e.w;
+  // after a fallback move: the whole wave searches v's list, once per entry
+  uint64_t need = __ballot(valid && kr == -3);
+  while (need) {
+    const int l = (int)__ffsll((unsigned long long)need) - 1;
+    need &= need - 1;
+    const int r = cand_pos(D, (int)rdlane((uint32_t)v, l), (int)rdlane((uint32_t)u, l), lane);
+    if (lane == l) kr = r;
+  }
+  if (!valid) return 0;
+  if (kr == -2) kr = (int)D.rpos[(size_t)u * D.cl + k];
+  float *pf = home(D, u, v, k);
+  float *pr = home(D, v, u, kr);
+  const float al = A.a_loc, bl = A.b_loc;
+  if (ATOMIC) {
+    // both first attempts in flight together
+    const unsigned int nw = __float_as_uint(fmaf(al, __uint_as_float(e.z), bl));
+    const unsigned int of = atomicCAS(reinterpret_cast<unsigned int *>(pf), e.z, nw);
+    const unsigned int orv = atomicCAS(reinterpret_cast<unsigned int *>(pr), e.z, nw);
+    uint32_t r = 0;
+    if (of != e.z) r += 1 + cas_apply(pf, of, al, bl);
+    if (orv != e.z) r += 1 + cas_apply(pr, orv, al, bl);
+    return r;
+  }
+  const float y = fmaf(al, tau_load(pf), bl);
+  __hip_atomic_store(pf, y, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  __hip_atomic_store(pr, y, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  return 0;
+}
+
+// Hands the wave's chunk of entries to the updater (or, once the updater has
+// stopped draining, applies it in place).  `head`, `tail` (last tail seen)
+// and `direct` are the wave's own.  Returns this lane's retries.
+template <bool ATOMIC>
+__device__ __forceinline__ uint32_t chunk_push(const Dev &D, const Iter &A, const QRing &q, int w,
+                                               uint32_t &head, uint32_t &tail, bool &direct,
+                                               int lane, uint4 e) {
+  if (__ballot(e.x != kNoEntry) == 0) return 0;
+  if (!direct && head - tail >= (uint32_t)kQChunks) {
+    uint32_t spins = 0;
+    while (true) {
+      tail = (uint32_t)uni((int)lds_ld(q.tail + w));
+      if (head - tail < (uint32_t)kQChunks) break;
+      __builtin_amdgcn_s_sleep(2);
+      if (++spins > kQSpin) {
+        if (lane == 0)
+          __hip_atomic_store(D.sync + 1, 2u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        direct = true;
+        break;
+      }
+    }
+  }
+  if (direct) return apply_entries<ATOMIC>(D, A, e, lane);
+  q.ent[((size_t)w * kQChunks + (head & (kQChunks - 1))) * 64 + lane] = e;
+  head += 1;
+  __atomic_signal_fence(__ATOMIC_SEQ_CST);
+  if (lane == 0) lds_st(q.head + w, head);
+  return 0;
+}
+
+// The updater wave: applies the chunks of every ant wave of its block until
+// all `na` ant waves are done and every chunk is applied.  A chunk arrives
+// about every 64 steps of an ant, so between chunks the wave sleeps and
+// takes almost no issue slots from the ant waves that share its SIMD.
+template <bool ATOMIC>
+__device__ __forceinline__ void chunk_updater(const Dev &D, const Iter &A, const QRing &q,
+                                              int lane, int na) {
+  static_assert((kQChunks & (kQChunks - 1)) == 0, "chunk slots: a power of two");
+  uint32_t retries = 0, idle = 0;
+  while (true) {
+    // read `done` before the heads: an ant wave publishes its last head
+    // before it counts itself done
+    const uint32_t done = (uint32_t)uni((int)lds_ld(q.done));
+    __atomic_signal_fence(__ATOMIC_SEQ_CST);
+    bool any = false;
+    for (int w = 0; w < na; ++w) {
+      const uint32_t h = (uint32_t)uni((int)lds_ld(q.head + w));
+      const uint32_t tl = (uint32_t)uni((int)lds_ld(q.tail + w));
+      if (h == tl) continue;
+      any = true;
+      const uint4 e = q.ent[((size_t)w * kQChunks + (tl & (kQChunks - 1))) * 64 + lane];
+      __atomic_signal_fence(__ATOMIC_SEQ_CST);
+      if (lane == 0) lds_st(q.tail + w, tl + 1);
+      retries += apply_entries<ATOMIC>(D, A, e, lane);
+    }
+    if (any) {
+      idle = 0;
+      continue;
+    }
+    if (done == (uint32_t)na) break;
+    __builtin_amdgcn_s_sleep(127);
+    if (++idle > kQIdle) {
+      if (lane == 0)
+        __hip_atomic_store(D.sync + 1, 2u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      break;
+    }
+  }
+  if (retries) atomicAdd(&D.counters[6], (unsigned long long)retries);
+}
+
+// ---------------------------------------------------------------------------
+// Asynchronous construction, dense memory, local updates through the
+// block's updater wave.  The step holds only what Alg. 2 needs: weigh the
+// current city's record, choose (Eq. 1 or Eq. 2 over the candidate set, the
+// fallback when it is empty), mark, issue the next record's load, and note
+// the crossing in the chunk entry.  Records come by buffer loads (the lane's
+// offset fixed, the row's a scalar; a read outside the table returns zeros
+// instead of faulting).  HALF: every candidate list fits lanes 0..31.
+// Decisions are the same as those of ant_async_dense.
+// ---------------------------------------------------------------------------
+template <bool ATOMIC, bool HALF>
+__device__ __forceinline__ void ant_queued(const Dev &D, const Iter &A, int ant, uint32_t *vis,
+                                           int lane, const QRing &q, int qw) {
+  const int n = D.n, cl = D.cl;
+  const int W = (n + 31) >> 5;
+  const uint64_t clmask = cl >= 64 ? ~0ull : (1ull << cl) - 1;
+  const int koff = (lane < cl ? lane : cl - 1) * 16;
+  const int rowb = cl * 16;  // bytes per record row
+  const __amdgpu_buffer_rsrc_t crs =
+      __builtin_amdgcn_make_buffer_rsrc(const_cast<uint4 *>(D.crec), 0, n * rowb, kBufWord3);
+  auto load_rec = [&](int city) {
+    const auto r = __builtin_amdgcn_raw_buffer_load_b128(crs, koff, city * rowb, 0);
+    return make_uint4(r[0], r[1], r[2], r[3]);
+  };
+
+  for (int w = lane; w < W; w += 64) vis[w] = 0u;
+  uint4 draws = philox_batch(A, ant, 0, lane);
+  const int start = (int)__umulhi(rdlane(draws.z, 0), (uint32_t)n);
+  if (lane == 0) vis[start >> 5] |= 1u << (start & 31);
+  uint4 rec = load_rec(start);
+
+  uint32_t qhead = 0, qtail = 0, c_retry = 0, c_roul = 0, c_fb = 0;
+  bool qdirect = false;
+  uint64_t c_fbu = 0;
+  int64_t len = 0;
+  int cur = start;
+  // steps in chunks of 64: lane l holds step t0 + l's draw, tour entry and
+  // crossing, so a chunk's draws come from one Philox batch, and its tour
+  // entries and crossings leave in one store each
+  for (int t0 = 0; t0 < n; t0 += 64) {
+    if (t0 > 0) draws = philox_batch(A, ant, t0, lane);
+    const int lt = lane + t0;
+    // local updates after every lperiod-th selected edge
+    const int lu = lt % (int)A.lperiod == 0 ? lt : -1;
+    uint4 e = make_uint4(kNoEntry, 0u, 0u, 0u);
+    int tb = start;
+    uint32_t clen = 0;  // at most 64 distances below 2^16 each
+    const int tend = min(t0 + 64, n);
+    for (int t = t0 > 0 ? t0 : 1; t < tend; ++t) {
+      // lanes >= cl repeat candidate cl - 1 (same city, same weight), so
+      // they never change a maximum or a prefix sum of positions < cl; the
+      // candidate mask leaves them out of every choice
+      const uint32_t word = vis[rec.x >> 5];
+      const bool unv = !((word >> (rec.x & 31)) & 1u);
+      const uint64_t umask = __builtin_amdgcn_ballot_w64(unv) & clmask;
+      int next, k;
+      uint32_t d, tv;
+      if (umask == 0) {
+        const Pick p = fallback_dense<false>(D, vis, cur, lane);
+        next = p.next;
+        k = -1;
+        d = p.d;
+        tv = __float_as_uint(p.tval);
+        ++c_fb;
+        c_fbu += (uint64_t)(n - t);
+      } else {
+        // tau * eta^beta >= 0, so its bit pattern orders like the value
+        const float w = unv ? __uint_as_float(rec.w) * __uint_as_float(rec.z) : 0.f;
+        if ((rdlane(draws.x, t & 63) >> 8) < A.q0_24) {
+          // Eq. 1: maximum weight, lowest position
+          const uint32_t wb = __float_as_uint(w);
+          const uint32_t mx = HALF ? half_umax_u(wb) : wave_umax_u(wb);
+          k = (int)__builtin_ctzll(__builtin_amdgcn_ballot_w64(wb == mx) & umask);
+        } else {
+          // Eq. 2 by roulette: inclusive Hillis-Steele scan over the
+          // positions (offsets 1, 2, 4, ... < cl), r = u * total, first
+          // member of the candidate set whose prefix sum exceeds r
+          float P = w;
+          for (int off = 1; off < cl; off <<= 1) {
+            const float o = __shfl_up(P, off, 64);
+            if (lane >= off) P = P + o;
+          }
+          const float total = __uint_as_float(rdlane(__float_as_uint(P), cl - 1));
+          const float r = ((float)(rdlane(draws.y, t & 63) >> 8) * 0x1p-24f) * total;
+          const uint64_t sel = __builtin_amdgcn_ballot_w64(P > r) & umask;
+          k = sel ? (int)__builtin_ctzll(sel) : 63 - (int)__builtin_clzll(umask);
+          ++c_roul;
+        }
+        next = (int)rdlane(rec.x, k);
+        d = rdlane(rec.y, k);
+        tv = rdlane(rec.w, k);
+      }
+      if (lane == 0) mark(vis, next);
+      rec = load_rec(next);
+      tb = lt == t ? next : tb;
+      if (lu == t)
+        e = make_uint4((uint32_t)cur | ((uint32_t)next << 16), (uint32_t)k, tv,
+                       (uint32_t)(k >= 0 ? -2 : -3));
+      clen += d;
+      cur = next;
+    }
+    len += clen;
+    if (lane < tend - t0) D.tours[(size_t)ant * n + lt] = tb;
+    if (tend == n) {
+      // closing edge (cur, start), every ant: both positions searched, the
+      // value read fresh; it takes lane n - t0, or a chunk of its own
+      const int k1 = cand_pos(D, cur, start, lane);
+      const int k2 = cand_pos(D, start, cur, lane);
+      const uint32_t x = rdlane(__float_as_uint(tau_load(home(D, cur, start, k1))), 0);
+      const uint4 ce =
+          make_uint4((uint32_t)cur | ((uint32_t)start << 16), (uint32_t)k1, x, (uint32_t)k2);
+      if (n - t0 == 64) {
+        c_retry += chunk_push<ATOMIC>(D, A, q, qw, qhead, qtail, qdirect, lane, e);
+        e = make_uint4(kNoEntry, 0u, 0u, 0u);
+      }
+      if (lane == ((n - t0) & 63)) e = ce;
+      len += D.dist[(size_t)cur * D.ldn + start];
+    }
+    c_retry += chunk_push<ATOMIC>(D, A, q, qw, qhead, qtail, qdirect, lane, e);
+  }
+  c_retry = (uint32_t)uni((int)wave_sum_u(c_retry));
+  if (lane == 0) {
+    D.lens[ant] = len;
+    add_counters(D, (uint32_t)(n - 1) - c_roul - c_fb, c_roul, c_fb, c_fbu, c_retry);
+  }
+}
+
+// One instance, updates through the block's updater wave: waves 0..na-1 are
+// ants blockIdx.x * na + wave, wave na (the last) applies their chunks.  The
+// host picks na so that every compute unit holds about the same number of
+// ants (the slowest unit sets the iteration time).  Dynamic LDS: the chunk
+// slots of the na ant waves, then their visited bitmaps.
+template <bool ATOMIC, bool HALF>
 __global__ __launch_bounds__(64 * (kQAnts + 1)) void k_construct_async_dense_q(Dev D, Iter A) {
-  extern __shared__ uint32_t smem[];
-  __shared__ UpdRing q;
+  extern __shared__ uint4 qsm[];
+  __shared__ uint32_t qhd[kQAnts], qtl[kQAnts], qdone;
   const int lane = threadIdx.x & 63;
   const int wv = threadIdx.x >> 6;
   const int na = (int)(blockDim.x >> 6) - 1;
   if (threadIdx.x < kQAnts) {
-    q.head[threadIdx.x] = 0;
-    q.tail[threadIdx.x] = 0;
+    qhd[threadIdx.x] = 0;
+    qtl[threadIdx.x] = 0;
   }
-  if (threadIdx.x == 0) q.done = 0;
+  if (threadIdx.x == 0) qdone = 0;
   __syncthreads();
+  const QRing q{qsm, qhd, qtl, &qdone};
   if (wv == na) {
-    ring_updater<ATOMIC>(D, A, q, lane, na);
+    chunk_updater<ATOMIC>(D, A, q, lane, na);
     return;
   }
+  uint32_t *vis = reinterpret_cast<uint32_t *>(qsm + (size_t)na * kQChunks * 64) +
+                  wv * ((D.n + 31) >> 5);
   const int ant = uni(blockIdx.x * na + wv);
-  if (ant < D.m)
-    ant_async_dense<ATOMIC, true>(D, A, ant, smem + wv * ((D.n + 31) >> 5), lane, &q, wv);
+  if (ant < D.m) ant_queued<ATOMIC, HALF>(D, A, ant, vis, lane, q, wv);
   __atomic_signal_fence(__ATOMIC_SEQ_CST);
-  if (lane == 0) atomicAdd(&q.done, 1u);
+  if (lane == 0) atomicAdd(&qdone, 1u);
 }
 
-// Many instances in one launch, updates through each block's rings: block b
-// runs ants bitems[b].y .. bitems[b].y + kBatchQAnts - 1 of instance
-// bitems[b].x (one instance per block, so the updater wave works with one
-// descriptor), wave kBatchQAnts applies their updates.
+// Many instances in one launch, updates through each block's updater wave:
+// block b runs ants bitems[b].y .. bitems[b].y + kBatchQAnts - 1 of
+// instance bitems[b].x (one instance per block, so the updater wave works
+// with one descriptor), wave kBatchQAnts applies their chunks.
 constexpr int kBatchQAnts = kBatchQAntsPerBlock;
 
-template <bool ATOMIC>
+template <bool ATOMIC, bool HALF>
 __global__ __launch_bounds__(64 * (kBatchQAnts + 1)) void k_construct_async_batch_q(
     const Dev *devs, const Iter *iters, const int2 *bitems, int nb, int wmax) {
-  extern __shared__ uint32_t smem[];
-  __shared__ UpdRing q;
+  extern __shared__ uint4 qsm[];
+  __shared__ uint32_t qhd[kBatchQAnts], qtl[kBatchQAnts], qdone;
   const int lane = threadIdx.x & 63;
   const int wv = threadIdx.x >> 6;
-  if (threadIdx.x < kQAnts) {
-    q.head[threadIdx.x] = 0;
-    q.tail[threadIdx.x] = 0;
+  if (threadIdx.x < kBatchQAnts) {
+    qhd[threadIdx.x] = 0;
+    qtl[threadIdx.x] = 0;
   }
-  if (threadIdx.x == 0) q.done = 0;
+  if (threadIdx.x == 0) qdone = 0;
   __syncthreads();
   const int b = blockIdx.x;  // the grid has exactly nb blocks
   const int2 item = bitems[b];
   const int inst = uni(item.x);
   const Dev D = devs[inst];
   const Iter A = iters[inst];
+  const QRing q{qsm, qhd, qtl, &qdone};
   if (wv == kBatchQAnts) {
-    ring_updater<ATOMIC>(D, A, q, lane, kBatchQAnts);
+    chunk_updater<ATOMIC>(D, A, q, lane, kBatchQAnts);
     return;
   }
+  uint32_t *vis = reinterpret_cast<uint32_t *>(qsm + (size_t)kBatchQAnts * kQChunks * 64) +
+                  wv * wmax;
   const int ant = uni(item.y + wv);
-  if (ant < D.m)
-    ant_async_dense<ATOMIC, true>(D, A, ant, smem + wv * wmax, lane, &q, wv);
+  if (ant < D.m) ant_queued<ATOMIC, HALF>(D, A, ant, vis, lane, q, wv);
   __atomic_signal_fence(__ATOMIC_SEQ_CST);
-  if (lane == 0) atomicAdd(&q.done, 1u);
+  if (lane == 0) atomicAdd(&qdone, 1u);
 }
 
 // Many instances in one launch: wave w builds the tour of ant items[w].y of
@@ -2001,11 +2140,17 @@ hipError_t launch_construct(const Dev &d, const Iter &it, int mode, int memory, 
     const int bpc = std::max(2, (per_cu + kQAnts - 1) / kQAnts);
     const int na = std::max(1, std::min(kQAnts, (d.m + cus * bpc - 1) / (cus * bpc)));
     const dim3 gq((d.m + na - 1) / na), bq(64 * (na + 1));
-    const size_t lq = (size_t)na * ((d.n + 31) / 32) * sizeof(uint32_t);
-    if (atomic)
-      hipLaunchKernelGGL(k_construct_async_dense_q<true>, gq, bq, lq, s, d, it);
+    const size_t lq = (size_t)na * kQChunks * 64 * sizeof(uint4) +
+                      (size_t)na * ((d.n + 31) / 32) * sizeof(uint32_t);
+    const bool half = d.cl <= 32;
+    if (atomic && half)
+      hipLaunchKernelGGL((k_construct_async_dense_q<true, true>), gq, bq, lq, s, d, it);
+    else if (atomic)
+      hipLaunchKernelGGL((k_construct_async_dense_q<true, false>), gq, bq, lq, s, d, it);
+    else if (half)
+      hipLaunchKernelGGL((k_construct_async_dense_q<false, true>), gq, bq, lq, s, d, it);
     else
-      hipLaunchKernelGGL(k_construct_async_dense_q<false>, gq, bq, lq, s, d, it);
+      hipLaunchKernelGGL((k_construct_async_dense_q<false, false>), gq, bq, lq, s, d, it);
   } else if (memory == 0 && lanes < 64) {
     const int g = 64 / lanes;
     const dim3 gg((d.m + apb * g - 1) / (apb * g));
@@ -2062,19 +2207,27 @@ hipError_t launch_best_global(const Dev &d, const Iter &it, int memory, hipStrea
 }
 
 hipError_t launch_batch_iteration(const Dev *devs, Iter *iters, const int2 *items, int nitems,
-                                  int count, int nmax, int mode, int lanes, int queued,
+                                  int count, int nmax, int clmax, int mode, int lanes, int queued,
                                   hipStream_t s) {
   const int apb = kAsyncBlock / 64;
   const int wmax = (nmax + 31) / 32;
   if (lanes == 64 && queued) {
-    const size_t lq = (size_t)kBatchQAnts * wmax * sizeof(uint32_t);
+    const size_t lq = (size_t)kBatchQAnts * kQChunks * 64 * sizeof(uint4) +
+                      (size_t)kBatchQAnts * wmax * sizeof(uint32_t);
     const dim3 gq(nitems), bq(64 * (kBatchQAnts + 1));
-    if (mode == 1)
-      hipLaunchKernelGGL(k_construct_async_batch_q<true>, gq, bq, lq, s, devs, iters, items,
-                         nitems, wmax);
+    const bool half = clmax <= 32;
+    if (mode == 1 && half)
+      hipLaunchKernelGGL((k_construct_async_batch_q<true, true>), gq, bq, lq, s, devs, iters,
+                         items, nitems, wmax);
+    else if (mode == 1)
+      hipLaunchKernelGGL((k_construct_async_batch_q<true, false>), gq, bq, lq, s, devs, iters,
+                         items, nitems, wmax);
+    else if (half)
+      hipLaunchKernelGGL((k_construct_async_batch_q<false, true>), gq, bq, lq, s, devs, iters,
+                         items, nitems, wmax);
     else
-      hipLaunchKernelGGL(k_construct_async_batch_q<false>, gq, bq, lq, s, devs, iters, items,
-                         nitems, wmax);
+      hipLaunchKernelGGL((k_construct_async_batch_q<false, false>), gq, bq, lq, s, devs, iters,
+                         items, nitems, wmax);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(k_best_batch, dim3(count), dim3(1024), 0, s, devs, iters);
