@@ -804,13 +804,15 @@ __device__ __forceinline__ void lds_st(uint32_t *p, uint32_t v) {
 }
 
 // Eq. 3 on both directed entries of the crossings held by the lanes of the
-// wave (one entry per lane, all lanes active).  Compare-and-swap mode: each
-// entry with x as the expected value (the two entries of an edge receive the
-// same maps, so they hold the same value once the updates in flight have
-// landed; a compare-and-swap that finds another value retries with it).
-// Unsynchronised mode (ACS-GPU-Alt, Sec. 3.1.2): the forward entry is read,
-// its map stored to both, and updates landing in between are lost.  Returns
-// this lane's retries.
+// wave (one entry per lane, all lanes active).  Compare-and-swap mode: the
+// forward entry with x as the expected value, then the reverse entry with
+// the value the forward entry held before the update as the expected value
+// (the two entries of an edge receive the same maps, so they hold the same
+// value once the updates in flight have landed; a compare-and-swap that
+// finds another value retries with it).  Unsynchronised mode (ACS-GPU-Alt,
+// Sec. 3.1.2): the forward entry is read and its map stored to both by
+// plain accesses; updates landing in between are lost, and other compute
+// units may see the stores late.  Returns this lane's retries.
 template <bool ATOMIC>
 __device__ __forceinline__ uint32_t apply_entries(const Dev &D, const Iter &A, uint4 e,
                                                   int lane) {
@@ -831,18 +833,23 @@ __device__ __forceinline__ uint32_t apply_entries(const Dev &D, const Iter &A, u
   float *pr = home(D, v, u, kr);
   const float al = A.a_loc, bl = A.b_loc;
   if (ATOMIC) {
-    // both first attempts in flight together
-    const unsigned int nw = __float_as_uint(fmaf(al, __uint_as_float(e.z), bl));
-    const unsigned int of = atomicCAS(reinterpret_cast<unsigned int *>(pf), e.z, nw);
-    const unsigned int orv = atomicCAS(reinterpret_cast<unsigned int *>(pr), e.z, nw);
+    // the value the ant read may be stale; the value the forward entry held
+    // just before its update is a fresh guess for the reverse entry
+    unsigned int seen = e.z;
     uint32_t r = 0;
-    if (of != e.z) r += 1 + cas_apply(pf, of, al, bl);
-    if (orv != e.z) r += 1 + cas_apply(pr, orv, al, bl);
-    return r;
+    while (true) {
+      const unsigned int nw = __float_as_uint(fmaf(al, __uint_as_float(seen), bl));
+      const unsigned int old = atomicCAS(reinterpret_cast<unsigned int *>(pf), seen, nw);
+      if (old == seen) break;
+      seen = old;
+      ++r;
+    }
+    return r + cas_apply(pr, seen, al, bl);
   }
-  const float y = fmaf(al, tau_load(pf), bl);
-  __hip_atomic_store(pf, y, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-  __hip_atomic_store(pr, y, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  const float y = fmaf(al,
+                       __hip_atomic_load(pf, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP), bl);
+  __hip_atomic_store(pf, y, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+  __hip_atomic_store(pr, y, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
   return 0;
 }
 
