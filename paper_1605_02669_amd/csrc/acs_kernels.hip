@@ -339,6 +339,34 @@ __global__ __launch_bounds__(256) void k_rpos(Dev D) {
   const_cast<int8_t *>(D.rpos)[e] = (int8_t)r;
 }
 
+// After a construction whose local updates went to canonical homes: the
+// value of each candidate slot that is a canonical home goes to the other
+// entry of its edge (the slot of the same edge in the other city's record
+// when each lists the other and this city is the smaller, else the dense
+// entry (v, u)).
+__device__ __forceinline__ void mirror_slot(const Dev &D, size_t e) {
+  const int u = (int)(e / (size_t)D.cl);
+  const uint4 r = D.crec[e];
+  const int v = (int)r.x, kr = (int)D.rpos[e];
+  if (kr >= 0) {
+    if (u < v) const_cast<uint4 *>(D.crec)[(size_t)v * D.cl + kr].w = r.w;
+  } else {
+    D.tau[(size_t)v * D.ldn + u] = __uint_as_float(r.w);
+  }
+}
+
+__global__ __launch_bounds__(256) void k_mirror_dense(Dev D) {
+  const size_t e = (size_t)blockIdx.x * 256 + threadIdx.x;
+  if (e < (size_t)D.n * D.cl) mirror_slot(D, e);
+}
+
+// The same for every instance of a batch (blockIdx.y = instance).
+__global__ __launch_bounds__(256) void k_mirror_batch(const Dev *devs) {
+  const Dev D = devs[blockIdx.y];
+  const size_t e = (size_t)blockIdx.x * 256 + threadIdx.x;
+  if (e < (size_t)D.n * D.cl) mirror_slot(D, e);
+}
+
 __global__ __launch_bounds__(256) void k_init(Dev D, float tau0) {
   const size_t e = (size_t)blockIdx.x * 256 + threadIdx.x;
   const size_t nd = (size_t)D.n * D.ldn;
@@ -758,31 +786,35 @@ __global__ __launch_bounds__(256) void k_construct_async_dense(Dev D, Iter A) {
 }
 
 // ---------------------------------------------------------------------------
-// Local updates handed to an updater wave, 64 crossings at a time.  gfx950
-// counts loads, stores and atomics of a wave in one in-order counter, so a
-// wave that waits for its next record also waits for every update it issued
-// before that load.  The ant wave therefore issues no update: the crossing
-// selected at step t goes into lane t % 64 of an entry held in registers,
-// and at the end of each 64-step chunk one LDS store of all lanes hands the
-// chunk to the block's updater wave, which applies Eq. 3 to both directed
-// entries of each crossed edge.
-// Each ant wave owns kQChunks chunk slots (single producer, single consumer):
-// it writes a chunk, then publishes its head; the updater reads a chunk,
-// then publishes its tail.  LDS instructions of one wave take effect in
-// issue order, so a published head covers a chunk already written, and a
-// published tail frees a chunk already read.  Every wait is bounded: on
-// exhaustion the error flag (2) is raised and the ant applies its chunks
+// Local updates handed to an updater wave.  gfx950 counts loads, stores and
+// atomics of a wave in one in-order counter, so a wave that waits for its
+// next record also waits for every update it issued before that load.  The
+// ant wave therefore issues no update: the crossing selected at step t goes
+// into lane t % 64 of an entry held in registers, and every kQGroup steps one
+// LDS store of those lanes hands the group to the block's updater wave,
+// which applies Eq. 3 to both directed entries of each crossed edge.  An
+// update thus lands a few steps after its crossing (at most a group plus
+// the updater's sleep), where an ant that applied it itself would have
+// waited for it.
+// Each ant wave owns a ring of kQRing entries indexed by step (single
+// producer, single consumer): the entry of step t sits at t % kQRing; the
+// ant publishes head = the first step not yet written, the updater tail =
+// the first step not yet read.  LDS instructions of one wave take effect in
+// issue order, so a published head covers entries already written, and a
+// published tail frees entries already read.  Every wait is bounded: on
+// exhaustion the error flag (2) is raised and the ant applies its entries
 // itself, so every wave still reaches its end.
 //
 // Entry of the crossing u -> v: {u | v << 16, k, x, kr}: k the position of v
 // in u's candidate list (-1 if none), x the pheromone of (u, v) as the ant
 // read it, kr the position of u in v's list: -2 = look it up in the reverse
 // table (v is the k-th candidate of u), -3 = search v's list (v is not a
-// candidate of u), else kr itself (-1: u is not a candidate of v).  Lanes
-// without a crossing hold x = kNoEntry in the first word.
+// candidate of u), else kr itself (-1: u is not a candidate of v).  Steps
+// without an update hold x = kNoEntry in the first word.
 // ---------------------------------------------------------------------------
-constexpr int kQAnts = 8;    // at most this many ant waves per block
-constexpr int kQChunks = 4;  // chunk slots per ant wave
+constexpr int kQAnts = 8;     // at most this many ant waves per block
+constexpr int kQGroup = 16;   // steps per hand-over (divides 64)
+constexpr int kQRing = 256;   // ring entries per ant wave (power of 2, >= 64 + kQGroup)
 constexpr uint32_t kQSpin = 1u << 22;
 constexpr uint32_t kQIdle = 1u << 20;
 constexpr uint32_t kNoEntry = 0xffffffffu;
@@ -790,10 +822,10 @@ constexpr uint32_t kNoEntry = 0xffffffffu;
 constexpr int kBufWord3 = 0x00020000;
 
 struct QRing {
-  uint4 *ent;      // [ant wave][kQChunks][64]
-  uint32_t *head;  // chunks written, per ant wave
-  uint32_t *tail;  // chunks read by the updater, per ant wave
-  uint32_t *done;  // ant waves that have pushed their last chunk
+  uint4 *ent;      // [ant wave][kQRing]
+  uint32_t *head;  // per ant wave: first step not yet written
+  uint32_t *tail;  // per ant wave: first step not yet read by the updater
+  uint32_t *done;  // ant waves that have written their last entry
 };
 
 __device__ __forceinline__ uint32_t lds_ld(const uint32_t *p) {
@@ -804,15 +836,23 @@ __device__ __forceinline__ void lds_st(uint32_t *p, uint32_t v) {
 }
 
 // Eq. 3 on both directed entries of the crossings held by the lanes of the
-// wave (one entry per lane, all lanes active).  Compare-and-swap mode: the
-// forward entry with x as the expected value, then the reverse entry with
-// the value the forward entry held before the update as the expected value
-// (the two entries of an edge receive the same maps, so they hold the same
-// value once the updates in flight have landed; a compare-and-swap that
-// finds another value retries with it).  Unsynchronised mode (ACS-GPU-Alt,
-// Sec. 3.1.2): the forward entry is read and its map stored to both by
-// plain accesses; updates landing in between are lost, and other compute
-// units may see the stores late.  Returns this lane's retries.
+// wave (one entry per lane, all lanes active).
+// Compare-and-swap mode: one entry of the edge is its canonical home and
+// receives the exact map by compare-and-swap (x, the value the ant read, as
+// the first expected value; a compare-and-swap that finds another value
+// retries with it); the other entry gets the value just written by a
+// device-coherent store, for readers at the other endpoint.  The canonical home is a
+// candidate slot: the one in the record of the smaller city when each city
+// lists the other, else the only one; k_mirror_dense copies every canonical
+// value to its other entry when the construction ends, so both entries
+// then hold exactly the result of all the maps.  An edge with both entries
+// in the dense matrix (a fallback move between cities that do not list each
+// other) gets both compare-and-swaps.
+// Unsynchronised mode (ACS-GPU-Alt, Sec. 3.1.2): each entry is read and its
+// map stored back, both device-coherent but not as one atomic operation;
+// updates landing in between are lost.  (The value the ant read is several
+// steps old by now: storing its map would undo the updates made since.)
+// Returns this lane's retries.
 template <bool ATOMIC>
 __device__ __forceinline__ uint32_t apply_entries(const Dev &D, const Iter &A, uint4 e,
                                                   int lane) {
@@ -833,39 +873,45 @@ __device__ __forceinline__ uint32_t apply_entries(const Dev &D, const Iter &A, u
   float *pr = home(D, v, u, kr);
   const float al = A.a_loc, bl = A.b_loc;
   if (ATOMIC) {
-    // the value the ant read may be stale; the value the forward entry held
-    // just before its update is a fresh guess for the reverse entry
-    unsigned int seen = e.z;
+    const bool both_dense = k < 0 && kr < 0;
+    const bool fwd_canon = k >= 0 && (kr < 0 || u < v);
+    float *pc = fwd_canon || both_dense ? pf : pr;
+    float *po = fwd_canon || both_dense ? pr : pf;
+    unsigned int seen = e.z, nw;
     uint32_t r = 0;
     while (true) {
-      const unsigned int nw = __float_as_uint(fmaf(al, __uint_as_float(seen), bl));
-      const unsigned int old = atomicCAS(reinterpret_cast<unsigned int *>(pf), seen, nw);
+      nw = __float_as_uint(fmaf(al, __uint_as_float(seen), bl));
+      const unsigned int old = atomicCAS(reinterpret_cast<unsigned int *>(pc), seen, nw);
       if (old == seen) break;
       seen = old;
       ++r;
     }
-    return r + cas_apply(pr, seen, al, bl);
+    // the value the first entry held just before its update is a fresh
+    // guess for the second
+    if (both_dense) return r + cas_apply(po, seen, al, bl);
+    __hip_atomic_store(po, __uint_as_float(nw), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    return r;
   }
-  const float y = fmaf(al,
-                       __hip_atomic_load(pf, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP), bl);
-  __hip_atomic_store(pf, y, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
-  __hip_atomic_store(pr, y, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+  const float xf = tau_load(pf), xr = tau_load(pr);
+  __hip_atomic_store(pf, fmaf(al, xf, bl), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  __hip_atomic_store(pr, fmaf(al, xr, bl), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
   return 0;
 }
 
-// Hands the wave's chunk of entries to the updater (or, once the updater has
-// stopped draining, applies it in place).  `head`, `tail` (last tail seen)
-// and `direct` are the wave's own.  Returns this lane's retries.
+// Hands the entries of steps [g0, g1) (lanes g0 - t0 .. g1 - t0 - 1 of `e`)
+// to the updater, or, once the updater has stopped draining, applies them in
+// place.  `head` (= g0 on entry), `tail` (last tail seen) and `direct` are
+// the wave's own.  Returns this lane's retries.
 template <bool ATOMIC>
-__device__ __forceinline__ uint32_t chunk_push(const Dev &D, const Iter &A, const QRing &q, int w,
+__device__ __forceinline__ uint32_t group_push(const Dev &D, const Iter &A, const QRing &q, int w,
                                                uint32_t &head, uint32_t &tail, bool &direct,
-                                               int lane, uint4 e) {
-  if (__ballot(e.x != kNoEntry) == 0) return 0;
-  if (!direct && head - tail >= (uint32_t)kQChunks) {
+                                               int lane, uint4 e, int t0, int g1) {
+  const bool mine = lane + t0 >= (int)head && lane + t0 < g1;
+  if (!direct && (uint32_t)g1 - tail > (uint32_t)kQRing) {
     uint32_t spins = 0;
     while (true) {
       tail = (uint32_t)uni((int)lds_ld(q.tail + w));
-      if (head - tail < (uint32_t)kQChunks) break;
+      if ((uint32_t)g1 - tail <= (uint32_t)kQRing) break;
       __builtin_amdgcn_s_sleep(2);
       if (++spins > kQSpin) {
         if (lane == 0)
@@ -875,45 +921,59 @@ __device__ __forceinline__ uint32_t chunk_push(const Dev &D, const Iter &A, cons
       }
     }
   }
-  if (direct) return apply_entries<ATOMIC>(D, A, e, lane);
-  q.ent[((size_t)w * kQChunks + (head & (kQChunks - 1))) * 64 + lane] = e;
-  head += 1;
+  if (direct) {
+    head = (uint32_t)g1;
+    return apply_entries<ATOMIC>(D, A, mine ? e : make_uint4(kNoEntry, 0u, 0u, 0u), lane);
+  }
+  if (mine) q.ent[(size_t)w * kQRing + ((lane + t0) & (kQRing - 1))] = e;
+  head = (uint32_t)g1;
   __atomic_signal_fence(__ATOMIC_SEQ_CST);
   if (lane == 0) lds_st(q.head + w, head);
   return 0;
 }
 
-// The updater wave: applies the chunks of every ant wave of its block until
-// all `na` ant waves are done and every chunk is applied.  A chunk arrives
-// about every 64 steps of an ant, so between chunks the wave sleeps and
-// takes almost no issue slots from the ant waves that share its SIMD.
+// The updater wave: applies the entries of every ant wave of its block until
+// all `na` ant waves are done and every entry is applied.  One pass takes
+// the pending entries of all rings at once, up to 64 (ring after ring, each
+// from its tail), and applies them together, so the updates of different
+// rings share their memory round trips.  With nothing pending it sleeps, so
+// it takes few issue slots from the ant waves that share its SIMD.
 template <bool ATOMIC>
-__device__ __forceinline__ void chunk_updater(const Dev &D, const Iter &A, const QRing &q,
-                                              int lane, int na) {
-  static_assert((kQChunks & (kQChunks - 1)) == 0, "chunk slots: a power of two");
+__device__ __forceinline__ void ring_updater(const Dev &D, const Iter &A, const QRing &q,
+                                             int lane, int na) {
+  static_assert((kQRing & (kQRing - 1)) == 0 && kQRing >= 64 + kQGroup, "ring size");
+  uint32_t tl[kQAnts];  // the updater's own tails (wave-uniform)
+#pragma unroll
+  for (int w = 0; w < kQAnts; ++w) tl[w] = 0;
   uint32_t retries = 0, idle = 0;
   while (true) {
     // read `done` before the heads: an ant wave publishes its last head
     // before it counts itself done
     const uint32_t done = (uint32_t)uni((int)lds_ld(q.done));
     __atomic_signal_fence(__ATOMIC_SEQ_CST);
-    bool any = false;
-    for (int w = 0; w < na; ++w) {
+    uint32_t taken = 0;  // lanes given an entry so far
+    uint4 e = make_uint4(kNoEntry, 0u, 0u, 0u);
+#pragma unroll
+    for (int w = 0; w < kQAnts; ++w) {
+      if (w >= na) break;
       const uint32_t h = (uint32_t)uni((int)lds_ld(q.head + w));
-      const uint32_t tl = (uint32_t)uni((int)lds_ld(q.tail + w));
-      if (h == tl) continue;
-      any = true;
-      const uint4 e = q.ent[((size_t)w * kQChunks + (tl & (kQChunks - 1))) * 64 + lane];
-      __atomic_signal_fence(__ATOMIC_SEQ_CST);
-      if (lane == 0) lds_st(q.tail + w, tl + 1);
-      retries += apply_entries<ATOMIC>(D, A, e, lane);
+      const uint32_t c = min(h - tl[w], 64u - taken);
+      if ((uint32_t)lane >= taken && (uint32_t)lane < taken + c)
+        e = q.ent[(size_t)w * kQRing + ((tl[w] + (uint32_t)lane - taken) & (kQRing - 1))];
+      tl[w] += c;
+      taken += c;
     }
-    if (any) {
+    if (taken) {
+      __atomic_signal_fence(__ATOMIC_SEQ_CST);
+#pragma unroll
+      for (int w = 0; w < kQAnts; ++w)
+        if (w < na && lane == 0) lds_st(q.tail + w, tl[w]);
+      retries += apply_entries<ATOMIC>(D, A, e, lane);
       idle = 0;
       continue;
     }
     if (done == (uint32_t)na) break;
-    __builtin_amdgcn_s_sleep(127);
+    __builtin_amdgcn_s_sleep(32);
     if (++idle > kQIdle) {
       if (lane == 0)
         __hip_atomic_store(D.sync + 1, 2u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
@@ -960,8 +1020,8 @@ __device__ __forceinline__ void ant_queued(const Dev &D, const Iter &A, int ant,
   int64_t len = 0;
   int cur = start;
   // steps in chunks of 64: lane l holds step t0 + l's draw, tour entry and
-  // crossing, so a chunk's draws come from one Philox batch, and its tour
-  // entries and crossings leave in one store each
+  // crossing, so a chunk's draws come from one Philox batch and its tour
+  // entries leave in one store; its crossings leave kQGroup at a time
   for (int t0 = 0; t0 < n; t0 += 64) {
     if (t0 > 0) draws = philox_batch(A, ant, t0, lane);
     const int lt = lane + t0;
@@ -971,77 +1031,77 @@ __device__ __forceinline__ void ant_queued(const Dev &D, const Iter &A, int ant,
     int tb = start;
     uint32_t clen = 0;  // at most 64 distances below 2^16 each
     const int tend = min(t0 + 64, n);
-    for (int t = t0 > 0 ? t0 : 1; t < tend; ++t) {
-      // lanes >= cl repeat candidate cl - 1 (same city, same weight), so
-      // they never change a maximum or a prefix sum of positions < cl; the
-      // candidate mask leaves them out of every choice
-      const uint32_t word = vis[rec.x >> 5];
-      const bool unv = !((word >> (rec.x & 31)) & 1u);
-      const uint64_t umask = __builtin_amdgcn_ballot_w64(unv) & clmask;
-      int next, k;
-      uint32_t d, tv;
-      if (umask == 0) {
-        const Pick p = fallback_dense<false>(D, vis, cur, lane);
-        next = p.next;
-        k = -1;
-        d = p.d;
-        tv = __float_as_uint(p.tval);
-        ++c_fb;
-        c_fbu += (uint64_t)(n - t);
-      } else {
-        // tau * eta^beta >= 0, so its bit pattern orders like the value
-        const float w = unv ? __uint_as_float(rec.w) * __uint_as_float(rec.z) : 0.f;
-        if ((rdlane(draws.x, t & 63) >> 8) < A.q0_24) {
-          // Eq. 1: maximum weight, lowest position
-          const uint32_t wb = __float_as_uint(w);
-          const uint32_t mx = HALF ? half_umax_u(wb) : wave_umax_u(wb);
-          k = (int)__builtin_ctzll(__builtin_amdgcn_ballot_w64(wb == mx) & umask);
+    for (int g0 = t0 > 0 ? t0 : 1; g0 < tend;) {
+      const int g1 = min((g0 & ~(kQGroup - 1)) + kQGroup, tend);
+      for (int t = g0; t < g1; ++t) {
+        // lanes >= cl repeat candidate cl - 1 (same city, same weight), so
+        // they never change a maximum or a prefix sum of positions < cl; the
+        // candidate mask leaves them out of every choice
+        const uint32_t word = vis[rec.x >> 5];
+        const bool unv = !((word >> (rec.x & 31)) & 1u);
+        const uint64_t umask = __builtin_amdgcn_ballot_w64(unv) & clmask;
+        int next, k;
+        uint32_t d, tv;
+        if (umask == 0) {
+          const Pick p = fallback_dense<false>(D, vis, cur, lane);
+          next = p.next;
+          k = -1;
+          d = p.d;
+          tv = __float_as_uint(p.tval);
+          ++c_fb;
+          c_fbu += (uint64_t)(n - t);
         } else {
-          // Eq. 2 by roulette: inclusive Hillis-Steele scan over the
-          // positions (offsets 1, 2, 4, ... < cl), r = u * total, first
-          // member of the candidate set whose prefix sum exceeds r
-          float P = w;
-          for (int off = 1; off < cl; off <<= 1) {
-            const float o = __shfl_up(P, off, 64);
-            if (lane >= off) P = P + o;
+          // tau * eta^beta >= 0, so its bit pattern orders like the value
+          const float w = unv ? __uint_as_float(rec.w) * __uint_as_float(rec.z) : 0.f;
+          if ((rdlane(draws.x, t & 63) >> 8) < A.q0_24) {
+            // Eq. 1: maximum weight, lowest position
+            const uint32_t wb = __float_as_uint(w);
+            const uint32_t mx = HALF ? half_umax_u(wb) : wave_umax_u(wb);
+            k = (int)__builtin_ctzll(__builtin_amdgcn_ballot_w64(wb == mx) & umask);
+          } else {
+            // Eq. 2 by roulette: inclusive Hillis-Steele scan over the
+            // positions (offsets 1, 2, 4, ... < cl), r = u * total, first
+            // member of the candidate set whose prefix sum exceeds r
+            float P = w;
+            for (int off = 1; off < cl; off <<= 1) {
+              const float o = __shfl_up(P, off, 64);
+              if (lane >= off) P = P + o;
+            }
+            const float total = __uint_as_float(rdlane(__float_as_uint(P), cl - 1));
+            const float r = ((float)(rdlane(draws.y, t & 63) >> 8) * 0x1p-24f) * total;
+            const uint64_t sel = __builtin_amdgcn_ballot_w64(P > r) & umask;
+            k = sel ? (int)__builtin_ctzll(sel) : 63 - (int)__builtin_clzll(umask);
+            ++c_roul;
           }
-          const float total = __uint_as_float(rdlane(__float_as_uint(P), cl - 1));
-          const float r = ((float)(rdlane(draws.y, t & 63) >> 8) * 0x1p-24f) * total;
-          const uint64_t sel = __builtin_amdgcn_ballot_w64(P > r) & umask;
-          k = sel ? (int)__builtin_ctzll(sel) : 63 - (int)__builtin_clzll(umask);
-          ++c_roul;
+          next = (int)rdlane(rec.x, k);
+          d = rdlane(rec.y, k);
+          tv = rdlane(rec.w, k);
         }
-        next = (int)rdlane(rec.x, k);
-        d = rdlane(rec.y, k);
-        tv = rdlane(rec.w, k);
+        if (lane == 0) mark(vis, next);
+        rec = load_rec(next);
+        tb = lt == t ? next : tb;
+        if (lu == t)
+          e = make_uint4((uint32_t)cur | ((uint32_t)next << 16), (uint32_t)k, tv,
+                         (uint32_t)(k >= 0 ? -2 : -3));
+        clen += d;
+        cur = next;
       }
-      if (lane == 0) mark(vis, next);
-      rec = load_rec(next);
-      tb = lt == t ? next : tb;
-      if (lu == t)
-        e = make_uint4((uint32_t)cur | ((uint32_t)next << 16), (uint32_t)k, tv,
-                       (uint32_t)(k >= 0 ? -2 : -3));
-      clen += d;
-      cur = next;
+      c_retry += group_push<ATOMIC>(D, A, q, qw, qhead, qtail, qdirect, lane, e, t0, g1);
+      g0 = g1;
     }
     len += clen;
     if (lane < tend - t0) D.tours[(size_t)ant * n + lt] = tb;
-    if (tend == n) {
-      // closing edge (cur, start), every ant: both positions searched, the
-      // value read fresh; it takes lane n - t0, or a chunk of its own
-      const int k1 = cand_pos(D, cur, start, lane);
-      const int k2 = cand_pos(D, start, cur, lane);
-      const uint32_t x = rdlane(__float_as_uint(tau_load(home(D, cur, start, k1))), 0);
-      const uint4 ce =
-          make_uint4((uint32_t)cur | ((uint32_t)start << 16), (uint32_t)k1, x, (uint32_t)k2);
-      if (n - t0 == 64) {
-        c_retry += chunk_push<ATOMIC>(D, A, q, qw, qhead, qtail, qdirect, lane, e);
-        e = make_uint4(kNoEntry, 0u, 0u, 0u);
-      }
-      if (lane == ((n - t0) & 63)) e = ce;
-      len += D.dist[(size_t)cur * D.ldn + start];
-    }
-    c_retry += chunk_push<ATOMIC>(D, A, q, qw, qhead, qtail, qdirect, lane, e);
+  }
+  // closing edge (cur, start), every ant, as step n: both positions
+  // searched, the value read fresh
+  {
+    const int k1 = cand_pos(D, cur, start, lane);
+    const int k2 = cand_pos(D, start, cur, lane);
+    const uint32_t x = rdlane(__float_as_uint(tau_load(home(D, cur, start, k1))), 0);
+    const uint4 ce =
+        make_uint4((uint32_t)cur | ((uint32_t)start << 16), (uint32_t)k1, x, (uint32_t)k2);
+    c_retry += group_push<ATOMIC>(D, A, q, qw, qhead, qtail, qdirect, lane, ce, n, n + 1);
+    len += D.dist[(size_t)cur * D.ldn + start];
   }
   c_retry = (uint32_t)uni((int)wave_sum_u(c_retry));
   if (lane == 0) {
@@ -1051,10 +1111,10 @@ __device__ __forceinline__ void ant_queued(const Dev &D, const Iter &A, int ant,
 }
 
 // One instance, updates through the block's updater wave: waves 0..na-1 are
-// ants blockIdx.x * na + wave, wave na (the last) applies their chunks.  The
+// ants blockIdx.x * na + wave, wave na (the last) applies their entries.  The
 // host picks na so that every compute unit holds about the same number of
-// ants (the slowest unit sets the iteration time).  Dynamic LDS: the chunk
-// slots of the na ant waves, then their visited bitmaps.
+// ants (the slowest unit sets the iteration time).  Dynamic LDS: the rings
+// of the na ant waves, then their visited bitmaps.
 template <bool ATOMIC, bool HALF>
 __global__ __launch_bounds__(64 * (kQAnts + 1)) void k_construct_async_dense_q(Dev D, Iter A) {
   extern __shared__ uint4 qsm[];
@@ -1070,10 +1130,10 @@ __global__ __launch_bounds__(64 * (kQAnts + 1)) void k_construct_async_dense_q(D
   __syncthreads();
   const QRing q{qsm, qhd, qtl, &qdone};
   if (wv == na) {
-    chunk_updater<ATOMIC>(D, A, q, lane, na);
+    ring_updater<ATOMIC>(D, A, q, lane, na);
     return;
   }
-  uint32_t *vis = reinterpret_cast<uint32_t *>(qsm + (size_t)na * kQChunks * 64) +
+  uint32_t *vis = reinterpret_cast<uint32_t *>(qsm + (size_t)na * kQRing) +
                   wv * ((D.n + 31) >> 5);
   const int ant = uni(blockIdx.x * na + wv);
   if (ant < D.m) ant_queued<ATOMIC, HALF>(D, A, ant, vis, lane, q, wv);
@@ -1084,7 +1144,7 @@ __global__ __launch_bounds__(64 * (kQAnts + 1)) void k_construct_async_dense_q(D
 // Many instances in one launch, updates through each block's updater wave:
 // block b runs ants bitems[b].y .. bitems[b].y + kBatchQAnts - 1 of
 // instance bitems[b].x (one instance per block, so the updater wave works
-// with one descriptor), wave kBatchQAnts applies their chunks.
+// with one descriptor), wave kBatchQAnts applies their entries.
 constexpr int kBatchQAnts = kBatchQAntsPerBlock;
 
 template <bool ATOMIC, bool HALF>
@@ -1107,10 +1167,10 @@ __global__ __launch_bounds__(64 * (kBatchQAnts + 1)) void k_construct_async_batc
   const Iter A = iters[inst];
   const QRing q{qsm, qhd, qtl, &qdone};
   if (wv == kBatchQAnts) {
-    chunk_updater<ATOMIC>(D, A, q, lane, kBatchQAnts);
+    ring_updater<ATOMIC>(D, A, q, lane, kBatchQAnts);
     return;
   }
-  uint32_t *vis = reinterpret_cast<uint32_t *>(qsm + (size_t)kBatchQAnts * kQChunks * 64) +
+  uint32_t *vis = reinterpret_cast<uint32_t *>(qsm + (size_t)kBatchQAnts * kQRing) +
                   wv * wmax;
   const int ant = uni(item.y + wv);
   if (ant < D.m) ant_queued<ATOMIC, HALF>(D, A, ant, vis, lane, q, wv);
@@ -2147,7 +2207,7 @@ hipError_t launch_construct(const Dev &d, const Iter &it, int mode, int memory, 
     const int bpc = std::max(2, (per_cu + kQAnts - 1) / kQAnts);
     const int na = std::max(1, std::min(kQAnts, (d.m + cus * bpc - 1) / (cus * bpc)));
     const dim3 gq((d.m + na - 1) / na), bq(64 * (na + 1));
-    const size_t lq = (size_t)na * kQChunks * 64 * sizeof(uint4) +
+    const size_t lq = (size_t)na * kQRing * sizeof(uint4) +
                       (size_t)na * ((d.n + 31) / 32) * sizeof(uint32_t);
     const bool half = d.cl <= 32;
     if (atomic && half)
@@ -2158,6 +2218,11 @@ hipError_t launch_construct(const Dev &d, const Iter &it, int mode, int memory, 
       hipLaunchKernelGGL((k_construct_async_dense_q<false, true>), gq, bq, lq, s, d, it);
     else
       hipLaunchKernelGGL((k_construct_async_dense_q<false, false>), gq, bq, lq, s, d, it);
+    if (atomic) {
+      const hipError_t e = hipGetLastError();
+      if (e != hipSuccess) return e;
+      hipLaunchKernelGGL(k_mirror_dense, dim3((d.n * d.cl + 255) / 256), dim3(256), 0, s, d);
+    }
   } else if (memory == 0 && lanes < 64) {
     const int g = 64 / lanes;
     const dim3 gg((d.m + apb * g - 1) / (apb * g));
@@ -2219,7 +2284,7 @@ hipError_t launch_batch_iteration(const Dev *devs, Iter *iters, const int2 *item
   const int apb = kAsyncBlock / 64;
   const int wmax = (nmax + 31) / 32;
   if (lanes == 64 && queued) {
-    const size_t lq = (size_t)kBatchQAnts * kQChunks * 64 * sizeof(uint4) +
+    const size_t lq = (size_t)kBatchQAnts * kQRing * sizeof(uint4) +
                       (size_t)kBatchQAnts * wmax * sizeof(uint32_t);
     const dim3 gq(nitems), bq(64 * (kBatchQAnts + 1));
     const bool half = clmax <= 32;
@@ -2237,6 +2302,12 @@ hipError_t launch_batch_iteration(const Dev *devs, Iter *iters, const int2 *item
                          items, nitems, wmax);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
+    if (mode == 1) {
+      hipLaunchKernelGGL(k_mirror_batch, dim3((nmax * clmax + 255) / 256, count), dim3(256), 0,
+                         s, devs);
+      e = hipGetLastError();
+      if (e != hipSuccess) return e;
+    }
     hipLaunchKernelGGL(k_best_batch, dim3(count), dim3(1024), 0, s, devs, iters);
     e = hipGetLastError();
     if (e != hipSuccess) return e;

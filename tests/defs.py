@@ -109,3 +109,9 @@ def round_to_f32(q: Fraction) -> np.float32:
     if rem > Fraction(1, 2) or (rem == Fraction(1, 2) and fl % 2 == 1):
         fl += 1
     return np.float32(sign * float(fl * scale))
+
+
+def fmaf32(a, x, b) -> np.float32:
+    """a * x + b for float32 operands, rounded once to float32 (what fmaf
+    computes)."""
+    return round_to_f32(Fraction(float(a)) * Fraction(float(x)) + Fraction(float(b)))

@@ -610,6 +610,86 @@ def test_queued_tours_valid(acs, n, m, period):
     col.close()
 
 
+@pytest.mark.parametrize("mode", ["ASYNC_ATOMIC", "ASYNC_RACY"])
+def test_updater_path_quality_matches_inwave(acs, mode):
+    """The updater wave applies a crossing's update a few steps after the
+    crossing; the ant applying it itself does so one step after.  On n=198
+    (where a delay is a large share of a tour) 10 seeds of 50 iterations of
+    both paths must reach mean best lengths within 2.5% of each other, so
+    the hand-over changes neither when updates become visible nor how many
+    are lost in any way that shows in the search."""
+    xy = inputs.uniform(198)
+    means = {}
+    for path in (1, 2):
+        res = []
+        for s in range(10):
+            col = acs.Colony(xy, mode=getattr(acs, "ACS_" + mode), seed=s, update_path=path)
+            col.iterate(50)
+            res.append(col.best()[1])
+            col.close()
+        means[path] = float(np.mean(res))
+    _say(f"{mode}: in-wave {means[1]:.0f}, updater {means[2]:.0f}")
+    assert abs(means[2] - means[1]) / means[1] < 0.025, means
+
+
+ACCUMULATE_PATHS = [("queued", dict(update_path=2)), ("inwave", dict(update_path=1)),
+                    ("lanes32", dict(lanes_per_ant=32))]
+
+
+@pytest.mark.parametrize("path,gkw", ACCUMULATE_PATHS, ids=[p[0] for p in ACCUMULATE_PATHS])
+def test_async_local_updates_accumulate_exactly(acs, path, gkw):
+    """Many ants, compare-and-swap mode: whatever the interleaving, every
+    entry ends the iteration at f^c(tau) (Eq. 3 applied c times in fp32, c =
+    the number of ants whose tour crosses the edge, closing edges included),
+    followed on the best-so-far tour's edges by Eq. 4, and the matrix stays
+    symmetric: no local update is lost or applied to one direction only."""
+    n = 1000
+    _say(f"accumulate {path} n={n} m={n}")
+    xy = inputs.uniform(n, 61)
+    col = acs.Colony(xy, m=n, mode=acs.ACS_ASYNC_ATOMIC, seed=5, **gkw)
+    orc = oracle.Oracle(xy, m=1, seed=5)
+    c = orc.constants()
+    col.iterate(4)
+    before = col.tau()
+    assert np.array_equal(before, before.T)
+    col.iterate(1)
+    after = col.tau()
+    assert np.array_equal(after, after.T)
+    tours = col.tours().astype(np.int64)
+    a, b = tours, np.roll(tours, -1, axis=1)
+    key = np.minimum(a, b) * n + np.maximum(a, b)
+    keys, counts = np.unique(key.ravel(), return_counts=True)
+    crossed = dict(zip(keys.tolist(), counts.tolist()))
+    best, L = col.best()
+    bt = np.asarray(best, dtype=np.int64)
+    bkeys = (np.minimum(bt, np.roll(bt, -1)) * n + np.maximum(bt, np.roll(bt, -1))).tolist()
+    # Eq. 4's deposit as the library computes it: rho / L_gb in double, then float
+    bg = np.float32(0.1 / L)
+    expect = {}
+    for kk, cnt in crossed.items():
+        u, v = divmod(kk, n)
+        expect[kk] = orc.local_map_k(before[u, v], cnt)
+    for kk in bkeys:
+        u, v = divmod(kk, n)
+        x = expect.get(kk, before[u, v])
+        expect[kk] = defs.fmaf32(c["a_glob"], x, bg)
+    # entries away from tau0 that ants crossed: there a lost or doubled
+    # local update changes the result (tau0 is the local map's fixed point)
+    strong = 0
+    for kk, want in expect.items():
+        u, v = divmod(kk, n)
+        assert after[u, v] == want, (u, v, crossed.get(kk, 0), before[u, v], after[u, v], want)
+        strong += int(kk in crossed and before[u, v] != c["tau0"])
+    # every other entry keeps its value
+    touched = np.zeros(n * n, dtype=bool)
+    touched[list(expect)] = True
+    touched = touched.reshape(n, n)
+    touched |= touched.T
+    assert np.array_equal(after[~touched], before[~touched])
+    assert len(expect) > n and strong > n // 2, (len(expect), strong)
+    col.close()
+
+
 # ---------------------------------------------------------------------------
 # Edge cases of the asynchronous kernels (default updater path, in-wave
 # updates, several ants per wavefront): one ant must equal the oracle, any

@@ -448,3 +448,18 @@ def test_vectorised_edge_distances_match_exact_definition():
     got = defs.edge_dists(xy, u, v)
     want = [defs.exact_dist(*xy[a], *xy[b]) for a, b in zip(u, v)]
     assert np.array_equal(got, want)
+
+
+def test_fmaf32_helper_rounds_once():
+    """The tests' exact fma (used to predict Eq. 4 on the GPU) against C's
+    fmaf inside the oracle's local map, and against a case where rounding
+    the product first gives another float."""
+    o = oracle.Oracle(inputs.uniform(50, 3), m=1)
+    c = o.constants()
+    g = np.random.default_rng(8)
+    for x in g.uniform(float(c["tau0"]) * 0.5, float(c["tau0"]) * 50, size=200).astype(np.float32):
+        assert defs.fmaf32(c["a_loc"], x, c["b_loc"]) == o.local_map_k(x, 1)
+    a, x, b = np.float32(1 + 2 ** -12), np.float32(1 + 2 ** -12), np.float32(-1)
+    # exact: 2^-11 + 2^-24; a product rounded to float first loses the 2^-24
+    assert defs.fmaf32(a, x, b) == np.float32(2 ** -11 + 2 ** -24)
+    assert np.float32(a * x) + b == np.float32(2 ** -11)
