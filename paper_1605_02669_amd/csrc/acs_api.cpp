@@ -46,7 +46,7 @@ size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
 
 // Device buffers of one handle, as offsets into one allocation.
 struct Layout {
-  size_t xy, dist, crec, cand, eta, tau, etad, rpos, spm, spm_tail, xnn, upd_rec, upd_nb, upd_next, upd_head, tours, lens,
+  size_t xy, dist, crec, cand, eta, tau, etad, rpos, ctau, spm, spm_tail, xnn, upd_rec, upd_nb, upd_next, upd_head, tours, lens,
       best, gstate, counters, sync, dmax, lnn, total;
 };
 
@@ -69,6 +69,7 @@ Layout make_layout(int n, int m, int cl, int ldn, int memory, int s) {
     L.tau = take(sizeof(float) * (size_t)n * ldn);
     L.etad = take(sizeof(float) * (size_t)n * ldn);
     L.rpos = take(sizeof(int8_t) * (size_t)n * cl);
+    L.ctau = take(sizeof(float) * (size_t)n * cl);
   } else {
     L.spm = take(sizeof(uint32_t) * 2 * (size_t)n * s);
     L.spm_tail = take(sizeof(uint32_t) * (size_t)n);
@@ -335,6 +336,7 @@ int acs_create(const double *coords_xy, int32_t n, const acs_params *p, acs_t **
     d.tau = reinterpret_cast<float *>(w + h->L.tau);
     d.etad = reinterpret_cast<const float *>(w + h->L.etad);
     d.rpos = reinterpret_cast<const int8_t *>(w + h->L.rpos);
+    d.ctau = reinterpret_cast<float *>(w + h->L.ctau);
   } else {
     d.spm = reinterpret_cast<uint2 *>(w + h->L.spm);
     d.spm_tail = reinterpret_cast<uint32_t *>(w + h->L.spm_tail);

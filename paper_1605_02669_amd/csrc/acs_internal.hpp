@@ -23,6 +23,10 @@ struct Dev {
   const float *etad;       // dense: n x ldn, eta^beta(d(i, j))
   const int8_t *rpos;      // dense: n x cl, position of i in the candidate list
                            //   of its k-th candidate, -1 if i is not in it
+  float *ctau;             // dense: n x cl, the candidate entries' pheromone
+                           //   while a construction with an updater wave runs
+                           //   (their records then hold the values of the
+                           //   iteration's start)
   // selective pheromone memory (Sec. 3.2): the record of city i is s pairs
   // {neighbour (-1 = empty slot), pheromone bits}; spm_tail[i] counts the
   // inserts (the most recently added slot is spm_tail[i] mod s)

@@ -154,6 +154,12 @@ __device__ __forceinline__ float *home(const Dev &D, int u, int v, int k) {
   return k >= 0 ? cand_tau(D, u, k) : D.tau + (size_t)u * D.ldn + v;
 }
 
+// Home of the directed entry (u, v) while a construction with an updater
+// wave runs: slot k of u's row of ctau, or tau[u][v].
+__device__ __forceinline__ float *qhome(const Dev &D, int u, int v, int k) {
+  return k >= 0 ? D.ctau + (size_t)u * D.cl + k : D.tau + (size_t)u * D.ldn + v;
+}
+
 // Agent-coherent read of one pheromone value (sees every CAS performed so
 // far on the device, whichever XCD performed it).
 __device__ __forceinline__ float tau_load(const float *p) {
@@ -339,32 +345,44 @@ __global__ __launch_bounds__(256) void k_rpos(Dev D) {
   const_cast<int8_t *>(D.rpos)[e] = (int8_t)r;
 }
 
-// After a construction whose local updates went to canonical homes: the
-// value of each candidate slot that is a canonical home goes to the other
-// entry of its edge (the slot of the same edge in the other city's record
-// when each lists the other and this city is the smaller, else the dense
-// entry (v, u)).
-__device__ __forceinline__ void mirror_slot(const Dev &D, size_t e) {
+// A construction with an updater wave keeps the candidate entries' live
+// pheromone in ctau (a record's 32 values in one 128-byte line), so the
+// records the ants load are not written while it runs.  Before it, ctau
+// takes the records' values; after it, each record takes back the value of
+// its edge's canonical home (itself, or the same edge's slot in the smaller
+// city's record when each city lists the other; see apply_entries), and a
+// candidate slot whose city is not listed back passes its value to the dense
+// entry (v, u).  Compare-and-swap mode only; the unsynchronised mode has no
+// canonical homes and copies each slot back as it is.
+__device__ __forceinline__ void ctau_out_slot(const Dev &D, size_t e, bool canonical) {
   const int u = (int)(e / (size_t)D.cl);
-  const uint4 r = D.crec[e];
-  const int v = (int)r.x, kr = (int)D.rpos[e];
-  if (kr >= 0) {
-    if (u < v) const_cast<uint4 *>(D.crec)[(size_t)v * D.cl + kr].w = r.w;
-  } else {
-    D.tau[(size_t)v * D.ldn + u] = __uint_as_float(r.w);
-  }
+  const int v = (int)D.crec[e].x, kr = (int)D.rpos[e];
+  const float x = canonical && kr >= 0 && u > v ? D.ctau[(size_t)v * D.cl + kr] : D.ctau[e];
+  const_cast<uint4 *>(D.crec)[e].w = __float_as_uint(x);
+  if (canonical && kr < 0) D.tau[(size_t)v * D.ldn + u] = x;
 }
 
-__global__ __launch_bounds__(256) void k_mirror_dense(Dev D) {
+__global__ __launch_bounds__(256) void k_ctau_in(Dev D) {
   const size_t e = (size_t)blockIdx.x * 256 + threadIdx.x;
-  if (e < (size_t)D.n * D.cl) mirror_slot(D, e);
+  if (e < (size_t)D.n * D.cl) D.ctau[e] = __uint_as_float(D.crec[e].w);
+}
+
+__global__ __launch_bounds__(256) void k_ctau_out(Dev D, int canonical) {
+  const size_t e = (size_t)blockIdx.x * 256 + threadIdx.x;
+  if (e < (size_t)D.n * D.cl) ctau_out_slot(D, e, canonical != 0);
 }
 
 // The same for every instance of a batch (blockIdx.y = instance).
-__global__ __launch_bounds__(256) void k_mirror_batch(const Dev *devs) {
+__global__ __launch_bounds__(256) void k_ctau_in_batch(const Dev *devs) {
   const Dev D = devs[blockIdx.y];
   const size_t e = (size_t)blockIdx.x * 256 + threadIdx.x;
-  if (e < (size_t)D.n * D.cl) mirror_slot(D, e);
+  if (e < (size_t)D.n * D.cl) D.ctau[e] = __uint_as_float(D.crec[e].w);
+}
+
+__global__ __launch_bounds__(256) void k_ctau_out_batch(const Dev *devs, int canonical) {
+  const Dev D = devs[blockIdx.y];
+  const size_t e = (size_t)blockIdx.x * 256 + threadIdx.x;
+  if (e < (size_t)D.n * D.cl) ctau_out_slot(D, e, canonical != 0);
 }
 
 __global__ __launch_bounds__(256) void k_init(Dev D, float tau0) {
@@ -843,11 +861,12 @@ __device__ __forceinline__ void lds_st(uint32_t *p, uint32_t v) {
 // retries with it); the other entry gets the value just written by a
 // device-coherent store, for readers at the other endpoint.  The canonical home is a
 // candidate slot: the one in the record of the smaller city when each city
-// lists the other, else the only one; k_mirror_dense copies every canonical
+// lists the other, else the only one; k_ctau_out copies every canonical
 // value to its other entry when the construction ends, so both entries
 // then hold exactly the result of all the maps.  An edge with both entries
 // in the dense matrix (a fallback move between cities that do not list each
-// other) gets both compare-and-swaps.
+// other) gets both compare-and-swaps.  Candidate entries live in ctau
+// meanwhile (see k_ctau_in).
 // Unsynchronised mode (ACS-GPU-Alt, Sec. 3.1.2): each entry is read and its
 // map stored back, both device-coherent but not as one atomic operation;
 // updates landing in between are lost.  (The value the ant read is several
@@ -869,8 +888,8 @@ __device__ __forceinline__ uint32_t apply_entries(const Dev &D, const Iter &A, u
   }
   if (!valid) return 0;
   if (kr == -2) kr = (int)D.rpos[(size_t)u * D.cl + k];
-  float *pf = home(D, u, v, k);
-  float *pr = home(D, v, u, kr);
+  float *pf = qhome(D, u, v, k);
+  float *pr = qhome(D, v, u, kr);
   const float al = A.a_loc, bl = A.b_loc;
   if (ATOMIC) {
     const bool both_dense = k < 0 && kr < 0;
@@ -1003,9 +1022,14 @@ __device__ __forceinline__ void ant_queued(const Dev &D, const Iter &A, int ant,
   const int rowb = cl * 16;  // bytes per record row
   const __amdgpu_buffer_rsrc_t crs =
       __builtin_amdgcn_make_buffer_rsrc(const_cast<uint4 *>(D.crec), 0, n * rowb, kBufWord3);
+  const __amdgpu_buffer_rsrc_t trs =
+      __builtin_amdgcn_make_buffer_rsrc(D.ctau, 0, n * cl * 4, kBufWord3);
+  // a record's fields and the live pheromone of its slot (the record's own
+  // pheromone word is the value of the iteration's start)
   auto load_rec = [&](int city) {
     const auto r = __builtin_amdgcn_raw_buffer_load_b128(crs, koff, city * rowb, 0);
-    return make_uint4(r[0], r[1], r[2], r[3]);
+    const uint32_t t = __builtin_amdgcn_raw_buffer_load_b32(trs, koff >> 2, city * cl * 4, 0);
+    return make_uint4(r[0], r[1], r[2], t);
   };
 
   for (int w = lane; w < W; w += 64) vis[w] = 0u;
@@ -1097,7 +1121,7 @@ __device__ __forceinline__ void ant_queued(const Dev &D, const Iter &A, int ant,
   {
     const int k1 = cand_pos(D, cur, start, lane);
     const int k2 = cand_pos(D, start, cur, lane);
-    const uint32_t x = rdlane(__float_as_uint(tau_load(home(D, cur, start, k1))), 0);
+    const uint32_t x = rdlane(__float_as_uint(tau_load(qhome(D, cur, start, k1))), 0);
     const uint4 ce =
         make_uint4((uint32_t)cur | ((uint32_t)start << 16), (uint32_t)k1, x, (uint32_t)k2);
     c_retry += group_push<ATOMIC>(D, A, q, qw, qhead, qtail, qdirect, lane, ce, n, n + 1);
@@ -2210,6 +2234,8 @@ hipError_t launch_construct(const Dev &d, const Iter &it, int mode, int memory, 
     const size_t lq = (size_t)na * kQRing * sizeof(uint4) +
                       (size_t)na * ((d.n + 31) / 32) * sizeof(uint32_t);
     const bool half = d.cl <= 32;
+    const dim3 gc((d.n * d.cl + 255) / 256);
+    hipLaunchKernelGGL(k_ctau_in, gc, dim3(256), 0, s, d);
     if (atomic && half)
       hipLaunchKernelGGL((k_construct_async_dense_q<true, true>), gq, bq, lq, s, d, it);
     else if (atomic)
@@ -2218,11 +2244,9 @@ hipError_t launch_construct(const Dev &d, const Iter &it, int mode, int memory, 
       hipLaunchKernelGGL((k_construct_async_dense_q<false, true>), gq, bq, lq, s, d, it);
     else
       hipLaunchKernelGGL((k_construct_async_dense_q<false, false>), gq, bq, lq, s, d, it);
-    if (atomic) {
-      const hipError_t e = hipGetLastError();
-      if (e != hipSuccess) return e;
-      hipLaunchKernelGGL(k_mirror_dense, dim3((d.n * d.cl + 255) / 256), dim3(256), 0, s, d);
-    }
+    const hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_ctau_out, gc, dim3(256), 0, s, d, atomic ? 1 : 0);
   } else if (memory == 0 && lanes < 64) {
     const int g = 64 / lanes;
     const dim3 gg((d.m + apb * g - 1) / (apb * g));
@@ -2288,6 +2312,8 @@ hipError_t launch_batch_iteration(const Dev *devs, Iter *iters, const int2 *item
                       (size_t)kBatchQAnts * wmax * sizeof(uint32_t);
     const dim3 gq(nitems), bq(64 * (kBatchQAnts + 1));
     const bool half = clmax <= 32;
+    const dim3 gc((nmax * clmax + 255) / 256, count);
+    hipLaunchKernelGGL(k_ctau_in_batch, gc, dim3(256), 0, s, devs);
     if (mode == 1 && half)
       hipLaunchKernelGGL((k_construct_async_batch_q<true, true>), gq, bq, lq, s, devs, iters,
                          items, nitems, wmax);
@@ -2302,12 +2328,9 @@ hipError_t launch_batch_iteration(const Dev *devs, Iter *iters, const int2 *item
                          items, nitems, wmax);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    if (mode == 1) {
-      hipLaunchKernelGGL(k_mirror_batch, dim3((nmax * clmax + 255) / 256, count), dim3(256), 0,
-                         s, devs);
-      e = hipGetLastError();
-      if (e != hipSuccess) return e;
-    }
+    hipLaunchKernelGGL(k_ctau_out_batch, gc, dim3(256), 0, s, devs, mode == 1 ? 1 : 0);
+    e = hipGetLastError();
+    if (e != hipSuccess) return e;
     hipLaunchKernelGGL(k_best_batch, dim3(count), dim3(1024), 0, s, devs, iters);
     e = hipGetLastError();
     if (e != hipSuccess) return e;
