@@ -136,6 +136,11 @@ EXTRA = {
     "n2392_alt": dict(kind="uniform", n=N, kw=dict(), modes=(("racy", 20),)),
     "n2392_period16": dict(kind="uniform", n=N, kw=dict(local_update_period=16),
                 modes=(("async", 20), ("racy", 20), ("sync", 2))),
+    # the in-step sequential schedule (Alg. 1 read literally) with m = n and
+    # with a 64-ant colony, beside the step-snapshot schedule at m = 64
+    "n2392_sequential": dict(kind="uniform", n=N, kw=dict(), modes=(("sequential", 1),)),
+    "n2392_sequential_m64": dict(kind="uniform", n=N, kw=dict(m=64),
+                                 modes=(("sequential", 5), ("sync", 5))),
 }
 
 
@@ -143,7 +148,8 @@ def run_extra(acs, inputs, name):
     spec = EXTRA[name]
     xy = inputs.uniform(spec["n"]) if spec["kind"] == "uniform" else inputs.clustered(spec["n"])
     res = {"n": spec["n"], **{k: v for k, v in spec["kw"].items()}}
-    modes = {"sync": acs.ACS_SYNC, "async": acs.ACS_ASYNC_ATOMIC, "racy": acs.ACS_ASYNC_RACY}
+    modes = {"sync": acs.ACS_SYNC, "async": acs.ACS_ASYNC_ATOMIC, "racy": acs.ACS_ASYNC_RACY,
+             "sequential": acs.ACS_SEQUENTIAL}
     for mode_name, iters in spec["modes"]:
         r = run_mode(acs, xy, modes[mode_name], iters, 1, **spec["kw"])
         res[mode_name] = {"steps_per_s": r["steps"] / r["seconds"],
@@ -241,10 +247,11 @@ def main():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--sync-steps", type=int, default=5)
     ap.add_argument("--no-cpu", action="store_true")
-    ap.add_argument("--extra", default="n198,n1000_clustered,n20000_spm,batch256,prior,n2392_alt,n2392_period16",
+    ap.add_argument("--extra", default="n198,n1000_clustered,n20000_spm,batch256,prior,n2392_alt,"
+                                       "n2392_period16,n2392_sequential,n2392_sequential_m64",
                     help="other workloads timed beside the headline (comma list of "
-                         "n198, n1000_clustered, n20000_spm, batch256, prior, n2392_alt, n2392_period16; "
-                         "empty for none)")
+                         "n198, n1000_clustered, n20000_spm, batch256, prior, n2392_alt, n2392_period16, "
+                         "n2392_sequential, n2392_sequential_m64; empty for none)")
     ap.add_argument("--copy-calibration-mb", type=int, default=0,
                     help="after timing, run one plain device copy of this many MiB "
                          "(reference kernel for hardware byte counters)")

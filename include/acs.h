@@ -58,8 +58,14 @@ enum acs_memory { ACS_DENSE = 0, ACS_SPM = 1 };
  * so far (the unsynchronised single-kernel construction of Sec. 3.1.2).
  * ACS_ASYNC_RACY: as ACS_ASYNC_ATOMIC, but each update writes the map of the
  * value the ant read with a plain store, so updates that race are lost: the
- * paper's ACS-GPU-Alt (Sec. 3.1.2, the variant without atomic operations). */
-enum acs_mode { ACS_SYNC = 0, ACS_ASYNC_ATOMIC = 1, ACS_ASYNC_RACY = 2 };
+ * paper's ACS-GPU-Alt (Sec. 3.1.2, the variant without atomic operations).
+ * ACS_SEQUENTIAL: Alg. 1 read literally, step by step and within a step ant
+ * by ant: ant a selects from the pheromone after the local updates of ants
+ * 0..a-1 of the same step (in-step Gauss-Seidel).  Deterministic like
+ * ACS_SYNC; dense memory only (ACS_E_UNSUPPORTED otherwise).  One block runs
+ * it: ants whose current city no earlier ant of the step touches select in
+ * parallel, so its speed depends on how often ants meet. */
+enum acs_mode { ACS_SYNC = 0, ACS_ASYNC_ATOMIC = 1, ACS_ASYNC_RACY = 2, ACS_SEQUENTIAL = 3 };
 
 typedef struct acs_params {
   uint32_t struct_size;  /* = sizeof(acs_params) */

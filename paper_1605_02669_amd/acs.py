@@ -24,7 +24,7 @@ ACS_E_STATE = -5
 ACS_E_UNSUPPORTED = -6
 
 ACS_DENSE, ACS_SPM = 0, 1
-ACS_SYNC, ACS_ASYNC_ATOMIC, ACS_ASYNC_RACY = 0, 1, 2
+ACS_SYNC, ACS_ASYNC_ATOMIC, ACS_ASYNC_RACY, ACS_SEQUENTIAL = 0, 1, 2, 3
 
 
 class acs_params(C.Structure):

@@ -46,13 +46,13 @@ size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
 
 // Device buffers of one handle, as offsets into one allocation.
 struct Layout {
-  size_t xy, dist, crec, cand, eta, tau, etad, rpos, ctau, spm, spm_tail, xnn, upd_rec, upd_nb, upd_next, upd_head, tours, lens,
+  size_t xy, dist, crec, cand, eta, tau, etad, rpos, ctau, gvis, spm, spm_tail, xnn, upd_rec, upd_nb, upd_next, upd_head, tours, lens,
       best, gstate, counters, sync, dmax, lnn, total;
 };
 
 constexpr int kEtaEntries = 65536;  // eta^beta for every 16-bit distance
 
-Layout make_layout(int n, int m, int cl, int ldn, int memory, int s) {
+Layout make_layout(int n, int m, int cl, int ldn, int memory, int s, int mode) {
   Layout L{};
   size_t off = 0;
   auto take = [&](size_t bytes) {
@@ -70,6 +70,7 @@ Layout make_layout(int n, int m, int cl, int ldn, int memory, int s) {
     L.etad = take(sizeof(float) * (size_t)n * ldn);
     L.rpos = take(sizeof(int8_t) * (size_t)n * cl);
     L.ctau = take(sizeof(float) * (size_t)n * cl);
+    if (mode == ACS_SEQUENTIAL) L.gvis = take(sizeof(uint32_t) * (size_t)m * ((n + 31) / 32));
   } else {
     L.spm = take(sizeof(uint32_t) * 2 * (size_t)n * s);
     L.spm_tail = take(sizeof(uint32_t) * (size_t)n);
@@ -104,8 +105,11 @@ int check_params(int32_t n, const acs_params *p) {
   if (!std::isfinite(p->tau0)) return fail(ACS_E_INVALID, "tau0 not finite");
   if (p->memory != ACS_DENSE && p->memory != ACS_SPM) return fail(ACS_E_INVALID, "bad memory");
   if (p->memory == ACS_SPM && p->spm_s < 1) return fail(ACS_E_INVALID, "spm_s must be >= 1");
-  if (p->mode != ACS_SYNC && p->mode != ACS_ASYNC_ATOMIC && p->mode != ACS_ASYNC_RACY)
+  if (p->mode != ACS_SYNC && p->mode != ACS_ASYNC_ATOMIC && p->mode != ACS_ASYNC_RACY &&
+      p->mode != ACS_SEQUENTIAL)
     return fail(ACS_E_INVALID, "bad mode");
+  if (p->mode == ACS_SEQUENTIAL && p->memory != ACS_DENSE)
+    return fail(ACS_E_UNSUPPORTED, "the sequential mode needs dense memory");
   if (p->local_update_period < 1) return fail(ACS_E_INVALID, "local_update_period must be >= 1");
   if (n > 65535) return fail(ACS_E_UNSUPPORTED, "n = %d > 65535", n);
   const uint32_t cl = std::min<uint32_t>(p->cl, (uint32_t)n - 1);
@@ -117,7 +121,8 @@ int check_params(int32_t n, const acs_params *p) {
     return fail(ACS_E_INVALID, "lanes_per_ant = %u not in {0, 16, 32, 64}", lpa);
   if (lpa != 0 && lpa < cl)
     return fail(ACS_E_UNSUPPORTED, "lanes_per_ant = %u < cl = %u", lpa, cl);
-  if (lpa != 0 && lpa != 64 && (p->mode == ACS_SYNC || p->memory != ACS_DENSE))
+  if (lpa != 0 && lpa != 64 &&
+      ((p->mode != ACS_ASYNC_ATOMIC && p->mode != ACS_ASYNC_RACY) || p->memory != ACS_DENSE))
     return fail(ACS_E_UNSUPPORTED, "lanes_per_ant < 64 needs an asynchronous mode and dense memory");
   if (p->update_path > 2) return fail(ACS_E_INVALID, "update_path = %u not in {0, 1, 2}",
                                       p->update_path);
@@ -264,7 +269,7 @@ int acs_workspace_bytes(int32_t n, const acs_params *p, size_t *out) {
   const int m = p->m ? (int)p->m : n;
   const int cl = (int)std::min<uint32_t>(p->cl, (uint32_t)n - 1);
   const int ldn = (int)align_up((size_t)n, 64);
-  *out = make_layout(n, m, cl, ldn, (int)p->memory, (int)p->spm_s).total;
+  *out = make_layout(n, m, cl, ldn, (int)p->memory, (int)p->spm_s, (int)p->mode).total;
   return ACS_OK;
 }
 
@@ -290,7 +295,7 @@ int acs_create(const double *coords_xy, int32_t n, const acs_params *p, acs_t **
   h->m = m;
   h->cl = (int)std::min<uint32_t>(p->cl, (uint32_t)n - 1);
   h->ldn = (int)align_up((size_t)n, 64);
-  h->L = make_layout(n, m, h->cl, h->ldn, (int)p->memory, (int)p->spm_s);
+  h->L = make_layout(n, m, h->cl, h->ldn, (int)p->memory, (int)p->spm_s, (int)p->mode);
 
   auto bail = [&](int code) {
     std::string keep = g_err;
@@ -337,6 +342,7 @@ int acs_create(const double *coords_xy, int32_t n, const acs_params *p, acs_t **
     d.etad = reinterpret_cast<const float *>(w + h->L.etad);
     d.rpos = reinterpret_cast<const int8_t *>(w + h->L.rpos);
     d.ctau = reinterpret_cast<float *>(w + h->L.ctau);
+    if (p->mode == ACS_SEQUENTIAL) d.gvis = reinterpret_cast<uint32_t *>(w + h->L.gvis);
   } else {
     d.spm = reinterpret_cast<uint2 *>(w + h->L.spm);
     d.spm_tail = reinterpret_cast<uint32_t *>(w + h->L.spm_tail);

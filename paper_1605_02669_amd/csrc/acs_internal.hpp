@@ -23,6 +23,7 @@ struct Dev {
   const float *etad;       // dense: n x ldn, eta^beta(d(i, j))
   const int8_t *rpos;      // dense: n x cl, position of i in the candidate list
                            //   of its k-th candidate, -1 if i is not in it
+  uint32_t *gvis;          // sequential mode: m x ceil(n / 32) visited bitmaps
   float *ctau;             // dense: n x cl, the candidate entries' pheromone
                            //   while a construction with an updater wave runs
                            //   (their records then hold the values of the
@@ -68,7 +69,8 @@ hipError_t launch_init_pheromone(const Dev &d, float tau0, hipStream_t s);
 // ---- one iteration ----
 // Construction of all m tours.  mode 0 = synchronous steps (cooperative
 // persistent launch), 1 = asynchronous with atomic local updates, 2 =
-// asynchronous with plain stores.  lanes: lanes per ant of the asynchronous
+// asynchronous with plain stores, 3 = sequential within each step (one
+// block).  lanes: lanes per ant of the asynchronous
 // dense kernels (64, 32 or 16; at least cl).  queued: the one-ant-per-wave
 // dense kernel hands its local updates to an updater wave per block.
 hipError_t launch_construct(const Dev &d, const Iter &it, int mode, int memory, int lanes,

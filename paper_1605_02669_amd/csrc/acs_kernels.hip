@@ -660,6 +660,124 @@ __global__ __launch_bounds__(1024) void k_construct_sync_dense(Dev D, Iter A) {
 }
 
 // ---------------------------------------------------------------------------
+// Sequential construction, dense memory (Alg. 1 read literally): step by
+// step, and within a step ant by ant, each ant selecting from the pheromone
+// after the local updates of the ants before it in the same step.  One block
+// of kSeqWaves waves.  A round gives the next kSeqWaves unresolved ants of
+// the step one wave each; they select in parallel from the current
+// pheromone.  An ant's choice depends on the pheromone only through the row
+// of its current city, and an ant's update writes rows cur and next, so the
+// round's ants up to (not including) the first whose row an earlier ant of
+// the round writes have made exactly the sequential choices.  They commit
+// (visited bit, tour entry, length, local update; their updates touch
+// disjoint entries); the rest select again in the next round.  Every round
+// commits at least its first ant.  Visited bitmaps live in global memory,
+// since an ant is served by different waves over the iteration.
+// ---------------------------------------------------------------------------
+constexpr int kSeqWaves = 16;
+// visited bitmaps in LDS when all m of them fit in this many words
+constexpr int kSeqLdsWords = 36 * 1024;
+
+// VIS_LDS: the m visited bitmaps in LDS (dynamic, m * ceil(n/32) words), else
+// in global memory.  In this schedule both entries of an edge always hold
+// the same value (every map is applied to both), so a committing ant stores
+// the map of the value it read to both without reading the second.
+template <bool VIS_LDS>
+__global__ __launch_bounds__(64 * kSeqWaves) void k_construct_seq_dense(Dev D, Iter A) {
+  extern __shared__ uint32_t smem[];
+  __shared__ int s_rows[kSeqWaves][2];  // rows the round's ant w writes (-1: none)
+  __shared__ int s_cur[kSeqWaves];      // current city of the round's ant w (-1: none)
+  const int lane = threadIdx.x & 63;
+  const int wv = threadIdx.x >> 6;
+  const int n = D.n, m = D.m, cl = D.cl;
+  const int W = (n + 31) >> 5;
+  const int kl = lane < cl ? lane : cl - 1;
+  uint32_t *const vbase = VIS_LDS ? smem : D.gvis;
+
+  for (int a = wv; a < m; a += kSeqWaves) {
+    uint32_t *vis = vbase + (size_t)a * W;
+    for (int w = lane; w < W; w += 64) vis[w] = 0u;
+    const uint4 draws = philox_batch(A, a, 0, lane);
+    const int start = (int)__umulhi(rdlane(draws.z, 0), (uint32_t)n);
+    if (lane == 0) {
+      vis[start >> 5] |= 1u << (start & 31);
+      D.tours[(size_t)a * n] = start;
+      D.lens[a] = 0;
+    }
+  }
+  __syncthreads();
+  uint32_t c_greedy = 0, c_roul = 0, c_fb = 0, c_retry = 0;
+  uint64_t c_fbu = 0;
+  for (int t = 1; t < n; ++t) {
+    const bool upd = t % (int)A.lperiod == 0;
+    for (int base = 0; base < m;) {
+      const int a = base + wv;
+      const bool act = a < m;
+      Pick p{};
+      int cur = -1, kr = -1;
+      if (act) {
+        uint32_t *vis = vbase + (size_t)a * W;
+        cur = D.tours[(size_t)a * n + t - 1];
+        const uint4 draws = philox_batch(A, a, t & ~63, lane);
+        const uint4 rec = D.crec[(size_t)cur * cl + kl];
+        const Cand c = weigh(D, vis, lane, rec);
+        p = select_dense<false>(D, A, vis, cur, lane, rec, c, draw_of(draws, t));
+        // position of cur in the chosen city's list, for the second entry
+        if (upd) kr = p.k >= 0 ? (int)D.rpos[(size_t)cur * cl + p.k] : cand_pos(D, p.next, cur, lane);
+      }
+      if (lane == 0) {
+        s_cur[wv] = cur;
+        s_rows[wv][0] = act && upd ? cur : -1;
+        s_rows[wv][1] = act && upd ? p.next : -1;
+      }
+      __syncthreads();
+      // the round commits its ants before the first one whose row an earlier
+      // ant of the round writes (every wave finds the same K): lane v holds
+      // ant v's current city and the rows it writes
+      const int vl = lane < kSeqWaves ? lane : kSeqWaves - 1;
+      const int lc = s_cur[vl], lr0 = s_rows[vl][0], lr1 = s_rows[vl][1];
+      bool bad = false;
+#pragma unroll
+      for (int u = 0; u + 1 < kSeqWaves; ++u) {
+        const int r0 = (int)rdlane((uint32_t)lr0, u), r1 = (int)rdlane((uint32_t)lr1, u);
+        bad |= lane > u && lane < kSeqWaves && lc >= 0 && (lc == r0 || lc == r1);
+      }
+      const uint64_t badm = __ballot(bad);
+      const int K = badm ? (int)__ffsll((unsigned long long)badm) - 1 : kSeqWaves;
+      if (act && wv < K) {
+        c_greedy += p.kind == 0;
+        c_roul += p.kind == 1;
+        if (p.kind == 2) { ++c_fb; c_fbu += (uint64_t)(n - t); }
+        if (lane == 0) {
+          __hip_atomic_fetch_or(vbase + (size_t)a * W + (p.next >> 5), 1u << (p.next & 31),
+                                __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+          D.tours[(size_t)a * n + t] = p.next;
+          D.lens[a] += p.d;
+        }
+        if (upd && lane < 2) {
+          float *h = lane == 0 ? home(D, cur, p.next, p.k) : home(D, p.next, cur, kr);
+          *h = fmaf(A.a_loc, p.tval, A.b_loc);
+        }
+      }
+      __syncthreads();
+      base += K;
+    }
+  }
+  // closing edges: lengths and updates (edges shared by several ants get the
+  // map once per ant, in any order)
+  for (int a = wv; a < m; a += kSeqWaves) {
+    const int cur = D.tours[(size_t)a * n + n - 1], start = D.tours[(size_t)a * n];
+    const int k1 = cand_pos(D, cur, start, lane);
+    const int k2 = cand_pos(D, start, cur, lane);
+    float *h = lane == 0 ? home(D, cur, start, k1) : home(D, start, cur, k2);
+    if (lane < 2) c_retry += cas_apply(h, __float_as_uint(tau_load(h)), A.a_loc, A.b_loc);
+    if (lane == 0) D.lens[a] += D.dist[(size_t)cur * D.ldn + start];
+  }
+  c_retry = (uint32_t)uni((int)(rdlane(c_retry, 0) + rdlane(c_retry, 1)));
+  if (lane == 0) add_counters(D, c_greedy, c_roul, c_fb, c_fbu, c_retry);
+}
+
+// ---------------------------------------------------------------------------
 // Asynchronous construction, dense memory: one launch per iteration, one ant
 // per wave, no waiting for the other ants.  Each crossing gets the local
 // update of Eq. 3 as a compare-and-swap of the exact map on both directed
@@ -2205,6 +2323,16 @@ hipError_t launch_init_pheromone(const Dev &d, float tau0, hipStream_t s) {
 
 hipError_t launch_construct(const Dev &d, const Iter &it, int mode, int memory, int lanes,
                             int queued, hipStream_t s) {
+  if (mode == 3) {
+    const size_t words = (size_t)d.m * ((d.n + 31) / 32);
+    if (words <= (size_t)kSeqLdsWords)
+      hipLaunchKernelGGL(k_construct_seq_dense<true>, dim3(1), dim3(64 * kSeqWaves),
+                         words * sizeof(uint32_t), s, d, it);
+    else
+      hipLaunchKernelGGL(k_construct_seq_dense<false>, dim3(1), dim3(64 * kSeqWaves), 0, s, d,
+                         it);
+    return hipGetLastError();
+  }
   if (mode == 0) {
     const int apb = kSyncBlock / 64;
     const int grid = (d.m + apb - 1) / apb;

@@ -94,6 +94,10 @@ def test_default_params():
     ({"cl": 0}, 10, acs.ACS_E_INVALID, "cl"),
     ({"cl": 100}, 200, acs.ACS_E_UNSUPPORTED, "cl = 100"),
     ({"local_update_period": 0}, 10, acs.ACS_E_INVALID, "period"),
+    ({"mode": acs.ACS_SEQUENTIAL, "memory": acs.ACS_SPM}, 10, acs.ACS_E_UNSUPPORTED,
+     "sequential mode needs dense"),
+    ({"mode": acs.ACS_SEQUENTIAL, "lanes_per_ant": 32}, 10, acs.ACS_E_UNSUPPORTED,
+     "asynchronous mode"),
 ])
 def test_invalid_parameters_rejected_before_any_device_work(kw, n, code, needle):
     rc, msg, h = _create_rc(inputs.uniform(max(n, 3))[:n], **kw)
@@ -127,6 +131,15 @@ def test_workspace_size_grows_with_instance():
     assert 0 < a < b
     # dense pheromone + distances dominate: at least n*n*(4+2) bytes
     assert b >= 2392 * 2392 * 6
+
+
+def test_sequential_mode_workspace_holds_visited_bitmaps():
+    p = acs.acs_default_params()
+    base = acs.acs_workspace_bytes(1000, p)
+    p.mode = acs.ACS_SEQUENTIAL
+    seq = acs.acs_workspace_bytes(1000, p)
+    # m = n = 1000 bitmaps of ceil(1000 / 32) words, 256-byte aligned
+    assert seq - base == (1000 * 32 * 4 + 255) // 256 * 256
 
 
 def test_without_gpu_create_reports_device_error():
