@@ -119,6 +119,92 @@ __device__ __forceinline__ f32x4 forward16(const Stage &S, float4 x, int lane, _
   return d;
 }
 
+// Inference with everything in registers.  The products are computed
+// transposed, Z^T = W^T H^T, so a layer's output tile (lane l: hidden units
+// 16t + 4(l/16) + v of row l % 16) is already the next layer's B operand
+// once the K index of that layer is permuted to match: within K block b,
+// B-row 8g + q is hidden unit 32b + 4g + q for q < 4 and 32b + 16 + 4g +
+// (q - 4) for q >= 4.  The weight tiles (A operands) are built in that
+// order once per wave.  The 64 -> 1 layer runs on the vector unit, on the
+// bf16-rounded activations, and the four lane groups' partial sums meet by
+// lane swaps.  No LDS.
+struct RegNet {
+  bf16x8 w1[4];     // A of layer 1, tile t: W1^T[16t + l%16][8(l/16) + q] (k < 4)
+  bf16x8 w2[4][2];  // A of layer 2, tile t, K block b (permuted K)
+  float b1[4][4], b2[4][4], w3[4][4];  // [t][v] at hidden 16t + 4(l/16) + v
+  float b3;
+};
+
+__device__ __forceinline__ int perm_k(int b, int g, int q) {
+  return q < 4 ? 32 * b + 4 * g + q : 32 * b + 16 + 4 * g + (q - 4);
+}
+
+__device__ __forceinline__ void load_regnet(RegNet &R, const float *P, int lane) {
+  const int g = lane >> 4, c16 = lane & 15;
+#pragma unroll
+  for (int t = 0; t < 4; ++t) {
+#pragma unroll
+    for (int q = 0; q < 8; ++q) {
+      const int k = 8 * g + q;
+      R.w1[t][q] = (__bf16)(k < 4 ? P[OW1 + k * H + 16 * t + c16] : 0.f);
+    }
+#pragma unroll
+    for (int b = 0; b < 2; ++b)
+#pragma unroll
+      for (int q = 0; q < 8; ++q)
+        R.w2[t][b][q] = (__bf16)P[OW2 + perm_k(b, g, q) * H + 16 * t + c16];
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int h = 16 * t + 4 * g + v;
+      R.b1[t][v] = P[OB1 + h];
+      R.b2[t][v] = P[OB2 + h];
+      R.w3[t][v] = (float)(__bf16)P[OW3 + h];
+    }
+  }
+  R.b3 = P[OB3];
+}
+
+// Logit of row l % 16 of a 16-row tile (every lane of the row's four lane
+// groups gets it); x: the row's features.
+__device__ __forceinline__ float forward16r(const RegNet &R, float4 x, int lane) {
+  const int g = lane >> 4;
+  bf16x8 bx;
+#pragma unroll
+  for (int q = 0; q < 8; ++q) bx[q] = (__bf16)0.f;
+  if (g == 0) {
+    bx[0] = (__bf16)x.x;
+    bx[1] = (__bf16)x.y;
+    bx[2] = (__bf16)x.z;
+    bx[3] = (__bf16)x.w;
+  }
+  const f32x4 zero = {0.f, 0.f, 0.f, 0.f};
+  bf16x8 h1[2];
+#pragma unroll
+  for (int t = 0; t < 4; ++t) {
+    const f32x4 d = mfma(R.w1[t], bx, zero);
+#pragma unroll
+    for (int v = 0; v < 4; ++v) h1[t >> 1][4 * (t & 1) + v] = (__bf16)fmaxf(d[v] + R.b1[t][v], 0.f);
+  }
+  float part = 0.f;
+#pragma unroll
+  for (int t = 0; t < 4; ++t) {
+    f32x4 d = mfma(R.w2[t][0], h1[0], zero);
+    d = mfma(R.w2[t][1], h1[1], d);
+#pragma unroll
+    for (int v = 0; v < 4; ++v)
+      part = fmaf((float)(__bf16)fmaxf(d[v] + R.b2[t][v], 0.f), R.w3[t][v], part);
+  }
+  // sum over the four lane groups: each swap pairs a lane with its partner,
+  // and the two results of a swap add up to own + partner
+  const auto a = __builtin_amdgcn_permlane16_swap(__float_as_uint(part), __float_as_uint(part),
+                                                  false, false);
+  part = __uint_as_float(a[0]) + __uint_as_float(a[1]);
+  const auto b = __builtin_amdgcn_permlane32_swap(__float_as_uint(part), __float_as_uint(part),
+                                                  false, false);
+  part = __uint_as_float(b[0]) + __uint_as_float(b[1]);
+  return part + R.b3;
+}
+
 __device__ __forceinline__ float4 load_x(const float *X, int row, int rows) {
   return row < rows ? *reinterpret_cast<const float4 *>(X + (size_t)row * 4)
                     : make_float4(0.f, 0.f, 0.f, 0.f);
@@ -130,20 +216,23 @@ constexpr int kFwdWaves = 4;
 
 __global__ __launch_bounds__(64 * kFwdWaves) void k_prior_forward(const float *P, const float *X,
                                                                   int rows, float *Z) {
-  __shared__ Stage S;
-  __shared__ alignas(16) __bf16 hb[kFwdWaves][2][16 * H];
-  stage_weights(S, P);
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-  __bf16 *h1 = hb[wv][0], *h2 = hb[wv][1];
-  for (int r0 = (blockIdx.x * kFwdWaves + wv) * 16; r0 < rows;
-       r0 += gridDim.x * kFwdWaves * 16) {
-    wave_sync();
-    const f32x4 z = forward16(S, load_x(X, r0 + (lane & 15), rows), lane, h1, h2);
-    if ((lane & 15) == 0)
-      for (int v = 0; v < 4; ++v) {
-        const int r = r0 + 4 * (lane >> 4) + v;
-        if (r < rows) Z[r] = z[v];
-      }
+  RegNet R;
+  load_regnet(R, P, lane);
+  // two independent 16-row tiles per pass (their matrix and vector work
+  // interleave), the next pass's features loaded ahead
+  const int stride = gridDim.x * kFwdWaves * 32;
+  int r0 = (blockIdx.x * kFwdWaves + wv) * 32;
+  float4 xa = load_x(X, r0 + (lane & 15), rows), xb = load_x(X, r0 + 16 + (lane & 15), rows);
+  for (; r0 < rows; r0 += stride) {
+    const float4 na = load_x(X, r0 + stride + (lane & 15), rows);
+    const float4 nb = load_x(X, r0 + stride + 16 + (lane & 15), rows);
+    const float za = forward16r(R, xa, lane), zb = forward16r(R, xb, lane);
+    const int row = r0 + (lane & 15);
+    if (lane < 16 && row < rows) Z[row] = za;
+    if (lane < 16 && row + 16 < rows) Z[row + 16] = zb;
+    xa = na;
+    xb = nb;
   }
 }
 
@@ -319,27 +408,20 @@ __global__ __launch_bounds__(256) void k_prior_features(Dev D, float *X) {
 // Scores of every candidate edge of the instance straight into the
 // eta^beta word of the candidate records: max(sigmoid(z), 1e-6).
 __global__ __launch_bounds__(64 * kFwdWaves) void k_prior_apply(Dev D, const float *P) {
-  __shared__ Stage S;
-  __shared__ alignas(16) __bf16 hb[kFwdWaves][2][16 * H];
-  stage_weights(S, P);
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-  __bf16 *h1 = hb[wv][0], *h2 = hb[wv][1];
+  RegNet R;
+  load_regnet(R, P, lane);
   const int rows = D.n * 16;
   for (int r0 = (blockIdx.x * kFwdWaves + wv) * 16; r0 < rows;
        r0 += gridDim.x * kFwdWaves * 16) {
-    wave_sync();
     const int row = r0 + (lane & 15);
     const float4 x = row < rows ? edge_features(D, row / 16, row % 16)
                                 : make_float4(0.f, 0.f, 0.f, 0.f);
-    const f32x4 z = forward16(S, x, lane, h1, h2);
-    if ((lane & 15) == 0)
-      for (int v = 0; v < 4; ++v) {
-        const int r = r0 + 4 * (lane >> 4) + v;
-        if (r < rows) {
-          const float sc = fmaxf(1.f / (1.f + __expf(-z[v])), 1e-6f);
-          const_cast<uint4 *>(D.crec)[(size_t)(r / 16) * D.cl + r % 16].z = __float_as_uint(sc);
-        }
-      }
+    const float z = forward16r(R, x, lane);
+    if (lane < 16 && row < rows) {
+      const float sc = fmaxf(1.f / (1.f + __expf(-z)), 1e-6f);
+      const_cast<uint4 *>(D.crec)[(size_t)(row / 16) * D.cl + row % 16].z = __float_as_uint(sc);
+    }
   }
 }
 
@@ -347,7 +429,7 @@ __global__ __launch_bounds__(64 * kFwdWaves) void k_prior_apply(Dev D, const flo
 
 hipError_t launch_prior_forward(const float *P, const float *X, int rows, float *Z,
                                 hipStream_t s) {
-  const int tiles = (rows + 15) / 16;
+  const int tiles = (rows + 31) / 32;
   int blocks = (tiles + kFwdWaves - 1) / kFwdWaves;
   blocks = blocks < 1024 ? (blocks > 0 ? blocks : 1) : 1024;
   hipLaunchKernelGGL(k_prior_forward, dim3(blocks), dim3(64 * kFwdWaves), 0, s, P, X, rows, Z);
