@@ -46,7 +46,7 @@ size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
 
 // Device buffers of one handle, as offsets into one allocation.
 struct Layout {
-  size_t xy, dist, crec, cand, eta, tau, etad, rpos, ctau, gvis, spm, spm_tail, xnn, upd_rec, upd_nb, upd_next, upd_head, tours, lens,
+  size_t xy, dist, crec, cand, eta, tau, tau2, etad, rpos, ctau, gvis, spm, spm_tail, xnn, upd_rec, upd_nb, upd_next, upd_head, tours, lens,
       best, gstate, counters, sync, dmax, lnn, total;
 };
 
@@ -71,6 +71,7 @@ Layout make_layout(int n, int m, int cl, int ldn, int memory, int s, int mode) {
     L.rpos = take(sizeof(int8_t) * (size_t)n * cl);
     L.ctau = take(sizeof(float) * (size_t)n * cl);
     if (mode == ACS_SEQUENTIAL) L.gvis = take(sizeof(uint32_t) * (size_t)m * ((n + 31) / 32));
+    if (mode == ACS_SYNC) L.tau2 = take(sizeof(float) * (size_t)n * ldn);
   } else {
     L.spm = take(sizeof(uint32_t) * 2 * (size_t)n * s);
     L.spm_tail = take(sizeof(uint32_t) * (size_t)n);
@@ -343,6 +344,7 @@ int acs_create(const double *coords_xy, int32_t n, const acs_params *p, acs_t **
     d.rpos = reinterpret_cast<const int8_t *>(w + h->L.rpos);
     d.ctau = reinterpret_cast<float *>(w + h->L.ctau);
     if (p->mode == ACS_SEQUENTIAL) d.gvis = reinterpret_cast<uint32_t *>(w + h->L.gvis);
+    if (p->mode == ACS_SYNC) d.tau2 = reinterpret_cast<float *>(w + h->L.tau2);
   } else {
     d.spm = reinterpret_cast<uint2 *>(w + h->L.spm);
     d.spm_tail = reinterpret_cast<uint32_t *>(w + h->L.spm_tail);

@@ -20,6 +20,7 @@ struct Dev {
   const uint4 *crec;       // n x cl candidate records (see above)
   const float *eta_tab;    // eta^beta indexed by distance (dmax + 1)
   float *tau;              // dense: n x ldn, home of non-candidate entries
+  float *tau2;             // dense synchronous mode: the second buffer of tau
   const float *etad;       // dense: n x ldn, eta^beta(d(i, j))
   const int8_t *rpos;      // dense: n x cl, position of i in the candidate list
                            //   of its k-th candidate, -1 if i is not in it

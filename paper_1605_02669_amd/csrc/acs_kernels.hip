@@ -486,10 +486,10 @@ __device__ __forceinline__ int pick_candidate(const Iter &A, int lane, int cl, C
 // in flight is fixed and the wait covers round r only).
 template <bool COHERENT>
 __device__ __forceinline__ Pick fallback_dense(const Dev &D, const uint32_t *vis, int cur,
-                                               int lane) {
+                                               int lane, const float *tsrc = nullptr) {
   const int n = D.n;
   Pick p;
-  const float *trow = D.tau + (size_t)cur * D.ldn;
+  const float *trow = (tsrc ? tsrc : D.tau) + (size_t)cur * D.ldn;
   const float *erow = D.etad + (size_t)cur * D.ldn;
   const uint16_t *drow = D.dist + (size_t)cur * D.ldn;
   const int rounds = (n + 511) >> 9;
@@ -547,12 +547,14 @@ __device__ __forceinline__ Pick fallback_dense(const Dev &D, const uint32_t *vis
   return p;
 }
 
+// tsrc: the dense pheromone matrix to read (default D.tau)
 template <bool COHERENT>
 __device__ __forceinline__ Pick select_dense(const Dev &D, const Iter &A, const uint32_t *vis,
-                                             int cur, int lane, uint4 rec, Cand c, uint2 q) {
+                                             int cur, int lane, uint4 rec, Cand c, uint2 q,
+                                             const float *tsrc = nullptr) {
   Pick p;
   const int k = pick_candidate(A, lane, D.cl, c, q, p.kind);
-  if (k < 0) return fallback_dense<COHERENT>(D, vis, cur, lane);
+  if (k < 0) return fallback_dense<COHERENT>(D, vis, cur, lane, tsrc);
   p.k = k;
   p.next = (int)rdlane(rec.x, k);
   p.d = rdlane(rec.y, k);
@@ -591,7 +593,22 @@ __device__ __forceinline__ void tour_put(const Dev &D, int ant, int t, int lane,
 // With a local-update period above 1, a step without updates leaves the
 // pheromone as it is, so it needs neither barrier; the closing edges wait for
 // the last step's selections before they write.
+//
+// With a period of 1 the pheromone is double-buffered instead, which needs
+// one barrier per step: buffer 0 is (candidate records' words, tau), buffer
+// 1 is (ctau, tau2), and buffer 1 starts the construction as a copy of
+// buffer 0 (k_sync_buf).  Step t selects from buffer t % 2, which holds every
+// update of steps < t, and applies the crossings of steps t - 1 and t to
+// buffer (t + 1) % 2, which then holds every update of steps < t + 1; nobody
+// reads that buffer during step t, and the barrier at the end of the step
+// separates its writes from step t + 1's reads and step t's reads from step
+// t + 1's writes.  The closing edges go to buffer n % 2, the final one.
 // ---------------------------------------------------------------------------
+__device__ __forceinline__ float *sync_home(const Dev &D, int buf, int u, int v, int k) {
+  if (buf == 0) return home(D, u, v, k);
+  return k >= 0 ? D.ctau + (size_t)u * D.cl + k : D.tau2 + (size_t)u * D.ldn + v;
+}
+
 __global__ __launch_bounds__(1024) void k_construct_sync_dense(Dev D, Iter A) {
   extern __shared__ uint32_t smem[];
   const int lane = threadIdx.x & 63;
@@ -602,6 +619,7 @@ __global__ __launch_bounds__(1024) void k_construct_sync_dense(Dev D, Iter A) {
   const int W = (n + 31) >> 5;
   const int kl = lane < cl ? lane : cl - 1;
   uint32_t *vis = smem + wv * W;
+  const bool dbuf = A.lperiod == 1;
 
   for (int w = lane; w < W; w += 64) vis[w] = 0u;
   uint4 draws = philox_batch(A, ant, 0, lane);
@@ -614,14 +632,20 @@ __global__ __launch_bounds__(1024) void k_construct_sync_dense(Dev D, Iter A) {
   uint32_t c_greedy = 0, c_roul = 0, c_fb = 0, c_retry = 0;
   uint64_t c_fbu = 0;
   uint32_t bar = 0;
+  // the previous step's crossing (double-buffered schedule)
+  int pu = -1, pv = -1, pk = -1, pk2 = -1;
+  float pval = 0.f;
   for (int t = 1; t < n; ++t) {
     Pick p{};
+    const int rb = dbuf ? (t & 1) : 0;
     if ((t & 63) == 0) draws = philox_batch(A, ant, t, lane);
     if (active) {
       uint4 rec = D.crec[(size_t)cur * cl + kl];
-      rec.w = __float_as_uint(tau_load(cand_tau(D, cur, kl)));
+      const float *ct = rb == 0 ? cand_tau(D, cur, kl) : D.ctau + (size_t)cur * cl + kl;
+      rec.w = __float_as_uint(tau_load(ct));
       const Cand c = weigh(D, vis, lane, rec);
-      p = select_dense<true>(D, A, vis, cur, lane, rec, c, draw_of(draws, t));
+      p = select_dense<true>(D, A, vis, cur, lane, rec, c, draw_of(draws, t),
+                             rb == 0 ? D.tau : D.tau2);
       c_greedy += p.kind == 0;
       c_roul += p.kind == 1;
       if (p.kind == 2) { ++c_fb; c_fbu += (uint64_t)(n - t); }
@@ -629,7 +653,30 @@ __global__ __launch_bounds__(1024) void k_construct_sync_dense(Dev D, Iter A) {
       tour_put(D, ant, t, lane, p.next, tb);
       len += p.d;
     }
-    if (t % A.lperiod == 0) {
+    if (dbuf) {
+      // crossings of steps t - 1 and t into buffer (t + 1) % 2: lanes 0 and
+      // 1 the previous crossing's two entries, lanes 2 and 3 this one's
+      if (active) {
+        const int k2 = cand_pos(D, p.next, cur, lane);
+        const int wb = rb ^ 1;
+        float *h = nullptr;
+        unsigned int seen = 0;
+        if (lane < 2 && pu >= 0) {
+          h = lane == 0 ? sync_home(D, wb, pu, pv, pk) : sync_home(D, wb, pv, pu, pk2);
+          seen = __float_as_uint(pval);
+        } else if (lane == 2 || lane == 3) {
+          h = lane == 2 ? sync_home(D, wb, cur, p.next, p.k) : sync_home(D, wb, p.next, cur, k2);
+          seen = __float_as_uint(p.tval);
+        }
+        if (h) c_retry += cas_apply(h, seen, A.a_loc, A.b_loc);
+        pu = cur;
+        pv = p.next;
+        pk = p.k;
+        pk2 = k2;
+        pval = p.tval;
+      }
+      grid_barrier(D.sync, (++bar) * gridDim.x);
+    } else if (t % A.lperiod == 0) {
       grid_barrier(D.sync, (++bar) * gridDim.x);
       if (active) {
         const int k2 = cand_pos(D, p.next, cur, lane);
@@ -640,22 +687,42 @@ __global__ __launch_bounds__(1024) void k_construct_sync_dense(Dev D, Iter A) {
     }
     if (active) cur = p.next;
   }
-  if ((n - 1) % A.lperiod != 0) grid_barrier(D.sync, (++bar) * gridDim.x);
+  if (!dbuf && (n - 1) % A.lperiod != 0) grid_barrier(D.sync, (++bar) * gridDim.x);
   if (active) {
     // closing edge: its length and, as the last step's crossings, its update
     len += D.dist[(size_t)cur * D.ldn + start];
+    const int fb = dbuf ? (n & 1) : 0;
     const int k1 = cand_pos(D, cur, start, lane);
     const int k2 = cand_pos(D, start, cur, lane);
-    float *h = lane == 0 ? home(D, cur, start, k1) : home(D, start, cur, k2);
+    float *h = lane == 0 ? sync_home(D, fb, cur, start, k1) : sync_home(D, fb, start, cur, k2);
     if (lane < 2) {
       const float seen = tau_load(h);
       c_retry += cas_apply(h, __float_as_uint(seen), A.a_loc, A.b_loc);
     }
-    c_retry = (uint32_t)uni((int)(rdlane(c_retry, 0) + rdlane(c_retry, 1)));
+    c_retry = (uint32_t)uni((int)(rdlane(c_retry, 0) + rdlane(c_retry, 1) + rdlane(c_retry, 2) +
+                                  rdlane(c_retry, 3)));
     if (lane == 0) {
       D.lens[ant] = len;
       add_counters(D, c_greedy, c_roul, c_fb, c_fbu, c_retry);
     }
+  }
+}
+
+// Buffer 1 of the double-buffered synchronous schedule from buffer 0 (dir 0),
+// or buffer 0 from buffer 1 (dir 1) when the construction ended in buffer 1.
+__global__ __launch_bounds__(256) void k_sync_buf(Dev D, int dir) {
+  const size_t e = (size_t)blockIdx.x * 256 + threadIdx.x;
+  if (e < (size_t)D.n * D.cl) {
+    if (dir == 0)
+      D.ctau[e] = __uint_as_float(D.crec[e].w);
+    else
+      const_cast<uint4 *>(D.crec)[e].w = __float_as_uint(D.ctau[e]);
+  }
+  if (e < (size_t)D.n * D.ldn) {
+    if (dir == 0)
+      D.tau2[e] = D.tau[e];
+    else
+      D.tau[e] = D.tau2[e];
   }
 }
 
@@ -2341,8 +2408,18 @@ hipError_t launch_construct(const Dev &d, const Iter &it, int mode, int memory, 
     void *args[] = {&dd, &a};
     const void *fn = memory == 0 ? reinterpret_cast<const void *>(&k_construct_sync_dense)
                                  : reinterpret_cast<const void *>(&k_construct_sync_spm);
-    return hipLaunchCooperativeKernel(fn, dim3(grid), dim3(kSyncBlock), args,
-                                      lds_bytes(d, kSyncBlock), s);
+    const bool dbuf = memory == 0 && it.lperiod == 1;
+    const dim3 gb((unsigned)(((size_t)d.n * d.ldn + 255) / 256));
+    if (dbuf) {
+      hipLaunchKernelGGL(k_sync_buf, gb, dim3(256), 0, s, d, 0);
+      const hipError_t e = hipGetLastError();
+      if (e != hipSuccess) return e;
+    }
+    const hipError_t e = hipLaunchCooperativeKernel(fn, dim3(grid), dim3(kSyncBlock), args,
+                                                    lds_bytes(d, kSyncBlock), s);
+    if (e != hipSuccess || !dbuf || (d.n & 1) == 0) return e;
+    hipLaunchKernelGGL(k_sync_buf, gb, dim3(256), 0, s, d, 1);
+    return hipGetLastError();
   }
   const int apb = kAsyncBlock / 64;
   const int grid = (d.m + apb - 1) / apb;

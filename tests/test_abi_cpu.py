@@ -133,13 +133,18 @@ def test_workspace_size_grows_with_instance():
     assert b >= 2392 * 2392 * 6
 
 
-def test_sequential_mode_workspace_holds_visited_bitmaps():
+def test_mode_specific_workspace():
     p = acs.acs_default_params()
+    p.mode = acs.ACS_ASYNC_ATOMIC
     base = acs.acs_workspace_bytes(1000, p)
     p.mode = acs.ACS_SEQUENTIAL
     seq = acs.acs_workspace_bytes(1000, p)
-    # m = n = 1000 bitmaps of ceil(1000 / 32) words, 256-byte aligned
+    p.mode = acs.ACS_SYNC
+    sync = acs.acs_workspace_bytes(1000, p)
+    # sequential: m = n = 1000 visited bitmaps of ceil(1000 / 32) words
     assert seq - base == (1000 * 32 * 4 + 255) // 256 * 256
+    # synchronous: the second buffer of the dense matrix (ldn = 1024)
+    assert sync - base == 1000 * 1024 * 4
 
 
 def test_without_gpu_create_reports_device_error():
