@@ -46,7 +46,7 @@ size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
 
 // Device buffers of one handle, as offsets into one allocation.
 struct Layout {
-  size_t xy, dist, crec, cand, eta, tau, tau2, etad, rpos, ctau, gvis, spm, spm_tail, xnn, upd_rec, upd_nb, upd_next, upd_head, tours, lens,
+  size_t xy, dist, crec, cand, eta, tau, tau2, etad, rpos, ctau, gvis, bflags, spm, spm_tail, xnn, upd_rec, upd_nb, upd_next, upd_head, tours, lens,
       best, gstate, counters, sync, dmax, lnn, total;
 };
 
@@ -81,6 +81,7 @@ Layout make_layout(int n, int m, int cl, int ldn, int memory, int s, int mode) {
     L.upd_next = take(sizeof(int32_t) * 2 * (size_t)m);
     L.upd_head = take(sizeof(int32_t) * (size_t)n);
   }
+  if (mode == ACS_SYNC) L.bflags = take(sizeof(uint64_t) * 16 * (size_t)((m + 15) / 16 + 1));
   L.tours = take(sizeof(int32_t) * (size_t)m * n);
   L.lens = take(sizeof(int64_t) * (size_t)m);
   L.best = take(sizeof(int32_t) * (size_t)n);
@@ -361,6 +362,10 @@ int acs_create(const double *coords_xy, int32_t n, const acs_params *p, acs_t **
   d.gstate = reinterpret_cast<int64_t *>(w + h->L.gstate);
   d.counters = reinterpret_cast<unsigned long long *>(w + h->L.counters);
   d.sync = reinterpret_cast<uint32_t *>(w + h->L.sync);
+  if (p->mode == ACS_SYNC) {
+    d.bflags = reinterpret_cast<unsigned long long *>(w + h->L.bflags);
+    d.nbflags = 16 * ((m + 15) / 16 + 1);
+  }
 
   if (p->mode == ACS_SYNC) {
     const int cap = acs::max_sync_ants(d, (int)p->memory);

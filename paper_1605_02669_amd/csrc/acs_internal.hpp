@@ -48,6 +48,9 @@ struct Dev {
                                  // unvisited cities at fallback steps,
                                  // compare-and-swap retries
   uint32_t *sync;          // [0] grid barrier counter, [1] error flag
+  unsigned long long *bflags;  // synchronous mode: barrier release word, then one
+                               //   flag per block, 16 words (128 bytes) apart
+  int32_t nbflags;             //   words in bflags
 };
 
 // Per-iteration scalars.

@@ -209,11 +209,78 @@ __device__ __forceinline__ void grid_barrier(uint32_t *sync, uint32_t target) {
     __hip_atomic_fetch_add(sync, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     uint32_t spins = 0;
     while (__hip_atomic_load(sync, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < target) {
-      // once any block has given up, no later barrier waits either
-      if (__hip_atomic_load(sync + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) break;
+      // once any block has given up, no later barrier waits either (looked
+      // at every 64th poll, so a poll is one load)
+      if ((spins & 63) == 63 &&
+          __hip_atomic_load(sync + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT))
+        break;
       __builtin_amdgcn_s_sleep(1);
       if (++spins > (1u << 22)) {
         __hip_atomic_store(sync + 1, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        break;
+      }
+    }
+  }
+  __syncthreads();
+  __atomic_signal_fence(__ATOMIC_SEQ_CST);
+}
+
+// Grid-wide barrier by flags (for grids of more than 32 blocks): each block
+// stores the barrier's epoch into a flag of its own (its own 128-byte line),
+// the first wave of block 0 waits until every flag holds the epoch and then
+// stores it into the release word, which every block waits for.  No two
+// blocks write the same line, so arrival costs one store instead of a
+// read-modify-write queued behind every other block's on one counter.  Epochs are (iteration << 32 | barrier
+// number), so flags left by an earlier construction never match.  Waits are
+// bounded like grid_barrier's and share its error flag.
+__device__ __forceinline__ uint64_t barrier_epoch(const Iter &A, uint32_t bar) {
+  return ((uint64_t)A.it << 32) | bar;
+}
+
+__device__ __forceinline__ bool barrier_gave_up(const Dev &D, uint32_t spins) {
+  return (spins & 63) == 63 &&
+         __hip_atomic_load(D.sync + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0;
+}
+
+__device__ __forceinline__ void grid_barrier_f(const Dev &D, uint64_t epoch) {
+  // few blocks: one counter is quicker (one hop instead of two)
+  if (gridDim.x <= 32) {
+    grid_barrier(D.sync, (uint32_t)epoch * gridDim.x);
+    return;
+  }
+  __builtin_amdgcn_s_waitcnt(0);
+  __syncthreads();
+  unsigned long long *rel = D.bflags;
+  if (threadIdx.x == 0)
+    __hip_atomic_store(D.bflags + 16 * ((size_t)blockIdx.x + 1), (unsigned long long)epoch,
+                       __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  if (blockIdx.x == 0 && threadIdx.x < 64) {
+    uint32_t spins = 0;
+    while (true) {
+      bool all = true;
+      for (uint32_t b = threadIdx.x; b < gridDim.x; b += 64)
+        all &= __hip_atomic_load(D.bflags + 16 * ((size_t)b + 1), __ATOMIC_RELAXED,
+                                 __HIP_MEMORY_SCOPE_AGENT) == epoch;
+      if (__ballot(!all) == 0) break;
+      if (barrier_gave_up(D, spins)) break;
+      __builtin_amdgcn_s_sleep(1);
+      if (++spins > (1u << 22)) {
+        if (threadIdx.x == 0)
+          __hip_atomic_store(D.sync + 1, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        break;
+      }
+    }
+    if (threadIdx.x == 0)
+      __hip_atomic_store(rel, (unsigned long long)epoch, __ATOMIC_RELAXED,
+                         __HIP_MEMORY_SCOPE_AGENT);
+  }
+  if (threadIdx.x == 0) {
+    uint32_t spins = 0;
+    while (__hip_atomic_load(rel, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != epoch) {
+      if (barrier_gave_up(D, spins)) break;
+      __builtin_amdgcn_s_sleep(1);
+      if (++spins > (1u << 22)) {
+        __hip_atomic_store(D.sync + 1, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         break;
       }
     }
@@ -394,6 +461,7 @@ __global__ __launch_bounds__(256) void k_init(Dev D, float tau0) {
     D.spm_tail[e] = (uint32_t)(D.spm_s - 1);
     D.upd_head[e] = -1;
   }
+  if (D.bflags && e < (size_t)D.nbflags) D.bflags[e] = 0ull;
   if (e == 0) {
     D.gstate[0] = -1;
     D.gstate[1] = -1;
@@ -675,19 +743,19 @@ __global__ __launch_bounds__(1024) void k_construct_sync_dense(Dev D, Iter A) {
         pk2 = k2;
         pval = p.tval;
       }
-      grid_barrier(D.sync, (++bar) * gridDim.x);
+      grid_barrier_f(D, barrier_epoch(A, ++bar));
     } else if (t % A.lperiod == 0) {
-      grid_barrier(D.sync, (++bar) * gridDim.x);
+      grid_barrier_f(D, barrier_epoch(A, ++bar));
       if (active) {
         const int k2 = cand_pos(D, p.next, cur, lane);
         float *h = lane == 0 ? home(D, cur, p.next, p.k) : home(D, p.next, cur, k2);
         if (lane < 2) c_retry += cas_apply(h, __float_as_uint(p.tval), A.a_loc, A.b_loc);
       }
-      if (t + 1 < n) grid_barrier(D.sync, (++bar) * gridDim.x);
+      if (t + 1 < n) grid_barrier_f(D, barrier_epoch(A, ++bar));
     }
     if (active) cur = p.next;
   }
-  if (!dbuf && (n - 1) % A.lperiod != 0) grid_barrier(D.sync, (++bar) * gridDim.x);
+  if (!dbuf && (n - 1) % A.lperiod != 0) grid_barrier_f(D, barrier_epoch(A, ++bar));
   if (active) {
     // closing edge: its length and, as the last step's crossings, its update
     len += D.dist[(size_t)cur * D.ldn + start];
@@ -1934,11 +2002,11 @@ __global__ __launch_bounds__(1024) void k_construct_sync_spm(Dev D, Iter A) {
       if (active && lane < 2)
         lead = spm_register(D, 2 * ant + lane, lane == 0 ? cur : next, lane == 0 ? next : cur);
       const uint64_t leads = __ballot(lead);
-      grid_barrier(D.sync, (++bar) * gridDim.x);
+      grid_barrier_f(D, barrier_epoch(A, ++bar));
       if (active)
         spm_sync_updates(D, leads & 1u, (leads >> 1) & 1u, cur, next, A.a_loc, A.b_loc, tau0,
                          lane, hits, misses);
-      if (t < n) grid_barrier(D.sync, (++bar) * gridDim.x);
+      if (t < n) grid_barrier_f(D, barrier_epoch(A, ++bar));
     }
     cur = next;
   }
@@ -2335,6 +2403,8 @@ size_t lds_bytes(const Dev &D, int block) {
 }
 
 constexpr int kSyncBlock = 1024;
+// the host sizes the barrier flags (Dev::bflags) for 16 ants per block
+static_assert(kSyncBlock == 64 * 16, "one synchronous block holds 16 ants");
 constexpr int kAsyncBlock = 256;
 
 }  // namespace
@@ -2384,6 +2454,7 @@ hipError_t launch_init_pheromone(const Dev &d, float tau0, hipStream_t s) {
   size_t total = (size_t)d.n * d.ldn;
   if (total < (size_t)d.n * d.spm_s) total = (size_t)d.n * d.spm_s;
   if (total < 8) total = 8;
+  if (total < (size_t)d.nbflags) total = (size_t)d.nbflags;
   hipLaunchKernelGGL(k_init, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, s, d, tau0);
   return hipGetLastError();
 }

@@ -143,8 +143,11 @@ def test_mode_specific_workspace():
     sync = acs.acs_workspace_bytes(1000, p)
     # sequential: m = n = 1000 visited bitmaps of ceil(1000 / 32) words
     assert seq - base == (1000 * 32 * 4 + 255) // 256 * 256
-    # synchronous: the second buffer of the dense matrix (ldn = 1024)
-    assert sync - base == 1000 * 1024 * 4
+    # synchronous: the second buffer of the dense matrix (ldn = 1024) and the
+    # barrier flags (a release word and one per block of 16 ants, 128 bytes
+    # apart), each 256-byte aligned
+    flags = 8 * 16 * ((1000 + 15) // 16 + 1)
+    assert sync - base == 1000 * 1024 * 4 + (flags + 255) // 256 * 256
 
 
 def test_without_gpu_create_reports_device_error():
