@@ -1260,10 +1260,11 @@ __device__ __forceinline__ void ring_updater(const Dev &D, const Iter &A, const 
 // block's updater wave.  The step holds only what Alg. 2 needs: weigh the
 // current city's record, choose (Eq. 1 or Eq. 2 over the candidate set, the
 // fallback when it is empty), mark, issue the next record's load, and note
-// the crossing in the chunk entry.  Records come by buffer loads (the lane's
-// offset fixed, the row's a scalar; a read outside the table returns zeros
-// instead of faulting).  HALF: every candidate list fits lanes 0..31.
-// Decisions are the same as those of ant_async_dense.
+// the crossing in the lane of its step; every kQGroup steps the noted
+// crossings go to the ring.  Records and their live pheromone (ctau) come by
+// buffer loads (the lane's offset fixed, the row's a scalar; a read outside
+// the table returns zeros instead of faulting).  HALF: every candidate list
+// fits lanes 0..31.  Decisions are the same as those of ant_async_dense.
 // ---------------------------------------------------------------------------
 template <bool ATOMIC, bool HALF>
 __device__ __forceinline__ void ant_queued(const Dev &D, const Iter &A, int ant, uint32_t *vis,
