@@ -185,6 +185,14 @@ __device__ __forceinline__ uint32_t cas_apply(float *p, unsigned int seen, float
   return retries;
 }
 
+// Whether the local map leaves x unchanged (in fp32).  During a
+// construction an entry only receives that map, so an entry read at such a
+// value still holds it, and its update can be skipped without changing any
+// result.
+__device__ __forceinline__ bool map_fixed(float x, float a, float b) {
+  return __float_as_uint(fmaf(a, x, b)) == __float_as_uint(x);
+}
+
 // Position of v in the candidate list of u (wave-uniform), or -1.
 __device__ __forceinline__ int cand_pos(const Dev &D, int u, int v, int lane) {
   const int kl = lane < D.cl ? lane : D.cl - 1;
@@ -736,7 +744,10 @@ __global__ __launch_bounds__(1024) void k_construct_sync_dense(Dev D, Iter A) {
           h = lane == 2 ? sync_home(D, wb, cur, p.next, p.k) : sync_home(D, wb, p.next, cur, k2);
           seen = __float_as_uint(p.tval);
         }
-        if (h) c_retry += cas_apply(h, seen, A.a_loc, A.b_loc);
+        // a value the map leaves unchanged stays so under the maps that reach
+        // the entry in this step: the update changes nothing
+        if (h && !map_fixed(__uint_as_float(seen), A.a_loc, A.b_loc))
+          c_retry += cas_apply(h, seen, A.a_loc, A.b_loc);
         pu = cur;
         pv = p.next;
         pk = p.k;
@@ -749,7 +760,8 @@ __global__ __launch_bounds__(1024) void k_construct_sync_dense(Dev D, Iter A) {
       if (active) {
         const int k2 = cand_pos(D, p.next, cur, lane);
         float *h = lane == 0 ? home(D, cur, p.next, p.k) : home(D, p.next, cur, k2);
-        if (lane < 2) c_retry += cas_apply(h, __float_as_uint(p.tval), A.a_loc, A.b_loc);
+        if (lane < 2 && !map_fixed(p.tval, A.a_loc, A.b_loc))
+          c_retry += cas_apply(h, __float_as_uint(p.tval), A.a_loc, A.b_loc);
       }
       if (t + 1 < n) grid_barrier_f(D, barrier_epoch(A, ++bar));
     }
@@ -994,10 +1006,11 @@ __device__ __forceinline__ void ant_async_dense(const Dev &D, const Iter &A, int
           pexp = __float_as_uint(rval);
           pend = true;
         }
+        if (pend && map_fixed(__uint_as_float(pexp), al, bl)) pend = false;
         if (pend)
           pret = atomicCAS(reinterpret_cast<unsigned int *>(pptr), pexp,
                            __float_as_uint(fmaf(al, __uint_as_float(pexp), bl)));
-      } else if (lane < 2) {
+      } else if (lane < 2 && !map_fixed(lane == 0 ? fval : rval, al, bl)) {
         float *h = lane == 0 ? fwd : home(D, cur, prev, kr);
         __hip_atomic_store(h, fmaf(al, lane == 0 ? fval : rval, bl), __ATOMIC_RELAXED,
                            __HIP_MEMORY_SCOPE_AGENT);
@@ -1150,6 +1163,9 @@ __device__ __forceinline__ uint32_t apply_entries(const Dev &D, const Iter &A, u
     float *pc = fwd_canon || both_dense ? pf : pr;
     float *po = fwd_canon || both_dense ? pr : pf;
     unsigned int seen = e.z, nw;
+    // the value the ant read is one the edge's entries have held; if the
+    // map leaves it unchanged (map_fixed), they hold it now: skip both writes
+    if (map_fixed(__uint_as_float(seen), al, bl)) return 0;
     uint32_t r = 0;
     while (true) {
       nw = __float_as_uint(fmaf(al, __uint_as_float(seen), bl));
@@ -1165,8 +1181,10 @@ __device__ __forceinline__ uint32_t apply_entries(const Dev &D, const Iter &A, u
     return r;
   }
   const float xf = tau_load(pf), xr = tau_load(pr);
-  __hip_atomic_store(pf, fmaf(al, xf, bl), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-  __hip_atomic_store(pr, fmaf(al, xr, bl), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  if (!map_fixed(xf, al, bl))
+    __hip_atomic_store(pf, fmaf(al, xf, bl), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  if (!map_fixed(xr, al, bl))
+    __hip_atomic_store(pr, fmaf(al, xr, bl), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
   return 0;
 }
 
@@ -1575,7 +1593,7 @@ __device__ __forceinline__ void ants_async_dense(const Dev &D, const Iter &A, in
       const uint32_t b = grp_bits<L>(__ballot(gl < cl && rec.x == (uint32_t)prev), base);
       const int kr = b ? __builtin_ctz(b) : -1;
       const float rval = kr >= 0 ? __uint_as_float(grp_read(rec.w, base, kr)) : fval;
-      if (gl < 2) {
+      if (gl < 2 && !map_fixed(gl == 0 ? fval : rval, al, bl)) {
         float *h = gl == 0 ? fwd : home(D, cur, prev, kr);
         const float seen = gl == 0 ? fval : rval;
         if (ATOMIC) {
