@@ -1290,6 +1290,7 @@ __device__ __forceinline__ void ant_queued(const Dev &D, const Iter &A, int ant,
   const int n = D.n, cl = D.cl;
   const int W = (n + 31) >> 5;
   const uint64_t clmask = cl >= 64 ? ~0ull : (1ull << cl) - 1;
+  const int dumw = lane % W;  // this lane's word for the visited-bit store
   const int koff = (lane < cl ? lane : cl - 1) * 16;
   const int rowb = cl * 16;  // bytes per record row
   const __amdgpu_buffer_rsrc_t crs =
@@ -1373,7 +1374,11 @@ __device__ __forceinline__ void ant_queued(const Dev &D, const Iter &A, int ant,
           d = rdlane(rec.y, k);
           tv = rdlane(rec.w, k);
         }
-        if (lane == 0) mark(vis, next);
+        // every lane ORs, lane 0 the visited bit and the others zero into a
+        // word of their own, so the store needs no branch around it
+        __hip_atomic_fetch_or(vis + (lane == 0 ? (next >> 5) : dumw),
+                              lane == 0 ? 1u << (next & 31) : 0u, __ATOMIC_RELAXED,
+                              __HIP_MEMORY_SCOPE_WORKGROUP);
         rec = load_rec(next);
         tb = lt == t ? next : tb;
         if (lu == t)
