@@ -46,11 +46,15 @@ size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
 
 // Device buffers of one handle, as offsets into one allocation.
 struct Layout {
-  size_t xy, dist, crec, cand, eta, tau, tau2, etad, rpos, ctau, gvis, bflags, spm, spm_tail, xnn, upd_rec, upd_nb, upd_next, upd_head, tours, lens,
+  size_t xy, dist, crec, cand, eta, tau, tau2, etad, rpos, ctau, gvis, fpre, flim, femax, fbound, bflags, spm, spm_tail, xnn, upd_rec, upd_nb, upd_next, upd_head, tours, lens,
       best, gstate, counters, sync, dmax, lnn, total;
 };
 
 constexpr int kEtaEntries = 65536;  // eta^beta for every 16-bit distance
+
+// The dense fallback first scans the kFpre cities after the candidates; it
+// needs the city after them too.
+bool fallback_prefix(int n, int cl) { return n - 1 > cl + acs::kFpre; }
 
 Layout make_layout(int n, int m, int cl, int ldn, int memory, int s, int mode) {
   Layout L{};
@@ -72,6 +76,12 @@ Layout make_layout(int n, int m, int cl, int ldn, int memory, int s, int mode) {
     L.ctau = take(sizeof(float) * (size_t)n * cl);
     if (mode == ACS_SEQUENTIAL) L.gvis = take(sizeof(uint32_t) * (size_t)m * ((n + 31) / 32));
     if (mode == ACS_SYNC) L.tau2 = take(sizeof(float) * (size_t)n * ldn);
+    if (fallback_prefix(n, cl)) {
+      L.fpre = take(sizeof(uint32_t) * 2 * (size_t)n * acs::kFpre);
+      L.flim = take(sizeof(uint32_t) * (size_t)n);
+      L.femax = take(sizeof(float) * (size_t)n);
+      L.fbound = take(sizeof(float) * (size_t)n);
+    }
   } else {
     L.spm = take(sizeof(uint32_t) * 2 * (size_t)n * s);
     L.spm_tail = take(sizeof(uint32_t) * (size_t)n);
@@ -346,6 +356,12 @@ int acs_create(const double *coords_xy, int32_t n, const acs_params *p, acs_t **
     d.ctau = reinterpret_cast<float *>(w + h->L.ctau);
     if (p->mode == ACS_SEQUENTIAL) d.gvis = reinterpret_cast<uint32_t *>(w + h->L.gvis);
     if (p->mode == ACS_SYNC) d.tau2 = reinterpret_cast<float *>(w + h->L.tau2);
+    if (fallback_prefix(n, h->cl)) {
+      d.fpre = reinterpret_cast<const uint4 *>(w + h->L.fpre);
+      d.flim = reinterpret_cast<const uint32_t *>(w + h->L.flim);
+      d.femax = reinterpret_cast<const float *>(w + h->L.femax);
+      d.fbound = reinterpret_cast<float *>(w + h->L.fbound);
+    }
   } else {
     d.spm = reinterpret_cast<uint2 *>(w + h->L.spm);
     d.spm_tail = reinterpret_cast<uint32_t *>(w + h->L.spm_tail);
@@ -728,6 +744,7 @@ int acs_batch_create(const double *const *coords, const int32_t *n, int32_t coun
     if (rc) return bail(rc);
     b->inst.push_back(h);
     devs[(size_t)i] = h->dev;
+    devs[(size_t)i].fpre = nullptr;  // batch fallbacks scan the whole row
     iters[(size_t)i] = h->base;
     b->nmax = std::max(b->nmax, n[i]);
     b->steps_per_iteration += (int64_t)h->m * (h->n - 1);

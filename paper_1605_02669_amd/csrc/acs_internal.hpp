@@ -25,6 +25,16 @@ struct Dev {
   const int8_t *rpos;      // dense: n x cl, position of i in the candidate list
                            //   of its k-th candidate, -1 if i is not in it
   uint32_t *gvis;          // sequential mode: m x ceil(n / 32) visited bitmaps
+  // dense memory, one colony with n - 1 > cl + kFpre: the greedy fallback's
+  // prefix, the kFpre cities that follow the candidates in (d, j) order
+  const uint4 *fpre;       //   n x kFpre / 2: lane l of row i holds the prefix
+                           //   positions 2l and 2l + 1 as {j | d << 16, bits of
+                           //   eta^beta(d)} twice
+  const uint32_t *flim;    //   n: key d << 16 | j of the first city after them
+  const float *femax;      //   n: largest eta^beta of the cities from flim on
+  float *fbound;           //   n: per construction, fl(T * femax) with T above
+                           //   every pheromone value those cities' entries of
+                           //   row i hold during it
   float *ctau;             // dense: n x cl, the candidate entries' pheromone
                            //   while a construction with an updater wave runs
                            //   (their records then hold the values of the
@@ -109,5 +119,6 @@ hipError_t launch_prior_apply(const Dev &d, const float *P, hipStream_t s);
 // Largest spm_s the GPU kernels support.
 constexpr int kMaxSpmS = 16;
 constexpr int kXnn = 128;  // extended neighbour list of the selective memory's fallback
+constexpr int kFpre = 128;  // dense fallback prefix (two cities per lane)
 
 }  // namespace acs

@@ -354,6 +354,44 @@ __global__ __launch_bounds__(256) void k_xnn(Dev D) {
   }
 }
 
+// The dense fallback's prefix of city i: positions cl .. cl + kFpre - 1 of
+// its neighbours in (d, j) order (the candidates are positions 0 .. cl - 1),
+// the key of position cl + kFpre, and the largest eta^beta of the cities
+// from that position on (eta^beta need not be monotone in fp32).
+__global__ __launch_bounds__(256) void k_fpre(Dev D) {
+  const int lane = threadIdx.x & 63;
+  const int i = blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (i >= D.n) return;
+  const uint16_t *row = D.dist + (size_t)i * D.ldn;
+  uint32_t *out = reinterpret_cast<uint32_t *>(const_cast<uint4 *>(D.fpre)) +
+                  (size_t)i * 2 * kFpre;
+  const int P = D.cl + kFpre;
+  int64_t last = -1;
+  for (int k = 0; k <= P; ++k) {
+    int64_t best = INT64_MAX;
+    for (int j = lane; j < D.n; j += 64) {
+      if (j == i) continue;
+      const int64_t key = ((int64_t)row[j] << 16) | j;
+      if (key > last && key < best) best = key;
+    }
+    best = wave_min(best);
+    if (lane == 0 && k >= D.cl && k < P) {
+      const uint32_t d = (uint32_t)(best >> 16), j = (uint32_t)(best & 0xffff);
+      out[2 * (k - D.cl)] = j | d << 16;
+      out[2 * (k - D.cl) + 1] = __float_as_uint(D.eta_tab[d]);
+    }
+    if (lane == 0 && k == P) const_cast<uint32_t *>(D.flim)[i] = (uint32_t)best;
+    last = best;
+  }
+  uint32_t emax = 0;
+  for (int j = lane; j < D.n; j += 64) {
+    const uint32_t key = (uint32_t)row[j] << 16 | (uint32_t)j;
+    if (j != i && (int64_t)key >= last) emax = max(emax, __float_as_uint(D.eta_tab[row[j]]));
+  }
+  emax = wave_umax_u(emax);
+  if (lane == 0) const_cast<float *>(D.femax)[i] = __uint_as_float(emax);
+}
+
 // Nearest-neighbour tour from city 0 (ties: lowest index), one block; its
 // length L_nn defines tau0 = 1 / (n * L_nn).
 __global__ __launch_bounds__(1024) void k_nn_tour(Dev D, int64_t *lnn) {
@@ -445,6 +483,44 @@ __global__ __launch_bounds__(256) void k_ctau_in(Dev D) {
 __global__ __launch_bounds__(256) void k_ctau_out(Dev D, int canonical) {
   const size_t e = (size_t)blockIdx.x * 256 + threadIdx.x;
   if (e < (size_t)D.n * D.cl) ctau_out_slot(D, e, canonical != 0);
+}
+
+// Before a construction, the bound that lets the dense fallback stop at its
+// prefix.  During a construction an entry only ever receives the local map
+// f(x) = fmaf(a, x, b) of a value one of the edge's entries held (the two
+// entries of an edge start equal in every mode whose updates copy between
+// them), and f(x) <= x above the map's real fixed point b / (1 - a), f(x) <=
+// that point rounded up below it.  So T = max(start values, the point with a
+// margin) bounds every value an entry of row i beyond the prefix holds, and
+// by monotone rounding fl(T * femax) bounds their weights tau * eta^beta.
+__global__ __launch_bounds__(256) void k_far_bound(Dev D, Iter A) {
+  const int lane = threadIdx.x & 63;
+  const int i = blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (i >= D.n) return;
+  const int n = D.n;
+  const uint32_t lim = D.flim[i];
+  const float *trow = D.tau + (size_t)i * D.ldn;
+  const uint16_t *drow = D.dist + (size_t)i * D.ldn;
+  uint32_t mx = 0;
+  for (int j0 = 8 * lane; j0 < n; j0 += 512) {
+    const float4 a = *reinterpret_cast<const float4 *>(trow + j0);
+    const float4 b = *reinterpret_cast<const float4 *>(trow + j0 + 4);
+    const uint4 dd = *reinterpret_cast<const uint4 *>(drow + j0);
+    const float t[8] = {a.x, a.y, a.z, a.w, b.x, b.y, b.z, b.w};
+    const uint32_t dw[4] = {dd.x, dd.y, dd.z, dd.w};
+#pragma unroll
+    for (int q = 0; q < 8; ++q) {
+      const int j = j0 + q;
+      const uint32_t key = ((dw[q >> 1] >> (16 * (q & 1))) & 0xffffu) << 16 | (uint32_t)j;
+      if (j < n && j != i && key >= lim) mx = max(mx, __float_as_uint(t[q]));
+    }
+  }
+  mx = wave_umax_u(mx);
+  if (lane == 0) {
+    const double fix = (double)A.b_loc / (1.0 - (double)A.a_loc);
+    const float hi = (float)(fix * (1.0 + 0x1p-20));
+    D.fbound[i] = fmaxf(__uint_as_float(mx), hi) * D.femax[i];
+  }
 }
 
 // The same for every instance of a batch (blockIdx.y = instance).
@@ -556,16 +632,48 @@ __device__ __forceinline__ int pick_candidate(const Iter &A, int lane, int cl, C
 }
 
 // Alg. 2, empty candidate set: greedy over every unvisited city, ties ->
-// lowest index.  Each lane scans eight consecutive cities per round.  The
-// loads of round r + 1 are issued before round r is examined (every round
-// loads, at an address clamped into the padded row, so the number of loads
-// in flight is fixed and the wait covers round r only).
+// lowest index.  With a prefix (D.fpre), the kFpre cities after the
+// candidates come first, two per lane; when the best unvisited one beats
+// D.fbound[cur] strictly, no city beyond the prefix can reach or tie it (the
+// candidates are all visited), so it is the answer of the whole scan.
+// Otherwise each lane scans eight consecutive cities per round.  The loads
+// of round r + 1 are issued before round r is examined (every round loads,
+// at an address clamped into the padded row, so the number of loads in
+// flight is fixed and the wait covers round r only).
 template <bool COHERENT>
 __device__ __forceinline__ Pick fallback_dense(const Dev &D, const uint32_t *vis, int cur,
                                                int lane, const float *tsrc = nullptr) {
   const int n = D.n;
   Pick p;
   const float *trow = (tsrc ? tsrc : D.tau) + (size_t)cur * D.ldn;
+  if (D.fpre) {
+    const uint4 pe = D.fpre[(size_t)cur * (kFpre / 2) + lane];
+    const float fb = D.fbound[cur];
+    const uint32_t j0 = pe.x & 0xffffu, j1 = pe.z & 0xffffu;
+    const float t0 = COHERENT ? tau_load(trow + j0) : trow[j0];
+    const float t1 = COHERENT ? tau_load(trow + j1) : trow[j1];
+    const bool u0 = !((vis[j0 >> 5] >> (j0 & 31)) & 1u);
+    const bool u1 = !((vis[j1 >> 5] >> (j1 & 31)) & 1u);
+    const float v0 = t0 * __uint_as_float(pe.y), v1 = t1 * __uint_as_float(pe.w);
+    // this lane's best (largest weight, then lowest index)
+    const bool second = u1 && (!u0 || v1 > v0 || (v1 == v0 && j1 < j0));
+    const bool any = u0 || u1;
+    const float bv = second ? v1 : v0;
+    const uint32_t bj = second ? j1 : j0;
+    // weights are >= 0, so their bit patterns order like the values
+    const uint32_t mx = wave_umax_u(any ? __float_as_uint(bv) : 0u);
+    if (mx > __float_as_uint(fb)) {
+      const uint32_t jn = wave_umin_u(any && __float_as_uint(bv) == mx ? bj : kNone);
+      const uint64_t own = __ballot(any && bj == jn);
+      const int owner = uni((int)__ffsll((unsigned long long)own) - 1);
+      p.k = -1;
+      p.next = (int)jn;
+      p.d = rdlane(second ? pe.z >> 16 : pe.x >> 16, owner);
+      p.tval = __uint_as_float(rdlane(__float_as_uint(second ? t1 : t0), owner));
+      p.kind = 2;
+      return p;
+    }
+  }
   const float *erow = D.etad + (size_t)cur * D.ldn;
   const uint16_t *drow = D.dist + (size_t)cur * D.ldn;
   const int rounds = (n + 511) >> 9;
@@ -2459,6 +2567,11 @@ hipError_t launch_crec(const Dev &d, const int32_t *cand_tmp, float tau0, hipStr
 }
 
 hipError_t launch_init_pheromone(const Dev &d, float tau0, hipStream_t s) {
+  if (d.fpre) {
+    hipLaunchKernelGGL(k_fpre, dim3((d.n + 3) / 4), dim3(256), 0, s, d);
+    const hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+  }
   if (d.xnn) {
     hipLaunchKernelGGL(k_xnn, dim3((d.n + 3) / 4), dim3(256), 0, s, d);
     const hipError_t e = hipGetLastError();
@@ -2485,6 +2598,15 @@ hipError_t launch_init_pheromone(const Dev &d, float tau0, hipStream_t s) {
 
 hipError_t launch_construct(const Dev &d, const Iter &it, int mode, int memory, int lanes,
                             int queued, hipStream_t s) {
+  // the fallback prefix's bound holds where every update maps an entry's own
+  // value or a value its edge's other entry held from an equal start; the
+  // unsynchronised in-wave ant writes f(forward value) into a reverse entry
+  // that may differ from it, and the narrow ants have their own fallback
+  if (memory == 0 && d.fpre && (mode == 0 || mode == 3 || (lanes == 64 && (mode == 1 || queued)))) {
+    hipLaunchKernelGGL(k_far_bound, dim3((d.n + 3) / 4), dim3(256), 0, s, d, it);
+    const hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+  }
   if (mode == 3) {
     const size_t words = (size_t)d.m * ((d.n + 31) / 32);
     if (words <= (size_t)kSeqLdsWords)
@@ -2560,12 +2682,15 @@ hipError_t launch_construct(const Dev &d, const Iter &it, int mode, int memory, 
     else
       hipLaunchKernelGGL((k_construct_async_dense_g<16, false>), gg, dim3(kAsyncBlock), lg, s, d, it);
   } else if (memory == 0) {
-    if (atomic)
+    if (atomic) {
       hipLaunchKernelGGL(k_construct_async_dense<true>, dim3(grid), dim3(kAsyncBlock), lds, s, d,
                          it);
-    else
+    } else {
+      Dev dd = d;
+      dd.fpre = nullptr;
       hipLaunchKernelGGL(k_construct_async_dense<false>, dim3(grid), dim3(kAsyncBlock), lds, s,
-                         d, it);
+                         dd, it);
+    }
   } else {
     if (atomic)
       hipLaunchKernelGGL(k_construct_async_spm<true>, dim3(grid), dim3(kAsyncBlock), lds, s, d,

@@ -15,6 +15,8 @@ are generated instead:
   falls outside the square is drawn again.
 * ``batch(count, seed)``: ``count`` instances with n log-uniform in
   [100, 2000], alternating uniform / clustered.
+* ``lattice(side, seed)``: the side x side integer grid with spacing 7, its
+  points in a seeded random order (many equal distances, so ties everywhere).
 
 All generators use numpy's Philox bit generator keyed by the seed, so an
 instance is fully determined by (kind, n, seed).
@@ -78,3 +80,11 @@ def coincident(n: int, seed: int, dup: int = 4) -> np.ndarray:
     if n > dup + 1:
         xy[dup + 1] = xy[dup] + np.array([0.2, -0.1])
     return xy
+
+
+def lattice(side: int, seed: int = 0, spacing: float = 7.0) -> np.ndarray:
+    """side * side grid points, shuffled by the seed, float64 array (side^2, 2)."""
+    g = _rng(seed, 0x6A1D)
+    ix, iy = np.meshgrid(np.arange(side), np.arange(side), indexing="ij")
+    pts = np.stack([ix.ravel(), iy.ravel()], axis=1).astype(np.float64) * spacing
+    return np.ascontiguousarray(pts[g.permutation(side * side)])

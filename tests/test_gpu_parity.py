@@ -114,13 +114,25 @@ EDGE_CASES = [
     ("n257_m600", 257, {"m": 600, "cl": 20}),
     ("n50_beta3", 50, {"beta": 3.0, "phi": 0.01, "rho": 0.2}),
     ("coincident", 60, {}),
+    # the dense fallback's prefix (the 128 cities after the candidates) is
+    # used from n - 1 > cl + 128 on
+    ("n162_cl32_prefix", 162, {}),
+    ("n161_cl32_no_prefix", 161, {}),
+    ("n400_cl2_fallbacks", 400, {"cl": 2}),
+    ("lattice_n400_cl4", 400, {"cl": 4}),
+    ("lattice_n324_cl8_beta0", 324, {"cl": 8, "beta": 0.0}),
 ]
 
 
 @pytest.mark.parametrize("name,n,kw", EDGE_CASES, ids=[c[0] for c in EDGE_CASES])
 def test_edge_cases_sync(acs, name, n, kw):
     _say(f"edge case {name}")
-    xy = inputs.coincident(n, 5) if name == "coincident" else inputs.uniform(n, 100 + n)
+    if name == "coincident":
+        xy = inputs.coincident(n, 5)
+    elif name.startswith("lattice"):
+        xy = inputs.lattice(int(round(n ** 0.5)), n)
+    else:
+        xy = inputs.uniform(n, 100 + n)
     col, orc = _pair(acs, xy, seed=3, **kw)
     for it in range(5):
         col.iterate(1)
@@ -165,6 +177,22 @@ def test_async_single_ant_equals_oracle(acs):
         col.iterate(1)
         orc.iterate(1)
         _compare(col, orc, it)
+    col.close()
+
+
+@pytest.mark.parametrize("path", [2, 1], ids=["queued", "inwave"])
+def test_async_single_ant_fallback_heavy_equals_oracle(acs, path):
+    """One ant on a 20 x 20 grid with cl = 4: the fallback decides many steps
+    (through its prefix or the whole row) once the global updates have made
+    the trails unequal, and one ant must follow the synchronous schedule."""
+    xy = inputs.lattice(20, 5)
+    col = acs.Colony(xy, m=1, cl=4, mode=acs.ACS_ASYNC_ATOMIC, seed=4, update_path=path)
+    orc = oracle.Oracle(xy, m=1, cl=4, seed=4)
+    for it in range(12):
+        col.iterate(1)
+        orc.iterate(1)
+        _compare(col, orc, it)
+    assert col.stats()["fallback"] == orc.counts()["fallback"] > 0
     col.close()
 
 
@@ -493,13 +521,20 @@ ASYNC_FIRST = [
     ("spm_racy", dict(cl=16, memory=1, spm_s=4, m=250), 0, "ASYNC_RACY"),
     ("queued_atomic", dict(), -2, "ASYNC_ATOMIC"),
     ("queued_racy_ragged", dict(m=333), -2, "ASYNC_RACY"),
+    # a grid with cl = 4: fallbacks at many steps, ties in every weight
+    ("queued_atomic_lattice_cl4", dict(cl=4), -2, "ASYNC_ATOMIC"),
+    ("inwave_atomic_lattice_cl4", dict(cl=4), -1, "ASYNC_ATOMIC"),
+    ("inwave_racy_lattice_cl4", dict(cl=4), -1, "ASYNC_RACY"),
 ]
 
 
 @pytest.mark.parametrize("name,kw,lanes,mode", ASYNC_FIRST, ids=[c[0] for c in ASYNC_FIRST])
 def test_async_first_iteration_equals_oracle(acs, name, kw, lanes, mode):
     n = 733
-    xy = inputs.clustered(n, 77) if "ragged" in name else inputs.uniform(n, 77)
+    if "lattice" in name:
+        xy = inputs.lattice(27, 77)
+    else:
+        xy = inputs.clustered(n, 77) if "ragged" in name else inputs.uniform(n, 77)
     orc = oracle.Oracle(xy, seed=12, **kw)
     c = orc.constants()
     assert orc.local_map_k(c["tau0"], 1) == c["tau0"]
@@ -757,13 +792,19 @@ SEQ_CASES = [
     ("n3_m1", 3, dict(m=1), 3),
     ("n5_q0_zero_m9", 5, dict(m=9, q0=0.0), 3),
     ("n40_q0_one_m40", 40, dict(q0=1.0), 3),
+    ("lattice_n400_cl4", 400, dict(cl=4), 3),
 ]
 
 
 @pytest.mark.parametrize("name,n,kw,iters", SEQ_CASES, ids=[c[0] for c in SEQ_CASES])
 def test_sequential_equals_oracle(acs, name, n, kw, iters):
     _say(f"sequential {name}")
-    xy = inputs.clustered(n, n + 9) if "clustered" in name else inputs.uniform(n, n + 9)
+    if "clustered" in name:
+        xy = inputs.clustered(n, n + 9)
+    elif name.startswith("lattice"):
+        xy = inputs.lattice(int(round(n ** 0.5)), n)
+    else:
+        xy = inputs.uniform(n, n + 9)
     col = acs.Colony(xy, mode=acs.ACS_SEQUENTIAL, seed=6, **kw)
     orc = oracle.Oracle(xy, mode=oracle.SEQUENTIAL, seed=6, **kw)
     for it in range(iters):
