@@ -744,7 +744,8 @@ int acs_batch_create(const double *const *coords, const int32_t *n, int32_t coun
     if (rc) return bail(rc);
     b->inst.push_back(h);
     devs[(size_t)i] = h->dev;
-    devs[(size_t)i].fpre = nullptr;  // batch fallbacks scan the whole row
+    // the unsynchronised mode's fallbacks scan whole rows (see launch_construct)
+    if (p->mode != ACS_ASYNC_ATOMIC) devs[(size_t)i].fpre = nullptr;
     iters[(size_t)i] = h->base;
     b->nmax = std::max(b->nmax, n[i]);
     b->steps_per_iteration += (int64_t)h->m * (h->n - 1);

@@ -493,10 +493,7 @@ __global__ __launch_bounds__(256) void k_ctau_out(Dev D, int canonical) {
 // that point rounded up below it.  So T = max(start values, the point with a
 // margin) bounds every value an entry of row i beyond the prefix holds, and
 // by monotone rounding fl(T * femax) bounds their weights tau * eta^beta.
-__global__ __launch_bounds__(256) void k_far_bound(Dev D, Iter A) {
-  const int lane = threadIdx.x & 63;
-  const int i = blockIdx.x * 4 + (threadIdx.x >> 6);
-  if (i >= D.n) return;
+__device__ __forceinline__ void far_bound_row(const Dev &D, const Iter &A, int i, int lane) {
   const int n = D.n;
   const uint32_t lim = D.flim[i];
   const float *trow = D.tau + (size_t)i * D.ldn;
@@ -521,6 +518,19 @@ __global__ __launch_bounds__(256) void k_far_bound(Dev D, Iter A) {
     const float hi = (float)(fix * (1.0 + 0x1p-20));
     D.fbound[i] = fmaxf(__uint_as_float(mx), hi) * D.femax[i];
   }
+}
+
+__global__ __launch_bounds__(256) void k_far_bound(Dev D, Iter A) {
+  const int i = blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (i < D.n) far_bound_row(D, A, i, threadIdx.x & 63);
+}
+
+// The same for every instance of a batch that has a prefix (blockIdx.y =
+// instance).
+__global__ __launch_bounds__(256) void k_far_bound_batch(const Dev *devs, const Iter *iters) {
+  const Dev &D = devs[blockIdx.y];
+  const int i = blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (D.fpre && i < D.n) far_bound_row(D, iters[blockIdx.y], i, threadIdx.x & 63);
 }
 
 // The same for every instance of a batch (blockIdx.y = instance).
@@ -1748,14 +1758,39 @@ __device__ __forceinline__ void ants_async_dense(const Dev &D, const Iter &A, in
       d = grp_read(rec.y, base, k);
       tval = __uint_as_float(grp_read(rec.w, base, k));
     } else {
-      // Alg. 2's fallback over every unvisited city, ties -> lowest index
+      // Alg. 2's fallback over every unvisited city, ties -> lowest index;
+      // first over the prefix (as in fallback_dense, 128 / L cities per lane)
       const float *trow = D.tau + (size_t)cur * ldn;
       const float *erow = D.etad + (size_t)cur * ldn;
       const uint16_t *drow = D.dist + (size_t)cur * ldn;
       float bv = 0.f, bt = 0.f;
       uint32_t bj = kNone, bd = 0;
+      bool found = false;
+      if (D.fpre) {
+        const uint4 *fr = D.fpre + (size_t)cur * (kFpre / 2);
+        const float fb = D.fbound[cur];
+        uint4 pe[64 / L];
+#pragma unroll
+        for (int r = 0; r < 64 / L; ++r) pe[r] = fr[gl + L * r];
+#pragma unroll
+        for (int r = 0; r < 64 / L; ++r) {
+#pragma unroll
+          for (int q = 0; q < 2; ++q) {
+            const uint32_t x = q ? pe[r].z : pe[r].x;
+            const uint32_t j = x & 0xffffu;
+            const float tq = trow[j];
+            const float v = tq * __uint_as_float(q ? pe[r].w : pe[r].y);
+            if (!((vis[j >> 5] >> (j & 31)) & 1u) &&
+                (bj == kNone || v > bv || (v == bv && j < bj))) {
+              bv = v; bj = j; bt = tq; bd = x >> 16;
+            }
+          }
+        }
+        found = grp_umax<L>(bj == kNone ? 0u : __float_as_uint(bv)) > __float_as_uint(fb);
+        if (!found) { bv = 0.f; bj = kNone; }
+      }
 #pragma unroll 2
-      for (int j0 = 4 * gl; j0 < n; j0 += 4 * L) {
+      for (int j0 = 4 * gl; !found && j0 < n; j0 += 4 * L) {
         const float4 tv = *reinterpret_cast<const float4 *>(trow + j0);
         const float4 ev = *reinterpret_cast<const float4 *>(erow + j0);
         const ushort4 dv = *reinterpret_cast<const ushort4 *>(drow + j0);
@@ -2600,9 +2635,9 @@ hipError_t launch_construct(const Dev &d, const Iter &it, int mode, int memory, 
                             int queued, hipStream_t s) {
   // the fallback prefix's bound holds where every update maps an entry's own
   // value or a value its edge's other entry held from an equal start; the
-  // unsynchronised in-wave ant writes f(forward value) into a reverse entry
-  // that may differ from it, and the narrow ants have their own fallback
-  if (memory == 0 && d.fpre && (mode == 0 || mode == 3 || (lanes == 64 && (mode == 1 || queued)))) {
+  // unsynchronised ants that issue their own updates write f(forward value)
+  // into a reverse entry that may differ from it, so they scan whole rows
+  if (memory == 0 && d.fpre && (mode != 2 || (lanes == 64 && queued))) {
     hipLaunchKernelGGL(k_far_bound, dim3((d.n + 3) / 4), dim3(256), 0, s, d, it);
     const hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
@@ -2673,14 +2708,16 @@ hipError_t launch_construct(const Dev &d, const Iter &it, int mode, int memory, 
     const int g = 64 / lanes;
     const dim3 gg((d.m + apb * g - 1) / (apb * g));
     const size_t lg = lds * g;
+    Dev dr = d;
+    dr.fpre = nullptr;
     if (lanes == 32 && atomic)
       hipLaunchKernelGGL((k_construct_async_dense_g<32, true>), gg, dim3(kAsyncBlock), lg, s, d, it);
     else if (lanes == 32)
-      hipLaunchKernelGGL((k_construct_async_dense_g<32, false>), gg, dim3(kAsyncBlock), lg, s, d, it);
+      hipLaunchKernelGGL((k_construct_async_dense_g<32, false>), gg, dim3(kAsyncBlock), lg, s, dr, it);
     else if (atomic)
       hipLaunchKernelGGL((k_construct_async_dense_g<16, true>), gg, dim3(kAsyncBlock), lg, s, d, it);
     else
-      hipLaunchKernelGGL((k_construct_async_dense_g<16, false>), gg, dim3(kAsyncBlock), lg, s, d, it);
+      hipLaunchKernelGGL((k_construct_async_dense_g<16, false>), gg, dim3(kAsyncBlock), lg, s, dr, it);
   } else if (memory == 0) {
     if (atomic) {
       hipLaunchKernelGGL(k_construct_async_dense<true>, dim3(grid), dim3(kAsyncBlock), lds, s, d,
@@ -2732,6 +2769,14 @@ hipError_t launch_batch_iteration(const Dev *devs, Iter *iters, const int2 *item
                                   hipStream_t s) {
   const int apb = kAsyncBlock / 64;
   const int wmax = (nmax + 31) / 32;
+  if (mode == 1) {
+    // instances without a prefix (and the unsynchronised mode, see
+    // launch_construct) have fpre null and scan whole rows
+    hipLaunchKernelGGL(k_far_bound_batch, dim3((nmax + 3) / 4, count), dim3(256), 0, s, devs,
+                       iters);
+    const hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+  }
   if (lanes == 64 && queued) {
     const size_t lq = (size_t)kBatchQAnts * kQRing * sizeof(uint4) +
                       (size_t)kBatchQAnts * wmax * sizeof(uint32_t);

@@ -180,13 +180,15 @@ def test_async_single_ant_equals_oracle(acs):
     col.close()
 
 
-@pytest.mark.parametrize("path", [2, 1], ids=["queued", "inwave"])
-def test_async_single_ant_fallback_heavy_equals_oracle(acs, path):
+@pytest.mark.parametrize("gpu", [dict(update_path=2), dict(update_path=1),
+                                 dict(lanes_per_ant=32), dict(lanes_per_ant=16)],
+                         ids=["queued", "inwave", "lanes32", "lanes16"])
+def test_async_single_ant_fallback_heavy_equals_oracle(acs, gpu):
     """One ant on a 20 x 20 grid with cl = 4: the fallback decides many steps
     (through its prefix or the whole row) once the global updates have made
     the trails unequal, and one ant must follow the synchronous schedule."""
     xy = inputs.lattice(20, 5)
-    col = acs.Colony(xy, m=1, cl=4, mode=acs.ACS_ASYNC_ATOMIC, seed=4, update_path=path)
+    col = acs.Colony(xy, m=1, cl=4, mode=acs.ACS_ASYNC_ATOMIC, seed=4, **gpu)
     orc = oracle.Oracle(xy, m=1, cl=4, seed=4)
     for it in range(12):
         col.iterate(1)
@@ -362,6 +364,23 @@ def test_batch_single_ant_equals_oracle(acs):
     b.close()
 
 
+def test_batch_single_ant_fallback_heavy_equals_oracle(acs):
+    """Grids with cl = 4 in a batch (fallbacks at many steps, every weight
+    tied), one ant each, over the iterations in which the batch tries every
+    launch shape: each instance matches the oracle bit for bit."""
+    insts = [inputs.lattice(14, 1), inputs.lattice(20, 2), inputs.uniform(300, 3),
+             inputs.lattice(11, 4)]
+    b = acs.Batch(insts, m=1, cl=4, seed=8)
+    orcs = [oracle.Oracle(x, m=1, cl=4, seed=8, instance=i) for i, x in enumerate(insts)]
+    for it in range(6):
+        b.iterate(1)
+        for i, o in enumerate(orcs):
+            o.iterate(1)
+            assert np.array_equal(b.tours(i), o.tours()), (i, it)
+            assert np.array_equal(b.tau(i), o.tau()), (i, it)
+    b.close()
+
+
 def test_batch_tours_valid(acs):
     insts = inputs.batch(24, seed=7, nmin=60, nmax=400)
     b = acs.Batch(insts, seed=2)
@@ -525,6 +544,9 @@ ASYNC_FIRST = [
     ("queued_atomic_lattice_cl4", dict(cl=4), -2, "ASYNC_ATOMIC"),
     ("inwave_atomic_lattice_cl4", dict(cl=4), -1, "ASYNC_ATOMIC"),
     ("inwave_racy_lattice_cl4", dict(cl=4), -1, "ASYNC_RACY"),
+    ("atomic_l32_lattice_cl4", dict(cl=4), 32, "ASYNC_ATOMIC"),
+    ("atomic_l16_lattice_cl4", dict(cl=4), 16, "ASYNC_ATOMIC"),
+    ("racy_l32_lattice_cl4", dict(cl=4), 32, "ASYNC_RACY"),
 ]
 
 
