@@ -57,9 +57,9 @@ struct Dev {
   unsigned long long *counters;  // greedy, roulette, fallback, hits, misses,
                                  // unvisited cities at fallback steps,
                                  // compare-and-swap retries
-  uint32_t *sync;          // [0] grid barrier counter, [1] error flag
-  unsigned long long *bflags;  // synchronous mode: barrier release word, then one
-                               //   flag per block, 16 words (128 bytes) apart
+  uint32_t *sync;          // [0] unused, [1] error flag
+  unsigned long long *bflags;  // synchronous mode: grid barrier flags, one per
+                               //   block, 16 words (128 bytes) apart, from word 16
   int32_t nbflags;             //   words in bflags
 };
 

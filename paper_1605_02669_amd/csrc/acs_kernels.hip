@@ -201,94 +201,55 @@ __device__ __forceinline__ int cand_pos(const Dev &D, int u, int v, int lane) {
   return b ? (int)__ffsll((unsigned long long)b) - 1 : -1;
 }
 
-// Grid-wide barrier for a cooperative launch.  Every wave waits for its own
-// memory operations first (the local updates are compare-and-swaps whose
-// results have been consumed, so they are performed at the device's
-// coherence point); one thread per block then arrives on a monotonically
-// growing counter and waits for all blocks.  Readers after the barrier use
-// agent-coherent loads for everything the updates touch, so no cache
-// write-back or invalidation is needed.  The wait is bounded: on exhaustion
-// an error flag is raised, later barriers no longer wait, and the kernel
-// runs to its end.
-__device__ __forceinline__ void grid_barrier(uint32_t *sync, uint32_t target) {
-  __builtin_amdgcn_s_waitcnt(0);
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    __hip_atomic_fetch_add(sync, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    uint32_t spins = 0;
-    while (__hip_atomic_load(sync, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < target) {
-      // once any block has given up, no later barrier waits either (looked
-      // at every 64th poll, so a poll is one load)
-      if ((spins & 63) == 63 &&
-          __hip_atomic_load(sync + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT))
-        break;
-      __builtin_amdgcn_s_sleep(1);
-      if (++spins > (1u << 22)) {
-        __hip_atomic_store(sync + 1, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        break;
-      }
-    }
-  }
-  __syncthreads();
-  __atomic_signal_fence(__ATOMIC_SEQ_CST);
-}
-
-// Grid-wide barrier by flags (for grids of more than 32 blocks): each block
-// stores the barrier's epoch into a flag of its own (its own 128-byte line),
-// the first wave of block 0 waits until every flag holds the epoch and then
-// stores it into the release word, which every block waits for.  No two
-// blocks write the same line, so arrival costs one store instead of a
-// read-modify-write queued behind every other block's on one counter.  Epochs are (iteration << 32 | barrier
-// number), so flags left by an earlier construction never match.  Waits are
-// bounded like grid_barrier's and share its error flag.
+// Grid-wide barrier for a cooperative launch, by flags.  Every wave waits for
+// its own memory operations first (the local updates are compare-and-swaps
+// whose results have been consumed, so they are performed at the device's
+// coherence point).  One thread per block then stores the barrier's epoch
+// into the block's own flag (its own 128-byte line), and the first wave of
+// every block waits until every flag has reached the epoch.  No two blocks
+// write the same line, so arrival costs one store instead of a
+// read-modify-write queued behind every other block's on one counter, and
+// no block waits for a second hop through a release word.  Readers after
+// the barrier use agent-coherent loads for everything the updates touch, so
+// no cache write-back or invalidation is needed.
+//
+// Epochs are (iteration << 32 | barrier number) and grow monotonically.  A
+// block can run at most one barrier ahead of the slowest (it cannot pass the
+// next barrier before the slowest block arrives there), so a waiting block
+// sees every flag at its epoch or the next: it waits for "at least", and
+// flags left by an earlier construction are below every epoch of a later
+// one.  The wait is bounded: on exhaustion an error flag is raised, later
+// barriers no longer wait, and the kernel runs to its end.
 __device__ __forceinline__ uint64_t barrier_epoch(const Iter &A, uint32_t bar) {
   return ((uint64_t)A.it << 32) | bar;
 }
 
+// once any block has given up, no later barrier waits either (looked at every
+// 64th poll, so a poll costs the flag loads only)
 __device__ __forceinline__ bool barrier_gave_up(const Dev &D, uint32_t spins) {
   return (spins & 63) == 63 &&
          __hip_atomic_load(D.sync + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0;
 }
 
 __device__ __forceinline__ void grid_barrier_f(const Dev &D, uint64_t epoch) {
-  // few blocks: one counter is quicker (one hop instead of two)
-  if (gridDim.x <= 32) {
-    grid_barrier(D.sync, (uint32_t)epoch * gridDim.x);
-    return;
-  }
   __builtin_amdgcn_s_waitcnt(0);
   __syncthreads();
-  unsigned long long *rel = D.bflags;
   if (threadIdx.x == 0)
     __hip_atomic_store(D.bflags + 16 * ((size_t)blockIdx.x + 1), (unsigned long long)epoch,
                        __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-  if (blockIdx.x == 0 && threadIdx.x < 64) {
+  if (threadIdx.x < 64) {
     uint32_t spins = 0;
     while (true) {
       bool all = true;
       for (uint32_t b = threadIdx.x; b < gridDim.x; b += 64)
         all &= __hip_atomic_load(D.bflags + 16 * ((size_t)b + 1), __ATOMIC_RELAXED,
-                                 __HIP_MEMORY_SCOPE_AGENT) == epoch;
+                                 __HIP_MEMORY_SCOPE_AGENT) >= epoch;
       if (__ballot(!all) == 0) break;
       if (barrier_gave_up(D, spins)) break;
       __builtin_amdgcn_s_sleep(1);
       if (++spins > (1u << 22)) {
         if (threadIdx.x == 0)
           __hip_atomic_store(D.sync + 1, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        break;
-      }
-    }
-    if (threadIdx.x == 0)
-      __hip_atomic_store(rel, (unsigned long long)epoch, __ATOMIC_RELAXED,
-                         __HIP_MEMORY_SCOPE_AGENT);
-  }
-  if (threadIdx.x == 0) {
-    uint32_t spins = 0;
-    while (__hip_atomic_load(rel, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != epoch) {
-      if (barrier_gave_up(D, spins)) break;
-      __builtin_amdgcn_s_sleep(1);
-      if (++spins > (1u << 22)) {
-        __hip_atomic_store(D.sync + 1, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         break;
       }
     }
@@ -2468,7 +2429,6 @@ __global__ __launch_bounds__(1024) void k_best(Dev D) {
     D.gstate[0] = s_better ? bl : lgb;
     D.gstate[1] = bl;
     D.gstate[2] = ba;
-    D.sync[0] = 0;  // barrier counter for the next construction
   }
   __syncthreads();
   const int n = D.n;
