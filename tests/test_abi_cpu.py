@@ -144,10 +144,32 @@ def test_mode_specific_workspace():
     # sequential: m = n = 1000 visited bitmaps of ceil(1000 / 32) words
     assert seq - base == (1000 * 32 * 4 + 255) // 256 * 256
     # synchronous: the second buffer of the dense matrix (ldn = 1024) and the
-    # barrier flags (a release word and one per block of 16 ants, 128 bytes
-    # apart), each 256-byte aligned
+    # barrier flags (one 128-byte line per block of 16 ants after a first,
+    # unused one), each 256-byte aligned
     flags = 8 * 16 * ((1000 + 15) // 16 + 1)
     assert sync - base == 1000 * 1024 * 4 + (flags + 255) // 256 * 256
+
+
+def test_fallback_prefix_workspace():
+    """The dense fallback's prefix (128 cities after the cl candidates, 8 bytes
+    each, plus three per-city words) exists only where n - 1 > cl + 128: at
+    n = 190 for cl = 32 but not for cl = 64."""
+    def al(x):
+        return (x + 255) // 256 * 256
+
+    n = 190
+    p = acs.acs_default_params()
+    p.mode = acs.ACS_ASYNC_ATOMIC
+    sizes = {}
+    for cl in (32, 64):
+        p.cl = cl
+        sizes[cl] = acs.acs_workspace_bytes(n, p)
+    # per-candidate arrays: record (16 B), index (4 B), reverse position
+    # (1 B), live pheromone (4 B)
+    def per_cand(cl):
+        return al(16 * n * cl) + al(4 * n * cl) + al(n * cl) + al(4 * n * cl)
+    prefix = al(8 * n * 128) + 3 * al(4 * n)
+    assert sizes[64] - sizes[32] == per_cand(64) - per_cand(32) - prefix
 
 
 def test_without_gpu_create_reports_device_error():
