@@ -140,7 +140,9 @@ int acs_workspace_bytes(int32_t n, const acs_params *p, size_t *out);
  * d_ij of Sec. 3), the cl nearest neighbours of each city sorted by
  * (d, index) (the candidate set of Sec. 3), eta^beta, the nearest-neighbour
  * tour from city 0 and tau0, and the initial pheromone (dense: tau0
- * everywhere; SPM: empty records).
+ * everywhere; SPM: empty records).  Dense memory with n - 1 > cl + 128 also
+ * gets the 128 cities after each city's candidates, which let the greedy
+ * fallback of Alg. 2 stop early when that is exact.
  * coords_xy: n (x, y) pairs of finite doubles, copied.  n >= 3.
  * Errors: ACS_E_INVALID (bad n, coordinates or parameters), ACS_E_NOMEM,
  * ACS_E_DEVICE, ACS_E_UNSUPPORTED (cl > 64, n > 65535, distances > 65535,
