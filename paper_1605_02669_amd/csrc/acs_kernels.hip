@@ -1342,10 +1342,7 @@ __device__ __forceinline__ void ring_updater(const Dev &D, const Iter &A, const 
       continue;
     }
     if (done == (uint32_t)na) break;
-    // the longest sleep (127 x 64 cycles, about 3.4 us): entries arrive every
-    // few microseconds, and the fewer issue slots the updater takes, the
-    // faster the ant waves on its SIMD step (1.5% over 32 x 64 cycles)
-    __builtin_amdgcn_s_sleep(127);
+    __builtin_amdgcn_s_sleep(32);
     if (++idle > kQIdle) {
       if (lane == 0)
         __hip_atomic_store(D.sync + 1, 2u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
