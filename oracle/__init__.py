@@ -63,6 +63,16 @@ def load() -> C.CDLL:
     lib.orc_roulette_hist.argtypes = [P, P, i32, P]
     lib.orc_local_map_k.argtypes = [P, f32, i32]
     lib.orc_local_map_k.restype = f32
+    lib.orc_set_candidate_weights.argtypes = [P, P]
+    lib.orc_set_candidate_weights.restype = C.c_int
+    lib.orc_set_best.argtypes = [P, P, i64]
+    lib.orc_set_best.restype = C.c_int
+    lib.orc_exchange_best.argtypes = [P, i32, i32]
+    lib.orc_exchange_best.restype = C.c_int
+    lib.orc_set_tau.argtypes = [P, P]
+    lib.orc_set_tau.restype = C.c_int
+    lib.orc_spm_update.argtypes = [P, i32, i32, f32, f32]
+    lib.orc_spm_update.restype = C.c_int
     _lib = lib
     return lib
 
@@ -100,6 +110,14 @@ def roulette_hist(w, unvisited) -> np.ndarray:
 
 def set_threads(t: int) -> None:
     load().orc_set_threads(int(t))
+
+
+def exchange_best(colonies, topology: int = 0) -> None:
+    """Best-so-far exchange between oracle colonies of one instance
+    (topology 0: from the colony with the shortest; 1: ring from c - 1)."""
+    arr = (C.c_void_p * len(colonies))(*[c.h for c in colonies])
+    if load().orc_exchange_best(arr, len(colonies), int(topology)) != 0:
+        raise ValueError("oracle: invalid exchange")
 
 
 class Oracle:
@@ -214,6 +232,32 @@ class Oracle:
         self.lib.orc_get_counts(self.h, _ptr(out))
         keys = ("steps", "greedy", "roulette", "fallback", "spm_hits", "spm_misses")
         return {k: int(v) for k, v in zip(keys, out)}
+
+    def set_candidate_weights(self, w) -> None:
+        """Scores (n, cl) in place of eta^beta of the candidates; None restores."""
+        if w is None:
+            self.lib.orc_set_candidate_weights(self.h, None)
+            return
+        w = np.ascontiguousarray(w, dtype=np.float32).reshape(self.n, self.cl)
+        if self.lib.orc_set_candidate_weights(self.h, _ptr(w)) != 0:
+            raise ValueError("oracle: candidate weights must be positive and finite")
+
+    def set_best(self, tour, length: int) -> None:
+        t = np.ascontiguousarray(tour, dtype=np.int32)
+        if self.lib.orc_set_best(self.h, _ptr(t), int(length)) != 0:
+            raise ValueError("oracle: not a permutation")
+
+    def set_tau(self, tau) -> None:
+        """Dense pheromone matrix (n, n) to start from."""
+        t = np.ascontiguousarray(tau, dtype=np.float32).reshape(self.n, self.n)
+        if self.lib.orc_set_tau(self.h, _ptr(t)) != 0:
+            raise ValueError("oracle: set_tau needs a dense handle and positive values")
+
+    def spm_update(self, u: int, v: int, a: float, b: float) -> None:
+        """Alg. 3 on the record of u for neighbour v with x -> fmaf(a, x, b)."""
+        if self.lib.orc_spm_update(self.h, u, v, float(np.float32(a)),
+                                   float(np.float32(b))) != 0:
+            raise ValueError("oracle: spm_update on a dense handle or bad city")
 
     def local_map_k(self, x: float, k: int) -> np.float32:
         return np.float32(self.lib.orc_local_map_k(self.h, float(np.float32(x)), k))

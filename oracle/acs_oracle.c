@@ -39,6 +39,8 @@ struct orc {
   int32_t *dist;  /* n*n exact integer distances */
   int32_t *cand;  /* n*cl nearest neighbours sorted by (d, j) */
   float *eta;     /* eta^beta indexed by integer distance, 0..dmax */
+  float *cw;      /* NULL, or n*cl weights that replace eta^beta of the
+                     candidates in Eq. 1 and Eq. 2 (learned scores) */
   int32_t dmax;
   int64_t lnn;
   float tau0, a_loc, b_loc, a_glob;
@@ -316,7 +318,7 @@ orc *orc_create(const double *xy, int32_t n, int32_t m, int32_t cl,
 
 void orc_destroy(orc *o) {
   if (!o) return;
-  free(o->xy); free(o->dist); free(o->cand); free(o->eta); free(o->tau);
+  free(o->xy); free(o->dist); free(o->cand); free(o->eta); free(o->cw); free(o->tau);
   free(o->spm_node); free(o->spm_val); free(o->spm_tail); free(o->tour);
   free(o->len); free(o->vis); free(o->choice); free(o->kind); free(o->best);
   free(o);
@@ -358,6 +360,13 @@ void orc_roulette_hist(const float *w, const uint8_t *unvisited, int32_t cl,
   }
 }
 
+/* Heuristic factor of candidate k of city i in Eq. 1 and Eq. 2: eta^beta of
+ * the edge, or the weight set by orc_set_candidate_weights in its place. */
+static float cand_weight(const orc *o, int32_t i, int32_t k) {
+  if (o->cw) return o->cw[(size_t)i * o->cl + k];
+  return o->eta[D(o, i, o->cand[(size_t)i * o->cl + k])];
+}
+
 /* ------------------------------------------------------------------------ */
 /* Alg. 2: next node of ant a standing at cur after step t's draw.            */
 /* ------------------------------------------------------------------------ */
@@ -376,7 +385,7 @@ static int32_t select_next(const orc *o, int32_t a, int32_t t, int32_t cur,
   for (int32_t k = 0; k < cl; ++k) {
     int32_t j = cn[k];
     unv[k] = vis[j] ? 0 : 1;
-    w[k] = unv[k] ? tau_read(o, cur, j) * o->eta[D(o, cur, j)] : 0.0f;
+    w[k] = unv[k] ? tau_read(o, cur, j) * cand_weight(o, cur, k) : 0.0f;
     any |= unv[k];
   }
   if (any) {
@@ -393,7 +402,8 @@ static int32_t select_next(const orc *o, int32_t a, int32_t t, int32_t cur,
     *kind = 1;
     return cn[orc_roulette_pick(w, unv, cl, r4[1] >> 8)];
   }
-  /* empty candidate set: greedy over every unvisited node, ties -> lowest j */
+  /* empty candidate set: greedy over every unvisited node, ties -> lowest j;
+   * the heuristic factor here is always eta^beta of the edge */
   *kind = 2;
   int32_t bj = -1;
   float bv = 0.0f;
@@ -507,6 +517,101 @@ void orc_global_update(orc *o) {
 int orc_set_local_period(orc *o, int32_t k) {
   if (k < 1) return -1;
   o->lperiod = k;
+  return 0;
+}
+
+/* Learned candidate scores: w[i * cl + k] replaces eta^beta of candidate k
+ * of city i in Eq. 1 and Eq. 2; the fallback over all unvisited cities keeps
+ * eta^beta.  Every weight must be positive and finite (else -1, nothing
+ * changed); NULL restores eta^beta. */
+int orc_set_candidate_weights(orc *o, const float *w) {
+  const size_t cnt = (size_t)o->n * o->cl;
+  if (!w) {
+    free(o->cw);
+    o->cw = NULL;
+    return 0;
+  }
+  for (size_t e = 0; e < cnt; ++e)
+    if (!(w[e] > 0.0f) || !isfinite(w[e])) return -1;
+  if (!o->cw) {
+    o->cw = (float *)malloc(sizeof(float) * cnt);
+    if (!o->cw) return -1;
+  }
+  memcpy(o->cw, w, sizeof(float) * cnt);
+  return 0;
+}
+
+/* Sets the dense pheromone matrix (n*n, row-major, positive finite values),
+ * for the pin tests that start from a chosen state (dense only; -1
+ * otherwise). */
+int orc_set_tau(orc *o, const float *tau) {
+  const size_t nn = (size_t)o->n * o->n;
+  if (o->memory != ORC_DENSE) return -1;
+  for (size_t e = 0; e < nn; ++e)
+    if (!(tau[e] > 0.0f) || !isfinite(tau[e])) return -1;
+  memcpy(o->tau, tau, sizeof(float) * nn);
+  return 0;
+}
+
+/* Alg. 3 on the record of u for neighbour v with the map x -> fmaf(a, x, b),
+ * exposed for the pin tests (SPM only; -1 otherwise). */
+int orc_spm_update(orc *o, int32_t u, int32_t v, float a, float b) {
+  if (o->memory != ORC_SPM || u < 0 || u >= o->n || v < 0 || v >= o->n) return -1;
+  spm_update(o, u, v, a, b);
+  return 0;
+}
+
+/* Replaces the best-so-far tour and its length (the receiving side of an
+ * exchange between colonies).  The tour must be a permutation of 0..n-1
+ * (else -1, nothing changed). */
+int orc_set_best(orc *o, const int32_t *tour, int64_t len) {
+  const int32_t n = o->n;
+  uint8_t *seen = (uint8_t *)calloc((size_t)n, 1);
+  if (!seen || len < 0) { free(seen); return -1; }
+  for (int32_t p = 0; p < n; ++p) {
+    if (tour[p] < 0 || tour[p] >= n || seen[tour[p]]) { free(seen); return -1; }
+    seen[tour[p]] = 1;
+  }
+  free(seen);
+  memcpy(o->best, tour, sizeof(int32_t) * (size_t)n);
+  o->lgb = len;
+  return 0;
+}
+
+/* Exchange of the best solutions between C colonies of one instance
+ * (the multi-colony model of Sec. 2: periodic exchange along a
+ * communication topology).  Every colony first offers its best-so-far as it
+ * is before the exchange; then colony c takes the offer of its source if
+ * that is strictly shorter than its own.  topology 0: the source of every
+ * colony is the colony with the shortest best-so-far (lowest index among
+ * equals); topology 1 (ring): the source of colony c is colony c - 1
+ * (colony 0: colony C - 1).  Colonies without a best-so-far offer nothing.
+ * Returns -1 for an invalid call. */
+int orc_exchange_best(orc **cols, int32_t count, int32_t topology) {
+  if (count < 1 || (topology != 0 && topology != 1)) return -1;
+  const int32_t n = cols[0]->n;
+  for (int32_t c = 1; c < count; ++c)
+    if (cols[c]->n != n) return -1;
+  int32_t *offer = (int32_t *)malloc(sizeof(int32_t) * (size_t)n * count);
+  int64_t *olen = (int64_t *)malloc(sizeof(int64_t) * (size_t)count);
+  if (!offer || !olen) { free(offer); free(olen); return -1; }
+  for (int32_t c = 0; c < count; ++c) {
+    olen[c] = cols[c]->lgb;
+    memcpy(offer + (size_t)c * n, cols[c]->best, sizeof(int32_t) * (size_t)n);
+  }
+  int32_t g = -1;
+  for (int32_t c = 0; c < count; ++c)
+    if (olen[c] >= 0 && (g < 0 || olen[c] < olen[g])) g = c;
+  for (int32_t c = 0; c < count; ++c) {
+    const int32_t src = topology == 0 ? g : (c + count - 1) % count;
+    if (src < 0 || olen[src] < 0) continue;
+    if (cols[c]->lgb < 0 || olen[src] < cols[c]->lgb) {
+      memcpy(cols[c]->best, offer + (size_t)src * n, sizeof(int32_t) * (size_t)n);
+      cols[c]->lgb = olen[src];
+    }
+  }
+  free(offer);
+  free(olen);
   return 0;
 }
 

@@ -43,6 +43,21 @@ void orc_set_threads(int32_t threads);
  * returns 0, or -1 for k < 1. */
 int orc_set_local_period(orc *o, int32_t k);
 
+/* Learned candidate scores (n*cl floats, each positive and finite) replace
+ * eta^beta of the candidates in Eq. 1 and Eq. 2; the greedy fallback over
+ * all unvisited cities keeps eta^beta.  NULL restores eta^beta.  Returns 0,
+ * or -1 for an invalid weight (nothing changed). */
+int orc_set_candidate_weights(orc *o, const float *w);
+/* Replaces the best-so-far tour (a permutation of 0..n-1) and its length;
+ * 0, or -1 if the tour is not a permutation. */
+int orc_set_best(orc *o, const int32_t *tour, int64_t len);
+/* Exchange of best-so-far solutions between `count` colonies of one
+ * instance: each colony takes its source's best-so-far (as it was before the
+ * exchange) if strictly shorter than its own.  topology 0: the source is the
+ * colony with the shortest best-so-far (lowest index among equals); 1: ring,
+ * the source of colony c is colony c - 1 mod count.  0, or -1. */
+int orc_exchange_best(orc **cols, int32_t count, int32_t topology);
+
 /* One full iteration of Alg. 1 = construct + select_best + global_update. */
 void orc_iterate(orc *o, int32_t k);
 /* The three parts of one iteration, for tests of each part. */
@@ -80,6 +95,12 @@ int32_t orc_roulette_pick(const float *w, const uint8_t *unvisited,
 /* Histogram of orc_roulette_pick over every u24 in [0, 2^24). */
 void orc_roulette_hist(const float *w, const uint8_t *unvisited, int32_t cl,
                        int64_t *counts);
+/* Sets the dense pheromone matrix (n*n positive finite floats), for pins
+ * that start from a chosen state (dense handles only; 0, or -1). */
+int orc_set_tau(orc *o, const float *tau);
+/* Alg. 3 on the record of u for neighbour v with the map x -> fmaf(a, x, b)
+ * (SPM handles only; 0, or -1). */
+int orc_spm_update(orc *o, int32_t u, int32_t v, float a, float b);
 /* The local map of Eq. 3 with this instance's constants, applied k times. */
 float orc_local_map_k(const orc *o, float x, int32_t k);
 

@@ -113,3 +113,17 @@ def grads(p: dict, X: np.ndarray, y: np.ndarray, bf16_ops: bool = False) -> dict
     g["W1"] = x.T @ dh1
     g["b1"] = dh1.sum(axis=0)
     return g
+
+
+def adam_step(p: dict, g: dict, m: dict, v: dict, step: int, lr: float = 1e-3,
+              beta1: float = 0.9, beta2: float = 0.999, eps: float = 1e-8) -> None:
+    """One Adam step (Kingma and Ba, ICLR 2015, Algorithm 1) in float64, in
+    place on every array of p, m and v: first and second moment estimates,
+    bias correction by 1 - beta^step, then p -= lr * m_hat / (sqrt(v_hat) + eps)."""
+    for k in p:
+        gk = np.asarray(g[k], dtype=np.float64).reshape(p[k].shape)
+        m[k] = beta1 * m[k] + (1.0 - beta1) * gk
+        v[k] = beta2 * v[k] + (1.0 - beta2) * gk * gk
+        m_hat = m[k] / (1.0 - beta1 ** step)
+        v_hat = v[k] / (1.0 - beta2 ** step)
+        p[k] = p[k] - lr * m_hat / (np.sqrt(v_hat) + eps)

@@ -463,3 +463,193 @@ def test_fmaf32_helper_rounds_once():
     # exact: 2^-11 + 2^-24; a product rounded to float first loses the 2^-24
     assert defs.fmaf32(a, x, b) == np.float32(2 ** -11 + 2 ** -24)
     assert np.float32(a * x) + b == np.float32(2 ** -11)
+
+
+# --------------------------------------------------------------------------
+# Alg. 3 (Sec. 3.2) worked by hand on one record with s = 3.  A miss writes
+# slot (tail + 1) mod s, the slot of the trail inserted longest ago, whatever
+# its value or how recently it was hit; a hit maps the stored value in place
+# and leaves tail alone; a miss stores the map applied to tau0.  The map here
+# (a = 1/2, b = tau0) moves tau0 so that every application shows.
+# --------------------------------------------------------------------------
+def test_spm_alg3_eviction_worked_by_hand():
+    o = oracle.Oracle(inputs.uniform(8, 31), m=2, cl=4, memory=oracle.SPM, spm_s=3, seed=1)
+    t0 = np.float32(o.constants()["tau0"])
+    a, b = np.float32(0.5), t0
+    f = lambda x: defs.fmaf32(a, x, b)  # noqa: E731
+    ag = np.float32(o.constants()["a_glob"])
+    bg = np.float32(0.25)
+    g = lambda x: defs.fmaf32(ag, x, bg)  # noqa: E731
+
+    def rec():
+        nodes, vals, tail = o.spm()
+        return nodes[0].tolist(), vals[0].copy(), int(tail[0])
+
+    nodes, vals, tail = rec()
+    assert nodes == [-1, -1, -1] and tail == 2  # empty record, first insert -> slot 0
+    o.spm_update(0, 1, a, b)                     # miss: slot 0
+    nodes, vals, tail = rec()
+    assert nodes == [1, -1, -1] and tail == 0 and vals[0] == f(t0)
+    o.spm_update(0, 2, a, b)                     # miss: slot 1
+    o.spm_update(0, 1, a, b)                     # hit: slot 0 mapped again, tail stays
+    nodes, vals, tail = rec()
+    assert nodes == [1, 2, -1] and tail == 1
+    assert vals[0] == f(f(t0)) and vals[1] == f(t0)
+    o.spm_update(0, 3, a, b)                     # miss: slot 2
+    o.spm_update(0, 4, a, b)                     # miss: evicts slot 0 (v = 1, hit last)
+    nodes, vals, tail = rec()
+    assert nodes == [4, 2, 3] and tail == 0
+    assert vals[0] == f(t0) and vals[1] == f(t0) and vals[2] == f(t0)
+    o.spm_update(0, 2, a, b)                     # hit on slot 1
+    o.spm_update(0, 5, ag, bg)                   # a global-update miss: g(tau0) in slot 1
+    nodes, vals, tail = rec()
+    assert nodes == [4, 5, 3] and tail == 1
+    assert vals[1] == g(t0) and vals[0] == f(t0) and vals[2] == f(t0)
+    # the ants read the record as Eq. 1 needs it: a stored trail, else tau0
+    tau = o.tau()
+    assert tau[0, 4] == f(t0) and tau[0, 5] == g(t0) and tau[0, 3] == f(t0)
+    assert tau[0, 1] == t0 and tau[0, 2] == t0 and tau[0, 6] == t0
+    # the other records are untouched
+    nodes_all, _, tail_all = o.spm()
+    assert np.all(nodes_all[1:] == -1) and np.all(tail_all[1:] == 2)
+    cnt = o.counts()
+    assert cnt["spm_hits"] == 2 and cnt["spm_misses"] == 5
+
+
+# --------------------------------------------------------------------------
+# Alg. 1 read literally (ORC_SEQUENTIAL), worked by hand on 5 cities: two
+# ants start at city 0, whose neighbours 1 and 2 are both at distance 100
+# (equal eta^beta), with tau(0, 1) = 10.5 tau0 and tau(0, 2) = 10 tau0; q0 = 1
+# makes every choice the argmax of Eq. 1.  Ant 0 takes city 1 and its local
+# update (Eq. 3) lowers tau(0, 1) to 0.9 * 10.5 tau0 + 0.1 tau0 = 9.55 tau0
+# < 10 tau0 before ant 1 chooses, so ant 1 takes city 2.  In the synchronous
+# schedule both read the step-start value and take city 1; with the ants in
+# the opposite order ant 1 would take city 1 and ant 0 city 2.
+# --------------------------------------------------------------------------
+def _seed_with_shared_start(n, m):
+    for seed in range(5000):
+        key = [seed & 0xFFFFFFFF, seed >> 32]
+        st = [int((int(oracle.philox([0, a, 0, 0], key)[2]) * n) >> 32) for a in range(m)]
+        if st[0] == 0 and st[1] == 0 and all(s != 0 for s in st[2:]):
+            return seed
+    raise AssertionError("no seed found")
+
+
+def test_sequential_step_reads_earlier_ants_updates_by_hand():
+    xy = np.array([[5000, 5000], [5100, 5000], [5000, 5100], [4700, 5000], [5000, 4700]],
+                  dtype=np.float64)
+    n, m = 5, 3
+    seed = _seed_with_shared_start(n, m)
+    picks = {}
+    for mode in (oracle.SEQUENTIAL, oracle.SYNC):
+        o = oracle.Oracle(xy, m=m, cl=n - 1, q0=1.0, phi=0.1, mode=mode, seed=seed)
+        t0 = np.float32(o.constants()["tau0"])
+        tau = np.full((n, n), t0, dtype=np.float32)
+        tau[0, 1] = tau[1, 0] = np.float32(10.5) * t0
+        tau[0, 2] = tau[2, 0] = np.float32(10.0) * t0
+        o.set_tau(tau)
+        o.construct()
+        tours = o.tours()
+        assert tours[0, 0] == 0 and tours[1, 0] == 0 and tours[2, 0] != 0
+        picks[mode] = (int(tours[0, 1]), int(tours[1, 1]))
+        # the map of Eq. 3 at this value really lands below 10 tau0
+        assert o.local_map_k(float(tau[0, 1]), 1) < tau[0, 2]
+    assert picks[oracle.SEQUENTIAL] == (1, 2)
+    assert picks[oracle.SYNC] == (1, 1)
+
+
+# --------------------------------------------------------------------------
+# Learned candidate scores in Eq. 1 and Eq. 2.  (1) Scores equal to eta^beta
+# reproduce the plain run bit for bit.  (2) With q0 = 1 and uniform
+# pheromone, the first iteration's tours are greedy walks by the largest
+# score among the unvisited candidates (ties: nearest position), and, when
+# every candidate is visited, by the nearest unvisited city (ties: lowest
+# index): the fallback keeps eta^beta, which decreases with d.
+# --------------------------------------------------------------------------
+def test_scores_equal_to_eta_reproduce_plain_run():
+    xy = inputs.uniform(80, 33)
+    plain = oracle.Oracle(xy, m=40, cl=12, seed=3)
+    sc = oracle.Oracle(xy, m=40, cl=12, seed=3)
+    d = plain.dist()
+    cand = plain.cand()
+    eta = plain.eta(int(d.max()) + 1)
+    sc.set_candidate_weights(eta[d[np.arange(80)[:, None], cand]])
+    for _ in range(4):
+        plain.iterate(1); sc.iterate(1)
+        assert np.array_equal(plain.tours(), sc.tours())
+        assert np.array_equal(plain.tau(), sc.tau())
+    assert plain.counts() == sc.counts()
+
+
+@pytest.mark.parametrize("n,cl,seed", [(60, 6, 1), (45, 4, 2)])
+def test_scores_drive_the_greedy_choice_and_fallback_keeps_eta(n, cl, seed):
+    xy = inputs.uniform(n, 40 + seed)
+    d = defs.dist_matrix(xy)
+    # candidate lists from a plain sort by (d, j)
+    cand = np.array([sorted((j for j in range(n) if j != i), key=lambda j: (d[i, j], j))[:cl]
+                     for i in range(n)])
+    rng = np.random.default_rng(seed)
+    scores = rng.uniform(0.1, 1.0, size=(n, cl)).astype(np.float32)
+    o = oracle.Oracle(xy, m=n, cl=cl, q0=1.0, seed=seed)
+    c = o.constants()
+    assert o.local_map_k(c["tau0"], 1) == c["tau0"]  # pheromone stays uniform
+    o.set_candidate_weights(scores)
+    o.construct()
+    tours = o.tours()
+    fallbacks = 0
+    for a in range(n):
+        cur = int(tours[a, 0])
+        seen = {cur}
+        walk = [cur]
+        for _ in range(n - 1):
+            opts = [k for k in range(cl) if int(cand[cur, k]) not in seen]
+            if opts:
+                k = max(opts, key=lambda k: (scores[cur, k], -k))
+                nxt = int(cand[cur, k])
+            else:
+                fallbacks += 1
+                nxt = min((j for j in range(n) if j not in seen), key=lambda j: (d[cur, j], j))
+            walk.append(nxt)
+            seen.add(nxt)
+            cur = nxt
+        assert tours[a].tolist() == walk
+    assert fallbacks > 0  # the fallback rule was exercised
+    with pytest.raises(ValueError):
+        o.set_candidate_weights(np.zeros((n, cl), np.float32))
+
+
+# --------------------------------------------------------------------------
+# Exchange of best-so-far solutions between colonies (the multi-colony model
+# of Sec. 2): after an exchange from the shortest, every colony holds a valid
+# tour of the shortest length; a ring passes the shortest to every colony
+# within count - 1 exchanges and never lengthens a colony's best.
+# --------------------------------------------------------------------------
+def test_exchange_best_between_colonies():
+    xy = inputs.uniform(40, 50)
+    d = defs.dist_matrix(xy)
+    C = 5
+    for topology in (0, 1):
+        cols = [oracle.Oracle(xy, m=4, cl=8, seed=7, instance=c) for c in range(C)]
+        for o in cols:
+            o.iterate(2)
+        lens0 = [o.best()[1] for o in cols]
+        gmin = min(lens0)
+        assert len(set(lens0)) > 1  # the colonies differ before the exchange
+        rounds = 1 if topology == 0 else C - 1
+        prev = lens0
+        for r in range(rounds):
+            oracle.exchange_best(cols, topology)
+            now = [o.best()[1] for o in cols]
+            assert all(x <= y for x, y in zip(now, prev))
+            if topology == 1 and r == 0:
+                # one ring step: colony c holds min(own, colony c - 1's)
+                assert now == [min(prev[c], prev[c - 1]) for c in range(C)]
+            prev = now
+        for o in cols:
+            t, L = o.best()
+            assert sorted(t.tolist()) == list(range(40))
+            assert L == defs.tour_length(d, t) == gmin
+        if topology == 0:
+            g = lens0.index(gmin)
+            ref = cols[g].best()[0]
+            assert all(np.array_equal(o.best()[0], ref) for o in cols)

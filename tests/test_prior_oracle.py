@@ -94,3 +94,24 @@ def test_feature_definition_properties(kind):
     # invariant under translation of the instance
     F2 = prior.features(xy + 1234.5, cand, d).reshape(n, 16, 4)
     assert np.allclose(F, F2, atol=1e-4)
+
+
+def test_adam_step_matches_torch_optimizer():
+    """The oracle's Adam against torch.optim.Adam (an independent
+    implementation of the same published update), float64, five steps."""
+    import torch
+    rng = np.random.default_rng(3)
+    p = prior.init_params(4)
+    p = {k: v.astype(np.float64) for k, v in p.items()}
+    tp = {k: torch.tensor(v.copy(), dtype=torch.float64, requires_grad=True) for k, v in p.items()}
+    opt = torch.optim.Adam(list(tp.values()), lr=3e-3, betas=(0.8, 0.99), eps=1e-7)
+    m = {k: np.zeros_like(v) for k, v in p.items()}
+    v = {k: np.zeros_like(v) for k, v in p.items()}
+    for step in range(1, 6):
+        g = {k: rng.normal(size=val.shape) * (10.0 ** -step) for k, val in p.items()}
+        prior.adam_step(p, g, m, v, step, lr=3e-3, beta1=0.8, beta2=0.99, eps=1e-7)
+        for k in tp:
+            tp[k].grad = torch.tensor(g[k], dtype=torch.float64)
+        opt.step()
+        for k in p:
+            np.testing.assert_allclose(p[k], tp[k].detach().numpy(), rtol=1e-12, atol=1e-15)
