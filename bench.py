@@ -92,11 +92,37 @@ def run_mode(acs, xy, mode, steps, warmup, seed=0, **kw):
     return res
 
 
+def host_cpu() -> dict:
+    """The host's CPU model, logical CPUs, the CPUs this process may run on,
+    and the OpenMP thread count the environment sets."""
+    model = None
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    try:
+        affinity = len(os.sched_getaffinity(0))
+    except (AttributeError, OSError):
+        affinity = os.cpu_count() or 1
+    omp = os.environ.get("OMP_NUM_THREADS")
+    return {"cpu_model": model, "nproc": os.cpu_count(), "affinity": affinity,
+            "omp_num_threads": int(omp) if omp and omp.isdigit() else None}
+
+
 def cpu_baseline(xy, budget_s: float = 12.0):
-    """The oracle on the host cores: all cores (OpenMP over the ants of a
-    step), then one thread (the paper's sequential convention)."""
+    """The oracle on the host cores: every core this process may use (OpenMP
+    over the ants of a step; the environment's OMP_NUM_THREADS caps it where
+    set, as on a shared host), then one thread (the paper's sequential
+    convention)."""
     import oracle
-    threads = min(os.cpu_count() or 1, 16)
+    host = host_cpu()
+    threads = host["affinity"]
+    if host["omp_num_threads"]:
+        threads = min(threads, host["omp_num_threads"])
     oracle.set_threads(threads)
     orc = oracle.Oracle(xy, cl=CL, seed=0)
     t0 = time.perf_counter()
@@ -117,7 +143,7 @@ def cpu_baseline(xy, budget_s: float = 12.0):
     steps1 = one.counts()["steps"]
     one.close()
     return dict(value=steps / dt, unit="steps/s", cores=threads, kind="oracle",
-                single_thread_value=steps1 / dt1,
+                single_thread_value=steps1 / dt1, host=host,
                 sample=f"{iters} synchronous iterations of the n={N}, m={N} workload "
                        f"({steps} steps, {dt:.1f} s, {threads} OpenMP threads); "
                        f"single thread: 1 iteration ({dt1:.1f} s)")
@@ -186,6 +212,69 @@ def run_batch(acs, inputs, iters=5, count=256):
             "create_s": create_s}
 
 
+def run_quality(acs, inputs, seeds=20, iters=100):
+    """Best tour length after `iters` iterations over `seeds` seeds at the
+    headline size, for the bit-exact synchronous mode, the asynchronous
+    atomic mode (headline kernel) and the unsynchronised Alt mode (Sec. 3.1.2
+    and Sec. 4.1 compare the atomic and the Alt variants this way)."""
+    import numpy as np
+    from scipy.stats import mannwhitneyu
+    xy = inputs.uniform(N)
+    arms = {"sync": acs.ACS_SYNC, "async_atomic": acs.ACS_ASYNC_ATOMIC,
+            "alt": acs.ACS_ASYNC_RACY}
+    res, out = {}, {"n": N, "seeds": seeds, "iterations": iters}
+    for name, mode in arms.items():
+        best = []
+        for s in range(seeds):
+            col = acs.Colony(xy, mode=mode, seed=s, cl=CL)
+            col.iterate(iters)
+            best.append(col.best()[1])
+            lnn = col.stats()["nn_length"]
+            col.close()
+        r = np.array(best, dtype=np.float64)
+        res[name] = r
+        out[name] = {"mean": r.mean(), "sd": r.std(), "min": r.min(), "max": r.max(),
+                     "vs_nn_percent": 100.0 * (r.mean() / lnn - 1.0)}
+    for a, b in (("async_atomic", "sync"), ("alt", "async_atomic"), ("alt", "sync")):
+        out[f"{a}_vs_{b}"] = {"gap_percent": 100.0 * (res[a].mean() / res[b].mean() - 1.0),
+                              "rank_sum_p": float(mannwhitneyu(res[a], res[b]).pvalue)}
+    return out
+
+
+def run_ants(acs, inputs, ants=(64, 256, 1024, N), seeds=10, budget_tours=25 * N,
+             budget_s=0.5):
+    """Fewer ants than cities (Sec. 4, the number of ants): mean best tour
+    length over `seeds` seeds for each colony size m, at an equal budget of
+    constructed solutions (budget_tours / m iterations) and at equal wall
+    clock (budget_s per run), asynchronous atomic mode at the headline size."""
+    import numpy as np
+    import torch
+    xy = inputs.uniform(N)
+    out = {"n": N, "seeds": seeds, "budget_tours": budget_tours, "budget_s": budget_s}
+    for m in ants:
+        iters = max(1, budget_tours // m)
+        eq_b, eq_t, its_t = [], [], []
+        for s in range(seeds):
+            col = acs.Colony(xy, m=m, mode=acs.ACS_ASYNC_ATOMIC, seed=s, cl=CL)
+            col.iterate(iters)
+            eq_b.append(col.best()[1])
+            col.close()
+            col = acs.Colony(xy, m=m, mode=acs.ACS_ASYNC_ATOMIC, seed=s, cl=CL)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            k = 0
+            while time.perf_counter() - t0 < budget_s:
+                col.iterate(1)
+                k += 1
+            eq_t.append(col.best()[1])
+            its_t.append(k)
+            col.close()
+        out[f"m{m}"] = {"equal_budget": {"iterations": iters, "mean_best": float(np.mean(eq_b))},
+                        "equal_time": {"iterations": float(np.mean(its_t)),
+                                       "mean_best": float(np.mean(eq_t))}}
+    return out
+
+
 MFMA_BF16_PEAK_TFLOPS = 2500.0
 # algorithmic flops per feature row of the 4-64-64-1 network: forward
 # 2 (4*64 + 64*64 + 64); backward adds the weight and input gradients of the
@@ -195,7 +284,7 @@ PRIOR_FWD_FLOPS = 2 * (4 * 64 + 64 * 64 + 64)
 PRIOR_BWD_FLOPS = PRIOR_FWD_FLOPS + 2 * (64 + 64 + 2 * 64 * 64 + 4 * 64)
 
 
-def run_prior(acs, inputs, rows=1 << 22, reps=5, eval_seeds=5, eval_budget_s=1.0):
+def run_prior(acs, inputs, rows=1 << 22, reps=5, eval_seeds=10, eval_budget_s=0.5):
     """The learned prior's kernels at training scale (BF16 matrix cores), and
     the equal-wall-clock comparison with plain ACS when trained parameters
     are present."""
@@ -248,10 +337,11 @@ def main():
     ap.add_argument("--sync-steps", type=int, default=5)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--extra", default="n198,n1000_clustered,n20000_spm,batch256,prior,n2392_alt,"
-                                       "n2392_period16,n2392_sequential,n2392_sequential_m64",
+                                       "n2392_period16,n2392_sequential,n2392_sequential_m64,"
+                                       "quality,ants",
                     help="other workloads timed beside the headline (comma list of "
                          "n198, n1000_clustered, n20000_spm, batch256, prior, n2392_alt, n2392_period16, "
-                         "n2392_sequential, n2392_sequential_m64; empty for none)")
+                         "n2392_sequential, n2392_sequential_m64, quality, ants; empty for none)")
     ap.add_argument("--copy-calibration-mb", type=int, default=0,
                     help="after timing, run one plain device copy of this many MiB "
                          "(reference kernel for hardware byte counters)")
@@ -319,6 +409,10 @@ def main():
     for name in [x for x in args.extra.split(",") if x]:
         if name == "batch256":
             extra[name] = run_batch(acs, inputs)
+        elif name == "quality":
+            extra[name] = run_quality(acs, inputs)
+        elif name == "ants":
+            extra[name] = run_ants(acs, inputs)
         elif name == "prior":
             extra[name] = run_prior(acs, inputs)
         else:

@@ -98,6 +98,13 @@ typedef struct acs_params {
                             0, the default) the ant waves hand them to one
                             updater wavefront per workgroup through LDS, so
                             an ant never waits for an atomic */
+  uint32_t wait_limit;   /* polls after which a bounded device wait (grid
+                            barrier, update ring) gives up; 0: the library's
+                            own limits.  A wait that gives up makes the
+                            iterate call return ACS_E_DEVICE (its results are
+                            then not to be trusted); every kernel still runs
+                            to its end.  Small values force that path, for
+                            tests of the error handling. */
 } acs_params;
 
 typedef struct acs_stats {
@@ -152,7 +159,8 @@ int acs_create(const double *coords_xy, int32_t n, const acs_params *p,
 
 /* Runs k >= 0 iterations of Alg. 1 on the handle's stream and returns once
  * they have finished.  The iteration counter persists across calls, so
- * acs_iterate(h, 2) equals acs_iterate(h, 1) twice. */
+ * acs_iterate(h, 2) equals acs_iterate(h, 1) twice.  ACS_E_DEVICE if a
+ * kernel failed or a bounded device wait gave up during the call. */
 int acs_iterate(struct acs_t *h, int32_t k);
 
 /* Best-so-far tour (n cities, starting at its ant's start city) and its
@@ -206,7 +214,8 @@ int acs_batch_workspace_bytes(const int32_t *n, int32_t count, const acs_params 
 int acs_batch_create(const double *const *coords, const int32_t *n, int32_t count,
                      const acs_params *p, acs_batch_t **out);
 
-/* k iterations of every instance; returns once they have finished.  The
+/* k iterations of every instance; returns once they have finished
+ * (ACS_E_DEVICE if a bounded device wait gave up in any instance).  The
  * first iterations also choose the launch shape: one untimed iteration,
  * then one timed iteration with each candidate, later iterations with the
  * fastest.  The candidates are 64 lanes per ant with the ant issuing its

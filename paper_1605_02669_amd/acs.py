@@ -36,6 +36,7 @@ class acs_params(C.Structure):
         ("rho", C.c_double), ("tau0", C.c_double), ("seed", C.c_uint64),
         ("stream", C.c_void_p), ("workspace", C.c_void_p), ("workspace_bytes", C.c_size_t),
         ("lanes_per_ant", C.c_uint32), ("update_path", C.c_uint32),
+        ("wait_limit", C.c_uint32),
     ]
 
 
@@ -200,7 +201,8 @@ class Colony:
 
     def __init__(self, xy, m=0, cl=32, beta=2.0, q0=0.9, phi=0.1, rho=0.1, tau0=0.0,
                  memory=ACS_DENSE, spm_s=8, mode=ACS_SYNC, seed=0, instance=0,
-                 local_update_period=1, lanes_per_ant=0, update_path=0, torch_memory=True):
+                 local_update_period=1, lanes_per_ant=0, update_path=0, wait_limit=0,
+                 torch_memory=True):
         self.xy = np.ascontiguousarray(xy, dtype=np.float64).reshape(-1, 2)
         n = self.xy.shape[0]
         p = acs_default_params()
@@ -209,6 +211,7 @@ class Colony:
         p.local_update_period = local_update_period
         p.lanes_per_ant = lanes_per_ant
         p.update_path = update_path
+        p.wait_limit = wait_limit
         self._ws = None
         if torch_memory:
             import torch
@@ -290,7 +293,7 @@ class Batch:
 
     def __init__(self, instances, m=0, cl=32, beta=2.0, q0=0.9, phi=0.1, rho=0.1, tau0=0.0,
                  seed=0, instance=0, local_update_period=1, mode=ACS_ASYNC_ATOMIC,
-                 lanes_per_ant=0, update_path=0, torch_memory=True):
+                 lanes_per_ant=0, update_path=0, wait_limit=0, torch_memory=True):
         self.xys = [np.ascontiguousarray(x, dtype=np.float64).reshape(-1, 2) for x in instances]
         sizes = np.array([x.shape[0] for x in self.xys], dtype=np.int32)
         p = acs_default_params()
@@ -299,6 +302,7 @@ class Batch:
         p.local_update_period = local_update_period
         p.lanes_per_ant = lanes_per_ant
         p.update_path = update_path
+        p.wait_limit = wait_limit
         self._ws = None
         if torch_memory:
             import torch

@@ -378,6 +378,7 @@ int acs_create(const double *coords_xy, int32_t n, const acs_params *p, acs_t **
   d.gstate = reinterpret_cast<int64_t *>(w + h->L.gstate);
   d.counters = reinterpret_cast<unsigned long long *>(w + h->L.counters);
   d.sync = reinterpret_cast<uint32_t *>(w + h->L.sync);
+  d.wait_limit = p->wait_limit;
   if (p->mode == ACS_SYNC) {
     d.bflags = reinterpret_cast<unsigned long long *>(w + h->L.bflags);
     d.nbflags = 16 * ((m + 15) / 16 + 1);
@@ -408,6 +409,8 @@ int acs_iterate(acs_t *h, int32_t k) {
     HIP_TRY(hipEventCreate(&e));
     h->ev.push_back(e);
   }
+  // a bounded wait that ran out in an earlier call was reported by it
+  HIP_TRY(hipMemsetAsync(h->ws + h->L.sync, 0, 2 * sizeof(uint32_t), h->stream));
   HIP_TRY(hipEventRecord(h->ev_begin, h->stream));
   for (int i = 0; i < k; ++i) {
     acs::Iter it = h->base;
@@ -577,6 +580,7 @@ struct acs_batch_t {
   bool own_ws = false;
   acs::Dev *d_devs = nullptr;
   acs::Iter *d_iters = nullptr;
+  uint32_t *d_flag = nullptr;  // OR of the instances' error flags (see k_best_batch)
   int nmax = 0, clmax = 0, mode = ACS_ASYNC_ATOMIC;
   int64_t steps_per_iteration = 0;
   // One launch configuration per candidate lanes-per-ant value: its work
@@ -624,7 +628,7 @@ void release_batch(acs_batch_t *b) {
 
 struct BatchLayout {
   std::vector<size_t> off;
-  size_t devs, iters, items, total;
+  size_t devs, iters, items, flag, total;
 };
 
 int batch_layout(const int32_t *n, int32_t count, const acs_params *p, BatchLayout *L,
@@ -649,6 +653,8 @@ int batch_layout(const int32_t *n, int32_t count, const acs_params *p, BatchLayo
   off = align_up(off + sizeof(acs::Iter) * (size_t)count, 256);
   L->items = off;
   off = align_up(off + sizeof(int2) * (size_t)*nitems, 256);
+  L->flag = off;
+  off = align_up(off + sizeof(uint32_t), 256);
   L->total = off;
   return ACS_OK;
 }
@@ -775,6 +781,7 @@ int acs_batch_create(const double *const *coords, const int32_t *n, int32_t coun
   std::stable_sort(order.begin(), order.end(), [&](int a, int c) { return n[a] > n[c]; });
   b->d_devs = reinterpret_cast<acs::Dev *>(b->ws + L.devs);
   b->d_iters = reinterpret_cast<acs::Iter *>(b->ws + L.iters);
+  b->d_flag = reinterpret_cast<uint32_t *>(b->ws + L.flag);
   int2 *d_items = reinterpret_cast<int2 *>(b->ws + L.items);
   std::vector<int2> items;
   items.reserve((size_t)nitems);
@@ -806,7 +813,7 @@ int acs_batch_create(const double *const *coords, const int32_t *n, int32_t coun
     if (hipStreamBeginCapture(b->stream, hipStreamCaptureModeThreadLocal) != hipSuccess) continue;
     const hipError_t le = acs::launch_batch_iteration(b->d_devs, b->d_iters, v.d_items, v.nitems,
                                                       b->count, b->nmax, b->clmax, b->mode, v.lanes,
-                                                      v.queued ? 1 : 0, b->stream);
+                                                      v.queued ? 1 : 0, b->d_flag, b->stream);
     hipGraph_t g = nullptr;
     const hipError_t ce = hipStreamEndCapture(b->stream, &g);
     if (le == hipSuccess && ce == hipSuccess && g) {
@@ -834,8 +841,10 @@ int acs_batch_iterate(acs_batch_t *b, int32_t k) {
     if (v.exec) return hipGraphLaunch(v.exec, b->stream);
     return acs::launch_batch_iteration(b->d_devs, b->d_iters, v.d_items, v.nitems, b->count,
                                        b->nmax, b->clmax, b->mode, v.lanes, v.queued ? 1 : 0,
-                                       b->stream);
+                                       b->d_flag, b->stream);
   };
+  // cleared outside the captured graphs (a memset node is not captured)
+  HIP_TRY(hipMemsetAsync(b->d_flag, 0, sizeof(uint32_t), b->stream));
   double total_ms = 0.0;
   int i = 0;
   // tuning: one untimed warm-up iteration, then one timed iteration per
@@ -876,6 +885,11 @@ int acs_batch_iterate(acs_batch_t *b, int32_t k) {
     h->construct_ms = 0.0;
     h->construct_launches = 0;
   }
+  uint32_t flag = 0;
+  HIP_TRY(hipMemcpy(&flag, b->d_flag, sizeof flag, hipMemcpyDeviceToHost));
+  if (flag)
+    return fail(ACS_E_DEVICE, "a bounded device wait was exhausted in a batch instance (flag %u: "
+                              "1 grid barrier, 2 update ring); local updates may be missing", flag);
   return ACS_OK;
 }
 

@@ -61,6 +61,8 @@ struct Dev {
   unsigned long long *bflags;  // synchronous mode: grid barrier flags, one per
                                //   block, 16 words (128 bytes) apart, from word 16
   int32_t nbflags;             //   words in bflags
+  uint32_t wait_limit;         // polls before a bounded wait gives up (0: the
+                               //   kernels' own limits)
 };
 
 // Per-iteration scalars.
@@ -103,9 +105,12 @@ hipError_t launch_best_global(const Dev &d, const Iter &it, int memory,
 // `queued`: items are (instance, first ant) of the kBatchQAntsPerBlock ants
 // of one block, whose updates an updater wave applies.
 constexpr int kBatchQAntsPerBlock = 4;
+// `flag` (device word): k_best_batch ORs every instance's error flag into it
+// and clears the instance's flag, so one read after the iteration reports an
+// exhausted bounded wait in any instance.
 hipError_t launch_batch_iteration(const Dev *devs, Iter *iters, const int2 *items, int nitems,
                                   int count, int nmax, int clmax, int mode, int lanes, int queued,
-                                  hipStream_t s);
+                                  uint32_t *flag, hipStream_t s);
 // Learned edge prior (acs_prior.hip): parameter count and kernels.
 constexpr int kPriorParams = 4545;
 hipError_t launch_prior_forward(const float *P, const float *X, int rows, float *Z,

@@ -247,7 +247,7 @@ __device__ __forceinline__ void grid_barrier_f(const Dev &D, uint64_t epoch) {
       if (__ballot(!all) == 0) break;
       if (barrier_gave_up(D, spins)) break;
       __builtin_amdgcn_s_sleep(1);
-      if (++spins > (1u << 22)) {
+      if (++spins > (D.wait_limit ? D.wait_limit : (1u << 22))) {
         if (threadIdx.x == 0)
           __hip_atomic_store(D.sync + 1, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         break;
@@ -1282,7 +1282,7 @@ __device__ __forceinline__ uint32_t group_push(const Dev &D, const Iter &A, cons
       tail = (uint32_t)uni((int)lds_ld(q.tail + w));
       if ((uint32_t)g1 - tail <= (uint32_t)kQRing) break;
       __builtin_amdgcn_s_sleep(2);
-      if (++spins > kQSpin) {
+      if (++spins > (D.wait_limit ? D.wait_limit : kQSpin)) {
         if (lane == 0)
           __hip_atomic_store(D.sync + 1, 2u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         direct = true;
@@ -1343,7 +1343,7 @@ __device__ __forceinline__ void ring_updater(const Dev &D, const Iter &A, const 
     }
     if (done == (uint32_t)na) break;
     __builtin_amdgcn_s_sleep(32);
-    if (++idle > kQIdle) {
+    if (++idle > (D.wait_limit ? D.wait_limit : kQIdle)) {
       if (lane == 0)
         __hip_atomic_store(D.sync + 1, 2u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
       break;
@@ -2483,14 +2483,18 @@ __global__ __launch_bounds__(256) void k_global_spm(Dev D, Iter A) {
 }
 
 // Batched iteration end: block b handles instance b (iteration best and
-// best-so-far), then advances that instance's iteration counter.
-__global__ __launch_bounds__(1024) void k_best_batch(const Dev *devs, Iter *iters) {
+// best-so-far), then advances that instance's iteration counter and moves
+// its error flag (an exhausted bounded wait) into the batch's flag.
+__global__ __launch_bounds__(1024) void k_best_batch(const Dev *devs, Iter *iters,
+                                                     uint32_t *flag) {
   __shared__ int s_better;
   const Dev D = devs[blockIdx.x];
   int64_t bl;
   int ba;
   argmin_len(D, bl, ba);
   if (threadIdx.x == 0) {
+    const uint32_t f = atomicExch(D.sync + 1, 0u);
+    if (f) atomicOr(flag, f);
     const int64_t lgb = D.gstate[0];
     s_better = (lgb < 0 || bl < lgb) ? 1 : 0;
     D.gstate[0] = s_better ? bl : lgb;
@@ -2726,7 +2730,7 @@ hipError_t launch_best_global(const Dev &d, const Iter &it, int memory, hipStrea
 
 hipError_t launch_batch_iteration(const Dev *devs, Iter *iters, const int2 *items, int nitems,
                                   int count, int nmax, int clmax, int mode, int lanes, int queued,
-                                  hipStream_t s) {
+                                  uint32_t *flag, hipStream_t s) {
   const int apb = kAsyncBlock / 64;
   const int wmax = (nmax + 31) / 32;
   if (mode == 1) {
@@ -2761,7 +2765,7 @@ hipError_t launch_batch_iteration(const Dev *devs, Iter *iters, const int2 *item
     hipLaunchKernelGGL(k_ctau_out_batch, gc, dim3(256), 0, s, devs, mode == 1 ? 1 : 0);
     e = hipGetLastError();
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k_best_batch, dim3(count), dim3(1024), 0, s, devs, iters);
+    hipLaunchKernelGGL(k_best_batch, dim3(count), dim3(1024), 0, s, devs, iters, flag);
     e = hipGetLastError();
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(k_global_batch, dim3((nmax + 255) / 256, count), dim3(256), 0, s, devs,
@@ -2791,7 +2795,7 @@ hipError_t launch_batch_iteration(const Dev *devs, Iter *iters, const int2 *item
                        items, nitems, wmax);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(k_best_batch, dim3(count), dim3(1024), 0, s, devs, iters);
+  hipLaunchKernelGGL(k_best_batch, dim3(count), dim3(1024), 0, s, devs, iters, flag);
   e = hipGetLastError();
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(k_global_batch, dim3((nmax + 255) / 256, count), dim3(256), 0, s, devs,

@@ -163,9 +163,23 @@ def test_trained_prior_gain(acs):
           f"train loss by epoch {[round(h, 4) for h in hist]}")
     assert hist[-1] < hist[0]
     assert l1 < l0
-    assert l1 <= rank_loss * 1.01
+    assert l1 < rank_loss
     xy = inputs.uniform(1000, 903)
     plain = [prior.run_equal_time(xy, 0.4, s)[0] for s in range(3)]
     learned = [prior.run_equal_time(xy, 0.4, s, P)[0] for s in range(3)]
     print(f"equal time 0.4 s, n=1000: plain {np.mean(plain):.0f}, learned {np.mean(learned):.0f} "
           f"({100 * (np.mean(learned) / np.mean(plain) - 1):+.2f}%)")
+
+
+def test_committed_prior_beats_plain_acs_at_equal_time(acs):
+    """The committed parameters against plain ACS with the configured
+    candidate lists (cl = 32) at equal wall-clock on n = 2392 uniform: mean
+    best tour length over 10 seeds shorter, one-sided rank-sum p < 0.05.
+    The network's inference counts in the learned arm's time."""
+    import torch
+    from paper_1605_02669_amd import prior
+    P = torch.tensor(np.load(prior.DEFAULT_PARAMS), device="cuda")
+    res = prior.evaluate(P, sizes=(2392,), kinds=("uniform",), seeds=10, budget_s=0.5,
+                         log=print)["uniform_2392"]
+    assert res["learned_mean"] < res["plain_mean"], res
+    assert res["rank_sum_p"] < 0.05, res

@@ -1,0 +1,81 @@
+"""Solution quality of the asynchronous modes at the headline size.
+
+The asynchronous modes let ants read pheromone that other ants are updating
+(parity unpinned by design), so they are judged by the distribution of the
+best tour length over 20 seeds, beside the bit-exact synchronous mode
+(Sec. 3.1.2 and Sec. 4.1 of the paper compare the atomic ACS-GPU with the
+unsynchronised ACS-GPU-Alt this way).  The headline kernel hands its local
+updates to an updater wave, so an update lands a few steps after its
+crossing; its mean must stay within a stated band of the ant-issued
+(in-wave) path's in both asynchronous modes.
+"""
+from __future__ import annotations
+
+import sys
+
+import numpy as np
+import pytest
+
+from paper_1605_02669_amd import inputs
+
+pytestmark = pytest.mark.gpu
+
+SEEDS = 20
+ITERS = 100
+# The updater path may move the mean best length by at most this fraction
+# against the in-wave path.  It is the band the n = 198 check uses, where a
+# delay of a few steps is a far larger share of a tour.
+BAND = 0.025
+
+
+def _say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def acs():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1605_02669_amd import acs as mod
+    mod.load()
+    return mod
+
+
+def _run(acs, xy, mode, seeds, iters, **kw):
+    out = []
+    for s in range(seeds):
+        col = acs.Colony(xy, mode=mode, seed=s, **kw)
+        col.iterate(iters)
+        out.append(col.best()[1])
+        lnn = col.stats()["nn_length"]
+        col.close()
+    return np.array(out, dtype=np.float64), lnn
+
+
+def test_quality_distribution_n2392(acs):
+    from scipy.stats import mannwhitneyu
+    xy = inputs.uniform(2392)
+    arms = {
+        "sync": dict(mode=acs.ACS_SYNC),
+        "atomic_updater": dict(mode=acs.ACS_ASYNC_ATOMIC, update_path=2),
+        "atomic_inwave": dict(mode=acs.ACS_ASYNC_ATOMIC, update_path=1),
+        "alt_updater": dict(mode=acs.ACS_ASYNC_RACY, update_path=2),
+        "alt_inwave": dict(mode=acs.ACS_ASYNC_RACY, update_path=1),
+    }
+    res = {}
+    for name, kw in arms.items():
+        mode = kw.pop("mode")
+        res[name], lnn = _run(acs, xy, mode, SEEDS, ITERS, **kw)
+        r = res[name]
+        _say(f"{name}: mean {r.mean():.0f}, sd {r.std():.0f}, min {r.min():.0f}, "
+             f"max {r.max():.0f} ({100 * (r.mean() / lnn - 1):+.2f}% vs nearest neighbour)")
+    for a, b in (("atomic_updater", "atomic_inwave"), ("alt_updater", "alt_inwave"),
+                 ("atomic_updater", "sync"), ("alt_updater", "atomic_updater")):
+        p = mannwhitneyu(res[a], res[b]).pvalue
+        _say(f"{a} vs {b}: {100 * (res[a].mean() / res[b].mean() - 1):+.2f}%, rank-sum p={p:.3g}")
+    for r in res.values():
+        assert r.max() < lnn  # every run improves on the nearest-neighbour tour
+    for a, b in (("atomic_updater", "atomic_inwave"), ("alt_updater", "alt_inwave")):
+        assert abs(res[a].mean() / res[b].mean() - 1) < BAND, (a, b)
