@@ -93,11 +93,14 @@ typedef struct acs_params {
                              0: 64 for one instance, chosen by timing for a
                              batch.  Never changes a decision, only how many
                              ants share a wavefront. */
-  uint32_t update_path;  /* asynchronous dense, one ant per wavefront: 1 the
-                            ant wave issues its local updates itself; 2 (and
-                            0, the default) the ant waves hand them to one
+  uint32_t update_path;  /* asynchronous modes, 64 lanes per ant: 1 the ant
+                            wave issues its local updates itself; 2 (and 0,
+                            the default) the ant waves hand them to one
                             updater wavefront per workgroup through LDS, so
-                            an ant never waits for an atomic */
+                            an ant never waits for an atomic; 3 as 2 with
+                            two ants per wavefront whose steps interleave
+                            (dense memory, one instance; the selective
+                            memory runs 3 as 2) */
   uint32_t wait_limit;   /* polls after which a bounded device wait (grid
                             barrier, update ring) gives up; 0: the library's
                             own limits.  A wait that gives up makes the
@@ -232,6 +235,18 @@ int acs_batch_iterate(acs_batch_t *b, int32_t k);
  * timed).  The arrays hold `cap` entries; at most 4 are written. */
 int acs_batch_tuning(acs_batch_t *b, int32_t *chosen, int32_t *count, int32_t *lanes,
                      int32_t *updater, double *ms, int32_t cap);
+
+/* Multi-colony use of a batch (the model of Sec. 2: several colonies on one
+ * instance with a periodic exchange of the best solution found so far along
+ * a communication topology).  The batch's instances must be copies of one
+ * instance (equal n; ACS_E_INVALID otherwise), each colony drawing its own
+ * random numbers (params.instance + i).  From this call on, after every
+ * `period`-th iteration (period >= 1; 0 turns the exchange off) colony c
+ * takes the best-so-far tour and length of its source when that is strictly
+ * shorter than its own; the next global update (Eq. 4) deposits on it.
+ * topology 0: the source is the colony with the shortest best-so-far tour
+ * (lowest index among equals); topology 1: colony c - 1 (a ring). */
+int acs_batch_set_exchange(acs_batch_t *b, int32_t topology, int32_t period);
 
 /* Number of instances, construction steps of one iteration (sum of
  * m_i (n_i - 1)), whether the iteration runs as a graph (1) or as direct

@@ -93,6 +93,7 @@ def load() -> C.CDLL:
                                    C.POINTER(C.c_double)]
     lib.acs_batch_tuning.argtypes = [P, C.POINTER(i32), C.POINTER(i32), P, P, P, i32]
     lib.acs_batch_instance.argtypes = [P, i32, C.POINTER(P)]
+    lib.acs_batch_set_exchange.argtypes = [P, i32, i32]
     lib.acs_batch_best_tour.argtypes = [P, i32, P, C.POINTER(i64)]
     lib.acs_batch_destroy.argtypes = [P]
     lib.acs_batch_destroy.restype = None
@@ -191,6 +192,19 @@ def acs_destroy(h) -> None:
     load().acs_destroy(h)
 
 
+def make_params(m=0, cl=32, beta=2.0, q0=0.9, phi=0.1, rho=0.1, tau0=0.0, memory=ACS_DENSE,
+                spm_s=8, mode=ACS_SYNC, seed=0, instance=0, local_update_period=1,
+                lanes_per_ant=0, update_path=0, wait_limit=0) -> acs_params:
+    p = acs_default_params()
+    p.m, p.cl, p.beta, p.q0, p.phi, p.rho, p.tau0 = m, cl, beta, q0, phi, rho, tau0
+    p.memory, p.spm_s, p.mode, p.seed, p.instance = memory, spm_s, mode, seed, instance
+    p.local_update_period = local_update_period
+    p.lanes_per_ant = lanes_per_ant
+    p.update_path = update_path
+    p.wait_limit = wait_limit
+    return p
+
+
 class Colony:
     """One colony on one instance, owning its handle.
 
@@ -205,13 +219,10 @@ class Colony:
                  torch_memory=True):
         self.xy = np.ascontiguousarray(xy, dtype=np.float64).reshape(-1, 2)
         n = self.xy.shape[0]
-        p = acs_default_params()
-        p.m, p.cl, p.beta, p.q0, p.phi, p.rho, p.tau0 = m, cl, beta, q0, phi, rho, tau0
-        p.memory, p.spm_s, p.mode, p.seed, p.instance = memory, spm_s, mode, seed, instance
-        p.local_update_period = local_update_period
-        p.lanes_per_ant = lanes_per_ant
-        p.update_path = update_path
-        p.wait_limit = wait_limit
+        p = make_params(m=m, cl=cl, beta=beta, q0=q0, phi=phi, rho=rho, tau0=tau0, memory=memory,
+                        spm_s=spm_s, mode=mode, seed=seed, instance=instance,
+                        local_update_period=local_update_period, lanes_per_ant=lanes_per_ant,
+                        update_path=update_path, wait_limit=wait_limit)
         self._ws = None
         if torch_memory:
             import torch
@@ -348,6 +359,12 @@ class Batch:
         names = [f"{lanes[j]}{'u' if upd[j] else ''}" for j in range(cnt.value)]
         return dict(chosen=names[ch.value] if ch.value >= 0 else None,
                     candidates={names[j]: float(ms[j]) for j in range(cnt.value)})
+
+    def set_exchange(self, topology: int, period: int) -> None:
+        """Best-so-far exchange between the instances (colonies of one
+        instance) after every `period`-th iteration; topology 0 from the best
+        colony, 1 from colony c - 1."""
+        _check(load().acs_batch_set_exchange(self.h, topology, period))
 
     def handle(self, i: int):
         h = C.c_void_p()

@@ -48,6 +48,7 @@ size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
 struct Layout {
   size_t xy, dist, crec, cand, eta, tau, tau2, etad, rpos, ctau, gvis, fpre, flim, femax, fbound, bflags, spm, spm_tail, xnn, upd_rec, upd_nb, upd_next, upd_head, tours, lens,
       best, gstate, counters, sync, dmax, lnn, total;
+  size_t dist_rows;  // rows of the distance matrix `dist` holds at a time
 };
 
 constexpr int kEtaEntries = 65536;  // eta^beta for every 16-bit distance
@@ -65,7 +66,17 @@ Layout make_layout(int n, int m, int cl, int ldn, int memory, int s, int mode) {
     return at;
   };
   L.xy = take(sizeof(double) * 2 * (size_t)n);
-  L.dist = take(sizeof(uint16_t) * (size_t)n * ldn);
+  // dense memory: the whole distance matrix; the selective memory keeps none
+  // (Sec. 3.2: O(n s) pheromone memory) and builds its neighbour lists from
+  // chunks of rows placed where the tours go
+  const size_t tour_bytes = sizeof(int32_t) * (size_t)m * n;
+  if (memory == ACS_DENSE) {
+    L.dist_rows = (size_t)n;
+    L.dist = take(sizeof(uint16_t) * (size_t)n * ldn);
+  } else {
+    L.dist_rows = std::min<size_t>((size_t)n, std::max<size_t>(64, tour_bytes /
+                                                                     (sizeof(uint16_t) * ldn)));
+  }
   L.crec = take(sizeof(uint4) * (size_t)n * cl);
   L.cand = take(sizeof(int32_t) * (size_t)n * cl);
   L.eta = take(sizeof(float) * kEtaEntries);
@@ -92,7 +103,12 @@ Layout make_layout(int n, int m, int cl, int ldn, int memory, int s, int mode) {
     L.upd_head = take(sizeof(int32_t) * (size_t)n);
   }
   if (mode == ACS_SYNC) L.bflags = take(sizeof(uint64_t) * 16 * (size_t)((m + 15) / 16 + 1));
-  L.tours = take(sizeof(int32_t) * (size_t)m * n);
+  if (memory == ACS_DENSE) {
+    L.tours = take(tour_bytes);
+  } else {
+    L.tours = take(std::max(tour_bytes, sizeof(uint16_t) * L.dist_rows * ldn));
+    L.dist = L.tours;
+  }
   L.lens = take(sizeof(int64_t) * (size_t)m);
   L.best = take(sizeof(int32_t) * (size_t)n);
   L.gstate = take(sizeof(int64_t) * 4);
@@ -136,7 +152,7 @@ int check_params(int32_t n, const acs_params *p) {
   if (lpa != 0 && lpa != 64 &&
       ((p->mode != ACS_ASYNC_ATOMIC && p->mode != ACS_ASYNC_RACY) || p->memory != ACS_DENSE))
     return fail(ACS_E_UNSUPPORTED, "lanes_per_ant < 64 needs an asynchronous mode and dense memory");
-  if (p->update_path > 2) return fail(ACS_E_INVALID, "update_path = %u not in {0, 1, 2}",
+  if (p->update_path > 3) return fail(ACS_E_INVALID, "update_path = %u not in {0, 1, 2, 3}",
                                       p->update_path);
   return ACS_OK;
 }
@@ -166,6 +182,7 @@ struct acs_t {
   int construct_launches = 0;
   std::vector<hipEvent_t> ev;
   hipEvent_t ev_begin = nullptr, ev_end = nullptr;
+  bool timed = true;  // events around every construction (not for a fixed workspace)
 };
 
 namespace {
@@ -175,14 +192,25 @@ bool live(const acs_t *h) {
   return h && g_live.count(h);
 }
 
-void release(acs_t *h) {
-  if (!h) return;
-  if (h->stream) (void)hipStreamSynchronize(h->stream);
+// Waits for the handle's stream and frees what the handle owns (its stream,
+// events and workspace, where it created them).
+void release_resources(acs_t *h) {
+  // (a handle on the null stream has work queued once it has a workspace)
+  if (h->stream || h->ws) (void)hipStreamSynchronize(h->stream);
   for (auto e : h->ev) (void)hipEventDestroy(e);
+  h->ev.clear();
   if (h->ev_begin) (void)hipEventDestroy(h->ev_begin);
   if (h->ev_end) (void)hipEventDestroy(h->ev_end);
+  h->ev_begin = h->ev_end = nullptr;
   if (h->own_ws && h->ws) (void)hipFree(h->ws);
+  h->ws = nullptr;
   if (h->own_stream && h->stream) (void)hipStreamDestroy(h->stream);
+  h->stream = nullptr;
+}
+
+void release(acs_t *h) {
+  if (!h) return;
+  release_resources(h);
   delete h;
 }
 
@@ -196,20 +224,35 @@ int sync_and_check(acs_t *h) {
   return ACS_OK;
 }
 
-int build(acs_t *h, const double *xy) {
+int build(acs_t *h, const double *xy, float *eta_host) {
   const int n = h->n;
   HIP_TRY(hipMemcpyAsync(h->ws + h->L.xy, xy, sizeof(double) * 2 * n, hipMemcpyHostToDevice,
                          h->stream));
   HIP_TRY(hipMemsetAsync(h->ws + h->L.dmax, 0, sizeof(uint32_t), h->stream));
-  HIP_TRY(acs::launch_dist(h->dev, reinterpret_cast<uint32_t *>(h->ws + h->L.dmax), h->stream));
+  uint32_t *dmax_d = reinterpret_cast<uint32_t *>(h->ws + h->L.dmax);
+  const bool dense = h->p.memory == ACS_DENSE;
+  // dense: the whole matrix; selective memory: only the largest distance
+  HIP_TRY(acs::launch_dist(h->dev, dmax_d, 0, n, dense, h->stream));
   uint32_t dmax = 0;
-  HIP_TRY(hipMemcpyAsync(&dmax, h->ws + h->L.dmax, sizeof dmax, hipMemcpyDeviceToHost, h->stream));
+  HIP_TRY(hipMemcpyAsync(&dmax, dmax_d, sizeof dmax, hipMemcpyDeviceToHost, h->stream));
   HIP_TRY(hipStreamSynchronize(h->stream));
   if (dmax > 65535u)
     return fail(ACS_E_UNSUPPORTED, "largest distance %u exceeds 65535", dmax);
 
   int32_t *cand = reinterpret_cast<int32_t *>(h->ws + h->L.cand);
-  HIP_TRY(acs::launch_cand(h->dev, cand, h->stream));
+  if (dense) {
+    HIP_TRY(acs::launch_cand(h->dev, cand, 0, n, h->stream));
+  } else {
+    // the neighbour lists of the selective memory from chunks of distance
+    // rows, computed in the region the tours take later
+    const int rows = (int)h->L.dist_rows;
+    for (int r0 = 0; r0 < n; r0 += rows) {
+      const int nr = std::min(rows, n - r0);
+      HIP_TRY(acs::launch_dist(h->dev, dmax_d, r0, nr, true, h->stream));
+      HIP_TRY(acs::launch_cand(h->dev, cand, r0, nr, h->stream));
+    }
+    h->dev.dist = nullptr;
+  }
   int64_t *lnn_d = reinterpret_cast<int64_t *>(h->ws + h->L.lnn);
   HIP_TRY(acs::launch_nn_tour(h->dev, lnn_d, h->stream));
   HIP_TRY(hipMemcpyAsync(&h->lnn, lnn_d, sizeof(int64_t), hipMemcpyDeviceToHost, h->stream));
@@ -220,7 +263,13 @@ int build(acs_t *h, const double *xy) {
   // Host constants of the method (scalars and the per-distance eta table).
   const acs_params &p = h->p;
   h->tau0 = p.tau0 > 0.0 ? (float)p.tau0 : (float)(1.0 / ((double)n * (double)h->lnn));
-  std::vector<float> eta(kEtaEntries, 0.f);
+  std::vector<float> eta_vec;
+  if (!eta_host) {
+    eta_vec.resize(kEtaEntries);
+    eta_host = eta_vec.data();
+  }
+  float *eta = eta_host;
+  std::fill(eta, eta + kEtaEntries, 0.f);
   for (uint32_t d = 0; d <= dmax; ++d) eta[d] = eta_beta(p.beta, d);
   if (p.memory == ACS_SPM) {
     // the selective memory's fallback relies on tau0 * eta^beta(d) strictly
@@ -230,7 +279,7 @@ int build(acs_t *h, const double *xy) {
         return fail(ACS_E_UNSUPPORTED,
                     "tau0 * eta^beta is not strictly decreasing at d = %u (selective memory)", d);
   }
-  HIP_TRY(hipMemcpyAsync(h->ws + h->L.eta, eta.data(), sizeof(float) * kEtaEntries,
+  HIP_TRY(hipMemcpyAsync(h->ws + h->L.eta, eta, sizeof(float) * kEtaEntries,
                          hipMemcpyHostToDevice, h->stream));
   HIP_TRY(acs::launch_crec(h->dev, cand, h->tau0, h->stream));
   HIP_TRY(acs::launch_init_pheromone(h->dev, h->tau0, h->stream));
@@ -251,43 +300,15 @@ int build(acs_t *h, const double *xy) {
   return ACS_OK;
 }
 
-}  // namespace
-
-extern "C" {
-
-int acs_default_params(acs_params *p) {
-  if (!p) return fail(ACS_E_INVALID, "params is NULL");
-  std::memset(p, 0, sizeof *p);
-  p->struct_size = sizeof(acs_params);
-  p->m = 0;
-  p->cl = 32;
-  p->memory = ACS_DENSE;
-  p->spm_s = 8;
-  p->mode = ACS_SYNC;
-  p->local_update_period = 1;
-  p->beta = 2.0;
-  p->q0 = 0.9;
-  p->phi = 0.1;
-  p->rho = 0.1;
-  p->tau0 = 0.0;
-  p->seed = 0;
-  return ACS_OK;
-}
-
-int acs_workspace_bytes(int32_t n, const acs_params *p, size_t *out) {
-  int rc = check_params(n, p);
-  if (rc) return rc;
-  if (!out) return fail(ACS_E_INVALID, "out is NULL");
-  const int m = p->m ? (int)p->m : n;
-  const int cl = (int)std::min<uint32_t>(p->cl, (uint32_t)n - 1);
-  const int ldn = (int)align_up((size_t)n, 64);
-  *out = make_layout(n, m, cl, ldn, (int)p->memory, (int)p->spm_s, (int)p->mode).total;
-  return ACS_OK;
-}
-
-int acs_create(const double *coords_xy, int32_t n, const acs_params *p, acs_t **out) {
-  if (!out) return fail(ACS_E_INVALID, "out is NULL");
-  *out = nullptr;
+// Sets up the fresh handle *h for the instance.  With fixed_ws (device
+// memory of fixed_bytes the caller keeps) nothing is created: the handle
+// runs on params.stream (NULL: the null stream), untimed, in that memory.
+// Otherwise the stream, events and workspace are the handle's own (or the
+// caller's, from params).  eta_host: host buffer of kEtaEntries floats for
+// the eta^beta table, NULL for a temporary one.  On failure the caller
+// releases what the handle holds.
+int init_handle(acs_t *h, const double *coords_xy, int32_t n, const acs_params *p, char *fixed_ws,
+                size_t fixed_bytes, float *eta_host) {
   int rc = check_params(n, p);
   if (rc) return rc;
   if (!coords_xy) return fail(ACS_E_INVALID, "coords is NULL");
@@ -300,8 +321,6 @@ int acs_create(const double *coords_xy, int32_t n, const acs_params *p, acs_t **
   if (hipGetDeviceCount(&ndev) != hipSuccess || ndev < 1)
     return fail(ACS_E_DEVICE, "no HIP device available");
 
-  acs_t *h = new (std::nothrow) acs_t;
-  if (!h) return fail(ACS_E_NOMEM, "host allocation failed");
   h->p = *p;
   h->n = n;
   h->m = m;
@@ -309,34 +328,37 @@ int acs_create(const double *coords_xy, int32_t n, const acs_params *p, acs_t **
   h->ldn = (int)align_up((size_t)n, 64);
   h->L = make_layout(n, m, h->cl, h->ldn, (int)p->memory, (int)p->spm_s, (int)p->mode);
 
-  auto bail = [&](int code) {
-    std::string keep = g_err;
-    release(h);
-    g_err = keep;
-    return code;
-  };
-  if (p->stream) {
+  if (fixed_ws) {
+    // caller-owned device memory: no stream, event or workspace is created
+    if (fixed_bytes < h->L.total)
+      return fail(ACS_E_BUFSIZE, "workspace of %zu bytes < %zu needed", fixed_bytes, h->L.total);
     h->stream = reinterpret_cast<hipStream_t>(p->stream);
+    h->ws = fixed_ws;
+    h->timed = false;
   } else {
-    if (hipStreamCreateWithFlags(&h->stream, hipStreamNonBlocking) != hipSuccess)
-      return bail(fail(ACS_E_DEVICE, "stream creation failed"));
-    h->own_stream = true;
-  }
-  if (p->workspace) {
-    if (p->workspace_bytes < h->L.total)
-      return bail(fail(ACS_E_BUFSIZE, "workspace of %zu bytes < %zu needed", p->workspace_bytes,
-                       h->L.total));
-    h->ws = reinterpret_cast<char *>(p->workspace);
-  } else {
-    hipError_t e = hipMalloc(&h->ws, h->L.total);
-    if (e != hipSuccess) {
-      h->ws = nullptr;
-      return bail(fail(ACS_E_NOMEM, "hipMalloc(%zu): %s", h->L.total, hipGetErrorString(e)));
+    if (p->stream) {
+      h->stream = reinterpret_cast<hipStream_t>(p->stream);
+    } else {
+      if (hipStreamCreateWithFlags(&h->stream, hipStreamNonBlocking) != hipSuccess)
+        return fail(ACS_E_DEVICE, "stream creation failed");
+      h->own_stream = true;
     }
-    h->own_ws = true;
+    if (p->workspace) {
+      if (p->workspace_bytes < h->L.total)
+        return fail(ACS_E_BUFSIZE, "workspace of %zu bytes < %zu needed", p->workspace_bytes,
+                    h->L.total);
+      h->ws = reinterpret_cast<char *>(p->workspace);
+    } else {
+      hipError_t e = hipMalloc(&h->ws, h->L.total);
+      if (e != hipSuccess) {
+        h->ws = nullptr;
+        return fail(ACS_E_NOMEM, "hipMalloc(%zu): %s", h->L.total, hipGetErrorString(e));
+      }
+      h->own_ws = true;
+    }
+    if (hipEventCreate(&h->ev_begin) != hipSuccess || hipEventCreate(&h->ev_end) != hipSuccess)
+      return fail(ACS_E_DEVICE, "event creation failed");
   }
-  if (hipEventCreate(&h->ev_begin) != hipSuccess || hipEventCreate(&h->ev_end) != hipSuccess)
-    return bail(fail(ACS_E_DEVICE, "event creation failed"));
 
   acs::Dev &d = h->dev;
   char *w = h->ws;
@@ -387,45 +409,50 @@ int acs_create(const double *coords_xy, int32_t n, const acs_params *p, acs_t **
   if (p->mode == ACS_SYNC) {
     const int cap = acs::max_sync_ants(d, (int)p->memory);
     if (m > cap)
-      return bail(fail(ACS_E_UNSUPPORTED, "m = %d ants exceed the %d one synchronous launch holds",
-                       m, cap));
+      return fail(ACS_E_UNSUPPORTED, "m = %d ants exceed the %d one synchronous launch holds",
+                  m, cap);
   }
-  rc = build(h, coords_xy);
-  if (rc) return bail(rc);
-  {
-    std::lock_guard<std::mutex> g(g_live_mu);
-    g_live.insert(h);
-  }
-  *out = h;
-  return ACS_OK;
+  return build(h, coords_xy, eta_host);
 }
 
-int acs_iterate(acs_t *h, int32_t k) {
-  if (!live(h)) return fail(ACS_E_STATE, "invalid handle");
+// How the asynchronous kernels with one ant per wave apply local updates
+// (acs_internal.hpp, launch_construct): 0 the ant itself, 1 an updater wave
+// per block, 2 that with two ants per wave.
+int queued_kind(const acs_t *h) {
+  switch (h->p.update_path) {
+    case 1: return 0;
+    case 2: return 1;
+    case 3: return 2;
+    default: return 1;
+  }
+}
+
+// k iterations of Alg. 1 on the handle (see acs_iterate).
+int iterate_handle(acs_t *h, int32_t k) {
   if (k < 0) return fail(ACS_E_INVALID, "k < 0");
   if (k == 0) return ACS_OK;
-  while ((int)h->ev.size() < 2 * k) {
+  while (h->timed && (int)h->ev.size() < 2 * k) {
     hipEvent_t e;
     HIP_TRY(hipEventCreate(&e));
     h->ev.push_back(e);
   }
   // a bounded wait that ran out in an earlier call was reported by it
   HIP_TRY(hipMemsetAsync(h->ws + h->L.sync, 0, 2 * sizeof(uint32_t), h->stream));
-  HIP_TRY(hipEventRecord(h->ev_begin, h->stream));
+  if (h->timed) HIP_TRY(hipEventRecord(h->ev_begin, h->stream));
   for (int i = 0; i < k; ++i) {
     acs::Iter it = h->base;
     it.it = h->iter + (uint32_t)i;
-    HIP_TRY(hipEventRecord(h->ev[2 * i], h->stream));
+    if (h->timed) HIP_TRY(hipEventRecord(h->ev[2 * i], h->stream));
     HIP_TRY(acs::launch_construct(h->dev, it, (int)h->p.mode, (int)h->p.memory,
                                   h->p.lanes_per_ant ? (int)h->p.lanes_per_ant : 64,
-                                  h->p.update_path == 1 ? 0 : 1, h->stream));
-    HIP_TRY(hipEventRecord(h->ev[2 * i + 1], h->stream));
+                                  queued_kind(h), h->stream));
+    if (h->timed) HIP_TRY(hipEventRecord(h->ev[2 * i + 1], h->stream));
     HIP_TRY(acs::launch_best_global(h->dev, it, (int)h->p.memory, h->stream));
   }
-  HIP_TRY(hipEventRecord(h->ev_end, h->stream));
+  if (h->timed) HIP_TRY(hipEventRecord(h->ev_end, h->stream));
   int rc = sync_and_check(h);
   h->iter += (uint32_t)k;
-  if (rc) return rc;
+  if (rc || !h->timed) return rc;
   double cms = 0.0;
   for (int i = 0; i < k; ++i) {
     float ms = 0.f;
@@ -440,8 +467,8 @@ int acs_iterate(acs_t *h, int32_t k) {
   return ACS_OK;
 }
 
-int acs_best_tour(acs_t *h, int32_t *tour_out, int64_t *len_out) {
-  if (!live(h)) return fail(ACS_E_STATE, "invalid handle");
+// Best-so-far tour and length of the handle (see acs_best_tour).
+int best_handle(acs_t *h, int32_t *tour_out, int64_t *len_out) {
   int64_t g[3];
   HIP_TRY(hipStreamSynchronize(h->stream));
   HIP_TRY(hipMemcpy(g, h->ws + h->L.gstate, sizeof g, hipMemcpyDeviceToHost));
@@ -450,6 +477,70 @@ int acs_best_tour(acs_t *h, int32_t *tour_out, int64_t *len_out) {
   if (tour_out)
     HIP_TRY(hipMemcpy(tour_out, h->ws + h->L.best, sizeof(int32_t) * h->n, hipMemcpyDeviceToHost));
   return ACS_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int acs_default_params(acs_params *p) {
+  if (!p) return fail(ACS_E_INVALID, "params is NULL");
+  std::memset(p, 0, sizeof *p);
+  p->struct_size = sizeof(acs_params);
+  p->m = 0;
+  p->cl = 32;
+  p->memory = ACS_DENSE;
+  p->spm_s = 8;
+  p->mode = ACS_SYNC;
+  p->local_update_period = 1;
+  p->beta = 2.0;
+  p->q0 = 0.9;
+  p->phi = 0.1;
+  p->rho = 0.1;
+  p->tau0 = 0.0;
+  p->seed = 0;
+  return ACS_OK;
+}
+
+int acs_workspace_bytes(int32_t n, const acs_params *p, size_t *out) {
+  int rc = check_params(n, p);
+  if (rc) return rc;
+  if (!out) return fail(ACS_E_INVALID, "out is NULL");
+  const int m = p->m ? (int)p->m : n;
+  const int cl = (int)std::min<uint32_t>(p->cl, (uint32_t)n - 1);
+  const int ldn = (int)align_up((size_t)n, 64);
+  *out = make_layout(n, m, cl, ldn, (int)p->memory, (int)p->spm_s, (int)p->mode).total;
+  return ACS_OK;
+}
+
+int acs_create(const double *coords_xy, int32_t n, const acs_params *p, acs_t **out) {
+  if (!out) return fail(ACS_E_INVALID, "out is NULL");
+  *out = nullptr;
+  acs_t *h = new (std::nothrow) acs_t;
+  if (!h) return fail(ACS_E_NOMEM, "host allocation failed");
+  const int rc = init_handle(h, coords_xy, n, p, nullptr, 0, nullptr);
+  if (rc) {
+    std::string keep = g_err;
+    release(h);
+    g_err = keep;
+    return rc;
+  }
+  {
+    std::lock_guard<std::mutex> g(g_live_mu);
+    g_live.insert(h);
+  }
+  *out = h;
+  return ACS_OK;
+}
+
+int acs_iterate(acs_t *h, int32_t k) {
+  if (!live(h)) return fail(ACS_E_STATE, "invalid handle");
+  return iterate_handle(h, k);
+}
+
+int acs_best_tour(acs_t *h, int32_t *tour_out, int64_t *len_out) {
+  if (!live(h)) return fail(ACS_E_STATE, "invalid handle");
+  return best_handle(h, tour_out, len_out);
 }
 
 int acs_pheromone_snapshot(acs_t *h, float *out, size_t count) {
@@ -600,6 +691,11 @@ struct acs_batch_t {
   int tuning_step = 0; // iterations spent on tuning so far
   hipEvent_t e0 = nullptr, e1 = nullptr;
   double iterate_ms = 0.0;
+  // best-so-far exchange between the instances (colonies of one instance)
+  int xtopology = 0, xperiod = 0;
+  int64_t iters_done = 0;
+  int32_t *d_offer = nullptr;
+  int64_t *d_olen = nullptr;
 };
 
 namespace {
@@ -628,7 +724,7 @@ void release_batch(acs_batch_t *b) {
 
 struct BatchLayout {
   std::vector<size_t> off;
-  size_t devs, iters, items, flag, total;
+  size_t devs, iters, items, flag, offer, olen, total;
 };
 
 int batch_layout(const int32_t *n, int32_t count, const acs_params *p, BatchLayout *L,
@@ -655,6 +751,12 @@ int batch_layout(const int32_t *n, int32_t count, const acs_params *p, BatchLayo
   off = align_up(off + sizeof(int2) * (size_t)*nitems, 256);
   L->flag = off;
   off = align_up(off + sizeof(uint32_t), 256);
+  int nmax = 0;
+  for (int i = 0; i < count; ++i) nmax = std::max(nmax, (int)n[i]);
+  L->offer = off;
+  off = align_up(off + sizeof(int32_t) * (size_t)count * nmax, 256);
+  L->olen = off;
+  off = align_up(off + sizeof(int64_t) * (size_t)count, 256);
   L->total = off;
   return ACS_OK;
 }
@@ -665,6 +767,9 @@ int check_batch_args(const int32_t *n, int32_t count, const acs_params *p) {
   if (p->mode != ACS_ASYNC_ATOMIC && p->mode != ACS_ASYNC_RACY)
     return fail(ACS_E_UNSUPPORTED, "batches run in an asynchronous mode");
   if (p->memory != ACS_DENSE) return fail(ACS_E_UNSUPPORTED, "batches use the dense memory");
+  if (p->update_path == 3)
+    return fail(ACS_E_UNSUPPORTED, "batches run one ant per wave (update_path 3 is for one "
+                                   "instance)");
   for (int i = 0; i < count; ++i) {
     const int rc = check_params(n[i], p);
     if (rc) return rc;
@@ -782,6 +887,8 @@ int acs_batch_create(const double *const *coords, const int32_t *n, int32_t coun
   b->d_devs = reinterpret_cast<acs::Dev *>(b->ws + L.devs);
   b->d_iters = reinterpret_cast<acs::Iter *>(b->ws + L.iters);
   b->d_flag = reinterpret_cast<uint32_t *>(b->ws + L.flag);
+  b->d_offer = reinterpret_cast<int32_t *>(b->ws + L.offer);
+  b->d_olen = reinterpret_cast<int64_t *>(b->ws + L.olen);
   int2 *d_items = reinterpret_cast<int2 *>(b->ws + L.items);
   std::vector<int2> items;
   items.reserve((size_t)nitems);
@@ -843,6 +950,13 @@ int acs_batch_iterate(acs_batch_t *b, int32_t k) {
                                        b->nmax, b->clmax, b->mode, v.lanes, v.queued ? 1 : 0,
                                        b->d_flag, b->stream);
   };
+  // the best-so-far exchange after every xperiod-th iteration of the batch
+  auto exchange = [&]() -> hipError_t {
+    ++b->iters_done;
+    if (b->xperiod <= 0 || b->iters_done % b->xperiod != 0) return hipSuccess;
+    return acs::launch_exchange_batch(b->d_devs, b->count, b->nmax, b->xtopology, b->d_offer,
+                                      b->d_olen, b->stream);
+  };
   // cleared outside the captured graphs (a memset node is not captured)
   HIP_TRY(hipMemsetAsync(b->d_flag, 0, sizeof(uint32_t), b->stream));
   double total_ms = 0.0;
@@ -854,6 +968,7 @@ int acs_batch_iterate(acs_batch_t *b, int32_t k) {
     HIP_TRY(hipEventRecord(b->e0, b->stream));
     HIP_TRY(launch(b->var[(size_t)(v < 0 ? 0 : v)]));
     HIP_TRY(hipEventRecord(b->e1, b->stream));
+    HIP_TRY(exchange());
     HIP_TRY(hipStreamSynchronize(b->stream));
     float ms = 0.f;
     HIP_TRY(hipEventElapsedTime(&ms, b->e0, b->e1));
@@ -870,7 +985,10 @@ int acs_batch_iterate(acs_batch_t *b, int32_t k) {
   }
   if (i < k) {
     HIP_TRY(hipEventRecord(b->e0, b->stream));
-    for (; i < k; ++i) HIP_TRY(launch(b->var[(size_t)b->chosen]));
+    for (; i < k; ++i) {
+      HIP_TRY(launch(b->var[(size_t)b->chosen]));
+      HIP_TRY(exchange());
+    }
     HIP_TRY(hipEventRecord(b->e1, b->stream));
     HIP_TRY(hipStreamSynchronize(b->stream));
     float ms = 0.f;
@@ -890,6 +1008,21 @@ int acs_batch_iterate(acs_batch_t *b, int32_t k) {
   if (flag)
     return fail(ACS_E_DEVICE, "a bounded device wait was exhausted in a batch instance (flag %u: "
                               "1 grid barrier, 2 update ring); local updates may be missing", flag);
+  return ACS_OK;
+}
+
+int acs_batch_set_exchange(acs_batch_t *b, int32_t topology, int32_t period) {
+  if (!live_batch(b)) return fail(ACS_E_STATE, "invalid batch handle");
+  if (topology != 0 && topology != 1)
+    return fail(ACS_E_INVALID, "topology = %d not in {0, 1}", topology);
+  if (period < 0) return fail(ACS_E_INVALID, "period = %d < 0", period);
+  for (acs_t *h : b->inst)
+    if (h->n != b->inst[0]->n)
+      return fail(ACS_E_INVALID, "the exchange needs colonies of one instance (n %d and %d)",
+                  b->inst[0]->n, h->n);
+  b->xtopology = topology;
+  b->xperiod = period;
+  b->iters_done = 0;
   return ACS_OK;
 }
 

@@ -2,7 +2,10 @@
 // kernels (acs_kernels.hip).  Not installed; not part of the public ABI.
 #pragma once
 #include <hip/hip_runtime.h>
+#include <stddef.h>
 #include <stdint.h>
+
+struct acs_params;
 
 namespace acs {
 
@@ -16,7 +19,9 @@ struct Dev {
   int32_t n, m, cl, ldn;
   int32_t spm_s;
   const double *xy;        // n x 2
-  const uint16_t *dist;    // n x ldn exact integer distances
+  const uint16_t *dist;    // dense: n x ldn exact integer distances; selective
+                           //   memory: a chunk of rows while the handle is
+                           //   built, NULL after (distances then come from xy)
   const uint4 *crec;       // n x cl candidate records (see above)
   const float *eta_tab;    // eta^beta indexed by distance (dmax + 1)
   float *tau;              // dense: n x ldn, home of non-candidate entries
@@ -76,8 +81,13 @@ struct Iter {
 };
 
 // ---- instance preparation ----
-hipError_t launch_dist(const Dev &d, uint32_t *dmax, hipStream_t s);
-hipError_t launch_cand(const Dev &d, int32_t *cand_tmp, hipStream_t s);
+// Distances of rows r0 .. r0 + rows - 1 (stored from the start of d.dist
+// when `store`) and their largest value into *dmax.
+hipError_t launch_dist(const Dev &d, uint32_t *dmax, int r0, int rows, bool store,
+                       hipStream_t s);
+// Candidate lists (and, with the selective memory, the extended neighbour
+// lists) of cities r0 .. r0 + rows - 1 from the distance rows d.dist holds.
+hipError_t launch_cand(const Dev &d, int32_t *cand_tmp, int r0, int rows, hipStream_t s);
 hipError_t launch_nn_tour(const Dev &d, int64_t *lnn_out, hipStream_t s);
 hipError_t launch_crec(const Dev &d, const int32_t *cand_tmp, float tau0, hipStream_t s);
 hipError_t launch_init_pheromone(const Dev &d, float tau0, hipStream_t s);
@@ -87,8 +97,10 @@ hipError_t launch_init_pheromone(const Dev &d, float tau0, hipStream_t s);
 // persistent launch), 1 = asynchronous with atomic local updates, 2 =
 // asynchronous with plain stores, 3 = sequential within each step (one
 // block).  lanes: lanes per ant of the asynchronous
-// dense kernels (64, 32 or 16; at least cl).  queued: the one-ant-per-wave
-// dense kernel hands its local updates to an updater wave per block.
+// dense kernels (64, 32 or 16; at least cl).  queued (asynchronous, 64
+// lanes per ant): 0 the ant issues its own local updates; 1 it hands them to
+// an updater wave per block; 2 as 1, with two ants per wave whose steps
+// interleave (dense memory; the selective memory treats 2 as 1).
 hipError_t launch_construct(const Dev &d, const Iter &it, int mode, int memory, int lanes,
                             int queued, hipStream_t s);
 // Largest m a synchronous launch can keep resident for this instance.
@@ -111,6 +123,12 @@ constexpr int kBatchQAntsPerBlock = 4;
 hipError_t launch_batch_iteration(const Dev *devs, Iter *iters, const int2 *items, int nitems,
                                   int count, int nmax, int clmax, int mode, int lanes, int queued,
                                   uint32_t *flag, hipStream_t s);
+// Best-so-far exchange between `count` colonies of one instance (n cities)
+// held by a batch: topology 0 from the colony with the shortest best-so-far
+// tour, 1 from colony c - 1; offer (count x n) and olen (count) are device
+// scratch.
+hipError_t launch_exchange_batch(const Dev *devs, int count, int n, int topology,
+                                 int32_t *offer, int64_t *olen, hipStream_t s);
 // Learned edge prior (acs_prior.hip): parameter count and kernels.
 constexpr int kPriorParams = 4545;
 hipError_t launch_prior_forward(const float *P, const float *X, int rows, float *Z,

@@ -64,6 +64,11 @@ __device__ __forceinline__ uint32_t exact_dist(double xi, double yi, double xj,
   return d;
 }
 
+// d(i, j) from the coordinates (the selective memory keeps no n x n matrix).
+__device__ __forceinline__ uint32_t dist_xy(const Dev &D, int i, int j) {
+  return exact_dist(D.xy[2 * i], D.xy[2 * i + 1], D.xy[2 * j], D.xy[2 * j + 1]);
+}
+
 template <typename T>
 __device__ __forceinline__ T wave_min(T v) {
 #pragma unroll
@@ -261,25 +266,30 @@ __device__ __forceinline__ void grid_barrier_f(const Dev &D, uint64_t epoch) {
 // ---------------------------------------------------------------------------
 // Instance preparation kernels.
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(256) void k_dist(Dev D, uint32_t *dmax) {
+// Rows r0 .. r0 + rows - 1 of the distance matrix, stored (when `store`)
+// from the start of D.dist, and the largest distance into *dmax.
+__global__ __launch_bounds__(256) void k_dist(Dev D, uint32_t *dmax, int r0, int rows,
+                                              int store) {
   const int j = blockIdx.x * 64 + (threadIdx.x & 63);
-  const int i = blockIdx.y * 4 + (threadIdx.x >> 6);
+  const int r = blockIdx.y * 4 + (threadIdx.x >> 6);
+  const int i = r0 + r;
   uint32_t d = 0;
-  if (i < D.n && j < D.n && i != j)
-    d = exact_dist(D.xy[2 * i], D.xy[2 * i + 1], D.xy[2 * j], D.xy[2 * j + 1]);
+  if (r < rows && i < D.n && j < D.n && i != j) d = dist_xy(D, i, j);
   const uint32_t wmax = wave_max(d);
   if ((threadIdx.x & 63) == 0 && wmax) atomicMax(dmax, wmax);
-  if (i < D.n && j < D.ldn) const_cast<uint16_t *>(D.dist)[(size_t)i * D.ldn + j] =
-      (uint16_t)(d > 65535u ? 65535u : d);
+  if (store && r < rows && i < D.n && j < D.ldn)
+    const_cast<uint16_t *>(D.dist)[(size_t)r * D.ldn + j] = (uint16_t)(d > 65535u ? 65535u : d);
 }
 
 // Candidate list of city i: its cl nearest neighbours by (d, j), one wave
 // per city, extracted in increasing order of the key (d << 16 | j).
-__global__ __launch_bounds__(256) void k_cand(Dev D, int32_t *cand) {
+// Cities r0 .. r0 + rows - 1, whose distance rows D.dist holds from its start.
+__global__ __launch_bounds__(256) void k_cand(Dev D, int32_t *cand, int r0, int rows) {
   const int lane = threadIdx.x & 63;
-  const int i = blockIdx.x * 4 + (threadIdx.x >> 6);
-  if (i >= D.n) return;
-  const uint16_t *row = D.dist + (size_t)i * D.ldn;
+  const int r = blockIdx.x * 4 + (threadIdx.x >> 6);
+  const int i = r0 + r;
+  if (r >= rows || i >= D.n) return;
+  const uint16_t *row = D.dist + (size_t)r * D.ldn;
   int64_t last = -1;
   for (int k = 0; k < D.cl; ++k) {
     int64_t best = INT64_MAX;
@@ -296,11 +306,13 @@ __global__ __launch_bounds__(256) void k_cand(Dev D, int32_t *cand) {
 
 // The xl nearest cities of every city by (d, j) (selective memory only):
 // the fallback's nearest unvisited city is usually among them.
-__global__ __launch_bounds__(256) void k_xnn(Dev D) {
+// Cities r0 .. r0 + rows - 1, as k_cand.
+__global__ __launch_bounds__(256) void k_xnn(Dev D, int r0, int rows) {
   const int lane = threadIdx.x & 63;
-  const int i = blockIdx.x * 4 + (threadIdx.x >> 6);
-  if (i >= D.n) return;
-  const uint16_t *row = D.dist + (size_t)i * D.ldn;
+  const int r = blockIdx.x * 4 + (threadIdx.x >> 6);
+  const int i = r0 + r;
+  if (r >= rows || i >= D.n) return;
+  const uint16_t *row = D.dist + (size_t)r * D.ldn;
   int64_t last = -1;
   for (int k = 0; k < D.xl; ++k) {
     int64_t best = INT64_MAX;
@@ -367,11 +379,11 @@ __global__ __launch_bounds__(1024) void k_nn_tour(Dev D, int64_t *lnn) {
   int64_t L = 0;
   for (int step = 1; step < D.n; ++step) {
     __syncthreads();
-    const uint16_t *row = D.dist + (size_t)cur * D.ldn;
     int64_t best = INT64_MAX;
     for (int j = tid; j < D.n; j += 1024)
       if (!((vis[j >> 5] >> (j & 31)) & 1u)) {
-        const int64_t key = ((int64_t)row[j] << 16) | j;
+        const uint32_t dj = D.dist ? D.dist[(size_t)cur * D.ldn + j] : dist_xy(D, cur, j);
+        const int64_t key = ((int64_t)dj << 16) | j;
         best = key < best ? key : best;
       }
     best = wave_min(best);
@@ -384,7 +396,7 @@ __global__ __launch_bounds__(1024) void k_nn_tour(Dev D, int64_t *lnn) {
     if (tid == 0) vis[nxt >> 5] |= 1u << (nxt & 31);
     cur = nxt;
   }
-  if (tid == 0) *lnn = L + D.dist[(size_t)cur * D.ldn];
+  if (tid == 0) *lnn = L + (D.dist ? D.dist[(size_t)cur * D.ldn] : dist_xy(D, cur, 0));
 }
 
 // Candidate records with the initial pheromone tau0 in the last word.
@@ -393,7 +405,7 @@ __global__ __launch_bounds__(256) void k_crec(Dev D, const int32_t *cand, float 
   if (e >= D.n * D.cl) return;
   const int i = e / D.cl;
   const uint32_t c = (uint32_t)cand[e];
-  const uint32_t d = D.dist[(size_t)i * D.ldn + c];
+  const uint32_t d = dist_xy(D, i, (int)c);
   const_cast<uint4 *>(D.crec)[e] =
       make_uint4(c, d, __float_as_uint(D.eta_tab[d]), __float_as_uint(tau0));
 }
@@ -1267,14 +1279,21 @@ __device__ __forceinline__ uint32_t apply_entries(const Dev &D, const Iter &A, u
   return 0;
 }
 
+template <bool ATOMIC>
+__device__ __forceinline__ uint32_t spm_apply_entries(const Dev &D, const Iter &A, uint4 e,
+                                                      uint32_t &hits, uint32_t &misses);
+
 // Hands the entries of steps [g0, g1) (lanes g0 - t0 .. g1 - t0 - 1 of `e`)
 // to the updater, or, once the updater has stopped draining, applies them in
 // place.  `head` (= g0 on entry), `tail` (last tail seen) and `direct` are
-// the wave's own.  Returns this lane's retries.
-template <bool ATOMIC>
+// the wave's own.  SPM: the entries are the selective memory's (see
+// spm_apply_entries; hits and misses count its updates).  Returns this
+// lane's retries.
+template <bool ATOMIC, bool SPM = false>
 __device__ __forceinline__ uint32_t group_push(const Dev &D, const Iter &A, const QRing &q, int w,
                                                uint32_t &head, uint32_t &tail, bool &direct,
-                                               int lane, uint4 e, int t0, int g1) {
+                                               int lane, uint4 e, int t0, int g1,
+                                               uint32_t &hits, uint32_t &misses) {
   const bool mine = lane + t0 >= (int)head && lane + t0 < g1;
   if (!direct && (uint32_t)g1 - tail > (uint32_t)kQRing) {
     uint32_t spins = 0;
@@ -1292,7 +1311,9 @@ __device__ __forceinline__ uint32_t group_push(const Dev &D, const Iter &A, cons
   }
   if (direct) {
     head = (uint32_t)g1;
-    return apply_entries<ATOMIC>(D, A, mine ? e : make_uint4(kNoEntry, 0u, 0u, 0u), lane);
+    const uint4 own = mine ? e : make_uint4(kNoEntry, 0u, 0u, 0u);
+    if (SPM) return spm_apply_entries<ATOMIC>(D, A, own, hits, misses);
+    return apply_entries<ATOMIC>(D, A, own, lane);
   }
   if (mine) q.ent[(size_t)w * kQRing + ((lane + t0) & (kQRing - 1))] = e;
   head = (uint32_t)g1;
@@ -1307,14 +1328,14 @@ __device__ __forceinline__ uint32_t group_push(const Dev &D, const Iter &A, cons
 // from its tail), and applies them together, so the updates of different
 // rings share their memory round trips.  With nothing pending it sleeps, so
 // it takes few issue slots from the ant waves that share its SIMD.
-template <bool ATOMIC>
+template <bool ATOMIC, bool SPM = false, int NR = kQAnts>
 __device__ __forceinline__ void ring_updater(const Dev &D, const Iter &A, const QRing &q,
                                              int lane, int na) {
   static_assert((kQRing & (kQRing - 1)) == 0 && kQRing >= 64 + kQGroup, "ring size");
-  uint32_t tl[kQAnts];  // the updater's own tails (wave-uniform)
+  uint32_t tl[NR];  // the updater's own tails (wave-uniform)
 #pragma unroll
-  for (int w = 0; w < kQAnts; ++w) tl[w] = 0;
-  uint32_t retries = 0, idle = 0;
+  for (int w = 0; w < NR; ++w) tl[w] = 0;
+  uint32_t retries = 0, idle = 0, hits = 0, misses = 0;
   while (true) {
     // read `done` before the heads: an ant wave publishes its last head
     // before it counts itself done
@@ -1323,7 +1344,7 @@ __device__ __forceinline__ void ring_updater(const Dev &D, const Iter &A, const 
     uint32_t taken = 0;  // lanes given an entry so far
     uint4 e = make_uint4(kNoEntry, 0u, 0u, 0u);
 #pragma unroll
-    for (int w = 0; w < kQAnts; ++w) {
+    for (int w = 0; w < NR; ++w) {
       if (w >= na) break;
       const uint32_t h = (uint32_t)uni((int)lds_ld(q.head + w));
       const uint32_t c = min(h - tl[w], 64u - taken);
@@ -1335,9 +1356,12 @@ __device__ __forceinline__ void ring_updater(const Dev &D, const Iter &A, const 
     if (taken) {
       __atomic_signal_fence(__ATOMIC_SEQ_CST);
 #pragma unroll
-      for (int w = 0; w < kQAnts; ++w)
+      for (int w = 0; w < NR; ++w)
         if (w < na && lane == 0) lds_st(q.tail + w, tl[w]);
-      retries += apply_entries<ATOMIC>(D, A, e, lane);
+      if (SPM)
+        retries += spm_apply_entries<ATOMIC>(D, A, e, hits, misses);
+      else
+        retries += apply_entries<ATOMIC>(D, A, e, lane);
       idle = 0;
       continue;
     }
@@ -1350,6 +1374,14 @@ __device__ __forceinline__ void ring_updater(const Dev &D, const Iter &A, const 
     }
   }
   if (retries) atomicAdd(&D.counters[6], (unsigned long long)retries);
+  if (SPM) {
+    hits = (uint32_t)uni((int)wave_sum_u(hits));
+    misses = (uint32_t)uni((int)wave_sum_u(misses));
+    if (lane == 0 && (hits | misses)) {
+      atomicAdd(&D.counters[3], (unsigned long long)hits);
+      atomicAdd(&D.counters[4], (unsigned long long)misses);
+    }
+  }
 }
 
 // ---------------------------------------------------------------------------
@@ -1390,7 +1422,7 @@ __device__ __forceinline__ void ant_queued(const Dev &D, const Iter &A, int ant,
   if (lane == 0) vis[start >> 5] |= 1u << (start & 31);
   uint4 rec = load_rec(start);
 
-  uint32_t qhead = 0, qtail = 0, c_retry = 0, c_roul = 0, c_fb = 0;
+  uint32_t qhead = 0, qtail = 0, c_retry = 0, c_roul = 0, c_fb = 0, unused = 0;
   bool qdirect = false;
   uint64_t c_fbu = 0;
   int64_t len = 0;
@@ -1466,7 +1498,8 @@ __device__ __forceinline__ void ant_queued(const Dev &D, const Iter &A, int ant,
         clen += d;
         cur = next;
       }
-      c_retry += group_push<ATOMIC>(D, A, q, qw, qhead, qtail, qdirect, lane, e, t0, g1);
+      c_retry += group_push<ATOMIC>(D, A, q, qw, qhead, qtail, qdirect, lane, e, t0, g1, unused,
+                                    unused);
       g0 = g1;
     }
     len += clen;
@@ -1480,7 +1513,8 @@ __device__ __forceinline__ void ant_queued(const Dev &D, const Iter &A, int ant,
     const uint32_t x = rdlane(__float_as_uint(tau_load(qhome(D, cur, start, k1))), 0);
     const uint4 ce =
         make_uint4((uint32_t)cur | ((uint32_t)start << 16), (uint32_t)k1, x, (uint32_t)k2);
-    c_retry += group_push<ATOMIC>(D, A, q, qw, qhead, qtail, qdirect, lane, ce, n, n + 1);
+    c_retry += group_push<ATOMIC>(D, A, q, qw, qhead, qtail, qdirect, lane, ce, n, n + 1, unused,
+                                  unused);
     len += D.dist[(size_t)cur * D.ldn + start];
   }
   c_retry = (uint32_t)uni((int)wave_sum_u(c_retry));
@@ -1519,6 +1553,208 @@ __global__ __launch_bounds__(64 * (kQAnts + 1)) void k_construct_async_dense_q(D
   if (ant < D.m) ant_queued<ATOMIC, HALF>(D, A, ant, vis, lane, q, wv);
   __atomic_signal_fence(__ATOMIC_SEQ_CST);
   if (lane == 0) atomicAdd(&qdone, 1u);
+}
+
+// ---------------------------------------------------------------------------
+// Two ants per wave, their steps interleaved.  Each step of an ant is a
+// dependent chain: the record of the city it moves to is loaded only once
+// the city is chosen, and the choice takes tens of dependent instructions.
+// Here one wave carries two ants (each with all 64 lanes, decisions still
+// wave-uniform) and alternates between them: while the record load of one
+// ant is in flight the wave computes the other ant's step, so the two chains
+// hide each other's memory latency without twice the waves competing for the
+// SIMD.  Each ant keeps its own ring; the step itself is ant_queued's.
+// ---------------------------------------------------------------------------
+struct QAnt {
+  uint4 rec;        // lane k: candidate k's record (index, d, eta^beta, live tau)
+  uint4 draws;      // Philox words of the current 64 steps (lane = step % 64)
+  uint4 e;          // lane t % 64: the crossing of step t, for the updater
+  uint32_t *vis;    // visited bitmap (LDS)
+  int ant, start, cur, tb, qw;
+  uint32_t qhead, qtail, clen, c_retry, c_roul, c_fb;
+  uint64_t c_fbu;
+  int64_t len;
+  bool qdirect;
+};
+
+template <bool HALF>
+__device__ __forceinline__ void qant_step(const Dev &D, const Iter &A, QAnt &s, int t, int t0,
+                                          int lane, int lu, uint64_t clmask, int dumw,
+                                          __amdgpu_buffer_rsrc_t crs, __amdgpu_buffer_rsrc_t trs,
+                                          int koff, int rowb) {
+  const int n = D.n, cl = D.cl;
+  const uint4 rec = s.rec;
+  const uint32_t word = s.vis[rec.x >> 5];
+  const bool unv = !((word >> (rec.x & 31)) & 1u);
+  const uint64_t umask = __builtin_amdgcn_ballot_w64(unv) & clmask;
+  int next, k;
+  uint32_t d, tv;
+  if (umask == 0) {
+    const Pick p = fallback_dense<false>(D, s.vis, s.cur, lane);
+    next = p.next;
+    k = -1;
+    d = p.d;
+    tv = __float_as_uint(p.tval);
+    ++s.c_fb;
+    s.c_fbu += (uint64_t)(n - t);
+  } else {
+    const float w = unv ? __uint_as_float(rec.w) * __uint_as_float(rec.z) : 0.f;
+    if ((rdlane(s.draws.x, t & 63) >> 8) < A.q0_24) {
+      const uint32_t wb = __float_as_uint(w);
+      const uint32_t mx = HALF ? half_umax_u(wb) : wave_umax_u(wb);
+      k = (int)__builtin_ctzll(__builtin_amdgcn_ballot_w64(wb == mx) & umask);
+    } else {
+      float P = w;
+      for (int off = 1; off < cl; off <<= 1) {
+        const float o = __shfl_up(P, off, 64);
+        if (lane >= off) P = P + o;
+      }
+      const float total = __uint_as_float(rdlane(__float_as_uint(P), cl - 1));
+      const float r = ((float)(rdlane(s.draws.y, t & 63) >> 8) * 0x1p-24f) * total;
+      const uint64_t sel = __builtin_amdgcn_ballot_w64(P > r) & umask;
+      k = sel ? (int)__builtin_ctzll(sel) : 63 - (int)__builtin_clzll(umask);
+      ++s.c_roul;
+    }
+    next = (int)rdlane(rec.x, k);
+    d = rdlane(rec.y, k);
+    tv = rdlane(rec.w, k);
+  }
+  __hip_atomic_fetch_or(s.vis + (lane == 0 ? (next >> 5) : dumw),
+                        lane == 0 ? 1u << (next & 31) : 0u, __ATOMIC_RELAXED,
+                        __HIP_MEMORY_SCOPE_WORKGROUP);
+  {
+    const auto r = __builtin_amdgcn_raw_buffer_load_b128(crs, koff, next * rowb, 0);
+    const uint32_t tt = __builtin_amdgcn_raw_buffer_load_b32(trs, koff >> 2, next * cl * 4, 0);
+    s.rec = make_uint4(r[0], r[1], r[2], tt);
+  }
+  const int lt = lane + t0;
+  s.tb = lt == t ? next : s.tb;
+  if (lu == t)
+    s.e = make_uint4((uint32_t)s.cur | ((uint32_t)next << 16), (uint32_t)k, tv,
+                     (uint32_t)(k >= 0 ? -2 : -3));
+  s.clen += d;
+  s.cur = next;
+}
+
+template <bool ATOMIC, bool HALF>
+__device__ __forceinline__ void ants_queued2(const Dev &D, const Iter &A, int antA, int antB,
+                                             uint32_t *visA, uint32_t *visB, int lane,
+                                             const QRing &q, int qwA, int qwB) {
+  const int n = D.n, cl = D.cl;
+  const int W = (n + 31) >> 5;
+  // A wave with one ant (odd m) runs a silent copy of it as its second ant,
+  // so both ants' loads are issued on every path and the wait for one ant's
+  // record never has to cover the other's: the copy hands over no update
+  // and writes no result.
+  const bool two = antB < D.m;  // wave-uniform
+  if (!two) antB = antA;
+  const uint64_t clmask = cl >= 64 ? ~0ull : (1ull << cl) - 1;
+  const int dumw = lane % W;
+  const int koff = (lane < cl ? lane : cl - 1) * 16;
+  const int rowb = cl * 16;
+  const __amdgpu_buffer_rsrc_t crs =
+      __builtin_amdgcn_make_buffer_rsrc(const_cast<uint4 *>(D.crec), 0, n * rowb, kBufWord3);
+  const __amdgpu_buffer_rsrc_t trs =
+      __builtin_amdgcn_make_buffer_rsrc(D.ctau, 0, n * cl * 4, kBufWord3);
+  auto init = [&](QAnt &s, int ant, uint32_t *vis, int qw) {
+    s.ant = ant;
+    s.vis = vis;
+    s.qw = qw;
+    for (int w = lane; w < W; w += 64) vis[w] = 0u;
+    s.draws = philox_batch(A, ant, 0, lane);
+    s.start = (int)__umulhi(rdlane(s.draws.z, 0), (uint32_t)n);
+    if (lane == 0) vis[s.start >> 5] |= 1u << (s.start & 31);
+    const auto r = __builtin_amdgcn_raw_buffer_load_b128(crs, koff, s.start * rowb, 0);
+    const uint32_t tt = __builtin_amdgcn_raw_buffer_load_b32(trs, koff >> 2, s.start * cl * 4, 0);
+    s.rec = make_uint4(r[0], r[1], r[2], tt);
+    s.cur = s.start;
+    s.qhead = s.qtail = s.c_retry = s.c_roul = s.c_fb = 0;
+    s.qdirect = false;
+    s.c_fbu = 0;
+    s.len = 0;
+  };
+  QAnt a{}, b{};
+  init(a, antA, visA, qwA);
+  init(b, antB, visB, qwB);
+  uint32_t unused = 0;
+  for (int t0 = 0; t0 < n; t0 += 64) {
+    if (t0 > 0) {
+      a.draws = philox_batch(A, antA, t0, lane);
+      b.draws = philox_batch(A, antB, t0, lane);
+    }
+    const int lt = lane + t0;
+    const int lu = lt % (int)A.lperiod == 0 ? lt : -1;
+    const int lub = two ? lu : -1;  // the silent copy notes no crossing
+    a.e = b.e = make_uint4(kNoEntry, 0u, 0u, 0u);
+    a.tb = a.start;
+    b.tb = b.start;
+    a.clen = b.clen = 0;
+    const int tend = min(t0 + 64, n);
+    for (int g0 = t0 > 0 ? t0 : 1; g0 < tend;) {
+      const int g1 = min((g0 & ~(kQGroup - 1)) + kQGroup, tend);
+      for (int t = g0; t < g1; ++t) {
+        qant_step<HALF>(D, A, a, t, t0, lane, lu, clmask, dumw, crs, trs, koff, rowb);
+        qant_step<HALF>(D, A, b, t, t0, lane, lub, clmask, dumw, crs, trs, koff, rowb);
+      }
+      a.c_retry += group_push<ATOMIC>(D, A, q, a.qw, a.qhead, a.qtail, a.qdirect, lane, a.e, t0,
+                                      g1, unused, unused);
+      b.c_retry += group_push<ATOMIC>(D, A, q, b.qw, b.qhead, b.qtail, b.qdirect, lane, b.e, t0,
+                                      g1, unused, unused);
+      g0 = g1;
+    }
+    a.len += a.clen;
+    b.len += b.clen;
+    if (lane < tend - t0) D.tours[(size_t)antA * n + lt] = a.tb;
+    if (two && lane < tend - t0) D.tours[(size_t)antB * n + lt] = b.tb;
+  }
+  auto finish = [&](QAnt &s) {
+    const int k1 = cand_pos(D, s.cur, s.start, lane);
+    const int k2 = cand_pos(D, s.start, s.cur, lane);
+    const uint32_t x = rdlane(__float_as_uint(tau_load(qhome(D, s.cur, s.start, k1))), 0);
+    const uint4 ce = make_uint4((uint32_t)s.cur | ((uint32_t)s.start << 16), (uint32_t)k1, x,
+                                (uint32_t)k2);
+    s.c_retry += group_push<ATOMIC>(D, A, q, s.qw, s.qhead, s.qtail, s.qdirect, lane, ce, n,
+                                    n + 1, unused, unused);
+    s.len += D.dist[(size_t)s.cur * D.ldn + s.start];
+    const uint32_t cr = (uint32_t)uni((int)wave_sum_u(s.c_retry));
+    if (lane == 0) {
+      D.lens[s.ant] = s.len;
+      add_counters(D, (uint32_t)(n - 1) - s.c_roul - s.c_fb, s.c_roul, s.c_fb, s.c_fbu, cr);
+    }
+  };
+  finish(a);
+  if (two) finish(b);
+}
+
+// One instance, two ants per wave, updates through the block's updater
+// wave: waves 0..np-1 carry ants 2 (blockIdx.x * np + wave) and that + 1
+// (rings 2 wave and 2 wave + 1), wave np applies the entries.  Dynamic LDS:
+// the 2 np rings, then the 2 np visited bitmaps.
+template <bool ATOMIC, bool HALF>
+__global__ __launch_bounds__(64 * (kQAnts + 1)) void k_construct_async_dense_q2(Dev D, Iter A) {
+  extern __shared__ uint4 qsm[];
+  __shared__ uint32_t qhd[2 * kQAnts], qtl[2 * kQAnts], qdone;
+  const int lane = threadIdx.x & 63;
+  const int wv = threadIdx.x >> 6;
+  const int np = (int)(blockDim.x >> 6) - 1;
+  if (threadIdx.x < 2 * kQAnts) {
+    qhd[threadIdx.x] = 0;
+    qtl[threadIdx.x] = 0;
+  }
+  if (threadIdx.x == 0) qdone = 0;
+  __syncthreads();
+  const QRing q{qsm, qhd, qtl, &qdone};
+  if (wv == np) {
+    ring_updater<ATOMIC, false, 2 * kQAnts>(D, A, q, lane, 2 * np);
+    return;
+  }
+  const int W = (D.n + 31) >> 5;
+  uint32_t *vis = reinterpret_cast<uint32_t *>(qsm + (size_t)2 * np * kQRing) + 2 * wv * W;
+  const int antA = uni(2 * (blockIdx.x * np + wv));
+  if (antA < D.m) ants_queued2<ATOMIC, HALF>(D, A, antA, antA + 1, vis, vis + W, lane, q, 2 * wv,
+                                             2 * wv + 1);
+  __atomic_signal_fence(__ATOMIC_SEQ_CST);
+  if (lane == 0) atomicAdd(&qdone, 2u);
 }
 
 // Many instances in one launch, updates through each block's updater wave:
@@ -1905,7 +2141,6 @@ __device__ __forceinline__ Cand weigh_spm(const Dev &D, const uint32_t *vis, int
 __device__ __forceinline__ Pick fallback_spm(const Dev &D, uint32_t *vis, int cur, int lane,
                                              uint2 pr, float tau0) {
   const int n = D.n, s = D.spm_s;
-  const uint16_t *drow = D.dist + (size_t)cur * D.ldn;
   const bool in_rec = lane < s && pr.x != kNone;
   const uint32_t rj = in_rec ? pr.x : 0u;
   const bool rec_unv = in_rec && !((vis[rj >> 5] >> (rj & 31)) & 1u);
@@ -1921,21 +2156,28 @@ __device__ __forceinline__ Pick fallback_spm(const Dev &D, uint32_t *vis, int cu
     const uint64_t ok = __ballot(idx < D.xl && !((vis[j >> 5] >> (j & 31)) & 1u));
     if (ok) {
       const uint32_t jj = rdlane(j, (int)__ffsll((unsigned long long)ok) - 1);
-      key = ((uint32_t)drow[jj] << 16) | jj;
+      key = (dist_xy(D, cur, (int)jj) << 16) | jj;
       break;
     }
   }
   if (key == kNone) {
-    // every listed city is taken: scan the whole row
-#pragma unroll 4
-    for (int j0 = 4 * lane; j0 < n; j0 += 256) {
-      const ushort4 dv = *reinterpret_cast<const ushort4 *>(drow + j0);
-      const uint32_t dq[4] = {dv.x, dv.y, dv.z, dv.w};
-      uint32_t bits = (vis[j0 >> 5] >> (j0 & 31)) & 0xfu;
-      if (j0 + 4 > n) bits |= (0xfu << (n - j0)) & 0xfu;
+    // every listed city is taken: scan every unvisited city, its distance
+    // from the coordinates.  A lane takes eight consecutive cities (one byte
+    // of the bitmap) per round and loads their coordinates together, so a
+    // round costs one load latency; a byte of visited cities loads nothing.
+    const double xc = D.xy[2 * cur], yc = D.xy[2 * cur + 1];
+    const double2 *xy2 = reinterpret_cast<const double2 *>(D.xy);
+    for (int j0 = 8 * lane; j0 < n; j0 += 512) {
+      uint32_t free8 = ~(vis[j0 >> 5] >> (j0 & 31)) & 0xffu;
+      if (j0 + 8 > n) free8 &= (1u << (n - j0)) - 1u;
+      if (!free8) continue;
+      double2 c[8];
 #pragma unroll
-      for (int q = 0; q < 4; ++q)
-        if (!((bits >> q) & 1u)) key = min(key, (dq[q] << 16) | (uint32_t)(j0 + q));
+      for (int q = 0; q < 8; ++q) c[q] = xy2[min(j0 + q, n - 1)];
+#pragma unroll
+      for (int q = 0; q < 8; ++q)
+        if ((free8 >> q) & 1u)
+          key = min(key, (exact_dist(xc, yc, c[q].x, c[q].y) << 16) | (uint32_t)(j0 + q));
     }
     key = wave_umin_u(key);
   }
@@ -1944,7 +2186,7 @@ __device__ __forceinline__ Pick fallback_spm(const Dev &D, uint32_t *vis, int cu
   uint32_t rd = 0;
   float rv = 0.f;
   if (rec_unv) {
-    rd = drow[rj];
+    rd = dist_xy(D, cur, (int)rj);
     rv = __uint_as_float(pr.y) * D.eta_tab[rd];
   }
   const bool off = key != kNone;
@@ -2123,7 +2365,7 @@ __global__ __launch_bounds__(1024) void k_construct_sync_spm(Dev D, Iter A) {
       len += p.d;
       next = p.next;
     }
-    if (active && t == n) len += D.dist[(size_t)cur * D.ldn + start];
+    if (active && t == n) len += dist_xy(D, cur, start);
     // t < n: the step's crossing (every lperiod-th step); t == n: the closing edge
     if (t == n || t % A.lperiod == 0) {
       bool lead = false;
@@ -2379,7 +2621,7 @@ __global__ __launch_bounds__(256) void k_construct_async_spm(Dev D, Iter A) {
       spm_racy_issue(D, q1, t1, start, cur, lane, 0, al, bl, tau0, hits, misses);
     }
   }
-  len += D.dist[(size_t)cur * D.ldn + start];
+  len += dist_xy(D, cur, start);
   c_retry = (uint32_t)uni((int)(rdlane(c_retry, 0) + rdlane(c_retry, 1)));
   hits = (uint32_t)uni((int)(rdlane(hits, 0) + rdlane(hits, 1)));
   misses = (uint32_t)uni((int)(rdlane(misses, 0) + rdlane(misses, 1)));
@@ -2390,6 +2632,196 @@ __global__ __launch_bounds__(256) void k_construct_async_spm(Dev D, Iter A) {
                  (uint32_t)(c_kind >> 42) & m21, c_fbu, c_retry);
     add_spm_counters(D, hits, misses);
   }
+}
+
+// ---------------------------------------------------------------------------
+// Asynchronous construction with the selective memory, updates through the
+// block's updater wave (as the dense k_construct_async_dense_q): the ant
+// wave issues no update, so its record loads never wait behind an atomic.
+// Entry of city r: {r, nbA, nbB, 0}: Alg. 3 on r's record for neighbour nbA
+// (the edge that reached r), then for nbB (the edge that left it); kNone
+// marks an edge without an update (local-update period).  One entry per
+// visited city keeps the two updates of a record in their order, and the
+// updates of different entries concern different records of one ant, so an
+// ant's updates land in the order Alg. 1 applies them.  The start city's
+// entry (its departure, then the closing edge) goes last.
+// ---------------------------------------------------------------------------
+template <bool ATOMIC>
+__device__ __forceinline__ uint32_t spm_apply_entries(const Dev &D, const Iter &A, uint4 e,
+                                                      uint32_t &hits, uint32_t &misses) {
+  if (e.x == kNoEntry) return 0;
+  const int r = (int)e.x, s = D.spm_s;
+  uint2 *rec = D.spm + (size_t)r * s;
+  const float a = A.a_loc, b = A.b_loc;
+  const uint32_t ins = __float_as_uint(fmaf(a, A.tau0, b));  // a new trail: the map of tau0
+  uint32_t retries = 0;
+  for (int u = 0; u < 2; ++u) {
+    const uint32_t nb = u == 0 ? e.y : e.z;
+    if (nb == kNone) continue;
+    while (true) {
+      // the record as it is now; the first slot holding nb is its trail
+      int found = -1;
+      uint2 cur = make_uint2(0u, 0u);
+      for (int i = 0; i < s; ++i) {
+        const uint2 x = pair_load_coherent(rec + i);
+        if (found < 0 && x.x == nb) {
+          found = i;
+          cur = x;
+        }
+      }
+      if (found < 0) {
+        // miss: the slot after the most recently added one
+        uint32_t t;
+        if (ATOMIC) {
+          t = atomicAdd(D.spm_tail + r, 1u);
+        } else {
+          t = __hip_atomic_load(D.spm_tail + r, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+          __hip_atomic_store(D.spm_tail + r, t + 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        }
+        pair_store_coherent(rec + (t + 1u) % (uint32_t)s, make_uint2(nb, ins));
+        ++misses;
+        break;
+      }
+      const uint2 nw = make_uint2(nb, __float_as_uint(fmaf(a, __uint_as_float(cur.y), b)));
+      if (!ATOMIC) {
+        pair_store_coherent(rec + found, nw);
+        ++hits;
+        break;
+      }
+      if (atomicCAS(reinterpret_cast<unsigned long long *>(rec + found), pack(cur), pack(nw)) ==
+          pack(cur)) {
+        ++hits;
+        break;
+      }
+      ++retries;  // the pair changed meanwhile: look again
+    }
+  }
+  return retries;
+}
+
+template <bool ATOMIC>
+__device__ __forceinline__ void spm_ant_queued(const Dev &D, const Iter &A, int ant,
+                                               uint32_t *vis, int lane, const QRing &q, int qw) {
+  const int n = D.n, cl = D.cl, s = D.spm_s;
+  const int W = (n + 31) >> 5;
+  const int kl = lane < cl ? lane : cl - 1;
+  const float al = A.a_loc, bl = A.b_loc, tau0 = A.tau0;
+
+  for (int w = lane; w < W; w += 64) vis[w] = 0u;
+  uint4 draws = philox_batch(A, ant, 0, lane);
+  const int start = (int)__umulhi(rdlane(draws.z, 0), (uint32_t)n);
+  if (lane == 0) vis[start >> 5] |= 1u << (start & 31);
+  uint4 rec = D.crec[(size_t)start * cl + kl];
+  uint2 pr = spm_record<false>(D, start, lane);
+  uint32_t tl = D.spm_tail[start];
+
+  uint32_t qhead = 0, qtail = 0, c_retry = 0, hits = 0, misses = 0;
+  bool qdirect = false;
+  uint64_t c_kind = 0;  // greedy | roulette << 21 | fallback << 42
+  uint64_t c_fbu = 0;
+  int64_t len = 0;
+  int cur = start, prev = -1;
+  bool arrived_upd = false;    // the edge that reached cur gets a local update
+  uint32_t nb_start = kNone;   // the start city's departure update (applied last)
+  const uint32_t lp = A.lperiod;
+  for (int t0 = 0; t0 < n; t0 += 64) {
+    if (t0 > 0) draws = philox_batch(A, ant, t0, lane);
+    uint4 e = make_uint4(kNoEntry, 0u, 0u, 0u);
+    int tb = start;
+    uint32_t clen = 0;
+    const int tend = min(t0 + 64, n);
+    for (int g0 = t0 > 0 ? t0 : 1; g0 < tend;) {
+      const int g1 = min((g0 & ~(kQGroup - 1)) + kQGroup, tend);
+      for (int t = g0; t < g1; ++t) {
+        // the ant's own update of the edge that reached cur, on its copy of
+        // cur's record before the copy is read (Alg. 1 order)
+        if (arrived_upd) {
+          uint32_t h0 = 0, m0 = 0;
+          spm_update_wave(pr, tl, s, lane, prev, al, bl, tau0, h0, m0);
+        }
+        const Cand c = weigh_spm(D, vis, lane, rec, pr, tau0);
+        Pick p;
+        const int k = pick_candidate(A, lane, cl, c, draw_of(draws, t), p.kind);
+        if (k >= 0) {
+          p.next = (int)rdlane(rec.x, k);
+          p.d = rdlane(rec.y, k);
+        } else {
+          p = fallback_spm(D, vis, cur, lane, pr, tau0);
+        }
+        if (lane == 0) mark(vis, p.next);
+        rec = D.crec[(size_t)p.next * cl + kl];
+        pr = spm_record<false>(D, p.next, lane);
+        tl = D.spm_tail[p.next];
+        c_kind += 1ull << (21 * p.kind);
+        if (p.kind == 2) c_fbu += (uint64_t)(n - t);
+        const bool upd = (uint32_t)t % lp == 0;
+        if (t == 1) {
+          nb_start = upd ? (uint32_t)p.next : kNone;
+        } else if (lane == t - t0 && (arrived_upd || upd)) {
+          e = make_uint4((uint32_t)cur, arrived_upd ? (uint32_t)prev : kNone,
+                         upd ? (uint32_t)p.next : kNone, 0u);
+        }
+        tb = lane == t - t0 ? p.next : tb;
+        clen += p.d;
+        arrived_upd = upd;
+        prev = cur;
+        cur = p.next;
+      }
+      c_retry += group_push<ATOMIC, true>(D, A, q, qw, qhead, qtail, qdirect, lane, e, t0, g1,
+                                          hits, misses);
+      g0 = g1;
+    }
+    len += clen;
+    if (lane < tend - t0) D.tours[(size_t)ant * n + t0 + lane] = tb;
+  }
+  // closing edge (cur, start), always updated: cur's entry, then start's
+  {
+    const uint4 ce = lane == 0 ? make_uint4((uint32_t)cur, arrived_upd ? (uint32_t)prev : kNone,
+                                            (uint32_t)start, 0u)
+                               : make_uint4((uint32_t)start, nb_start, (uint32_t)cur, 0u);
+    c_retry += group_push<ATOMIC, true>(D, A, q, qw, qhead, qtail, qdirect, lane, ce, n, n + 2,
+                                        hits, misses);
+    len += dist_xy(D, cur, start);
+  }
+  c_retry = (uint32_t)uni((int)wave_sum_u(c_retry));
+  hits = (uint32_t)uni((int)wave_sum_u(hits));
+  misses = (uint32_t)uni((int)wave_sum_u(misses));
+  if (lane == 0) {
+    D.lens[ant] = len;
+    const uint32_t m21 = (1u << 21) - 1;
+    add_counters(D, (uint32_t)c_kind & m21, (uint32_t)(c_kind >> 21) & m21,
+                 (uint32_t)(c_kind >> 42) & m21, c_fbu, c_retry);
+    if (hits | misses) add_spm_counters(D, hits, misses);
+  }
+}
+
+// One instance, selective memory, updates through the block's updater wave
+// (waves 0..na-1 are ants, wave na applies their entries); LDS as in
+// k_construct_async_dense_q.
+template <bool ATOMIC>
+__global__ __launch_bounds__(64 * (kQAnts + 1)) void k_construct_async_spm_q(Dev D, Iter A) {
+  extern __shared__ uint4 qsm[];
+  __shared__ uint32_t qhd[kQAnts], qtl[kQAnts], qdone;
+  const int lane = threadIdx.x & 63;
+  const int wv = threadIdx.x >> 6;
+  const int na = (int)(blockDim.x >> 6) - 1;
+  if (threadIdx.x < kQAnts) {
+    qhd[threadIdx.x] = 0;
+    qtl[threadIdx.x] = 0;
+  }
+  if (threadIdx.x == 0) qdone = 0;
+  __syncthreads();
+  const QRing q{qsm, qhd, qtl, &qdone};
+  if (wv == na) {
+    ring_updater<ATOMIC, true>(D, A, q, lane, na);
+    return;
+  }
+  uint32_t *vis = reinterpret_cast<uint32_t *>(qsm + (size_t)na * kQRing) +
+                  wv * ((D.n + 31) >> 5);
+  const int ant = uni(blockIdx.x * na + wv);
+  if (ant < D.m) spm_ant_queued<ATOMIC>(D, A, ant, vis, lane, q, wv);
+  __atomic_signal_fence(__ATOMIC_SEQ_CST);
+  if (lane == 0) atomicAdd(&qdone, 1u);
 }
 
 // ---------------------------------------------------------------------------
@@ -2529,6 +2961,40 @@ __global__ __launch_bounds__(256) void k_global_batch(const Dev *devs, const Ite
   *h2 = fmaf(ag, *h2, bg);
 }
 
+// Best-so-far exchange between the colonies of a batch that all solve one
+// instance (the multi-colony model of the paper's Sec. 2: periodic exchange
+// of the best solution found so far along a communication topology).  Every
+// colony first offers its best-so-far tour and length (block per colony);
+// then every colony takes its source's offer when it is strictly shorter
+// than its own: topology 0, the source is the colony with the shortest
+// offer (lowest index among equals); topology 1, colony c - 1 (a ring).
+// Reading every offer before any colony changes keeps the exchange
+// independent of the order the blocks run in.
+__global__ __launch_bounds__(256) void k_offer_batch(const Dev *devs, int n, int32_t *offer,
+                                                     int64_t *olen) {
+  const Dev D = devs[blockIdx.x];
+  for (int p = threadIdx.x; p < n; p += blockDim.x) offer[(size_t)blockIdx.x * n + p] = D.best[p];
+  if (threadIdx.x == 0) olen[blockIdx.x] = D.gstate[0];
+}
+
+__global__ __launch_bounds__(256) void k_accept_batch(const Dev *devs, int count, int n,
+                                                      int topology, const int32_t *offer,
+                                                      const int64_t *olen) {
+  const int c = blockIdx.x;
+  int src = (c + count - 1) % count;
+  if (topology == 0) {
+    src = -1;
+    for (int i = 0; i < count; ++i)
+      if (olen[i] >= 0 && (src < 0 || olen[i] < olen[src])) src = i;
+  }
+  if (src < 0 || olen[src] < 0) return;
+  const Dev D = devs[c];
+  const int64_t own = olen[c];
+  if (own >= 0 && olen[src] >= own) return;
+  for (int p = threadIdx.x; p < n; p += blockDim.x) D.best[p] = offer[(size_t)src * n + p];
+  if (threadIdx.x == 0) D.gstate[0] = olen[src];
+}
+
 size_t lds_bytes(const Dev &D, int block) {
   return (size_t)(block / 64) * ((D.n + 31) / 32) * sizeof(uint32_t);
 }
@@ -2543,14 +3009,18 @@ constexpr int kAsyncBlock = 256;
 // ---------------------------------------------------------------------------
 // Launch wrappers.
 // ---------------------------------------------------------------------------
-hipError_t launch_dist(const Dev &d, uint32_t *dmax, hipStream_t s) {
-  dim3 grid((d.ldn + 63) / 64, (d.n + 3) / 4);
-  hipLaunchKernelGGL(k_dist, grid, dim3(256), 0, s, d, dmax);
+hipError_t launch_dist(const Dev &d, uint32_t *dmax, int r0, int rows, bool store,
+                       hipStream_t s) {
+  dim3 grid((d.ldn + 63) / 64, (rows + 3) / 4);
+  hipLaunchKernelGGL(k_dist, grid, dim3(256), 0, s, d, dmax, r0, rows, store ? 1 : 0);
   return hipGetLastError();
 }
 
-hipError_t launch_cand(const Dev &d, int32_t *cand_tmp, hipStream_t s) {
-  hipLaunchKernelGGL(k_cand, dim3((d.n + 3) / 4), dim3(256), 0, s, d, cand_tmp);
+hipError_t launch_cand(const Dev &d, int32_t *cand_tmp, int r0, int rows, hipStream_t s) {
+  hipLaunchKernelGGL(k_cand, dim3((rows + 3) / 4), dim3(256), 0, s, d, cand_tmp, r0, rows);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess || !d.xnn) return e;
+  hipLaunchKernelGGL(k_xnn, dim3((rows + 3) / 4), dim3(256), 0, s, d, r0, rows);
   return hipGetLastError();
 }
 
@@ -2571,11 +3041,6 @@ hipError_t launch_init_pheromone(const Dev &d, float tau0, hipStream_t s) {
     const hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
   }
-  if (d.xnn) {
-    hipLaunchKernelGGL(k_xnn, dim3((d.n + 3) / 4), dim3(256), 0, s, d);
-    const hipError_t e = hipGetLastError();
-    if (e != hipSuccess) return e;
-  }
   if (d.rpos) {
     hipLaunchKernelGGL(k_rpos, dim3((d.n * d.cl + 255) / 256), dim3(256), 0, s, d);
     const hipError_t e = hipGetLastError();
@@ -2587,12 +3052,26 @@ hipError_t launch_init_pheromone(const Dev &d, float tau0, hipStream_t s) {
     const hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
   }
-  size_t total = (size_t)d.n * d.ldn;
-  if (total < (size_t)d.n * d.spm_s) total = (size_t)d.n * d.spm_s;
+  size_t total = d.tau ? (size_t)d.n * d.ldn : (size_t)d.n;
+  if (d.spm && total < (size_t)d.n * d.spm_s) total = (size_t)d.n * d.spm_s;
   if (total < 8) total = 8;
   if (total < (size_t)d.nbflags) total = (size_t)d.nbflags;
   hipLaunchKernelGGL(k_init, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, s, d, tau0);
   return hipGetLastError();
+}
+
+// Ant waves per block of the kernels with an updater wave: the m ants spread
+// evenly over the compute units, two or more blocks per unit, at most
+// kQAnts per block.
+static hipError_t queued_ants_per_block(int m, int *na) {
+  int dev = 0, cus = 256;
+  if (hipGetDevice(&dev) != hipSuccess ||
+      hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
+    return hipErrorInvalidDevice;
+  const int per_cu = (m + cus - 1) / cus;
+  const int bpc = std::max(2, (per_cu + kQAnts - 1) / kQAnts);
+  *na = std::max(1, std::min(kQAnts, (m + cus * bpc - 1) / (cus * bpc)));
+  return hipSuccess;
 }
 
 hipError_t launch_construct(const Dev &d, const Iter &it, int mode, int memory, int lanes,
@@ -2641,16 +3120,33 @@ hipError_t launch_construct(const Dev &d, const Iter &it, int mode, int memory, 
   const int grid = (d.m + apb - 1) / apb;
   const size_t lds = lds_bytes(d, kAsyncBlock);
   const bool atomic = mode == 1;
-  if (memory == 0 && lanes == 64 && queued) {
-    // ants per block: spread the m ants evenly over the compute units, two
-    // or more blocks per unit, at most kQAnts per block
-    int dev = 0, cus = 256;
-    if (hipGetDevice(&dev) != hipSuccess ||
-        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
-      return hipErrorInvalidDevice;
-    const int per_cu = (d.m + cus - 1) / cus;
-    const int bpc = std::max(2, (per_cu + kQAnts - 1) / kQAnts);
-    const int na = std::max(1, std::min(kQAnts, (d.m + cus * bpc - 1) / (cus * bpc)));
+  if (memory == 0 && lanes == 64 && queued == 2) {
+    // two ants per wave: np pair waves per block
+    const int pairs = (d.m + 1) / 2;
+    int np = 0;
+    const hipError_t qe = queued_ants_per_block(pairs, &np);
+    if (qe != hipSuccess) return qe;
+    const dim3 gq((pairs + np - 1) / np), bq(64 * (np + 1));
+    const size_t lq = (size_t)2 * np * kQRing * sizeof(uint4) +
+                      (size_t)2 * np * ((d.n + 31) / 32) * sizeof(uint32_t);
+    const bool half = d.cl <= 32;
+    const dim3 gc((d.n * d.cl + 255) / 256);
+    hipLaunchKernelGGL(k_ctau_in, gc, dim3(256), 0, s, d);
+    if (atomic && half)
+      hipLaunchKernelGGL((k_construct_async_dense_q2<true, true>), gq, bq, lq, s, d, it);
+    else if (atomic)
+      hipLaunchKernelGGL((k_construct_async_dense_q2<true, false>), gq, bq, lq, s, d, it);
+    else if (half)
+      hipLaunchKernelGGL((k_construct_async_dense_q2<false, true>), gq, bq, lq, s, d, it);
+    else
+      hipLaunchKernelGGL((k_construct_async_dense_q2<false, false>), gq, bq, lq, s, d, it);
+    const hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_ctau_out, gc, dim3(256), 0, s, d, atomic ? 1 : 0);
+  } else if (memory == 0 && lanes == 64 && queued) {
+    int na = 0;
+    const hipError_t qe = queued_ants_per_block(d.m, &na);
+    if (qe != hipSuccess) return qe;
     const dim3 gq((d.m + na - 1) / na), bq(64 * (na + 1));
     const size_t lq = (size_t)na * kQRing * sizeof(uint4) +
                       (size_t)na * ((d.n + 31) / 32) * sizeof(uint32_t);
@@ -2692,6 +3188,17 @@ hipError_t launch_construct(const Dev &d, const Iter &it, int mode, int memory, 
       hipLaunchKernelGGL(k_construct_async_dense<false>, dim3(grid), dim3(kAsyncBlock), lds, s,
                          dd, it);
     }
+  } else if (queued) {
+    int na = 0;
+    const hipError_t e = queued_ants_per_block(d.m, &na);
+    if (e != hipSuccess) return e;
+    const dim3 gq((d.m + na - 1) / na), bq(64 * (na + 1));
+    const size_t lq = (size_t)na * kQRing * sizeof(uint4) +
+                      (size_t)na * ((d.n + 31) / 32) * sizeof(uint32_t);
+    if (atomic)
+      hipLaunchKernelGGL(k_construct_async_spm_q<true>, gq, bq, lq, s, d, it);
+    else
+      hipLaunchKernelGGL(k_construct_async_spm_q<false>, gq, bq, lq, s, d, it);
   } else {
     if (atomic)
       hipLaunchKernelGGL(k_construct_async_spm<true>, dim3(grid), dim3(kAsyncBlock), lds, s, d,
@@ -2725,6 +3232,16 @@ hipError_t launch_best_global(const Dev &d, const Iter &it, int memory, hipStrea
     hipLaunchKernelGGL(k_global_dense, dim3((d.n + 255) / 256), dim3(256), 0, s, d, it);
   else
     hipLaunchKernelGGL(k_global_spm, dim3((d.n + 3) / 4), dim3(256), 0, s, d, it);
+  return hipGetLastError();
+}
+
+hipError_t launch_exchange_batch(const Dev *devs, int count, int n, int topology,
+                                 int32_t *offer, int64_t *olen, hipStream_t s) {
+  hipLaunchKernelGGL(k_offer_batch, dim3(count), dim3(256), 0, s, devs, n, offer, olen);
+  const hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_accept_batch, dim3(count), dim3(256), 0, s, devs, count, n, topology,
+                     offer, olen);
   return hipGetLastError();
 }
 
