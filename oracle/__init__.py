@@ -73,6 +73,13 @@ def load() -> C.CDLL:
     lib.orc_set_tau.restype = C.c_int
     lib.orc_spm_update.argtypes = [P, i32, i32, f32, f32]
     lib.orc_spm_update.restype = C.c_int
+    lib.orc_set_local_search.argtypes = [P, i32]
+    lib.orc_set_local_search.restype = C.c_int
+    lib.orc_local_search_tour.argtypes = [P, P, i64, P]
+    lib.orc_local_search_tour.restype = i64
+    lib.orc_local_search.argtypes = [P]
+    lib.orc_ls_moves.argtypes = [P]
+    lib.orc_ls_moves.restype = i64
     _lib = lib
     return lib
 
@@ -125,7 +132,7 @@ class Oracle:
 
     def __init__(self, xy, m=None, cl=32, beta=2.0, q0=0.9, phi=0.1, rho=0.1,
                  tau0=0.0, memory=DENSE, spm_s=8, mode=SYNC, seed=0, instance=0,
-                 local_update_period=1):
+                 local_update_period=1, local_search=0):
         self.lib = load()
         self.xy = np.ascontiguousarray(xy, dtype=np.float64).reshape(-1, 2)
         n = self.xy.shape[0]
@@ -138,6 +145,9 @@ class Oracle:
         if self.lib.orc_set_local_period(self.h, int(local_update_period)) != 0:
             self.close()
             raise ValueError("oracle: local_update_period must be >= 1")
+        if self.lib.orc_set_local_search(self.h, int(local_search)) != 0:
+            self.close()
+            raise ValueError("oracle: local_search must be 0 or 1")
         self.n, self.m = n, m
         self.cl = self.lib.orc_cl(self.h)
         self.memory, self.spm_s = memory, spm_s
@@ -162,6 +172,20 @@ class Oracle:
 
     def select_best(self):
         self.lib.orc_select_best(self.h)
+
+    def local_search(self):
+        """The local search on every ant's tour (when it is set)."""
+        self.lib.orc_local_search(self.h)
+
+    def local_search_tour(self, tour, length: int):
+        """The descent on one tour: (improved tour, its length, moves)."""
+        t = np.array(tour, dtype=np.int32)
+        mv = C.c_int64()
+        L = int(self.lib.orc_local_search_tour(self.h, _ptr(t), int(length), C.byref(mv)))
+        return t, L, mv.value
+
+    def ls_moves(self) -> int:
+        return int(self.lib.orc_ls_moves(self.h))
 
     def global_update(self):
         self.lib.orc_global_update(self.h)

@@ -63,6 +63,8 @@ struct orc {
   int32_t ib;
 
   int64_t cnt_steps, cnt_greedy, cnt_roul, cnt_fb, cnt_hit, cnt_miss;
+  int32_t ls;       /* local search after construction: 0 none, 1 2-opt + Or-opt */
+  int64_t cnt_ls;   /* improving local-search moves applied */
 };
 
 static int g_threads = 1;
@@ -479,6 +481,245 @@ void orc_construct(orc *o) {
     local_update(o, o->tour[(size_t)a * n + n - 1], o->tour[(size_t)a * n]);
 }
 
+/* ------------------------------------------------------------------------ */
+/* Local search (Sec. 5.1 leaves "a local search heuristic, e.g. 3-Opt" as   */
+/* further research).  Reading: first-improvement descent over 2-opt moves   */
+/* and Or-opt moves (a segment of 1..3 cities moved elsewhere, a subset of   */
+/* the 3-opt exchanges), every move creating an edge from the examined city  */
+/* a to one of its candidates (the cl nearest), with a FIFO queue of cities  */
+/* to examine (don't-look bits).  Distances are integers, so a move is taken */
+/* only if it shortens the tour by at least 1 and the descent ends.          */
+/*                                                                            */
+/* For a popped city a the moves are tried in this order, the first that     */
+/* shortens the tour is applied:                                              */
+/*  1. 2-opt on a's successor b: for each candidate c (k ascending) while    */
+/*     d(a,c) < d(a,b), e = succ(c): edges (a,b), (c,e) -> (a,c), (b,e).      */
+/*  2. 2-opt on a's predecessor b: for each c while d(a,c) < d(b,a),          */
+/*     e = pred(c): edges (b,a), (e,c) -> (a,c), (b,e).                        */
+/*  3. Or-opt, L = 1, 2, 3: the segment S = a and the L - 1 cities after it,  */
+/*     p = pred(a), x the city after S; for each candidate c (k ascending):   */
+/*     (A) S between c and e = succ(c), a next to c;                          */
+/*     (B) S reversed between f = pred(c) and c, a next to c.                 */
+/* Then the cities at the ends of the changed edges are queued, in the order  */
+/* listed at each move, if not queued already.  The queue starts with the    */
+/* tour in order.  At most 50 n moves are applied.                           */
+/*                                                                            */
+/* The array holds the cycle; how a move rewrites it is fixed as well: a     */
+/* 2-opt move reverses the forward path between the two cities when it holds */
+/* at most half of them, else the rest of the tour (the same cycle); an      */
+/* Or-opt move shifts the shorter of the two blocks between the segment's    */
+/* old and new places by L positions and writes the segment into the gap.    */
+/* ------------------------------------------------------------------------ */
+typedef struct {
+  int32_t n;
+  int32_t *t, *pos, *q;
+  uint8_t *inq;
+  int32_t qh, qn;
+} ls_state;
+
+static int32_t ls_at(const ls_state *w, int32_t i) { return w->t[((i % w->n) + w->n) % w->n]; }
+static int32_t ls_succ(const ls_state *w, int32_t c) { return ls_at(w, w->pos[c] + 1); }
+static int32_t ls_pred(const ls_state *w, int32_t c) { return ls_at(w, w->pos[c] - 1); }
+
+static void ls_put(ls_state *w, int32_t i, int32_t c) {
+  i = ((i % w->n) + w->n) % w->n;
+  w->t[i] = c;
+  w->pos[c] = i;
+}
+
+static void ls_push(ls_state *w, int32_t c) {
+  if (w->inq[c]) return;
+  w->inq[c] = 1;
+  w->q[(w->qh + w->qn) % w->n] = c;
+  w->qn++;
+}
+
+/* the forward path from city u to city v, reversed (or the rest of the tour) */
+static void ls_reverse(ls_state *w, int32_t u, int32_t v) {
+  const int32_t n = w->n;
+  int32_t i = w->pos[u], j = w->pos[v];
+  int32_t len = (j - i + n) % n + 1;
+  if (2 * len > n) {
+    const int32_t i2 = (j + 1) % n, j2 = (i - 1 + n) % n;
+    i = i2;
+    j = j2;
+    len = n - len;
+  }
+  for (int32_t s = 0; s < len / 2; ++s) {
+    const int32_t a = ls_at(w, i + s), b = ls_at(w, j - s);
+    ls_put(w, i + s, b);
+    ls_put(w, j - s, a);
+  }
+}
+
+/* Or-opt: the segment of L cities at positions i .. i + L - 1 goes between
+ * cities c and e = succ(c) in its own orientation (side 0), or reversed
+ * between f = pred(c) and c (side 1). */
+static void ls_oropt(ls_state *w, int32_t i, int32_t L, int32_t c, int32_t side) {
+  const int32_t n = w->n;
+  int32_t seg[3];
+  for (int32_t q = 0; q < L; ++q) seg[q] = ls_at(w, i + q);
+  if (side == 0) {
+    /* cycle p S [x .. c] e ... : blocks B = x..c, C = e..p */
+    const int32_t nb = (w->pos[c] - (i + L) % n + n) % n + 1, nc = n - L - nb;
+    if (nb <= nc) {
+      for (int32_t r = 0; r < nb; ++r) ls_put(w, i + r, ls_at(w, i + L + r));
+      for (int32_t q = 0; q < L; ++q) ls_put(w, i + nb + q, seg[q]);
+    } else {
+      const int32_t e0 = (w->pos[c] + 1) % n;
+      for (int32_t r = nc - 1; r >= 0; --r) ls_put(w, e0 + r + L, ls_at(w, e0 + r));
+      for (int32_t q = 0; q < L; ++q) ls_put(w, e0 + q, seg[q]);
+    }
+  } else {
+    /* cycle f [c .. p] S x ... : blocks C = c..p, B = x..f */
+    const int32_t c0 = w->pos[c];
+    const int32_t nc = (i - 1 - c0 + 2 * n) % n + 1, nb = n - L - nc;
+    if (nc <= nb) {
+      for (int32_t r = nc - 1; r >= 0; --r) ls_put(w, c0 + r + L, ls_at(w, c0 + r));
+      for (int32_t q = 0; q < L; ++q) ls_put(w, c0 + q, seg[L - 1 - q]);
+    } else {
+      for (int32_t r = 0; r < nb; ++r) ls_put(w, i + r, ls_at(w, i + L + r));
+      for (int32_t q = 0; q < L; ++q) ls_put(w, i + nb + q, seg[L - 1 - q]);
+    }
+  }
+}
+
+/* One descent on tour[0..n-1] (rewritten in place); returns the new length,
+ * *moves the number of moves applied. */
+static int64_t ls_descent(const orc *o, int32_t *tour, int64_t len, ls_state *w, int64_t *moves) {
+  const int32_t n = o->n, cl = o->cl;
+  w->t = tour;
+  for (int32_t p = 0; p < n; ++p) w->pos[tour[p]] = p;
+  memset(w->inq, 0, (size_t)n);
+  w->qh = 0;
+  w->qn = 0;
+  for (int32_t p = 0; p < n; ++p) ls_push(w, tour[p]);
+  const int64_t cap = 50 * (int64_t)n;
+  int64_t mv = 0;
+  while (w->qn > 0 && mv < cap) {
+    const int32_t a = w->q[w->qh];
+    w->qh = (w->qh + 1) % n;
+    w->qn--;
+    w->inq[a] = 0;
+    const int32_t *ca = o->cand + (size_t)a * cl;
+    int done = 0;
+    /* 1. 2-opt on the successor */
+    {
+      const int32_t b = ls_succ(w, a);
+      for (int32_t k = 0; k < cl && !done; ++k) {
+        const int32_t c = ca[k];
+        if (D(o, a, c) >= D(o, a, b)) break;
+        const int32_t e = ls_succ(w, c);
+        if (c == b || e == a) continue;
+        const int64_t delta = (int64_t)D(o, a, c) + D(o, b, e) - D(o, a, b) - D(o, c, e);
+        if (delta < 0) {
+          ls_reverse(w, b, c);
+          len += delta;
+          ls_push(w, a); ls_push(w, b); ls_push(w, c); ls_push(w, e);
+          done = 1;
+        }
+      }
+    }
+    /* 2. 2-opt on the predecessor */
+    if (!done) {
+      const int32_t b = ls_pred(w, a);
+      for (int32_t k = 0; k < cl && !done; ++k) {
+        const int32_t c = ca[k];
+        if (D(o, a, c) >= D(o, b, a)) break;
+        const int32_t e = ls_pred(w, c);
+        if (c == b || e == a) continue;
+        const int64_t delta = (int64_t)D(o, a, c) + D(o, b, e) - D(o, b, a) - D(o, e, c);
+        if (delta < 0) {
+          ls_reverse(w, a, e);
+          len += delta;
+          ls_push(w, a); ls_push(w, b); ls_push(w, c); ls_push(w, e);
+          done = 1;
+        }
+      }
+    }
+    /* 3. Or-opt */
+    for (int32_t L = 1; L <= 3 && !done; ++L) {
+      if (n < L + 3) break;
+      const int32_t i = w->pos[a];
+      const int32_t s1 = a, sL = ls_at(w, i + L - 1);
+      const int32_t p = ls_at(w, i - 1), x = ls_at(w, i + L);
+      const int64_t g = (int64_t)D(o, p, s1) + D(o, sL, x) - D(o, p, x);
+      for (int32_t k = 0; k < cl && !done; ++k) {
+        const int32_t c = ca[k];
+        const int32_t off = (w->pos[c] - i + n) % n;
+        if (off < L) continue; /* c inside the segment */
+        /* (A) between c and its successor */
+        if (c != p) {
+          const int32_t e = ls_succ(w, c);
+          const int64_t delta = (int64_t)D(o, c, s1) + D(o, sL, e) - D(o, c, e) - g;
+          if (delta < 0) {
+            ls_oropt(w, i, L, c, 0);
+            len += delta;
+            ls_push(w, p); ls_push(w, x); ls_push(w, s1); ls_push(w, sL);
+            ls_push(w, c); ls_push(w, e);
+            done = 1;
+            break;
+          }
+        }
+        /* (B) reversed, between the predecessor of c and c */
+        if (c != x) {
+          const int32_t f = ls_pred(w, c);
+          const int64_t delta = (int64_t)D(o, f, sL) + D(o, s1, c) - D(o, f, c) - g;
+          if (delta < 0) {
+            ls_oropt(w, i, L, c, 1);
+            len += delta;
+            ls_push(w, p); ls_push(w, x); ls_push(w, s1); ls_push(w, sL);
+            ls_push(w, f); ls_push(w, c);
+            done = 1;
+            break;
+          }
+        }
+      }
+    }
+    if (done) mv++;
+  }
+  *moves = mv;
+  return len;
+}
+
+int64_t orc_local_search_tour(const orc *o, int32_t *tour, int64_t len, int64_t *moves) {
+  const int32_t n = o->n;
+  ls_state w;
+  w.n = n;
+  w.pos = (int32_t *)malloc(sizeof(int32_t) * (size_t)n);
+  w.q = (int32_t *)malloc(sizeof(int32_t) * (size_t)n);
+  w.inq = (uint8_t *)malloc((size_t)n);
+  int64_t mv = 0;
+  if (w.pos && w.q && w.inq) len = ls_descent(o, tour, len, &w, &mv);
+  else len = -1;
+  free(w.pos);
+  free(w.q);
+  free(w.inq);
+  if (moves) *moves = mv;
+  return len;
+}
+
+int orc_set_local_search(orc *o, int32_t kind) {
+  if (kind != 0 && kind != 1) return -1;
+  o->ls = kind;
+  return 0;
+}
+
+/* The local search on every ant's tour, after the construction (and its
+ * local updates) and before the iteration best is chosen. */
+void orc_local_search(orc *o) {
+  if (!o->ls) return;
+  const int32_t n = o->n, m = o->m;
+  int64_t total = 0;
+#pragma omp parallel for schedule(dynamic, 1) num_threads(g_threads) reduction(+ : total)
+  for (int32_t a = 0; a < m; ++a) {
+    int64_t mv = 0;
+    o->len[a] = orc_local_search_tour(o, o->tour + (size_t)a * n, o->len[a], &mv);
+    total += mv;
+  }
+  o->cnt_ls += total;
+}
+
 /* Alg. 1: iteration best (lowest ant index among equal lengths); it becomes
  * the best-so-far only if strictly shorter. */
 void orc_select_best(orc *o) {
@@ -618,6 +859,7 @@ int orc_exchange_best(orc **cols, int32_t count, int32_t topology) {
 void orc_iterate(orc *o, int32_t k) {
   for (int32_t i = 0; i < k; ++i) {
     orc_construct(o);
+    orc_local_search(o);
     orc_select_best(o);
     orc_global_update(o);
     o->iter++;
@@ -672,6 +914,8 @@ int64_t orc_get_iter_best(const orc *o, int32_t *ant) {
   if (ant) *ant = o->ib;
   return o->lib;
 }
+int64_t orc_ls_moves(const orc *o) { return o->cnt_ls; }
+
 void orc_get_counts(const orc *o, int64_t *out6) {
   out6[0] = o->cnt_steps; out6[1] = o->cnt_greedy; out6[2] = o->cnt_roul;
   out6[3] = o->cnt_fb; out6[4] = o->cnt_hit; out6[5] = o->cnt_miss;

@@ -58,12 +58,21 @@ int orc_set_best(orc *o, const int32_t *tour, int64_t len);
  * the source of colony c is colony c - 1 mod count.  0, or -1. */
 int orc_exchange_best(orc **cols, int32_t count, int32_t topology);
 
-/* One full iteration of Alg. 1 = construct + select_best + global_update. */
+/* Local search after the construction (kind 1: 2-opt and Or-opt descent over
+ * the candidate lists on every ant's tour; 0: none, the default).  0, or -1. */
+int orc_set_local_search(orc *o, int32_t kind);
+/* The descent on one tour (n cities, rewritten in place) of length len:
+ * returns the new length; *moves (may be NULL) the moves applied. */
+int64_t orc_local_search_tour(const orc *o, int32_t *tour, int64_t len, int64_t *moves);
+
+/* One full iteration of Alg. 1 = construct (+ local search, if set) +
+ * select_best + global_update. */
 void orc_iterate(orc *o, int32_t k);
 /* The three parts of one iteration, for tests of each part. */
 void orc_construct(orc *o);
 void orc_select_best(orc *o);
 void orc_global_update(orc *o);
+void orc_local_search(orc *o);
 
 /* Accessors (caller-owned outputs). */
 int32_t orc_n(const orc *o);
@@ -84,6 +93,8 @@ int64_t orc_get_iter_best(const orc *o, int32_t *ant);
 /* counters since create: [steps, greedy, roulette, fallback, spm_hits,
  * spm_misses] */
 void orc_get_counts(const orc *o, int64_t *out6);
+/* Local-search moves applied since create. */
+int64_t orc_ls_moves(const orc *o);
 
 /* Pieces exposed for the pin tests. */
 void orc_philox(const uint32_t ctr[4], const uint32_t key[2], uint32_t out[4]);
