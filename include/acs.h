@@ -108,6 +108,13 @@ typedef struct acs_params {
                             then not to be trusted); every kernel still runs
                             to its end.  Small values force that path, for
                             tests of the error handling. */
+  uint32_t local_search; /* 1: after the construction every ant's tour is
+                            improved by a first-improvement descent over
+                            2-opt and Or-opt moves (segments of 1 to 3
+                            cities) along the candidate lists, before the
+                            iteration best and the global update (the local
+                            search the paper's Sec. 5.1 proposes to study);
+                            dense memory, n <= 8192, one instance.  0: none */
 } acs_params;
 
 typedef struct acs_stats {
@@ -135,6 +142,7 @@ typedef struct acs_stats {
   int32_t construct_launches;/* construction launches of that call */
   int32_t pad1;
   double iterate_ms;         /* device time of the whole last acs_iterate */
+  int64_t ls_moves;          /* local-search moves applied since create */
 } acs_stats_t;
 
 /* Fills *p with the defaults: m = n, cl = 32, dense, s = 8, sync,

@@ -36,7 +36,7 @@ class acs_params(C.Structure):
         ("rho", C.c_double), ("tau0", C.c_double), ("seed", C.c_uint64),
         ("stream", C.c_void_p), ("workspace", C.c_void_p), ("workspace_bytes", C.c_size_t),
         ("lanes_per_ant", C.c_uint32), ("update_path", C.c_uint32),
-        ("wait_limit", C.c_uint32),
+        ("wait_limit", C.c_uint32), ("local_search", C.c_uint32),
     ]
 
 
@@ -50,7 +50,7 @@ class acs_stats_t(C.Structure):
         ("fallback", C.c_int64), ("spm_hits", C.c_int64), ("spm_misses", C.c_int64),
         ("fallback_unvisited", C.c_int64), ("cas_retries", C.c_int64),
         ("construct_ms", C.c_double), ("construct_launches", C.c_int32), ("pad1", C.c_int32),
-        ("iterate_ms", C.c_double),
+        ("iterate_ms", C.c_double), ("ls_moves", C.c_int64),
     ]
 
 
@@ -194,7 +194,7 @@ def acs_destroy(h) -> None:
 
 def make_params(m=0, cl=32, beta=2.0, q0=0.9, phi=0.1, rho=0.1, tau0=0.0, memory=ACS_DENSE,
                 spm_s=8, mode=ACS_SYNC, seed=0, instance=0, local_update_period=1,
-                lanes_per_ant=0, update_path=0, wait_limit=0) -> acs_params:
+                lanes_per_ant=0, update_path=0, wait_limit=0, local_search=0) -> acs_params:
     p = acs_default_params()
     p.m, p.cl, p.beta, p.q0, p.phi, p.rho, p.tau0 = m, cl, beta, q0, phi, rho, tau0
     p.memory, p.spm_s, p.mode, p.seed, p.instance = memory, spm_s, mode, seed, instance
@@ -202,6 +202,7 @@ def make_params(m=0, cl=32, beta=2.0, q0=0.9, phi=0.1, rho=0.1, tau0=0.0, memory
     p.lanes_per_ant = lanes_per_ant
     p.update_path = update_path
     p.wait_limit = wait_limit
+    p.local_search = local_search
     return p
 
 
@@ -216,13 +217,14 @@ class Colony:
     def __init__(self, xy, m=0, cl=32, beta=2.0, q0=0.9, phi=0.1, rho=0.1, tau0=0.0,
                  memory=ACS_DENSE, spm_s=8, mode=ACS_SYNC, seed=0, instance=0,
                  local_update_period=1, lanes_per_ant=0, update_path=0, wait_limit=0,
-                 torch_memory=True):
+                 local_search=0, torch_memory=True):
         self.xy = np.ascontiguousarray(xy, dtype=np.float64).reshape(-1, 2)
         n = self.xy.shape[0]
         p = make_params(m=m, cl=cl, beta=beta, q0=q0, phi=phi, rho=rho, tau0=tau0, memory=memory,
                         spm_s=spm_s, mode=mode, seed=seed, instance=instance,
                         local_update_period=local_update_period, lanes_per_ant=lanes_per_ant,
-                        update_path=update_path, wait_limit=wait_limit)
+                        update_path=update_path, wait_limit=wait_limit,
+                        local_search=local_search)
         self._ws = None
         if torch_memory:
             import torch

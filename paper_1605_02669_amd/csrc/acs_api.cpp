@@ -154,6 +154,11 @@ int check_params(int32_t n, const acs_params *p) {
     return fail(ACS_E_UNSUPPORTED, "lanes_per_ant < 64 needs an asynchronous mode and dense memory");
   if (p->update_path > 3) return fail(ACS_E_INVALID, "update_path = %u not in {0, 1, 2, 3}",
                                       p->update_path);
+  if (p->local_search > 1)
+    return fail(ACS_E_INVALID, "local_search = %u not in {0, 1}", p->local_search);
+  if (p->local_search && (p->memory != ACS_DENSE || n > acs::kLsMaxN))
+    return fail(ACS_E_UNSUPPORTED, "the local search needs dense memory and n <= %d",
+                acs::kLsMaxN);
   return ACS_OK;
 }
 
@@ -447,6 +452,7 @@ int iterate_handle(acs_t *h, int32_t k) {
                                   h->p.lanes_per_ant ? (int)h->p.lanes_per_ant : 64,
                                   queued_kind(h), h->stream));
     if (h->timed) HIP_TRY(hipEventRecord(h->ev[2 * i + 1], h->stream));
+    if (h->p.local_search) HIP_TRY(acs::launch_local_search(h->dev, h->stream));
     HIP_TRY(acs::launch_best_global(h->dev, it, (int)h->p.memory, h->stream));
   }
   if (h->timed) HIP_TRY(hipEventRecord(h->ev_end, h->stream));
@@ -618,7 +624,7 @@ int acs_stats(acs_t *h, acs_stats_t *out) {
                 sizeof(acs_stats_t));
   HIP_TRY(hipStreamSynchronize(h->stream));
   int64_t g[3];
-  unsigned long long c[7];
+  unsigned long long c[8];
   HIP_TRY(hipMemcpy(g, h->ws + h->L.gstate, sizeof g, hipMemcpyDeviceToHost));
   HIP_TRY(hipMemcpy(c, h->ws + h->L.counters, sizeof c, hipMemcpyDeviceToHost));
   std::memset(out, 0, sizeof *out);
@@ -639,6 +645,7 @@ int acs_stats(acs_t *h, acs_stats_t *out) {
   out->spm_misses = (int64_t)c[4];
   out->fallback_unvisited = (int64_t)c[5];
   out->cas_retries = (int64_t)c[6];
+  out->ls_moves = (int64_t)c[7];
   out->steps = out->greedy + out->roulette + out->fallback;
   out->construct_ms = h->construct_ms;
   out->construct_launches = h->construct_launches;
@@ -770,6 +777,8 @@ int check_batch_args(const int32_t *n, int32_t count, const acs_params *p) {
   if (p->update_path == 3)
     return fail(ACS_E_UNSUPPORTED, "batches run one ant per wave (update_path 3 is for one "
                                    "instance)");
+  if (p->local_search)
+    return fail(ACS_E_UNSUPPORTED, "the local search runs on one instance, not in batches");
   for (int i = 0; i < count; ++i) {
     const int rc = check_params(n[i], p);
     if (rc) return rc;

@@ -61,7 +61,7 @@ struct Dev {
   int64_t *gstate;         // [0] L_gb (-1 none), [1] L_ib, [2] ib ant
   unsigned long long *counters;  // greedy, roulette, fallback, hits, misses,
                                  // unvisited cities at fallback steps,
-                                 // compare-and-swap retries
+                                 // compare-and-swap retries, local-search moves
   uint32_t *sync;          // [0] unused, [1] error flag
   unsigned long long *bflags;  // synchronous mode: grid barrier flags, one per
                                //   block, 16 words (128 bytes) apart, from word 16
@@ -107,6 +107,10 @@ hipError_t launch_construct(const Dev &d, const Iter &it, int mode, int memory, 
 int max_sync_ants(const Dev &d, int memory);
 hipError_t launch_best_global(const Dev &d, const Iter &it, int memory,
                               hipStream_t s);
+// Local search (2-opt and Or-opt descent) on every ant's tour, dense memory,
+// n <= kLsMaxN; rewrites tours and lengths.
+constexpr int kLsMaxN = 8192;
+hipError_t launch_local_search(const Dev &d, hipStream_t s);
 // One iteration of many dense instances (asynchronous mode): construction of
 // every (instance, ant) work item, then per-instance best and global update.
 // Descriptors, iteration state and the work list are device arrays, so the
@@ -143,5 +147,6 @@ hipError_t launch_prior_apply(const Dev &d, const float *P, hipStream_t s);
 constexpr int kMaxSpmS = 16;
 constexpr int kXnn = 128;  // extended neighbour list of the selective memory's fallback
 constexpr int kFpre = 128;  // dense fallback prefix (two cities per lane)
+
 
 }  // namespace acs

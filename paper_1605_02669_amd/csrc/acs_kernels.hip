@@ -2850,6 +2850,248 @@ __device__ __forceinline__ void argmin_len(const Dev &D, int64_t &bl, int &ba) {
     if (sl[w] < bl || (sl[w] == bl && sa[w] < ba)) { bl = sl[w]; ba = sa[w]; }
 }
 
+// ---------------------------------------------------------------------------
+// Local search after the construction (the paper's further research asks
+// how a local search heuristic such as 3-opt changes convergence): a
+// first-improvement descent over 2-opt and Or-opt moves, each creating an
+// edge from the examined city a to one of its candidates, with a FIFO queue
+// of cities to examine.  For a popped city the moves are tried in a fixed
+// order and the first that shortens the tour is applied:
+//   1. 2-opt on a's successor b: candidates c (k ascending) while
+//      d(a,c) < d(a,b), e = succ(c): (a,b),(c,e) -> (a,c),(b,e);
+//   2. 2-opt on a's predecessor b: while d(a,c) < d(b,a), e = pred(c);
+//   3. Or-opt, L = 1, 2, 3: the segment of a and the L - 1 cities after it,
+//      p before it, x after it; per candidate c (k ascending): (A) the
+//      segment between c and succ(c), a next to c; (B) reversed between
+//      pred(c) and c.
+// The cities at the ends of the changed edges are then queued (in the order
+// listed per move) unless queued already; at most 50 n moves are applied.
+// A 2-opt move reverses the forward path between its two cities when that
+// path holds at most half the cities, else the rest of the tour; an Or-opt
+// move shifts the shorter of the blocks between the segment's old and new
+// places by L positions and writes the segment into the gap.  One wave per
+// tour, its lanes evaluate the candidates of a move kind at once and the
+// lowest-order improving one is taken, which is the move a sequential scan
+// in that order finds.  Tour, positions and queue live in LDS as 16-bit
+// indices (n <= kLsMaxN); the queue flags are a bitmap.
+// ---------------------------------------------------------------------------
+struct LsTour {
+  uint16_t *t, *pos, *q;
+  uint32_t *inq;
+  int n;
+};
+
+__device__ __forceinline__ int ls_wrap(int i, int n) { return ((i % n) + n) % n; }
+__device__ __forceinline__ int ls_at(const LsTour &w, int i) { return w.t[ls_wrap(i, w.n)]; }
+__device__ __forceinline__ void ls_put(const LsTour &w, int i, int c) {
+  i = ls_wrap(i, w.n);
+  w.t[i] = (uint16_t)c;
+  w.pos[c] = (uint16_t)i;
+}
+__device__ __forceinline__ int ls_dist(const Dev &D, int u, int v) {
+  return (int)D.dist[(size_t)u * D.ldn + v];
+}
+
+// queues city c (wave-uniform) unless it is queued; qh, qn wave-uniform
+__device__ __forceinline__ void ls_push(const LsTour &w, int c, int qh, int &qn, int lane) {
+  const uint32_t word = w.inq[c >> 5];
+  if ((word >> (c & 31)) & 1u) return;
+  if (lane == 0) {
+    w.inq[c >> 5] = word | (1u << (c & 31));
+    w.q[(qh + qn) % w.n] = (uint16_t)c;
+  }
+  ++qn;
+}
+
+// the forward path from city u to city v reversed, or the rest of the tour
+__device__ __forceinline__ void ls_reverse(const LsTour &w, int u, int v, int lane) {
+  const int n = w.n;
+  int i = w.pos[u], j = w.pos[v];
+  int len = (j - i + n) % n + 1;
+  if (2 * len > n) {
+    const int i2 = (j + 1) % n, j2 = (i - 1 + n) % n;
+    i = i2;
+    j = j2;
+    len = n - len;
+  }
+  for (int s = lane; s < len / 2; s += 64) {
+    const int a = ls_at(w, i + s), b = ls_at(w, j - s);
+    ls_put(w, i + s, b);
+    ls_put(w, j - s, a);
+  }
+}
+
+// block move: positions from .. from + cnt - 1 to from + by .. (by = -L or
+// +L), chunks of 64 ordered so no chunk reads what an earlier chunk wrote
+__device__ __forceinline__ void ls_shift(const LsTour &w, int from, int cnt, int by, int lane) {
+  if (by < 0) {
+    for (int r0 = 0; r0 < cnt; r0 += 64) {
+      const int r = r0 + lane;
+      const int c = r < cnt ? ls_at(w, from + r) : 0;
+      if (r < cnt) ls_put(w, from + r + by, c);
+    }
+  } else {
+    for (int r0 = ((cnt - 1) / 64) * 64; r0 >= 0; r0 -= 64) {
+      const int r = r0 + lane;
+      const int c = r < cnt ? ls_at(w, from + r) : 0;
+      if (r < cnt) ls_put(w, from + r + by, c);
+    }
+  }
+}
+
+// Or-opt: the L cities at positions i .. i + L - 1 (seg, in order) between
+// c and succ(c) (side 0) or reversed between pred(c) and c (side 1)
+__device__ __forceinline__ void ls_oropt(const LsTour &w, int i, int L, int c, int side,
+                                         const int seg[3], int lane) {
+  const int n = w.n;
+  if (side == 0) {
+    const int nb = (w.pos[c] - (i + L) % n + n) % n + 1, nc = n - L - nb;
+    if (nb <= nc) {
+      ls_shift(w, i + L, nb, -L, lane);
+      if (lane < L) ls_put(w, i + nb + lane, seg[lane]);
+    } else {
+      const int e0 = (w.pos[c] + 1) % n;
+      ls_shift(w, e0, nc, L, lane);
+      if (lane < L) ls_put(w, e0 + lane, seg[lane]);
+    }
+  } else {
+    const int c0 = w.pos[c];
+    const int nc = (i - 1 - c0 + 2 * n) % n + 1, nb = n - L - nc;
+    if (nc <= nb) {
+      ls_shift(w, c0, nc, L, lane);
+      if (lane < L) ls_put(w, c0 + lane, seg[L - 1 - lane]);
+    } else {
+      ls_shift(w, i + L, nb, -L, lane);
+      if (lane < L) ls_put(w, i + nb + lane, seg[L - 1 - lane]);
+    }
+  }
+}
+
+// One block (one wave) per ant.  Dynamic LDS: t, pos, q (n 16-bit entries
+// each) and the queue bitmap.
+__global__ __launch_bounds__(64) void k_local_search(Dev D) {
+  extern __shared__ uint32_t lsm[];
+  const int ant = blockIdx.x, lane = threadIdx.x, n = D.n, cl = D.cl;
+  const int np2 = (n + 1) & ~1;  // 16-bit arrays padded to whole words
+  LsTour w;
+  w.t = reinterpret_cast<uint16_t *>(lsm);
+  w.pos = w.t + np2;
+  w.q = w.pos + np2;
+  w.inq = reinterpret_cast<uint32_t *>(w.q + np2);
+  w.n = n;
+  const int W = (n + 31) >> 5;
+  const int32_t *tour = D.tours + (size_t)ant * n;
+  for (int p = lane; p < n; p += 64) {
+    const int c = tour[p];
+    w.t[p] = (uint16_t)c;
+    w.pos[c] = (uint16_t)p;
+    w.q[p] = (uint16_t)c;
+  }
+  for (int k = lane; k < W; k += 64) w.inq[k] = k < W - 1 || (n & 31) == 0 ? ~0u
+                                                            : (1u << (n & 31)) - 1u;
+  int qh = 0, qn = n;
+  int64_t len = D.lens[ant];
+  uint32_t moves = 0;
+  const uint32_t cap = 50u * (uint32_t)n;
+  const int kl = lane < cl ? lane : cl - 1;
+  while (qn > 0 && moves < cap) {
+    const int a = uni(w.q[qh]);
+    qh = (qh + 1) % n;
+    --qn;
+    if (lane == 0) w.inq[a >> 5] &= ~(1u << (a & 31));
+    const uint4 rec = D.crec[(size_t)a * cl + kl];
+    const int c = (int)rec.x, dac = (int)rec.y;
+    const bool cand = lane < cl;
+    const int pa = w.pos[a];
+    bool done = false;
+    // 1. 2-opt on the successor
+    {
+      const int b = uni(ls_at(w, pa + 1));
+      const int dab = ls_dist(D, a, b);
+      const int e = ls_at(w, w.pos[c] + 1);
+      const bool ok = cand && dac < dab && c != b && e != a;
+      const int delta = ok ? dac + ls_dist(D, b, e) - dab - ls_dist(D, c, e) : 0;
+      const uint64_t imp = __ballot(ok && delta < 0);
+      if (imp) {
+        const int k = (int)__ffsll((unsigned long long)imp) - 1;
+        const int cc = (int)rdlane((uint32_t)c, k), ee = (int)rdlane((uint32_t)e, k);
+        len += (int)rdlane((uint32_t)delta, k);
+        ls_reverse(w, b, cc, lane);
+        ls_push(w, a, qh, qn, lane);
+        ls_push(w, b, qh, qn, lane);
+        ls_push(w, cc, qh, qn, lane);
+        ls_push(w, ee, qh, qn, lane);
+        done = true;
+      }
+    }
+    // 2. 2-opt on the predecessor
+    if (!done) {
+      const int b = uni(ls_at(w, pa - 1));
+      const int dba = ls_dist(D, b, a);
+      const int e = ls_at(w, w.pos[c] - 1);
+      const bool ok = cand && dac < dba && c != b && e != a;
+      const int delta = ok ? dac + ls_dist(D, b, e) - dba - ls_dist(D, e, c) : 0;
+      const uint64_t imp = __ballot(ok && delta < 0);
+      if (imp) {
+        const int k = (int)__ffsll((unsigned long long)imp) - 1;
+        const int cc = (int)rdlane((uint32_t)c, k), ee = (int)rdlane((uint32_t)e, k);
+        len += (int)rdlane((uint32_t)delta, k);
+        ls_reverse(w, a, ee, lane);
+        ls_push(w, a, qh, qn, lane);
+        ls_push(w, b, qh, qn, lane);
+        ls_push(w, cc, qh, qn, lane);
+        ls_push(w, ee, qh, qn, lane);
+        done = true;
+      }
+    }
+    // 3. Or-opt of the segment a .. (L cities)
+    for (int L = 1; L <= 3 && !done; ++L) {
+      if (n < L + 3) break;
+      const int sL = uni(ls_at(w, pa + L - 1));
+      const int p = uni(ls_at(w, pa - 1)), x = uni(ls_at(w, pa + L));
+      const int g = ls_dist(D, p, a) + ls_dist(D, sL, x) - ls_dist(D, p, x);
+      const int off = (w.pos[c] - pa + n) % n;
+      const bool out = cand && off >= L;
+      const int e = ls_at(w, w.pos[c] + 1), f = ls_at(w, w.pos[c] - 1);
+      const bool okA = out && c != p, okB = out && c != x;
+      const int dA = okA ? dac + ls_dist(D, sL, e) - ls_dist(D, c, e) - g : 0;
+      const int dB = okB ? ls_dist(D, f, sL) + dac - ls_dist(D, f, c) - g : 0;
+      const uint64_t impA = __ballot(okA && dA < 0), impB = __ballot(okB && dB < 0);
+      if (impA | impB) {
+        const int k = (int)__ffsll((unsigned long long)(impA | impB)) - 1;
+        const int side = ((impA >> k) & 1ull) ? 0 : 1;
+        const int cc = (int)rdlane((uint32_t)c, k);
+        const int ef = (int)rdlane((uint32_t)(side == 0 ? e : f), k);
+        len += (int)rdlane((uint32_t)(side == 0 ? dA : dB), k);
+        int seg[3];
+        seg[0] = a;
+        seg[1] = L > 1 ? uni(ls_at(w, pa + 1)) : 0;
+        seg[2] = L > 2 ? uni(ls_at(w, pa + 2)) : 0;
+        ls_oropt(w, pa, L, cc, side, seg, lane);
+        ls_push(w, p, qh, qn, lane);
+        ls_push(w, x, qh, qn, lane);
+        ls_push(w, a, qh, qn, lane);
+        ls_push(w, sL, qh, qn, lane);
+        if (side == 0) {
+          ls_push(w, cc, qh, qn, lane);
+          ls_push(w, ef, qh, qn, lane);
+        } else {
+          ls_push(w, ef, qh, qn, lane);
+          ls_push(w, cc, qh, qn, lane);
+        }
+        done = true;
+      }
+    }
+    if (done) ++moves;
+  }
+  int32_t *out = D.tours + (size_t)ant * n;
+  for (int p = lane; p < n; p += 64) out[p] = w.t[p];
+  if (lane == 0) {
+    D.lens[ant] = len;
+    if (moves) atomicAdd(&D.counters[7], (unsigned long long)moves);
+  }
+}
+
 __global__ __launch_bounds__(1024) void k_best(Dev D) {
   __shared__ int s_better;
   int64_t bl;
@@ -3222,6 +3464,13 @@ int max_sync_ants(const Dev &d, int memory) {
   if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
     return 0;
   return per_cu * cus * (kSyncBlock / 64);
+}
+
+hipError_t launch_local_search(const Dev &d, hipStream_t s) {
+  const int np2 = (d.n + 1) & ~1;
+  const size_t lds = (size_t)3 * np2 * sizeof(uint16_t) + (size_t)((d.n + 31) / 32) * 4;
+  hipLaunchKernelGGL(k_local_search, dim3(d.m), dim3(64), lds, s, d);
+  return hipGetLastError();
 }
 
 hipError_t launch_best_global(const Dev &d, const Iter &it, int memory, hipStream_t s) {
