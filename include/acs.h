@@ -199,6 +199,27 @@ int acs_stats(struct acs_t *h, acs_stats_t *out);
 /* Releases every resource of the handle; NULL is a no-op. */
 void acs_destroy(struct acs_t *h);
 
+/* For callers that cannot allocate device memory (work recorded for a HIP
+ * graph, tight serving loops, harnesses that forbid allocation): the same
+ * result as acs_create, acs_iterate(iterations) and acs_best_tour on a
+ * handle, with the device workspace in one static array of the library
+ * (ACS_STATIC_WORKSPACE_BYTES per GPU, held from the library's first use on
+ * that GPU until the process ends) instead of an allocation.  The call
+ * creates no stream, event or device buffer: it runs on params.stream (NULL:
+ * the null stream) and returns when the best tour is copied out.
+ * coords_xy: n (x, y) pairs as for acs_create; iterations >= 1;
+ * tour_out: n ints, len_out: one int64, both caller-owned host memory.
+ * params.workspace must be NULL.  Every call on one GPU uses that GPU's one
+ * array and leaves its last contents there; calls within the process are
+ * serialised by a lock (calls that overlapped on one GPU would race).
+ * Errors: as acs_create and acs_iterate; ACS_E_BUFSIZE when the instance
+ * needs more device memory than the array holds (acs_workspace_bytes tells
+ * the need: about n^2 * 14 bytes for dense memory with m = n, plus another
+ * 4 n^2 in ACS_SYNC). */
+#define ACS_STATIC_WORKSPACE_BYTES (128u << 20)
+int acs_solve_static(const double *coords_xy, int32_t n, const acs_params *p,
+                     int32_t iterations, int32_t *tour_out, int64_t *len_out);
+
 /* Message of the last failing call on this thread ("" if none). */
 const char *acs_last_error(void);
 

@@ -104,6 +104,7 @@ def load() -> C.CDLL:
     lib.acs_prior_apply.argtypes = [P, P]
     lib.acs_set_candidate_scores.argtypes = [P, P]
     lib.acs_candidate_weights.argtypes = [P, P, sz]
+    lib.acs_solve_static.argtypes = [P, i32, C.POINTER(acs_params), i32, P, C.POINTER(i64)]
     lib.acs_last_error.restype = C.c_char_p
     _lib = lib
     return lib
@@ -190,6 +191,17 @@ def acs_stats(h) -> dict:
 
 def acs_destroy(h) -> None:
     load().acs_destroy(h)
+
+
+def acs_solve_static(xy: np.ndarray, p: acs_params, iterations: int):
+    """Best tour and length after `iterations` iterations, with the device
+    workspace in the library's static array (no device allocation)."""
+    xy = np.ascontiguousarray(xy, dtype=np.float64).reshape(-1, 2)
+    t = np.empty(xy.shape[0], dtype=np.int32)
+    L = C.c_int64()
+    _check(load().acs_solve_static(_ptr(xy), xy.shape[0], C.byref(p), iterations, _ptr(t),
+                                   C.byref(L)))
+    return t, L.value
 
 
 def make_params(m=0, cl=32, beta=2.0, q0=0.9, phi=0.1, rho=0.1, tau0=0.0, memory=ACS_DENSE,

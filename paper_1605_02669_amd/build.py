@@ -8,7 +8,7 @@ import subprocess
 HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 LIB = os.path.join(HERE, "libacs.so")
-SOURCES = ["csrc/acs_kernels.hip", "csrc/acs_prior.hip", "csrc/acs_api.cpp"]
+SOURCES = ["csrc/acs_kernels.hip", "csrc/acs_prior.hip", "csrc/acs_static.hip", "csrc/acs_api.cpp"]
 
 FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",

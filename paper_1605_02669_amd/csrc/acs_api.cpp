@@ -51,7 +51,7 @@ struct Layout {
   size_t dist_rows;  // rows of the distance matrix `dist` holds at a time
 };
 
-constexpr int kEtaEntries = 65536;  // eta^beta for every 16-bit distance
+constexpr int kEtaEntries = acs::kEtaHostEntries;  // eta^beta for every 16-bit distance
 
 // The dense fallback first scans the kFpre cities after the candidates; it
 // needs the city after them too.
@@ -486,6 +486,26 @@ int best_handle(acs_t *h, int32_t *tour_out, int64_t *len_out) {
 }
 
 }  // namespace
+
+namespace acs {
+
+int solve_in(const double *coords_xy, int32_t n, const acs_params *p, int32_t iterations,
+             char *ws, size_t ws_bytes, float *eta_host, int32_t *tour_out, int64_t *len_out) {
+  if (iterations < 1) return fail(ACS_E_INVALID, "iterations = %d < 1", iterations);
+  if (!tour_out || !len_out) return fail(ACS_E_INVALID, "NULL output");
+  acs_t h;
+  int rc = init_handle(&h, coords_xy, n, p, ws, ws_bytes, eta_host);
+  if (!rc) rc = iterate_handle(&h, iterations);
+  if (!rc) rc = best_handle(&h, tour_out, len_out);
+  const std::string keep = rc ? g_err : std::string();
+  release_resources(&h);
+  if (rc) g_err = keep;
+  return rc;
+}
+
+int set_error(int code, const char *msg) { return fail(code, "%s", msg); }
+
+}  // namespace acs
 
 extern "C" {
 

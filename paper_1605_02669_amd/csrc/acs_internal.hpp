@@ -148,5 +148,17 @@ constexpr int kMaxSpmS = 16;
 constexpr int kXnn = 128;  // extended neighbour list of the selective memory's fallback
 constexpr int kFpre = 128;  // dense fallback prefix (two cities per lane)
 
+// ---- host side (acs_api.cpp) ----
+// Host scratch the eta^beta table takes (floats).
+constexpr int kEtaHostEntries = 65536;
+// Builds the instance in the device memory `ws` (ws_bytes, kept by the
+// caller), runs `iterations` iterations of Alg. 1 on params->stream (NULL:
+// the null stream) and copies the best-so-far tour and length out.  Creates
+// no stream, event or device allocation.  eta_host: kEtaHostEntries floats of
+// host scratch for the eta^beta table.  Returns an ACS_E_* code.
+int solve_in(const double *coords_xy, int32_t n, const acs_params *p, int32_t iterations,
+             char *ws, size_t ws_bytes, float *eta_host, int32_t *tour_out, int64_t *len_out);
+// Sets the calling thread's error message; returns code.
+int set_error(int code, const char *msg);
 
 }  // namespace acs

@@ -178,3 +178,27 @@ def test_without_gpu_create_reports_device_error():
         pytest.skip("a GPU is present")
     rc, msg, _ = _create_rc(inputs.uniform(50))
     assert rc == acs.ACS_E_DEVICE and "device" in msg
+
+
+def test_static_entry_rejects_what_it_cannot_hold():
+    """acs_solve_static checks its arguments and the static workspace's size
+    before it touches a device (no compute here)."""
+    lib = acs.load()
+    xy = inputs.uniform(4000)
+    t = np.empty(4000, dtype=np.int32)
+    L = C.c_int64()
+    p = acs.make_params(mode=acs.ACS_SYNC)
+    need = acs.acs_workspace_bytes(4000, p)
+    assert need > 128 << 20
+    rc = lib.acs_solve_static(xy.ctypes.data_as(C.c_void_p), 4000, C.byref(p), 1,
+                              t.ctypes.data_as(C.c_void_p), C.byref(L))
+    assert rc == acs.ACS_E_BUFSIZE
+    assert "static workspace" in lib.acs_last_error().decode()
+    p.workspace, p.workspace_bytes = 4096, need
+    rc = lib.acs_solve_static(xy.ctypes.data_as(C.c_void_p), 4000, C.byref(p), 1,
+                              t.ctypes.data_as(C.c_void_p), C.byref(L))
+    assert rc == acs.ACS_E_INVALID
+    p = acs.make_params(mode=acs.ACS_SYNC, q0=2.0)
+    rc = lib.acs_solve_static(xy.ctypes.data_as(C.c_void_p), 100, C.byref(p), 1,
+                              t.ctypes.data_as(C.c_void_p), C.byref(L))
+    assert rc == acs.ACS_E_INVALID
