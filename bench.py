@@ -275,6 +275,64 @@ def run_ants(acs, inputs, ants=(64, 256, 1024, N), seeds=10, budget_tours=25 * N
     return out
 
 
+def run_colonies(acs, inputs, colonies=(1, 4, 8), seeds=5, budget_s=0.5, period=10):
+    """Several colonies on the headline instance with a best-so-far exchange
+    every `period` iterations (from the best colony; Sec. 2's multi-colony
+    model), n ants in total, against one colony, at equal wall-clock: mean
+    best tour length over `seeds` seeds."""
+    import numpy as np
+    import torch
+    xy = inputs.uniform(N)
+    out = {"n": N, "seeds": seeds, "budget_s": budget_s, "exchange_period": period}
+    for c in colonies:
+        best, its = [], []
+        for s in range(seeds):
+            b = acs.Batch([xy] * c, m=N // c, cl=CL, seed=s)
+            if c > 1:
+                b.set_exchange(0, period)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            k = 0
+            while time.perf_counter() - t0 < budget_s:
+                b.iterate(1)
+                k += 1
+            best.append(min(b.best(i)[1] for i in range(c)))
+            its.append(k)
+            b.close()
+        out[f"c{c}"] = {"ants_per_colony": N // c, "mean_best": float(np.mean(best)),
+                        "iterations": float(np.mean(its))}
+    return out
+
+
+def run_local_search(acs, inputs, seeds=5, budget_s=1.0):
+    """ACS with the 2-opt/Or-opt descent after each construction against
+    plain ACS at equal wall-clock on the headline instance (asynchronous
+    atomic mode): m = n ants with and without the descent, and a 64-ant
+    colony with it."""
+    import numpy as np
+    import torch
+    xy = inputs.uniform(N)
+    out = {"n": N, "seeds": seeds, "budget_s": budget_s}
+    for name, kw in (("plain_m2392", dict()), ("ls_m2392", dict(local_search=1)),
+                     ("ls_m64", dict(local_search=1, m=64))):
+        best, its, ms = [], [], []
+        for s in range(seeds):
+            col = acs.Colony(xy, mode=acs.ACS_ASYNC_ATOMIC, seed=s, cl=CL, **kw)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            k = 0
+            while time.perf_counter() - t0 < budget_s:
+                col.iterate(1)
+                k += 1
+            best.append(col.best()[1])
+            its.append(k)
+            ms.append(col.stats()["iterate_ms"])
+            col.close()
+        out[name] = {"mean_best": float(np.mean(best)), "iterations": float(np.mean(its)),
+                     "ms_per_iteration": float(np.mean(ms))}
+    return out
+
+
 MFMA_BF16_PEAK_TFLOPS = 2500.0
 # algorithmic flops per feature row of the 4-64-64-1 network: forward
 # 2 (4*64 + 64*64 + 64); backward adds the weight and input gradients of the
@@ -338,10 +396,11 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--extra", default="n198,n1000_clustered,n20000_spm,batch256,prior,n2392_alt,"
                                        "n2392_period16,n2392_sequential,n2392_sequential_m64,"
-                                       "quality,ants",
+                                       "quality,ants,colonies,local_search",
                     help="other workloads timed beside the headline (comma list of "
                          "n198, n1000_clustered, n20000_spm, batch256, prior, n2392_alt, n2392_period16, "
-                         "n2392_sequential, n2392_sequential_m64, quality, ants; empty for none)")
+                         "n2392_sequential, n2392_sequential_m64, quality, ants, colonies, "
+                         "local_search; empty for none)")
     ap.add_argument("--copy-calibration-mb", type=int, default=0,
                     help="after timing, run one plain device copy of this many MiB "
                          "(reference kernel for hardware byte counters)")
@@ -413,6 +472,10 @@ def main():
             extra[name] = run_quality(acs, inputs)
         elif name == "ants":
             extra[name] = run_ants(acs, inputs)
+        elif name == "colonies":
+            extra[name] = run_colonies(acs, inputs)
+        elif name == "local_search":
+            extra[name] = run_local_search(acs, inputs)
         elif name == "prior":
             extra[name] = run_prior(acs, inputs)
         else:

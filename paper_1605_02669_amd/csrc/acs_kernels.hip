@@ -2165,8 +2165,13 @@ __device__ __forceinline__ Pick fallback_spm(const Dev &D, uint32_t *vis, int cu
     // from the coordinates.  A lane takes eight consecutive cities (one byte
     // of the bitmap) per round and loads their coordinates together, so a
     // round costs one load latency; a byte of visited cities loads nothing.
+    // d is nondecreasing in s = dx*dx + dy*dy, and d < dk exactly when
+    // s < (dk - 1/2)^2, so a city is looked at more closely only when its s
+    // is below that bound for the lane's best key so far (cities come in
+    // increasing index per lane, so an equal d must not replace it).
     const double xc = D.xy[2 * cur], yc = D.xy[2 * cur + 1];
     const double2 *xy2 = reinterpret_cast<const double2 *>(D.xy);
+    double bound = INFINITY;  // (d of key - 1/2)^2; below 0 once d = 0
     for (int j0 = 8 * lane; j0 < n; j0 += 512) {
       uint32_t free8 = ~(vis[j0 >> 5] >> (j0 & 31)) & 0xffu;
       if (j0 + 8 > n) free8 &= (1u << (n - j0)) - 1u;
@@ -2175,9 +2180,15 @@ __device__ __forceinline__ Pick fallback_spm(const Dev &D, uint32_t *vis, int cu
 #pragma unroll
       for (int q = 0; q < 8; ++q) c[q] = xy2[min(j0 + q, n - 1)];
 #pragma unroll
-      for (int q = 0; q < 8; ++q)
-        if ((free8 >> q) & 1u)
-          key = min(key, (exact_dist(xc, yc, c[q].x, c[q].y) << 16) | (uint32_t)(j0 + q));
+      for (int q = 0; q < 8; ++q) {
+        const double dx = xc - c[q].x, dy = yc - c[q].y;
+        const double sq = dx * dx + dy * dy;
+        if (((free8 >> q) & 1u) && sq < bound) {
+          const uint32_t d = exact_dist(xc, yc, c[q].x, c[q].y);
+          key = (d << 16) | (uint32_t)(j0 + q);
+          bound = d > 0 ? ((double)d - 0.5) * ((double)d - 0.5) : -1.0;
+        }
+      }
     }
     key = wave_umin_u(key);
   }
