@@ -97,10 +97,7 @@ typedef struct acs_params {
                             wave issues its local updates itself; 2 (and 0,
                             the default) the ant waves hand them to one
                             updater wavefront per workgroup through LDS, so
-                            an ant never waits for an atomic; 3 as 2 with
-                            two ants per wavefront whose steps interleave
-                            (dense memory, one instance; the selective
-                            memory runs 3 as 2) */
+                            an ant never waits for an atomic */
   uint32_t wait_limit;   /* polls after which a bounded device wait (grid
                             barrier, update ring) gives up; 0: the library's
                             own limits.  A wait that gives up makes the

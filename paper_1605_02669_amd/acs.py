@@ -367,9 +367,9 @@ class Batch:
         with an updater wave), with the ms of their timed iterations, and
         the chosen one (None while tuning)."""
         ch, cnt = C.c_int32(), C.c_int32()
-        lanes, upd = (C.c_int32 * 4)(), (C.c_int32 * 4)()
-        ms = (C.c_double * 4)()
-        _check(load().acs_batch_tuning(self.h, C.byref(ch), C.byref(cnt), lanes, upd, ms, 4))
+        lanes, upd = (C.c_int32 * 8)(), (C.c_int32 * 8)()
+        ms = (C.c_double * 8)()
+        _check(load().acs_batch_tuning(self.h, C.byref(ch), C.byref(cnt), lanes, upd, ms, 8))
         names = [f"{lanes[j]}{'u' if upd[j] else ''}" for j in range(cnt.value)]
         return dict(chosen=names[ch.value] if ch.value >= 0 else None,
                     candidates={names[j]: float(ms[j]) for j in range(cnt.value)})

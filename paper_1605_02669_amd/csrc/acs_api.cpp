@@ -152,7 +152,7 @@ int check_params(int32_t n, const acs_params *p) {
   if (lpa != 0 && lpa != 64 &&
       ((p->mode != ACS_ASYNC_ATOMIC && p->mode != ACS_ASYNC_RACY) || p->memory != ACS_DENSE))
     return fail(ACS_E_UNSUPPORTED, "lanes_per_ant < 64 needs an asynchronous mode and dense memory");
-  if (p->update_path > 3) return fail(ACS_E_INVALID, "update_path = %u not in {0, 1, 2, 3}",
+  if (p->update_path > 2) return fail(ACS_E_INVALID, "update_path = %u not in {0, 1, 2}",
                                       p->update_path);
   if (p->local_search > 1)
     return fail(ACS_E_INVALID, "local_search = %u not in {0, 1}", p->local_search);
@@ -422,15 +422,8 @@ int init_handle(acs_t *h, const double *coords_xy, int32_t n, const acs_params *
 
 // How the asynchronous kernels with one ant per wave apply local updates
 // (acs_internal.hpp, launch_construct): 0 the ant itself, 1 an updater wave
-// per block, 2 that with two ants per wave.
-int queued_kind(const acs_t *h) {
-  switch (h->p.update_path) {
-    case 1: return 0;
-    case 2: return 1;
-    case 3: return 2;
-    default: return 1;
-  }
-}
+// per block (the default).
+int queued_kind(const acs_t *h) { return h->p.update_path == 1 ? 0 : 1; }
 
 // k iterations of Alg. 1 on the handle (see acs_iterate).
 int iterate_handle(acs_t *h, int32_t k) {
@@ -794,9 +787,6 @@ int check_batch_args(const int32_t *n, int32_t count, const acs_params *p) {
   if (p->mode != ACS_ASYNC_ATOMIC && p->mode != ACS_ASYNC_RACY)
     return fail(ACS_E_UNSUPPORTED, "batches run in an asynchronous mode");
   if (p->memory != ACS_DENSE) return fail(ACS_E_UNSUPPORTED, "batches use the dense memory");
-  if (p->update_path == 3)
-    return fail(ACS_E_UNSUPPORTED, "batches run one ant per wave (update_path 3 is for one "
-                                   "instance)");
   if (p->local_search)
     return fail(ACS_E_UNSUPPORTED, "the local search runs on one instance, not in batches");
   for (int i = 0; i < count; ++i) {

@@ -99,8 +99,7 @@ hipError_t launch_init_pheromone(const Dev &d, float tau0, hipStream_t s);
 // block).  lanes: lanes per ant of the asynchronous
 // dense kernels (64, 32 or 16; at least cl).  queued (asynchronous, 64
 // lanes per ant): 0 the ant issues its own local updates; 1 it hands them to
-// an updater wave per block; 2 as 1, with two ants per wave whose steps
-// interleave (dense memory; the selective memory treats 2 as 1).
+// an updater wave per block.
 hipError_t launch_construct(const Dev &d, const Iter &it, int mode, int memory, int lanes,
                             int queued, hipStream_t s);
 // Largest m a synchronous launch can keep resident for this instance.

@@ -375,22 +375,44 @@ __global__ __launch_bounds__(1024) void k_nn_tour(Dev D, int64_t *lnn) {
   for (int w = tid; w < W; w += 1024) vis[w] = 0;
   __syncthreads();
   if (tid == 0) vis[0] = 1u;
+  __shared__ int64_t listed;
   int cur = 0;
   int64_t L = 0;
   for (int step = 1; step < D.n; ++step) {
     __syncthreads();
-    int64_t best = INT64_MAX;
-    for (int j = tid; j < D.n; j += 1024)
-      if (!((vis[j >> 5] >> (j & 31)) & 1u)) {
-        const uint32_t dj = D.dist ? D.dist[(size_t)cur * D.ldn + j] : dist_xy(D, cur, j);
-        const int64_t key = ((int64_t)dj << 16) | j;
-        best = key < best ? key : best;
+    // without a distance matrix: the first unvisited city of cur's list of
+    // nearest cities (sorted by (d, j)) is the answer when there is one
+    if (!D.dist && tid < 64) {
+      int64_t key = -1;
+      const uint16_t *xr = D.xnn + (size_t)cur * D.xl;
+      for (int b0 = 0; b0 < D.xl; b0 += 64) {
+        const int idx = b0 + tid;
+        const uint32_t j = idx < D.xl ? (uint32_t)xr[idx] : 0u;
+        const uint64_t ok = __ballot(idx < D.xl && !((vis[j >> 5] >> (j & 31)) & 1u));
+        if (ok) {
+          const uint32_t jj = rdlane(j, (int)__ffsll((unsigned long long)ok) - 1);
+          key = ((int64_t)dist_xy(D, cur, (int)jj) << 16) | jj;
+          break;
+        }
       }
-    best = wave_min(best);
-    if ((tid & 63) == 0) red[tid >> 6] = best;
+      if (tid == 0) listed = key;
+    }
     __syncthreads();
-    best = red[0];
-    for (int w = 1; w < 16; ++w) best = red[w] < best ? red[w] : best;
+    int64_t best = D.dist ? -1 : listed;
+    if (best < 0) {
+      best = INT64_MAX;
+      for (int j = tid; j < D.n; j += 1024)
+        if (!((vis[j >> 5] >> (j & 31)) & 1u)) {
+          const uint32_t dj = D.dist ? D.dist[(size_t)cur * D.ldn + j] : dist_xy(D, cur, j);
+          const int64_t key = ((int64_t)dj << 16) | j;
+          best = key < best ? key : best;
+        }
+      best = wave_min(best);
+      if ((tid & 63) == 0) red[tid >> 6] = best;
+      __syncthreads();
+      best = red[0];
+      for (int w = 1; w < 16; ++w) best = red[w] < best ? red[w] : best;
+    }
     const int nxt = (int)(best & 0xffff);
     L += best >> 16;
     if (tid == 0) vis[nxt >> 5] |= 1u << (nxt & 31);
@@ -1433,8 +1455,9 @@ __device__ __forceinline__ void ant_queued(const Dev &D, const Iter &A, int ant,
   for (int t0 = 0; t0 < n; t0 += 64) {
     if (t0 > 0) draws = philox_batch(A, ant, t0, lane);
     const int lt = lane + t0;
-    // local updates after every lperiod-th selected edge
-    const int lu = lt % (int)A.lperiod == 0 ? lt : -1;
+    // local updates after every lperiod-th selected edge: bit t - t0 of
+    // `upd` marks the steps of this chunk that have one
+    const uint64_t upd = __builtin_amdgcn_ballot_w64(lt % (int)A.lperiod == 0);
     uint4 e = make_uint4(kNoEntry, 0u, 0u, 0u);
     int tb = start;
     uint32_t clen = 0;  // at most 64 distances below 2^16 each
@@ -1446,11 +1469,11 @@ __device__ __forceinline__ void ant_queued(const Dev &D, const Iter &A, int ant,
         // they never change a maximum or a prefix sum of positions < cl; the
         // candidate mask leaves them out of every choice
         const uint32_t word = vis[rec.x >> 5];
-        const bool unv = !((word >> (rec.x & 31)) & 1u);
+        const bool unv = !__builtin_amdgcn_ubfe(word, rec.x, 1);
         const uint64_t umask = __builtin_amdgcn_ballot_w64(unv) & clmask;
         int next, k;
         uint32_t d, tv;
-        if (umask == 0) {
+        if (__builtin_expect(umask == 0, 0)) {
           const Pick p = fallback_dense<false>(D, vis, cur, lane);
           next = p.next;
           k = -1;
@@ -1461,7 +1484,7 @@ __device__ __forceinline__ void ant_queued(const Dev &D, const Iter &A, int ant,
         } else {
           // tau * eta^beta >= 0, so its bit pattern orders like the value
           const float w = unv ? __uint_as_float(rec.w) * __uint_as_float(rec.z) : 0.f;
-          if ((rdlane(draws.x, t & 63) >> 8) < A.q0_24) {
+          if (__builtin_expect((rdlane(draws.x, t & 63) >> 8) < A.q0_24, 1)) {
             // Eq. 1: maximum weight, lowest position
             const uint32_t wb = __float_as_uint(w);
             const uint32_t mx = HALF ? half_umax_u(wb) : wave_umax_u(wb);
@@ -1491,10 +1514,15 @@ __device__ __forceinline__ void ant_queued(const Dev &D, const Iter &A, int ant,
                               lane == 0 ? 1u << (next & 31) : 0u, __ATOMIC_RELAXED,
                               __HIP_MEMORY_SCOPE_WORKGROUP);
         rec = load_rec(next);
-        tb = lt == t ? next : tb;
-        if (lu == t)
-          e = make_uint4((uint32_t)cur | ((uint32_t)next << 16), (uint32_t)k, tv,
-                         (uint32_t)(k >= 0 ? -2 : -3));
+        // the tour entry and the crossing go into lane t - t0
+        const bool mine = lt == t;
+        tb = mine ? next : tb;
+        if ((upd >> (t - t0)) & 1ull) {
+          e.x = mine ? (uint32_t)cur | ((uint32_t)next << 16) : e.x;
+          e.y = mine ? (uint32_t)k : e.y;
+          e.z = mine ? tv : e.z;
+          e.w = mine ? (uint32_t)(k >= 0 ? -2 : -3) : e.w;
+        }
         clen += d;
         cur = next;
       }
@@ -1553,208 +1581,6 @@ __global__ __launch_bounds__(64 * (kQAnts + 1)) void k_construct_async_dense_q(D
   if (ant < D.m) ant_queued<ATOMIC, HALF>(D, A, ant, vis, lane, q, wv);
   __atomic_signal_fence(__ATOMIC_SEQ_CST);
   if (lane == 0) atomicAdd(&qdone, 1u);
-}
-
-// ---------------------------------------------------------------------------
-// Two ants per wave, their steps interleaved.  Each step of an ant is a
-// dependent chain: the record of the city it moves to is loaded only once
-// the city is chosen, and the choice takes tens of dependent instructions.
-// Here one wave carries two ants (each with all 64 lanes, decisions still
-// wave-uniform) and alternates between them: while the record load of one
-// ant is in flight the wave computes the other ant's step, so the two chains
-// hide each other's memory latency without twice the waves competing for the
-// SIMD.  Each ant keeps its own ring; the step itself is ant_queued's.
-// ---------------------------------------------------------------------------
-struct QAnt {
-  uint4 rec;        // lane k: candidate k's record (index, d, eta^beta, live tau)
-  uint4 draws;      // Philox words of the current 64 steps (lane = step % 64)
-  uint4 e;          // lane t % 64: the crossing of step t, for the updater
-  uint32_t *vis;    // visited bitmap (LDS)
-  int ant, start, cur, tb, qw;
-  uint32_t qhead, qtail, clen, c_retry, c_roul, c_fb;
-  uint64_t c_fbu;
-  int64_t len;
-  bool qdirect;
-};
-
-template <bool HALF>
-__device__ __forceinline__ void qant_step(const Dev &D, const Iter &A, QAnt &s, int t, int t0,
-                                          int lane, int lu, uint64_t clmask, int dumw,
-                                          __amdgpu_buffer_rsrc_t crs, __amdgpu_buffer_rsrc_t trs,
-                                          int koff, int rowb) {
-  const int n = D.n, cl = D.cl;
-  const uint4 rec = s.rec;
-  const uint32_t word = s.vis[rec.x >> 5];
-  const bool unv = !((word >> (rec.x & 31)) & 1u);
-  const uint64_t umask = __builtin_amdgcn_ballot_w64(unv) & clmask;
-  int next, k;
-  uint32_t d, tv;
-  if (umask == 0) {
-    const Pick p = fallback_dense<false>(D, s.vis, s.cur, lane);
-    next = p.next;
-    k = -1;
-    d = p.d;
-    tv = __float_as_uint(p.tval);
-    ++s.c_fb;
-    s.c_fbu += (uint64_t)(n - t);
-  } else {
-    const float w = unv ? __uint_as_float(rec.w) * __uint_as_float(rec.z) : 0.f;
-    if ((rdlane(s.draws.x, t & 63) >> 8) < A.q0_24) {
-      const uint32_t wb = __float_as_uint(w);
-      const uint32_t mx = HALF ? half_umax_u(wb) : wave_umax_u(wb);
-      k = (int)__builtin_ctzll(__builtin_amdgcn_ballot_w64(wb == mx) & umask);
-    } else {
-      float P = w;
-      for (int off = 1; off < cl; off <<= 1) {
-        const float o = __shfl_up(P, off, 64);
-        if (lane >= off) P = P + o;
-      }
-      const float total = __uint_as_float(rdlane(__float_as_uint(P), cl - 1));
-      const float r = ((float)(rdlane(s.draws.y, t & 63) >> 8) * 0x1p-24f) * total;
-      const uint64_t sel = __builtin_amdgcn_ballot_w64(P > r) & umask;
-      k = sel ? (int)__builtin_ctzll(sel) : 63 - (int)__builtin_clzll(umask);
-      ++s.c_roul;
-    }
-    next = (int)rdlane(rec.x, k);
-    d = rdlane(rec.y, k);
-    tv = rdlane(rec.w, k);
-  }
-  __hip_atomic_fetch_or(s.vis + (lane == 0 ? (next >> 5) : dumw),
-                        lane == 0 ? 1u << (next & 31) : 0u, __ATOMIC_RELAXED,
-                        __HIP_MEMORY_SCOPE_WORKGROUP);
-  {
-    const auto r = __builtin_amdgcn_raw_buffer_load_b128(crs, koff, next * rowb, 0);
-    const uint32_t tt = __builtin_amdgcn_raw_buffer_load_b32(trs, koff >> 2, next * cl * 4, 0);
-    s.rec = make_uint4(r[0], r[1], r[2], tt);
-  }
-  const int lt = lane + t0;
-  s.tb = lt == t ? next : s.tb;
-  if (lu == t)
-    s.e = make_uint4((uint32_t)s.cur | ((uint32_t)next << 16), (uint32_t)k, tv,
-                     (uint32_t)(k >= 0 ? -2 : -3));
-  s.clen += d;
-  s.cur = next;
-}
-
-template <bool ATOMIC, bool HALF>
-__device__ __forceinline__ void ants_queued2(const Dev &D, const Iter &A, int antA, int antB,
-                                             uint32_t *visA, uint32_t *visB, int lane,
-                                             const QRing &q, int qwA, int qwB) {
-  const int n = D.n, cl = D.cl;
-  const int W = (n + 31) >> 5;
-  // A wave with one ant (odd m) runs a silent copy of it as its second ant,
-  // so both ants' loads are issued on every path and the wait for one ant's
-  // record never has to cover the other's: the copy hands over no update
-  // and writes no result.
-  const bool two = antB < D.m;  // wave-uniform
-  if (!two) antB = antA;
-  const uint64_t clmask = cl >= 64 ? ~0ull : (1ull << cl) - 1;
-  const int dumw = lane % W;
-  const int koff = (lane < cl ? lane : cl - 1) * 16;
-  const int rowb = cl * 16;
-  const __amdgpu_buffer_rsrc_t crs =
-      __builtin_amdgcn_make_buffer_rsrc(const_cast<uint4 *>(D.crec), 0, n * rowb, kBufWord3);
-  const __amdgpu_buffer_rsrc_t trs =
-      __builtin_amdgcn_make_buffer_rsrc(D.ctau, 0, n * cl * 4, kBufWord3);
-  auto init = [&](QAnt &s, int ant, uint32_t *vis, int qw) {
-    s.ant = ant;
-    s.vis = vis;
-    s.qw = qw;
-    for (int w = lane; w < W; w += 64) vis[w] = 0u;
-    s.draws = philox_batch(A, ant, 0, lane);
-    s.start = (int)__umulhi(rdlane(s.draws.z, 0), (uint32_t)n);
-    if (lane == 0) vis[s.start >> 5] |= 1u << (s.start & 31);
-    const auto r = __builtin_amdgcn_raw_buffer_load_b128(crs, koff, s.start * rowb, 0);
-    const uint32_t tt = __builtin_amdgcn_raw_buffer_load_b32(trs, koff >> 2, s.start * cl * 4, 0);
-    s.rec = make_uint4(r[0], r[1], r[2], tt);
-    s.cur = s.start;
-    s.qhead = s.qtail = s.c_retry = s.c_roul = s.c_fb = 0;
-    s.qdirect = false;
-    s.c_fbu = 0;
-    s.len = 0;
-  };
-  QAnt a{}, b{};
-  init(a, antA, visA, qwA);
-  init(b, antB, visB, qwB);
-  uint32_t unused = 0;
-  for (int t0 = 0; t0 < n; t0 += 64) {
-    if (t0 > 0) {
-      a.draws = philox_batch(A, antA, t0, lane);
-      b.draws = philox_batch(A, antB, t0, lane);
-    }
-    const int lt = lane + t0;
-    const int lu = lt % (int)A.lperiod == 0 ? lt : -1;
-    const int lub = two ? lu : -1;  // the silent copy notes no crossing
-    a.e = b.e = make_uint4(kNoEntry, 0u, 0u, 0u);
-    a.tb = a.start;
-    b.tb = b.start;
-    a.clen = b.clen = 0;
-    const int tend = min(t0 + 64, n);
-    for (int g0 = t0 > 0 ? t0 : 1; g0 < tend;) {
-      const int g1 = min((g0 & ~(kQGroup - 1)) + kQGroup, tend);
-      for (int t = g0; t < g1; ++t) {
-        qant_step<HALF>(D, A, a, t, t0, lane, lu, clmask, dumw, crs, trs, koff, rowb);
-        qant_step<HALF>(D, A, b, t, t0, lane, lub, clmask, dumw, crs, trs, koff, rowb);
-      }
-      a.c_retry += group_push<ATOMIC>(D, A, q, a.qw, a.qhead, a.qtail, a.qdirect, lane, a.e, t0,
-                                      g1, unused, unused);
-      b.c_retry += group_push<ATOMIC>(D, A, q, b.qw, b.qhead, b.qtail, b.qdirect, lane, b.e, t0,
-                                      g1, unused, unused);
-      g0 = g1;
-    }
-    a.len += a.clen;
-    b.len += b.clen;
-    if (lane < tend - t0) D.tours[(size_t)antA * n + lt] = a.tb;
-    if (two && lane < tend - t0) D.tours[(size_t)antB * n + lt] = b.tb;
-  }
-  auto finish = [&](QAnt &s) {
-    const int k1 = cand_pos(D, s.cur, s.start, lane);
-    const int k2 = cand_pos(D, s.start, s.cur, lane);
-    const uint32_t x = rdlane(__float_as_uint(tau_load(qhome(D, s.cur, s.start, k1))), 0);
-    const uint4 ce = make_uint4((uint32_t)s.cur | ((uint32_t)s.start << 16), (uint32_t)k1, x,
-                                (uint32_t)k2);
-    s.c_retry += group_push<ATOMIC>(D, A, q, s.qw, s.qhead, s.qtail, s.qdirect, lane, ce, n,
-                                    n + 1, unused, unused);
-    s.len += D.dist[(size_t)s.cur * D.ldn + s.start];
-    const uint32_t cr = (uint32_t)uni((int)wave_sum_u(s.c_retry));
-    if (lane == 0) {
-      D.lens[s.ant] = s.len;
-      add_counters(D, (uint32_t)(n - 1) - s.c_roul - s.c_fb, s.c_roul, s.c_fb, s.c_fbu, cr);
-    }
-  };
-  finish(a);
-  if (two) finish(b);
-}
-
-// One instance, two ants per wave, updates through the block's updater
-// wave: waves 0..np-1 carry ants 2 (blockIdx.x * np + wave) and that + 1
-// (rings 2 wave and 2 wave + 1), wave np applies the entries.  Dynamic LDS:
-// the 2 np rings, then the 2 np visited bitmaps.
-template <bool ATOMIC, bool HALF>
-__global__ __launch_bounds__(64 * (kQAnts + 1)) void k_construct_async_dense_q2(Dev D, Iter A) {
-  extern __shared__ uint4 qsm[];
-  __shared__ uint32_t qhd[2 * kQAnts], qtl[2 * kQAnts], qdone;
-  const int lane = threadIdx.x & 63;
-  const int wv = threadIdx.x >> 6;
-  const int np = (int)(blockDim.x >> 6) - 1;
-  if (threadIdx.x < 2 * kQAnts) {
-    qhd[threadIdx.x] = 0;
-    qtl[threadIdx.x] = 0;
-  }
-  if (threadIdx.x == 0) qdone = 0;
-  __syncthreads();
-  const QRing q{qsm, qhd, qtl, &qdone};
-  if (wv == np) {
-    ring_updater<ATOMIC, false, 2 * kQAnts>(D, A, q, lane, 2 * np);
-    return;
-  }
-  const int W = (D.n + 31) >> 5;
-  uint32_t *vis = reinterpret_cast<uint32_t *>(qsm + (size_t)2 * np * kQRing) + 2 * wv * W;
-  const int antA = uni(2 * (blockIdx.x * np + wv));
-  if (antA < D.m) ants_queued2<ATOMIC, HALF>(D, A, antA, antA + 1, vis, vis + W, lane, q, 2 * wv,
-                                             2 * wv + 1);
-  __atomic_signal_fence(__ATOMIC_SEQ_CST);
-  if (lane == 0) atomicAdd(&qdone, 2u);
 }
 
 // Many instances in one launch, updates through each block's updater wave:
@@ -3373,30 +3199,7 @@ hipError_t launch_construct(const Dev &d, const Iter &it, int mode, int memory, 
   const int grid = (d.m + apb - 1) / apb;
   const size_t lds = lds_bytes(d, kAsyncBlock);
   const bool atomic = mode == 1;
-  if (memory == 0 && lanes == 64 && queued == 2) {
-    // two ants per wave: np pair waves per block
-    const int pairs = (d.m + 1) / 2;
-    int np = 0;
-    const hipError_t qe = queued_ants_per_block(pairs, &np);
-    if (qe != hipSuccess) return qe;
-    const dim3 gq((pairs + np - 1) / np), bq(64 * (np + 1));
-    const size_t lq = (size_t)2 * np * kQRing * sizeof(uint4) +
-                      (size_t)2 * np * ((d.n + 31) / 32) * sizeof(uint32_t);
-    const bool half = d.cl <= 32;
-    const dim3 gc((d.n * d.cl + 255) / 256);
-    hipLaunchKernelGGL(k_ctau_in, gc, dim3(256), 0, s, d);
-    if (atomic && half)
-      hipLaunchKernelGGL((k_construct_async_dense_q2<true, true>), gq, bq, lq, s, d, it);
-    else if (atomic)
-      hipLaunchKernelGGL((k_construct_async_dense_q2<true, false>), gq, bq, lq, s, d, it);
-    else if (half)
-      hipLaunchKernelGGL((k_construct_async_dense_q2<false, true>), gq, bq, lq, s, d, it);
-    else
-      hipLaunchKernelGGL((k_construct_async_dense_q2<false, false>), gq, bq, lq, s, d, it);
-    const hipError_t e = hipGetLastError();
-    if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k_ctau_out, gc, dim3(256), 0, s, d, atomic ? 1 : 0);
-  } else if (memory == 0 && lanes == 64 && queued) {
+  if (memory == 0 && lanes == 64 && queued) {
     int na = 0;
     const hipError_t qe = queued_ants_per_block(d.m, &na);
     if (qe != hipSuccess) return qe;

@@ -542,10 +542,6 @@ ASYNC_FIRST = [
     ("queued_racy_ragged", dict(m=333), -2, "ASYNC_RACY"),
     # a grid with cl = 4: fallbacks at many steps, ties in every weight
     ("queued_atomic_lattice_cl4", dict(cl=4), -2, "ASYNC_ATOMIC"),
-    ("pairs_atomic", dict(), -3, "ASYNC_ATOMIC"),
-    ("pairs_racy_ragged", dict(m=333), -3, "ASYNC_RACY"),
-    ("pairs_atomic_lattice_cl4", dict(cl=4), -3, "ASYNC_ATOMIC"),
-    ("pairs_atomic_cl48", dict(cl=48, m=101), -3, "ASYNC_ATOMIC"),
     ("inwave_atomic_lattice_cl4", dict(cl=4), -1, "ASYNC_ATOMIC"),
     ("inwave_racy_lattice_cl4", dict(cl=4), -1, "ASYNC_RACY"),
     ("atomic_l32_lattice_cl4", dict(cl=4), 32, "ASYNC_ATOMIC"),
@@ -694,7 +690,7 @@ def test_updater_path_quality_matches_inwave(acs, mode):
 
 
 ACCUMULATE_PATHS = [("queued", dict(update_path=2)), ("inwave", dict(update_path=1)),
-                    ("lanes32", dict(lanes_per_ant=32)), ("pairs", dict(update_path=3))]
+                    ("lanes32", dict(lanes_per_ant=32))]
 
 
 @pytest.mark.parametrize("path,gkw", ACCUMULATE_PATHS, ids=[p[0] for p in ACCUMULATE_PATHS])
@@ -765,7 +761,7 @@ ASYNC_EDGE = [
     ("n130_cl16_beta3", 130, dict(cl=16, beta=3.0)),
 ]
 ASYNC_PATHS = [("queued", dict(update_path=2)), ("inwave", dict(update_path=1)),
-               ("lanes16", dict(lanes_per_ant=16)), ("pairs", dict(update_path=3))]
+               ("lanes16", dict(lanes_per_ant=16))]
 
 
 @pytest.mark.parametrize("path,gkw", ASYNC_PATHS, ids=[p[0] for p in ASYNC_PATHS])

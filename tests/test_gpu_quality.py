@@ -63,7 +63,6 @@ def test_quality_distribution_n2392(acs):
     arms = {
         "sync": dict(mode=acs.ACS_SYNC),
         "atomic_updater": dict(mode=acs.ACS_ASYNC_ATOMIC, update_path=2),
-        "atomic_pairs": dict(mode=acs.ACS_ASYNC_ATOMIC, update_path=3),
         "atomic_inwave": dict(mode=acs.ACS_ASYNC_ATOMIC, update_path=1),
         "alt_updater": dict(mode=acs.ACS_ASYNC_RACY, update_path=2),
         "alt_inwave": dict(mode=acs.ACS_ASYNC_RACY, update_path=1),
@@ -76,8 +75,7 @@ def test_quality_distribution_n2392(acs):
         _say(f"{name}: mean {r.mean():.0f}, sd {r.std():.0f}, min {r.min():.0f}, "
              f"max {r.max():.0f} ({100 * (r.mean() / lnn - 1):+.2f}% vs nearest neighbour)")
     for a, b in (("atomic_updater", "atomic_inwave"), ("alt_updater", "alt_inwave"),
-                 ("atomic_pairs", "atomic_inwave"), ("atomic_updater", "sync"),
-                 ("alt_updater", "atomic_updater")):
+                 ("atomic_updater", "sync"), ("alt_updater", "atomic_updater")):
         p = mannwhitneyu(res[a], res[b]).pvalue
         _say(f"{a} vs {b}: {100 * (res[a].mean() / res[b].mean() - 1):+.2f}%, rank-sum p={p:.3g}")
     # every asynchronous arm's mean stays within SYNC_BAND of the bit-exact
@@ -87,6 +85,5 @@ def test_quality_distribution_n2392(acs):
     # the colony exploring)
     for name, r in res.items():
         assert abs(r.mean() / res["sync"].mean() - 1) < SYNC_BAND, name
-    for a, b in (("atomic_updater", "atomic_inwave"), ("alt_updater", "alt_inwave"),
-                 ("atomic_pairs", "atomic_inwave")):
+    for a, b in (("atomic_updater", "atomic_inwave"), ("alt_updater", "alt_inwave")):
         assert abs(res[a].mean() / res[b].mean() - 1) < BAND, (a, b)
