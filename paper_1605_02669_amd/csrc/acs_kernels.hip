@@ -149,6 +149,29 @@ __device__ __forceinline__ uint32_t rdlane(uint32_t v, int k) {
 
 __device__ __forceinline__ int uni(int v) { return __builtin_amdgcn_readfirstlane(v); }
 
+// v_writelane: lane k of the result is s (wave-uniform), the other lanes
+// keep old.  The compiler exposes it only as the LLVM intrinsic.
+extern "C" __device__ int acs_writelane_i32(int s, int k, int old) __asm("llvm.amdgcn.writelane.i32");
+__device__ __forceinline__ uint32_t wrlane(uint32_t s, int k, uint32_t old) {
+  return (uint32_t)acs_writelane_i32((int)s, k, (int)old);
+}
+
+// Maximum over lanes 0..L-1 (L = 16, 32 or 64) as a scalar: the row
+// maxima by DPP, then one read per row.  Fewer instructions than a
+// full-wave finish when only the scalar is needed.
+template <int L>
+__device__ __forceinline__ uint32_t rows_umax_s(uint32_t v) {
+  static_assert(L == 16 || L == 32 || L == 64, "16, 32 or 64 lanes");
+  v = max(v, (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0xB1, 0xF, 0xF, false));
+  v = max(v, (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x4E, 0xF, 0xF, false));
+  v = max(v, (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x141, 0xF, 0xF, false));
+  v = max(v, (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x140, 0xF, 0xF, false));
+  if (L == 16) return rdlane(v, 0);
+  const uint32_t m01 = max(rdlane(v, 0), rdlane(v, 16));
+  if (L == 32) return m01;
+  return max(m01, max(rdlane(v, 32), rdlane(v, 48)));
+}
+
 // Pheromone slot of candidate k in city u's record.
 __device__ __forceinline__ float *cand_tau(const Dev &D, int u, int k) {
   return reinterpret_cast<float *>(const_cast<uint4 *>(D.crec) + (size_t)u * D.cl + k) + 3;
@@ -1455,20 +1478,26 @@ __device__ __forceinline__ void ant_queued(const Dev &D, const Iter &A, int ant,
   for (int t0 = 0; t0 < n; t0 += 64) {
     if (t0 > 0) draws = philox_batch(A, ant, t0, lane);
     const int lt = lane + t0;
-    // local updates after every lperiod-th selected edge: bit t - t0 of
-    // `upd` marks the steps of this chunk that have one
+    // bit t - t0 of `upd`: step t has a local update (after every
+    // lperiod-th selected edge); of `greedy`: step t takes Eq. 1's argmax
     const uint64_t upd = __builtin_amdgcn_ballot_w64(lt % (int)A.lperiod == 0);
-    uint4 e = make_uint4(kNoEntry, 0u, 0u, 0u);
+    const uint64_t greedy = __builtin_amdgcn_ballot_w64((draws.x >> 8) < A.q0_24);
+    // lane t - t0 holds step t's crossing (x = kNoEntry: no update) and
+    // tour entry; every crossing is a candidate move (kr = -2) unless the
+    // fallback made it
+    uint4 e = make_uint4(kNoEntry, 0u, 0u, (uint32_t)-2);
     int tb = start;
     uint32_t clen = 0;  // at most 64 distances below 2^16 each
     const int tend = min(t0 + 64, n);
     for (int g0 = t0 > 0 ? t0 : 1; g0 < tend;) {
       const int g1 = min((g0 & ~(kQGroup - 1)) + kQGroup, tend);
-      for (int t = g0; t < g1; ++t) {
+      uint64_t sb = 1ull << (g0 - t0);  // bit t - t0
+      for (int t = g0; t < g1; ++t, sb <<= 1) {
+        const int tl = t - t0;
         // lanes >= cl repeat candidate cl - 1 (same city, same weight), so
         // they never change a maximum or a prefix sum of positions < cl; the
         // candidate mask leaves them out of every choice
-        const uint32_t word = vis[rec.x >> 5];
+        const uint32_t word = vis[__builtin_amdgcn_ubfe(rec.x, 5, 11)];
         const bool unv = !__builtin_amdgcn_ubfe(word, rec.x, 1);
         const uint64_t umask = __builtin_amdgcn_ballot_w64(unv) & clmask;
         int next, k;
@@ -1479,15 +1508,16 @@ __device__ __forceinline__ void ant_queued(const Dev &D, const Iter &A, int ant,
           k = -1;
           d = p.d;
           tv = __float_as_uint(p.tval);
+          if (upd & sb) e.w = wrlane((uint32_t)-3, tl, e.w);
           ++c_fb;
           c_fbu += (uint64_t)(n - t);
         } else {
           // tau * eta^beta >= 0, so its bit pattern orders like the value
           const float w = unv ? __uint_as_float(rec.w) * __uint_as_float(rec.z) : 0.f;
-          if (__builtin_expect((rdlane(draws.x, t & 63) >> 8) < A.q0_24, 1)) {
+          if (greedy & sb) {
             // Eq. 1: maximum weight, lowest position
             const uint32_t wb = __float_as_uint(w);
-            const uint32_t mx = HALF ? half_umax_u(wb) : wave_umax_u(wb);
+            const uint32_t mx = rows_umax_s<HALF ? 32 : 64>(wb);
             k = (int)__builtin_ctzll(__builtin_amdgcn_ballot_w64(wb == mx) & umask);
           } else {
             // Eq. 2 by roulette: inclusive Hillis-Steele scan over the
@@ -1499,7 +1529,7 @@ __device__ __forceinline__ void ant_queued(const Dev &D, const Iter &A, int ant,
               if (lane >= off) P = P + o;
             }
             const float total = __uint_as_float(rdlane(__float_as_uint(P), cl - 1));
-            const float r = ((float)(rdlane(draws.y, t & 63) >> 8) * 0x1p-24f) * total;
+            const float r = ((float)(rdlane(draws.y, tl) >> 8) * 0x1p-24f) * total;
             const uint64_t sel = __builtin_amdgcn_ballot_w64(P > r) & umask;
             k = sel ? (int)__builtin_ctzll(sel) : 63 - (int)__builtin_clzll(umask);
             ++c_roul;
@@ -1508,20 +1538,16 @@ __device__ __forceinline__ void ant_queued(const Dev &D, const Iter &A, int ant,
           d = rdlane(rec.y, k);
           tv = rdlane(rec.w, k);
         }
-        // every lane ORs, lane 0 the visited bit and the others zero into a
-        // word of their own, so the store needs no branch around it
-        __hip_atomic_fetch_or(vis + (lane == 0 ? (next >> 5) : dumw),
-                              lane == 0 ? 1u << (next & 31) : 0u, __ATOMIC_RELAXED,
-                              __HIP_MEMORY_SCOPE_WORKGROUP);
         rec = load_rec(next);
-        // the tour entry and the crossing go into lane t - t0
-        const bool mine = lt == t;
-        tb = mine ? next : tb;
-        if ((upd >> (t - t0)) & 1ull) {
-          e.x = mine ? (uint32_t)cur | ((uint32_t)next << 16) : e.x;
-          e.y = mine ? (uint32_t)k : e.y;
-          e.z = mine ? tv : e.z;
-          e.w = mine ? (uint32_t)(k >= 0 ? -2 : -3) : e.w;
+        // one lane marks the city (lane k holds it as its candidate)
+        if (lane == (k < 0 ? 0 : k))
+          __hip_atomic_fetch_or(vis + (next >> 5), 1u << (next & 31), __ATOMIC_RELAXED,
+                                __HIP_MEMORY_SCOPE_WORKGROUP);
+        tb = (int)wrlane((uint32_t)next, tl, (uint32_t)tb);
+        if (upd & sb) {
+          e.x = wrlane((uint32_t)cur | ((uint32_t)next << 16), tl, e.x);
+          e.y = wrlane((uint32_t)k, tl, e.y);
+          e.z = wrlane(tv, tl, e.z);
         }
         clen += d;
         cur = next;
