@@ -2562,25 +2562,52 @@ __device__ __forceinline__ uint32_t spm_apply_entries(const Dev &D, const Iter &
   return retries;
 }
 
-template <bool ATOMIC>
+// The ant of k_construct_async_spm_q.  Records come by buffer loads: the
+// candidates' {j, d, eta^beta} on lanes 0..cl-1, the selective record's
+// pairs on lanes 0..s-1 and its insert counter.  Before the record of cur is
+// read, the ant applies its own update of the edge that reached cur to its
+// copy (Alg. 1 order): only a miss matters there, which replaces the slot
+// after the most recently added one by prev (visited, so its trail is never
+// read).  S: s when known at compile time (0: D.spm_s).  L: lanes holding
+// the candidates (16, 32 or 64).
+template <bool ATOMIC, int S, int L>
 __device__ __forceinline__ void spm_ant_queued(const Dev &D, const Iter &A, int ant,
                                                uint32_t *vis, int lane, const QRing &q, int qw) {
-  const int n = D.n, cl = D.cl, s = D.spm_s;
+  const int n = D.n, cl = D.cl, s = S ? S : D.spm_s;
   const int W = (n + 31) >> 5;
-  const int kl = lane < cl ? lane : cl - 1;
-  const float al = A.a_loc, bl = A.b_loc, tau0 = A.tau0;
+  const uint64_t clmask = cl >= 64 ? ~0ull : (1ull << cl) - 1;
+  const int koff = (lane < cl ? lane : cl - 1) * 16;
+  const int rowb = cl * 16;
+  const int soff = (lane < s ? lane : s - 1) * 8;
+  const float tau0 = A.tau0;
+  const __amdgpu_buffer_rsrc_t crs =
+      __builtin_amdgcn_make_buffer_rsrc(const_cast<uint4 *>(D.crec), 0, n * rowb, kBufWord3);
+  const __amdgpu_buffer_rsrc_t srs =
+      __builtin_amdgcn_make_buffer_rsrc(D.spm, 0, n * s * 8, kBufWord3);
+  const __amdgpu_buffer_rsrc_t trs =
+      __builtin_amdgcn_make_buffer_rsrc(D.spm_tail, 0, n * 4, kBufWord3);
+  auto load_rec = [&](int city) {
+    const auto r = __builtin_amdgcn_raw_buffer_load_b96(crs, koff, city * rowb, 0);
+    return make_uint3(r[0], r[1], r[2]);
+  };
+  auto load_pair = [&](int city) {
+    const auto r = __builtin_amdgcn_raw_buffer_load_b64(srs, soff, city * s * 8, 0);
+    return make_uint2(r[0], r[1]);
+  };
+  auto load_tail = [&](int city) {
+    return __builtin_amdgcn_raw_buffer_load_b32(trs, 0, city * 4, 0);
+  };
 
   for (int w = lane; w < W; w += 64) vis[w] = 0u;
   uint4 draws = philox_batch(A, ant, 0, lane);
   const int start = (int)__umulhi(rdlane(draws.z, 0), (uint32_t)n);
   if (lane == 0) vis[start >> 5] |= 1u << (start & 31);
-  uint4 rec = D.crec[(size_t)start * cl + kl];
-  uint2 pr = spm_record<false>(D, start, lane);
-  uint32_t tl = D.spm_tail[start];
+  uint3 rec = load_rec(start);
+  uint2 pr = load_pair(start);
+  uint32_t tlv = load_tail(start);
 
-  uint32_t qhead = 0, qtail = 0, c_retry = 0, hits = 0, misses = 0;
+  uint32_t qhead = 0, qtail = 0, c_retry = 0, hits = 0, misses = 0, c_roul = 0, c_fb = 0;
   bool qdirect = false;
-  uint64_t c_kind = 0;  // greedy | roulette << 21 | fallback << 42
   uint64_t c_fbu = 0;
   int64_t len = 0;
   int cur = start, prev = -1;
@@ -2589,46 +2616,90 @@ __device__ __forceinline__ void spm_ant_queued(const Dev &D, const Iter &A, int 
   const uint32_t lp = A.lperiod;
   for (int t0 = 0; t0 < n; t0 += 64) {
     if (t0 > 0) draws = philox_batch(A, ant, t0, lane);
+    const uint64_t upd = __builtin_amdgcn_ballot_w64((uint32_t)(lane + t0) % lp == 0);
+    const uint64_t greedy = __builtin_amdgcn_ballot_w64((draws.x >> 8) < A.q0_24);
+    // lane t - t0: step t's entry (x = kNoEntry: none) and tour entry
     uint4 e = make_uint4(kNoEntry, 0u, 0u, 0u);
     int tb = start;
     uint32_t clen = 0;
     const int tend = min(t0 + 64, n);
     for (int g0 = t0 > 0 ? t0 : 1; g0 < tend;) {
       const int g1 = min((g0 & ~(kQGroup - 1)) + kQGroup, tend);
-      for (int t = g0; t < g1; ++t) {
-        // the ant's own update of the edge that reached cur, on its copy of
-        // cur's record before the copy is read (Alg. 1 order)
+      uint64_t sb = 1ull << (g0 - t0);  // bit t - t0
+      for (int t = g0; t < g1; ++t, sb <<= 1) {
+        const int tl = t - t0;
         if (arrived_upd) {
-          uint32_t h0 = 0, m0 = 0;
-          spm_update_wave(pr, tl, s, lane, prev, al, bl, tau0, h0, m0);
+          const uint64_t hit =
+              __builtin_amdgcn_ballot_w64(lane < s && pr.x == (uint32_t)prev);
+          if (!hit) {
+            const uint32_t tu = (uint32_t)uni((int)tlv) + 1u;
+            const int slot = (int)(S ? (tu % (uint32_t)S) : (tu % (uint32_t)s));
+            if (lane == slot) pr.x = (uint32_t)prev;
+          }
         }
-        const Cand c = weigh_spm(D, vis, lane, rec, pr, tau0);
-        Pick p;
-        const int k = pick_candidate(A, lane, cl, c, draw_of(draws, t), p.kind);
-        if (k >= 0) {
-          p.next = (int)rdlane(rec.x, k);
-          p.d = rdlane(rec.y, k);
+        // the candidates' trails: the first slot holding j, else tau0
+        float tj = tau0;
+#pragma unroll
+        for (int i = (S ? S : kMaxSpmS) - 1; i >= 0; --i) {
+          if (S == 0 && i >= s) continue;
+          const uint32_t node = rdlane(pr.x, i);
+          const uint32_t val = rdlane(pr.y, i);
+          tj = rec.x == node ? __uint_as_float(val) : tj;
+        }
+        const uint32_t word = vis[__builtin_amdgcn_ubfe(rec.x, 5, 11)];
+        const bool unv = !__builtin_amdgcn_ubfe(word, rec.x, 1);
+        const uint64_t umask = __builtin_amdgcn_ballot_w64(unv) & clmask;
+        int next, k;
+        uint32_t d;
+        if (__builtin_expect(umask == 0, 0)) {
+          const Pick p = fallback_spm(D, vis, cur, lane, pr, tau0);
+          next = p.next;
+          k = -1;
+          d = p.d;
+          ++c_fb;
+          c_fbu += (uint64_t)(n - t);
         } else {
-          p = fallback_spm(D, vis, cur, lane, pr, tau0);
+          const float w = unv ? tj * __uint_as_float(rec.z) : 0.f;
+          if (greedy & sb) {
+            // Eq. 1: maximum weight, lowest position
+            const uint32_t wb = __float_as_uint(w);
+            const uint32_t mx = rows_umax_s<L>(wb);
+            k = (int)__builtin_ctzll(__builtin_amdgcn_ballot_w64(wb == mx) & umask);
+          } else {
+            // Eq. 2 by roulette, as in ant_queued
+            float P = w;
+            for (int off = 1; off < cl; off <<= 1) {
+              const float o = __shfl_up(P, off, 64);
+              if (lane >= off) P = P + o;
+            }
+            const float total = __uint_as_float(rdlane(__float_as_uint(P), cl - 1));
+            const float r = ((float)(rdlane(draws.y, tl) >> 8) * 0x1p-24f) * total;
+            const uint64_t sel = __builtin_amdgcn_ballot_w64(P > r) & umask;
+            k = sel ? (int)__builtin_ctzll(sel) : 63 - (int)__builtin_clzll(umask);
+            ++c_roul;
+          }
+          next = (int)rdlane(rec.x, k);
+          d = rdlane(rec.y, k);
         }
-        if (lane == 0) mark(vis, p.next);
-        rec = D.crec[(size_t)p.next * cl + kl];
-        pr = spm_record<false>(D, p.next, lane);
-        tl = D.spm_tail[p.next];
-        c_kind += 1ull << (21 * p.kind);
-        if (p.kind == 2) c_fbu += (uint64_t)(n - t);
-        const bool upd = (uint32_t)t % lp == 0;
+        rec = load_rec(next);
+        pr = load_pair(next);
+        tlv = load_tail(next);
+        if (lane == (k < 0 ? 0 : k))
+          __hip_atomic_fetch_or(vis + (next >> 5), 1u << (next & 31), __ATOMIC_RELAXED,
+                                __HIP_MEMORY_SCOPE_WORKGROUP);
+        const bool up = (upd & sb) != 0;
         if (t == 1) {
-          nb_start = upd ? (uint32_t)p.next : kNone;
-        } else if (lane == t - t0 && (arrived_upd || upd)) {
-          e = make_uint4((uint32_t)cur, arrived_upd ? (uint32_t)prev : kNone,
-                         upd ? (uint32_t)p.next : kNone, 0u);
+          nb_start = up ? (uint32_t)next : kNone;
+        } else if (arrived_upd || up) {
+          e.x = wrlane((uint32_t)cur, tl, e.x);
+          e.y = wrlane(arrived_upd ? (uint32_t)prev : kNone, tl, e.y);
+          e.z = wrlane(up ? (uint32_t)next : kNone, tl, e.z);
         }
-        tb = lane == t - t0 ? p.next : tb;
-        clen += p.d;
-        arrived_upd = upd;
+        tb = (int)wrlane((uint32_t)next, tl, (uint32_t)tb);
+        clen += d;
+        arrived_upd = up;
         prev = cur;
-        cur = p.next;
+        cur = next;
       }
       c_retry += group_push<ATOMIC, true>(D, A, q, qw, qhead, qtail, qdirect, lane, e, t0, g1,
                                           hits, misses);
@@ -2651,17 +2722,16 @@ __device__ __forceinline__ void spm_ant_queued(const Dev &D, const Iter &A, int 
   misses = (uint32_t)uni((int)wave_sum_u(misses));
   if (lane == 0) {
     D.lens[ant] = len;
-    const uint32_t m21 = (1u << 21) - 1;
-    add_counters(D, (uint32_t)c_kind & m21, (uint32_t)(c_kind >> 21) & m21,
-                 (uint32_t)(c_kind >> 42) & m21, c_fbu, c_retry);
+    add_counters(D, (uint32_t)(n - 1) - c_roul - c_fb, c_roul, c_fb, c_fbu, c_retry);
     if (hits | misses) add_spm_counters(D, hits, misses);
   }
 }
 
 // One instance, selective memory, updates through the block's updater wave
 // (waves 0..na-1 are ants, wave na applies their entries); LDS as in
-// k_construct_async_dense_q.
-template <bool ATOMIC>
+// k_construct_async_dense_q.  S and L as in spm_ant_queued (the host picks
+// them from s and cl).
+template <bool ATOMIC, int S, int L>
 __global__ __launch_bounds__(64 * (kQAnts + 1)) void k_construct_async_spm_q(Dev D, Iter A) {
   extern __shared__ uint4 qsm[];
   __shared__ uint32_t qhd[kQAnts], qtl[kQAnts], qdone;
@@ -2682,7 +2752,7 @@ __global__ __launch_bounds__(64 * (kQAnts + 1)) void k_construct_async_spm_q(Dev
   uint32_t *vis = reinterpret_cast<uint32_t *>(qsm + (size_t)na * kQRing) +
                   wv * ((D.n + 31) >> 5);
   const int ant = uni(blockIdx.x * na + wv);
-  if (ant < D.m) spm_ant_queued<ATOMIC>(D, A, ant, vis, lane, q, wv);
+  if (ant < D.m) spm_ant_queued<ATOMIC, S, L>(D, A, ant, vis, lane, q, wv);
   __atomic_signal_fence(__ATOMIC_SEQ_CST);
   if (lane == 0) atomicAdd(&qdone, 1u);
 }
@@ -3277,10 +3347,21 @@ hipError_t launch_construct(const Dev &d, const Iter &it, int mode, int memory, 
     const dim3 gq((d.m + na - 1) / na), bq(64 * (na + 1));
     const size_t lq = (size_t)na * kQRing * sizeof(uint4) +
                       (size_t)na * ((d.n + 31) / 32) * sizeof(uint32_t);
-    if (atomic)
-      hipLaunchKernelGGL(k_construct_async_spm_q<true>, gq, bq, lq, s, d, it);
-    else
-      hipLaunchKernelGGL(k_construct_async_spm_q<false>, gq, bq, lq, s, d, it);
+    // the common shapes get kernels with s and the candidate lanes fixed
+    const int sk = d.spm_s == 8 ? 8 : 0;
+    const int lk = sk == 0 ? 64 : d.cl <= 16 ? 16 : d.cl <= 32 ? 32 : 64;
+#define ACS_SPM_Q(AT, SS, LL) \
+    if (atomic == AT && sk == SS && lk == LL) \
+      hipLaunchKernelGGL((k_construct_async_spm_q<AT, SS, LL>), gq, bq, lq, s, d, it);
+    ACS_SPM_Q(true, 8, 16)
+    ACS_SPM_Q(true, 8, 32)
+    ACS_SPM_Q(true, 8, 64)
+    ACS_SPM_Q(true, 0, 64)
+    ACS_SPM_Q(false, 8, 16)
+    ACS_SPM_Q(false, 8, 32)
+    ACS_SPM_Q(false, 8, 64)
+    ACS_SPM_Q(false, 0, 64)
+#undef ACS_SPM_Q
   } else {
     if (atomic)
       hipLaunchKernelGGL(k_construct_async_spm<true>, dim3(grid), dim3(kAsyncBlock), lds, s, d,
