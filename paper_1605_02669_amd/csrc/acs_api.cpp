@@ -46,12 +46,18 @@ size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
 
 // Device buffers of one handle, as offsets into one allocation.
 struct Layout {
-  size_t xy, dist, crec, cand, eta, tau, tau2, etad, rpos, ctau, gvis, fpre, flim, femax, fbound, bflags, spm, spm_tail, xnn, upd_rec, upd_nb, upd_next, upd_head, tours, lens,
+  size_t xy, dist, crec, cand, eta, tau, tau2, etad, rpos, ctau, gvis, fpre, flim, femax, fbound, bflags, spm, spm_tail, xnn, gbox, gstart, gcnt, gcity, gxy, upd_rec, upd_nb, upd_next, upd_head, tours, lens,
       best, gstate, counters, sync, dmax, lnn, total;
   size_t dist_rows;  // rows of the distance matrix `dist` holds at a time
 };
 
 constexpr int kEtaEntries = acs::kEtaHostEntries;  // eta^beta for every 16-bit distance
+
+// Cells per side of the selective memory's search grid (about two cities
+// per cell); the grid has at most (side + 1)^2 cells.
+int grid_side(int n) {
+  return std::min(256, std::max(1, (int)std::ceil(std::sqrt((double)n / 2.0))));
+}
 
 // The dense fallback first scans the kFpre cities after the candidates; it
 // needs the city after them too.
@@ -96,7 +102,13 @@ Layout make_layout(int n, int m, int cl, int ldn, int memory, int s, int mode) {
   } else {
     L.spm = take(sizeof(uint32_t) * 2 * (size_t)n * s);
     L.spm_tail = take(sizeof(uint32_t) * (size_t)n);
-    L.xnn = take(sizeof(uint16_t) * (size_t)n * std::min(acs::kXnn, n - 1));
+    L.xnn = take(sizeof(uint32_t) * (size_t)n * std::min(acs::kXnn, n - 1));
+    const size_t cells = (size_t)(grid_side(n) + 1) * (grid_side(n) + 1);
+    L.gbox = take(sizeof(double) * 4);
+    L.gstart = take(sizeof(int32_t) * (cells + 1));
+    L.gcnt = take(sizeof(int32_t) * cells);
+    L.gcity = take(sizeof(uint32_t) * (size_t)n);
+    L.gxy = take(sizeof(double) * 2 * (size_t)n);
     L.upd_rec = take(sizeof(int32_t) * 2 * (size_t)m);
     L.upd_nb = take(sizeof(int32_t) * 2 * (size_t)m);
     L.upd_next = take(sizeof(int32_t) * 2 * (size_t)m);
@@ -240,9 +252,29 @@ int build(acs_t *h, const double *xy, float *eta_host) {
   HIP_TRY(acs::launch_dist(h->dev, dmax_d, 0, n, dense, h->stream));
   uint32_t dmax = 0;
   HIP_TRY(hipMemcpyAsync(&dmax, dmax_d, sizeof dmax, hipMemcpyDeviceToHost, h->stream));
+  double box[4] = {0, 0, 0, 0};
+  if (!dense) {
+    double *box_d = reinterpret_cast<double *>(h->ws + h->L.gbox);
+    HIP_TRY(acs::launch_grid_box(h->dev, box_d, h->stream));
+    HIP_TRY(hipMemcpyAsync(box, box_d, sizeof box, hipMemcpyDeviceToHost, h->stream));
+  }
   HIP_TRY(hipStreamSynchronize(h->stream));
   if (dmax > 65535u)
     return fail(ACS_E_UNSUPPORTED, "largest distance %u exceeds 65535", dmax);
+  if (!dense) {
+    // square cells of side (largest extent) / side over the bounding box
+    const int g = grid_side(n);
+    const double wx = box[2] - box[0], wy = box[3] - box[1];
+    const double ext = std::max(wx, wy);
+    acs::Dev &dv = h->dev;
+    dv.gx0 = box[0];
+    dv.gy0 = box[1];
+    dv.gh = ext > 0.0 ? ext / g : 1.0;
+    dv.ginv = 1.0 / dv.gh;
+    dv.gnx = std::min(g + 1, (int)std::floor(wx * dv.ginv) + 1);
+    dv.gny = std::min(g + 1, (int)std::floor(wy * dv.ginv) + 1);
+    HIP_TRY(acs::launch_grid(dv, reinterpret_cast<int32_t *>(h->ws + h->L.gcnt), h->stream));
+  }
 
   int32_t *cand = reinterpret_cast<int32_t *>(h->ws + h->L.cand);
   if (dense) {
@@ -392,8 +424,11 @@ int init_handle(acs_t *h, const double *coords_xy, int32_t n, const acs_params *
   } else {
     d.spm = reinterpret_cast<uint2 *>(w + h->L.spm);
     d.spm_tail = reinterpret_cast<uint32_t *>(w + h->L.spm_tail);
-    d.xnn = reinterpret_cast<const uint16_t *>(w + h->L.xnn);
+    d.xnn = reinterpret_cast<const uint32_t *>(w + h->L.xnn);
     d.xl = std::min(acs::kXnn, n - 1);
+    d.gstart = reinterpret_cast<const int32_t *>(w + h->L.gstart);
+    d.gcity = reinterpret_cast<const uint32_t *>(w + h->L.gcity);
+    d.gxy = reinterpret_cast<const double2 *>(w + h->L.gxy);
     d.upd_rec = reinterpret_cast<int32_t *>(w + h->L.upd_rec);
     d.upd_nb = reinterpret_cast<int32_t *>(w + h->L.upd_nb);
     d.upd_next = reinterpret_cast<int32_t *>(w + h->L.upd_next);

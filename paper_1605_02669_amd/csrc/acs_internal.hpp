@@ -48,9 +48,19 @@ struct Dev {
   // {neighbour (-1 = empty slot), pheromone bits}; spm_tail[i] counts the
   // inserts (the most recently added slot is spm_tail[i] mod s)
   uint2 *spm;              // SPM: n x s
-  const uint16_t *xnn;     // SPM: n x xl, the xl nearest cities by (d, j)
+  const uint32_t *xnn;     // SPM: n x xl, the xl nearest cities by (d, j), as
+                           //   keys d << 16 | j
   int32_t xl;              //   (xl = min(kXnn, n - 1))
   uint32_t *spm_tail;      // SPM: n
+  // SPM: uniform grid of square cells over the cities for the fallback's
+  // nearest-city search: cell (x, y) of side gh from (gx0, gy0), gnx x gny
+  // cells, row-major; the cities of cell c are gcity[gstart[c] ..
+  // gstart[c + 1]) with their coordinates in gxy (same order)
+  const int32_t *gstart;   //   gnx * gny + 1
+  const uint32_t *gcity;   //   n
+  const double2 *gxy;      //   n
+  int32_t gnx, gny;
+  double gx0, gy0, gh, ginv;
   int32_t *upd_rec;        // SPM synchronous updates of one step: record
   int32_t *upd_nb;         //   ... and neighbour of update e = 2 * ant + w,
   int32_t *upd_next;       //   ... the next update of the same record (-1 end)
@@ -89,6 +99,11 @@ hipError_t launch_dist(const Dev &d, uint32_t *dmax, int r0, int rows, bool stor
 // lists) of cities r0 .. r0 + rows - 1 from the distance rows d.dist holds.
 hipError_t launch_cand(const Dev &d, int32_t *cand_tmp, int r0, int rows, hipStream_t s);
 hipError_t launch_nn_tour(const Dev &d, int64_t *lnn_out, hipStream_t s);
+// Bounding box of the cities into box[0..3] = {xmin, ymin, xmax, ymax}.
+hipError_t launch_grid_box(const Dev &d, double *box, hipStream_t s);
+// The grid's cell lists (d.gnx, d.gny, d.gx0, d.gy0, d.ginv set): counts,
+// starts, then the cities in cell order; cnt: gnx * gny ints of scratch.
+hipError_t launch_grid(const Dev &d, int32_t *cnt, hipStream_t s);
 hipError_t launch_crec(const Dev &d, const int32_t *cand_tmp, float tau0, hipStream_t s);
 hipError_t launch_init_pheromone(const Dev &d, float tau0, hipStream_t s);
 

@@ -327,9 +327,9 @@ __global__ __launch_bounds__(256) void k_cand(Dev D, int32_t *cand, int r0, int 
   }
 }
 
-// The xl nearest cities of every city by (d, j) (selective memory only):
-// the fallback's nearest unvisited city is usually among them.
-// Cities r0 .. r0 + rows - 1, as k_cand.
+// The xl nearest cities of every city by (d, j) (selective memory only),
+// each stored as its key d << 16 | j: the fallback's nearest unvisited city
+// is usually among them.  Cities r0 .. r0 + rows - 1, as k_cand.
 __global__ __launch_bounds__(256) void k_xnn(Dev D, int r0, int rows) {
   const int lane = threadIdx.x & 63;
   const int r = blockIdx.x * 4 + (threadIdx.x >> 6);
@@ -345,7 +345,7 @@ __global__ __launch_bounds__(256) void k_xnn(Dev D, int r0, int rows) {
       if (key > last && key < best) best = key;
     }
     best = wave_min(best);
-    if (lane == 0) const_cast<uint16_t *>(D.xnn)[(size_t)i * D.xl + k] = (uint16_t)(best & 0xffff);
+    if (lane == 0) const_cast<uint32_t *>(D.xnn)[(size_t)i * D.xl + k] = (uint32_t)best;
     last = best;
   }
 }
@@ -388,6 +388,94 @@ __global__ __launch_bounds__(256) void k_fpre(Dev D) {
   if (lane == 0) const_cast<float *>(D.femax)[i] = __uint_as_float(emax);
 }
 
+// Uniform grid over the cities (selective memory): the fallback's search
+// for the nearest unvisited city reads only the cells around the current
+// city.  Cell of a coordinate, clamped to the grid.
+__device__ __forceinline__ int grid_cx(const Dev &D, double x) {
+  return min(max((int)((x - D.gx0) * D.ginv), 0), D.gnx - 1);
+}
+__device__ __forceinline__ int grid_cy(const Dev &D, double y) {
+  return min(max((int)((y - D.gy0) * D.ginv), 0), D.gny - 1);
+}
+
+// Bounding box, one block of 1024 threads.
+__global__ __launch_bounds__(1024) void k_grid_box(Dev D, double *box) {
+  __shared__ double sm[4][16];
+  double v[4] = {INFINITY, INFINITY, -INFINITY, -INFINITY};
+  for (int j = threadIdx.x; j < D.n; j += 1024) {
+    const double x = D.xy[2 * j], y = D.xy[2 * j + 1];
+    v[0] = fmin(v[0], x);
+    v[1] = fmin(v[1], y);
+    v[2] = fmax(v[2], x);
+    v[3] = fmax(v[3], y);
+  }
+#pragma unroll
+  for (int off = 32; off; off >>= 1) {
+    v[0] = fmin(v[0], __shfl_xor(v[0], off, 64));
+    v[1] = fmin(v[1], __shfl_xor(v[1], off, 64));
+    v[2] = fmax(v[2], __shfl_xor(v[2], off, 64));
+    v[3] = fmax(v[3], __shfl_xor(v[3], off, 64));
+  }
+  const int w = threadIdx.x >> 6;
+  if ((threadIdx.x & 63) == 0)
+    for (int q = 0; q < 4; ++q) sm[q][w] = v[q];
+  __syncthreads();
+  if (threadIdx.x < 4) {
+    double r = sm[threadIdx.x][0];
+    for (int i = 1; i < 16; ++i)
+      r = threadIdx.x < 2 ? fmin(r, sm[threadIdx.x][i]) : fmax(r, sm[threadIdx.x][i]);
+    box[threadIdx.x] = r;
+  }
+}
+
+__global__ __launch_bounds__(256) void k_grid_count(Dev D, int32_t *cnt) {
+  const int j = blockIdx.x * 256 + threadIdx.x;
+  if (j >= D.n) return;
+  atomicAdd(&cnt[grid_cy(D, D.xy[2 * j + 1]) * D.gnx + grid_cx(D, D.xy[2 * j])], 1);
+}
+
+// Exclusive prefix sum of the counts into gstart (one block); cnt becomes
+// the fill cursor (a copy of the starts).
+__global__ __launch_bounds__(1024) void k_grid_scan(Dev D, int32_t *cnt) {
+  __shared__ int32_t part[1024];
+  const int cells = D.gnx * D.gny;
+  const int per = (cells + 1023) / 1024;
+  const int c0 = min(cells, (int)threadIdx.x * per), c1 = min(cells, c0 + per);
+  int32_t sum = 0;
+  for (int c = c0; c < c1; ++c) sum += cnt[c];
+  part[threadIdx.x] = sum;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    int32_t run = 0;
+    for (int i = 0; i < 1024; ++i) {
+      const int32_t x = part[i];
+      part[i] = run;
+      run += x;
+    }
+  }
+  __syncthreads();
+  int32_t *gstart = const_cast<int32_t *>(D.gstart);
+  int32_t run = part[threadIdx.x];
+  for (int c = c0; c < c1; ++c) {
+    const int32_t x = cnt[c];
+    gstart[c] = run;
+    cnt[c] = run;
+    run += x;
+  }
+  if (threadIdx.x == 0) gstart[cells] = D.n;
+}
+
+// Cities into their cells (order inside a cell is immaterial: the search
+// takes the least (d, j) over every city it reads).
+__global__ __launch_bounds__(256) void k_grid_fill(Dev D, int32_t *cur) {
+  const int j = blockIdx.x * 256 + threadIdx.x;
+  if (j >= D.n) return;
+  const double x = D.xy[2 * j], y = D.xy[2 * j + 1];
+  const int p = atomicAdd(&cur[grid_cy(D, y) * D.gnx + grid_cx(D, x)], 1);
+  const_cast<uint32_t *>(D.gcity)[p] = (uint32_t)j;
+  const_cast<double2 *>(D.gxy)[p] = make_double2(x, y);
+}
+
 // Nearest-neighbour tour from city 0 (ties: lowest index), one block; its
 // length L_nn defines tau0 = 1 / (n * L_nn).
 __global__ __launch_bounds__(1024) void k_nn_tour(Dev D, int64_t *lnn) {
@@ -407,14 +495,14 @@ __global__ __launch_bounds__(1024) void k_nn_tour(Dev D, int64_t *lnn) {
     // nearest cities (sorted by (d, j)) is the answer when there is one
     if (!D.dist && tid < 64) {
       int64_t key = -1;
-      const uint16_t *xr = D.xnn + (size_t)cur * D.xl;
+      const uint32_t *xr = D.xnn + (size_t)cur * D.xl;
       for (int b0 = 0; b0 < D.xl; b0 += 64) {
         const int idx = b0 + tid;
-        const uint32_t j = idx < D.xl ? (uint32_t)xr[idx] : 0u;
+        const uint32_t e = idx < D.xl ? xr[idx] : 0u;
+        const uint32_t j = e & 0xffffu;
         const uint64_t ok = __ballot(idx < D.xl && !((vis[j >> 5] >> (j & 31)) & 1u));
         if (ok) {
-          const uint32_t jj = rdlane(j, (int)__ffsll((unsigned long long)ok) - 1);
-          key = ((int64_t)dist_xy(D, cur, (int)jj) << 16) | jj;
+          key = (int64_t)rdlane(e, (int)__ffsll((unsigned long long)ok) - 1);
           break;
         }
       }
@@ -1991,69 +2079,116 @@ __device__ __forceinline__ Cand weigh_spm(const Dev &D, const uint32_t *vis, int
 // unvisited cities of the record, ties -> lowest index: exactly the greedy
 // argmax over all unvisited cities.
 __device__ __forceinline__ Pick fallback_spm(const Dev &D, uint32_t *vis, int cur, int lane,
-                                             uint2 pr, float tau0) {
-  const int n = D.n, s = D.spm_s;
+                                             uint2 pr, float tau0, int unvisited) {
+  const int s = D.spm_s;
+  // every load that does not depend on another goes out first: the first
+  // 128 keys of cur's extended list (two per lane), cur's coordinates and
+  // those of the record's cities
+  const uint32_t *xr = D.xnn + (size_t)cur * D.xl;
+  const uint32_t e0 = lane < D.xl ? xr[lane] : kNone;
+  const uint32_t e1 = lane + 64 < D.xl ? xr[lane + 64] : kNone;
+  const double xc = D.xy[2 * cur], yc = D.xy[2 * cur + 1];
   const bool in_rec = lane < s && pr.x != kNone;
   const uint32_t rj = in_rec ? pr.x : 0u;
+  const double2 rxy = reinterpret_cast<const double2 *>(D.xy)[rj];
   const bool rec_unv = in_rec && !((vis[rj >> 5] >> (rj & 31)) & 1u);
-  // hide the record's unvisited cities from the scan of the others
+  // hide the record's unvisited cities from the search of the others
   if (rec_unv) atomicOr(&vis[rj >> 5], 1u << (rj & 31));
-  uint32_t key = kNone;
   // the extended neighbour list is sorted by (d, j), so its first city that
   // is neither visited nor in the record is the nearest such city overall
-  const uint16_t *xr = D.xnn + (size_t)cur * D.xl;
-  for (int b0 = 0; b0 < D.xl; b0 += 64) {
-    const int idx = b0 + lane;
-    const uint32_t j = idx < D.xl ? (uint32_t)xr[idx] : 0u;
-    const uint64_t ok = __ballot(idx < D.xl && !((vis[j >> 5] >> (j & 31)) & 1u));
-    if (ok) {
-      const uint32_t jj = rdlane(j, (int)__ffsll((unsigned long long)ok) - 1);
-      key = (dist_xy(D, cur, (int)jj) << 16) | jj;
-      break;
-    }
+  uint32_t key = kNone;
+  {
+    const uint32_t j0 = e0 & 0xffffu, j1 = e1 & 0xffffu;
+    const uint64_t ok0 = __ballot(e0 != kNone && !((vis[j0 >> 5] >> (j0 & 31)) & 1u));
+    const uint64_t ok1 = __ballot(e1 != kNone && !((vis[j1 >> 5] >> (j1 & 31)) & 1u));
+    if (ok0)
+      key = rdlane(e0, (int)__ffsll((unsigned long long)ok0) - 1);
+    else if (ok1)
+      key = rdlane(e1, (int)__ffsll((unsigned long long)ok1) - 1);
   }
-  if (key == kNone) {
-    // every listed city is taken: scan every unvisited city, its distance
-    // from the coordinates.  A lane takes eight consecutive cities (one byte
-    // of the bitmap) per round and loads their coordinates together, so a
-    // round costs one load latency; a byte of visited cities loads nothing.
-    // d is nondecreasing in s = dx*dx + dy*dy, and d < dk exactly when
-    // s < (dk - 1/2)^2, so a city is looked at more closely only when its s
-    // is below that bound for the lane's best key so far (cities come in
-    // increasing index per lane, so an equal d must not replace it).
-    const double xc = D.xy[2 * cur], yc = D.xy[2 * cur + 1];
-    const double2 *xy2 = reinterpret_cast<const double2 *>(D.xy);
-    double bound = INFINITY;  // (d of key - 1/2)^2; below 0 once d = 0
-    for (int j0 = 8 * lane; j0 < n; j0 += 512) {
-      uint32_t free8 = ~(vis[j0 >> 5] >> (j0 & 31)) & 0xffu;
-      if (j0 + 8 > n) free8 &= (1u << (n - j0)) - 1u;
-      if (!free8) continue;
-      double2 c[8];
-#pragma unroll
-      for (int q = 0; q < 8; ++q) c[q] = xy2[min(j0 + q, n - 1)];
-#pragma unroll
-      for (int q = 0; q < 8; ++q) {
-        const double dx = xc - c[q].x, dy = yc - c[q].y;
-        const double sq = dx * dx + dy * dy;
-        if (((free8 >> q) & 1u) && sq < bound) {
-          const uint32_t d = exact_dist(xc, yc, c[q].x, c[q].y);
-          key = (d << 16) | (uint32_t)(j0 + q);
-          bound = d > 0 ? ((double)d - 0.5) * ((double)d - 0.5) : -1.0;
+  for (int b0 = 128; key == kNone && b0 < D.xl; b0 += 64) {
+    // lists longer than 128 (not built today)
+    const int idx = b0 + lane;
+    const uint32_t e = idx < D.xl ? xr[idx] : kNone;
+    const uint32_t j = e & 0xffffu;
+    const uint64_t ok = __ballot(e != kNone && !((vis[j >> 5] >> (j & 31)) & 1u));
+    if (ok) key = rdlane(e, (int)__ffsll((unsigned long long)ok) - 1);
+  }
+  // (when every unvisited city is in the record there is nothing to find)
+  const int rec_left = __popcll(__ballot(rec_unv));
+  if (key == kNone && unvisited > rec_left) {
+    // every listed city is taken: search the grid ring by ring around cur's
+    // cell (ring r: the cells at Chebyshev distance r).  Every city of ring
+    // r lies at least lb(r) = (r - 1) * gh + (cur's distance to its cell's
+    // nearest edge) from cur, so once lb(r) >= d + 1/2 for the best d found
+    // no farther city can reach d, let alone beat it (ties go to the lower
+    // index, so cities at the best d are still read).  Each lane keeps the
+    // least key over the cities it reads; a city is looked at more closely
+    // only when its s = dx*dx + dy*dy is below (d + 1/2)^2, which is exactly
+    // when its distance is at most d.
+    const int cx = grid_cx(D, xc), cy = grid_cy(D, yc);
+    const double fx = xc - (D.gx0 + cx * D.gh), fy = yc - (D.gy0 + cy * D.gh);
+    // the margin covers rounding in the cell of a coordinate
+    const double edge =
+        fmax(0.0, fmin(fmin(fx, D.gh - fx), fmin(fy, D.gh - fy))) -
+        1e-9 * (fabs(D.gx0) + fabs(D.gy0) + D.gh * (double)(D.gnx + D.gny));
+    uint32_t lkey = kNone;
+    double bound = INFINITY;  // (d + 1/2)^2 for the best key so far
+    const int rmax = max(D.gnx, D.gny);
+    for (int r = 0; r <= rmax; ++r) {
+      if (key != kNone && r >= 1) {
+        const double lb = (double)(r - 1) * D.gh + edge;
+        if (lb > 0.0 && lb * lb >= bound) break;
+      }
+      const int ncell = r == 0 ? 1 : 8 * r;
+      for (int q = lane; q < ncell; q += 64) {
+        int ix, iy;
+        if (r == 0) {
+          ix = cx;
+          iy = cy;
+        } else if (q < 2 * r + 1) {  // top row
+          ix = cx - r + q;
+          iy = cy - r;
+        } else if (q < 4 * r + 2) {  // bottom row
+          ix = cx - r + (q - 2 * r - 1);
+          iy = cy + r;
+        } else if (q < 6 * r + 1) {  // left column without the corners
+          ix = cx - r;
+          iy = cy - r + 1 + (q - 4 * r - 2);
+        } else {                     // right column without the corners
+          ix = cx + r;
+          iy = cy - r + 1 + (q - 6 * r - 1);
+        }
+        if (ix < 0 || iy < 0 || ix >= D.gnx || iy >= D.gny) continue;
+        const int c = iy * D.gnx + ix;
+        const int p1 = D.gstart[c + 1];
+        for (int p = D.gstart[c]; p < p1; ++p) {
+          const uint32_t j = D.gcity[p];
+          if ((vis[j >> 5] >> (j & 31)) & 1u) continue;
+          const double2 cxy = D.gxy[p];
+          const double dx = xc - cxy.x, dy = yc - cxy.y;
+          if (dx * dx + dy * dy < bound) {
+            const uint32_t d = exact_dist(xc, yc, cxy.x, cxy.y);
+            const uint32_t kk = (d << 16) | j;
+            if (kk < lkey) lkey = kk;
+          }
         }
       }
+      key = wave_umin_u(lkey);
+      if (key != kNone) {
+        const double b = (double)(key >> 16) + 0.5;
+        bound = b * b;
+      }
     }
-    key = wave_umin_u(key);
   }
   if (rec_unv) atomicAnd(&vis[rj >> 5], ~(1u << (rj & 31)));
   // record candidates on lanes < s, the off-record candidate on its own
-  uint32_t rd = 0;
-  float rv = 0.f;
-  if (rec_unv) {
-    rd = dist_xy(D, cur, (int)rj);
-    rv = __uint_as_float(pr.y) * D.eta_tab[rd];
-  }
+  const uint32_t rd = rec_unv ? exact_dist(xc, yc, rxy.x, rxy.y) : 0u;
   const bool off = key != kNone;
-  const float ov = off ? tau0 * D.eta_tab[key >> 16] : 0.f;
+  const float re = D.eta_tab[rd];
+  const float oe = D.eta_tab[off ? key >> 16 : 0u];
+  const float rv = rec_unv ? __uint_as_float(pr.y) * re : 0.f;
+  const float ov = off ? tau0 * oe : 0.f;
   const uint64_t any_rec = __ballot(rec_unv);
   uint32_t mx = any_rec ? wave_umax_u(rec_unv ? __float_as_uint(rv) : 0u) : 0u;
   if (off && (!any_rec || __float_as_uint(ov) > mx)) mx = __float_as_uint(ov);
@@ -2218,7 +2353,7 @@ __global__ __launch_bounds__(1024) void k_construct_sync_spm(Dev D, Iter A) {
         p.next = (int)rdlane(rec.x, k);
         p.d = rdlane(rec.y, k);
       } else {
-        p = fallback_spm(D, vis, cur, lane, pr, tau0);
+        p = fallback_spm(D, vis, cur, lane, pr, tau0, n - t);
       }
       c_greedy += p.kind == 0;
       c_roul += p.kind == 1;
@@ -2444,7 +2579,7 @@ __global__ __launch_bounds__(256) void k_construct_async_spm(Dev D, Iter A) {
       p.next = (int)rdlane(rec.x, k);
       p.d = rdlane(rec.y, k);
     } else {
-      p = fallback_spm(D, vis, cur, lane, pr, tau0);
+      p = fallback_spm(D, vis, cur, lane, pr, tau0, n - t);
     }
     c_kind += 1ull << (21 * p.kind);
     if (p.kind == 2) c_fbu += (uint64_t)(n - t);
@@ -2652,7 +2787,7 @@ __device__ __forceinline__ void spm_ant_queued(const Dev &D, const Iter &A, int 
         int next, k;
         uint32_t d;
         if (__builtin_expect(umask == 0, 0)) {
-          const Pick p = fallback_spm(D, vis, cur, lane, pr, tau0);
+          const Pick p = fallback_spm(D, vis, cur, lane, pr, tau0, n - t);
           next = p.next;
           k = -1;
           d = p.d;
@@ -3188,6 +3323,22 @@ hipError_t launch_dist(const Dev &d, uint32_t *dmax, int r0, int rows, bool stor
                        hipStream_t s) {
   dim3 grid((d.ldn + 63) / 64, (rows + 3) / 4);
   hipLaunchKernelGGL(k_dist, grid, dim3(256), 0, s, d, dmax, r0, rows, store ? 1 : 0);
+  return hipGetLastError();
+}
+
+hipError_t launch_grid_box(const Dev &d, double *box, hipStream_t s) {
+  hipLaunchKernelGGL(k_grid_box, dim3(1), dim3(1024), 0, s, d, box);
+  return hipGetLastError();
+}
+
+hipError_t launch_grid(const Dev &d, int32_t *cnt, hipStream_t s) {
+  const size_t cells = (size_t)d.gnx * d.gny;
+  hipError_t e = hipMemsetAsync(cnt, 0, cells * sizeof(int32_t), s);
+  if (e != hipSuccess) return e;
+  const dim3 g((d.n + 255) / 256);
+  hipLaunchKernelGGL(k_grid_count, g, dim3(256), 0, s, d, cnt);
+  hipLaunchKernelGGL(k_grid_scan, dim3(1), dim3(1024), 0, s, d, cnt);
+  hipLaunchKernelGGL(k_grid_fill, g, dim3(256), 0, s, d, cnt);
   return hipGetLastError();
 }
 
