@@ -2697,6 +2697,19 @@ __device__ __forceinline__ uint32_t spm_apply_entries(const Dev &D, const Iter &
   return retries;
 }
 
+// Trail of this lane's candidate j from the record pairs on lanes 0..S-1:
+// slot I is broadcast over each row of 16 lanes by DPP (row_newbcast), from
+// the last slot to the first, so the first slot holding j is the one kept.
+template <int I>
+__device__ __forceinline__ void spm_trail_rows(uint2 pr, uint32_t j, float &t) {
+  if constexpr (I >= 0) {
+    const uint32_t node = (uint32_t)__builtin_amdgcn_mov_dpp((int)pr.x, 0x150 + I, 0xF, 0xF, true);
+    const uint32_t val = (uint32_t)__builtin_amdgcn_mov_dpp((int)pr.y, 0x150 + I, 0xF, 0xF, true);
+    t = j == node ? __uint_as_float(val) : t;
+    spm_trail_rows<I - 1>(pr, j, t);
+  }
+}
+
 // The ant of k_construct_async_spm_q.  Records come by buffer loads: the
 // candidates' {j, d, eta^beta} on lanes 0..cl-1, the selective record's
 // pairs on lanes 0..s-1 and its insert counter.  Before the record of cur is
@@ -2772,14 +2785,20 @@ __device__ __forceinline__ void spm_ant_queued(const Dev &D, const Iter &A, int 
             if (lane == slot) pr.x = (uint32_t)prev;
           }
         }
-        // the candidates' trails: the first slot holding j, else tau0
+        // the candidates' trails: the first slot holding j, else tau0.  With
+        // every candidate in lanes 0..15 a DPP row broadcast hands slot i to
+        // them (no scalar round trip); otherwise a lane read per slot.
         float tj = tau0;
+        if constexpr (L == 16 && S != 0) {
+          spm_trail_rows<S - 1>(pr, rec.x, tj);
+        } else {
 #pragma unroll
-        for (int i = (S ? S : kMaxSpmS) - 1; i >= 0; --i) {
-          if (S == 0 && i >= s) continue;
-          const uint32_t node = rdlane(pr.x, i);
-          const uint32_t val = rdlane(pr.y, i);
-          tj = rec.x == node ? __uint_as_float(val) : tj;
+          for (int i = (S ? S : kMaxSpmS) - 1; i >= 0; --i) {
+            if (S == 0 && i >= s) continue;
+            const uint32_t node = rdlane(pr.x, i);
+            const uint32_t val = rdlane(pr.y, i);
+            tj = rec.x == node ? __uint_as_float(val) : tj;
+          }
         }
         const uint32_t word = vis[__builtin_amdgcn_ubfe(rec.x, 5, 11)];
         const bool unv = !__builtin_amdgcn_ubfe(word, rec.x, 1);
