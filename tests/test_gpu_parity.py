@@ -331,6 +331,55 @@ def test_spm_async_tours_valid(acs, n, m):
     col.close()
 
 
+def _grid_instance(kind, n, seed):
+    if kind == "clustered":
+        return inputs.clustered(n, seed)
+    if kind == "line":
+        xy = inputs.uniform(n, seed)
+        xy[:, 1] = 5000.0  # every city on one horizontal line: a grid one cell high
+        return xy
+    # every location taken by four cities: distance 0 within a group, ties
+    # between the group's cities everywhere else
+    return np.ascontiguousarray(np.repeat(inputs.uniform(n // 4, seed), 4, axis=0))
+
+
+# The selective memory's fallback past its 128-city list searches a grid of
+# cells ring by ring (exact, ties to the lower index).  Short candidate lists
+# on instances where the list runs out often: clustered cities, cities on a
+# line (a grid one cell high) and coincident cities (distance 0).
+GRID_CASES = [
+    ("clustered_n600", "clustered", 600, dict(m=64, cl=4, spm_s=4), 3),
+    ("line_n400", "line", 400, dict(m=50, cl=4, spm_s=8), 3),
+    ("coincident_n320", "coincident", 320, dict(m=40, cl=3, spm_s=2), 3),
+]
+
+
+@pytest.mark.parametrize("name,kind,n,kw,iters", GRID_CASES, ids=[c[0] for c in GRID_CASES])
+def test_spm_grid_search_sync_parity(acs, name, kind, n, kw, iters):
+    _say(f"SPM grid search {name}")
+    xy = _grid_instance(kind, n, 900 + n)
+    col, orc = _pair(acs, xy, memory=1, seed=5, **kw)
+    for it in range(iters):
+        col.iterate(1)
+        orc.iterate(1)
+        _compare(col, orc, it)
+    assert col.stats()["fallback"] > 0
+    col.close()
+
+
+@pytest.mark.parametrize("kind", ["clustered", "line"])
+def test_spm_grid_search_single_ant_equals_oracle(acs, kind):
+    _say(f"SPM grid search, one asynchronous ant, {kind}")
+    xy = _grid_instance(kind, 500, 77)
+    col = acs.Colony(xy, m=1, cl=4, memory=1, spm_s=4, mode=acs.ACS_ASYNC_ATOMIC, seed=4)
+    orc = oracle.Oracle(xy, m=1, cl=4, memory=1, spm_s=4, seed=4)
+    for it in range(4):
+        col.iterate(1)
+        orc.iterate(1)
+        _compare(col, orc, it)
+    col.close()
+
+
 def test_spm_async_single_ant_equals_oracle(acs):
     xy = inputs.uniform(250, 6)
     col = acs.Colony(xy, m=1, cl=12, memory=1, spm_s=6, mode=acs.ACS_ASYNC_ATOMIC, seed=8)
