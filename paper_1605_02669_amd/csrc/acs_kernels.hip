@@ -626,9 +626,15 @@ __device__ __forceinline__ void far_bound_row(const Dev &D, const Iter &A, int i
   }
 }
 
-__global__ __launch_bounds__(256) void k_far_bound(Dev D, Iter A) {
+// ctau_rows: the wave of row i also copies that row's candidate pheromone
+// into ctau (k_ctau_in's work, for a construction with an updater wave).
+__global__ __launch_bounds__(256) void k_far_bound(Dev D, Iter A, int ctau_rows) {
   const int i = blockIdx.x * 4 + (threadIdx.x >> 6);
-  if (i < D.n) far_bound_row(D, A, i, threadIdx.x & 63);
+  const int lane = threadIdx.x & 63;
+  if (i >= D.n) return;
+  if (ctau_rows && lane < D.cl)
+    D.ctau[(size_t)i * D.cl + lane] = __uint_as_float(D.crec[(size_t)i * D.cl + lane].w);
+  far_bound_row(D, A, i, lane);
 }
 
 // The same for every instance of a batch that has a prefix (blockIdx.y =
@@ -3197,24 +3203,22 @@ __global__ __launch_bounds__(1024) void k_best(Dev D) {
     for (int p = threadIdx.x; p < n; p += blockDim.x) D.best[p] = D.tours[(size_t)ba * n + p];
 }
 
-// Eq. 4 on the best-so-far tour, dense memory: one thread per tour edge; the
-// 2n directed entries are distinct, so plain read-modify-writes suffice.
+// Eq. 4 on the best-so-far tour, dense memory: one wave per tour edge finds
+// both candidate positions with one coalesced load of each row; the 2n
+// directed entries are distinct, so plain read-modify-writes suffice.
 __global__ __launch_bounds__(256) void k_global_dense(Dev D, Iter A) {
-  const int p = blockIdx.x * blockDim.x + threadIdx.x;
+  const int lane = threadIdx.x & 63;
+  const int p = uni(blockIdx.x * 4 + (threadIdx.x >> 6));
   const int n = D.n;
   if (p >= n) return;
   const float ag = A.a_glob;
   const float bg = (float)(A.rho / (double)D.gstate[0]);
   const int u = D.best[p], v = D.best[p + 1 < n ? p + 1 : 0];
-  int ku = -1, kv = -1;
-  for (int k = 0; k < D.cl; ++k) {
-    if (D.crec[(size_t)u * D.cl + k].x == (uint32_t)v) ku = k;
-    if (D.crec[(size_t)v * D.cl + k].x == (uint32_t)u) kv = k;
+  const int ku = cand_pos(D, u, v, lane), kv = cand_pos(D, v, u, lane);
+  if (lane < 2) {
+    float *h = lane == 0 ? home(D, u, v, ku) : home(D, v, u, kv);
+    *h = fmaf(ag, *h, bg);
   }
-  float *h1 = home(D, u, v, ku);
-  float *h2 = home(D, v, u, kv);
-  *h1 = fmaf(ag, *h1, bg);
-  *h2 = fmaf(ag, *h2, bg);
 }
 
 // Eq. 4 with the selective memory, in the order of the tour: edge p updates
@@ -3425,8 +3429,11 @@ hipError_t launch_construct(const Dev &d, const Iter &it, int mode, int memory, 
   // value or a value its edge's other entry held from an equal start; the
   // unsynchronised ants that issue their own updates write f(forward value)
   // into a reverse entry that may differ from it, so they scan whole rows
-  if (memory == 0 && d.fpre && (mode != 2 || (lanes == 64 && queued))) {
-    hipLaunchKernelGGL(k_far_bound, dim3((d.n + 3) / 4), dim3(256), 0, s, d, it);
+  const bool queued_dense = memory == 0 && lanes == 64 && queued && (mode == 1 || mode == 2);
+  const bool far = memory == 0 && d.fpre && (mode != 2 || (lanes == 64 && queued));
+  if (far) {
+    hipLaunchKernelGGL(k_far_bound, dim3((d.n + 3) / 4), dim3(256), 0, s, d, it,
+                       queued_dense ? 1 : 0);
     const hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
   }
@@ -3474,7 +3481,7 @@ hipError_t launch_construct(const Dev &d, const Iter &it, int mode, int memory, 
                       (size_t)na * ((d.n + 31) / 32) * sizeof(uint32_t);
     const bool half = d.cl <= 32;
     const dim3 gc((d.n * d.cl + 255) / 256);
-    hipLaunchKernelGGL(k_ctau_in, gc, dim3(256), 0, s, d);
+    if (!far) hipLaunchKernelGGL(k_ctau_in, gc, dim3(256), 0, s, d);
     if (atomic && half)
       hipLaunchKernelGGL((k_construct_async_dense_q<true, true>), gq, bq, lq, s, d, it);
     else if (atomic)
@@ -3569,7 +3576,7 @@ hipError_t launch_best_global(const Dev &d, const Iter &it, int memory, hipStrea
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   if (memory == 0)
-    hipLaunchKernelGGL(k_global_dense, dim3((d.n + 255) / 256), dim3(256), 0, s, d, it);
+    hipLaunchKernelGGL(k_global_dense, dim3((d.n + 3) / 4), dim3(256), 0, s, d, it);
   else
     hipLaunchKernelGGL(k_global_spm, dim3((d.n + 3) / 4), dim3(256), 0, s, d, it);
   return hipGetLastError();
