@@ -253,6 +253,10 @@ SPM_CASES = [
     ("n201_m201_s4", 201, dict(cl=32, spm_s=4), 4),
     ("n150_m33_s1", 150, dict(m=33, cl=10, spm_s=1), 4),
     ("n97_m200_s16_q0", 97, dict(m=200, cl=20, spm_s=16, q0=0.0), 4),
+    # about 130 updates of each record in every step: the record's update
+    # list is longer than one wave and is gathered by scanning every
+    # registration instead
+    ("n6_m400_s2", 6, dict(m=400, cl=3, spm_s=2), 4),
 ]
 
 
