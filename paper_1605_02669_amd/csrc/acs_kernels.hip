@@ -2135,13 +2135,20 @@ __device__ __forceinline__ Pick fallback_spm(const Dev &D, uint32_t *vis, int cu
     const int cx = grid_cx(D, xc), cy = grid_cy(D, yc);
     const double fx = xc - (D.gx0 + cx * D.gh), fy = yc - (D.gy0 + cy * D.gh);
     // the margin covers rounding in the cell of a coordinate
-    const double edge =
-        fmax(0.0, fmin(fmin(fx, D.gh - fx), fmin(fy, D.gh - fy))) -
-        1e-9 * (fabs(D.gx0) + fabs(D.gy0) + D.gh * (double)(D.gnx + D.gny));
+    const double margin = 1e-9 * (fabs(D.gx0) + fabs(D.gy0) + D.gh * (double)(D.gnx + D.gny));
+    const double edge = fmax(0.0, fmin(fmin(fx, D.gh - fx), fmin(fy, D.gh - fy))) - margin;
+    // Every city of rings 0..r lies within (r + 1) * gh * sqrt(2) of cur.
+    // Where that is below d_last - 1/2 (d_last: the list's last distance),
+    // each such city is nearer than d_last, so it is on the list, and so
+    // visited or in the record: the search starts at the first ring that
+    // can hold anything else.
+    const uint32_t klast = D.xl <= 128 ? rdlane(D.xl - 1 < 64 ? e0 : e1, (D.xl - 1) & 63) : 0u;
+    const double reach = ((double)(klast >> 16) - 0.5 - margin) / (D.gh * 1.4142135623730951);
+    const int rfirst = reach > 1.0 ? (int)ceil(reach - 1.0) : 0;
     uint32_t lkey = kNone;
     double bound = INFINITY;  // (d + 1/2)^2 for the best key so far
     const int rmax = max(D.gnx, D.gny);
-    for (int r = 0; r <= rmax; ++r) {
+    for (int r = rfirst; r <= rmax; ++r) {
       if (key != kNone && r >= 1) {
         const double lb = (double)(r - 1) * D.gh + edge;
         if (lb > 0.0 && lb * lb >= bound) break;
@@ -2168,15 +2175,26 @@ __device__ __forceinline__ Pick fallback_spm(const Dev &D, uint32_t *vis, int cu
         if (ix < 0 || iy < 0 || ix >= D.gnx || iy >= D.gny) continue;
         const int c = iy * D.gnx + ix;
         const int p1 = D.gstart[c + 1];
-        for (int p = D.gstart[c]; p < p1; ++p) {
-          const uint32_t j = D.gcity[p];
-          if ((vis[j >> 5] >> (j & 31)) & 1u) continue;
-          const double2 cxy = D.gxy[p];
-          const double dx = xc - cxy.x, dy = yc - cxy.y;
-          if (dx * dx + dy * dy < bound) {
-            const uint32_t d = exact_dist(xc, yc, cxy.x, cxy.y);
-            const uint32_t kk = (d << 16) | j;
-            if (kk < lkey) lkey = kk;
+        // four cities of the cell per round, their loads issued together
+        for (int p = D.gstart[c]; p < p1; p += 4) {
+          uint32_t jq[4];
+          double2 cq[4];
+#pragma unroll
+          for (int u = 0; u < 4; ++u) {
+            const int pu = min(p + u, p1 - 1);
+            jq[u] = D.gcity[pu];
+            cq[u] = D.gxy[pu];
+          }
+#pragma unroll
+          for (int u = 0; u < 4; ++u) {
+            const uint32_t j = jq[u];
+            if (p + u >= p1 || ((vis[j >> 5] >> (j & 31)) & 1u)) continue;
+            const double dx = xc - cq[u].x, dy = yc - cq[u].y;
+            if (dx * dx + dy * dy < bound) {
+              const uint32_t d = exact_dist(xc, yc, cq[u].x, cq[u].y);
+              const uint32_t kk = (d << 16) | j;
+              if (kk < lkey) lkey = kk;
+            }
           }
         }
       }
