@@ -28,7 +28,7 @@ sys.path.insert(0, ROOT)
 METRIC = "ant construction steps/s at n=2392,m=n; tour gap vs plain ACS at equal time"
 HBM_PEAK_GBS = 8000.0
 N, CL = 2392, 32
-KERNEL = "k_construct_async_dense_q<true, true>"
+KERNEL = "k_construct_async_dense_q<true, true, true>"
 KERNEL_SOURCE = os.path.join(ROOT, "paper_1605_02669_amd", "csrc", "acs_kernels.hip")
 TRAFFIC_PROFILE = os.path.join(ROOT, "profiles", "k_construct_async_dense_q_n2392.md")
 

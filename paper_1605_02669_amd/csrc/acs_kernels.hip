@@ -1532,9 +1532,11 @@ __device__ __forceinline__ void ring_updater(const Dev &D, const Iter &A, const 
 // crossings go to the ring.  Records and their live pheromone (ctau) come by
 // buffer loads (the lane's offset fixed, the row's a scalar; a read outside
 // the table returns zeros instead of faulting).  HALF: every candidate list
-// fits lanes 0..31.  Decisions are the same as those of ant_async_dense.
+// fits lanes 0..31.  EVERY: every step has a local update (period 1), so
+// the per-step test drops out.  Decisions are the same as those of
+// ant_async_dense.
 // ---------------------------------------------------------------------------
-template <bool ATOMIC, bool HALF>
+template <bool ATOMIC, bool HALF, bool EVERY = false>
 __device__ __forceinline__ void ant_queued(const Dev &D, const Iter &A, int ant, uint32_t *vis,
                                            int lane, const QRing &q, int qw) {
   const int n = D.n, cl = D.cl;
@@ -1602,7 +1604,7 @@ __device__ __forceinline__ void ant_queued(const Dev &D, const Iter &A, int ant,
           k = -1;
           d = p.d;
           tv = __float_as_uint(p.tval);
-          if (upd & sb) e.w = wrlane((uint32_t)-3, tl, e.w);
+          if (EVERY || (upd & sb)) e.w = wrlane((uint32_t)-3, tl, e.w);
           ++c_fb;
           c_fbu += (uint64_t)(n - t);
         } else {
@@ -1638,7 +1640,7 @@ __device__ __forceinline__ void ant_queued(const Dev &D, const Iter &A, int ant,
           __hip_atomic_fetch_or(vis + (next >> 5), 1u << (next & 31), __ATOMIC_RELAXED,
                                 __HIP_MEMORY_SCOPE_WORKGROUP);
         tb = (int)wrlane((uint32_t)next, tl, (uint32_t)tb);
-        if (upd & sb) {
+        if (EVERY || (upd & sb)) {
           e.x = wrlane((uint32_t)cur | ((uint32_t)next << 16), tl, e.x);
           e.y = wrlane((uint32_t)k, tl, e.y);
           e.z = wrlane(tv, tl, e.z);
@@ -1677,7 +1679,7 @@ __device__ __forceinline__ void ant_queued(const Dev &D, const Iter &A, int ant,
 // host picks na so that every compute unit holds about the same number of
 // ants (the slowest unit sets the iteration time).  Dynamic LDS: the rings
 // of the na ant waves, then their visited bitmaps.
-template <bool ATOMIC, bool HALF>
+template <bool ATOMIC, bool HALF, bool EVERY>
 __global__ __launch_bounds__(64 * (kQAnts + 1)) void k_construct_async_dense_q(Dev D, Iter A) {
   extern __shared__ uint4 qsm[];
   __shared__ uint32_t qhd[kQAnts], qtl[kQAnts], qdone;
@@ -1698,7 +1700,7 @@ __global__ __launch_bounds__(64 * (kQAnts + 1)) void k_construct_async_dense_q(D
   uint32_t *vis = reinterpret_cast<uint32_t *>(qsm + (size_t)na * kQRing) +
                   wv * ((D.n + 31) >> 5);
   const int ant = uni(blockIdx.x * na + wv);
-  if (ant < D.m) ant_queued<ATOMIC, HALF>(D, A, ant, vis, lane, q, wv);
+  if (ant < D.m) ant_queued<ATOMIC, HALF, EVERY>(D, A, ant, vis, lane, q, wv);
   __atomic_signal_fence(__ATOMIC_SEQ_CST);
   if (lane == 0) atomicAdd(&qdone, 1u);
 }
@@ -3500,14 +3502,19 @@ hipError_t launch_construct(const Dev &d, const Iter &it, int mode, int memory, 
     const bool half = d.cl <= 32;
     const dim3 gc((d.n * d.cl + 255) / 256);
     if (!far) hipLaunchKernelGGL(k_ctau_in, gc, dim3(256), 0, s, d);
-    if (atomic && half)
-      hipLaunchKernelGGL((k_construct_async_dense_q<true, true>), gq, bq, lq, s, d, it);
-    else if (atomic)
-      hipLaunchKernelGGL((k_construct_async_dense_q<true, false>), gq, bq, lq, s, d, it);
-    else if (half)
-      hipLaunchKernelGGL((k_construct_async_dense_q<false, true>), gq, bq, lq, s, d, it);
-    else
-      hipLaunchKernelGGL((k_construct_async_dense_q<false, false>), gq, bq, lq, s, d, it);
+    const bool every = it.lperiod == 1;
+#define ACS_DENSE_Q(AT, HF, EV)                                                        \
+    if (atomic == AT && half == HF && every == EV)                                      \
+      hipLaunchKernelGGL((k_construct_async_dense_q<AT, HF, EV>), gq, bq, lq, s, d, it);
+    ACS_DENSE_Q(true, true, true)
+    ACS_DENSE_Q(true, true, false)
+    ACS_DENSE_Q(true, false, true)
+    ACS_DENSE_Q(true, false, false)
+    ACS_DENSE_Q(false, true, true)
+    ACS_DENSE_Q(false, true, false)
+    ACS_DENSE_Q(false, false, true)
+    ACS_DENSE_Q(false, false, false)
+#undef ACS_DENSE_Q
     const hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(k_ctau_out, gc, dim3(256), 0, s, d, atomic ? 1 : 0);
