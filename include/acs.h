@@ -134,8 +134,11 @@ typedef struct acs_stats {
                                 cities the greedy scan had to consider */
   int64_t cas_retries;       /* local-update compare-and-swaps that found
                                 the entry changed and were repeated */
-  double construct_ms;       /* device time of the construction kernels of
-                                the last acs_iterate call (HIP events) */
+  double construct_ms;       /* device time of the construction kernel
+                                launches of the last acs_iterate call: HIP
+                                events recorded right around each one, so
+                                the small bound and copy kernels beside it
+                                are not counted (iterate_ms has them) */
   int32_t construct_launches;/* construction launches of that call */
   int32_t pad1;
   double iterate_ms;         /* device time of the whole last acs_iterate */

@@ -475,11 +475,11 @@ int iterate_handle(acs_t *h, int32_t k) {
   for (int i = 0; i < k; ++i) {
     acs::Iter it = h->base;
     it.it = h->iter + (uint32_t)i;
-    if (h->timed) HIP_TRY(hipEventRecord(h->ev[2 * i], h->stream));
     HIP_TRY(acs::launch_construct(h->dev, it, (int)h->p.mode, (int)h->p.memory,
                                   h->p.lanes_per_ant ? (int)h->p.lanes_per_ant : 64,
-                                  queued_kind(h), h->stream));
-    if (h->timed) HIP_TRY(hipEventRecord(h->ev[2 * i + 1], h->stream));
+                                  queued_kind(h), h->stream,
+                                  h->timed ? h->ev[2 * i] : nullptr,
+                                  h->timed ? h->ev[2 * i + 1] : nullptr));
     if (h->p.local_search) HIP_TRY(acs::launch_local_search(h->dev, h->stream));
     HIP_TRY(acs::launch_best_global(h->dev, it, (int)h->p.memory, h->stream));
   }

@@ -114,9 +114,12 @@ hipError_t launch_init_pheromone(const Dev &d, float tau0, hipStream_t s);
 // block).  lanes: lanes per ant of the asynchronous
 // dense kernels (64, 32 or 16; at least cl).  queued (asynchronous, 64
 // lanes per ant): 0 the ant issues its own local updates; 1 it hands them to
-// an updater wave per block.
+// an updater wave per block.  ev0 / ev1, when not null, are recorded on s
+// right before and after the construction kernel (not around the bound,
+// buffer and live-pheromone copy kernels launched beside it).
 hipError_t launch_construct(const Dev &d, const Iter &it, int mode, int memory, int lanes,
-                            int queued, hipStream_t s);
+                            int queued, hipStream_t s, hipEvent_t ev0 = nullptr,
+                            hipEvent_t ev1 = nullptr);
 // Largest m a synchronous launch can keep resident for this instance.
 int max_sync_ants(const Dev &d, int memory);
 hipError_t launch_best_global(const Dev &d, const Iter &it, int memory,

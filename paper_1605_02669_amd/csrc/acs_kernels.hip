@@ -3444,7 +3444,10 @@ static hipError_t queued_ants_per_block(int m, int *na) {
 }
 
 hipError_t launch_construct(const Dev &d, const Iter &it, int mode, int memory, int lanes,
-                            int queued, hipStream_t s) {
+                            int queued, hipStream_t s, hipEvent_t ev0, hipEvent_t ev1) {
+  // ev0 / ev1 (optional) bracket the construction kernel itself, so that
+  // their interval leaves out the bound, buffer and copy kernels beside it
+  auto mark = [s](hipEvent_t e) { return e ? hipEventRecord(e, s) : hipSuccess; };
   // the fallback prefix's bound holds where every update maps an entry's own
   // value or a value its edge's other entry held from an equal start; the
   // unsynchronised ants that issue their own updates write f(forward value)
@@ -3459,13 +3462,16 @@ hipError_t launch_construct(const Dev &d, const Iter &it, int mode, int memory, 
   }
   if (mode == 3) {
     const size_t words = (size_t)d.m * ((d.n + 31) / 32);
+    const hipError_t me = mark(ev0);
+    if (me != hipSuccess) return me;
     if (words <= (size_t)kSeqLdsWords)
       hipLaunchKernelGGL(k_construct_seq_dense<true>, dim3(1), dim3(64 * kSeqWaves),
                          words * sizeof(uint32_t), s, d, it);
     else
       hipLaunchKernelGGL(k_construct_seq_dense<false>, dim3(1), dim3(64 * kSeqWaves), 0, s, d,
                          it);
-    return hipGetLastError();
+    const hipError_t e = hipGetLastError();
+    return e != hipSuccess ? e : mark(ev1);
   }
   if (mode == 0) {
     const int apb = kSyncBlock / 64;
@@ -3482,8 +3488,11 @@ hipError_t launch_construct(const Dev &d, const Iter &it, int mode, int memory, 
       const hipError_t e = hipGetLastError();
       if (e != hipSuccess) return e;
     }
-    const hipError_t e = hipLaunchCooperativeKernel(fn, dim3(grid), dim3(kSyncBlock), args,
-                                                    lds_bytes(d, kSyncBlock), s);
+    const hipError_t me = mark(ev0);
+    if (me != hipSuccess) return me;
+    hipError_t e = hipLaunchCooperativeKernel(fn, dim3(grid), dim3(kSyncBlock), args,
+                                              lds_bytes(d, kSyncBlock), s);
+    if (e == hipSuccess) e = mark(ev1);
     if (e != hipSuccess || !dbuf || (d.n & 1) == 0) return e;
     hipLaunchKernelGGL(k_sync_buf, gb, dim3(256), 0, s, d, 1);
     return hipGetLastError();
@@ -3502,6 +3511,8 @@ hipError_t launch_construct(const Dev &d, const Iter &it, int mode, int memory, 
     const bool half = d.cl <= 32;
     const dim3 gc((d.n * d.cl + 255) / 256);
     if (!far) hipLaunchKernelGGL(k_ctau_in, gc, dim3(256), 0, s, d);
+    const hipError_t me = mark(ev0);
+    if (me != hipSuccess) return me;
     const bool every = it.lperiod == 1;
 #define ACS_DENSE_Q(AT, HF, EV)                                                        \
     if (atomic == AT && half == HF && every == EV)                                      \
@@ -3515,10 +3526,15 @@ hipError_t launch_construct(const Dev &d, const Iter &it, int mode, int memory, 
     ACS_DENSE_Q(false, false, true)
     ACS_DENSE_Q(false, false, false)
 #undef ACS_DENSE_Q
-    const hipError_t e = hipGetLastError();
+    hipError_t e = hipGetLastError();
+    if (e == hipSuccess) e = mark(ev1);
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(k_ctau_out, gc, dim3(256), 0, s, d, atomic ? 1 : 0);
-  } else if (memory == 0 && lanes < 64) {
+    return hipGetLastError();
+  }
+  const hipError_t me = mark(ev0);
+  if (me != hipSuccess) return me;
+  if (memory == 0 && lanes < 64) {
     const int g = 64 / lanes;
     const dim3 gg((d.m + apb * g - 1) / (apb * g));
     const size_t lg = lds * g;
@@ -3572,7 +3588,8 @@ hipError_t launch_construct(const Dev &d, const Iter &it, int mode, int memory, 
       hipLaunchKernelGGL(k_construct_async_spm<false>, dim3(grid), dim3(kAsyncBlock), lds, s, d,
                          it);
   }
-  return hipGetLastError();
+  const hipError_t e = hipGetLastError();
+  return e != hipSuccess ? e : mark(ev1);
 }
 
 int max_sync_ants(const Dev &d, int memory) {
