@@ -9,7 +9,8 @@
 //   B (32 x 16): lane l holds B[8 (l / 16) + 0..7][l % 16]
 //   D (16 x 16): lane l holds D[4 (l / 16) + 0..3][l % 16]
 // Weights are kept in fp32 (master copy, optimizer state) and rounded to
-// bf16 when staged into LDS; activations are rounded to bf16 between layers.
+// bf16 when a wave loads its operand tiles; activations are rounded to bf16
+// between layers.
 //
 // Parameter vector (floats): W1[4][64] | b1[64] | W2[64][64] | b2[64] |
 // W3[64] | b3[1] (row-major, x @ W + b).
@@ -22,101 +23,40 @@ namespace {
 
 typedef __attribute__((__vector_size__(8 * sizeof(__bf16)))) __bf16 bf16x8;
 typedef __attribute__((__vector_size__(4 * sizeof(float)))) float f32x4;
+typedef __attribute__((__vector_size__(2 * sizeof(__bf16)))) __bf16 bf16x2;
+typedef __attribute__((__vector_size__(2 * sizeof(float)))) float f32x2;
+// an operand as four dwords: bf16 entries 2p (low half) and 2p + 1 (high
+// half) share dword p
+typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
 
 constexpr int H = 64;
 constexpr int OW1 = 0, OB1 = 256, OW2 = 320, OB2 = 4416, OW3 = 4480, OB3 = 4544;
 
-// Weights staged in LDS, transposed so that a B operand is one 16-byte read:
-//   w1t[n][k]  (64 x 32, k >= 4 zero)        B[k][n] = W1[k][n]
-//   w2t[n][k]  (64 x 64)                      B[k][n] = W2[k][n]
-//   w2r[n][k]  (64 x 64) = W2 row-major       B[k][n] = W2[n][k]   (W2^T)
-//   w3t[n][k]  (16 x 64, n >= 1 zero)         B[k][n] = W3[k]
-struct alignas(16) Stage {
-  __bf16 w1t[H * 32];
-  __bf16 w2t[H * H];
-  __bf16 w2r[H * H];
-  __bf16 w3t[16 * H];
-  float b1[H], b2[H], w3[H], b3;
-};
-
-__device__ __forceinline__ void stage_weights(Stage &S, const float *P) {
-  for (int e = threadIdx.x; e < H * 32; e += blockDim.x) {
-    const int n = e / 32, k = e % 32;
-    S.w1t[e] = (__bf16)(k < 4 ? P[OW1 + k * H + n] : 0.f);
-  }
-  for (int e = threadIdx.x; e < H * H; e += blockDim.x) {
-    const int n = e / H, k = e % H;
-    S.w2t[e] = (__bf16)P[OW2 + k * H + n];
-    S.w2r[e] = (__bf16)P[OW2 + e];
-  }
-  for (int e = threadIdx.x; e < 16 * H; e += blockDim.x) {
-    const int n = e / H, k = e % H;
-    S.w3t[e] = (__bf16)(n == 0 ? P[OW3 + k] : 0.f);
-  }
-  for (int e = threadIdx.x; e < H; e += blockDim.x) {
-    S.b1[e] = P[OB1 + e];
-    S.b2[e] = P[OB2 + e];
-    S.w3[e] = P[OW3 + e];
-  }
-  if (threadIdx.x == 0) S.b3 = P[OB3];
-  __syncthreads();
-}
-
-// The lanes of a wave exchange activations through LDS.  LDS operations of
-// one wave complete in issue order; this keeps the compiler from moving LDS
-// accesses across the exchange points.
-__device__ __forceinline__ void wave_sync() {
-  __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
-  __builtin_amdgcn_wave_barrier();
-}
-
-__device__ __forceinline__ bf16x8 ld8(const __bf16 *p) {
-  return *reinterpret_cast<const bf16x8 *>(p);
-}
-
 __device__ __forceinline__ f32x4 mfma(bf16x8 a, bf16x8 b, f32x4 c) {
   return __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, c, 0, 0, 0);
 }
+__device__ __forceinline__ f32x4 mfma(bf16x8 a, u32x4 b, f32x4 c) {
+  return mfma(a, __builtin_bit_cast(bf16x8, b), c);
+}
+__device__ __forceinline__ f32x4 mfma(u32x4 a, bf16x8 b, f32x4 c) {
+  return mfma(__builtin_bit_cast(bf16x8, a), b, c);
+}
+__device__ __forceinline__ f32x4 mfma(u32x4 a, u32x4 b, f32x4 c) {
+  return mfma(__builtin_bit_cast(bf16x8, a), __builtin_bit_cast(bf16x8, b), c);
+}
 
-// Forward pass of 16 rows held by one wave.  x: this lane's row features
-// (valid in lane group 0).  Writes relu activations (bf16, row-major
-// [16][64]) to h1 and h2 and returns the logit of rows 4g + v in z[v] for
-// lanes with l % 16 == 0.
-__device__ __forceinline__ f32x4 forward16(const Stage &S, float4 x, int lane, __bf16 *h1,
-                                           __bf16 *h2) {
-  const int g = lane >> 4, c16 = lane & 15;
-  bf16x8 a1;
-  for (int q = 0; q < 8; ++q) a1[q] = (__bf16)0.f;
-  if (g == 0) {
-    a1[0] = (__bf16)x.x;
-    a1[1] = (__bf16)x.y;
-    a1[2] = (__bf16)x.z;
-    a1[3] = (__bf16)x.w;
-  }
-  const f32x4 zero = {0.f, 0.f, 0.f, 0.f};
-#pragma unroll
-  for (int t = 0; t < 4; ++t) {
-    const f32x4 d = mfma(a1, ld8(S.w1t + (16 * t + c16) * 32 + 8 * g), zero);
-#pragma unroll
-    for (int v = 0; v < 4; ++v)
-      h1[(4 * g + v) * H + 16 * t + c16] = (__bf16)fmaxf(d[v] + S.b1[16 * t + c16], 0.f);
-  }
-  wave_sync();
-  const bf16x8 a2a = ld8(h1 + c16 * H + 8 * g), a2b = ld8(h1 + c16 * H + 32 + 8 * g);
-#pragma unroll
-  for (int t = 0; t < 4; ++t) {
-    f32x4 d = mfma(a2a, ld8(S.w2t + (16 * t + c16) * H + 8 * g), zero);
-    d = mfma(a2b, ld8(S.w2t + (16 * t + c16) * H + 32 + 8 * g), d);
-#pragma unroll
-    for (int v = 0; v < 4; ++v)
-      h2[(4 * g + v) * H + 16 * t + c16] = (__bf16)fmaxf(d[v] + S.b2[16 * t + c16], 0.f);
-  }
-  wave_sync();
-  const bf16x8 a3a = ld8(h2 + c16 * H + 8 * g), a3b = ld8(h2 + c16 * H + 32 + 8 * g);
-  f32x4 d = mfma(a3a, ld8(S.w3t + c16 * H + 8 * g), zero);
-  d = mfma(a3b, ld8(S.w3t + c16 * H + 32 + 8 * g), d);
-  for (int v = 0; v < 4; ++v) d[v] += S.b3;
-  return d;
+// two floats rounded to bf16 (to nearest, ties to even) in one dword, a in
+// the low half; and the two halves back as floats
+__device__ __forceinline__ unsigned pk2(float a, float b) {
+  return __builtin_bit_cast(unsigned, __builtin_convertvector((f32x2){a, b}, bf16x2));
+}
+__device__ __forceinline__ float lo_f(unsigned w) { return __uint_as_float(w << 16); }
+__device__ __forceinline__ float hi_f(unsigned w) { return __uint_as_float(w & 0xffff0000u); }
+
+// max(x, 0) as one integer max on the bits: a float with the sign bit set
+// (negative, or -0) is a negative integer and becomes +0
+__device__ __forceinline__ float relu(float x) {
+  return __int_as_float(max(__float_as_int(x), 0));
 }
 
 // Inference with everything in registers.  The products are computed
@@ -125,14 +65,15 @@ __device__ __forceinline__ f32x4 forward16(const Stage &S, float4 x, int lane, _
 // once the K index of that layer is permuted to match: within K block b,
 // B-row 8g + q is hidden unit 32b + 4g + q for q < 4 and 32b + 16 + 4g +
 // (q - 4) for q >= 4.  The weight tiles (A operands) are built in that
-// order once per wave.  The 64 -> 1 layer runs on the vector unit, on the
-// bf16-rounded activations, and the four lane groups' partial sums meet by
-// lane swaps.  No LDS.
+// order once per wave.  The biases start the accumulators.  The 64 -> 1
+// layer is one more product whose A operand repeats W3 in all 16 rows, so
+// that every lane of a row receives the row's logit.  No LDS.
 struct RegNet {
   bf16x8 w1[4];     // A of layer 1, tile t: W1^T[16t + l%16][8(l/16) + q] (k < 4)
   bf16x8 w2[4][2];  // A of layer 2, tile t, K block b (permuted K)
-  float b1[4][4], b2[4][4], w3[4][4];  // [t][v] at hidden 16t + 4(l/16) + v
-  float b3;
+  bf16x8 w3[2];     // A of layer 3, K block b: W3[perm_k(b, l/16, q)] in every row
+  f32x4 b1[4], b2[4];  // [t][v] at hidden 16t + 4(l/16) + v
+  f32x4 b3;            // b3 in every entry
 };
 
 __device__ __forceinline__ int perm_k(int b, int g, int q) {
@@ -158,51 +99,46 @@ __device__ __forceinline__ void load_regnet(RegNet &R, const float *P, int lane)
       const int h = 16 * t + 4 * g + v;
       R.b1[t][v] = P[OB1 + h];
       R.b2[t][v] = P[OB2 + h];
-      R.w3[t][v] = (float)(__bf16)P[OW3 + h];
     }
   }
-  R.b3 = P[OB3];
+#pragma unroll
+  for (int b = 0; b < 2; ++b)
+#pragma unroll
+    for (int q = 0; q < 8; ++q) R.w3[b][q] = (__bf16)P[OW3 + perm_k(b, g, q)];
+  const float b3 = P[OB3];
+  R.b3 = (f32x4){b3, b3, b3, b3};
 }
 
 // Logit of row l % 16 of a 16-row tile (every lane of the row's four lane
-// groups gets it); x: the row's features.
-__device__ __forceinline__ float forward16r(const RegNet &R, float4 x, int lane) {
+// groups gets it); x: the row's features.  Also leaves the activations as
+// the gradient needs them: h1 and h2 = H1^T and H2^T as B operands (K
+// blocks 0 and 1), so entry 4(t & 1) + v of block t >> 1 is hidden unit
+// 16t + 4(l/16) + v of the row.
+__device__ __forceinline__ float forward16r(const RegNet &R, float4 x, int lane, u32x4 h1[2],
+                                            u32x4 h2[2]) {
   const int g = lane >> 4;
-  bf16x8 bx;
-#pragma unroll
-  for (int q = 0; q < 8; ++q) bx[q] = (__bf16)0.f;
-  if (g == 0) {
-    bx[0] = (__bf16)x.x;
-    bx[1] = (__bf16)x.y;
-    bx[2] = (__bf16)x.z;
-    bx[3] = (__bf16)x.w;
-  }
-  const f32x4 zero = {0.f, 0.f, 0.f, 0.f};
-  bf16x8 h1[2];
+  const u32x4 bx = g == 0 ? (u32x4){pk2(x.x, x.y), pk2(x.z, x.w), 0u, 0u} : (u32x4){0u, 0u, 0u, 0u};
 #pragma unroll
   for (int t = 0; t < 4; ++t) {
-    const f32x4 d = mfma(R.w1[t], bx, zero);
-#pragma unroll
-    for (int v = 0; v < 4; ++v) h1[t >> 1][4 * (t & 1) + v] = (__bf16)fmaxf(d[v] + R.b1[t][v], 0.f);
+    const f32x4 d = mfma(R.w1[t], bx, R.b1[t]);
+    h1[t >> 1][2 * (t & 1)] = pk2(relu(d[0]), relu(d[1]));
+    h1[t >> 1][2 * (t & 1) + 1] = pk2(relu(d[2]), relu(d[3]));
   }
-  float part = 0.f;
 #pragma unroll
   for (int t = 0; t < 4; ++t) {
-    f32x4 d = mfma(R.w2[t][0], h1[0], zero);
+    f32x4 d = mfma(R.w2[t][0], h1[0], R.b2[t]);
     d = mfma(R.w2[t][1], h1[1], d);
-#pragma unroll
-    for (int v = 0; v < 4; ++v)
-      part = fmaf((float)(__bf16)fmaxf(d[v] + R.b2[t][v], 0.f), R.w3[t][v], part);
+    h2[t >> 1][2 * (t & 1)] = pk2(relu(d[0]), relu(d[1]));
+    h2[t >> 1][2 * (t & 1) + 1] = pk2(relu(d[2]), relu(d[3]));
   }
-  // sum over the four lane groups: each swap pairs a lane with its partner,
-  // and the two results of a swap add up to own + partner
-  const auto a = __builtin_amdgcn_permlane16_swap(__float_as_uint(part), __float_as_uint(part),
-                                                  false, false);
-  part = __uint_as_float(a[0]) + __uint_as_float(a[1]);
-  const auto b = __builtin_amdgcn_permlane32_swap(__float_as_uint(part), __float_as_uint(part),
-                                                  false, false);
-  part = __uint_as_float(b[0]) + __uint_as_float(b[1]);
-  return part + R.b3;
+  f32x4 z = mfma(R.w3[0], h2[0], R.b3);
+  z = mfma(R.w3[1], h2[1], z);
+  return z[0];
+}
+
+__device__ __forceinline__ float forward16r(const RegNet &R, float4 x, int lane) {
+  u32x4 h1[2], h2[2];
+  return forward16r(R, x, lane, h1, h2);
 }
 
 __device__ __forceinline__ float4 load_x(const float *X, int row, int rows) {
@@ -210,8 +146,8 @@ __device__ __forceinline__ float4 load_x(const float *X, int row, int rows) {
                     : make_float4(0.f, 0.f, 0.f, 0.f);
 }
 
-// Logits of `rows` feature rows: four waves per block share the staged
-// weights; each wave takes 16-row tiles with its own activation buffers.
+// Logits of `rows` feature rows: each wave builds its weight tiles in
+// registers and takes two 16-row tiles per pass.
 constexpr int kFwdWaves = 4;
 
 __global__ __launch_bounds__(64 * kFwdWaves) void k_prior_forward(const float *P, const float *X,
@@ -237,145 +173,188 @@ __global__ __launch_bounds__(64 * kFwdWaves) void k_prior_forward(const float *P
 }
 
 // Gradient of the mean binary cross-entropy (with logits) over all `rows`
-// rows, accumulated into G; loss sum into *L.  kGradWaves waves per block
-// share the staged weights; each wave takes 32-row tiles (two 16-row
-// forward passes) with its own buffers.  dW2 = H1^T dH2 and dH1 = dH2 W2^T
-// run on the matrix cores; the 4-wide first layer, the 64 -> 1 last layer
-// and the biases on the vector units.  The waves' partial sums meet in LDS,
-// and each block adds its total to G once per parameter.
-constexpr int kGradWaves = 3;
+// rows, accumulated into G; loss sum into *L.  Each wave takes 32-row tiles
+// (two 16-row halves) and keeps everything in registers:
+//   forward   as in inference, the products transposed (rows across lanes);
+//   dH2       dz w3 masked by H2 > 0, lane by lane; dW3, db2, db3 as
+//             lane-local sums on the vector unit;
+//   turn      H1 and dH2 turned around (rows within a lane);
+//   dH1       dH2 W2^T on the matrix cores, masked by H1 > 0;
+//   dW2       H1^T dH2 on the matrix cores, K = the tile's 32 rows;
+//   dW1, db1  dH1^T [X 1] on the matrix cores, dH1 carried as a sum of two
+//             bf16 values (16 significant bits) against the bf16 inputs.
+// A product with a 0/1 selection matrix turns a 16 x 16 block around
+// exactly: each sum has one nonzero term, a bf16 value times 1.  Afterwards
+// lane l holds rows 4(l/16) + v of one hidden unit, and the two halves give
+// the eight rows of an operand.  The lanes' and waves' partial sums meet in
+// LDS at the end, and each block adds its total to G once per parameter.
+constexpr int kGradWaves = 4;
 
-struct GradWave {
-  __bf16 h1[32 * H];    // row-major activations of the first hidden layer
-  __bf16 h2[32 * H];    // second hidden layer, then (in place) dL/dH2
-  __bf16 h1t[H * 32];   // H1^T [feature][row]: each feature's four 8-row
-  __bf16 dh2t[H * 32];  //   chunks in the order chunk ^ ((feature >> 2) & 3), so
-                        //   the transposing stores of 64 features spread over
-                        //   more banks while a chunk stays one 16-byte load
-  float zs[32], dzs[32], xs[32 * 4];
-};
+// B operand that picks hidden units 16 (2b + odd) + l % 16 out of K block b
+// of a transposed tile (the inverse of perm_k).
+__device__ __forceinline__ bf16x8 pick_tile(int lane, int odd) {
+  const int g = lane >> 4, c16 = lane & 15;
+  bf16x8 s;
+#pragma unroll
+  for (int q = 0; q < 8; ++q)
+    s[q] = (__bf16)(g == (c16 >> 2) && q == 4 * odd + (c16 & 3) ? 1.f : 0.f);
+  return s;
+}
 
 __global__ __launch_bounds__(64 * kGradWaves) void k_prior_grad(const float *P, const float *X,
                                                                 const float *Y, int rows,
                                                                 float *G, float *L) {
-  __shared__ Stage S;
-  __shared__ union alignas(16) {
-    GradWave w[kGradWaves];
-    float red[kPriorParams + 1];  // block totals (the last entry: loss)
-  } U;
-  stage_weights(S, P);
+  __shared__ float red[kPriorParams + 1];  // block totals (the last entry: loss)
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   const int g = lane >> 4, c16 = lane & 15;
-  GradWave &B = U.w[wv];
-  __bf16 *h1 = B.h1, *h2 = B.h2, *dh2 = B.h2, *h1t = B.h1t, *dh2t = B.dh2t;
-  float *zs = B.zs, *dzs = B.dzs, *xs = B.xs;
+  for (int e = threadIdx.x; e <= kPriorParams; e += blockDim.x) red[e] = 0.f;
+  RegNet R;
+  load_regnet(R, P, lane);
+  // B of dH1 = dH2 W2^T, tile t, K block b: W2[16t + l%16][perm_k(b, g, q)]
+  bf16x8 w2b[4][2];
+#pragma unroll
+  for (int t = 0; t < 4; ++t)
+#pragma unroll
+    for (int b = 0; b < 2; ++b)
+#pragma unroll
+      for (int q = 0; q < 8; ++q)
+        w2b[t][b][q] = (__bf16)P[OW2 + (16 * t + c16) * H + perm_k(b, g, q)];
+  float w3[4][4];  // W3 (bf16) at hidden 16t + 4g + v
+#pragma unroll
+  for (int t = 0; t < 4; ++t)
+#pragma unroll
+    for (int v = 0; v < 4; ++v) w3[t][v] = (float)(__bf16)P[OW3 + 16 * t + 4 * g + v];
+  const bf16x8 pick0 = pick_tile(lane, 0), pick1 = pick_tile(lane, 1);
+  bf16x8 pickx;  // B operand that picks input column l % 16 (identity)
+#pragma unroll
+  for (int q = 0; q < 8; ++q) pickx[q] = (__bf16)(8 * g + q == c16 ? 1.f : 0.f);
   const float inv_rows = 1.f / (float)rows;
-  f32x4 gw2[4][4];
+  const f32x4 zero = {0.f, 0.f, 0.f, 0.f};
+  f32x4 gw2[4][4];  // dW2[16mt + 4g + v][16nt + l%16]
+#pragma unroll
   for (int a = 0; a < 4; ++a)
-    for (int b = 0; b < 4; ++b) gw2[a][b] = (f32x4){0.f, 0.f, 0.f, 0.f};
-  float gw1[4][4] = {};  // [nt][input] partials for feature 16 nt + c16
-  float gb1[4] = {};
-  float gw3 = 0.f, gb2 = 0.f, gb3 = 0.f, loss = 0.f;  // lane = feature
-  const float w3f = (float)S.w3t[lane];  // W3 as the forward pass used it (bf16)
+#pragma unroll
+    for (int b = 0; b < 4; ++b) gw2[a][b] = zero;
+  // [dW1; db1]^T[16mt + 4g + v][c] at lane column c = l%16 (c < 4: input c;
+  // c = 4: the bias)
+  f32x4 gw1[4] = {zero, zero, zero, zero};
+  // lane-local partial sums at hidden 16t + 4g + v over the lane's rows
+  float gw3[4][4] = {}, gb2[4][4] = {};
+  float gb3 = 0.f, loss = 0.f;  // lanes 0..15 only (one lane per row)
 
-  for (int r0 = (blockIdx.x * kGradWaves + wv) * 32; r0 < rows;
-       r0 += gridDim.x * kGradWaves * 32) {
-    wave_sync();
-    // forward of two 16-row halves; the first layer's inputs are kept as the
-    // bf16 values the matrix cores multiplied (for its weight gradient)
-    for (int hf = 0; hf < 2; ++hf) {
-      const int row = r0 + 16 * hf + c16;
-      const float4 x = load_x(X, row, rows);
-      if (g == 0) {
-        xs[(16 * hf + c16) * 4 + 0] = (float)(__bf16)x.x;
-        xs[(16 * hf + c16) * 4 + 1] = (float)(__bf16)x.y;
-        xs[(16 * hf + c16) * 4 + 2] = (float)(__bf16)x.z;
-        xs[(16 * hf + c16) * 4 + 3] = (float)(__bf16)x.w;
-      }
-      const f32x4 z = forward16(S, x, lane, h1 + 16 * hf * H, h2 + 16 * hf * H);
-      if (c16 == 0)
-        for (int v = 0; v < 4; ++v) zs[16 * hf + 4 * g + v] = z[v];
+  const int stride = gridDim.x * kGradWaves * 32;
+  int r0 = (blockIdx.x * kGradWaves + wv) * 32;
+  float4 xn[2];
+  float yn[2];
+#pragma unroll
+  for (int hf = 0; hf < 2; ++hf) {
+    const int row = r0 + 16 * hf + c16;
+    xn[hf] = load_x(X, row, rows);
+    yn[hf] = row < rows ? Y[row] : 0.f;
+  }
+  for (; r0 < rows; r0 += stride) {
+    const float4 x[2] = {xn[0], xn[1]};
+    const float y[2] = {yn[0], yn[1]};
+#pragma unroll
+    for (int hf = 0; hf < 2; ++hf) {  // the next tile's rows, loaded ahead
+      const int row = r0 + stride + 16 * hf + c16;
+      xn[hf] = load_x(X, row, rows);
+      yn[hf] = row < rows ? Y[row] : 0.f;
     }
-    wave_sync();
-    // dz = (sigmoid(z) - y) / rows, loss = softplus(z) - y z (rows past the end: 0)
-    if (lane < 32) {
-      const int row = r0 + lane;
+    // operands over the tile's 32 rows: K position 8g + q is row 4g + q of
+    // the first half (q < 4) or row 4g + q - 4 of the second
+    u32x4 ah1[4], bdh2[4], adh1[4], adh1l[4], bx;
+#pragma unroll
+    for (int hf = 0; hf < 2; ++hf) {
+      u32x4 h1[2], h2[2], dh2[2];
+      const float z = forward16r(R, x[hf], lane, h1, h2);
+      // dz = (sigmoid(z) - y) / rows, loss = softplus(z) - y z (rows past
+      // the end: 0); the reciprocal and logarithm of the vector unit (about
+      // 1 ulp) are ample for a training signal
+      const int row = r0 + 16 * hf + c16;
       float dz = 0.f;
       if (row < rows) {
-        const float z = zs[lane], y = Y[row];
-        dz = (1.f / (1.f + __expf(-z)) - y) * inv_rows;
-        loss += fmaxf(z, 0.f) + log1pf(__expf(-fabsf(z))) - y * z;
+        const float e = __expf(-fabsf(z));
+        const float sg = __builtin_amdgcn_rcpf(1.f + e);  // sigmoid(|z|)
+        dz = ((z >= 0.f ? sg : e * sg) - y[hf]) * inv_rows;
+        if (g == 0) loss += fmaxf(z, 0.f) + __logf(1.f + e) - y[hf] * z;
       }
-      dzs[lane] = dz;
-    }
-    wave_sync();
-    // last layer and dH2 (lane = feature f), dH2 written over H2 in place
-    {
-      const int f = lane;
-      // unrolled by 8 so the rows' LDS loads and stores overlap (1.17 ->
-      // 0.73 ms per 4.2 M rows; full unrolling is no faster than none)
-#pragma unroll 8
-      for (int r = 0; r < 32; ++r) {
-        const float hv = (float)h2[r * H + f];
-        const float dz = dzs[r];
-        gw3 += hv * dz;
-        const float dh = hv > 0.f ? dz * w3f : 0.f;
-        gb2 += dh;
-        dh2[r * H + f] = (__bf16)dh;
-        const int rs = r ^ (8 * ((f >> 2) & 3));  // 16-byte chunks swizzled by feature
-        dh2t[f * 32 + rs] = (__bf16)dh;
-        h1t[f * 32 + rs] = h1[r * H + f];
-      }
-      if (lane < 32) gb3 += dzs[lane];
-    }
-    wave_sync();
-    // dW2 += H1^T dH2: M = 64 features (4 tiles), N = 64 (4 tiles), K = 32 rows
-    for (int mt = 0; mt < 4; ++mt) {
-      const int fa = 16 * mt + c16;
-      const bf16x8 a = ld8(h1t + fa * 32 + 8 * (g ^ ((fa >> 2) & 3)));
-      for (int nt = 0; nt < 4; ++nt)
-        gw2[mt][nt] = mfma(a, ld8(dh2t + (16 * nt + c16) * 32 + 8 * (g ^ (((16 * nt + c16) >> 2) & 3))),
-                           gw2[mt][nt]);
-    }
-    // dH1 = dH2 W2^T, masked by H1 > 0: M = 32 rows (2 tiles), N = 64, K = 64
-    for (int mh = 0; mh < 2; ++mh) {
-      const bf16x8 aa = ld8(dh2 + (16 * mh + c16) * H + 8 * g);
-      const bf16x8 ab = ld8(dh2 + (16 * mh + c16) * H + 32 + 8 * g);
-      for (int nt = 0; nt < 4; ++nt) {
-        const f32x4 zero = {0.f, 0.f, 0.f, 0.f};
-        f32x4 d = mfma(aa, ld8(S.w2r + (16 * nt + c16) * H + 8 * g), zero);
-        d = mfma(ab, ld8(S.w2r + (16 * nt + c16) * H + 32 + 8 * g), d);
-        for (int v = 0; v < 4; ++v) {
-          const int r = 16 * mh + 4 * g + v;
-          const int f = 16 * nt + c16;
-          const float dh1 = (float)h1[r * H + f] > 0.f ? d[v] : 0.f;
-          gb1[nt] += dh1;
-          for (int c = 0; c < 4; ++c) gw1[nt][c] += xs[r * 4 + c] * dh1;
+      if (g == 0) gb3 += dz;
+      // last layer and dH2^T (bf16, in H1^T's operand layout)
+#pragma unroll
+      for (int t = 0; t < 4; ++t)
+#pragma unroll
+        for (int p = 0; p < 2; ++p) {
+          const unsigned w = h2[t >> 1][2 * (t & 1) + p];
+          float dh[2];
+#pragma unroll
+          for (int o = 0; o < 2; ++o) {
+            const int v = 2 * p + o;
+            const float hv = o ? hi_f(w) : lo_f(w);
+            gw3[t][v] = fmaf(hv, dz, gw3[t][v]);
+            dh[o] = hv > 0.f ? dz * w3[t][v] : 0.f;
+            gb2[t][v] += dh[o];
+          }
+          dh2[t >> 1][2 * (t & 1) + p] = pk2(dh[0], dh[1]);
+        }
+      // the inputs (bf16, as the first layer multiplied them) and a 1 for
+      // the bias, turned around: lane l holds column l%16 of rows 4g + v
+      const u32x4 xe = g == 0 ? (u32x4){pk2(x[hf].x, x[hf].y), pk2(x[hf].z, x[hf].w),
+                                        pk2(1.f, 0.f), 0u}
+                              : (u32x4){0u, 0u, 0u, 0u};
+      const f32x4 tx = mfma(xe, pickx, zero);
+      bx[2 * hf] = pk2(tx[0], tx[1]);
+      bx[2 * hf + 1] = pk2(tx[2], tx[3]);
+#pragma unroll
+      for (int t = 0; t < 4; ++t) {
+        // H1 and dH2 turned around: rows 4g + v of hidden unit 16t + l%16
+        const f32x4 t1 = mfma(h1[t >> 1], (t & 1) ? pick1 : pick0, zero);
+        const f32x4 t2 = mfma(dh2[t >> 1], (t & 1) ? pick1 : pick0, zero);
+        // dH1 at the same positions, masked by H1 > 0, as a bf16 pair
+        // hi + lo
+        f32x4 d = mfma(dh2[0], w2b[t][0], zero);
+        d = mfma(dh2[1], w2b[t][1], d);
+#pragma unroll
+        for (int p = 0; p < 2; ++p) {
+          ah1[t][2 * hf + p] = pk2(t1[2 * p], t1[2 * p + 1]);
+          bdh2[t][2 * hf + p] = pk2(t2[2 * p], t2[2 * p + 1]);
+          const float d0 = t1[2 * p] > 0.f ? d[2 * p] : 0.f;
+          const float d1 = t1[2 * p + 1] > 0.f ? d[2 * p + 1] : 0.f;
+          const unsigned hi = pk2(d0, d1);
+          adh1[t][2 * hf + p] = hi;
+          adh1l[t][2 * hf + p] = pk2(d0 - lo_f(hi), d1 - hi_f(hi));
         }
       }
     }
+#pragma unroll
+    for (int mt = 0; mt < 4; ++mt) {
+#pragma unroll
+      for (int nt = 0; nt < 4; ++nt) gw2[mt][nt] = mfma(ah1[mt], bdh2[nt], gw2[mt][nt]);
+      gw1[mt] = mfma(adh1[mt], bx, gw1[mt]);
+      gw1[mt] = mfma(adh1l[mt], bx, gw1[mt]);
+    }
   }
-  // the waves' partial sums meet in LDS (over the now unused wave buffers)
-  __syncthreads();
-  for (int e = threadIdx.x; e <= kPriorParams; e += blockDim.x) U.red[e] = 0.f;
-  __syncthreads();
+  __syncthreads();  // red is clear
+#pragma unroll
   for (int mt = 0; mt < 4; ++mt)
-    for (int nt = 0; nt < 4; ++nt)
-      for (int v = 0; v < 4; ++v)
-        atomicAdd(&U.red[OW2 + (16 * mt + 4 * g + v) * H + 16 * nt + c16], gw2[mt][nt][v]);
-  for (int nt = 0; nt < 4; ++nt) {
-    atomicAdd(&U.red[OB1 + 16 * nt + c16], gb1[nt]);
-    for (int c = 0; c < 4; ++c) atomicAdd(&U.red[OW1 + c * H + 16 * nt + c16], gw1[nt][c]);
-  }
-  atomicAdd(&U.red[OW3 + lane], gw3);
-  atomicAdd(&U.red[OB2 + lane], gb2);
-  if (lane < 32) {
-    atomicAdd(&U.red[OB3], gb3);
-    atomicAdd(&U.red[kPriorParams], loss);
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int h = 16 * mt + 4 * g + v;
+#pragma unroll
+      for (int nt = 0; nt < 4; ++nt)
+        atomicAdd(&red[OW2 + h * H + 16 * nt + c16], gw2[mt][nt][v]);
+      if (c16 < 4) atomicAdd(&red[OW1 + c16 * H + h], gw1[mt][v]);
+      if (c16 == 4) atomicAdd(&red[OB1 + h], gw1[mt][v]);
+      atomicAdd(&red[OW3 + h], gw3[mt][v]);
+      atomicAdd(&red[OB2 + h], gb2[mt][v]);
+    }
+  if (lane < 16) {
+    atomicAdd(&red[OB3], gb3);
+    atomicAdd(&red[kPriorParams], loss);
   }
   __syncthreads();
-  for (int e = threadIdx.x; e < kPriorParams; e += blockDim.x) atomicAdd(&G[e], U.red[e]);
-  if (threadIdx.x == 0) atomicAdd(L, U.red[kPriorParams]);
+  for (int e = threadIdx.x; e < kPriorParams; e += blockDim.x) atomicAdd(&G[e], red[e]);
+  if (threadIdx.x == 0) atomicAdd(L, red[kPriorParams]);
 }
 
 // Adam (Kingma and Ba, 2015) on the fp32 parameters; clears the gradient.
@@ -448,7 +427,7 @@ hipError_t launch_prior_grad(const float *P, const float *X, const float *Y, int
                              float *L, hipStream_t s) {
   const int tiles = (rows + 31) / 32;
   int blocks = (tiles + kGradWaves - 1) / kGradWaves;
-  blocks = blocks < 512 ? (blocks > 0 ? blocks : 1) : 512;
+  blocks = blocks < 256 ? (blocks > 0 ? blocks : 1) : 256;
   hipLaunchKernelGGL(k_prior_grad, dim3(blocks), dim3(64 * kGradWaves), 0, s, P, X, Y, rows, G,
                      L);
   return hipGetLastError();
