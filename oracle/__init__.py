@@ -75,8 +75,10 @@ def load() -> C.CDLL:
     lib.orc_spm_update.restype = C.c_int
     lib.orc_set_local_search.argtypes = [P, i32]
     lib.orc_set_local_search.restype = C.c_int
-    lib.orc_local_search_tour.argtypes = [P, P, i64, P]
+    lib.orc_local_search_tour.argtypes = [P, P, i64, P, P]
     lib.orc_local_search_tour.restype = i64
+    lib.orc_set_local_search_cap.argtypes = [P, i64]
+    lib.orc_set_local_search_cap.restype = C.c_int
     lib.orc_local_search.argtypes = [P]
     lib.orc_ls_moves.argtypes = [P]
     lib.orc_ls_moves.restype = i64
@@ -147,7 +149,7 @@ class Oracle:
             raise ValueError("oracle: local_update_period must be >= 1")
         if self.lib.orc_set_local_search(self.h, int(local_search)) != 0:
             self.close()
-            raise ValueError("oracle: local_search must be 0 or 1")
+            raise ValueError("oracle: local_search must be 0, 1 or 2")
         self.n, self.m = n, m
         self.cl = self.lib.orc_cl(self.h)
         self.memory, self.spm_s = memory, spm_s
@@ -177,12 +179,20 @@ class Oracle:
         """The local search on every ant's tour (when it is set)."""
         self.lib.orc_local_search(self.h)
 
-    def local_search_tour(self, tour, length: int):
-        """The descent on one tour: (improved tour, its length, moves)."""
+    def local_search_tour(self, tour, length: int, kinds: bool = False):
+        """The descent on one tour: (improved tour, its length, moves), and
+        with ``kinds`` the moves by kind (2-opt, Or-opt, 3-opt (i) .. (iv))."""
         t = np.array(tour, dtype=np.int32)
         mv = C.c_int64()
-        L = int(self.lib.orc_local_search_tour(self.h, _ptr(t), int(length), C.byref(mv)))
-        return t, L, mv.value
+        kd = np.zeros(6, dtype=np.int64)
+        L = int(self.lib.orc_local_search_tour(self.h, _ptr(t), int(length), C.byref(mv),
+                                               _ptr(kd)))
+        return (t, L, mv.value, kd.tolist()) if kinds else (t, L, mv.value)
+
+    def set_local_search_cap(self, moves: int):
+        """At most ``moves`` moves per descent (0: the default 50 n)."""
+        if self.lib.orc_set_local_search_cap(self.h, int(moves)) != 0:
+            raise ValueError("oracle: the move cap must be >= 0")
 
     def ls_moves(self) -> int:
         return int(self.lib.orc_ls_moves(self.h))

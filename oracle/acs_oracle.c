@@ -63,8 +63,10 @@ struct orc {
   int32_t ib;
 
   int64_t cnt_steps, cnt_greedy, cnt_roul, cnt_fb, cnt_hit, cnt_miss;
-  int32_t ls;       /* local search after construction: 0 none, 1 2-opt + Or-opt */
+  int32_t ls;       /* local search after construction: 0 none, 1 2-opt + Or-opt,
+                       2 the same and the four pure 3-opt reconnections */
   int64_t cnt_ls;   /* improving local-search moves applied */
+  int64_t ls_cap;   /* moves per descent, 0: 50 n (a smaller cap is for tests) */
 };
 
 static int g_threads = 1;
@@ -500,6 +502,19 @@ void orc_construct(orc *o) {
 /*     p = pred(a), x the city after S; for each candidate c (k ascending):   */
 /*     (A) S between c and e = succ(c), a next to c;                          */
 /*     (B) S reversed between f = pred(c) and c, a next to c.                 */
+/*  4. (kind 2 only) 3-opt: with b = succ(a), the tour a [B = b..c]           */
+/*     [C = d..e] f becomes a X Y f, one of the four reconnections that      */
+/*     replace all three removed edges (a,b), (c,d), (e,f), tried in this    */
+/*     order, the first created edge joining a to a candidate x with         */
+/*     d(a,x) < d(a,b) (x's candidate index k ascending), the second one     */
+/*     joining the named city to one of its candidates y (ascending) while   */
+/*     the partial gain stays positive:                                       */
+/*     (i)   C B:   x = d, y = e from b's candidates: (a,d), (e,b), (c,f);    */
+/*     (ii)  C B':  x = d, y = e from c's candidates: (a,d), (c,e), (b,f);    */
+/*     (iii) C' B:  x = e, y = d from b's candidates: (a,e), (b,d), (c,f);    */
+/*     (iv)  B' C': x = c, y = e from b's candidates: (a,c), (b,e), (d,f).    */
+/*     The positions after a are rewritten in place by reversals of B, C or  */
+/*     both together; a, b, c, d, e, f are queued.                            */
 /* Then the cities at the ends of the changed edges are queued, in the order  */
 /* listed at each move, if not queued already.  The queue starts with the    */
 /* tour in order.  At most 50 n moves are applied.                           */
@@ -584,9 +599,110 @@ static void ls_oropt(ls_state *w, int32_t i, int32_t L, int32_t c, int32_t side)
   }
 }
 
+/* the cities at positions i .. j (forward, j reached from i) in reverse order */
+static void ls_reverse_at(ls_state *w, int32_t i, int32_t j) {
+  const int32_t n = w->n;
+  const int32_t len = (j - i + n) % n + 1;
+  for (int32_t s = 0; s < len / 2; ++s) {
+    const int32_t a = ls_at(w, i + s), b = ls_at(w, j - s);
+    ls_put(w, i + s, b);
+    ls_put(w, j - s, a);
+  }
+}
+
+/* 3-opt step of the descent (move 4 above) for the popped city a; returns
+ * 1 + the reconnection's index (0 .. 3) if a move was applied, else 0. */
+static int ls_three_opt(const orc *o, ls_state *w, int32_t a, int64_t *len) {
+  const int32_t n = o->n, cl = o->cl;
+  const int32_t *ca = o->cand + (size_t)a * cl;
+  const int32_t pa = w->pos[a];
+  const int32_t b = ls_at(w, pa + 1);
+  const int64_t dab = D(o, a, b);
+  for (int32_t type = 0; type < 4; ++type) {
+    for (int32_t kx = 0; kx < cl; ++kx) {
+      const int32_t x = ca[kx];
+      const int64_t dax = D(o, a, x);
+      if (dax >= dab) break;
+      const int32_t ox = (w->pos[x] - pa + n) % n; /* offset of x after a */
+      /* the city whose candidates give y, and the gain so far */
+      int32_t from;
+      int64_t g;
+      if (type == 0 || type == 1) { /* x = d */
+        if (ox < 2) continue;
+        const int32_t c = ls_at(w, pa + ox - 1);
+        from = type == 0 ? b : c;
+        g = dab - dax + D(o, c, x);
+      } else if (type == 2) { /* x = e */
+        if (ox < 3) continue;
+        from = b;
+        g = dab - dax + D(o, x, ls_at(w, pa + ox + 1));
+      } else { /* x = c */
+        if (ox < 2 || ox > n - 3) continue;
+        from = b;
+        g = dab - dax + D(o, x, ls_at(w, pa + ox + 1));
+      }
+      const int32_t *cy = o->cand + (size_t)from * cl;
+      for (int32_t ky = 0; ky < cl; ++ky) {
+        const int32_t y = cy[ky];
+        const int64_t dfy = D(o, from, y);
+        if (dfy >= g) break;
+        const int32_t oy = (w->pos[y] - pa + n) % n;
+        int32_t c, d, e, f, oe, od;
+        int64_t delta;
+        if (type == 0 || type == 1) {
+          od = ox;
+          oe = oy;
+          if (type == 0 ? oe < od : oe <= od) continue;
+        } else if (type == 2) {
+          od = oy;
+          oe = ox;
+          if (od < 2 || od >= oe) continue;
+        } else {
+          od = ox + 1;
+          oe = oy;
+          if (oe <= od) continue;
+        }
+        c = ls_at(w, pa + od - 1);
+        d = ls_at(w, pa + od);
+        e = ls_at(w, pa + oe);
+        f = ls_at(w, pa + oe + 1);
+        const int64_t removed = dab + D(o, c, d) + D(o, e, f);
+        if (type == 0) delta = D(o, a, d) + D(o, e, b) + D(o, c, f) - removed;
+        else if (type == 1) delta = D(o, a, d) + D(o, c, e) + D(o, b, f) - removed;
+        else if (type == 2) delta = D(o, a, e) + D(o, b, d) + D(o, c, f) - removed;
+        else delta = D(o, a, c) + D(o, b, e) + D(o, d, f) - removed;
+        if (delta >= 0) continue;
+        /* positions pa + 1 .. pa + oe hold B (od - 1 cities) then C */
+        const int32_t p0 = pa + 1, nb = od - 1, nc = oe - od + 1;
+        if (type == 0) {          /* C B */
+          ls_reverse_at(w, p0 % n, (p0 + oe - 1) % n);
+          ls_reverse_at(w, p0 % n, (p0 + nc - 1) % n);
+          ls_reverse_at(w, (p0 + nc) % n, (p0 + oe - 1) % n);
+        } else if (type == 1) {   /* C B' */
+          ls_reverse_at(w, p0 % n, (p0 + oe - 1) % n);
+          ls_reverse_at(w, p0 % n, (p0 + nc - 1) % n);
+        } else if (type == 2) {   /* C' B */
+          ls_reverse_at(w, p0 % n, (p0 + oe - 1) % n);
+          ls_reverse_at(w, (p0 + nc) % n, (p0 + oe - 1) % n);
+        } else {                  /* B' C' */
+          ls_reverse_at(w, p0 % n, (p0 + nb - 1) % n);
+          ls_reverse_at(w, (p0 + nb) % n, (p0 + oe - 1) % n);
+        }
+        *len += delta;
+        ls_push(w, a); ls_push(w, b); ls_push(w, c);
+        ls_push(w, d); ls_push(w, e); ls_push(w, f);
+        return 1 + type;
+      }
+    }
+  }
+  return 0;
+}
+
 /* One descent on tour[0..n-1] (rewritten in place); returns the new length,
- * *moves the number of moves applied. */
-static int64_t ls_descent(const orc *o, int32_t *tour, int64_t len, ls_state *w, int64_t *moves) {
+ * *moves the number of moves applied, kinds[0 .. 5] (if not NULL) the moves
+ * by kind: 2-opt, Or-opt, 3-opt (i) .. (iv). */
+static int64_t ls_descent(const orc *o, int32_t *tour, int64_t len, ls_state *w, int64_t *moves,
+                          int64_t *kinds) {
   const int32_t n = o->n, cl = o->cl;
   w->t = tour;
   for (int32_t p = 0; p < n; ++p) w->pos[tour[p]] = p;
@@ -594,7 +710,7 @@ static int64_t ls_descent(const orc *o, int32_t *tour, int64_t len, ls_state *w,
   w->qh = 0;
   w->qn = 0;
   for (int32_t p = 0; p < n; ++p) ls_push(w, tour[p]);
-  const int64_t cap = 50 * (int64_t)n;
+  const int64_t cap = o->ls_cap > 0 ? o->ls_cap : 50 * (int64_t)n;
   int64_t mv = 0;
   while (w->qn > 0 && mv < cap) {
     const int32_t a = w->q[w->qh];
@@ -617,6 +733,7 @@ static int64_t ls_descent(const orc *o, int32_t *tour, int64_t len, ls_state *w,
           len += delta;
           ls_push(w, a); ls_push(w, b); ls_push(w, c); ls_push(w, e);
           done = 1;
+          if (kinds) kinds[0]++;
         }
       }
     }
@@ -634,6 +751,7 @@ static int64_t ls_descent(const orc *o, int32_t *tour, int64_t len, ls_state *w,
           len += delta;
           ls_push(w, a); ls_push(w, b); ls_push(w, c); ls_push(w, e);
           done = 1;
+          if (kinds) kinds[0]++;
         }
       }
     }
@@ -658,6 +776,7 @@ static int64_t ls_descent(const orc *o, int32_t *tour, int64_t len, ls_state *w,
             ls_push(w, p); ls_push(w, x); ls_push(w, s1); ls_push(w, sL);
             ls_push(w, c); ls_push(w, e);
             done = 1;
+            if (kinds) kinds[1]++;
             break;
           }
         }
@@ -671,9 +790,18 @@ static int64_t ls_descent(const orc *o, int32_t *tour, int64_t len, ls_state *w,
             ls_push(w, p); ls_push(w, x); ls_push(w, s1); ls_push(w, sL);
             ls_push(w, f); ls_push(w, c);
             done = 1;
+            if (kinds) kinds[1]++;
             break;
           }
         }
+      }
+    }
+    /* 4. 3-opt */
+    if (!done && o->ls >= 2 && n >= 6) {
+      const int r = ls_three_opt(o, w, a, &len);
+      if (r) {
+        done = 1;
+        if (kinds) kinds[1 + r]++;
       }
     }
     if (done) mv++;
@@ -682,7 +810,8 @@ static int64_t ls_descent(const orc *o, int32_t *tour, int64_t len, ls_state *w,
   return len;
 }
 
-int64_t orc_local_search_tour(const orc *o, int32_t *tour, int64_t len, int64_t *moves) {
+int64_t orc_local_search_tour(const orc *o, int32_t *tour, int64_t len, int64_t *moves,
+                              int64_t *kinds) {
   const int32_t n = o->n;
   ls_state w;
   w.n = n;
@@ -690,7 +819,9 @@ int64_t orc_local_search_tour(const orc *o, int32_t *tour, int64_t len, int64_t 
   w.q = (int32_t *)malloc(sizeof(int32_t) * (size_t)n);
   w.inq = (uint8_t *)malloc((size_t)n);
   int64_t mv = 0;
-  if (w.pos && w.q && w.inq) len = ls_descent(o, tour, len, &w, &mv);
+  if (kinds)
+    for (int k = 0; k < 6; ++k) kinds[k] = 0;
+  if (w.pos && w.q && w.inq) len = ls_descent(o, tour, len, &w, &mv, kinds);
   else len = -1;
   free(w.pos);
   free(w.q);
@@ -700,8 +831,14 @@ int64_t orc_local_search_tour(const orc *o, int32_t *tour, int64_t len, int64_t 
 }
 
 int orc_set_local_search(orc *o, int32_t kind) {
-  if (kind != 0 && kind != 1) return -1;
+  if (kind < 0 || kind > 2) return -1;
   o->ls = kind;
+  return 0;
+}
+
+int orc_set_local_search_cap(orc *o, int64_t moves) {
+  if (moves < 0) return -1;
+  o->ls_cap = moves;
   return 0;
 }
 
@@ -714,7 +851,7 @@ void orc_local_search(orc *o) {
 #pragma omp parallel for schedule(dynamic, 1) num_threads(g_threads) reduction(+ : total)
   for (int32_t a = 0; a < m; ++a) {
     int64_t mv = 0;
-    o->len[a] = orc_local_search_tour(o, o->tour + (size_t)a * n, o->len[a], &mv);
+    o->len[a] = orc_local_search_tour(o, o->tour + (size_t)a * n, o->len[a], &mv, NULL);
     total += mv;
   }
   o->cnt_ls += total;

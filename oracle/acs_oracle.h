@@ -59,11 +59,19 @@ int orc_set_best(orc *o, const int32_t *tour, int64_t len);
 int orc_exchange_best(orc **cols, int32_t count, int32_t topology);
 
 /* Local search after the construction (kind 1: 2-opt and Or-opt descent over
- * the candidate lists on every ant's tour; 0: none, the default).  0, or -1. */
+ * the candidate lists on every ant's tour; kind 2: the same with the four
+ * pure 3-opt reconnections as a fourth move; 0: none, the default).  0, or
+ * -1. */
 int orc_set_local_search(orc *o, int32_t kind);
+/* At most `moves` moves per descent (0: the default 50 n); lets a test look
+ * at the tour after the first move.  0, or -1. */
+int orc_set_local_search_cap(orc *o, int64_t moves);
 /* The descent on one tour (n cities, rewritten in place) of length len:
- * returns the new length; *moves (may be NULL) the moves applied. */
-int64_t orc_local_search_tour(const orc *o, int32_t *tour, int64_t len, int64_t *moves);
+ * returns the new length; *moves (may be NULL) the moves applied; kinds
+ * (may be NULL, 6 entries) the moves by kind: 2-opt, Or-opt, 3-opt
+ * reconnections (i) .. (iv). */
+int64_t orc_local_search_tour(const orc *o, int32_t *tour, int64_t len, int64_t *moves,
+                              int64_t *kinds);
 
 /* One full iteration of Alg. 1 = construct (+ local search, if set) +
  * select_best + global_update. */

@@ -12,7 +12,11 @@ Each check rests on something other than the oracle's own code:
   edges, checked exhaustively, can be exchanged for a shorter pair;
 * ACS with the local search on: every ant's tour is the descent of the tour
   the construction built (the iteration best and the global update then
-  use the improved tours).
+  use the improved tours);
+* the 3-opt move (kind 2): from tours where 2-opt and Or-opt find nothing,
+  the first move equals the first improving reconnection of an enumeration
+  that builds every candidate tour by slicing and measures it from the
+  distance matrix, for each of the four reconnections.
 """
 from __future__ import annotations
 
@@ -111,5 +115,145 @@ def test_acs_with_local_search_improves_every_ant():
         t, L, _ = plain.local_search_tour(built[a], blen[a])
         assert np.array_equal(ls.tours()[a], t) and ls.lengths()[a] == L
     assert ls.ls_moves() > 0
+    plain.close()
+    ls.close()
+
+
+# --- the 3-opt move (kind 2) -----------------------------------------------
+#
+# Reconnections of a [B = b..c] [C = d..e] f (b = succ(a)), in the order the
+# descent tries them, with the city whose candidates give the second new edge:
+#   (i) C B (y = e from b), (ii) C B' (y = e from c), (iii) C' B (x = e,
+#   y = d from b), (iv) B' C' (x = c, y = e from b).
+# The enumeration below builds each candidate tour by list slicing and takes
+# its length from the distance matrix, so neither the gain formulas nor the
+# in-place reversals of the oracle enter it.
+
+
+def _cands(d, cl):
+    n = d.shape[0]
+    return [sorted((j for j in range(n) if j != i), key=lambda j: (d[i, j], j))[:cl]
+            for i in range(n)]
+
+
+def _first_three_opt(d, cand, T):
+    """First improving 3-opt move over the cities in array order: (expected
+    array, its length, reconnection index 0..3), or None."""
+    n = len(T)
+    L0 = defs.tour_length(d, T)
+    for i in range(n):
+        a, b = T[i], T[(i + 1) % n]
+        off = {T[(i + k) % n]: k for k in range(n)}
+        at = lambda k: T[(i + k) % n]  # noqa: E731
+        for typ in range(4):
+            for x in cand[a]:
+                if not d[a, x] < d[a, b]:
+                    continue
+                ox = off[x]
+                if typ in (0, 1):
+                    if ox < 2:
+                        continue
+                    frm, g = (b if typ == 0 else at(ox - 1)), d[a, b] - d[a, x] + d[at(ox - 1), x]
+                elif typ == 2:
+                    if ox < 3:
+                        continue
+                    frm, g = b, d[a, b] - d[a, x] + d[x, at(ox + 1)]
+                else:
+                    if ox < 2 or ox > n - 3:
+                        continue
+                    frm, g = b, d[a, b] - d[a, x] + d[x, at(ox + 1)]
+                for y in cand[frm]:
+                    if not d[frm, y] < g:
+                        continue
+                    oy = off[y]
+                    if typ == 0:
+                        od, oe, ok = ox, oy, oy >= ox
+                    elif typ == 1:
+                        od, oe, ok = ox, oy, oy > ox
+                    elif typ == 2:
+                        od, oe, ok = oy, ox, 2 <= oy < ox
+                    else:
+                        od, oe, ok = ox + 1, oy, oy > ox + 1
+                    if not ok:
+                        continue
+                    B = [at(k) for k in range(1, od)]
+                    C = [at(k) for k in range(od, oe + 1)]
+                    block = [C + B, C + B[::-1], C[::-1] + B, B[::-1] + C[::-1]][typ]
+                    E = list(T)
+                    for k, city in enumerate(block):
+                        E[(i + 1 + k) % n] = city
+                    L = defs.tour_length(d, E)
+                    if L < L0:
+                        return E, L, typ
+    return None
+
+
+def test_three_opt_first_move_matches_enumeration():
+    rng = np.random.default_rng(11)
+    seen = [0, 0, 0, 0]
+    for trial in range(300):
+        n = int(rng.integers(16, 41))
+        make = inputs.uniform if trial % 2 else inputs.clustered
+        xy = make(n, 3000 + trial)
+        d = defs.dist_matrix(xy)
+        cl = min(int(rng.choice([6, 10, n - 1])), n - 1)
+        cand = _cands(d, cl)
+        o1 = oracle.Oracle(xy, m=1, cl=cl, seed=trial, local_search=1)
+        T = rng.permutation(n).astype(np.int32)
+        L = defs.tour_length(d, T)
+        for _ in range(20):  # 2-opt and Or-opt until a fresh descent moves nothing
+            T, L, mv = o1.local_search_tour(T, L)
+            if mv == 0:
+                break
+        o1.close()
+        if mv:
+            continue
+        o2 = oracle.Oracle(xy, m=1, cl=cl, seed=trial, local_search=2)
+        o2.set_local_search_cap(1)
+        t, L2, mv2, kinds = o2.local_search_tour(T, L, kinds=True)
+        o2.close()
+        want = _first_three_opt(d, cand, T.tolist())
+        if want is None:
+            assert mv2 == 0 and t.tolist() == T.tolist(), trial
+            continue
+        E, LE, typ = want
+        assert mv2 == 1 and kinds[2 + typ] == 1, (trial, kinds, typ)
+        assert t.tolist() == E and L2 == LE, trial
+        seen[typ] += 1
+    assert min(seen) > 0, seen
+
+
+@pytest.mark.parametrize("n,cl,kind", [(40, 8, "uniform"), (120, 16, "uniform"),
+                                       (300, 32, "clustered"), (64, 63, "uniform"),
+                                       (6, 5, "uniform")])
+def test_three_opt_descent_gives_a_valid_shorter_tour(n, cl, kind):
+    xy = getattr(inputs, kind)(n, 170 + n)
+    o = oracle.Oracle(xy, m=6, cl=cl, seed=3, local_search=2)
+    o.construct()
+    rng = np.random.default_rng(n)
+    starts = list(o.tours()) + [rng.permutation(n).astype(np.int32) for _ in range(4)]
+    for t0 in starts:
+        L0 = int(defs.tour_lengths(xy, np.asarray(t0)[None, :])[0])
+        t, L, mv, kinds = o.local_search_tour(t0, L0, kinds=True)
+        assert sorted(t.tolist()) == list(range(n))
+        assert L == int(defs.tour_lengths(xy, t[None, :])[0])
+        assert L <= L0 and L0 - L >= mv and sum(kinds) == mv
+    o.close()
+
+
+def test_acs_with_three_opt_is_the_descent_of_every_ant():
+    xy = inputs.clustered(160, 12)
+    plain = oracle.Oracle(xy, m=10, cl=16, seed=6)
+    ls = oracle.Oracle(xy, m=10, cl=16, seed=6, local_search=2)
+    plain.construct()
+    ls.construct()
+    built, blen = plain.tours(), plain.lengths()
+    ls.local_search()
+    three = 0
+    for a in range(10):
+        t, L, _, kinds = ls.local_search_tour(built[a], blen[a], kinds=True)
+        assert np.array_equal(ls.tours()[a], t) and ls.lengths()[a] == L
+        three += sum(kinds[2:])
+    assert three > 0
     plain.close()
     ls.close()
