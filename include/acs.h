@@ -111,7 +111,10 @@ typedef struct acs_params {
                             cities) along the candidate lists, before the
                             iteration best and the global update (the local
                             search the paper's Sec. 5.1 proposes to study);
-                            dense memory, n <= 8192, one instance.  0: none */
+                            2: the same with 3-opt moves as well (the four
+                            reconnections that replace three edges by three
+                            new ones); dense memory, n <= 8192, one
+                            instance.  0: none */
 } acs_params;
 
 typedef struct acs_stats {

@@ -166,8 +166,8 @@ int check_params(int32_t n, const acs_params *p) {
     return fail(ACS_E_UNSUPPORTED, "lanes_per_ant < 64 needs an asynchronous mode and dense memory");
   if (p->update_path > 2) return fail(ACS_E_INVALID, "update_path = %u not in {0, 1, 2}",
                                       p->update_path);
-  if (p->local_search > 1)
-    return fail(ACS_E_INVALID, "local_search = %u not in {0, 1}", p->local_search);
+  if (p->local_search > 2)
+    return fail(ACS_E_INVALID, "local_search = %u not in {0, 1, 2}", p->local_search);
   if (p->local_search && (p->memory != ACS_DENSE || n > acs::kLsMaxN))
     return fail(ACS_E_UNSUPPORTED, "the local search needs dense memory and n <= %d",
                 acs::kLsMaxN);
@@ -480,7 +480,8 @@ int iterate_handle(acs_t *h, int32_t k) {
                                   queued_kind(h), h->stream,
                                   h->timed ? h->ev[2 * i] : nullptr,
                                   h->timed ? h->ev[2 * i + 1] : nullptr));
-    if (h->p.local_search) HIP_TRY(acs::launch_local_search(h->dev, h->stream));
+    if (h->p.local_search)
+      HIP_TRY(acs::launch_local_search(h->dev, (int)h->p.local_search, h->stream));
     HIP_TRY(acs::launch_best_global(h->dev, it, (int)h->p.memory, h->stream));
   }
   if (h->timed) HIP_TRY(hipEventRecord(h->ev_end, h->stream));

@@ -124,10 +124,10 @@ hipError_t launch_construct(const Dev &d, const Iter &it, int mode, int memory, 
 int max_sync_ants(const Dev &d, int memory);
 hipError_t launch_best_global(const Dev &d, const Iter &it, int memory,
                               hipStream_t s);
-// Local search (2-opt and Or-opt descent) on every ant's tour, dense memory,
-// n <= kLsMaxN; rewrites tours and lengths.
+// Local search (2-opt and Or-opt descent; kind 2 adds 3-opt moves) on every
+// ant's tour, dense memory, n <= kLsMaxN; rewrites tours and lengths.
 constexpr int kLsMaxN = 8192;
-hipError_t launch_local_search(const Dev &d, hipStream_t s);
+hipError_t launch_local_search(const Dev &d, int kind, hipStream_t s);
 // One iteration of many dense instances (asynchronous mode): construction of
 // every (instance, ant) work item, then per-instance best and global update.
 // Descriptors, iteration state and the work list are device arrays, so the

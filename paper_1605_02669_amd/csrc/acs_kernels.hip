@@ -2976,7 +2976,9 @@ __device__ __forceinline__ void argmin_len(const Dev &D, int64_t &bl, int &ba) {
 //   3. Or-opt, L = 1, 2, 3: the segment of a and the L - 1 cities after it,
 //      p before it, x after it; per candidate c (k ascending): (A) the
 //      segment between c and succ(c), a next to c; (B) reversed between
-//      pred(c) and c.
+//      pred(c) and c;
+//   4. (kind 2) 3-opt, the four reconnections that replace (a,b), (c,d) and
+//      (e,f) of a [b..c] [d..e] f by three new edges (see ls_three_opt).
 // The cities at the ends of the changed edges are then queued (in the order
 // listed per move) unless queued already; at most 50 n moves are applied.
 // A 2-opt move reverses the forward path between its two cities when that
@@ -3080,9 +3082,112 @@ __device__ __forceinline__ void ls_oropt(const LsTour &w, int i, int L, int c, i
   }
 }
 
+// the cities at positions i .. j (forward, j reached from i) in reverse order
+__device__ __forceinline__ void ls_reverse_at(const LsTour &w, int i, int j, int lane) {
+  const int n = w.n;
+  const int len = (j - i + n) % n + 1;
+  for (int s = lane; s < len / 2; s += 64) {
+    const int a = ls_at(w, i + s), b = ls_at(w, j - s);
+    ls_put(w, i + s, b);
+    ls_put(w, j - s, a);
+  }
+}
+
+// 3-opt for the popped city a at position pa (local search kind 2): with
+// b = succ(a), the tour a [B = b..c] [C = d..e] f becomes a C B, a C B',
+// a C' B or a B' C' f (tried in that order).  The first new edge joins a to
+// a candidate x with d(a,x) < d(a,b), x = d, d, e, c for the four, taken in
+// candidate order by the whole wave; the lanes then take the candidates y
+// of b (of c for C B') for the second new edge, (e,b), (c,e), (b,d), (b,e),
+// while the partial gain stays positive, and the lowest improving lane is
+// the move a sequential scan finds.  Returns true if a move was applied.
+__device__ __forceinline__ bool ls_three_opt(const Dev &D, const LsTour &w, int a, int pa,
+                                          int64_t &len, int qh, int &qn, int lane) {
+  const int n = w.n, cl = D.cl;
+  const int kl = lane < cl ? lane : cl - 1;
+  const int b = uni(ls_at(w, pa + 1));
+  const int dab = ls_dist(D, a, b);
+  const uint4 ra = D.crec[(size_t)a * cl + kl];
+  const uint4 rb = D.crec[(size_t)b * cl + kl];
+  // a's candidates closer than b: a prefix (the lists are sorted by distance)
+  const uint64_t far = __ballot(lane >= cl || !((int)ra.y < dab));
+  const int nx = far ? (int)__ffsll((unsigned long long)far) - 1 : 64;
+  for (int type = 0; type < 4; ++type) {
+    for (int kx = 0; kx < nx; ++kx) {
+      const int x = (int)rdlane(ra.x, kx), dax = (int)rdlane(ra.y, kx);
+      const int ox = (w.pos[x] - pa + n) % n;
+      int from, g;
+      if (type <= 1) {  // x = d
+        if (ox < 2) continue;
+        const int c = uni(ls_at(w, pa + ox - 1));
+        from = type == 0 ? b : c;
+        g = dab - dax + ls_dist(D, c, x);
+      } else {  // x = e (type 2) or c (type 3)
+        if (ox < (type == 2 ? 3 : 2) || (type == 3 && ox > n - 3)) continue;
+        from = b;
+        g = dab - dax + ls_dist(D, x, uni(ls_at(w, pa + ox + 1)));
+      }
+      const uint4 ry = type == 1 ? D.crec[(size_t)from * cl + kl] : rb;
+      const int y = (int)ry.x;
+      const int oy = (w.pos[y] - pa + n) % n;
+      int od, oe;
+      bool ok = lane < cl && (int)ry.y < g;
+      if (type == 0) {
+        od = ox, oe = oy;
+        ok = ok && oy >= ox;
+      } else if (type == 1) {
+        od = ox, oe = oy;
+        ok = ok && oy > ox;
+      } else if (type == 2) {
+        od = oy, oe = ox;
+        ok = ok && oy >= 2 && oy < ox;
+      } else {
+        od = ox + 1, oe = oy;
+        ok = ok && oy > ox + 1;
+      }
+      const int c = ls_at(w, pa + od - 1), d = ls_at(w, pa + od);
+      const int e = ls_at(w, pa + oe), f = ls_at(w, pa + oe + 1);
+      const int removed = dab + ls_dist(D, c, d) + ls_dist(D, e, f);
+      int added = 0;
+      if (ok) {
+        if (type == 0) added = ls_dist(D, a, d) + ls_dist(D, e, b) + ls_dist(D, c, f);
+        else if (type == 1) added = ls_dist(D, a, d) + ls_dist(D, c, e) + ls_dist(D, b, f);
+        else if (type == 2) added = ls_dist(D, a, e) + ls_dist(D, b, d) + ls_dist(D, c, f);
+        else added = ls_dist(D, a, c) + ls_dist(D, b, e) + ls_dist(D, d, f);
+      }
+      const uint64_t imp = __ballot(ok && added - removed < 0);
+      if (!imp) continue;
+      const int k = (int)__ffsll((unsigned long long)imp) - 1;
+      const int kod = (int)rdlane((uint32_t)od, k), koe = (int)rdlane((uint32_t)oe, k);
+      const int kc = (int)rdlane((uint32_t)c, k), kd = (int)rdlane((uint32_t)d, k);
+      const int ke = (int)rdlane((uint32_t)e, k), kf = (int)rdlane((uint32_t)f, k);
+      len += (int)rdlane((uint32_t)(added - removed), k);
+      // positions pa + 1 .. pa + oe hold B (od - 1 cities) then C
+      const int p0 = (pa + 1) % n, pe = (pa + koe) % n;
+      const int nb = kod - 1, nc = koe - kod + 1;
+      if (type == 3) {
+        ls_reverse_at(w, p0, (p0 + nb - 1) % n, lane);
+        ls_reverse_at(w, (p0 + nb) % n, pe, lane);
+      } else {
+        ls_reverse_at(w, p0, pe, lane);                                 // C' B'
+        if (type <= 1) ls_reverse_at(w, p0, (p0 + nc - 1) % n, lane);   // C
+        if (type != 1) ls_reverse_at(w, (p0 + nc) % n, pe, lane);       // B
+      }
+      ls_push(w, a, qh, qn, lane);
+      ls_push(w, b, qh, qn, lane);
+      ls_push(w, kc, qh, qn, lane);
+      ls_push(w, kd, qh, qn, lane);
+      ls_push(w, ke, qh, qn, lane);
+      ls_push(w, kf, qh, qn, lane);
+      return true;
+    }
+  }
+  return false;
+}
+
 // One block (one wave) per ant.  Dynamic LDS: t, pos, q (n 16-bit entries
-// each) and the queue bitmap.
-__global__ __launch_bounds__(64) void k_local_search(Dev D) {
+// each) and the queue bitmap.  kind 2 adds the 3-opt move.
+__global__ __launch_bounds__(64) void k_local_search(Dev D, int kind) {
   extern __shared__ uint32_t lsm[];
   const int ant = blockIdx.x, lane = threadIdx.x, n = D.n, cl = D.cl;
   const int np2 = (n + 1) & ~1;  // 16-bit arrays padded to whole words
@@ -3195,6 +3300,8 @@ __global__ __launch_bounds__(64) void k_local_search(Dev D) {
         done = true;
       }
     }
+    // 4. 3-opt
+    if (!done && kind >= 2 && n >= 6) done = ls_three_opt(D, w, a, pa, len, qh, qn, lane);
     if (done) ++moves;
   }
   int32_t *out = D.tours + (size_t)ant * n;
@@ -3606,10 +3713,10 @@ int max_sync_ants(const Dev &d, int memory) {
   return per_cu * cus * (kSyncBlock / 64);
 }
 
-hipError_t launch_local_search(const Dev &d, hipStream_t s) {
+hipError_t launch_local_search(const Dev &d, int kind, hipStream_t s) {
   const int np2 = (d.n + 1) & ~1;
   const size_t lds = (size_t)3 * np2 * sizeof(uint16_t) + (size_t)((d.n + 31) / 32) * 4;
-  hipLaunchKernelGGL(k_local_search, dim3(d.m), dim3(64), lds, s, d);
+  hipLaunchKernelGGL(k_local_search, dim3(d.m), dim3(64), lds, s, d, kind);
   return hipGetLastError();
 }
 

@@ -1,5 +1,6 @@
 """The local search after the construction (2-opt and Or-opt descent along
-the candidate lists) on the GPU against the oracle's descent: in the
+the candidate lists, and with kind 2 the 3-opt move as well) on the GPU
+against the oracle's descent: in the
 synchronous mode, and with one ant in the asynchronous mode, tours,
 lengths, best-so-far tour, pheromone and the number of moves must be equal
 bit for bit after every iteration (the descent's move order and its
@@ -45,13 +46,14 @@ CASES = [
 ]
 
 
+@pytest.mark.parametrize("kind", [1, 2])
 @pytest.mark.parametrize("name,make,kw,iters", CASES, ids=[c[0] for c in CASES])
-def test_sync_with_local_search_equals_oracle(acs, name, make, kw, iters):
-    _say(f"local search, synchronous: {name}")
+def test_sync_with_local_search_equals_oracle(acs, name, make, kw, iters, kind):
+    _say(f"local search {kind}, synchronous: {name}")
     xy = make()
     oracle.set_threads(8)
-    col = acs.Colony(xy, mode=acs.ACS_SYNC, seed=13, local_search=1, **kw)
-    orc = oracle.Oracle(xy, seed=13, local_search=1, **kw)
+    col = acs.Colony(xy, mode=acs.ACS_SYNC, seed=13, local_search=kind, **kw)
+    orc = oracle.Oracle(xy, seed=13, local_search=kind, **kw)
     for it in range(iters):
         col.iterate(1)
         orc.iterate(1)
@@ -68,12 +70,12 @@ def test_sync_with_local_search_equals_oracle(acs, name, make, kw, iters):
     orc.close()
 
 
-@pytest.mark.parametrize("path", [2, 1])
-def test_async_one_ant_with_local_search_equals_oracle(acs, path):
+@pytest.mark.parametrize("path,kind", [(2, 1), (1, 1), (1, 2)])
+def test_async_one_ant_with_local_search_equals_oracle(acs, path, kind):
     xy = inputs.uniform(260, 47)
-    col = acs.Colony(xy, m=1, mode=acs.ACS_ASYNC_ATOMIC, seed=2, local_search=1,
+    col = acs.Colony(xy, m=1, mode=acs.ACS_ASYNC_ATOMIC, seed=2, local_search=kind,
                      update_path=path)
-    orc = oracle.Oracle(xy, m=1, seed=2, local_search=1)
+    orc = oracle.Oracle(xy, m=1, seed=2, local_search=kind)
     for it in range(6):
         col.iterate(1)
         orc.iterate(1)
@@ -82,10 +84,11 @@ def test_async_one_ant_with_local_search_equals_oracle(acs, path):
     col.close()
 
 
-def test_headline_size_with_local_search_valid(acs):
+@pytest.mark.parametrize("kind", [1, 2])
+def test_headline_size_with_local_search_valid(acs, kind):
     n = 2392
     xy = inputs.uniform(n)
-    col = acs.Colony(xy, mode=acs.ACS_ASYNC_ATOMIC, seed=0, local_search=1)
+    col = acs.Colony(xy, mode=acs.ACS_ASYNC_ATOMIC, seed=0, local_search=kind)
     plain = acs.Colony(xy, mode=acs.ACS_ASYNC_ATOMIC, seed=0)
     col.iterate(2)
     plain.iterate(2)
@@ -93,7 +96,7 @@ def test_headline_size_with_local_search_valid(acs):
     assert np.all(np.sort(tours, axis=1) == np.arange(n)[None, :])
     assert np.array_equal(defs.tour_lengths(xy, tours), lens)
     st = col.stats()
-    _say(f"n=2392 with local search: best {st['best_length']} ({plain.stats()['best_length']} "
+    _say(f"n=2392 with local search {kind}: best {st['best_length']} ({plain.stats()['best_length']} "
          f"without), {st['ls_moves']} moves, iteration {st['iterate_ms']:.2f} ms")
     assert st["best_length"] < plain.stats()["best_length"]
     col.close()
