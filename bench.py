@@ -305,16 +305,18 @@ def run_colonies(acs, inputs, colonies=(1, 4, 8), seeds=5, budget_s=0.5, period=
 
 
 def run_local_search(acs, inputs, seeds=5, budget_s=1.0):
-    """ACS with the 2-opt/Or-opt descent after each construction against
-    plain ACS at equal wall-clock on the headline instance (asynchronous
-    atomic mode): m = n ants with and without the descent, and a 64-ant
-    colony with it."""
+    """ACS with a descent after each construction against plain ACS at equal
+    wall-clock on the headline instance (asynchronous atomic mode): m = n
+    ants with and without the descent (2-opt and Or-opt; and with the 3-opt
+    move as well), and 64-ant colonies with each descent."""
     import numpy as np
     import torch
     xy = inputs.uniform(N)
     out = {"n": N, "seeds": seeds, "budget_s": budget_s}
     for name, kw in (("plain_m2392", dict()), ("ls_m2392", dict(local_search=1)),
-                     ("ls_m64", dict(local_search=1, m=64))):
+                     ("ls_m64", dict(local_search=1, m=64)),
+                     ("ls3_m2392", dict(local_search=2)),
+                     ("ls3_m64", dict(local_search=2, m=64))):
         best, its, ms = [], [], []
         for s in range(seeds):
             col = acs.Colony(xy, mode=acs.ACS_ASYNC_ATOMIC, seed=s, cl=CL, **kw)
