@@ -389,6 +389,9 @@ int init_handle(acs_t *h, const double *coords_xy, int32_t n, const acs_params *
       hipError_t e = hipMalloc(&h->ws, h->L.total);
       if (e != hipSuccess) {
         h->ws = nullptr;
+        // the failed allocation is also this thread's last HIP error, which
+        // the launch checks of later calls would otherwise report as theirs
+        (void)hipGetLastError();
         return fail(ACS_E_NOMEM, "hipMalloc(%zu): %s", h->L.total, hipGetErrorString(e));
       }
       h->own_ws = true;
@@ -888,6 +891,7 @@ int acs_batch_create(const double *const *coords, const int32_t *n, int32_t coun
     hipError_t e = hipMalloc(&b->ws, L.total);
     if (e != hipSuccess) {
       b->ws = nullptr;
+      (void)hipGetLastError();  // not the last error of later calls (see acs_create)
       return bail(fail(ACS_E_NOMEM, "hipMalloc(%zu): %s", L.total, hipGetErrorString(e)));
     }
     b->own_ws = true;
