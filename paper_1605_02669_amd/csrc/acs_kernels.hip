@@ -1374,28 +1374,30 @@ __device__ __forceinline__ uint32_t apply_entries(const Dev &D, const Iter &A, u
   const bool valid = e.x != kNoEntry;
   const int u = (int)(e.x & 0xffffu), v = (int)(e.x >> 16), k = (int)e.y;
   int kr = (int)e.w;
+  const float al = A.a_loc, bl = A.b_loc;
+  // compare-and-swap mode: the value the ant read is one the edge's entries
+  // have held; if the map leaves it unchanged (map_fixed), they hold it now
+  // and neither is written.  Tested first, so that such an entry needs
+  // neither the reverse position nor the fallback's search.
+  const bool fixed = ATOMIC && valid && map_fixed(__uint_as_float(e.z), al, bl);
   // after a fallback move: the whole wave searches v's list, once per entry
-  uint64_t need = __ballot(valid && kr == -3);
+  uint64_t need = __ballot(valid && !fixed && kr == -3);
   while (need) {
     const int l = (int)__ffsll((unsigned long long)need) - 1;
     need &= need - 1;
     const int r = cand_pos(D, (int)rdlane((uint32_t)v, l), (int)rdlane((uint32_t)u, l), lane);
     if (lane == l) kr = r;
   }
-  if (!valid) return 0;
+  if (!valid || fixed) return 0;
   if (kr == -2) kr = (int)D.rpos[(size_t)u * D.cl + k];
   float *pf = qhome(D, u, v, k);
   float *pr = qhome(D, v, u, kr);
-  const float al = A.a_loc, bl = A.b_loc;
   if (ATOMIC) {
     const bool both_dense = k < 0 && kr < 0;
     const bool fwd_canon = k >= 0 && (kr < 0 || u < v);
     float *pc = fwd_canon || both_dense ? pf : pr;
     float *po = fwd_canon || both_dense ? pr : pf;
     unsigned int seen = e.z, nw;
-    // the value the ant read is one the edge's entries have held; if the
-    // map leaves it unchanged (map_fixed), they hold it now: skip both writes
-    if (map_fixed(__uint_as_float(seen), al, bl)) return 0;
     uint32_t r = 0;
     while (true) {
       nw = __float_as_uint(fmaf(al, __uint_as_float(seen), bl));
