@@ -16,6 +16,9 @@ FLAGS = [
     "-ffp-contract=off",
     # no packed FP32 instructions in device code
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+    # matrix-core results in VGPRs, where the vector unit reads them, instead
+    # of AGPRs and a copy per value (only the prior's kernels use MFMA)
+    "-mllvm", "-amdgpu-mfma-vgpr-form=1",
     "-Wall", "-Wno-unused-function",
 ]
 

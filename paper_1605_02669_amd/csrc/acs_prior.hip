@@ -45,6 +45,15 @@ __device__ __forceinline__ f32x4 mfma(u32x4 a, u32x4 b, f32x4 c) {
   return mfma(__builtin_bit_cast(bf16x8, a), __builtin_bit_cast(bf16x8, b), c);
 }
 
+// the K = 16 product: A lane l holds A[l % 16][4 (l / 16) + 0..3], B lane l
+// holds B[4 (l / 16) + 0..3][l % 16], D as above
+typedef __attribute__((__vector_size__(4 * sizeof(short)))) short s16x4;
+typedef unsigned int u32x2 __attribute__((ext_vector_type(2)));
+__device__ __forceinline__ f32x4 mfma16(u32x2 a, u32x2 b, f32x4 c) {
+  return __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(__builtin_bit_cast(s16x4, a),
+                                                   __builtin_bit_cast(s16x4, b), c, 0, 0, 0);
+}
+
 // two floats rounded to bf16 (to nearest, ties to even) in one dword, a in
 // the low half; and the two halves back as floats
 __device__ __forceinline__ unsigned pk2(float a, float b) {
@@ -74,6 +83,12 @@ struct RegNet {
   bf16x8 w3[2];     // A of layer 3, K block b: W3[perm_k(b, l/16, q)] in every row
   f32x4 b1[4], b2[4];  // [t][v] at hidden 16t + 4(l/16) + v
   f32x4 b3;            // b3 in every entry
+  __device__ __forceinline__ bf16x8 W1(int t) const { return w1[t]; }
+  __device__ __forceinline__ bf16x8 W2(int t, int b) const { return w2[t][b]; }
+  __device__ __forceinline__ bf16x8 W3(int b) const { return w3[b]; }
+  __device__ __forceinline__ f32x4 B1(int t) const { return b1[t]; }
+  __device__ __forceinline__ f32x4 B2(int t) const { return b2[t]; }
+  __device__ __forceinline__ f32x4 B3() const { return b3; }
 };
 
 __device__ __forceinline__ int perm_k(int b, int g, int q) {
@@ -114,25 +129,26 @@ __device__ __forceinline__ void load_regnet(RegNet &R, const float *P, int lane)
 // the gradient needs them: h1 and h2 = H1^T and H2^T as B operands (K
 // blocks 0 and 1), so entry 4(t & 1) + v of block t >> 1 is hidden unit
 // 16t + 4(l/16) + v of the row.
-__device__ __forceinline__ float forward16r(const RegNet &R, float4 x, int lane, u32x4 h1[2],
+template <class Net>
+__device__ __forceinline__ float forward16r(const Net &R, float4 x, int lane, u32x4 h1[2],
                                             u32x4 h2[2]) {
   const int g = lane >> 4;
   const u32x4 bx = g == 0 ? (u32x4){pk2(x.x, x.y), pk2(x.z, x.w), 0u, 0u} : (u32x4){0u, 0u, 0u, 0u};
 #pragma unroll
   for (int t = 0; t < 4; ++t) {
-    const f32x4 d = mfma(R.w1[t], bx, R.b1[t]);
+    const f32x4 d = mfma(R.W1(t), bx, R.B1(t));
     h1[t >> 1][2 * (t & 1)] = pk2(relu(d[0]), relu(d[1]));
     h1[t >> 1][2 * (t & 1) + 1] = pk2(relu(d[2]), relu(d[3]));
   }
 #pragma unroll
   for (int t = 0; t < 4; ++t) {
-    f32x4 d = mfma(R.w2[t][0], h1[0], R.b2[t]);
-    d = mfma(R.w2[t][1], h1[1], d);
+    f32x4 d = mfma(R.W2(t, 0), h1[0], R.B2(t));
+    d = mfma(R.W2(t, 1), h1[1], d);
     h2[t >> 1][2 * (t & 1)] = pk2(relu(d[0]), relu(d[1]));
     h2[t >> 1][2 * (t & 1) + 1] = pk2(relu(d[2]), relu(d[3]));
   }
-  f32x4 z = mfma(R.w3[0], h2[0], R.b3);
-  z = mfma(R.w3[1], h2[1], z);
+  f32x4 z = mfma(R.W3(0), h2[0], R.B3());
+  z = mfma(R.W3(1), h2[1], z);
   return z[0];
 }
 
@@ -174,21 +190,25 @@ __global__ __launch_bounds__(64 * kFwdWaves) void k_prior_forward(const float *P
 
 // Gradient of the mean binary cross-entropy (with logits) over all `rows`
 // rows, accumulated into G; loss sum into *L.  Each wave takes 32-row tiles
-// (two 16-row halves) and keeps everything in registers:
+// (two 16-row halves, one after the other) and keeps activations and
+// partial sums in registers:
 //   forward   as in inference, the products transposed (rows across lanes);
 //   dH2       dz w3 masked by H2 > 0, lane by lane; dW3, db2, db3 as
 //             lane-local sums on the vector unit;
 //   turn      H1 and dH2 turned around (rows within a lane);
 //   dH1       dH2 W2^T on the matrix cores, masked by H1 > 0;
-//   dW2       H1^T dH2 on the matrix cores, K = the tile's 32 rows;
+//   dW2       H1^T dH2 on the matrix cores (K = 16, the half's rows);
 //   dW1, db1  dH1^T [X 1] on the matrix cores, dH1 carried as a sum of two
 //             bf16 values (16 significant bits) against the bf16 inputs.
 // A product with a 0/1 selection matrix turns a 16 x 16 block around
 // exactly: each sum has one nonzero term, a bf16 value times 1.  Afterwards
-// lane l holds rows 4(l/16) + v of one hidden unit, and the two halves give
-// the eight rows of an operand.  The lanes' and waves' partial sums meet in
-// LDS at the end, and each block adds its total to G once per parameter.
-constexpr int kGradWaves = 4;
+// lane l holds rows 4(l/16) + v of one hidden unit, which is the K = 16
+// operand layout.  The weight tiles sit in LDS, one 16-byte entry per lane,
+// and are read where they are used, so that a wave holds at most 256
+// registers and two waves share a SIMD.  The lanes' and waves' partial sums
+// meet in LDS at the end, and each block adds its total to G once per
+// parameter.
+constexpr int kGradWaves = 8;  // two per SIMD: a wave holds 256 registers
 
 // B operand that picks hidden units 16 (2b + odd) + l % 16 out of K block b
 // of a transposed tile (the inverse of perm_k).
@@ -201,33 +221,101 @@ __device__ __forceinline__ bf16x8 pick_tile(int lane, int odd) {
   return s;
 }
 
+// Every lane's operand tiles in LDS, one 16-byte entry per tile and lane
+// (lane l reads entry [tile][l]: no bank conflicts), read where they are
+// used instead of held in registers across the loop.
+enum : int {
+  kTW1 = 0, kTW2 = 4, kTW3 = 12, kTB1 = 14, kTB2 = 18, kTB3 = 22, kTW2b = 23, kTPick = 31,
+  kTPickX = 33, kTW3f = 34, kTiles = 38
+};
+
+struct LdsNet {
+  const u32x4 (*tl)[64];
+  int lane;
+  __device__ __forceinline__ u32x4 at(int i) const { return tl[i][lane]; }
+  __device__ __forceinline__ bf16x8 W1(int t) const {
+    return __builtin_bit_cast(bf16x8, at(kTW1 + t));
+  }
+  __device__ __forceinline__ bf16x8 W2(int t, int b) const {
+    return __builtin_bit_cast(bf16x8, at(kTW2 + 2 * t + b));
+  }
+  __device__ __forceinline__ bf16x8 W3(int b) const {
+    return __builtin_bit_cast(bf16x8, at(kTW3 + b));
+  }
+  __device__ __forceinline__ f32x4 B1(int t) const {
+    return __builtin_bit_cast(f32x4, at(kTB1 + t));
+  }
+  __device__ __forceinline__ f32x4 B2(int t) const {
+    return __builtin_bit_cast(f32x4, at(kTB2 + t));
+  }
+  __device__ __forceinline__ f32x4 B3() const { return __builtin_bit_cast(f32x4, at(kTB3)); }
+  __device__ __forceinline__ bf16x8 W2b(int t, int b) const {
+    return __builtin_bit_cast(bf16x8, at(kTW2b + 2 * t + b));
+  }
+  __device__ __forceinline__ bf16x8 Pick(int odd) const {
+    return __builtin_bit_cast(bf16x8, at(kTPick + odd));
+  }
+  __device__ __forceinline__ bf16x8 PickX() const {
+    return __builtin_bit_cast(bf16x8, at(kTPickX));
+  }
+  __device__ __forceinline__ f32x4 W3f(int t) const {
+    return __builtin_bit_cast(f32x4, at(kTW3f + t));
+  }
+};
+
 __global__ __launch_bounds__(64 * kGradWaves) void k_prior_grad(const float *P, const float *X,
                                                                 const float *Y, int rows,
                                                                 float *G, float *L) {
-  __shared__ float red[kPriorParams + 1];  // block totals (the last entry: loss)
+  __shared__ union alignas(16) {
+    u32x4 tl[kTiles][64];         // operand tiles
+    float red[kPriorParams + 1];  // block totals (the last entry: loss)
+  } U;
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   const int g = lane >> 4, c16 = lane & 15;
-  for (int e = threadIdx.x; e <= kPriorParams; e += blockDim.x) red[e] = 0.f;
-  RegNet R;
-  load_regnet(R, P, lane);
-  // B of dH1 = dH2 W2^T, tile t, K block b: W2[16t + l%16][perm_k(b, g, q)]
-  bf16x8 w2b[4][2];
+  {
+    RegNet N;
+    load_regnet(N, P, lane);
+    // B of dH1 = dH2 W2^T, tile t, K block b: W2[16t + l%16][perm_k(b, g, q)]
+    bf16x8 w2b[4][2];
 #pragma unroll
-  for (int t = 0; t < 4; ++t)
+    for (int t = 0; t < 4; ++t)
 #pragma unroll
-    for (int b = 0; b < 2; ++b)
+      for (int b = 0; b < 2; ++b)
 #pragma unroll
-      for (int q = 0; q < 8; ++q)
-        w2b[t][b][q] = (__bf16)P[OW2 + (16 * t + c16) * H + perm_k(b, g, q)];
-  float w3[4][4];  // W3 (bf16) at hidden 16t + 4g + v
+        for (int q = 0; q < 8; ++q)
+          w2b[t][b][q] = (__bf16)P[OW2 + (16 * t + c16) * H + perm_k(b, g, q)];
+    f32x4 w3f[4];  // W3 (bf16) at hidden 16t + 4g + v
 #pragma unroll
-  for (int t = 0; t < 4; ++t)
+    for (int t = 0; t < 4; ++t)
 #pragma unroll
-    for (int v = 0; v < 4; ++v) w3[t][v] = (float)(__bf16)P[OW3 + 16 * t + 4 * g + v];
-  const bf16x8 pick0 = pick_tile(lane, 0), pick1 = pick_tile(lane, 1);
-  bf16x8 pickx;  // B operand that picks input column l % 16 (identity)
+      for (int v = 0; v < 4; ++v) w3f[t][v] = (float)(__bf16)P[OW3 + 16 * t + 4 * g + v];
+    bf16x8 pickx;  // B operand that picks input column l % 16 (identity)
 #pragma unroll
-  for (int q = 0; q < 8; ++q) pickx[q] = (__bf16)(8 * g + q == c16 ? 1.f : 0.f);
+    for (int q = 0; q < 8; ++q) pickx[q] = (__bf16)(8 * g + q == c16 ? 1.f : 0.f);
+    // the waves store the tiles in turn
+    auto put = [&](int i, auto v) {
+      if (i % kGradWaves == wv) U.tl[i][lane] = __builtin_bit_cast(u32x4, v);
+    };
+#pragma unroll
+    for (int t = 0; t < 4; ++t) {
+      put(kTW1 + t, N.w1[t]);
+      put(kTW2 + 2 * t, N.w2[t][0]);
+      put(kTW2 + 2 * t + 1, N.w2[t][1]);
+      put(kTB1 + t, N.b1[t]);
+      put(kTB2 + t, N.b2[t]);
+      put(kTW2b + 2 * t, w2b[t][0]);
+      put(kTW2b + 2 * t + 1, w2b[t][1]);
+      put(kTW3f + t, w3f[t]);
+    }
+    put(kTW3, N.w3[0]);
+    put(kTW3 + 1, N.w3[1]);
+    put(kTB3, N.b3);
+    put(kTPick, pick_tile(lane, 0));
+    put(kTPick + 1, pick_tile(lane, 1));
+    put(kTPickX, pickx);
+  }
+  __syncthreads();
+  const LdsNet R{U.tl, lane};
   const float inv_rows = 1.f / (float)rows;
   const f32x4 zero = {0.f, 0.f, 0.f, 0.f};
   f32x4 gw2[4][4];  // dW2[16mt + 4g + v][16nt + l%16]
@@ -253,6 +341,9 @@ __global__ __launch_bounds__(64 * kGradWaves) void k_prior_grad(const float *P, 
     yn[hf] = row < rows ? Y[row] : 0.f;
   }
   for (; r0 < rows; r0 += stride) {
+    // the tiles are read from LDS where they are used, every pass (a
+    // compiler barrier: not hoisted out of the loop)
+    __asm__ volatile("" ::: "memory");
     const float4 x[2] = {xn[0], xn[1]};
     const float y[2] = {yn[0], yn[1]};
 #pragma unroll
@@ -261,13 +352,12 @@ __global__ __launch_bounds__(64 * kGradWaves) void k_prior_grad(const float *P, 
       xn[hf] = load_x(X, row, rows);
       yn[hf] = row < rows ? Y[row] : 0.f;
     }
-    // operands over the tile's 32 rows: K position 8g + q is row 4g + q of
-    // the first half (q < 4) or row 4g + q - 4 of the second
-    u32x4 ah1[4], bdh2[4], adh1[4], adh1l[4], bx;
 #pragma unroll
     for (int hf = 0; hf < 2; ++hf) {
       u32x4 h1[2], h2[2], dh2[2];
+      __builtin_amdgcn_sched_barrier(0);
       const float z = forward16r(R, x[hf], lane, h1, h2);
+      __builtin_amdgcn_sched_barrier(0);
       // dz = (sigmoid(z) - y) / rows, loss = softplus(z) - y z (rows past
       // the end: 0); the reciprocal and logarithm of the vector unit (about
       // 1 ulp) are ample for a training signal
@@ -282,7 +372,8 @@ __global__ __launch_bounds__(64 * kGradWaves) void k_prior_grad(const float *P, 
       if (g == 0) gb3 += dz;
       // last layer and dH2^T (bf16, in H1^T's operand layout)
 #pragma unroll
-      for (int t = 0; t < 4; ++t)
+      for (int t = 0; t < 4; ++t) {
+        const f32x4 w3t = R.W3f(t);
 #pragma unroll
         for (int p = 0; p < 2; ++p) {
           const unsigned w = h2[t >> 1][2 * (t & 1) + p];
@@ -292,49 +383,55 @@ __global__ __launch_bounds__(64 * kGradWaves) void k_prior_grad(const float *P, 
             const int v = 2 * p + o;
             const float hv = o ? hi_f(w) : lo_f(w);
             gw3[t][v] = fmaf(hv, dz, gw3[t][v]);
-            dh[o] = hv > 0.f ? dz * w3[t][v] : 0.f;
+            dh[o] = hv > 0.f ? dz * w3t[v] : 0.f;
             gb2[t][v] += dh[o];
           }
           dh2[t >> 1][2 * (t & 1) + p] = pk2(dh[0], dh[1]);
         }
+      }
       // the inputs (bf16, as the first layer multiplied them) and a 1 for
       // the bias, turned around: lane l holds column l%16 of rows 4g + v
       const u32x4 xe = g == 0 ? (u32x4){pk2(x[hf].x, x[hf].y), pk2(x[hf].z, x[hf].w),
                                         pk2(1.f, 0.f), 0u}
                               : (u32x4){0u, 0u, 0u, 0u};
-      const f32x4 tx = mfma(xe, pickx, zero);
-      bx[2 * hf] = pk2(tx[0], tx[1]);
-      bx[2 * hf + 1] = pk2(tx[2], tx[3]);
+      const f32x4 tx = mfma(xe, R.PickX(), zero);
+      const u32x2 bx = {pk2(tx[0], tx[1]), pk2(tx[2], tx[3])};
+      // operands over the half's 16 rows: K position 4g + v is row 4g + v
+      u32x2 ah1[4], bdh2[4], adh1[4], adh1l[4];
 #pragma unroll
       for (int t = 0; t < 4; ++t) {
         // H1 and dH2 turned around: rows 4g + v of hidden unit 16t + l%16
-        const f32x4 t1 = mfma(h1[t >> 1], (t & 1) ? pick1 : pick0, zero);
-        const f32x4 t2 = mfma(dh2[t >> 1], (t & 1) ? pick1 : pick0, zero);
+        const bf16x8 pick = R.Pick(t & 1);
+        const f32x4 t1 = mfma(h1[t >> 1], pick, zero);
+        const f32x4 t2 = mfma(dh2[t >> 1], pick, zero);
         // dH1 at the same positions, masked by H1 > 0, as a bf16 pair
         // hi + lo
-        f32x4 d = mfma(dh2[0], w2b[t][0], zero);
-        d = mfma(dh2[1], w2b[t][1], d);
+        f32x4 d = mfma(dh2[0], R.W2b(t, 0), zero);
+        d = mfma(dh2[1], R.W2b(t, 1), d);
 #pragma unroll
         for (int p = 0; p < 2; ++p) {
-          ah1[t][2 * hf + p] = pk2(t1[2 * p], t1[2 * p + 1]);
-          bdh2[t][2 * hf + p] = pk2(t2[2 * p], t2[2 * p + 1]);
+          ah1[t][p] = pk2(t1[2 * p], t1[2 * p + 1]);
+          bdh2[t][p] = pk2(t2[2 * p], t2[2 * p + 1]);
           const float d0 = t1[2 * p] > 0.f ? d[2 * p] : 0.f;
           const float d1 = t1[2 * p + 1] > 0.f ? d[2 * p + 1] : 0.f;
           const unsigned hi = pk2(d0, d1);
-          adh1[t][2 * hf + p] = hi;
-          adh1l[t][2 * hf + p] = pk2(d0 - lo_f(hi), d1 - hi_f(hi));
+          adh1[t][p] = hi;
+          adh1l[t][p] = pk2(d0 - lo_f(hi), d1 - hi_f(hi));
         }
       }
-    }
+      // dW2 += H1^T dH2 and [dW1; db1]^T += dH1^T [X 1] over the half
 #pragma unroll
-    for (int mt = 0; mt < 4; ++mt) {
+      for (int mt = 0; mt < 4; ++mt) {
 #pragma unroll
-      for (int nt = 0; nt < 4; ++nt) gw2[mt][nt] = mfma(ah1[mt], bdh2[nt], gw2[mt][nt]);
-      gw1[mt] = mfma(adh1[mt], bx, gw1[mt]);
-      gw1[mt] = mfma(adh1l[mt], bx, gw1[mt]);
+        for (int nt = 0; nt < 4; ++nt) gw2[mt][nt] = mfma16(ah1[mt], bdh2[nt], gw2[mt][nt]);
+        gw1[mt] = mfma16(adh1[mt], bx, gw1[mt]);
+        gw1[mt] = mfma16(adh1l[mt], bx, gw1[mt]);
+      }
     }
   }
-  __syncthreads();  // red is clear
+  __syncthreads();  // every wave is done with the tiles
+  for (int e = threadIdx.x; e <= kPriorParams; e += blockDim.x) U.red[e] = 0.f;
+  __syncthreads();
 #pragma unroll
   for (int mt = 0; mt < 4; ++mt)
 #pragma unroll
@@ -342,19 +439,19 @@ __global__ __launch_bounds__(64 * kGradWaves) void k_prior_grad(const float *P, 
       const int h = 16 * mt + 4 * g + v;
 #pragma unroll
       for (int nt = 0; nt < 4; ++nt)
-        atomicAdd(&red[OW2 + h * H + 16 * nt + c16], gw2[mt][nt][v]);
-      if (c16 < 4) atomicAdd(&red[OW1 + c16 * H + h], gw1[mt][v]);
-      if (c16 == 4) atomicAdd(&red[OB1 + h], gw1[mt][v]);
-      atomicAdd(&red[OW3 + h], gw3[mt][v]);
-      atomicAdd(&red[OB2 + h], gb2[mt][v]);
+        atomicAdd(&U.red[OW2 + h * H + 16 * nt + c16], gw2[mt][nt][v]);
+      if (c16 < 4) atomicAdd(&U.red[OW1 + c16 * H + h], gw1[mt][v]);
+      if (c16 == 4) atomicAdd(&U.red[OB1 + h], gw1[mt][v]);
+      atomicAdd(&U.red[OW3 + h], gw3[mt][v]);
+      atomicAdd(&U.red[OB2 + h], gb2[mt][v]);
     }
   if (lane < 16) {
-    atomicAdd(&red[OB3], gb3);
-    atomicAdd(&red[kPriorParams], loss);
+    atomicAdd(&U.red[OB3], gb3);
+    atomicAdd(&U.red[kPriorParams], loss);
   }
   __syncthreads();
-  for (int e = threadIdx.x; e < kPriorParams; e += blockDim.x) atomicAdd(&G[e], red[e]);
-  if (threadIdx.x == 0) atomicAdd(L, red[kPriorParams]);
+  for (int e = threadIdx.x; e < kPriorParams; e += blockDim.x) atomicAdd(&G[e], U.red[e]);
+  if (threadIdx.x == 0) atomicAdd(L, U.red[kPriorParams]);
 }
 
 // Adam (Kingma and Ba, 2015) on the fp32 parameters; clears the gradient.
@@ -426,6 +523,7 @@ hipError_t launch_prior_forward(const float *P, const float *X, int rows, float 
 hipError_t launch_prior_grad(const float *P, const float *X, const float *Y, int rows, float *G,
                              float *L, hipStream_t s) {
   const int tiles = (rows + 31) / 32;
+  // one block per CU (fewer block totals to add into G)
   int blocks = (tiles + kGradWaves - 1) / kGradWaves;
   blocks = blocks < 256 ? (blocks > 0 ? blocks : 1) : 256;
   hipLaunchKernelGGL(k_prior_grad, dim3(blocks), dim3(64 * kGradWaves), 0, s, P, X, Y, rows, G,
