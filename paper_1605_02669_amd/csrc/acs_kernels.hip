@@ -3097,16 +3097,20 @@ __device__ __forceinline__ void ls_reverse_at(const LsTour &w, int i, int j, int
 
 // 3-opt for the popped city a at position pa (local search kind 2): with
 // b = succ(a), the tour a [B = b..c] [C = d..e] f becomes a C B, a C B',
-// a C' B or a B' C' f (tried in that order).  The first new edge joins a to
-// a candidate x with d(a,x) < d(a,b), x = d, d, e, c for the four, taken in
-// candidate order by the whole wave; the lanes then take the candidates y
-// of b (of c for C B') for the second new edge, (e,b), (c,e), (b,d), (b,e),
-// while the partial gain stays positive, and the lowest improving lane is
-// the move a sequential scan finds.  Returns true if a move was applied.
+// a C' B or a B' C' f (reconnections 0 to 3, tried in that order).  The
+// first new edge joins a to a candidate x with d(a,x) < d(a,b), x = d, d, e,
+// c for the four, in candidate order; the second joins b (c for C B') to one
+// of its candidates y, in candidate order, while the partial gain stays
+// positive.  The move a sequential scan finds is the lowest (reconnection,
+// x, y).  The wave takes one x at a time with all four reconnections at once
+// (their loads in one round, the lanes taking y), keeps the first improving
+// move of the most preferred reconnection seen, and stops early once
+// reconnection 0 has one.  Returns true if a move was applied.
 __device__ __forceinline__ bool ls_three_opt(const Dev &D, const LsTour &w, int a, int pa,
                                           int64_t &len, int qh, int &qn, int lane) {
   const int n = w.n, cl = D.cl;
   const int kl = lane < cl ? lane : cl - 1;
+  const bool cand = lane < cl;
   const int b = uni(ls_at(w, pa + 1));
   const int dab = ls_dist(D, a, b);
   const uint4 ra = D.crec[(size_t)a * cl + kl];
@@ -3114,77 +3118,75 @@ __device__ __forceinline__ bool ls_three_opt(const Dev &D, const LsTour &w, int 
   // a's candidates closer than b: a prefix (the lists are sorted by distance)
   const uint64_t far = __ballot(lane >= cl || !((int)ra.y < dab));
   const int nx = far ? (int)__ffsll((unsigned long long)far) - 1 : 64;
-  for (int type = 0; type < 4; ++type) {
-    for (int kx = 0; kx < nx; ++kx) {
-      const int x = (int)rdlane(ra.x, kx), dax = (int)rdlane(ra.y, kx);
-      const int ox = (w.pos[x] - pa + n) % n;
-      int from, g;
-      if (type <= 1) {  // x = d
-        if (ox < 2) continue;
-        const int c = uni(ls_at(w, pa + ox - 1));
-        from = type == 0 ? b : c;
-        g = dab - dax + ls_dist(D, c, x);
-      } else {  // x = e (type 2) or c (type 3)
-        if (ox < (type == 2 ? 3 : 2) || (type == 3 && ox > n - 3)) continue;
-        from = b;
-        g = dab - dax + ls_dist(D, x, uni(ls_at(w, pa + ox + 1)));
-      }
-      const uint4 ry = type == 1 ? D.crec[(size_t)from * cl + kl] : rb;
-      const int y = (int)ry.x;
-      const int oy = (w.pos[y] - pa + n) % n;
+  const int yb = (int)rb.x, dyb = (int)rb.y;  // b's candidates
+  const int oyb = (w.pos[yb] - pa + n) % n;
+  int best = 4, bod = 0, boe = 0, bc = 0, bd = 0, be = 0, bf = 0, bdelta = 0;
+  for (int kx = 0; kx < nx && best > 0; ++kx) {
+    const int x = (int)rdlane(ra.x, kx), dax = (int)rdlane(ra.y, kx);
+    const int ox = (w.pos[x] - pa + n) % n;
+    const int px = uni(ls_at(w, pa + ox - 1)), sx = uni(ls_at(w, pa + ox + 1));
+    const int g01 = dab - dax + ls_dist(D, px, x);  // x = d: removed (c, d), c = pred(x)
+    const int g23 = dab - dax + ls_dist(D, x, sx);  // x = e or c: removed (x, succ(x))
+    const uint4 rc = D.crec[(size_t)px * cl + kl];  // candidates of c for C B'
+    const int yc = (int)rc.x, dyc = (int)rc.y;
+    const int oyc = (w.pos[yc] - pa + n) % n;
+#pragma unroll
+    for (int type = 0; type < 4; ++type) {
+      if (type >= best) break;
       int od, oe;
-      bool ok = lane < cl && (int)ry.y < g;
+      bool ok;
       if (type == 0) {
-        od = ox, oe = oy;
-        ok = ok && oy >= ox;
+        od = ox, oe = oyb;
+        ok = cand && dyb < g01 && ox >= 2 && oyb >= ox;
       } else if (type == 1) {
-        od = ox, oe = oy;
-        ok = ok && oy > ox;
+        od = ox, oe = oyc;
+        ok = cand && dyc < g01 && ox >= 2 && oyc > ox;
       } else if (type == 2) {
-        od = oy, oe = ox;
-        ok = ok && oy >= 2 && oy < ox;
+        od = oyb, oe = ox;
+        ok = cand && dyb < g23 && ox >= 3 && oyb >= 2 && oyb < ox;
       } else {
-        od = ox + 1, oe = oy;
-        ok = ok && oy > ox + 1;
+        od = ox + 1, oe = oyb;
+        ok = cand && dyb < g23 && ox >= 2 && ox <= n - 3 && oyb > ox + 1;
       }
       const int c = ls_at(w, pa + od - 1), d = ls_at(w, pa + od);
       const int e = ls_at(w, pa + oe), f = ls_at(w, pa + oe + 1);
       const int removed = dab + ls_dist(D, c, d) + ls_dist(D, e, f);
-      int added = 0;
-      if (ok) {
-        if (type == 0) added = ls_dist(D, a, d) + ls_dist(D, e, b) + ls_dist(D, c, f);
-        else if (type == 1) added = ls_dist(D, a, d) + ls_dist(D, c, e) + ls_dist(D, b, f);
-        else if (type == 2) added = ls_dist(D, a, e) + ls_dist(D, b, d) + ls_dist(D, c, f);
-        else added = ls_dist(D, a, c) + ls_dist(D, b, e) + ls_dist(D, d, f);
-      }
+      int added;
+      if (type == 0) added = ls_dist(D, a, d) + ls_dist(D, e, b) + ls_dist(D, c, f);
+      else if (type == 1) added = ls_dist(D, a, d) + ls_dist(D, c, e) + ls_dist(D, b, f);
+      else if (type == 2) added = ls_dist(D, a, e) + ls_dist(D, b, d) + ls_dist(D, c, f);
+      else added = ls_dist(D, a, c) + ls_dist(D, b, e) + ls_dist(D, d, f);
       const uint64_t imp = __ballot(ok && added - removed < 0);
-      if (!imp) continue;
-      const int k = (int)__ffsll((unsigned long long)imp) - 1;
-      const int kod = (int)rdlane((uint32_t)od, k), koe = (int)rdlane((uint32_t)oe, k);
-      const int kc = (int)rdlane((uint32_t)c, k), kd = (int)rdlane((uint32_t)d, k);
-      const int ke = (int)rdlane((uint32_t)e, k), kf = (int)rdlane((uint32_t)f, k);
-      len += (int)rdlane((uint32_t)(added - removed), k);
-      // positions pa + 1 .. pa + oe hold B (od - 1 cities) then C
-      const int p0 = (pa + 1) % n, pe = (pa + koe) % n;
-      const int nb = kod - 1, nc = koe - kod + 1;
-      if (type == 3) {
-        ls_reverse_at(w, p0, (p0 + nb - 1) % n, lane);
-        ls_reverse_at(w, (p0 + nb) % n, pe, lane);
-      } else {
-        ls_reverse_at(w, p0, pe, lane);                                 // C' B'
-        if (type <= 1) ls_reverse_at(w, p0, (p0 + nc - 1) % n, lane);   // C
-        if (type != 1) ls_reverse_at(w, (p0 + nc) % n, pe, lane);       // B
+      if (imp) {
+        const int k = (int)__ffsll((unsigned long long)imp) - 1;
+        best = type;
+        bod = (int)rdlane((uint32_t)od, k), boe = (int)rdlane((uint32_t)oe, k);
+        bc = (int)rdlane((uint32_t)c, k), bd = (int)rdlane((uint32_t)d, k);
+        be = (int)rdlane((uint32_t)e, k), bf = (int)rdlane((uint32_t)f, k);
+        bdelta = (int)rdlane((uint32_t)(added - removed), k);
       }
-      ls_push(w, a, qh, qn, lane);
-      ls_push(w, b, qh, qn, lane);
-      ls_push(w, kc, qh, qn, lane);
-      ls_push(w, kd, qh, qn, lane);
-      ls_push(w, ke, qh, qn, lane);
-      ls_push(w, kf, qh, qn, lane);
-      return true;
     }
   }
-  return false;
+  if (best == 4) return false;
+  len += bdelta;
+  // positions pa + 1 .. pa + oe hold B (od - 1 cities) then C
+  const int p0 = (pa + 1) % n, pe = (pa + boe) % n;
+  const int nb = bod - 1, nc = boe - bod + 1;
+  if (best == 3) {
+    ls_reverse_at(w, p0, (p0 + nb - 1) % n, lane);
+    ls_reverse_at(w, (p0 + nb) % n, pe, lane);
+  } else {
+    ls_reverse_at(w, p0, pe, lane);                                 // C' B'
+    if (best <= 1) ls_reverse_at(w, p0, (p0 + nc - 1) % n, lane);   // C
+    if (best != 1) ls_reverse_at(w, (p0 + nc) % n, pe, lane);       // B
+  }
+  ls_push(w, a, qh, qn, lane);
+  ls_push(w, b, qh, qn, lane);
+  ls_push(w, bc, qh, qn, lane);
+  ls_push(w, bd, qh, qn, lane);
+  ls_push(w, be, qh, qn, lane);
+  ls_push(w, bf, qh, qn, lane);
+  return true;
 }
 
 // One block (one wave) per ant.  Dynamic LDS: t, pos, q (n 16-bit entries
@@ -3223,22 +3225,38 @@ __global__ __launch_bounds__(64) void k_local_search(Dev D, int kind) {
     const int c = (int)rec.x, dac = (int)rec.y;
     const bool cand = lane < cl;
     const int pa = w.pos[a];
+    // moves 1 to 3 all read the tour as it stands, so their distances are
+    // loaded together (one round of memory latency); the first improving
+    // move in the order above is then applied
+    const int bs = uni(ls_at(w, pa + 1)), bp = uni(ls_at(w, pa - 1));  // succ, pred of a
+    const int pc = w.pos[c];
+    const int e = ls_at(w, pc + 1), f = ls_at(w, pc - 1);  // succ, pred of c
+    const int dab = ls_dist(D, a, bs), dba = ls_dist(D, bp, a);
+    const int dbe = ls_dist(D, bs, e), dce = ls_dist(D, c, e);
+    const int dbf = ls_dist(D, bp, f), dfc = ls_dist(D, f, c);
+    const int off = (pc - pa + n) % n;
+    int sl[3], xl[3], gl[3], dse[3], dfs[3];  // Or-opt, L = 1, 2, 3
+#pragma unroll
+    for (int i = 0; i < 3; ++i) {
+      sl[i] = uni(ls_at(w, pa + i));      // the segment's last city
+      xl[i] = uni(ls_at(w, pa + i + 1));  // the city after it
+      gl[i] = dba + ls_dist(D, sl[i], xl[i]) - ls_dist(D, bp, xl[i]);
+      dse[i] = ls_dist(D, sl[i], e);
+      dfs[i] = ls_dist(D, f, sl[i]);
+    }
     bool done = false;
     // 1. 2-opt on the successor
     {
-      const int b = uni(ls_at(w, pa + 1));
-      const int dab = ls_dist(D, a, b);
-      const int e = ls_at(w, w.pos[c] + 1);
-      const bool ok = cand && dac < dab && c != b && e != a;
-      const int delta = ok ? dac + ls_dist(D, b, e) - dab - ls_dist(D, c, e) : 0;
+      const bool ok = cand && dac < dab && c != bs && e != a;
+      const int delta = dac + dbe - dab - dce;
       const uint64_t imp = __ballot(ok && delta < 0);
       if (imp) {
         const int k = (int)__ffsll((unsigned long long)imp) - 1;
         const int cc = (int)rdlane((uint32_t)c, k), ee = (int)rdlane((uint32_t)e, k);
         len += (int)rdlane((uint32_t)delta, k);
-        ls_reverse(w, b, cc, lane);
+        ls_reverse(w, bs, cc, lane);
         ls_push(w, a, qh, qn, lane);
-        ls_push(w, b, qh, qn, lane);
+        ls_push(w, bs, qh, qn, lane);
         ls_push(w, cc, qh, qn, lane);
         ls_push(w, ee, qh, qn, lane);
         done = true;
@@ -3246,19 +3264,16 @@ __global__ __launch_bounds__(64) void k_local_search(Dev D, int kind) {
     }
     // 2. 2-opt on the predecessor
     if (!done) {
-      const int b = uni(ls_at(w, pa - 1));
-      const int dba = ls_dist(D, b, a);
-      const int e = ls_at(w, w.pos[c] - 1);
-      const bool ok = cand && dac < dba && c != b && e != a;
-      const int delta = ok ? dac + ls_dist(D, b, e) - dba - ls_dist(D, e, c) : 0;
+      const bool ok = cand && dac < dba && c != bp && f != a;
+      const int delta = dac + dbf - dba - dfc;
       const uint64_t imp = __ballot(ok && delta < 0);
       if (imp) {
         const int k = (int)__ffsll((unsigned long long)imp) - 1;
-        const int cc = (int)rdlane((uint32_t)c, k), ee = (int)rdlane((uint32_t)e, k);
+        const int cc = (int)rdlane((uint32_t)c, k), ee = (int)rdlane((uint32_t)f, k);
         len += (int)rdlane((uint32_t)delta, k);
         ls_reverse(w, a, ee, lane);
         ls_push(w, a, qh, qn, lane);
-        ls_push(w, b, qh, qn, lane);
+        ls_push(w, bp, qh, qn, lane);
         ls_push(w, cc, qh, qn, lane);
         ls_push(w, ee, qh, qn, lane);
         done = true;
@@ -3267,15 +3282,11 @@ __global__ __launch_bounds__(64) void k_local_search(Dev D, int kind) {
     // 3. Or-opt of the segment a .. (L cities)
     for (int L = 1; L <= 3 && !done; ++L) {
       if (n < L + 3) break;
-      const int sL = uni(ls_at(w, pa + L - 1));
-      const int p = uni(ls_at(w, pa - 1)), x = uni(ls_at(w, pa + L));
-      const int g = ls_dist(D, p, a) + ls_dist(D, sL, x) - ls_dist(D, p, x);
-      const int off = (w.pos[c] - pa + n) % n;
+      const int sL = sl[L - 1], x = xl[L - 1], g = gl[L - 1];
       const bool out = cand && off >= L;
-      const int e = ls_at(w, w.pos[c] + 1), f = ls_at(w, w.pos[c] - 1);
-      const bool okA = out && c != p, okB = out && c != x;
-      const int dA = okA ? dac + ls_dist(D, sL, e) - ls_dist(D, c, e) - g : 0;
-      const int dB = okB ? ls_dist(D, f, sL) + dac - ls_dist(D, f, c) - g : 0;
+      const bool okA = out && c != bp, okB = out && c != x;
+      const int dA = dac + dse[L - 1] - dce - g;
+      const int dB = dfs[L - 1] + dac - dfc - g;
       const uint64_t impA = __ballot(okA && dA < 0), impB = __ballot(okB && dB < 0);
       if (impA | impB) {
         const int k = (int)__ffsll((unsigned long long)(impA | impB)) - 1;
@@ -3283,12 +3294,9 @@ __global__ __launch_bounds__(64) void k_local_search(Dev D, int kind) {
         const int cc = (int)rdlane((uint32_t)c, k);
         const int ef = (int)rdlane((uint32_t)(side == 0 ? e : f), k);
         len += (int)rdlane((uint32_t)(side == 0 ? dA : dB), k);
-        int seg[3];
-        seg[0] = a;
-        seg[1] = L > 1 ? uni(ls_at(w, pa + 1)) : 0;
-        seg[2] = L > 2 ? uni(ls_at(w, pa + 2)) : 0;
+        const int seg[3] = {sl[0], sl[1], sl[2]};
         ls_oropt(w, pa, L, cc, side, seg, lane);
-        ls_push(w, p, qh, qn, lane);
+        ls_push(w, bp, qh, qn, lane);
         ls_push(w, x, qh, qn, lane);
         ls_push(w, a, qh, qn, lane);
         ls_push(w, sL, qh, qn, lane);
