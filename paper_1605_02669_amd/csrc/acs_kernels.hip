@@ -1849,6 +1849,8 @@ __device__ __forceinline__ void ants_async_dense(const Dev &D, const Iter &A, in
   if (t0 > 0)
     draws = philox10(make_uint4((uint32_t)(t0 + gl), (uint32_t)ant, A.it, A.instance), A.key0,
                      A.key1);
+  // the chunk's greedy draws (lane gl: step t0 + gl) as one ballot
+  const uint32_t gbits = grp_bits<L>(__ballot((draws.x >> 8) < A.q0_24), base);
   uint32_t clen = 0;
   const int tend = min(t0 + L, n + 1);
   for (int t = t0 > 0 ? t0 : 1; t < tend; ++t) {
@@ -1878,14 +1880,12 @@ __device__ __forceinline__ void ants_async_dense(const Dev &D, const Iter &A, in
       }
     }
     if (t == n) break;
-    const uint32_t q24 = grp_read(draws.x, base, t - t0) >> 8;
-    const uint32_t u24 = grp_read(draws.y, base, t - t0) >> 8;
     const uint32_t umask = grp_bits<L>(__ballot(unv), base);
     int next, kind, k = -1;
     uint32_t d;
     float tval;
     if (umask) {
-      if (q24 < A.q0_24) {
+      if ((gbits >> (t - t0)) & 1u) {
         const uint32_t mx = grp_umax<L>(__float_as_uint(w));
         k = __builtin_ctz(grp_bits<L>(__ballot(unv && __float_as_uint(w) == mx), base));
         kind = 0;
@@ -1896,6 +1896,7 @@ __device__ __forceinline__ void ants_async_dense(const Dev &D, const Iter &A, in
           if (gl >= off) P = P + o;
         }
         const float total = __uint_as_float(grp_read(__float_as_uint(P), base, cl - 1));
+        const uint32_t u24 = grp_read(draws.y, base, t - t0) >> 8;
         const float r = ((float)u24 * 0x1p-24f) * total;
         const uint32_t sel = grp_bits<L>(__ballot(unv && P > r), base);
         k = sel ? __builtin_ctz(sel) : 31 - __builtin_clz(umask);
