@@ -1334,6 +1334,9 @@ constexpr uint32_t kQIdle = 1u << 20;
 constexpr uint32_t kNoEntry = 0xffffffffu;
 // fourth word of a buffer resource for untyped dword loads (gfx9 family)
 constexpr int kBufWord3 = 0x00020000;
+// cache policy of a buffer load that reads what the device's coherence point
+// holds (sc1), for values other waves update during the launch
+constexpr int kCoherent = 16;
 
 struct QRing {
   uint4 *ent;      // [ant wave][kQRing]
@@ -1552,10 +1555,12 @@ __device__ __forceinline__ void ant_queued(const Dev &D, const Iter &A, int ant,
   const __amdgpu_buffer_rsrc_t trs =
       __builtin_amdgcn_make_buffer_rsrc(D.ctau, 0, n * cl * 4, kBufWord3);
   // a record's fields and the live pheromone of its slot (the record's own
-  // pheromone word is the value of the iteration's start)
+  // pheromone word is the value of the iteration's start), the latter read
+  // device-coherently
   auto load_rec = [&](int city) {
     const auto r = __builtin_amdgcn_raw_buffer_load_b128(crs, koff, city * rowb, 0);
-    const uint32_t t = __builtin_amdgcn_raw_buffer_load_b32(trs, koff >> 2, city * cl * 4, 0);
+    const uint32_t t =
+        __builtin_amdgcn_raw_buffer_load_b32(trs, koff >> 2, city * cl * 4, kCoherent);
     return make_uint4(r[0], r[1], r[2], t);
   };
 
@@ -2768,11 +2773,11 @@ __device__ __forceinline__ void spm_ant_queued(const Dev &D, const Iter &A, int 
     return make_uint3(r[0], r[1], r[2]);
   };
   auto load_pair = [&](int city) {
-    const auto r = __builtin_amdgcn_raw_buffer_load_b64(srs, soff, city * s * 8, 0);
+    const auto r = __builtin_amdgcn_raw_buffer_load_b64(srs, soff, city * s * 8, kCoherent);
     return make_uint2(r[0], r[1]);
   };
   auto load_tail = [&](int city) {
-    return __builtin_amdgcn_raw_buffer_load_b32(trs, 0, city * 4, 0);
+    return __builtin_amdgcn_raw_buffer_load_b32(trs, 0, city * 4, kCoherent);
   };
 
   for (int w = lane; w < W; w += 64) vis[w] = 0u;
